@@ -1,0 +1,59 @@
+/*
+ * qnsch_oracle.h -- FP64 CPU oracle of the primitive-variable q-NSCH time step.
+ * TEST INFRASTRUCTURE ONLY: used by tests/, the smoke check and the benchmark's
+ * CPU-baseline leg; never by the GPU library.  Array layout and equations are
+ * described at the top of qnsch_oracle.c.
+ */
+#ifndef QNSCH_ORACLE_H
+#define QNSCH_ORACLE_H
+
+#define ORC_MAXLEV 12
+#define ORC_MAXV 200
+
+enum { ORC_WALL = 0, ORC_PERIODIC = 1 };
+enum { ORC_OK = 0, ORC_ENOCONV = -3, ORC_EDIVERGED = -4 };
+
+typedef struct {
+    int m1, m2;
+    double Lx, Ly;
+    int bcx, bcy;
+    int levels; /* 0 = automatic */
+} orc_grid;
+
+typedef struct {
+    double rho1, rho2, visc1, visc2; /* fluid 1 is c = 1 */
+    double Re, We, inv_Fr, Pe, M, eps, eta;
+    double mob_reg; /* the constant under the square root of the mobility */
+    double rho_ref; /* density the gravity term is measured against */
+} orc_params;
+
+typedef struct {
+    double tol;
+    int max_vcycles, nu1, nu2, nu_coarse;
+    double vanka_omega;
+} orc_opts;
+
+typedef struct orc_ctx orc_ctx;
+
+orc_ctx *orc_create(const orc_grid *, const orc_params *, const orc_opts *);
+void orc_destroy(orc_ctx *);
+int orc_levels(const orc_ctx *);
+void orc_set_state(orc_ctx *, const double *c, const double *mu, const double *p, const double *u, const double *v);
+void orc_get_state(const orc_ctx *, double *c, double *mu, double *p, double *u, double *v);
+void orc_begin_step(orc_ctx *, double dt);
+void orc_residual(orc_ctx *, double *r_out, double norms[5]);
+void orc_halfsweep(orc_ctx *, int colour);
+void orc_vcycle(orc_ctx *);
+int orc_solve(orc_ctx *);
+int orc_step(orc_ctx *, double dt);
+int orc_stats(const orc_ctx *, double *hist);
+void orc_mass(orc_ctx *, double out[2]);
+void orc_energy(orc_ctx *, double out[5]);
+void orc_dissipation(orc_ctx *, double out[4]);
+int orc_num_unknowns(const orc_ctx *);
+int orc_dense(orc_ctx *, double *Nvec, double *Jmat);
+void orc_add_unknowns(orc_ctx *, const double *dx);
+void orc_jvp(orc_ctx *, const double *d, double *out);
+void orc_material(const orc_ctx *, double c1, double c0, double out[6]);
+
+#endif

@@ -1,0 +1,117 @@
+"""Seeded synthetic workloads: grids, physical parameters and initial states.
+
+This module holds only input generation (grid shapes, parameter sets and
+initial fields); none of the scheme's arithmetic lives here.  It is shared by
+the GPU package's tests/benchmark and by the oracle-side tests, which is why it
+depends on numpy only.
+
+Shapes and parameters follow the paper's experiments (sec. 8: capillary wave,
+rising droplet, Rayleigh-Taylor), scaled to the workloads named below.  Fluid 1
+is the phase c = 1 (its density is rho1, sec. 2.1).
+
+Field arrays have shape (m2, m1): row j, column i.  u[j, i] is the x-velocity
+on the west face of cell (i, j); v[j, i] the y-velocity on its south face.
+"""
+import math
+
+import numpy as np
+
+WALL, PERIODIC = 0, 1
+
+
+def eta_of(rho1, rho2):
+    """Interface ratio parameter of sec. 8.1 (sharp-interface matching) for
+    the density pair; the equal-density limit of the same expression is
+    3/(2 sqrt 2 rho1)."""
+    if abs(rho2 - rho1) < 1e-6 * rho1:
+        return 3.0 / (2.0 * math.sqrt(2.0) * rho1)
+    d = rho2 - rho1
+    return d ** 3 / (2.0 * math.sqrt(2.0) * rho1 * rho2 * (rho2 ** 2 - rho1 ** 2 - 2.0 * rho1 * rho2 * math.log(rho2 / rho1)))
+
+
+def splitmix64(seed, n):
+    """n uniform doubles in [0,1) from the SplitMix64 generator (Steele, Lea,
+    Flood 2014), top 53 bits of each output."""
+    out = np.empty(n, dtype=np.float64)
+    mask = (1 << 64) - 1
+    s = seed & mask
+    for k in range(n):
+        s = (s + 0x9E3779B97F4A7C15) & mask
+        z = s
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        z = z ^ (z >> 31)
+        out[k] = (z >> 11) * (1.0 / 9007199254740992.0)
+    return out
+
+
+def _centres(m1, m2, h):
+    x = (np.arange(m1) + 0.5) * h
+    y = (np.arange(m2) + 0.5) * h
+    return np.meshgrid(x, y)  # (m2, m1)
+
+
+def default_opts(tol=1e-10):
+    return dict(tol=tol, max_vcycles=50, nu1=2, nu2=2, nu_coarse=30, vanka_omega=1.0)
+
+
+def params(rho1, rho2, visc1, visc2, Re, We, inv_Fr, eps, M=None, Pe=None, eta=None, mob_reg=None, rho_ref=0.0):
+    return dict(rho1=rho1, rho2=rho2, visc1=visc1, visc2=visc2, Re=Re, We=We, inv_Fr=inv_Fr,
+                Pe=(1.0 / eps) if Pe is None else Pe, M=eps if M is None else M, eps=eps,
+                eta=eta_of(rho1, rho2) if eta is None else eta,
+                mob_reg=eps if mob_reg is None else mob_reg, rho_ref=rho_ref)
+
+
+def capillary(m1=32, m2=64, eps=0.02, levels=4):
+    """Capillary wave on [0,1]x[0,2], periodic in x, walls in y; interface at
+    y = 1 + 0.01 cos(2 pi x) with fluid 1 (c = 1) above; no gravity."""
+    h = 1.0 / m1
+    grid = dict(m1=m1, m2=m2, Lx=1.0, Ly=m2 * h, bcx=PERIODIC, bcy=WALL, levels=levels)
+    par = params(1.0, 3.0, 1.0, 1.0, Re=100.0, We=100.0, inv_Fr=0.0, eps=eps)
+    X, Y = _centres(m1, m2, h)
+    c = 0.5 * (1.0 + np.tanh((Y - 1.0 - 0.01 * np.cos(2 * np.pi * X)) / (2.0 * math.sqrt(2.0) * eps)))
+    return dict(name="capillary_%dx%d" % (m1, m2), grid=grid, params=par, dt=1e-3, state=dict(c=c))
+
+
+def rising_drop(m1=256, m2=512, eps=0.01, levels=0, radius=0.25, rho_ratio=10.0, visc_ratio=10.0,
+                Re=35.0, We=10.0, inv_Fr=1.0, dt=5e-4):
+    """Light drop (fluid 1, c = 1) of the given radius centred at (0.5, 0.5)
+    in [0,1]x[0,2] with walls on all sides and gravity along -y."""
+    h = 1.0 / m1
+    grid = dict(m1=m1, m2=m2, Lx=1.0, Ly=m2 * h, bcx=WALL, bcy=WALL, levels=levels)
+    par = params(1.0, rho_ratio, 1.0, visc_ratio, Re=Re, We=We, inv_Fr=inv_Fr, eps=eps)
+    X, Y = _centres(m1, m2, h)
+    r = np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2)
+    c = 0.5 * (1.0 - np.tanh((r - radius) / (2.0 * math.sqrt(2.0) * eps)))
+    return dict(name="rising_drop_%dx%d" % (m1, m2), grid=grid, params=par, dt=dt, state=dict(c=c))
+
+
+def rayleigh_taylor(m1=512, m2=2048, eps=0.005, levels=0, seed=1703, noise=1e-3):
+    """Heavy fluid (c = 0, rho2 = 3) above light fluid (c = 1, rho1 = 1) in
+    [0,1]x[0,4], periodic in x, walls in y, interface y = 2 + 0.1 cos(2 pi x)
+    plus seeded uniform noise of the given amplitude on c."""
+    h = 1.0 / m1
+    grid = dict(m1=m1, m2=m2, Lx=1.0, Ly=m2 * h, bcx=PERIODIC, bcy=WALL, levels=levels)
+    par = params(1.0, 3.0, 1.0, 1.0, Re=3000.0, We=200.0, inv_Fr=1.0, eps=eps)
+    X, Y = _centres(m1, m2, h)
+    c = 0.5 * (1.0 - np.tanh((Y - 2.0 - 0.1 * np.cos(2 * np.pi * X)) / (2.0 * math.sqrt(2.0) * eps)))
+    xi = (splitmix64(seed, m1 * m2).reshape(m2, m1) * 2.0 - 1.0) * noise
+    return dict(name="rayleigh_taylor_%dx%d" % (m1, m2), grid=grid, params=par, dt=2.5e-4, state=dict(c=c + xi))
+
+
+def random_state(grid, seed, amp=(0.05, 0.1, 0.1, 0.2, 0.2), base_c=0.5):
+    """Smooth-ish random state (c, mu, p, u, v) for operator and identity tests:
+    c = base_c + noise, the rest zero-mean noise, wall faces zeroed."""
+    rng = np.random.default_rng(seed)
+    m1, m2 = grid["m1"], grid["m2"]
+    st = {}
+    for k, (name, a) in enumerate(zip(("c", "mu", "p", "u", "v"), amp)):
+        f = rng.uniform(-a, a, size=(m2, m1))
+        if name == "c":
+            f = f + base_c
+        st[name] = f
+    if grid["bcx"] == WALL:
+        st["u"][:, 0] = 0.0
+    if grid["bcy"] == WALL:
+        st["v"][0, :] = 0.0
+    return st
