@@ -1,0 +1,149 @@
+/*
+ * qnsch.h -- C ABI of the MI355X (gfx950) solver for one time step of the
+ * primitive-variable scheme for the quasi-incompressible
+ * Navier-Stokes-Cahn-Hilliard system.
+ *
+ * Reference: Guo, Lin, Lowengrub, Wise, "Mass conservative and energy stable
+ * finite difference methods for the quasi-incompressible Navier-Stokes-Cahn-
+ * Hilliard system: primitive variable and projection-type schemes".
+ *
+ * The discrete problem (sec. 6.1, eqs. (pm-num-mx), (pm-num-mass),
+ * (pm-num-phase), (pm-num-chem) with the advection and surface-tension forms of
+ * App. A.5-A.6 and the boundary conditions of App. A.4): given the state at
+ * time n, find w = (c, mubar, pbar, u, v) at time n+1 with N(w) = 0.  It is
+ * solved by the nonlinear FAS multigrid of sec. 7.1 (pointwise Newton update of
+ * (c, mubar), Vanka box update of (u, v, pbar), red-black order, V-cycles).
+ *
+ * Grid and host array layout (all host arrays are double, m1*m2 entries,
+ * row-major with x fastest, index j*m1 + i):
+ *   cell (i,j): 0 <= i < m1, 0 <= j < m2, centre ((i+1/2)h, (j+1/2)h),
+ *               h = Lx/m1 = Ly/m2 (square cells, sec. 5);
+ *   c, mu (mubar), p (pbar): cell values;
+ *   u[j*m1+i]: x-velocity on the west face of cell (i,j), at (i h, (j+1/2)h);
+ *              with walls in x the entries i = 0 are the wall (zero) and the
+ *              east wall face x = Lx is not stored; periodic in x: face i = 0
+ *              is also the face x = Lx;
+ *   v[j*m1+i]: y-velocity on the south face of cell (i,j), at ((i+1/2)h, j h),
+ *              with the same convention in y.
+ *
+ * Ownership: the caller owns every host buffer; calls copy synchronously on the
+ * context's stream.  The library owns all device memory of a context.  A
+ * context must be used from one host thread at a time.
+ *
+ * Errors: functions return QNSCH_OK (0) or a negative code; qnsch_last_error()
+ * gives a message.  A step that fails leaves the state at time n.
+ */
+#ifndef QNSCH_H
+#define QNSCH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    QNSCH_OK = 0,
+    QNSCH_EINVAL = -1,    /* bad argument (dims, parameters, NULL) */
+    QNSCH_ENOMEM = -2,    /* device allocation failed */
+    QNSCH_ENOCONV = -3,   /* max_vcycles reached above tol */
+    QNSCH_EDIVERGED = -4, /* non-finite residual, or c past the density pole */
+    QNSCH_EDEVICE = -5,   /* HIP runtime error */
+    QNSCH_EBUSY = -6      /* call not allowed in the current phase */
+};
+
+enum { QNSCH_BC_WALL = 0, QNSCH_BC_PERIODIC = 1 };
+enum { QNSCH_FP64 = 0, QNSCH_MIXED = 1 };
+
+typedef struct {
+    int32_t m1, m2;     /* cells in x and y; both even, divisible by 2^levels */
+    double Lx, Ly;      /* domain size; Lx/m1 must equal Ly/m2 */
+    int32_t bc_x, bc_y; /* QNSCH_BC_WALL (no-slip u, Neumann c, mu, p) or PERIODIC */
+    int32_t levels;     /* multigrid levels; 0 = coarsen to a smallest dimension of 4 */
+} qnsch_grid;
+
+/* Non-dimensional parameters of sec. 2.2; fluid 1 is c = 1 (rho(1) = rho1). */
+typedef struct {
+    double rho1, rho2;   /* densities, > 0 */
+    double visc1, visc2; /* viscosities, > 0 */
+    double Re, We;       /* Reynolds and Weber numbers, > 0 */
+    double inv_Fr;       /* 1/Fr, gravity along -y; 0 = no gravity */
+    double Pe, M;        /* Peclet number and the Mach-like number M, > 0 */
+    double eps;          /* interface thickness parameter, > 0 */
+    double eta;          /* interface ratio parameter, > 0 */
+    double mob_reg;      /* constant under the square root of the mobility (sec. 6.1); >= 0 */
+    double rho_ref;      /* density the gravity force is measured against (0 with walls in y) */
+} qnsch_params;
+
+typedef struct {
+    int32_t precision;   /* QNSCH_FP64 or QNSCH_MIXED */
+    double tol;          /* stop when every per-equation norm sqrt(h^2 sum r^2) <= tol */
+    int32_t max_vcycles; /* error QNSCH_ENOCONV beyond this */
+    int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black) */
+    int32_t nu_coarse;   /* sweeps on the coarsest level */
+    double vanka_omega;  /* relaxation factor of the box update (1 = exact box solve) */
+} qnsch_opts;
+
+typedef struct {
+    int32_t vcycles;        /* V-cycles of the last step */
+    double res[5];          /* final per-equation residual norms (c, mu, p, u, v) */
+    double res0[5];         /* residual norms before the first V-cycle */
+    double step_ms;         /* wall time of the last step */
+} qnsch_step_stats;
+
+typedef struct qnsch_ctx qnsch_ctx;
+
+/* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 30 coarse sweeps, omega 1. */
+void qnsch_default_opts(qnsch_opts *opts);
+
+/* Create a context on the current HIP device.  hip_stream: a hipStream_t to
+ * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
+ * device memory (roughly 120 bytes per finest cell in FP64).  Returns
+ * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
+int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
+                 void *hip_stream, qnsch_ctx **out);
+void qnsch_destroy(qnsch_ctx *ctx);
+const char *qnsch_last_error(const qnsch_ctx *ctx);
+int qnsch_levels(const qnsch_ctx *ctx);
+
+/* State at time n (host arrays, layout above).  mu, p, u, v may be NULL (zero).
+ * Wall faces are forced to zero.  Ends any step in progress. */
+int qnsch_set_state(qnsch_ctx *ctx, const double *c, const double *mu, const double *p,
+                    const double *u, const double *v);
+/* During a step (after qnsch_begin_step): overwrite the current iterate with
+ * host arrays, keeping the time-n data; for inspection of single phases. */
+int qnsch_set_iterate(qnsch_ctx *ctx, const double *c, const double *mu, const double *p,
+                      const double *u, const double *v);
+/* Current iterate (after a successful step: the state at time n+1).  NULL
+ * pointers are skipped. */
+int qnsch_get_state(qnsch_ctx *ctx, double *c, double *mu, double *p, double *u, double *v);
+
+/* One time step of size dt (sec. 6.1 solved by sec. 7.1): V-cycles until every
+ * residual norm is <= tol.  On failure the state stays at time n. */
+int qnsch_step(qnsch_ctx *ctx, double dt);
+
+/* Phases of a step, for inspection: begin_step fixes the time-n data (the
+ * current state) on every level; vcycle runs one V-cycle and fixes the mean of
+ * pbar to zero; residual returns r = -N(w) of the current iterate (5 fields of
+ * m1*m2, order c, mu, p, u, v; NULL to skip) and its norms; halfsweep runs one
+ * colour half-sweep (colour 0: (i+j) even) on the finest level; end_step
+ * commits the iterate as the new state. */
+int qnsch_begin_step(qnsch_ctx *ctx, double dt);
+int qnsch_vcycle(qnsch_ctx *ctx);
+int qnsch_residual(qnsch_ctx *ctx, double *r_out, double norms[5]);
+int qnsch_halfsweep(qnsch_ctx *ctx, int colour);
+int qnsch_end_step(qnsch_ctx *ctx);
+
+/* Mass of the two components of the current state (Theorem of sec. 6.1):
+ * out = {h^2 sum rho(c) c, h^2 sum rho(c) (1-c)}.  FP64, deterministic. */
+int qnsch_mass(qnsch_ctx *ctx, double out[2]);
+/* Discrete energy of the current state (Theorem of sec. 6.1 with the norms of
+ * App. A.7): out = {E, kinetic, gradient, bulk (double well), potential}. */
+int qnsch_energy(qnsch_ctx *ctx, double out[5]);
+int qnsch_stats(const qnsch_ctx *ctx, qnsch_step_stats *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,189 @@
+"""ctypes binding of ``libqnsch_hip.so`` (the C ABI of ``include/qnsch.h``).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+Importing this module does not need a GPU; creating a context does.  If the
+library has not been built the binding raises instead of falling back.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(PKG, "libqnsch_hip.so")
+
+OK, EINVAL, ENOMEM, ENOCONV, EDIVERGED, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6
+WALL, PERIODIC = 0, 1
+FP64, MIXED = 0, 1
+
+# every exported symbol declared in include/qnsch.h
+SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
+           "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
+           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_mass", "qnsch_energy", "qnsch_stats")
+
+
+class QnschError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("qnsch error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Grid(C.Structure):
+    _fields_ = [("m1", C.c_int32), ("m2", C.c_int32), ("Lx", C.c_double), ("Ly", C.c_double),
+                ("bc_x", C.c_int32), ("bc_y", C.c_int32), ("levels", C.c_int32)]
+
+
+class Params(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("rho1", "rho2", "visc1", "visc2", "Re", "We", "inv_Fr", "Pe", "M",
+                                           "eps", "eta", "mob_reg", "rho_ref")]
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_vcycles", C.c_int32), ("nu1", C.c_int32),
+                ("nu2", C.c_int32), ("nu_coarse", C.c_int32), ("vanka_omega", C.c_double)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("vcycles", C.c_int32), ("res", C.c_double * 5), ("res0", C.c_double * 5), ("step_ms", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it is missing (no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError("libqnsch_hip.so is not built: run __graft_entry__.build() (hipcc, gfx950)")
+        L = C.CDLL(LIB)
+        P = C.POINTER(C.c_double)
+        vp = C.c_void_p
+        L.qnsch_default_opts.argtypes = [C.POINTER(Opts)]
+        L.qnsch_default_opts.restype = None
+        L.qnsch_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.qnsch_destroy.argtypes = [vp]
+        L.qnsch_destroy.restype = None
+        L.qnsch_last_error.argtypes = [vp]
+        L.qnsch_last_error.restype = C.c_char_p
+        L.qnsch_levels.argtypes = [vp]
+        L.qnsch_set_state.argtypes = [vp, P, P, P, P, P]
+        L.qnsch_set_iterate.argtypes = [vp, P, P, P, P, P]
+        L.qnsch_get_state.argtypes = [vp, P, P, P, P, P]
+        L.qnsch_step.argtypes = [vp, C.c_double]
+        L.qnsch_begin_step.argtypes = [vp, C.c_double]
+        L.qnsch_vcycle.argtypes = [vp]
+        L.qnsch_residual.argtypes = [vp, P, P]
+        L.qnsch_halfsweep.argtypes = [vp, C.c_int]
+        L.qnsch_end_step.argtypes = [vp]
+        L.qnsch_mass.argtypes = [vp, P]
+        L.qnsch_energy.argtypes = [vp, P]
+        L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def default_opts():
+    o = Opts()
+    lib().qnsch_default_opts(C.byref(o))
+    return {n: getattr(o, n) for n, _ in Opts._fields_}
+
+
+class Solver:
+    """One simulation on the GPU.  Fields are (m2, m1) numpy arrays; u[j, i]
+    is the west face of cell (i, j), v[j, i] its south face."""
+
+    def __init__(self, grid, params, opts=None, stream=None):
+        self.m1, self.m2 = int(grid["m1"]), int(grid["m2"])
+        g = Grid(self.m1, self.m2, grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
+        p = Params(*[float(params[n]) for n, _ in Params._fields_])
+        o = None
+        if opts is not None:
+            d = default_opts()
+            d.update(opts)
+            o = Opts(*[d[n] for n, _ in Opts._fields_])
+        h = C.c_void_p()
+        rc = lib().qnsch_create(C.byref(g), C.byref(p), C.byref(o) if o is not None else None,
+                                C.c_void_p(stream) if stream else None, C.byref(h))
+        if rc != OK:
+            raise QnschError(rc, "qnsch_create rejected the configuration")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().qnsch_destroy(self.h)
+            self.h = None
+
+    def _chk(self, rc):
+        if rc != OK:
+            raise QnschError(rc, lib().qnsch_last_error(self.h).decode())
+        return rc
+
+    @property
+    def levels(self):
+        return lib().qnsch_levels(self.h)
+
+    def _f(self, a):
+        return None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(self.m2, self.m1)
+
+    def set_state(self, c, mu=None, p=None, u=None, v=None):
+        arrs = [self._f(a) for a in (c, mu, p, u, v)]
+        self._chk(lib().qnsch_set_state(self.h, *[_ptr(a) for a in arrs]))
+
+    def get_state(self):
+        out = [np.zeros((self.m2, self.m1)) for _ in range(5)]
+        self._chk(lib().qnsch_get_state(self.h, *[_ptr(a) for a in out]))
+        return dict(zip(("c", "mu", "p", "u", "v"), out))
+
+    def step(self, dt, check=True):
+        rc = lib().qnsch_step(self.h, dt)
+        if check:
+            self._chk(rc)
+        return rc
+
+    def begin_step(self, dt):
+        self._chk(lib().qnsch_begin_step(self.h, dt))
+
+    def vcycle(self):
+        self._chk(lib().qnsch_vcycle(self.h))
+
+    def residual(self):
+        r = np.zeros((5, self.m2, self.m1))
+        n = np.zeros(5)
+        self._chk(lib().qnsch_residual(self.h, _ptr(r), _ptr(n)))
+        return r, n
+
+    def halfsweep(self, colour):
+        self._chk(lib().qnsch_halfsweep(self.h, colour))
+
+    def end_step(self):
+        self._chk(lib().qnsch_end_step(self.h))
+
+    def mass(self):
+        out = np.zeros(2)
+        self._chk(lib().qnsch_mass(self.h, _ptr(out)))
+        return out
+
+    def energy(self):
+        out = np.zeros(5)
+        self._chk(lib().qnsch_energy(self.h, _ptr(out)))
+        return out
+
+    def stats(self):
+        s = StepStats()
+        self._chk(lib().qnsch_stats(self.h, C.byref(s)))
+        return dict(vcycles=s.vcycles, res=list(s.res), res0=list(s.res0), step_ms=s.step_ms)
+
+    def set_iterate(self, c, mu=None, p=None, u=None, v=None):
+        arrs = [self._f(a) for a in (c, mu, p, u, v)]
+        self._chk(lib().qnsch_set_iterate(self.h, *[_ptr(a) for a in arrs]))
+
+    def set_time_n_and_iterate(self, wn, w, dt):
+        """time-n data from the state dict wn, then the iterate w"""
+        self.set_state(*[wn.get(k) for k in ("c", "mu", "p", "u", "v")])
+        self.begin_step(dt)
+        self.set_iterate(*[w.get(k) for k in ("c", "mu", "p", "u", "v")])

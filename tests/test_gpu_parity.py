@@ -1,0 +1,203 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Element-by-element comparisons on the same seeded inputs at sizes the oracle
+finishes in seconds (several 256-thread blocks and ragged tails), and at the
+rising-droplet size of the benchmark (256 x 512) on a full V-cycle and on
+properties of the converged step.  Tolerance: 1e-10 relative in FP64 for
+converged and per-cycle fields; 1e-12 for single residual evaluations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as OR
+from paper_1703_06606_amd import qnsch as Q
+from paper_1703_06606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("c", "mu", "p", "u", "v")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def pair(cfg, opts):
+    return Q.Solver(cfg["grid"], cfg["params"], opts), OR.Oracle(cfg["grid"], cfg["params"], opts)
+
+
+def rel(a, b, floor=1e-12):
+    return np.abs(a - b).max() / max(np.abs(b).max(), floor)
+
+
+def grid_(m1, m2, bcx, bcy, levels=0):
+    return dict(m1=m1, m2=m2, Lx=1.0, Ly=m2 / m1, bcx=bcx, bcy=bcy, levels=levels)
+
+
+def par_O1(**kw):
+    p = dict(rho1=1.0, rho2=2.5, visc1=1.0, visc2=1.8, Re=3.0, We=2.0, inv_Fr=0.7, Pe=2.0, M=0.8,
+             eps=0.5, eta=0.9, mob_reg=0.05, rho_ref=0.0)
+    p.update(kw)
+    return p
+
+
+SHAPES = [(16, 24, 0, 0), (16, 24, 1, 0), (16, 16, 1, 1), (40, 24, 0, 0), (40, 24, 1, 0)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
+def test_residual_matches_oracle(shape):
+    m1, m2, bx, by = shape
+    say("residual parity", shape)
+    cfg = dict(grid=grid_(m1, m2, bx, by, levels=2), params=par_O1(rho2=3.0))
+    g, o = pair(cfg, W.default_opts())
+    w, wn = W.random_state(cfg["grid"], 21), W.random_state(cfg["grid"], 22)
+    for s in (g, o):
+        s.set_time_n_and_iterate(wn, w, 0.3)
+    rg, ng = g.residual()
+    ro, no = o.residual()
+    for q, k in enumerate(FIELDS):
+        assert rel(rg[q], ro[q]) < 1e-12, (k, rel(rg[q], ro[q]))
+    assert np.allclose(ng, no, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
+def test_halfsweeps_match_oracle(shape):
+    m1, m2, bx, by = shape
+    say("halfsweep parity", shape)
+    cfg = dict(grid=grid_(m1, m2, bx, by, levels=2), params=par_O1(rho2=3.0))
+    g, o = pair(cfg, W.default_opts())
+    w, wn = W.random_state(cfg["grid"], 23), W.random_state(cfg["grid"], 24)
+    for s in (g, o):
+        s.set_time_n_and_iterate(wn, w, 0.3)
+    for colour in (0, 1, 0):
+        g.halfsweep(colour)
+        o.halfsweep(colour)
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k]) < 1e-11, (colour, k, rel(a[k], b[k]))
+
+
+def _periodic_drop():
+    c = W.rising_drop(32, 32, eps=0.04)
+    c["grid"] = grid_(32, 32, 1, 1)
+    c["params"] = dict(c["params"], inv_Fr=0.0)
+    return c
+
+
+def _cases():
+    return {
+        "capillary_32x64": W.capillary(),
+        "drop_32x64": W.rising_drop(32, 64, eps=0.04),
+        "drop_40x24_ragged": W.rising_drop(40, 24, eps=0.05, radius=0.2),
+        "periodic_box_32x32": _periodic_drop(),
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_vcycles_match_oracle(name):
+    cfg = _cases()[name]
+    say("vcycle parity", name)
+    g, o = pair(cfg, W.default_opts())
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+        s.begin_step(cfg["dt"])
+    for it in range(3):
+        g.vcycle()
+        o.vcycle()
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < 1e-10, (it, k, rel(a[k], b[k], 1e-9))
+        _, ng = g.residual()
+        _, no = o.residual()
+        assert np.allclose(ng, no, rtol=1e-6, atol=1e-14), (ng, no)
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_converged_step_matches_oracle(name):
+    cfg = _cases()[name]
+    say("step parity", name)
+    g, o = pair(cfg, W.default_opts(1e-10))
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+    mg0 = g.mass()
+    assert np.allclose(mg0, o.mass(), rtol=1e-13)
+    eg0, eo0 = g.energy(), o.energy()
+    assert np.allclose(eg0, eo0, rtol=1e-12, atol=1e-300)
+    for step in range(2):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < 1e-10, (step, k, rel(a[k], b[k], 1e-9))
+        assert abs(g.stats()["vcycles"] - o.stats()[0]) <= 1
+        mg = g.mass()
+        assert np.abs(mg - mg0).max() <= 1e-12 * max(1.0, np.abs(mg0).max())
+        eg = g.energy()
+        assert np.allclose(eg, o.energy(), rtol=1e-10, atol=1e-14)
+        assert eg[0] <= eg0[0] + 1e-14
+        mg0, eg0 = mg, eg
+
+
+def test_failure_paths_leave_state_at_time_n():
+    cfg = W.rising_drop(16, 32, eps=0.08)
+    g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(0.0), max_vcycles=1))
+    g.set_state(cfg["state"]["c"])
+    s0 = g.get_state()
+    assert g.step(cfg["dt"], check=False) == Q.ENOCONV
+    s1 = g.get_state()
+    for k in FIELDS:
+        assert np.array_equal(s0[k], s1[k])
+    g = Q.Solver(cfg["grid"], dict(cfg["params"], rho2=100.0), W.default_opts())
+    cc = cfg["state"]["c"].copy()
+    cc[3, 3] = -0.05
+    g.set_state(cc)
+    assert g.step(cfg["dt"], check=False) == Q.EDIVERGED
+    assert np.array_equal(g.get_state()["c"], cc)
+    with pytest.raises(Q.QnschError):
+        Q.Solver(dict(cfg["grid"], m1=15), cfg["params"])
+
+
+def test_deterministic():
+    cfg = W.rising_drop(64, 128, eps=0.02)
+    out = []
+    for _ in range(2):
+        g = Q.Solver(cfg["grid"], cfg["params"], W.default_opts(1e-10))
+        g.set_state(cfg["state"]["c"])
+        g.step(cfg["dt"])
+        out.append(g.get_state())
+    for k in FIELDS:
+        assert np.array_equal(out[0][k], out[1][k])
+
+
+def test_full_size_rising_drop():
+    """256 x 512 rising droplet (the benchmark's workload): one V-cycle
+    compared field by field with the oracle; then the converged step checked
+    by the oracle's own residual at the GPU's solution, by mass conservation
+    and by the energy law."""
+    cfg = W.rising_drop()
+    say("full size", cfg["name"])
+    opts = W.default_opts(1e-10)
+    g, o = pair(cfg, opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+        s.begin_step(cfg["dt"])
+    g.vcycle()
+    o.vcycle()
+    a, b = g.get_state(), o.get_state()
+    for k in FIELDS:
+        assert rel(a[k], b[k], 1e-9) < 1e-10, (k, rel(a[k], b[k], 1e-9))
+    # converged step on the GPU, residual evaluated by the oracle
+    g.set_state(cfg["state"]["c"])
+    m0, e0 = g.mass(), g.energy()
+    assert g.step(cfg["dt"]) == Q.OK
+    s = g.get_state()
+    o2 = OR.Oracle(cfg["grid"], cfg["params"], opts)
+    o2.set_time_n_and_iterate(dict(c=cfg["state"]["c"]), s, cfg["dt"])
+    _, no = o2.residual()
+    assert no.max() <= 2e-10, no
+    m1, e1 = g.mass(), g.energy()
+    assert np.abs(m1 - m0).max() <= 1e-12 * np.abs(m0).max()
+    assert e1[0] < e0[0]
+    say("full size vcycles", g.stats()["vcycles"], "step ms", g.stats()["step_ms"])
