@@ -142,6 +142,19 @@ int qnsch_mass(qnsch_ctx *ctx, double out[2]);
  * App. A.7): out = {E, kinetic, gradient, bulk (double well), potential}. */
 int qnsch_energy(qnsch_ctx *ctx, double out[5]);
 int qnsch_stats(const qnsch_ctx *ctx, qnsch_step_stats *out);
+/* Block until all work of the context's stream has finished. */
+int qnsch_synchronize(qnsch_ctx *ctx);
+
+/* Measurement support.  qnsch_profile(ctx, 1) starts timing every launch of
+ * the finest-level half-sweep kernel with HIP events on the context's stream
+ * (and resets the counters; 0 stops); qnsch_profile_read returns
+ * {launches, total milliseconds}. */
+int qnsch_profile(qnsch_ctx *ctx, int enable);
+int qnsch_profile_read(qnsch_ctx *ctx, double out[2]);
+/* Copy-kernel probe on the current device: copies n doubles reps times
+ * between two buffers it allocates and frees; out = {GB/s counting read and
+ * write, milliseconds per copy}. */
+int qnsch_copy_probe(size_t n, int reps, double out[2]);
 
 #ifdef __cplusplus
 }

@@ -9,8 +9,14 @@
 //
 // Layout: every field of a level is an m2 x pitch array of doubles, row j,
 // column i.  Cell fields at cell (i,j); u(i,j) on the west face of cell (i,j)
-// (x = i h); v(i,j) on the south face (y = j h).  Ghosts are not stored: the
-// loaders below apply the boundary conditions of App. A.4.
+// (x = i h); v(i,j) on the south face (y = j h).  Ghosts are not stored.
+//
+// Work is organised in LDS tiles: a workgroup loads a TX x TY block of cells
+// with a halo of one cell below and two above in each direction (the reach of
+// a Vanka box), applying the boundary conditions of App. A.4 while loading,
+// and computes the cell functions of the time-n data (rho^n, mu(c^n), m(c^n))
+// and rho(c) once per tile element.  The equations below then read the tile
+// without any boundary logic.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,39 +38,43 @@ struct View {
     double inv_h;
 };
 
+struct Rhs {
+    const double *fc, *fmu, *fp, *fu, *fv; // FAS right-hand side; NULL = 0
+};
+
 // --------------------------------------------------------------------------
-// loaders with boundary conditions
+// loaders with boundary conditions (used only by the tile loader)
 
 __device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
 
 // cell field: Neumann mirror or periodic image (x first, then y)
-__device__ __forceinline__ double ldc(const double *f, const View &L, int i, int j)
+__device__ __forceinline__ double ldc(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
-    if (i < 0 || i >= L.m1) i = L.bcx ? wrapi(i, L.m1) : (i < 0 ? 0 : L.m1 - 1);
-    if (j < 0 || j >= L.m2) j = L.bcy ? wrapi(j, L.m2) : (j < 0 ? 0 : L.m2 - 1);
-    return f[(size_t)j * L.pitch + i];
+    if (i < 0 || i >= m1) i = bcx ? wrapi(i, m1) : (i < 0 ? 0 : m1 - 1);
+    if (j < 0 || j >= m2) j = bcy ? wrapi(j, m2) : (j < 0 ? 0 : m2 - 1);
+    return f[(size_t)j * pitch + i];
 }
-// east-west face field at x = i h, row j: zero on x-walls, reflected
-// (ghost = -interior) across y-walls
-__device__ __forceinline__ double ldu(const double *f, const View &L, int i, int j)
+// east-west face field at x = i h, row j: zero on (and beyond) x-walls,
+// reflected (ghost = -interior) across y-walls
+__device__ __forceinline__ double ldu(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
-    if (L.bcx) i = wrapi(i, L.m1);
-    else if (i <= 0 || i >= L.m1) return 0.0;
-    if (j < 0 || j >= L.m2) {
-        if (L.bcy) j = wrapi(j, L.m2);
-        else return -f[(size_t)(j < 0 ? 0 : L.m2 - 1) * L.pitch + i];
+    if (bcx) i = wrapi(i, m1);
+    else if (i <= 0 || i >= m1) return 0.0;
+    if (j < 0 || j >= m2) {
+        if (bcy) j = wrapi(j, m2);
+        else return -f[(size_t)(j < 0 ? 0 : m2 - 1) * pitch + i];
     }
-    return f[(size_t)j * L.pitch + i];
+    return f[(size_t)j * pitch + i];
 }
-__device__ __forceinline__ double ldv(const double *f, const View &L, int i, int j)
+__device__ __forceinline__ double ldv(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
-    if (L.bcy) j = wrapi(j, L.m2);
-    else if (j <= 0 || j >= L.m2) return 0.0;
-    if (i < 0 || i >= L.m1) {
-        if (L.bcx) i = wrapi(i, L.m1);
-        else return -f[(size_t)j * L.pitch + (i < 0 ? 0 : L.m1 - 1)];
+    if (bcy) j = wrapi(j, m2);
+    else if (j <= 0 || j >= m2) return 0.0;
+    if (i < 0 || i >= m1) {
+        if (bcx) i = wrapi(i, m1);
+        else return -f[(size_t)j * pitch + (i < 0 ? 0 : m1 - 1)];
     }
-    return f[(size_t)j * L.pitch + i];
+    return f[(size_t)j * pitch + i];
 }
 __device__ __forceinline__ bool u_unk(const View &L, int i) { return L.bcx || (i >= 1 && i <= L.m1 - 1); }
 __device__ __forceinline__ bool v_unk(const View &L, int j) { return L.bcy || (j >= 1 && j <= L.m2 - 1); }
@@ -72,8 +82,18 @@ __device__ __forceinline__ bool v_unk(const View &L, int j) { return L.bcy || (j
 // --------------------------------------------------------------------------
 // material laws (sec. 2.1, sec. 6.1)
 
-__device__ __forceinline__ double rho_of(const Phys &P, double c) { return P.rho12 / (P.drho * c + P.rho1); }
-__device__ __forceinline__ double visc_of(const Phys &P, double c) { return P.visc12 / (P.dvisc * c + P.visc1); }
+// reciprocal: hardware estimate refined by two Newton steps (relative error a
+// few ulp, far below the solver tolerances)
+__device__ __forceinline__ double frcp(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ double rho_of(const Phys &P, double c) { return P.rho12 * frcp(P.drho * c + P.rho1); }
+__device__ __forceinline__ double visc_of(const Phys &P, double c) { return P.visc12 * frcp(P.dvisc * c + P.visc1); }
 __device__ __forceinline__ double mob_of(const Phys &P, double c)
 {
     double q = c * (1.0 - c);
@@ -86,278 +106,353 @@ __device__ __forceinline__ double dwell(double c)
 }
 
 // --------------------------------------------------------------------------
-// cell equations: phase (pm-num-phase), chemical potential (pm-num-chem) and
-// mass (pm-num-mass), with the entries of their Jacobian the smoother needs
+// LDS tile
 
+enum { T_C = 0, T_MU, T_P, T_U, T_V, T_CN, T_UN, T_VN, T_RN, T_MV, T_MOB, T_RS, T_NF };
+
+// A tile covers level cells i0-1 .. i0+TX+1, j0-1 .. j0+TY+1 (W = TX+3
+// columns); q(f, i, j) takes level coordinates.
+struct Tile {
+    double *s; // T_NF arrays of W*H doubles in LDS
+    int i0, j0, W, H;
+    __device__ __forceinline__ int idx(int i, int j) const { return (j - j0 + 1) * W + (i - i0 + 1); }
+    __device__ __forceinline__ double q(int f, int i, int j) const { return s[f * W * H + idx(i, j)]; }
+    __device__ __forceinline__ void set(int f, int i, int j, double v) const { s[f * W * H + idx(i, j)] = v; }
+};
+
+// cooperative load of a tile (all threads of the block take part; the caller
+// synchronises afterwards).  The level may be in global memory or in LDS.
+__device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Tile &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        double *s = T.s + e;
+        const int st = n;
+        if (i > L.m1 + 1 || j > L.m2 + 1) {
+            // beyond the reach of any cell of the level (tile larger than the level)
+            for (int f = 0; f < T_NF; f++) s[f * st] = 0.0;
+            continue;
+        }
+        const double c = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        const double cn = ldc(L.cn, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_C * st] = c;
+        s[T_MU * st] = ldc(L.mu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_P * st] = ldc(L.p, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_U * st] = ldu(L.u, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_V * st] = ldv(L.v, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_CN * st] = cn;
+        s[T_UN * st] = ldu(L.un, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_VN * st] = ldv(L.vn, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_RN * st] = rho_of(P, cn);
+        s[T_MV * st] = visc_of(P, cn);
+        s[T_MOB * st] = mob_of(P, cn);
+        s[T_RS * st] = rho_of(P, c);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Lane pairs.  Each cell (or box) is handled by two adjacent lanes: lane 0
+// takes every x-direction contribution, lane 1 the same code on transposed
+// strides (y-direction), so the pair runs one instruction stream without
+// divergence.  Partial sums are exchanged with a one-lane shuffle.
+
+struct Ax {
+    int dn, dt;            // element strides of the tile along the normal / tangential axis
+    int FN, FT, FNN, FTN;  // own velocity, other velocity and their time-n fields
+    int per, ia, ma;       // periodic along the axis; cell index and count along it
+    int pert, it, mt;      // the same for the tangential axis
+    double grav;           // 1 on the y lane: gravity acts on the north-south faces
+    int hlf;
+};
+
+__device__ __forceinline__ Ax make_ax(const View &L, const Tile &T, int i, int j, int hlf)
+{
+    Ax a;
+    a.hlf = hlf;
+    a.dn = hlf ? T.W : 1;
+    a.dt = hlf ? 1 : T.W;
+    a.FN = hlf ? T_V : T_U;
+    a.FT = hlf ? T_U : T_V;
+    a.FNN = hlf ? T_VN : T_UN;
+    a.FTN = hlf ? T_UN : T_VN;
+    a.per = hlf ? L.bcy : L.bcx;
+    a.ia = hlf ? j : i;
+    a.ma = hlf ? L.m2 : L.m1;
+    a.pert = hlf ? L.bcx : L.bcy;
+    a.it = hlf ? i : j;
+    a.mt = hlf ? L.m1 : L.m2;
+    a.grav = hlf ? 1.0 : 0.0;
+    return a;
+}
+
+__device__ __forceinline__ double other(double x) { return __shfl_xor(x, 1, 64); }
+
+// element-indexed tile read
+__device__ __forceinline__ double tq(const Tile &T, int f, int e) { return T.s[f * T.W * T.H + e]; }
+
+// contributions of one axis to the cell equations at cell element e
+struct CellAx {
+    double adv, div, Lmu, Lp, Sm, Gc, Gn, Lr, dGc, dLra, dLrb;
+};
+
+__device__ __forceinline__ CellAx cell_axis(const Tile &T, const Ax &a, int e, double ih)
+{
+    const double ih2 = ih * ih;
+    // faces of the cell on a wall carry no flux (the mirrored ghost equals the
+    // cell); the masks matter for derivatives only
+    const double wP = (a.per || a.ia < a.ma - 1) ? 1.0 : 0.0, wM = (a.per || a.ia > 0) ? 1.0 : 0.0;
+    const int eP = e + a.dn, eM = e - a.dn;
+    const double c = tq(T, T_C, e), cP = tq(T, T_C, eP), cM = tq(T, T_C, eM);
+    const double n = tq(T, T_CN, e), nP = tq(T, T_CN, eP), nM = tq(T, T_CN, eM);
+    const double mu = tq(T, T_MU, e), p = tq(T, T_P, e);
+    const double rnP = tq(T, T_RN, eP), rnM = tq(T, T_RN, eM), rn = tq(T, T_RN, e);
+    const double rs = tq(T, T_RS, e);
+    const double m0 = tq(T, T_MOB, e);
+    const double mP = 0.5 * (tq(T, T_MOB, eP) + m0) * wP, mM = 0.5 * (tq(T, T_MOB, eM) + m0) * wM;
+    const double uP = tq(T, a.FN, eP), u0 = tq(T, a.FN, e);
+    CellAx x;
+    // rho^n u . grad c^n in the special form of App. A.5
+    x.adv = 0.5 * ih * (rnP * (nP - n) * uP + rnM * (n - nM) * u0);
+    x.div = ih * (uP - u0);
+    x.Lmu = ih2 * (mP * (tq(T, T_MU, eP) - mu) - mM * (mu - tq(T, T_MU, eM)));
+    x.Lp = ih2 * (mP * (tq(T, T_P, eP) - p) - mM * (p - tq(T, T_P, eM)));
+    x.Sm = ih2 * (mP + mM);
+    const double dP = cP - c, dM = c - cM, gP = nP - n, gM = n - nM;
+    x.Gc = 0.5 * ih2 * (dP * dP + dM * dM);
+    x.Gn = 0.5 * ih2 * (gP * gP + gM * gM);
+    const double rh = 0.5 * (rs + rn);
+    const double kP = 0.5 * (0.5 * (tq(T, T_RS, eP) + rnP) + rh) * wP;
+    const double kM = 0.5 * (0.5 * (tq(T, T_RS, eM) + rnM) + rh) * wM;
+    const double hP = 0.5 * (dP + gP), hM = 0.5 * (dM + gM);
+    x.Lr = ih2 * (kP * hP - kM * hM);
+    x.dGc = ih2 * (wP * (-dP) + wM * dM);
+    x.dLra = ih2 * (wP * hP - wM * hM);
+    x.dLrb = ih2 * (kP + kM);
+    return x;
+}
+
+__device__ __forceinline__ CellAx cell_sum(const CellAx &x)
+{
+    CellAx s;
+    s.adv = x.adv + other(x.adv);
+    s.div = x.div + other(x.div);
+    s.Lmu = x.Lmu + other(x.Lmu);
+    s.Lp = x.Lp + other(x.Lp);
+    s.Sm = x.Sm + other(x.Sm);
+    s.Gc = x.Gc + other(x.Gc);
+    s.Gn = x.Gn + other(x.Gn);
+    s.Lr = x.Lr + other(x.Lr);
+    s.dGc = x.dGc + other(x.dGc);
+    s.dLra = x.dLra + other(x.dLra);
+    s.dLrb = x.dLrb + other(x.dLrb);
+    return s;
+}
+
+// cell equations: phase (pm-num-phase), chemical potential (pm-num-chem) and
+// mass (pm-num-mass), with the Jacobian entries the smoother needs, from the
+// two axis sums
 struct CellEq {
     double Nc, Nmu, Np;
     double Jcc, Jcm, Jmc, Jmm; // d(Nc,Nmu)/d(c,mu) at the cell
     double Jpp;                // dNp/dp at the cell
 };
 
-__device__ __forceinline__ CellEq eq_cell(const Phys &P, const View &L, int i, int j)
+__device__ __forceinline__ CellEq cell_eq(const Phys &P, const Tile &T, int e, const CellAx &s)
 {
-    const double ih = L.inv_h, ih2 = ih * ih;
-    // 5-point gathers (E, W, N, S) with boundary images
-    const double c = ldc(L.c, L, i, j), cE = ldc(L.c, L, i + 1, j), cW = ldc(L.c, L, i - 1, j),
-                 cN = ldc(L.c, L, i, j + 1), cS = ldc(L.c, L, i, j - 1);
-    const double n = ldc(L.cn, L, i, j), nE = ldc(L.cn, L, i + 1, j), nW = ldc(L.cn, L, i - 1, j),
-                 nN = ldc(L.cn, L, i, j + 1), nS = ldc(L.cn, L, i, j - 1);
-    const double mu = ldc(L.mu, L, i, j), muE = ldc(L.mu, L, i + 1, j), muW = ldc(L.mu, L, i - 1, j),
-                 muN = ldc(L.mu, L, i, j + 1), muS = ldc(L.mu, L, i, j - 1);
-    const double p = ldc(L.p, L, i, j), pE = ldc(L.p, L, i + 1, j), pW = ldc(L.p, L, i - 1, j),
-                 pN = ldc(L.p, L, i, j + 1), pS = ldc(L.p, L, i, j - 1);
-    const double uE = ldu(L.u, L, i + 1, j), uW = ldu(L.u, L, i, j);
-    const double vN = ldv(L.v, L, i, j + 1), vS = ldv(L.v, L, i, j);
-    // faces that lie on a wall carry no flux (the mirrored ghost equals the cell)
-    const double wE = (L.bcx || i < L.m1 - 1) ? 1.0 : 0.0, wW = (L.bcx || i > 0) ? 1.0 : 0.0;
-    const double wN = (L.bcy || j < L.m2 - 1) ? 1.0 : 0.0, wS = (L.bcy || j > 0) ? 1.0 : 0.0;
-
-    const double rn = rho_of(P, n), rnE = rho_of(P, nE), rnW = rho_of(P, nW), rnN = rho_of(P, nN), rnS = rho_of(P, nS);
-    const double rs = rho_of(P, c);
-    // mobility m(c^n) averaged to the faces (A m)
-    const double m0 = mob_of(P, n);
-    const double mE = 0.5 * (mob_of(P, nE) + m0) * wE, mW = 0.5 * (mob_of(P, nW) + m0) * wW;
-    const double mN = 0.5 * (mob_of(P, nN) + m0) * wN, mS = 0.5 * (mob_of(P, nS) + m0) * wS;
-    const double Lmu = ih2 * (mE * (muE - mu) - mW * (mu - muW) + mN * (muN - mu) - mS * (mu - muS));
-    const double Lp = ih2 * (mE * (pE - p) - mW * (p - pW) + mN * (pN - p) - mS * (p - pS));
-    const double Sm = ih2 * (mE + mW + mN + mS);
-
-    CellEq e;
-    // advection rho^n u . grad c^n in the special form of App. A.5
-    const double adv = 0.5 * ih * (rnE * (nE - n) * uE + rnW * (n - nW) * uW + rnN * (nN - n) * vN + rnS * (n - nS) * vS);
-    e.Nc = rs * (c - n) * P.inv_dt + adv - P.inv_Pe * Lmu - P.alpha * P.inv_Pe * Lp;
-    e.Np = ih * (uE - uW + vN - vS) - P.alpha * P.inv_Pe * Lmu - P.alpha * P.alpha * P.inv_Pe * Lp;
-
-    // chemical potential: time averages of sec. 4.1, pointwise |grad_D c|^2
+    const double c = tq(T, T_C, e), n = tq(T, T_CN, e), mu = tq(T, T_MU, e);
+    const double rs = tq(T, T_RS, e), rn = tq(T, T_RN, e);
+    CellEq q;
+    q.Nc = rs * (c - n) * P.inv_dt + s.adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp;
+    q.Np = s.div - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp;
+    // time averages of sec. 4.1; pointwise |grad_D c|^2 = a_x((D_x c)^2) + a_y((D_y c)^2)
     const double rh = 0.5 * (rs + rn);
     const double q1 = c * (c - 1.0), q0 = n * (n - 1.0);
     const double g = 0.25 * (q1 + q0) * (c + n - 1.0);
     const double Fh = 0.5 * (dwell(c) + dwell(n));
     const double r = -P.alpha * rs * rn;
-    const double dE = cE - c, dW = c - cW, dN = cN - c, dS = c - cS;
-    const double Gc = 0.5 * ih2 * (dE * dE + dW * dW + dN * dN + dS * dS);
-    const double eE = nE - n, eW = n - nW, eN = nN - n, eS = n - nS;
-    const double Gn = 0.5 * ih2 * (eE * eE + eW * eW + eN * eN + eS * eS);
-    const double Gh = 0.5 * (Gc + Gn);
-    // div_d(A rho^{n+1/2} grad_D c^{n+1/2}); rho^{n+1/2} of a neighbour from its c and c^n
-    const double rhE = 0.5 * (rho_of(P, cE) + rnE), rhW = 0.5 * (rho_of(P, cW) + rnW);
-    const double rhN = 0.5 * (rho_of(P, cN) + rnN), rhS = 0.5 * (rho_of(P, cS) + rnS);
-    const double kE = 0.5 * (rhE + rh) * wE, kW = 0.5 * (rhW + rh) * wW, kN = 0.5 * (rhN + rh) * wN, kS = 0.5 * (rhS + rh) * wS;
-    const double hE = 0.5 * (dE + eE), hW = 0.5 * (dW + eW), hN = 0.5 * (dN + eN), hS = 0.5 * (dS + eS);
-    const double Lr = ih2 * (kE * hE - kW * hW + kN * hN - kS * hS);
-    e.Nmu = rs * mu - P.K1 * (rh * g + Fh * r) - P.K2 * Gh * r + P.K3 * Lr;
-
+    const double Gh = 0.5 * (s.Gc + s.Gn);
+    q.Nmu = rs * mu - P.K1 * (rh * g + Fh * r) - P.K2 * Gh * r + P.K3 * s.Lr;
     // Jacobian in (c_ij, mubar_ij); rho' = -alpha rho^2
     const double drs = -P.alpha * rs * rs;
-    e.Jcc = (drs * (c - n) + rs) * P.inv_dt;
-    e.Jcm = P.inv_Pe * Sm;
-    e.Jmm = rs;
+    q.Jcc = (drs * (c - n) + rs) * P.inv_dt;
+    q.Jcm = P.inv_Pe * s.Sm;
+    q.Jmm = rs;
     const double dg = 0.25 * ((2.0 * c - 1.0) * (c + n - 1.0) + q1 + q0);
-    const double f1 = q1 * (c - 0.5);                  // F'(c)
+    const double f1 = q1 * (c - 0.5);                   // F'(c)
     const double dr = P.alpha * P.alpha * rs * rs * rn; // dr/dc
-    const double dGc = ih2 * (wE * (-dE) + wW * dW + wN * (-dN) + wS * dS);
-    // d Lr / dc: the cell's own rho^{n+1/2} and c^{n+1/2} both move
-    const double dLr = ih2 * (0.25 * drs * (wE * hE - wW * hW + wN * hN - wS * hS) - 0.5 * (kE + kW + kN + kS));
-    e.Jmc = drs * mu - P.K1 * (0.5 * drs * g + rh * dg + 0.5 * f1 * r + Fh * dr) - P.K2 * (0.5 * dGc * r + Gh * dr) + P.K3 * dLr;
-    e.Jpp = P.alpha * P.alpha * P.inv_Pe * Sm;
-    return e;
+    const double dLr = 0.25 * drs * s.dLra - 0.5 * s.dLrb;
+    q.Jmc = drs * mu - P.K1 * (0.5 * drs * g + rh * dg + 0.5 * f1 * r + Fh * dr) - P.K2 * (0.5 * s.dGc * r + Gh * dr)
+          + P.K3 * dLr;
+    q.Jpp = P.alpha * P.alpha * P.inv_Pe * s.Sm;
+    return q;
 }
 
 // --------------------------------------------------------------------------
-// momentum equations (pm-num-mx) at a face, with the derivative with respect
-// to the face's own velocity.  The advection (e1e1-1) plus the half-divergence
-// term (e1e1-2) are combined into their skew form
-//   1/(2h) [w_R u_{i+1} - w_L u_{i-1} + Z_t u_{j+1} - Z_b u_{j-1}],
+// momentum equation (pm-num-mx) on the face stored at element ef (the west
+// face of its cell on the x lane, the south face on the y lane), with the
+// derivative with respect to the face's own velocity.  Advection (e1e1-1) plus
+// the half-divergence term (e1e1-2) are used in their skew form
+//   1/(2h) [w_R u_{+1} - w_L u_{-1} + Z_t u_{t+1} - Z_b u_{t-1}],
 // which is the same sum with the terms on the face's own value cancelled.
-
+// (it = tangential index of the face's row.)
 struct FaceEq {
     double N, diag;
 };
 
-__device__ __forceinline__ FaceEq eq_u(const Phys &P, const View &L, int i, int j)
+__device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax &a, int ef, int it, double ih)
 {
-    const double ih = L.inv_h, ih2 = ih * ih;
-    // cells L = (i-1, j), R = (i, j) and the rows above and below
-    const double nL = ldc(L.cn, L, i - 1, j), nR = ldc(L.cn, L, i, j);
-    const double nLt = ldc(L.cn, L, i - 1, j + 1), nRt = ldc(L.cn, L, i, j + 1);
-    const double nLb = ldc(L.cn, L, i - 1, j - 1), nRb = ldc(L.cn, L, i, j - 1);
-    const double rL = rho_of(P, nL), rR = rho_of(P, nR);
-    const double Rt = 0.25 * (rL + rR + rho_of(P, nLt) + rho_of(P, nRt));
-    const double Rb = 0.25 * (rL + rR + rho_of(P, nLb) + rho_of(P, nRb));
-    const double mvL = visc_of(P, nL), mvR = visc_of(P, nR);
-    const double nut = 0.25 * (mvL + mvR + visc_of(P, nLt) + visc_of(P, nRt));
-    const double nub = 0.25 * (mvL + mvR + visc_of(P, nLb) + visc_of(P, nRb));
+    const double ih2 = ih * ih;
+    const int eL = ef - a.dn, eR = ef, dt = a.dt;
+    const double rL = tq(T, T_RN, eL), rR = tq(T, T_RN, eR);
+    const double Rt = 0.25 * (rL + rR + tq(T, T_RN, eL + dt) + tq(T, T_RN, eR + dt));
+    const double Rb = 0.25 * (rL + rR + tq(T, T_RN, eL - dt) + tq(T, T_RN, eR - dt));
+    const double mvL = tq(T, T_MV, eL), mvR = tq(T, T_MV, eR);
+    const double nut = 0.25 * (mvL + mvR + tq(T, T_MV, eL + dt) + tq(T, T_MV, eR + dt));
+    const double nub = 0.25 * (mvL + mvR + tq(T, T_MV, eL - dt) + tq(T, T_MV, eR - dt));
     const double Arn = 0.5 * (rL + rR);
-    const double Ars = 0.5 * (rho_of(P, ldc(L.c, L, i - 1, j)) + rho_of(P, ldc(L.c, L, i, j)));
-    const double un0 = ldu(L.un, L, i, j);
-    const double wL = rL * 0.5 * (ldu(L.un, L, i - 1, j) + un0);
-    const double wR = rR * 0.5 * (un0 + ldu(L.un, L, i + 1, j));
-    const double Vt = 0.5 * (ldv(L.vn, L, i - 1, j + 1) + ldv(L.vn, L, i, j + 1));
-    const double Vb = 0.5 * (ldv(L.vn, L, i - 1, j) + ldv(L.vn, L, i, j));
-    const double u0 = ldu(L.u, L, i, j), uE = ldu(L.u, L, i + 1, j), uW = ldu(L.u, L, i - 1, j);
-    const double uN = ldu(L.u, L, i, j + 1), uS = ldu(L.u, L, i, j - 1);
-    const double thR = ih * (uE - u0 + ldv(L.v, L, i, j + 1) - ldv(L.v, L, i, j));
-    const double thL = ih * (u0 - uW + ldv(L.v, L, i - 1, j + 1) - ldv(L.v, L, i - 1, j));
-    const double pL = ldc(L.p, L, i - 1, j), pR = ldc(L.p, L, i, j);
-    const double muL = ldc(L.mu, L, i - 1, j), muR = ldc(L.mu, L, i, j);
-
-    FaceEq e;
-    e.N = Arn * (u0 - un0) * P.inv_dt
+    const double Ars = 0.5 * (tq(T, T_RS, eL) + tq(T, T_RS, eR));
+    const double un0 = tq(T, a.FNN, ef);
+    const double wL = rL * 0.5 * (tq(T, a.FNN, ef - a.dn) + un0);
+    const double wR = rR * 0.5 * (un0 + tq(T, a.FNN, ef + a.dn));
+    const double Vt = 0.5 * (tq(T, a.FTN, eL + dt) + tq(T, a.FTN, eR + dt));
+    const double Vb = 0.5 * (tq(T, a.FTN, eL) + tq(T, a.FTN, eR));
+    const double u0 = tq(T, a.FN, ef), uE = tq(T, a.FN, ef + a.dn), uW = tq(T, a.FN, ef - a.dn);
+    const double uN = tq(T, a.FN, ef + dt), uS = tq(T, a.FN, ef - dt);
+    const double thR = ih * (uE - u0 + tq(T, a.FT, eR + dt) - tq(T, a.FT, eR));
+    const double thL = ih * (u0 - uW + tq(T, a.FT, eL + dt) - tq(T, a.FT, eL));
+    const double nL = tq(T, T_CN, eL), nR = tq(T, T_CN, eR);
+    FaceEq q;
+    q.N = Arn * (u0 - un0) * P.inv_dt
         + 0.5 * ih * (wR * uE - wL * uW + Rt * Vt * uN - Rb * Vb * uS)
         + 0.5 * (Ars - Arn) * P.inv_dt * u0
-        + P.inv_M * ih * (pR - pL)
-        - P.inv_M * ih * 0.5 * (rR * muL + rL * muR) * (nR - nL)
+        + P.inv_M * ih * (tq(T, T_P, eR) - tq(T, T_P, eL))
+        - P.inv_M * ih * 0.5 * (rR * tq(T, T_MU, eL) + rL * tq(T, T_MU, eR)) * (nR - nL)
         - P.inv_Re * ih2 * (mvR * (uE - u0) - mvL * (u0 - uW) + nut * (uN - u0) - nub * (u0 - uS))
-        - (P.inv_Re / 3.0) * ih * (mvR * thR - mvL * thL);
-    // own-face derivative; across a y-wall the reflected ghost doubles the
-    // viscous coupling and the advection coefficient enters with a sign flip
-    const bool gt = !L.bcy && j == L.m2 - 1, gb = !L.bcy && j == 0;
-    e.diag = 0.5 * (Arn + Ars) * P.inv_dt + (4.0 / 3.0) * P.inv_Re * ih2 * (mvL + mvR)
-           + P.inv_Re * ih2 * (nut * (gt ? 2.0 : 1.0) + nub * (gb ? 2.0 : 1.0))
-           + 0.5 * ih * ((gb ? Rb * Vb : 0.0) - (gt ? Rt * Vt : 0.0));
-    return e;
+        - (P.inv_Re / 3.0) * ih * (mvR * thR - mvL * thL)
+        + a.grav * P.inv_Fr * (Arn - P.rho_ref);
+    // own-face derivative; across a tangential wall the reflected ghost doubles
+    // the viscous coupling and the advection coefficient enters with a sign flip
+    const double gt = (!a.pert && it == a.mt - 1) ? 1.0 : 0.0, gb = (!a.pert && it == 0) ? 1.0 : 0.0;
+    q.diag = 0.5 * (Arn + Ars) * P.inv_dt + (4.0 / 3.0) * P.inv_Re * ih2 * (mvL + mvR)
+           + P.inv_Re * ih2 * (nut * (1.0 + gt) + nub * (1.0 + gb)) + 0.5 * ih * (gb * Rb * Vb - gt * Rt * Vt);
+    return q;
 }
 
-__device__ __forceinline__ FaceEq eq_v(const Phys &P, const View &L, int i, int j)
-{
-    const double ih = L.inv_h, ih2 = ih * ih;
-    // cells B = (i, j-1), T = (i, j) and the columns left and right
-    const double nB = ldc(L.cn, L, i, j - 1), nT = ldc(L.cn, L, i, j);
-    const double nBr = ldc(L.cn, L, i + 1, j - 1), nTr = ldc(L.cn, L, i + 1, j);
-    const double nBl = ldc(L.cn, L, i - 1, j - 1), nTl = ldc(L.cn, L, i - 1, j);
-    const double rB = rho_of(P, nB), rT = rho_of(P, nT);
-    const double Rr = 0.25 * (rB + rT + rho_of(P, nBr) + rho_of(P, nTr));
-    const double Rl = 0.25 * (rB + rT + rho_of(P, nBl) + rho_of(P, nTl));
-    const double mvB = visc_of(P, nB), mvT = visc_of(P, nT);
-    const double nur = 0.25 * (mvB + mvT + visc_of(P, nBr) + visc_of(P, nTr));
-    const double nul = 0.25 * (mvB + mvT + visc_of(P, nBl) + visc_of(P, nTl));
-    const double Arn = 0.5 * (rB + rT);
-    const double Ars = 0.5 * (rho_of(P, ldc(L.c, L, i, j - 1)) + rho_of(P, ldc(L.c, L, i, j)));
-    const double vn0 = ldv(L.vn, L, i, j);
-    const double wB = rB * 0.5 * (ldv(L.vn, L, i, j - 1) + vn0);
-    const double wT = rT * 0.5 * (vn0 + ldv(L.vn, L, i, j + 1));
-    const double Ur = 0.5 * (ldu(L.un, L, i + 1, j - 1) + ldu(L.un, L, i + 1, j));
-    const double Ul = 0.5 * (ldu(L.un, L, i, j - 1) + ldu(L.un, L, i, j));
-    const double v0 = ldv(L.v, L, i, j), vN = ldv(L.v, L, i, j + 1), vS = ldv(L.v, L, i, j - 1);
-    const double vE = ldv(L.v, L, i + 1, j), vW = ldv(L.v, L, i - 1, j);
-    const double thT = ih * (ldu(L.u, L, i + 1, j) - ldu(L.u, L, i, j) + vN - v0);
-    const double thB = ih * (ldu(L.u, L, i + 1, j - 1) - ldu(L.u, L, i, j - 1) + v0 - vS);
-    const double pB = ldc(L.p, L, i, j - 1), pT = ldc(L.p, L, i, j);
-    const double muB = ldc(L.mu, L, i, j - 1), muT = ldc(L.mu, L, i, j);
-
-    FaceEq e;
-    e.N = Arn * (v0 - vn0) * P.inv_dt
-        + 0.5 * ih * (Rr * Ur * vE - Rl * Ul * vW + wT * vN - wB * vS)
-        + 0.5 * (Ars - Arn) * P.inv_dt * v0
-        + P.inv_M * ih * (pT - pB)
-        - P.inv_M * ih * 0.5 * (rT * muB + rB * muT) * (nT - nB)
-        - P.inv_Re * ih2 * (nur * (vE - v0) - nul * (v0 - vW) + mvT * (vN - v0) - mvB * (v0 - vS))
-        - (P.inv_Re / 3.0) * ih * (mvT * thT - mvB * thB)
-        + P.inv_Fr * (Arn - P.rho_ref);
-    const bool gr = !L.bcx && i == L.m1 - 1, gl = !L.bcx && i == 0;
-    e.diag = 0.5 * (Arn + Ars) * P.inv_dt + (4.0 / 3.0) * P.inv_Re * ih2 * (mvB + mvT)
-           + P.inv_Re * ih2 * (nur * (gr ? 2.0 : 1.0) + nul * (gl ? 2.0 : 1.0))
-           + 0.5 * ih * ((gl ? Rl * Ul : 0.0) - (gr ? Rr * Ur : 0.0));
-    return e;
-}
-
-// --------------------------------------------------------------------------
-// smoother for one cell of the current colour (sec. 7.1)
-
-struct Rhs {
-    const double *fc, *fmu, *fp, *fu, *fv; // FAS right-hand side; NULL = 0
-};
 __device__ __forceinline__ double ldf(const double *f, const View &L, int i, int j)
 {
     return f ? f[(size_t)j * L.pitch + i] : 0.0;
 }
 
-// Step 1 (CH point Newton) and step 2 (Vanka box) at cell (i,j).  Velocities
-// are read from L.u/L.v (the snapshot of this colour) and the box faces are
-// written to unew/vnew; c, mubar, pbar are updated in place.
-__device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const Rhs &F, double *unew, double *vnew,
-                                           int i, int j, double omega)
+// --------------------------------------------------------------------------
+// smoother for one cell of the current colour (sec. 7.1), run by a lane pair.
+// Step 1: Newton on (N_c, N_mu) in (c_ij, mubar_ij).  Step 2: Vanka box on
+// (uW, uE, vS, vN, p).  Velocities come from the tile (the snapshot of this
+// colour); the box faces go to unew/vnew, c, mubar, pbar to the level arrays.
+// c, mubar and rho(c) of the cell are also written to the tile (identical
+// values from both lanes), which no other pair of this colour reads.
+__device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
+                                           double *vnew, int i, int j, int hlf, double omega)
 {
     const size_t k = (size_t)j * L.pitch + i;
-    // ---- step 1: Newton on (N_c, N_mu) in (c_ij, mubar_ij)
-    {
-        CellEq e = eq_cell(P, L, i, j);
-        const double r1 = ldf(F.fc, L, i, j) - e.Nc, r2 = ldf(F.fmu, L, i, j) - e.Nmu;
-        const double det = e.Jcc * e.Jmm - e.Jcm * e.Jmc;
-        const double dc = (e.Jmm * r1 - e.Jcm * r2) / det;
-        const double dm = (e.Jcc * r2 - e.Jmc * r1) / det;
-        L.c[k] += dc;
-        L.mu[k] += dm;
-    }
-    // ---- step 2: Vanka box, unknowns (uW, uE, vS, vN, p)
-    const int ie = i + 1 < L.m1 ? i + 1 : 0; // storage column of the east face (periodic)
-    const int jn = j + 1 < L.m2 ? j + 1 : 0;
-    const bool hW = u_unk(L, i), hE = L.bcx || i + 1 < L.m1;
-    const bool hS = v_unk(L, j), hN = L.bcy || j + 1 < L.m2;
     const double ih = L.inv_h, ih2 = ih * ih;
-    double A[5][5], b[5];
-    for (int r = 0; r < 5; r++)
-        for (int s = 0; s < 5; s++) A[r][s] = 0.0;
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    // ---- step 1
+    CellAx x = cell_axis(T, a, e, ih);
+    CellAx s = cell_sum(x);
+    CellEq q = cell_eq(P, T, e, s);
+    const double r1 = ldf(F.fc, L, i, j) - q.Nc, r2 = ldf(F.fmu, L, i, j) - q.Nmu;
+    const double idet = frcp(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
+    const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e);
+    const double cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
+    const double mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
+    if (hlf == 0) {
+        L.c[k] = cnew;
+        L.mu[k] = mnew;
+    }
+    T.s[T_C * T.W * T.H + e] = cnew;
+    T.s[T_MU * T.W * T.H + e] = mnew;
+    T.s[T_RS * T.W * T.H + e] = rho_of(P, cnew);
+    // ---- step 2: this lane's two faces along its axis
+    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
+    const FaceEq flo = face_eq(P, T, a, e, a.it, ih);
+    const FaceEq fhi = face_eq(P, T, a, e + a.dn, a.it, ih);
+    const double *fN = hlf ? F.fv : F.fu;
+    const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
+    const size_t khi = (size_t)jhi * L.pitch + ihi;
+    const double blo = hlo ? ldf(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
+    const double bhi = hhi ? ldf(fN, L, ihi, jhi) - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
+    // mass equation with the new mubar of the cell (linear in it: -Sm per axis)
+    const double Lmu_new = s.Lmu - s.Sm * (mnew - m0);
+    const double bp = ldf(F.fp, L, i, j) - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
     // box-cell coefficients of the off-diagonal couplings
-    const double n0 = ldc(L.cn, L, i, j);
-    const double r0 = rho_of(P, n0), mv0 = visc_of(P, n0);
-    const double wx = r0 * 0.5 * (ldu(L.un, L, i, j) + ldu(L.un, L, i + 1, j)); // rho^n a_x u^n at the cell
-    const double wy = r0 * 0.5 * (ldv(L.vn, L, i, j) + ldv(L.vn, L, i, j + 1));
+    const double w_ax = tq(T, T_RN, e) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn)); // rho^n a u^n
+    const double mv0 = tq(T, T_MV, e);
     const double vis = (4.0 / 3.0) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0;
     const double gp = P.inv_M * ih;
-    if (hW) {
-        FaceEq e = eq_u(P, L, i, j);
-        A[0][0] = e.diag; A[0][1] = 0.5 * ih * wx - vis; A[0][2] = gd; A[0][3] = -gd; A[0][4] = gp;
-        b[0] = ldf(F.fu, L, i, j) - e.N;
-    } else { A[0][0] = 1.0; b[0] = 0.0; }
-    if (hE) {
-        FaceEq e = eq_u(P, L, i + 1, j);
-        A[1][1] = e.diag; A[1][0] = -0.5 * ih * wx - vis; A[1][2] = -gd; A[1][3] = gd; A[1][4] = -gp;
-        b[1] = ldf(F.fu, L, ie, j) - e.N;
-    } else { A[1][1] = 1.0; b[1] = 0.0; }
-    if (hS) {
-        FaceEq e = eq_v(P, L, i, j);
-        A[2][2] = e.diag; A[2][3] = 0.5 * ih * wy - vis; A[2][0] = gd; A[2][1] = -gd; A[2][4] = gp;
-        b[2] = ldf(F.fv, L, i, j) - e.N;
-    } else { A[2][2] = 1.0; b[2] = 0.0; }
-    if (hN) {
-        FaceEq e = eq_v(P, L, i, j + 1);
-        A[3][3] = e.diag; A[3][2] = -0.5 * ih * wy - vis; A[3][0] = -gd; A[3][1] = gd; A[3][4] = -gp;
-        b[3] = ldf(F.fv, L, i, jn) - e.N;
-    } else { A[3][3] = 1.0; b[3] = 0.0; }
-    {
-        CellEq e = eq_cell(P, L, i, j);
-        A[4][0] = hW ? -ih : 0.0; A[4][1] = hE ? ih : 0.0; A[4][2] = hS ? -ih : 0.0; A[4][3] = hN ? ih : 0.0;
-        A[4][4] = e.Jpp;
-        b[4] = ldf(F.fp, L, i, j) - e.Np;
-    }
+    // exchange: the pair now holds the x rows (lane 0) and the y rows (lane 1)
+    const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const int o_hlo = __shfl_xor((int)hlo, 1, 64), o_hhi = __shfl_xor((int)hhi, 1, 64);
+    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
+    const double wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
+    double A[5][5], b[5];
+    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi; b[4] = bp;
+    const double d0 = hlf ? o_dlo : dlo, d1 = hlf ? o_dhi : dhi, d2 = hlf ? dlo : o_dlo, d3 = hlf ? dhi : o_dhi;
+    // rows: momentum at uW, uE, vS, vN, then mass; columns in the same order;
+    // a face on a wall is not an unknown (identity row, no coupling)
+    const double mW = xl ? 1.0 : 0.0, mE = xh ? 1.0 : 0.0, mS = yl ? 1.0 : 0.0, mN = yh ? 1.0 : 0.0;
+    A[0][0] = d0; A[0][1] = mW * (0.5 * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd; A[0][4] = mW * gp;
+    A[1][1] = d1; A[1][0] = mE * (-0.5 * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd; A[1][4] = -mE * gp;
+    A[2][2] = d2; A[2][3] = mS * (0.5 * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
+    A[3][3] = d3; A[3][2] = mN * (-0.5 * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
+    A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
     // Gaussian elimination in the order u, u, v, v, p: the velocity block has a
     // positive definite symmetric part (mass + viscous; advection is skew) and
     // the last pivot is the positive pressure Schur complement
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const double inv = 1.0 / A[q][q];
+    for (int c = 0; c < 4; c++) {
+        const double inv = frcp(A[c][c]);
 #pragma unroll
-        for (int r = q + 1; r < 5; r++) {
-            const double l = A[r][q] * inv;
+        for (int r = c + 1; r < 5; r++) {
+            const double l = A[r][c] * inv;
 #pragma unroll
-            for (int s = q + 1; s < 5; s++) A[r][s] -= l * A[q][s];
-            b[r] -= l * b[q];
+            for (int t = c + 1; t < 5; t++) A[r][t] -= l * A[c][t];
+            b[r] -= l * b[c];
         }
     }
 #pragma unroll
-    for (int q = 4; q >= 0; q--) {
-        double s = b[q];
+    for (int c = 4; c >= 0; c--) {
+        double acc = b[c];
 #pragma unroll
-        for (int t = q + 1; t < 5; t++) s -= A[q][t] * b[t];
-        b[q] = s / A[q][q];
+        for (int t = c + 1; t < 5; t++) acc -= A[c][t] * b[t];
+        b[c] = acc * frcp(A[c][c]);
     }
-    if (hW) unew[k] = L.u[k] + omega * b[0];
-    if (hE) unew[(size_t)j * L.pitch + ie] = L.u[(size_t)j * L.pitch + ie] + omega * b[1];
-    if (hS) vnew[k] = L.v[k] + omega * b[2];
-    if (hN) vnew[(size_t)jn * L.pitch + i] = L.v[(size_t)jn * L.pitch + i] + omega * b[3];
-    L.p[k] += omega * b[4];
+    double *dst = hlf ? vnew : unew;
+    const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
+    if (hlo) dst[k] = tq(T, a.FN, e) + omega * dl;
+    if (hhi) dst[khi] = tq(T, a.FN, e + a.dn) + omega * dh;
+    if (hlf == 0) L.p[k] = tq(T, T_P, e) + omega * b[4];
+}
+
+// residuals r = f - N(w) of the five equations attached to cell (i,j): the
+// cell equations and the momentum equation of its west face (lane 0) or south
+// face (lane 1); zero for a face on a wall.  Both lanes return rc, rm, rp;
+// rf is this lane's face residual.
+__device__ __forceinline__ void resid_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j,
+                                           int hlf, double &rc, double &rm, double &rp, double &rf)
+{
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    const CellAx s = cell_sum(cell_axis(T, a, e, L.inv_h));
+    const CellEq q = cell_eq(P, T, e, s);
+    rc = ldf(F.fc, L, i, j) - q.Nc;
+    rm = ldf(F.fmu, L, i, j) - q.Nmu;
+    rp = ldf(F.fp, L, i, j) - q.Np;
+    const bool hlo = a.per || a.ia >= 1;
+    const FaceEq f = face_eq(P, T, a, e, a.it, L.inv_h);
+    rf = hlo ? ldf(hlf ? F.fv : F.fu, L, i, j) - f.N : 0.0;
 }
 
 } // namespace qn

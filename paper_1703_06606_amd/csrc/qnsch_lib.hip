@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "qnsch.h"
@@ -25,38 +26,113 @@ using namespace qn;
 // ===========================================================================
 // kernels
 
-// one colour half-sweep: one thread per cell of the colour (colour-compressed
-// indexing; rows of m1/2 cells)
-__global__ __launch_bounds__(BLK) void k_halfsweep(Phys P, View L, Rhs F, double *unew, double *vnew, int colour,
-                                                   double omega)
+// Tiles of TX x TY cells; TX even so that the colour of a cell is fixed by its
+// parity inside the tile.  Static LDS: T_NF * (TX+3) * (TY+3) doubles.  Tile
+// kernels run TX*TY threads: a lane pair per cell of one colour (half-sweeps)
+// or a lane pair per two cells (residual kernels).
+#define TX 32
+#define TY 16
+#define TBLK (TX * TY)
+#define TILE_DOUBLES (T_NF * (TX + 3) * (TY + 3))
+static_assert(TILE_DOUBLES * 8 + 16 * NRED * 8 <= 65536, "tile exceeds 64 KiB of LDS");
+
+__device__ __forceinline__ Tile block_tile(double *sm)
 {
-    const int half = L.m1 >> 1;
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= half * L.m2) return;
-    const int j = t / half;
-    const int i = 2 * (t - j * half) + ((j + colour) & 1);
-    relax_cell(P, L, F, unew, vnew, i, j, omega);
+    Tile T;
+    T.s = sm;
+    T.i0 = blockIdx.x * TX;
+    T.j0 = blockIdx.y * TY;
+    T.W = TX + 3;
+    T.H = TY + 3;
+    return T;
 }
 
-// all sweeps of the coarsest level in one workgroup; the u/v buffers alternate
-// (a -> b -> a ...), the number of half-sweeps is even so the result is in a
-__global__ __launch_bounds__(1024) void k_coarse_solve(Phys P, View L, Rhs F, double *ua, double *va, double *ub,
-                                                       double *vb, int sweeps, double omega)
+// one colour half-sweep on a tile.  The finest level (no FAS right-hand side)
+// and the coarse levels are separate kernels so that profiles tell them apart.
+__device__ __forceinline__ void halfsweep_body(const Phys &P, const View &L, const Rhs &F, double *unew,
+                                               double *vnew, int colour, double omega)
 {
-    const int half = L.m1 >> 1;
-    const int n = half * L.m2;
+    __shared__ double sm[TILE_DOUBLES];
+    const Tile T = block_tile(sm);
+    tile_load(P, L, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    const int lj = pr / (TX / 2), k = pr - lj * (TX / 2);
+    const int j = T.j0 + lj;
+    const int i = T.i0 + 2 * k + ((j + colour) & 1);
+    if (i < L.m1 && j < L.m2) relax_pair(P, L, T, F, unew, vnew, i, j, hlf, omega);
+}
+__global__ __launch_bounds__(TBLK) void k_halfsweep_fine(Phys P, View L, double *unew, double *vnew, int colour,
+                                                         double omega)
+{
+    const Rhs F = { nullptr, nullptr, nullptr, nullptr, nullptr };
+    halfsweep_body(P, L, F, unew, vnew, colour, omega);
+}
+__global__ __launch_bounds__(TBLK) void k_halfsweep_coarse(Phys P, View L, Rhs F, double *unew, double *vnew,
+                                                           int colour, double omega)
+{
+    halfsweep_body(P, L, F, unew, vnew, colour, omega);
+}
+
+// plain copy, used to measure the copy bandwidth and to calibrate counters
+__global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a, double *__restrict__ b, size_t n)
+{
+    for (size_t k = (size_t)blockIdx.x * BLK + threadIdx.x; k < n; k += (size_t)gridDim.x * BLK) b[k] = a[k];
+}
+
+// LDS bytes of the coarsest-level solve: 15 level arrays + one tile
+__host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
+{
+    return (size_t)15 * m1 * m2 + (size_t)T_NF * (m1 + 3) * (m2 + 3);
+}
+
+// all sweeps of the coarsest level in one workgroup with the whole level
+// resident in LDS; the u/v buffers alternate (a -> b -> a ...), the number of
+// half-sweeps is even, so the result is in a
+__global__ __launch_bounds__(512) void k_coarse_solve(Phys P, View L, Rhs F, double *ua, double *va, int sweeps,
+                                                      double omega)
+{
+    extern __shared__ double sm[];
+    const int m1 = L.m1, m2 = L.m2, n = m1 * m2;
+    double *hc = sm, *hmu = sm + n, *hp = sm + 2 * n, *uA = sm + 3 * n, *vA = sm + 4 * n, *uB = sm + 5 * n,
+           *vB = sm + 6 * n, *hcn = sm + 7 * n, *hun = sm + 8 * n, *hvn = sm + 9 * n, *hf = sm + 10 * n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t k = (size_t)j * L.pitch + i;
+        hc[e] = L.c[k]; hmu[e] = L.mu[k]; hp[e] = L.p[k]; uA[e] = ua[k]; vA[e] = va[k];
+        hcn[e] = L.cn[k]; hun[e] = L.un[k]; hvn[e] = L.vn[k];
+        hf[e] = F.fc ? F.fc[k] : 0.0;
+        hf[n + e] = F.fmu ? F.fmu[k] : 0.0;
+        hf[2 * n + e] = F.fp ? F.fp[k] : 0.0;
+        hf[3 * n + e] = F.fu ? F.fu[k] : 0.0;
+        hf[4 * n + e] = F.fv ? F.fv[k] : 0.0;
+    }
+    __syncthreads();
+    View H = L;
+    H.c = hc; H.mu = hmu; H.p = hp; H.cn = hcn; H.un = hun; H.vn = hvn; H.pitch = m1;
+    const Rhs FH = { hf, hf + n, hf + 2 * n, hf + 3 * n, hf + 4 * n };
+    Tile T;
+    T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    const int half = m1 >> 1;
     for (int s = 0; s < 2 * sweeps; s++) {
         const int colour = s & 1;
-        View V = L;
         double *uw, *vw;
-        if (s & 1) { V.u = ub; V.v = vb; uw = ua; vw = va; }
-        else { V.u = ua; V.v = va; uw = ub; vw = vb; }
-        for (int t = threadIdx.x; t < n; t += blockDim.x) {
-            const int j = t / half;
-            const int i = 2 * (t - j * half) + ((j + colour) & 1);
-            relax_cell(P, V, F, uw, vw, i, j, omega);
+        if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
+        else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
+        tile_load(P, H, T);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
+            const int pr = t >> 1;
+            const int j = pr / half;
+            const int i = 2 * (pr - j * half) + ((j + colour) & 1);
+            relax_pair(P, H, T, FH, uw, vw, i, j, t & 1, omega);
         }
         __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t k = (size_t)j * L.pitch + i;
+        L.c[k] = hc[e]; L.mu[k] = hmu[e]; L.p[k] = hp[e]; ua[k] = uA[e]; va[k] = vA[e];
     }
 }
 
@@ -69,66 +145,83 @@ struct Coarse {
 
 // fine residual r = f - N(w) restricted to the coarse grid together with the
 // iterate (cells: mean of the four children; faces: mean of the two coincident
-// fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w)
-__global__ __launch_bounds__(BLK) void k_restrict(Phys P, View Lf, Rhs F, Coarse C)
+// fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w).
+// A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane pair each.
+__global__ __launch_bounds__(TBLK) void k_restrict(Phys P, View Lf, Rhs F, Coarse C)
 {
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= C.m1 * C.m2) return;
-    const int J = t / C.m1, I = t - J * C.m1;
-    double rc = 0, rm = 0, rp = 0, sc = 0, sm = 0, sp = 0;
+    __shared__ double sm[TILE_DOUBLES];
+    const Tile T = block_tile(sm);
+    tile_load(P, Lf, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    if (pr >= (TX / 2) * (TY / 2)) return;
+    const int I = T.i0 / 2 + pr % (TX / 2), J = T.j0 / 2 + pr / (TX / 2);
+    if (I >= C.m1 || J >= C.m2) return;
+    double rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sp = 0, sf = 0;
+    const int fN = hlf ? T_V : T_U;
 #pragma unroll
     for (int b = 0; b < 2; b++)
 #pragma unroll
         for (int a = 0; a < 2; a++) {
             const int i = 2 * I + a, j = 2 * J + b;
-            const CellEq e = eq_cell(P, Lf, i, j);
-            rc += ldf(F.fc, Lf, i, j) - e.Nc;
-            rm += ldf(F.fmu, Lf, i, j) - e.Nmu;
-            rp += ldf(F.fp, Lf, i, j) - e.Np;
-            const size_t k = (size_t)j * Lf.pitch + i;
-            sc += Lf.c[k];
-            sm += Lf.mu[k];
-            sp += Lf.p[k];
+            double xc, xm, xp, xf;
+            resid_pair(P, Lf, T, F, i, j, hlf, xc, xm, xp, xf);
+            rc += xc; rm += xm; rp += xp;
+            // the lane's face of the coarse cell: west faces (a = 0) on the x
+            // lane, south faces (b = 0) on the y lane
+            if ((hlf ? b : a) == 0) { rf += xf; sf += T.q(fN, i, j); }
+            sc += T.q(T_C, i, j); smu += T.q(T_MU, i, j); sp += T.q(T_P, i, j);
         }
-    double ru = 0, rv = 0, su = 0, sv = 0;
-#pragma unroll
-    for (int b = 0; b < 2; b++) {
-        const int i = 2 * I, j = 2 * J + b;
-        if (u_unk(Lf, i)) ru += ldf(F.fu, Lf, i, j) - eq_u(P, Lf, i, j).N;
-        su += Lf.u[(size_t)j * Lf.pitch + i];
-    }
-#pragma unroll
-    for (int a = 0; a < 2; a++) {
-        const int i = 2 * I + a, j = 2 * J;
-        if (v_unk(Lf, j)) rv += ldf(F.fv, Lf, i, j) - eq_v(P, Lf, i, j).N;
-        sv += Lf.v[(size_t)j * Lf.pitch + i];
-    }
     const size_t k = (size_t)J * C.pitch + I;
-    C.c[k] = C.c0[k] = 0.25 * sc;
-    C.mu[k] = C.mu0[k] = 0.25 * sm;
-    C.p[k] = C.p0[k] = 0.25 * sp;
-    C.u[k] = C.u0[k] = 0.5 * su;
-    C.v[k] = C.v0[k] = 0.5 * sv;
-    C.fc[k] = 0.25 * rc;
-    C.fmu[k] = 0.25 * rm;
-    C.fp[k] = 0.25 * rp;
-    C.fu[k] = 0.5 * ru;
-    C.fv[k] = 0.5 * rv;
+    if (hlf == 0) {
+        C.c[k] = C.c0[k] = 0.25 * sc;
+        C.mu[k] = C.mu0[k] = 0.25 * smu;
+        C.p[k] = C.p0[k] = 0.25 * sp;
+        C.fc[k] = 0.25 * rc;
+        C.fmu[k] = 0.25 * rm;
+        C.fp[k] = 0.25 * rp;
+        C.u[k] = C.u0[k] = 0.5 * sf;
+        C.fu[k] = 0.5 * rf;
+    } else {
+        C.v[k] = C.v0[k] = 0.5 * sf;
+        C.fv[k] = 0.5 * rf;
+    }
+}
+
+// the two cells of a tile handled by lane pair pr: (2k, lj) and (2k+1, lj)
+__device__ __forceinline__ void pair_cells(const Tile &T, int &i, int &j)
+{
+    const int pr = threadIdx.x >> 1;
+    const int lj = pr / (TX / 2), k = pr - lj * (TX / 2);
+    i = T.i0 + 2 * k;
+    j = T.j0 + lj;
 }
 
 // f_H = N_H(R w) + R r (FAS coarse right-hand side); walls carry no equation
-__global__ __launch_bounds__(BLK) void k_coarse_rhs(Phys P, View Lc, Coarse C)
+__global__ __launch_bounds__(TBLK) void k_coarse_rhs(Phys P, View Lc, Coarse C)
 {
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= C.m1 * C.m2) return;
-    const int J = t / C.m1, I = t - J * C.m1;
-    const size_t k = (size_t)J * C.pitch + I;
-    const CellEq e = eq_cell(P, Lc, I, J);
-    C.fc[k] += e.Nc;
-    C.fmu[k] += e.Nmu;
-    C.fp[k] += e.Np;
-    C.fu[k] = u_unk(Lc, I) ? C.fu[k] + eq_u(P, Lc, I, J).N : 0.0;
-    C.fv[k] = v_unk(Lc, J) ? C.fv[k] + eq_v(P, Lc, I, J).N : 0.0;
+    __shared__ double sm[TILE_DOUBLES];
+    const Tile T = block_tile(sm);
+    tile_load(P, Lc, T);
+    __syncthreads();
+    const int hlf = threadIdx.x & 1;
+    int i, j;
+    pair_cells(T, i, j);
+    const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
+    for (int a = 0; a < 2; a++, i++) {
+        if (i >= C.m1 || j >= C.m2) continue;
+        double rc, rm, rp, rf;
+        resid_pair(P, Lc, T, Z, i, j, hlf, rc, rm, rp, rf); // r = -N_H(R w)
+        const size_t k = (size_t)j * C.pitch + i;
+        if (hlf == 0) {
+            C.fc[k] -= rc;
+            C.fmu[k] -= rm;
+            C.fp[k] -= rp;
+            C.fu[k] = u_unk(Lc, i) ? C.fu[k] - rf : 0.0;
+        } else {
+            C.fv[k] = v_unk(Lc, j) ? C.fv[k] - rf : 0.0;
+        }
+    }
 }
 
 // w_h += P(w_H - R w_h): cells piecewise constant; faces copy the coincident
@@ -165,10 +258,11 @@ __global__ __launch_bounds__(BLK) void k_prolong(View Lf, double *uf, double *vf
     }
 }
 
-// wave64 + LDS block sum of NRED values; thread 0 writes the block's partials
-__device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out)
+// wave64 + LDS block sum of NRED values (blocks of up to 16 waves); one
+// partial row per block
+__device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out, int block)
 {
-    __shared__ double sh[BLK / 64][NRED];
+    __shared__ double sh[16][NRED];
 #pragma unroll
     for (int q = 0; q < NRED; q++)
 #pragma unroll
@@ -180,38 +274,43 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out)
     __syncthreads();
     if (threadIdx.x < NRED) {
         double s = 0.0;
-        for (int ww = 0; ww < BLK / 64; ww++) s += sh[ww][threadIdx.x];
-        out[(size_t)blockIdx.x * NRED + threadIdx.x] = s;
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) s += sh[ww][threadIdx.x];
+        out[(size_t)block * NRED + threadIdx.x] = s;
     }
 }
 
 // residual norms of the finest level: per block sums of r^2 for the five
 // equations, the sum of pbar, and the count of cells that are non-finite or
 // past the density pole; optionally the residual fields themselves
-__global__ __launch_bounds__(BLK) void k_resid_norm(Phys P, View L, Rhs F, double *partials, double *rout)
+__global__ __launch_bounds__(TBLK) void k_resid_norm(Phys P, View L, Rhs F, double *partials, double *rout)
 {
-    const int t = blockIdx.x * BLK + threadIdx.x;
+    __shared__ double sm[TILE_DOUBLES];
+    const Tile T = block_tile(sm);
+    tile_load(P, L, T);
+    __syncthreads();
     double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     const size_t n = (size_t)L.m1 * L.m2;
-    if (t < L.m1 * L.m2) {
-        const int j = t / L.m1, i = t - j * L.m1;
-        const CellEq e = eq_cell(P, L, i, j);
-        const double r0 = ldf(F.fc, L, i, j) - e.Nc, r1 = ldf(F.fmu, L, i, j) - e.Nmu, r2 = ldf(F.fp, L, i, j) - e.Np;
-        const double r3 = u_unk(L, i) ? ldf(F.fu, L, i, j) - eq_u(P, L, i, j).N : 0.0;
-        const double r4 = v_unk(L, j) ? ldf(F.fv, L, i, j) - eq_v(P, L, i, j).N : 0.0;
-        v[0] = r0 * r0; v[1] = r1 * r1; v[2] = r2 * r2; v[3] = r3 * r3; v[4] = r4 * r4;
-        const size_t k = (size_t)j * L.pitch + i;
-        v[5] = L.p[k];
-        const double c = L.c[k];
-        const bool ok = isfinite(c) && isfinite(L.mu[k]) && isfinite(L.p[k]) && isfinite(L.u[k]) && isfinite(L.v[k])
-                      && (P.drho * c + P.rho1 > 0.0);
-        v[6] = ok ? 0.0 : 1.0;
-        if (rout) {
-            const size_t q = (size_t)j * L.m1 + i;
-            rout[q] = r0; rout[n + q] = r1; rout[2 * n + q] = r2; rout[3 * n + q] = r3; rout[4 * n + q] = r4;
+    const int hlf = threadIdx.x & 1;
+    int i, j;
+    pair_cells(T, i, j);
+    for (int a = 0; a < 2; a++, i++) {
+        if (i >= L.m1 || j >= L.m2) continue;
+        double rc, rm, rp, rf;
+        resid_pair(P, L, T, F, i, j, hlf, rc, rm, rp, rf);
+        const size_t q = (size_t)j * L.m1 + i;
+        v[3 + hlf] += rf * rf;
+        if (rout) rout[(3 + hlf) * n + q] = rf;
+        if (hlf == 0) {
+            v[0] += rc * rc; v[1] += rm * rm; v[2] += rp * rp;
+            const double c = T.q(T_C, i, j), pp = T.q(T_P, i, j);
+            v[5] += pp;
+            const bool ok = isfinite(c) && isfinite(T.q(T_MU, i, j)) && isfinite(pp) && isfinite(T.q(T_U, i, j))
+                          && isfinite(T.q(T_V, i, j)) && (P.drho * c + P.rho1 > 0.0);
+            v[6] += ok ? 0.0 : 1.0;
+            if (rout) { rout[q] = rc; rout[n + q] = rm; rout[2 * n + q] = rp; }
         }
     }
-    block_sum_store(v, partials);
+    block_sum_store(v, partials, blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // mass and energy partial sums of the current state
@@ -226,16 +325,18 @@ __global__ __launch_bounds__(BLK) void k_mass_energy(Phys P, View L, double h, d
         v[0] = r * c;
         v[1] = r * (1.0 - c);
         // kinetic energy on the west and south faces of the cell (App. A.7)
-        const double rw = rho_of(P, ldc(L.c, L, i - 1, j)), rs = rho_of(P, ldc(L.c, L, i, j - 1));
+        const double cw = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i - 1, j);
+        const double cs = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j - 1);
+        const double rw = rho_of(P, cw), rs = rho_of(P, cs);
         if (u_unk(L, i)) { const double u = L.u[k]; v[2] += 0.25 * (r + rw) * u * u; }
         if (v_unk(L, j)) { const double w = L.v[k]; v[2] += 0.25 * (r + rs) * w * w; }
         // gradient energy [rho D c, D c] on the same faces (walls carry none)
-        if (L.bcx || i > 0) { const double d = (c - ldc(L.c, L, i - 1, j)) * L.inv_h; v[3] += 0.5 * (r + rw) * d * d; }
-        if (L.bcy || j > 0) { const double d = (c - ldc(L.c, L, i, j - 1)) * L.inv_h; v[3] += 0.5 * (r + rs) * d * d; }
+        if (L.bcx || i > 0) { const double d = (c - cw) * L.inv_h; v[3] += 0.5 * (r + rw) * d * d; }
+        if (L.bcy || j > 0) { const double d = (c - cs) * L.inv_h; v[3] += 0.5 * (r + rs) * d * d; }
         v[4] = r * dwell(c);
         v[5] = (r - P.rho_ref) * (j + 0.5) * h;
     }
-    block_sum_store(v, partials);
+    block_sum_store(v, partials, blockIdx.x);
 }
 
 // single-block fixed-order sum of the per-block partials
@@ -325,6 +426,12 @@ struct qnsch_ctx {
     double *partials = nullptr, *red = nullptr, *rout = nullptr;
     double *hred = nullptr; // pinned
     std::string err;
+    // timing of the finest-level half-sweep launches (HIP events on the
+    // context's stream), enabled by qnsch_profile
+    int prof = 0, prof_used = 0;
+    std::vector<hipEvent_t> ev;
+    double prof_ms = 0.0;
+    long prof_n = 0;
     int in_step = 0;
     double dt = 0;
     qnsch_step_stats st;
@@ -379,14 +486,46 @@ static Coarse coarse_of(qnsch_ctx *x, int l)
     return C;
 }
 static unsigned nblocks(size_t n) { return (unsigned)((n + BLK - 1) / BLK); }
+static dim3 tiles(int m1, int m2) { return dim3((unsigned)((m1 + TX - 1) / TX), (unsigned)((m2 + TY - 1) / TY)); }
+
+static int prof_collect(qnsch_ctx *x)
+{
+    for (int q = 0; q < x->prof_used; q++) {
+        float ms = 0.f;
+        HIPCHK(x, hipEventElapsedTime(&ms, x->ev[2 * q], x->ev[2 * q + 1]));
+        x->prof_ms += ms;
+        x->prof_n++;
+    }
+    x->prof_used = 0;
+    return QNSCH_OK;
+}
 
 static int halfsweep(qnsch_ctx *x, int l, int colour)
 {
     DLev &D = x->L[l];
     View V = view_of(x, l);
-    size_t n = (size_t)(D.m1 / 2) * D.m2;
-    hipLaunchKernelGGL(k_halfsweep, dim3(nblocks(n)), dim3(BLK), 0, x->s, x->P, V, rhs_of(x, l), D.ub[D.cur ^ 1],
-                       D.vb[D.cur ^ 1], colour, x->opt.vanka_omega);
+    if (l == 0) {
+        const bool tm = x->prof != 0;
+        if (tm) {
+            if ((size_t)(2 * x->prof_used + 2) > x->ev.size()) {
+                for (int q = 0; q < 64; q++) {
+                    hipEvent_t e;
+                    HIPCHK(x, hipEventCreate(&e));
+                    x->ev.push_back(e);
+                }
+            }
+            HIPCHK(x, hipEventRecord(x->ev[2 * x->prof_used], x->s));
+        }
+        hipLaunchKernelGGL(k_halfsweep_fine, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, V, D.ub[D.cur ^ 1],
+                           D.vb[D.cur ^ 1], colour, x->opt.vanka_omega);
+        if (tm) {
+            HIPCHK(x, hipEventRecord(x->ev[2 * x->prof_used + 1], x->s));
+            x->prof_used++;
+        }
+    } else {
+        hipLaunchKernelGGL(k_halfsweep_coarse, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, V, rhs_of(x, l),
+                           D.ub[D.cur ^ 1], D.vb[D.cur ^ 1], colour, x->opt.vanka_omega);
+    }
     D.cur ^= 1;
     return launch_check(x, "k_halfsweep");
 }
@@ -397,10 +536,11 @@ static int vcycle_rec(qnsch_ctx *x, int l)
     int rc;
     if (l == x->nlev - 1) {
         size_t n = (size_t)(D.m1 / 2) * D.m2;
-        unsigned th = (unsigned)(n < 1024 ? ((n + 63) / 64) * 64 : 1024);
-        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(th), 0, x->s, x->P, view_of(x, l), rhs_of(x, l),
-                           D.ub[D.cur], D.vb[D.cur], D.ub[D.cur ^ 1], D.vb[D.cur ^ 1], x->opt.nu_coarse,
-                           x->opt.vanka_omega);
+        unsigned th = (unsigned)(2 * n < 512 ? ((2 * n + 63) / 64) * 64 : 512);
+        size_t lds = coarse_lds_doubles(D.m1, D.m2) * sizeof(double);
+        Rhs F = l > 0 ? rhs_of(x, l) : Rhs{ nullptr, nullptr, nullptr, nullptr, nullptr };
+        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(th), lds, x->s, x->P, view_of(x, l), F, D.ub[D.cur],
+                           D.vb[D.cur], x->opt.nu_coarse, x->opt.vanka_omega);
         return launch_check(x, "k_coarse_solve");
     }
     for (int s = 0; s < x->opt.nu1; s++) {
@@ -409,10 +549,10 @@ static int vcycle_rec(qnsch_ctx *x, int l)
     }
     DLev &C = x->L[l + 1];
     size_t nc = (size_t)C.m1 * C.m2;
-    hipLaunchKernelGGL(k_restrict, dim3(nblocks(nc)), dim3(BLK), 0, x->s, x->P, view_of(x, l), rhs_of(x, l),
+    hipLaunchKernelGGL(k_restrict, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, view_of(x, l), rhs_of(x, l),
                        coarse_of(x, l + 1));
     if ((rc = launch_check(x, "k_restrict"))) return rc;
-    hipLaunchKernelGGL(k_coarse_rhs, dim3(nblocks(nc)), dim3(BLK), 0, x->s, x->P, view_of(x, l + 1),
+    hipLaunchKernelGGL(k_coarse_rhs, tiles(C.m1, C.m2), dim3(TBLK), 0, x->s, x->P, view_of(x, l + 1),
                        coarse_of(x, l + 1));
     if ((rc = launch_check(x, "k_coarse_rhs"))) return rc;
     if ((rc = vcycle_rec(x, l + 1))) return rc;
@@ -432,12 +572,13 @@ static int norms(qnsch_ctx *x, double *rout, bool shift)
 {
     DLev &D = x->L[0];
     size_t n = (size_t)D.m1 * D.m2;
-    unsigned nb = nblocks(n);
+    const dim3 tg = tiles(D.m1, D.m2);
+    unsigned nbt = tg.x * tg.y, nb = nblocks(n);
     Rhs F = {};
-    hipLaunchKernelGGL(k_resid_norm, dim3(nb), dim3(BLK), 0, x->s, x->P, view_of(x, 0), F, x->partials, rout);
+    hipLaunchKernelGGL(k_resid_norm, tg, dim3(TBLK), 0, x->s, x->P, view_of(x, 0), F, x->partials, rout);
     int rc;
     if ((rc = launch_check(x, "k_resid_norm"))) return rc;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLK), 0, x->s, x->partials, (int)nb, x->red);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLK), 0, x->s, x->partials, (int)nbt, x->red);
     if ((rc = launch_check(x, "k_finalize"))) return rc;
     if (shift) {
         hipLaunchKernelGGL(k_shift_p, dim3(nb), dim3(BLK), 0, x->s, D.p, D.m1, D.m2, D.pitch, x->red);
@@ -446,7 +587,7 @@ static int norms(qnsch_ctx *x, double *rout, bool shift)
     HIPCHK(x, hipMemcpyAsync(x->hred, x->red, NRED * sizeof(double), hipMemcpyDeviceToHost, x->s));
     HIPCHK(x, hipStreamSynchronize(x->s));
     for (int q = 0; q < 5; q++) x->hred[q] = sqrt(D.h * D.h * x->hred[q]);
-    return QNSCH_OK;
+    return prof_collect(x);
 }
 
 static int restore(qnsch_ctx *x)
@@ -497,9 +638,10 @@ int qnsch_levels(const qnsch_ctx *x) { return x ? x->nlev : 0; }
 void qnsch_destroy(qnsch_ctx *x)
 {
     if (!x) return;
-    if (x->s) hipStreamSynchronize(x->s);
-    for (void *p : x->allocs) hipFree(p);
-    if (x->hred) hipHostFree(x->hred);
+    if (x->s) (void)hipStreamSynchronize(x->s);
+    for (void *p : x->allocs) (void)hipFree(p);
+    for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
+    if (x->hred) (void)hipHostFree(x->hred);
     delete x;
 }
 
@@ -528,8 +670,8 @@ int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o
             nl++;
     }
     if (nl > 16 || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) return QNSCH_EINVAL;
-    // the coarsest level is relaxed by one workgroup: at most 1024 cells per colour x 4
-    if ((size_t)(g->m1 >> (nl - 1)) * (g->m2 >> (nl - 1)) > 8192) return QNSCH_EINVAL;
+    // the coarsest level is relaxed by one workgroup with the level in LDS
+    if (coarse_lds_doubles(g->m1 >> (nl - 1), g->m2 >> (nl - 1)) * sizeof(double) > 65536) return QNSCH_EINVAL;
 
     qnsch_ctx *x = new qnsch_ctx();
     x->g = *g;
@@ -572,7 +714,9 @@ int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o
     if (!rc) {
         x->mu_save = dalloc(x, n0, &rc);
         x->p_save = dalloc(x, n0, &rc);
-        x->partials = dalloc(x, (size_t)nblocks((size_t)g->m1 * g->m2) * NRED, &rc);
+        const dim3 tg = tiles(g->m1, g->m2);
+        const size_t nbmax = std::max((size_t)nblocks((size_t)g->m1 * g->m2), (size_t)tg.x * tg.y);
+        x->partials = dalloc(x, nbmax * NRED, &rc);
         x->red = dalloc(x, NRED, &rc);
         x->rout = nullptr;
     }
@@ -798,6 +942,65 @@ int qnsch_energy(qnsch_ctx *x, double out[5])
     out[4] = p.inv_Fr * h2 * x->hred[5];
     out[0] = out[1] + out[2] + out[3] + out[4];
     return QNSCH_OK;
+}
+
+int qnsch_profile(qnsch_ctx *x, int enable)
+{
+    if (!x) return QNSCH_EINVAL;
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    int rc;
+    if ((rc = prof_collect(x))) return rc;
+    x->prof = enable ? 1 : 0;
+    x->prof_ms = 0.0;
+    x->prof_n = 0;
+    return QNSCH_OK;
+}
+
+int qnsch_profile_read(qnsch_ctx *x, double out[2])
+{
+    if (!x || !out) return QNSCH_EINVAL;
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    int rc;
+    if ((rc = prof_collect(x))) return rc;
+    out[0] = (double)x->prof_n;
+    out[1] = x->prof_ms;
+    return QNSCH_OK;
+}
+
+int qnsch_synchronize(qnsch_ctx *x)
+{
+    if (!x) return QNSCH_EINVAL;
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    return QNSCH_OK;
+}
+
+int qnsch_copy_probe(size_t n, int reps, double out[2])
+{
+    if (n == 0 || reps < 1 || !out) return QNSCH_EINVAL;
+    double *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, n * sizeof(double)) != hipSuccess) return QNSCH_ENOMEM;
+    if (hipMalloc(&b, n * sizeof(double)) != hipSuccess) { (void)hipFree(a); return QNSCH_ENOMEM; }
+    int rc = QNSCH_OK;
+    hipEvent_t e0, e1;
+    if (hipMemset(a, 0, n * sizeof(double)) != hipSuccess || hipEventCreate(&e0) != hipSuccess
+        || hipEventCreate(&e1) != hipSuccess) {
+        rc = QNSCH_EDEVICE;
+    } else {
+        const unsigned grid = 256u * 8u;
+        hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(BLK), 0, nullptr, a, b, n); // warm-up
+        (void)hipEventRecord(e0, nullptr);
+        for (int r = 0; r < reps; r++) hipLaunchKernelGGL(k_copy_probe, dim3(grid), dim3(BLK), 0, nullptr, a, b, n);
+        (void)hipEventRecord(e1, nullptr);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = QNSCH_EDEVICE;
+        out[1] = ms / reps;
+        out[0] = 2.0 * n * sizeof(double) / (out[1] * 1e-3) / 1e9;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    (void)hipFree(a);
+    (void)hipFree(b);
+    return rc;
 }
 
 int qnsch_stats(const qnsch_ctx *x, qnsch_step_stats *out)

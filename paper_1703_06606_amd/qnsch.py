@@ -19,7 +19,8 @@ FP64, MIXED = 0, 1
 # every exported symbol declared in include/qnsch.h
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
            "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
-           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_mass", "qnsch_energy", "qnsch_stats")
+           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_mass", "qnsch_energy", "qnsch_stats",
+           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_copy_probe")
 
 
 class QnschError(RuntimeError):
@@ -79,12 +80,25 @@ def lib():
         L.qnsch_mass.argtypes = [vp, P]
         L.qnsch_energy.argtypes = [vp, P]
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
+        L.qnsch_synchronize.argtypes = [vp]
+        L.qnsch_profile.argtypes = [vp, C.c_int]
+        L.qnsch_profile_read.argtypes = [vp, P]
+        L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
         _lib = L
     return _lib
 
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def copy_probe(n_doubles, reps=20):
+    """{GB/s, ms per copy} of a plain device copy kernel of n doubles"""
+    out = np.zeros(2)
+    rc = lib().qnsch_copy_probe(n_doubles, reps, _ptr(out))
+    if rc != OK:
+        raise QnschError(rc, "copy probe failed")
+    return float(out[0]), float(out[1])
 
 
 def default_opts():
@@ -177,6 +191,17 @@ class Solver:
         s = StepStats()
         self._chk(lib().qnsch_stats(self.h, C.byref(s)))
         return dict(vcycles=s.vcycles, res=list(s.res), res0=list(s.res0), step_ms=s.step_ms)
+
+    def synchronize(self):
+        self._chk(lib().qnsch_synchronize(self.h))
+
+    def profile(self, enable):
+        self._chk(lib().qnsch_profile(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        out = np.zeros(2)
+        self._chk(lib().qnsch_profile_read(self.h, _ptr(out)))
+        return int(out[0]), float(out[1])
 
     def set_iterate(self, c, mu=None, p=None, u=None, v=None):
         arrs = [self._f(a) for a in (c, mu, p, u, v)]

@@ -43,14 +43,15 @@ def par_O1(**kw):
     return p
 
 
-SHAPES = [(16, 24, 0, 0), (16, 24, 1, 0), (16, 16, 1, 1), (40, 24, 0, 0), (40, 24, 1, 0)]
+SHAPES = [(16, 24, 0, 0), (16, 24, 1, 0), (16, 16, 1, 1), (40, 24, 0, 0), (40, 24, 1, 0), (72, 40, 1, 1),
+          (8, 8, 1, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
 def test_residual_matches_oracle(shape):
     m1, m2, bx, by = shape
     say("residual parity", shape)
-    cfg = dict(grid=grid_(m1, m2, bx, by, levels=2), params=par_O1(rho2=3.0))
+    cfg = dict(grid=grid_(m1, m2, bx, by, levels=0), params=par_O1(rho2=3.0))
     g, o = pair(cfg, W.default_opts())
     w, wn = W.random_state(cfg["grid"], 21), W.random_state(cfg["grid"], 22)
     for s in (g, o):
@@ -66,7 +67,7 @@ def test_residual_matches_oracle(shape):
 def test_halfsweeps_match_oracle(shape):
     m1, m2, bx, by = shape
     say("halfsweep parity", shape)
-    cfg = dict(grid=grid_(m1, m2, bx, by, levels=2), params=par_O1(rho2=3.0))
+    cfg = dict(grid=grid_(m1, m2, bx, by, levels=0), params=par_O1(rho2=3.0))
     g, o = pair(cfg, W.default_opts())
     w, wn = W.random_state(cfg["grid"], 23), W.random_state(cfg["grid"], 24)
     for s in (g, o):
