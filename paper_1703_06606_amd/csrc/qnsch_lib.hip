@@ -36,12 +36,23 @@ using namespace qn;
 #define TILE_DOUBLES (T_NF * (TX + 3) * (TY + 3))
 static_assert(TILE_DOUBLES * 8 + 16 * NRED * 8 <= 65536, "tile exceeds 64 KiB of LDS");
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumber the tiles so that XCD x gets a contiguous band of tiles (rows of
+// the tile grid): neighbouring tiles, which read each other's halos, then
+// share one L2.
+#define NXCD 8
+__device__ __forceinline__ int tile_id()
+{
+    const int n = gridDim.x * gridDim.y, lin = blockIdx.x + blockIdx.y * gridDim.x;
+    return (n % NXCD == 0) ? (lin % NXCD) * (n / NXCD) + lin / NXCD : lin;
+}
 __device__ __forceinline__ Tile block_tile(double *sm)
 {
+    const int t = tile_id();
     Tile T;
     T.s = sm;
-    T.i0 = blockIdx.x * TX;
-    T.j0 = blockIdx.y * TY;
+    T.i0 = (t % gridDim.x) * TX;
+    T.j0 = (t / gridDim.x) * TY;
     T.W = TX + 3;
     T.H = TY + 3;
     return T;
@@ -310,7 +321,7 @@ __global__ __launch_bounds__(TBLK) void k_resid_norm(Phys P, View L, Rhs F, doub
             if (rout) { rout[q] = rc; rout[n + q] = rm; rout[2 * n + q] = rp; }
         }
     }
-    block_sum_store(v, partials, blockIdx.y * gridDim.x + blockIdx.x);
+    block_sum_store(v, partials, tile_id());
 }
 
 // mass and energy partial sums of the current state
@@ -510,7 +521,7 @@ static int halfsweep(qnsch_ctx *x, int l, int colour)
             if ((size_t)(2 * x->prof_used + 2) > x->ev.size()) {
                 for (int q = 0; q < 64; q++) {
                     hipEvent_t e;
-                    HIPCHK(x, hipEventCreate(&e));
+                    HIPCHK(x, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
                     x->ev.push_back(e);
                 }
             }
