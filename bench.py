@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0
 HALFSWEEP_BYTES_PER_CELL = 8 * 8 + 3 * 8 / 2 + 2 * 8
 KERNEL = "k_halfsweep_fine"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_traffic.txt")
-SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f) for f in ("qnsch_dev.hpp", "qnsch_lib.hip")]
+SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f) for f in ("qnsch_dev.hpp", "qnsch_kern.hpp", "qnsch_lib.hip")]
 
 
 def source_hash():

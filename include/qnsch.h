@@ -156,6 +156,52 @@ int qnsch_profile_read(qnsch_ctx *ctx, double out[2]);
  * write, milliseconds per copy}. */
 int qnsch_copy_probe(size_t n, int reps, double out[2]);
 
+/* ---------------------------------------------------------------------------
+ * Serving: many independent simulations with continuous batching.
+ *
+ * A server owns a queue of requests (each a grid, parameters, options, an
+ * initial concentration and a number of steps of size dt).  qnsch_server_
+ * progress admits queued requests first come, first served while a slot is
+ * free and their device footprint fits the HBM budget, keeps every admitted
+ * hierarchy resident, and issues the next operation of every running request;
+ * operations of the same kind (a colour half-sweep at whatever level, a
+ * restriction, ...) are merged into one work-list launch.  A request's result
+ * does not depend on which other requests share its launches.  The caller
+ * submits requests whenever they arrive and calls progress in a loop.
+ * Requests, results and histories are host memory owned by the server until
+ * it is destroyed.
+ */
+typedef struct qnsch_server qnsch_server;
+
+/* Device bytes a context of this grid allocates (0 if the grid is invalid);
+ * the server admits requests by this footprint. */
+size_t qnsch_footprint(const qnsch_grid *grid);
+
+/* hbm_budget: device bytes the admitted requests may hold together;
+ * max_slots: most requests in flight; hip_stream: stream to run on (NULL =
+ * default). */
+int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *hip_stream, qnsch_server **out);
+void qnsch_server_destroy(qnsch_server *srv);
+const char *qnsch_server_last_error(const qnsch_server *srv);
+/* Queue a request; c0 (m1*m2, host) is copied.  QNSCH_ENOMEM if its footprint
+ * exceeds the whole budget; QNSCH_EINVAL as for qnsch_create. */
+int qnsch_server_submit(qnsch_server *srv, const qnsch_grid *grid, const qnsch_params *params,
+                        const qnsch_opts *opts, const double *c0, int32_t nsteps, double dt, uint64_t *id);
+/* Run up to max_ticks scheduler ticks; returns the number of unfinished
+ * requests (queued + running) or a negative error. */
+int qnsch_server_progress(qnsch_server *srv, int32_t max_ticks);
+/* state: 0 queued, 1 running, 2 done; status: QNSCH_OK or the request's error. */
+int qnsch_server_poll(qnsch_server *srv, uint64_t id, int32_t *state, int32_t *status);
+/* Results of a finished request (NULL pointers are skipped): final state
+ * (layout as qnsch_get_state), per step {mass 2, energy 5, wall ms, V-cycles},
+ * times = {queue wait ms, submit-to-done ms}.  Returns the request's status
+ * (QNSCH_EBUSY while it is not finished). */
+int qnsch_server_result(qnsch_server *srv, uint64_t id, double *c, double *mu, double *p, double *u, double *v,
+                        double *mass_hist, double *energy_hist, double *step_ms, int32_t *vcycles, double *times);
+/* out = {p50 step ms, p99 step ms, cell-steps done, seconds from first
+ * admission to last completion, cell-steps/s, steps done, launches, ticks}. */
+int qnsch_server_stats(qnsch_server *srv, double out[8]);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,510 @@
+// qnsch_kern.hpp -- work-list kernels of the FP64 multigrid step.
+//
+// Every kernel takes a work list: up to MAXITEMS items, each naming one level
+// of one simulation (a device descriptor) and the range of workgroups that
+// work on it.  A launch therefore applies the same operation (a colour
+// half-sweep, a restriction, ...) to many simulations at once, at whatever
+// level each of them is; a single simulation is a list of one item.  The
+// work of a workgroup depends only on its item, so a simulation's results do
+// not depend on what else shares the launch.
+#pragma once
+#include "qnsch_dev.hpp"
+
+namespace qn {
+
+#define BLK 256
+#define NRED 8 // reduction slots
+#define TX 32
+#define TY 16
+#define TBLK (TX * TY)
+#define TILE_DOUBLES (T_NF * (TX + 3) * (TY + 3))
+#define NXCD 8
+#define MAXITEMS 64
+static_assert(TILE_DOUBLES * 8 + 16 * NRED * 8 <= 65536, "tile exceeds 64 KiB of LDS");
+
+// one level of one simulation, in device memory
+struct Desc {
+    Phys P;
+    double *c, *mu, *p, *ub[2], *vb[2], *cn, *un, *vn; // level arrays (u/v ping-pong)
+    double *fc, *fmu, *fp, *fu, *fv;                    // FAS right-hand side (NULL on the finest level)
+    double *c0, *mu0, *p0, *u0, *v0;                    // restricted iterate (coarse levels)
+    int m1, m2, pitch, bcx, bcy;
+    double h, inv_h;
+    const Desc *coarse;                                 // next coarser level (NULL on the coarsest)
+    double *partials;                                   // per-simulation reduction partials (finest level)
+    double *red;                                        // reduced values (device)
+    double *red_host;                                   // reduced values (pinned host)
+    double *mus, *ps;                                   // mubar, pbar of time n (finest level)
+    double *rout;                                       // residual fields (finest level, optional)
+};
+
+struct Items {
+    int n;
+    int start[MAXITEMS + 1];  // first workgroup of each item; start[n] = total
+    const Desc *d[MAXITEMS];  // the level worked on
+    short par[MAXITEMS];      // current u/v buffer of that level
+    short cpar[MAXITEMS];     // current u/v buffer of the next coarser level
+    int tx[MAXITEMS];         // tiles per row (tile kernels); partial count (k_finalize)
+};
+
+__device__ __forceinline__ int find_item(const Items &it)
+{
+    int k = 0;
+    while (k + 1 < it.n && (int)blockIdx.x >= it.start[k + 1]) k++;
+    return k;
+}
+
+__device__ __forceinline__ View view_of(const Desc &d, int par)
+{
+    View V;
+    V.c = d.c; V.mu = d.mu; V.p = d.p;
+    V.u = d.ub[par]; V.v = d.vb[par];
+    V.cn = d.cn; V.un = d.un; V.vn = d.vn;
+    V.m1 = d.m1; V.m2 = d.m2; V.pitch = d.pitch;
+    V.bcx = d.bcx; V.bcy = d.bcy;
+    V.inv_h = d.inv_h;
+    return V;
+}
+__device__ __forceinline__ Rhs rhs_of(const Desc &d)
+{
+    const Rhs F = { d.fc, d.fmu, d.fp, d.fu, d.fv };
+    return F;
+}
+
+// Workgroups are dispatched round-robin over the XCDs, each with its own L2.
+// Items start at multiples of NXCD and their tiles are renumbered so that an
+// XCD gets a contiguous band of tiles: neighbouring tiles, which read each
+// other's halos, share one L2.
+__device__ __forceinline__ Tile item_tile(double *sm, const Items &it, int k, const Desc &d)
+{
+    const int tx = it.tx[k];
+    const int ty = (d.m2 + TY - 1) / TY;
+    const int n = tx * ty, lin = (int)blockIdx.x - it.start[k];
+    const int t = (n % NXCD == 0) ? (lin % NXCD) * (n / NXCD) + lin / NXCD : lin;
+    Tile T;
+    T.s = sm;
+    T.i0 = (t % tx) * TX;
+    T.j0 = (t / tx) * TY;
+    T.W = TX + 3;
+    T.H = TY + 3;
+    return T;
+}
+__device__ __forceinline__ bool tile_valid(const Items &it, int k, const Desc &d)
+{
+    return (int)blockIdx.x - it.start[k] < it.tx[k] * ((d.m2 + TY - 1) / TY);
+}
+
+// --------------------------------------------------------------------------
+// one colour half-sweep (sec. 7.1) on a tile: a lane pair per cell of the
+// colour.  The u/v snapshot is buffer par, the new faces go to buffer par^1.
+__device__ __forceinline__ void halfsweep_body(const Items &it, int colour, double omega)
+{
+    __shared__ double sm[TILE_DOUBLES];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const int par = it.par[k];
+    const View L = view_of(d, par);
+    const Tile T = item_tile(sm, it, k, d);
+    tile_load(d.P, L, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
+    const int j = T.j0 + lj;
+    const int i = T.i0 + 2 * kk + ((j + colour) & 1);
+    if (i < L.m1 && j < L.m2) relax_pair(d.P, L, T, rhs_of(d), d.ub[par ^ 1], d.vb[par ^ 1], i, j, hlf, omega);
+}
+__global__ __launch_bounds__(TBLK) void k_halfsweep(Items it, int colour, double omega)
+{
+    halfsweep_body(it, colour, omega);
+}
+// the same kernel under its own name for launches whose items are all finest
+// levels, so that profiles tell the finest level apart
+__global__ __launch_bounds__(TBLK) void k_halfsweep_fine(Items it, int colour, double omega)
+{
+    halfsweep_body(it, colour, omega);
+}
+
+// plain copy, used to measure the copy bandwidth and to calibrate counters
+__global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a, double *__restrict__ b, size_t n)
+{
+    for (size_t q = (size_t)blockIdx.x * BLK + threadIdx.x; q < n; q += (size_t)gridDim.x * BLK) b[q] = a[q];
+}
+
+// LDS doubles of the coarsest-level solve: 15 level arrays + one tile
+__host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
+{
+    return (size_t)15 * m1 * m2 + (size_t)T_NF * (m1 + 3) * (m2 + 3);
+}
+
+// all sweeps of the coarsest level in one workgroup per item, with the whole
+// level resident in LDS; the u/v buffers alternate, the number of half-sweeps
+// is even, so the result stays in buffer par
+__global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, double omega)
+{
+    extern __shared__ double sm[];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int par = it.par[k];
+    const View L = view_of(d, par);
+    double *ua = d.ub[par], *va = d.vb[par];
+    const int m1 = L.m1, m2 = L.m2, n = m1 * m2;
+    double *hc = sm, *hmu = sm + n, *hp = sm + 2 * n, *uA = sm + 3 * n, *vA = sm + 4 * n, *uB = sm + 5 * n,
+           *vB = sm + 6 * n, *hcn = sm + 7 * n, *hun = sm + 8 * n, *hvn = sm + 9 * n, *hf = sm + 10 * n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t q = (size_t)j * L.pitch + i;
+        hc[e] = L.c[q]; hmu[e] = L.mu[q]; hp[e] = L.p[q]; uA[e] = ua[q]; vA[e] = va[q];
+        hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
+        hf[e] = d.fc ? d.fc[q] : 0.0;
+        hf[n + e] = d.fmu ? d.fmu[q] : 0.0;
+        hf[2 * n + e] = d.fp ? d.fp[q] : 0.0;
+        hf[3 * n + e] = d.fu ? d.fu[q] : 0.0;
+        hf[4 * n + e] = d.fv ? d.fv[q] : 0.0;
+    }
+    __syncthreads();
+    View H = L;
+    H.c = hc; H.mu = hmu; H.p = hp; H.cn = hcn; H.un = hun; H.vn = hvn; H.pitch = m1;
+    const Rhs FH = { hf, hf + n, hf + 2 * n, hf + 3 * n, hf + 4 * n };
+    Tile T;
+    T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    const int half = m1 >> 1;
+    for (int s = 0; s < 2 * sweeps; s++) {
+        const int colour = s & 1;
+        double *uw, *vw;
+        if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
+        else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
+        tile_load(d.P, H, T);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
+            const int pr = t >> 1;
+            const int j = pr / half;
+            const int i = 2 * (pr - j * half) + ((j + colour) & 1);
+            relax_pair(d.P, H, T, FH, uw, vw, i, j, t & 1, omega);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t q = (size_t)j * L.pitch + i;
+        L.c[q] = hc[e]; L.mu[q] = hmu[e]; L.p[q] = hp[e]; ua[q] = uA[e]; va[q] = vA[e];
+    }
+}
+
+// fine residual r = f - N(w) restricted to the coarse grid together with the
+// iterate (cells: mean of the four children; faces: mean of the two coincident
+// fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w).
+// A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane pair each.
+__global__ __launch_bounds__(TBLK) void k_restrict(Items it)
+{
+    __shared__ double sm[TILE_DOUBLES];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const Desc &C = *d.coarse;
+    const View Lf = view_of(d, it.par[k]);
+    const Tile T = item_tile(sm, it, k, d);
+    tile_load(d.P, Lf, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    if (pr >= (TX / 2) * (TY / 2)) return;
+    const int I = T.i0 / 2 + pr % (TX / 2), J = T.j0 / 2 + pr / (TX / 2);
+    if (I >= C.m1 || J >= C.m2) return;
+    double rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sp = 0, sf = 0;
+    const int fN = hlf ? T_V : T_U;
+    const Rhs F = rhs_of(d);
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            const int i = 2 * I + a, j = 2 * J + b;
+            double xc, xm, xp, xf;
+            resid_pair(d.P, Lf, T, F, i, j, hlf, xc, xm, xp, xf);
+            rc += xc; rm += xm; rp += xp;
+            // the lane's faces of the coarse cell: west faces (a = 0) on the
+            // x lane, south faces (b = 0) on the y lane
+            if ((hlf ? b : a) == 0) { rf += xf; sf += T.q(fN, i, j); }
+            sc += T.q(T_C, i, j); smu += T.q(T_MU, i, j); sp += T.q(T_P, i, j);
+        }
+    const size_t q = (size_t)J * C.pitch + I;
+    const int cp = it.cpar[k];
+    if (hlf == 0) {
+        C.c[q] = C.c0[q] = 0.25 * sc;
+        C.mu[q] = C.mu0[q] = 0.25 * smu;
+        C.p[q] = C.p0[q] = 0.25 * sp;
+        C.fc[q] = 0.25 * rc;
+        C.fmu[q] = 0.25 * rm;
+        C.fp[q] = 0.25 * rp;
+        C.ub[cp][q] = C.u0[q] = 0.5 * sf;
+        C.fu[q] = 0.5 * rf;
+    } else {
+        C.vb[cp][q] = C.v0[q] = 0.5 * sf;
+        C.fv[q] = 0.5 * rf;
+    }
+}
+
+// the two cells of a tile handled by lane pair pr: (2k, lj) and (2k+1, lj)
+__device__ __forceinline__ void pair_cells(const Tile &T, int &i, int &j)
+{
+    const int pr = threadIdx.x >> 1;
+    const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
+    i = T.i0 + 2 * kk;
+    j = T.j0 + lj;
+}
+
+// f_H = N_H(R w) + R r (FAS coarse right-hand side) on the coarse level the
+// item names; walls carry no equation
+__global__ __launch_bounds__(TBLK) void k_coarse_rhs(Items it)
+{
+    __shared__ double sm[TILE_DOUBLES];
+    const int k = find_item(it);
+    const Desc &C = *it.d[k];
+    if (!tile_valid(it, k, C)) return;
+    const View Lc = view_of(C, it.par[k]);
+    const Tile T = item_tile(sm, it, k, C);
+    tile_load(C.P, Lc, T);
+    __syncthreads();
+    const int hlf = threadIdx.x & 1;
+    int i, j;
+    pair_cells(T, i, j);
+    const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
+    for (int a = 0; a < 2; a++, i++) {
+        if (i >= C.m1 || j >= C.m2) continue;
+        double rc, rm, rp, rf;
+        resid_pair(C.P, Lc, T, Z, i, j, hlf, rc, rm, rp, rf); // r = -N_H(R w)
+        const size_t q = (size_t)j * C.pitch + i;
+        if (hlf == 0) {
+            C.fc[q] -= rc;
+            C.fmu[q] -= rm;
+            C.fp[q] -= rp;
+            C.fu[q] = u_unk(Lc, i) ? C.fu[q] - rf : 0.0;
+        } else {
+            C.fv[q] = v_unk(Lc, j) ? C.fv[q] - rf : 0.0;
+        }
+    }
+}
+
+// w_h += P(w_H - R w_h) on the level the item names: cells piecewise
+// constant; faces copy the coincident coarse face and average the two coarse
+// faces across the coarse cell.  One thread per fine cell.
+__global__ __launch_bounds__(BLK) void k_prolong(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const Desc &C = *d.coarse;
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I, kf = (size_t)j * d.pitch + i;
+    const double *Cu = C.ub[it.cpar[k]], *Cv = C.vb[it.cpar[k]];
+    double *uf = d.ub[it.par[k]], *vf = d.vb[it.par[k]];
+    d.c[kf] += C.c[kc] - C.c0[kc];
+    d.mu[kf] += C.mu[kc] - C.mu0[kc];
+    d.p[kf] += C.p[kc] - C.p0[kc];
+    if (d.bcx || i >= 1) {
+        double du = Cu[kc] - C.u0[kc];
+        if (i & 1) {
+            double e = 0.0;
+            if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
+            else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
+            du = 0.5 * (du + e);
+        }
+        uf[kf] += du;
+    }
+    if (d.bcy || j >= 1) {
+        double dv = Cv[kc] - C.v0[kc];
+        if (j & 1) {
+            double e = 0.0;
+            if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
+            else if (d.bcy) e = Cv[I] - C.v0[I];
+            dv = 0.5 * (dv + e);
+        }
+        vf[kf] += dv;
+    }
+}
+
+// wave64 + LDS block sum of NRED values (blocks of up to 16 waves)
+__device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out)
+{
+    __shared__ double sh[16][NRED];
+#pragma unroll
+    for (int q = 0; q < NRED; q++)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0)
+#pragma unroll
+        for (int q = 0; q < NRED; q++) sh[w][q] = v[q];
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        double s = 0.0;
+        for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) s += sh[ww][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// residual norms of a finest level: per tile sums of r^2 for the five
+// equations, the sum of pbar, and the count of cells that are non-finite or
+// past the density pole (partials indexed by the tile's place in the band
+// order); optionally the residual fields themselves
+__global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
+{
+    __shared__ double sm[TILE_DOUBLES];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const View L = view_of(d, it.par[k]);
+    const Tile T = item_tile(sm, it, k, d);
+    tile_load(d.P, L, T);
+    __syncthreads();
+    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    const size_t n = (size_t)L.m1 * L.m2;
+    const int hlf = threadIdx.x & 1;
+    const Rhs F = rhs_of(d);
+    int i, j;
+    pair_cells(T, i, j);
+    for (int a = 0; a < 2; a++, i++) {
+        if (i >= L.m1 || j >= L.m2) continue;
+        double rc, rm, rp, rf;
+        resid_pair(d.P, L, T, F, i, j, hlf, rc, rm, rp, rf);
+        const size_t q = (size_t)j * L.m1 + i;
+        v[3 + hlf] += rf * rf;
+        if (d.rout) d.rout[(3 + hlf) * n + q] = rf;
+        if (hlf == 0) {
+            v[0] += rc * rc; v[1] += rm * rm; v[2] += rp * rp;
+            const double c = T.q(T_C, i, j), pp = T.q(T_P, i, j);
+            v[5] += pp;
+            const bool ok = isfinite(c) && isfinite(T.q(T_MU, i, j)) && isfinite(pp) && isfinite(T.q(T_U, i, j))
+                          && isfinite(T.q(T_V, i, j)) && (d.P.drho * c + d.P.rho1 > 0.0);
+            v[6] += ok ? 0.0 : 1.0;
+            if (d.rout) { d.rout[q] = rc; d.rout[n + q] = rm; d.rout[2 * n + q] = rp; }
+        }
+    }
+    const int tl = (T.j0 / TY) * it.tx[k] + T.i0 / TX;
+    block_sum_store(v, d.partials + (size_t)tl * NRED);
+}
+
+// mass and energy partial sums of the current state, one thread per cell
+__global__ __launch_bounds__(BLK) void k_mass_energy(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const View L = view_of(d, it.par[k]);
+    const Phys &P = d.P;
+    const int b = (int)blockIdx.x - it.start[k];
+    const int t = b * BLK + threadIdx.x;
+    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (t < L.m1 * L.m2) {
+        const int j = t / L.m1, i = t - j * L.m1;
+        const size_t q = (size_t)j * L.pitch + i;
+        const double c = L.c[q], r = rho_of(P, c);
+        v[0] = r * c;
+        v[1] = r * (1.0 - c);
+        const double cw = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i - 1, j);
+        const double cs = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j - 1);
+        const double rw = rho_of(P, cw), rs = rho_of(P, cs);
+        // kinetic energy on the west and south faces of the cell (App. A.7)
+        if (u_unk(L, i)) { const double u = L.u[q]; v[2] += 0.25 * (r + rw) * u * u; }
+        if (v_unk(L, j)) { const double w = L.v[q]; v[2] += 0.25 * (r + rs) * w * w; }
+        // gradient energy [rho D c, D c] on the same faces (walls carry none)
+        if (L.bcx || i > 0) { const double g = (c - cw) * L.inv_h; v[3] += 0.5 * (r + rw) * g * g; }
+        if (L.bcy || j > 0) { const double g = (c - cs) * L.inv_h; v[3] += 0.5 * (r + rs) * g * g; }
+        v[4] = r * dwell(c);
+        v[5] = (r - P.rho_ref) * (j + 0.5) * d.h;
+    }
+    block_sum_store(v, d.partials + (size_t)b * NRED);
+}
+
+// fixed-order sum of a simulation's partials (one workgroup per item); the
+// norms become sqrt(h^2 sum r^2); written to device and pinned host memory.
+// mode 0: residual reduction (5 norms, sum p, bad count); 1: plain sums.
+__global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
+{
+    __shared__ double sh[BLK][NRED];
+    const int k = blockIdx.x;
+    if (k >= it.n) return;
+    const Desc &d = *it.d[k];
+    const int nblk = it.tx[k];
+    double s[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    for (int b = threadIdx.x; b < nblk; b += BLK)
+#pragma unroll
+        for (int q = 0; q < NRED; q++) s[q] += d.partials[(size_t)b * NRED + q];
+#pragma unroll
+    for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] = s[q];
+    __syncthreads();
+    for (int o = BLK / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+#pragma unroll
+            for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] += sh[threadIdx.x + o][q];
+        __syncthreads();
+    }
+    if (threadIdx.x < NRED) {
+        double x = sh[0][threadIdx.x];
+        if (mode == 0 && threadIdx.x < 5) x = sqrt(d.h * d.h * x);
+        d.red[threadIdx.x] = x;
+        d.red_host[threadIdx.x] = x;
+    }
+}
+
+// pbar -= mean(pbar), the mean from the reduced sums
+__global__ __launch_bounds__(BLK) void k_shift_p(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    d.p[(size_t)j * d.pitch + i] -= d.red[5] / (double)(d.m1 * d.m2);
+}
+
+// time-n data of the finest level = current iterate; keep mubar, pbar of time n
+__global__ __launch_bounds__(BLK) void k_begin(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const size_t q = (size_t)j * d.pitch + i;
+    const int par = it.par[k];
+    d.cn[q] = d.c[q];
+    d.un[q] = d.ub[par][q];
+    d.vn[q] = d.vb[par][q];
+    d.mus[q] = d.mu[q];
+    d.ps[q] = d.p[q];
+}
+
+// time-n data of the coarser level of the item's level
+__global__ __launch_bounds__(BLK) void k_restrict_n(Items it)
+{
+    const int k = find_item(it);
+    const Desc &F = *it.d[k];
+    const Desc &C = *F.coarse;
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= C.m1 * C.m2) return;
+    const int J = t / C.m1, I = t - J * C.m1;
+    const size_t f = (size_t)(2 * J) * F.pitch + 2 * I, q = (size_t)J * C.pitch + I;
+    C.cn[q] = 0.25 * (F.cn[f] + F.cn[f + 1] + F.cn[f + F.pitch] + F.cn[f + F.pitch + 1]);
+    C.un[q] = 0.5 * (F.un[f] + F.un[f + F.pitch]);
+    C.vn[q] = 0.5 * (F.vn[f] + F.vn[f + 1]);
+}
+
+// restore the state of time n on the finest level (failed step)
+__global__ __launch_bounds__(BLK) void k_restore(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const size_t q = (size_t)j * d.pitch + i;
+    const int par = it.par[k];
+    d.c[q] = d.cn[q];
+    d.ub[par][q] = d.un[q];
+    d.vb[par][q] = d.vn[q];
+    d.mu[q] = d.mus[q];
+    d.p[q] = d.ps[q];
+}
+
+} // namespace qn

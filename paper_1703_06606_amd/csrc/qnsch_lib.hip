@@ -1,5 +1,7 @@
-// qnsch_lib.hip -- kernels and host driver of the FP64 multigrid time step,
-// behind the C ABI of include/qnsch.h.
+// qnsch_lib.hip -- host driver of the FP64 multigrid time step behind the C
+// ABI of include/qnsch.h: per-simulation contexts, the operation programme of
+// a time step, and a continuous-batching server that runs many simulations
+// through the same work-list kernels.
 //
 // One step (sec. 6.1 solved as in sec. 7.1): fix the time-n data on every
 // level, then run FAS V-cycles (red-black CH point Newton + Vanka box
@@ -7,440 +9,91 @@
 // per-equation residual norm is below tol.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
-#include <algorithm>
+#include <tuple>
 #include <vector>
 
 #include "qnsch.h"
-#include "qnsch_dev.hpp"
+#include "qnsch_kern.hpp"
 
 using namespace qn;
 
-#define BLK 256
-#define NRED 8 // reduction slots per block
-
 // ===========================================================================
-// kernels
+// operations of a time step
 
-// Tiles of TX x TY cells; TX even so that the colour of a cell is fixed by its
-// parity inside the tile.  Static LDS: T_NF * (TX+3) * (TY+3) doubles.  Tile
-// kernels run TX*TY threads: a lane pair per cell of one colour (half-sweeps)
-// or a lane pair per two cells (residual kernels).
-#define TX 32
-#define TY 16
-#define TBLK (TX * TY)
-#define TILE_DOUBLES (T_NF * (TX + 3) * (TY + 3))
-static_assert(TILE_DOUBLES * 8 + 16 * NRED * 8 <= 65536, "tile exceeds 64 KiB of LDS");
-
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
-// Renumber the tiles so that XCD x gets a contiguous band of tiles (rows of
-// the tile grid): neighbouring tiles, which read each other's halos, then
-// share one L2.
-#define NXCD 8
-__device__ __forceinline__ int tile_id()
-{
-    const int n = gridDim.x * gridDim.y, lin = blockIdx.x + blockIdx.y * gridDim.x;
-    return (n % NXCD == 0) ? (lin % NXCD) * (n / NXCD) + lin / NXCD : lin;
-}
-__device__ __forceinline__ Tile block_tile(double *sm)
-{
-    const int t = tile_id();
-    Tile T;
-    T.s = sm;
-    T.i0 = (t % gridDim.x) * TX;
-    T.j0 = (t / gridDim.x) * TY;
-    T.W = TX + 3;
-    T.H = TY + 3;
-    return T;
-}
-
-// one colour half-sweep on a tile.  The finest level (no FAS right-hand side)
-// and the coarse levels are separate kernels so that profiles tell them apart.
-__device__ __forceinline__ void halfsweep_body(const Phys &P, const View &L, const Rhs &F, double *unew,
-                                               double *vnew, int colour, double omega)
-{
-    __shared__ double sm[TILE_DOUBLES];
-    const Tile T = block_tile(sm);
-    tile_load(P, L, T);
-    __syncthreads();
-    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
-    const int lj = pr / (TX / 2), k = pr - lj * (TX / 2);
-    const int j = T.j0 + lj;
-    const int i = T.i0 + 2 * k + ((j + colour) & 1);
-    if (i < L.m1 && j < L.m2) relax_pair(P, L, T, F, unew, vnew, i, j, hlf, omega);
-}
-__global__ __launch_bounds__(TBLK) void k_halfsweep_fine(Phys P, View L, double *unew, double *vnew, int colour,
-                                                         double omega)
-{
-    const Rhs F = { nullptr, nullptr, nullptr, nullptr, nullptr };
-    halfsweep_body(P, L, F, unew, vnew, colour, omega);
-}
-__global__ __launch_bounds__(TBLK) void k_halfsweep_coarse(Phys P, View L, Rhs F, double *unew, double *vnew,
-                                                           int colour, double omega)
-{
-    halfsweep_body(P, L, F, unew, vnew, colour, omega);
-}
-
-// plain copy, used to measure the copy bandwidth and to calibrate counters
-__global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a, double *__restrict__ b, size_t n)
-{
-    for (size_t k = (size_t)blockIdx.x * BLK + threadIdx.x; k < n; k += (size_t)gridDim.x * BLK) b[k] = a[k];
-}
-
-// LDS bytes of the coarsest-level solve: 15 level arrays + one tile
-__host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
-{
-    return (size_t)15 * m1 * m2 + (size_t)T_NF * (m1 + 3) * (m2 + 3);
-}
-
-// all sweeps of the coarsest level in one workgroup with the whole level
-// resident in LDS; the u/v buffers alternate (a -> b -> a ...), the number of
-// half-sweeps is even, so the result is in a
-__global__ __launch_bounds__(512) void k_coarse_solve(Phys P, View L, Rhs F, double *ua, double *va, int sweeps,
-                                                      double omega)
-{
-    extern __shared__ double sm[];
-    const int m1 = L.m1, m2 = L.m2, n = m1 * m2;
-    double *hc = sm, *hmu = sm + n, *hp = sm + 2 * n, *uA = sm + 3 * n, *vA = sm + 4 * n, *uB = sm + 5 * n,
-           *vB = sm + 6 * n, *hcn = sm + 7 * n, *hun = sm + 8 * n, *hvn = sm + 9 * n, *hf = sm + 10 * n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int j = e / m1, i = e - j * m1;
-        const size_t k = (size_t)j * L.pitch + i;
-        hc[e] = L.c[k]; hmu[e] = L.mu[k]; hp[e] = L.p[k]; uA[e] = ua[k]; vA[e] = va[k];
-        hcn[e] = L.cn[k]; hun[e] = L.un[k]; hvn[e] = L.vn[k];
-        hf[e] = F.fc ? F.fc[k] : 0.0;
-        hf[n + e] = F.fmu ? F.fmu[k] : 0.0;
-        hf[2 * n + e] = F.fp ? F.fp[k] : 0.0;
-        hf[3 * n + e] = F.fu ? F.fu[k] : 0.0;
-        hf[4 * n + e] = F.fv ? F.fv[k] : 0.0;
-    }
-    __syncthreads();
-    View H = L;
-    H.c = hc; H.mu = hmu; H.p = hp; H.cn = hcn; H.un = hun; H.vn = hvn; H.pitch = m1;
-    const Rhs FH = { hf, hf + n, hf + 2 * n, hf + 3 * n, hf + 4 * n };
-    Tile T;
-    T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
-    const int half = m1 >> 1;
-    for (int s = 0; s < 2 * sweeps; s++) {
-        const int colour = s & 1;
-        double *uw, *vw;
-        if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
-        else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
-        tile_load(P, H, T);
-        __syncthreads();
-        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
-            const int pr = t >> 1;
-            const int j = pr / half;
-            const int i = 2 * (pr - j * half) + ((j + colour) & 1);
-            relax_pair(P, H, T, FH, uw, vw, i, j, t & 1, omega);
-        }
-        __syncthreads();
-    }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int j = e / m1, i = e - j * m1;
-        const size_t k = (size_t)j * L.pitch + i;
-        L.c[k] = hc[e]; L.mu[k] = hmu[e]; L.p[k] = hp[e]; ua[k] = uA[e]; va[k] = vA[e];
-    }
-}
-
-struct Coarse {
-    double *c, *mu, *p, *u, *v;
-    double *c0, *mu0, *p0, *u0, *v0;
-    double *fc, *fmu, *fp, *fu, *fv;
-    int m1, m2, pitch;
+enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, OP_COARSE, OP_PROLONG, OP_STEPEND,
+              OP_RESTORE };
+struct Op {
+    int kind, level, colour;
 };
 
-// fine residual r = f - N(w) restricted to the coarse grid together with the
-// iterate (cells: mean of the four children; faces: mean of the two coincident
-// fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w).
-// A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane pair each.
-__global__ __launch_bounds__(TBLK) void k_restrict(Phys P, View Lf, Rhs F, Coarse C)
+// one V-cycle of a hierarchy of L levels, ending with the residual norms and
+// the pbar mean removal
+static void vcycle_program(int L, int nu1, int nu2, std::vector<Op> &out)
 {
-    __shared__ double sm[TILE_DOUBLES];
-    const Tile T = block_tile(sm);
-    tile_load(P, Lf, T);
-    __syncthreads();
-    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
-    if (pr >= (TX / 2) * (TY / 2)) return;
-    const int I = T.i0 / 2 + pr % (TX / 2), J = T.j0 / 2 + pr / (TX / 2);
-    if (I >= C.m1 || J >= C.m2) return;
-    double rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sp = 0, sf = 0;
-    const int fN = hlf ? T_V : T_U;
-#pragma unroll
-    for (int b = 0; b < 2; b++)
-#pragma unroll
-        for (int a = 0; a < 2; a++) {
-            const int i = 2 * I + a, j = 2 * J + b;
-            double xc, xm, xp, xf;
-            resid_pair(P, Lf, T, F, i, j, hlf, xc, xm, xp, xf);
-            rc += xc; rm += xm; rp += xp;
-            // the lane's face of the coarse cell: west faces (a = 0) on the x
-            // lane, south faces (b = 0) on the y lane
-            if ((hlf ? b : a) == 0) { rf += xf; sf += T.q(fN, i, j); }
-            sc += T.q(T_C, i, j); smu += T.q(T_MU, i, j); sp += T.q(T_P, i, j);
+    for (int l = 0; l + 1 < L; l++) {
+        for (int s = 0; s < nu1; s++) {
+            out.push_back({ OP_HS, l, 0 });
+            out.push_back({ OP_HS, l, 1 });
         }
-    const size_t k = (size_t)J * C.pitch + I;
-    if (hlf == 0) {
-        C.c[k] = C.c0[k] = 0.25 * sc;
-        C.mu[k] = C.mu0[k] = 0.25 * smu;
-        C.p[k] = C.p0[k] = 0.25 * sp;
-        C.fc[k] = 0.25 * rc;
-        C.fmu[k] = 0.25 * rm;
-        C.fp[k] = 0.25 * rp;
-        C.u[k] = C.u0[k] = 0.5 * sf;
-        C.fu[k] = 0.5 * rf;
-    } else {
-        C.v[k] = C.v0[k] = 0.5 * sf;
-        C.fv[k] = 0.5 * rf;
+        out.push_back({ OP_RESTRICT, l, 0 });
+        out.push_back({ OP_CRHS, l + 1, 0 });
     }
-}
-
-// the two cells of a tile handled by lane pair pr: (2k, lj) and (2k+1, lj)
-__device__ __forceinline__ void pair_cells(const Tile &T, int &i, int &j)
-{
-    const int pr = threadIdx.x >> 1;
-    const int lj = pr / (TX / 2), k = pr - lj * (TX / 2);
-    i = T.i0 + 2 * k;
-    j = T.j0 + lj;
-}
-
-// f_H = N_H(R w) + R r (FAS coarse right-hand side); walls carry no equation
-__global__ __launch_bounds__(TBLK) void k_coarse_rhs(Phys P, View Lc, Coarse C)
-{
-    __shared__ double sm[TILE_DOUBLES];
-    const Tile T = block_tile(sm);
-    tile_load(P, Lc, T);
-    __syncthreads();
-    const int hlf = threadIdx.x & 1;
-    int i, j;
-    pair_cells(T, i, j);
-    const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
-    for (int a = 0; a < 2; a++, i++) {
-        if (i >= C.m1 || j >= C.m2) continue;
-        double rc, rm, rp, rf;
-        resid_pair(P, Lc, T, Z, i, j, hlf, rc, rm, rp, rf); // r = -N_H(R w)
-        const size_t k = (size_t)j * C.pitch + i;
-        if (hlf == 0) {
-            C.fc[k] -= rc;
-            C.fmu[k] -= rm;
-            C.fp[k] -= rp;
-            C.fu[k] = u_unk(Lc, i) ? C.fu[k] - rf : 0.0;
-        } else {
-            C.fv[k] = v_unk(Lc, j) ? C.fv[k] - rf : 0.0;
+    out.push_back({ OP_COARSE, L - 1, 0 });
+    for (int l = L - 2; l >= 0; l--) {
+        out.push_back({ OP_PROLONG, l, 0 });
+        for (int s = 0; s < nu2; s++) {
+            out.push_back({ OP_HS, l, 0 });
+            out.push_back({ OP_HS, l, 1 });
         }
     }
+    out.push_back({ OP_NORM, 0, 0 });
 }
-
-// w_h += P(w_H - R w_h): cells piecewise constant; faces copy the coincident
-// coarse face and average the two coarse faces across the coarse cell
-__global__ __launch_bounds__(BLK) void k_prolong(View Lf, double *uf, double *vf, Coarse C, int bcx, int bcy)
+// time-n data of every level, then the residual of the initial iterate
+static void begin_program(int L, std::vector<Op> &out)
 {
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= Lf.m1 * Lf.m2) return;
-    const int j = t / Lf.m1, i = t - j * Lf.m1;
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I, kf = (size_t)j * Lf.pitch + i;
-    Lf.c[kf] += C.c[kc] - C.c0[kc];
-    Lf.mu[kf] += C.mu[kc] - C.mu0[kc];
-    Lf.p[kf] += C.p[kc] - C.p0[kc];
-    if (u_unk(Lf, i)) {
-        double d = C.u[kc] - C.u0[kc];
-        if (i & 1) {
-            double e = 0.0;
-            if (I + 1 < C.m1) e = C.u[kc + 1] - C.u0[kc + 1];
-            else if (bcx) e = C.u[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
-            d = 0.5 * (d + e);
-        }
-        uf[kf] += d;
-    }
-    if (v_unk(Lf, j)) {
-        double d = C.v[kc] - C.v0[kc];
-        if (j & 1) {
-            double e = 0.0;
-            if (J + 1 < C.m2) e = C.v[kc + C.pitch] - C.v0[kc + C.pitch];
-            else if (bcy) e = C.v[I] - C.v0[I];
-            d = 0.5 * (d + e);
-        }
-        vf[kf] += d;
-    }
-}
-
-// wave64 + LDS block sum of NRED values (blocks of up to 16 waves); one
-// partial row per block
-__device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out, int block)
-{
-    __shared__ double sh[16][NRED];
-#pragma unroll
-    for (int q = 0; q < NRED; q++)
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o, 64);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (l == 0)
-#pragma unroll
-        for (int q = 0; q < NRED; q++) sh[w][q] = v[q];
-    __syncthreads();
-    if (threadIdx.x < NRED) {
-        double s = 0.0;
-        for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) s += sh[ww][threadIdx.x];
-        out[(size_t)block * NRED + threadIdx.x] = s;
-    }
-}
-
-// residual norms of the finest level: per block sums of r^2 for the five
-// equations, the sum of pbar, and the count of cells that are non-finite or
-// past the density pole; optionally the residual fields themselves
-__global__ __launch_bounds__(TBLK) void k_resid_norm(Phys P, View L, Rhs F, double *partials, double *rout)
-{
-    __shared__ double sm[TILE_DOUBLES];
-    const Tile T = block_tile(sm);
-    tile_load(P, L, T);
-    __syncthreads();
-    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
-    const size_t n = (size_t)L.m1 * L.m2;
-    const int hlf = threadIdx.x & 1;
-    int i, j;
-    pair_cells(T, i, j);
-    for (int a = 0; a < 2; a++, i++) {
-        if (i >= L.m1 || j >= L.m2) continue;
-        double rc, rm, rp, rf;
-        resid_pair(P, L, T, F, i, j, hlf, rc, rm, rp, rf);
-        const size_t q = (size_t)j * L.m1 + i;
-        v[3 + hlf] += rf * rf;
-        if (rout) rout[(3 + hlf) * n + q] = rf;
-        if (hlf == 0) {
-            v[0] += rc * rc; v[1] += rm * rm; v[2] += rp * rp;
-            const double c = T.q(T_C, i, j), pp = T.q(T_P, i, j);
-            v[5] += pp;
-            const bool ok = isfinite(c) && isfinite(T.q(T_MU, i, j)) && isfinite(pp) && isfinite(T.q(T_U, i, j))
-                          && isfinite(T.q(T_V, i, j)) && (P.drho * c + P.rho1 > 0.0);
-            v[6] += ok ? 0.0 : 1.0;
-            if (rout) { rout[q] = rc; rout[n + q] = rm; rout[2 * n + q] = rp; }
-        }
-    }
-    block_sum_store(v, partials, tile_id());
-}
-
-// mass and energy partial sums of the current state
-__global__ __launch_bounds__(BLK) void k_mass_energy(Phys P, View L, double h, double *partials)
-{
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
-    if (t < L.m1 * L.m2) {
-        const int j = t / L.m1, i = t - j * L.m1;
-        const size_t k = (size_t)j * L.pitch + i;
-        const double c = L.c[k], r = rho_of(P, c);
-        v[0] = r * c;
-        v[1] = r * (1.0 - c);
-        // kinetic energy on the west and south faces of the cell (App. A.7)
-        const double cw = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i - 1, j);
-        const double cs = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j - 1);
-        const double rw = rho_of(P, cw), rs = rho_of(P, cs);
-        if (u_unk(L, i)) { const double u = L.u[k]; v[2] += 0.25 * (r + rw) * u * u; }
-        if (v_unk(L, j)) { const double w = L.v[k]; v[2] += 0.25 * (r + rs) * w * w; }
-        // gradient energy [rho D c, D c] on the same faces (walls carry none)
-        if (L.bcx || i > 0) { const double d = (c - cw) * L.inv_h; v[3] += 0.5 * (r + rw) * d * d; }
-        if (L.bcy || j > 0) { const double d = (c - cs) * L.inv_h; v[3] += 0.5 * (r + rs) * d * d; }
-        v[4] = r * dwell(c);
-        v[5] = (r - P.rho_ref) * (j + 0.5) * h;
-    }
-    block_sum_store(v, partials, blockIdx.x);
-}
-
-// single-block fixed-order sum of the per-block partials
-__global__ __launch_bounds__(BLK) void k_finalize(const double *partials, int nblk, double *out)
-{
-    __shared__ double sh[BLK][NRED];
-    double s[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
-    for (int b = threadIdx.x; b < nblk; b += BLK)
-#pragma unroll
-        for (int q = 0; q < NRED; q++) s[q] += partials[(size_t)b * NRED + q];
-#pragma unroll
-    for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] = s[q];
-    __syncthreads();
-    for (int o = BLK / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o)
-#pragma unroll
-            for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] += sh[threadIdx.x + o][q];
-        __syncthreads();
-    }
-    if (threadIdx.x < NRED) out[threadIdx.x] = sh[0][threadIdx.x];
-}
-
-// pbar -= mean(pbar), the mean taken from the reduced sums
-__global__ __launch_bounds__(BLK) void k_shift_p(double *p, int m1, int m2, int pitch, const double *red)
-{
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= m1 * m2) return;
-    const int j = t / m1, i = t - j * m1;
-    p[(size_t)j * pitch + i] -= red[5] / (double)(m1 * m2);
-}
-
-// time-n data of the finest level = current iterate; keep mubar, pbar of time n
-__global__ __launch_bounds__(BLK) void k_begin(View L, double *cn, double *un, double *vn, double *mus, double *ps)
-{
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= L.m1 * L.m2) return;
-    const int j = t / L.m1, i = t - j * L.m1;
-    const size_t k = (size_t)j * L.pitch + i;
-    cn[k] = L.c[k];
-    un[k] = L.u[k];
-    vn[k] = L.v[k];
-    mus[k] = L.mu[k];
-    ps[k] = L.p[k];
-}
-
-// time-n data of a coarse level from the next finer one
-__global__ __launch_bounds__(BLK) void k_restrict_n(const double *fcn, const double *fun, const double *fvn, int fpitch,
-                                                    double *ccn, double *cun, double *cvn, int m1, int m2, int pitch)
-{
-    const int t = blockIdx.x * BLK + threadIdx.x;
-    if (t >= m1 * m2) return;
-    const int J = t / m1, I = t - J * m1;
-    const size_t f = (size_t)(2 * J) * fpitch + 2 * I, k = (size_t)J * pitch + I;
-    ccn[k] = 0.25 * (fcn[f] + fcn[f + 1] + fcn[f + fpitch] + fcn[f + fpitch + 1]);
-    cun[k] = 0.5 * (fun[f] + fun[f + fpitch]);
-    cvn[k] = 0.5 * (fvn[f] + fvn[f + 1]);
+    out.push_back({ OP_BEGIN, 0, 0 });
+    for (int l = 0; l + 1 < L; l++) out.push_back({ OP_RN, l, 0 });
+    out.push_back({ OP_NORM0, 0, 0 });
 }
 
 // ===========================================================================
-// host side
+// contexts
 
 namespace {
-
 struct DLev {
     int m1 = 0, m2 = 0, pitch = 0;
     double h = 0;
-    double *c = nullptr, *mu = nullptr, *p = nullptr, *ub[2] = { nullptr, nullptr }, *vb[2] = { nullptr, nullptr };
-    int cur = 0;
-    double *cn = nullptr, *un = nullptr, *vn = nullptr;
-    double *fc = nullptr, *fmu = nullptr, *fp = nullptr, *fu = nullptr, *fv = nullptr;
-    double *c0 = nullptr, *mu0 = nullptr, *p0 = nullptr, *u0 = nullptr, *v0 = nullptr;
+    int cur = 0; // current u/v buffer
     size_t n() const { return (size_t)pitch * m2; }
 };
-
 } // namespace
 
 struct qnsch_ctx {
     qnsch_grid g;
     qnsch_params prm;
     qnsch_opts opt;
-    Phys P;
     int nlev = 0;
     DLev L[16];
+    Desc *hd = nullptr;   // pinned host copy of the level descriptors
+    Desc *dd = nullptr;   // device descriptors
     hipStream_t s = nullptr;
     std::vector<void *> allocs;
-    double *mu_save = nullptr, *p_save = nullptr;
-    double *partials = nullptr, *red = nullptr, *rout = nullptr;
-    double *hred = nullptr; // pinned
+    double *red_host = nullptr; // pinned
+    hipEvent_t ev = nullptr;    // completion of the last host-read reduction
+    size_t footprint = 0;
     std::string err;
     // timing of the finest-level half-sweep launches (HIP events on the
     // context's stream), enabled by qnsch_profile
     int prof = 0, prof_used = 0;
-    std::vector<hipEvent_t> ev;
+    std::vector<hipEvent_t> pev;
     double prof_ms = 0.0;
     long prof_n = 0;
     int in_step = 0;
@@ -457,53 +110,74 @@ struct qnsch_ctx {
         }                                                                                     \
     } while (0)
 
-static int launch_check(qnsch_ctx *x, const char *what)
+static unsigned nblocks(size_t n) { return (unsigned)((n + BLK - 1) / BLK); }
+static int tiles_x(int m1) { return (m1 + TX - 1) / TX; }
+static int tiles_y(int m2) { return (m2 + TY - 1) / TY; }
+
+// ---------------------------------------------------------------------------
+// work lists
+
+struct ItemList {
+    Items it;
+    int blocks = 0;
+    size_t lds = 0;
+    bool all_fine = true;
+    ItemList() { memset(&it, 0, sizeof(it)); }
+};
+
+// workgroups of an operation on (context, level)
+static int op_blocks(const qnsch_ctx *x, int kind, int l)
 {
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        x->err = std::string(what) + ": " + hipGetErrorString(e);
-        return QNSCH_EDEVICE;
+    const DLev &D = x->L[l];
+    switch (kind) {
+    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0:
+        return tiles_x(D.m1) * tiles_y(D.m2);
+    case OP_COARSE: return 1;
+    case OP_RN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
+    default: return (int)nblocks((size_t)D.m1 * D.m2);
     }
-    return QNSCH_OK;
 }
 
-static View view_of(qnsch_ctx *x, int l)
+static void add_item(ItemList &W, const qnsch_ctx *x, int kind, int l)
 {
-    DLev &D = x->L[l];
-    View V;
-    V.c = D.c; V.mu = D.mu; V.p = D.p;
-    V.u = D.ub[D.cur]; V.v = D.vb[D.cur];
-    V.cn = D.cn; V.un = D.un; V.vn = D.vn;
-    V.m1 = D.m1; V.m2 = D.m2; V.pitch = D.pitch;
-    V.bcx = x->g.bc_x; V.bcy = x->g.bc_y;
-    V.inv_h = 1.0 / D.h;
-    return V;
+    Items &it = W.it;
+    const int start = ((W.blocks + NXCD - 1) / NXCD) * NXCD;
+    const int k = it.n;
+    it.start[k] = start;
+    it.d[k] = x->dd + l;
+    it.par[k] = (short)x->L[l].cur;
+    it.cpar[k] = (short)(l + 1 < x->nlev ? x->L[l + 1].cur : 0);
+    it.tx[k] = tiles_x(x->L[l].m1);
+    W.blocks = start + op_blocks(x, kind, l);
+    it.n = k + 1;
+    it.start[k + 1] = W.blocks;
+    if (l != 0) W.all_fine = false;
+    if (kind == OP_COARSE) W.lds = std::max(W.lds, coarse_lds_doubles(x->L[l].m1, x->L[l].m2) * sizeof(double));
 }
-static Rhs rhs_of(qnsch_ctx *x, int l)
+
+// finalize list: one workgroup per simulation, tx = number of partials
+static ItemList finalize_list(const std::vector<std::pair<qnsch_ctx *, int>> &v, int partial_kind)
 {
-    DLev &D = x->L[l];
-    Rhs F;
-    F.fc = D.fc; F.fmu = D.fmu; F.fp = D.fp; F.fu = D.fu; F.fv = D.fv;
+    ItemList F;
+    for (auto &e : v) {
+        qnsch_ctx *x = e.first;
+        const int k = F.it.n;
+        F.it.d[k] = x->dd;
+        F.it.par[k] = (short)x->L[0].cur;
+        F.it.tx[k] = op_blocks(x, partial_kind, 0);
+        F.it.start[k] = k;
+        F.it.n = k + 1;
+        F.it.start[k + 1] = k + 1;
+    }
+    F.blocks = F.it.n;
     return F;
 }
-static Coarse coarse_of(qnsch_ctx *x, int l)
-{
-    DLev &D = x->L[l];
-    Coarse C;
-    C.c = D.c; C.mu = D.mu; C.p = D.p; C.u = D.ub[D.cur]; C.v = D.vb[D.cur];
-    C.c0 = D.c0; C.mu0 = D.mu0; C.p0 = D.p0; C.u0 = D.u0; C.v0 = D.v0;
-    C.fc = D.fc; C.fmu = D.fmu; C.fp = D.fp; C.fu = D.fu; C.fv = D.fv;
-    C.m1 = D.m1; C.m2 = D.m2; C.pitch = D.pitch;
-    return C;
-}
-static unsigned nblocks(size_t n) { return (unsigned)((n + BLK - 1) / BLK); }
-static dim3 tiles(int m1, int m2) { return dim3((unsigned)((m1 + TX - 1) / TX), (unsigned)((m2 + TY - 1) / TY)); }
 
 static int prof_collect(qnsch_ctx *x)
 {
     for (int q = 0; q < x->prof_used; q++) {
         float ms = 0.f;
-        HIPCHK(x, hipEventElapsedTime(&ms, x->ev[2 * q], x->ev[2 * q + 1]));
+        HIPCHK(x, hipEventElapsedTime(&ms, x->pev[2 * q], x->pev[2 * q + 1]));
         x->prof_ms += ms;
         x->prof_n++;
     }
@@ -511,108 +185,100 @@ static int prof_collect(qnsch_ctx *x)
     return QNSCH_OK;
 }
 
-static int halfsweep(qnsch_ctx *x, int l, int colour)
+// Launch one operation for a set of (context, level) entries, in lists of at
+// most MAXITEMS; all entries share the kind and colour.  Errors are reported
+// on the first context.
+static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx *, int>> &v, hipStream_t s)
 {
-    DLev &D = x->L[l];
-    View V = view_of(x, l);
-    if (l == 0) {
-        const bool tm = x->prof != 0;
-        if (tm) {
-            if ((size_t)(2 * x->prof_used + 2) > x->ev.size()) {
-                for (int q = 0; q < 64; q++) {
-                    hipEvent_t e;
-                    HIPCHK(x, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
-                    x->ev.push_back(e);
-                }
+    if (v.empty()) return QNSCH_OK;
+    qnsch_ctx *x0 = v[0].first;
+    for (size_t b = 0; b < v.size(); b += MAXITEMS) {
+        const size_t e = std::min(v.size(), b + MAXITEMS);
+        std::vector<std::pair<qnsch_ctx *, int>> part(v.begin() + b, v.begin() + e);
+        ItemList W;
+        for (auto &pe : part) add_item(W, pe.first, kind, pe.second);
+        const double omega = x0->opt.vanka_omega;
+        switch (kind) {
+        case OP_HS: {
+            const bool tm = part.size() == 1 && part[0].second == 0 && part[0].first->prof;
+            qnsch_ctx *x = part[0].first;
+            if (tm) {
+                if ((size_t)(2 * x->prof_used + 2) > x->pev.size())
+                    for (int q = 0; q < 64; q++) {
+                        hipEvent_t ev;
+                        HIPCHK(x, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+                        x->pev.push_back(ev);
+                    }
+                HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
             }
-            HIPCHK(x, hipEventRecord(x->ev[2 * x->prof_used], x->s));
+            if (W.all_fine) hipLaunchKernelGGL(k_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
+            else hipLaunchKernelGGL(k_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
+            if (tm) {
+                HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
+                x->prof_used++;
+            }
+            for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
+            break;
         }
-        hipLaunchKernelGGL(k_halfsweep_fine, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, V, D.ub[D.cur ^ 1],
-                           D.vb[D.cur ^ 1], colour, x->opt.vanka_omega);
-        if (tm) {
-            HIPCHK(x, hipEventRecord(x->ev[2 * x->prof_used + 1], x->s));
-            x->prof_used++;
+        case OP_RESTRICT: hipLaunchKernelGGL(k_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
+        case OP_CRHS: hipLaunchKernelGGL(k_coarse_rhs, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
+        case OP_COARSE: {
+            int nmax = 0;
+            for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
+            const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
+            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, x0->opt.nu_coarse, omega);
+            break;
         }
-    } else {
-        hipLaunchKernelGGL(k_halfsweep_coarse, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, V, rhs_of(x, l),
-                           D.ub[D.cur ^ 1], D.vb[D.cur ^ 1], colour, x->opt.vanka_omega);
-    }
-    D.cur ^= 1;
-    return launch_check(x, "k_halfsweep");
-}
-
-static int vcycle_rec(qnsch_ctx *x, int l)
-{
-    DLev &D = x->L[l];
-    int rc;
-    if (l == x->nlev - 1) {
-        size_t n = (size_t)(D.m1 / 2) * D.m2;
-        unsigned th = (unsigned)(2 * n < 512 ? ((2 * n + 63) / 64) * 64 : 512);
-        size_t lds = coarse_lds_doubles(D.m1, D.m2) * sizeof(double);
-        Rhs F = l > 0 ? rhs_of(x, l) : Rhs{ nullptr, nullptr, nullptr, nullptr, nullptr };
-        hipLaunchKernelGGL(k_coarse_solve, dim3(1), dim3(th), lds, x->s, x->P, view_of(x, l), F, D.ub[D.cur],
-                           D.vb[D.cur], x->opt.nu_coarse, x->opt.vanka_omega);
-        return launch_check(x, "k_coarse_solve");
-    }
-    for (int s = 0; s < x->opt.nu1; s++) {
-        if ((rc = halfsweep(x, l, 0))) return rc;
-        if ((rc = halfsweep(x, l, 1))) return rc;
-    }
-    DLev &C = x->L[l + 1];
-    size_t nc = (size_t)C.m1 * C.m2;
-    hipLaunchKernelGGL(k_restrict, tiles(D.m1, D.m2), dim3(TBLK), 0, x->s, x->P, view_of(x, l), rhs_of(x, l),
-                       coarse_of(x, l + 1));
-    if ((rc = launch_check(x, "k_restrict"))) return rc;
-    hipLaunchKernelGGL(k_coarse_rhs, tiles(C.m1, C.m2), dim3(TBLK), 0, x->s, x->P, view_of(x, l + 1),
-                       coarse_of(x, l + 1));
-    if ((rc = launch_check(x, "k_coarse_rhs"))) return rc;
-    if ((rc = vcycle_rec(x, l + 1))) return rc;
-    size_t nf = (size_t)D.m1 * D.m2;
-    hipLaunchKernelGGL(k_prolong, dim3(nblocks(nf)), dim3(BLK), 0, x->s, view_of(x, l), D.ub[D.cur], D.vb[D.cur],
-                       coarse_of(x, l + 1), x->g.bc_x, x->g.bc_y);
-    if ((rc = launch_check(x, "k_prolong"))) return rc;
-    for (int s = 0; s < x->opt.nu2; s++) {
-        if ((rc = halfsweep(x, l, 0))) return rc;
-        if ((rc = halfsweep(x, l, 1))) return rc;
+        case OP_PROLONG: hipLaunchKernelGGL(k_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_BEGIN: hipLaunchKernelGGL(k_begin, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_RN: hipLaunchKernelGGL(k_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_RESTORE: hipLaunchKernelGGL(k_restore, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_NORM0:
+        case OP_NORM: {
+            hipLaunchKernelGGL(k_resid_norm, dim3(W.blocks), dim3(TBLK), 0, s, W.it);
+            ItemList F = finalize_list(part, OP_NORM);
+            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 0);
+            if (kind == OP_NORM) {
+                ItemList S;
+                for (auto &pe : part) add_item(S, pe.first, OP_BEGIN, 0);
+                hipLaunchKernelGGL(k_shift_p, dim3(S.blocks), dim3(BLK), 0, s, S.it);
+            }
+            break;
+        }
+        case OP_STEPEND: {
+            hipLaunchKernelGGL(k_mass_energy, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            ItemList F = finalize_list(part, OP_STEPEND);
+            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
+            break;
+        }
+        default: break;
+        }
+        hipError_t err = hipGetLastError();
+        if (err != hipSuccess) {
+            x0->err = std::string("kernel launch: ") + hipGetErrorString(err);
+            return QNSCH_EDEVICE;
+        }
     }
     return QNSCH_OK;
 }
 
-// residual norms of the finest level into hred[0..7]: 5 norms, sum p, bad count
-static int norms(qnsch_ctx *x, double *rout, bool shift)
+// run a sequence of operations on one context
+static int run_ops(qnsch_ctx *x, const std::vector<Op> &prog)
 {
-    DLev &D = x->L[0];
-    size_t n = (size_t)D.m1 * D.m2;
-    const dim3 tg = tiles(D.m1, D.m2);
-    unsigned nbt = tg.x * tg.y, nb = nblocks(n);
-    Rhs F = {};
-    hipLaunchKernelGGL(k_resid_norm, tg, dim3(TBLK), 0, x->s, x->P, view_of(x, 0), F, x->partials, rout);
-    int rc;
-    if ((rc = launch_check(x, "k_resid_norm"))) return rc;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLK), 0, x->s, x->partials, (int)nbt, x->red);
-    if ((rc = launch_check(x, "k_finalize"))) return rc;
-    if (shift) {
-        hipLaunchKernelGGL(k_shift_p, dim3(nb), dim3(BLK), 0, x->s, D.p, D.m1, D.m2, D.pitch, x->red);
-        if ((rc = launch_check(x, "k_shift_p"))) return rc;
+    std::vector<std::pair<qnsch_ctx *, int>> v(1);
+    for (const Op &o : prog) {
+        v[0] = { x, o.level };
+        int rc = launch_op(o.kind, o.colour, v, x->s);
+        if (rc) return rc;
     }
-    HIPCHK(x, hipMemcpyAsync(x->hred, x->red, NRED * sizeof(double), hipMemcpyDeviceToHost, x->s));
+    return QNSCH_OK;
+}
+
+// wait for the context's stream (the reduced values are then in red_host)
+static int read_red(qnsch_ctx *x)
+{
     HIPCHK(x, hipStreamSynchronize(x->s));
-    for (int q = 0; q < 5; q++) x->hred[q] = sqrt(D.h * D.h * x->hred[q]);
     return prof_collect(x);
-}
-
-static int restore(qnsch_ctx *x)
-{
-    DLev &D = x->L[0];
-    size_t bytes = D.n() * sizeof(double);
-    HIPCHK(x, hipMemcpyAsync(D.c, D.cn, bytes, hipMemcpyDeviceToDevice, x->s));
-    HIPCHK(x, hipMemcpyAsync(D.ub[D.cur], D.un, bytes, hipMemcpyDeviceToDevice, x->s));
-    HIPCHK(x, hipMemcpyAsync(D.vb[D.cur], D.vn, bytes, hipMemcpyDeviceToDevice, x->s));
-    HIPCHK(x, hipMemcpyAsync(D.mu, x->mu_save, bytes, hipMemcpyDeviceToDevice, x->s));
-    HIPCHK(x, hipMemcpyAsync(D.p, x->p_save, bytes, hipMemcpyDeviceToDevice, x->s));
-    HIPCHK(x, hipStreamSynchronize(x->s));
-    x->in_step = 0;
-    return QNSCH_OK;
 }
 
 static double *dalloc(qnsch_ctx *x, size_t n, int *rc)
@@ -623,8 +289,58 @@ static double *dalloc(qnsch_ctx *x, size_t n, int *rc)
         return nullptr;
     }
     x->allocs.push_back(p);
+    x->footprint += n * sizeof(double);
     if (hipMemsetAsync(p, 0, n * sizeof(double), x->s) != hipSuccess) *rc = QNSCH_EDEVICE;
     return (double *)p;
+}
+
+// level count of a grid (0 = automatic) or -1 if invalid
+static int level_count(const qnsch_grid *g)
+{
+    int nl = g->levels;
+    if (nl <= 0) {
+        nl = 1;
+        while (nl < 16 && g->m1 % (1 << (nl + 1)) == 0 && g->m2 % (1 << (nl + 1)) == 0 && (g->m1 >> nl) >= 4
+               && (g->m2 >> nl) >= 4)
+            nl++;
+    }
+    if (nl > 16 || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) return -1;
+    if (coarse_lds_doubles(g->m1 >> (nl - 1), g->m2 >> (nl - 1)) * sizeof(double) > 65536) return -1;
+    return nl;
+}
+
+// device bytes of a context (the allocations of qnsch_create)
+static size_t footprint_of(const qnsch_grid *g)
+{
+    const int nl = level_count(g);
+    if (nl < 0) return 0;
+    size_t b = 0;
+    for (int l = 0; l < nl; l++) {
+        const size_t n = (size_t)(g->m1 >> l) * (g->m2 >> l);
+        b += n * (l > 0 ? 20 : 10);
+    }
+    const size_t n0 = (size_t)g->m1 * g->m2;
+    b += 2 * n0 + (size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks(n0)) * NRED + NRED;
+    return b * sizeof(double) + (size_t)nl * sizeof(Desc);
+}
+
+static void phys_of(const qnsch_params *p, Phys &P)
+{
+    P.rho1 = p->rho1; P.rho2 = p->rho2; P.rho12 = p->rho1 * p->rho2; P.drho = p->rho2 - p->rho1;
+    P.visc1 = p->visc1; P.visc2 = p->visc2; P.visc12 = p->visc1 * p->visc2; P.dvisc = p->visc2 - p->visc1;
+    P.alpha = (p->rho2 - p->rho1) / (p->rho1 * p->rho2);
+    P.inv_Re = 1.0 / p->Re; P.inv_M = 1.0 / p->M; P.inv_Pe = 1.0 / p->Pe;
+    P.K1 = p->M * p->eta / (p->eps * p->We);
+    P.K2 = p->eps * p->eta * p->M / (2.0 * p->We);
+    P.K3 = p->eps * p->eta * p->M / p->We;
+    P.inv_Fr = p->inv_Fr; P.rho_ref = p->rho_ref; P.mob_reg = p->mob_reg;
+    P.inv_dt = 0.0;
+}
+
+static int upload_desc(qnsch_ctx *x)
+{
+    HIPCHK(x, hipMemcpyAsync(x->dd, x->hd, x->nlev * sizeof(Desc), hipMemcpyHostToDevice, x->s));
+    return QNSCH_OK;
 }
 
 // ===========================================================================
@@ -649,17 +365,18 @@ int qnsch_levels(const qnsch_ctx *x) { return x ? x->nlev : 0; }
 void qnsch_destroy(qnsch_ctx *x)
 {
     if (!x) return;
-    if (x->s) (void)hipStreamSynchronize(x->s);
+    (void)hipStreamSynchronize(x->s);
     for (void *p : x->allocs) (void)hipFree(p);
-    for (hipEvent_t e : x->ev) (void)hipEventDestroy(e);
-    if (x->hred) (void)hipHostFree(x->hred);
+    for (hipEvent_t e : x->pev) (void)hipEventDestroy(e);
+    if (x->ev) (void)hipEventDestroy(x->ev);
+    if (x->red_host) (void)hipHostFree(x->red_host);
+    if (x->hd) (void)hipHostFree(x->hd);
     delete x;
 }
 
-int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream, qnsch_ctx **out)
+static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o)
 {
-    if (!g || !p || !out) return QNSCH_EINVAL;
-    *out = nullptr;
+    if (!g || !p) return QNSCH_EINVAL;
     if (g->m1 < 4 || g->m2 < 4 || (g->m1 & 1) || (g->m2 & 1)) return QNSCH_EINVAL;
     if (!(g->Lx > 0) || !(g->Ly > 0)) return QNSCH_EINVAL;
     const double hx = g->Lx / g->m1, hy = g->Ly / g->m2;
@@ -668,77 +385,82 @@ int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o
     if (!(p->rho1 > 0) || !(p->rho2 > 0) || !(p->visc1 > 0) || !(p->visc2 > 0) || !(p->Re > 0) || !(p->We > 0)
         || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
         return QNSCH_EINVAL;
-    qnsch_opts opt;
-    qnsch_default_opts(&opt);
-    if (o) opt = *o;
-    if (opt.nu1 < 0 || opt.nu2 < 0 || opt.nu_coarse < 1 || opt.max_vcycles < 0 || opt.precision != QNSCH_FP64)
+    if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0 || o->precision != QNSCH_FP64))
         return QNSCH_EINVAL;
-    int nl = g->levels;
-    if (nl <= 0) {
-        nl = 1;
-        while (nl < 16 && g->m1 % (1 << (nl + 1)) == 0 && g->m2 % (1 << (nl + 1)) == 0 && (g->m1 >> nl) >= 4
-               && (g->m2 >> nl) >= 4)
-            nl++;
-    }
-    if (nl > 16 || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) return QNSCH_EINVAL;
-    // the coarsest level is relaxed by one workgroup with the level in LDS
-    if (coarse_lds_doubles(g->m1 >> (nl - 1), g->m2 >> (nl - 1)) * sizeof(double) > 65536) return QNSCH_EINVAL;
+    if (level_count(g) < 0) return QNSCH_EINVAL;
+    return QNSCH_OK;
+}
 
+int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream, qnsch_ctx **out)
+{
+    if (!out) return QNSCH_EINVAL;
+    *out = nullptr;
+    int rc = validate(g, p, o);
+    if (rc) return rc;
     qnsch_ctx *x = new qnsch_ctx();
     x->g = *g;
-    x->g.levels = nl;
+    x->nlev = level_count(g);
+    x->g.levels = x->nlev;
     x->prm = *p;
-    x->opt = opt;
-    x->nlev = nl;
+    qnsch_default_opts(&x->opt);
+    if (o) x->opt = *o;
     x->s = (hipStream_t)stream;
-    Phys &P = x->P;
-    P.rho1 = p->rho1; P.rho2 = p->rho2; P.rho12 = p->rho1 * p->rho2; P.drho = p->rho2 - p->rho1;
-    P.visc1 = p->visc1; P.visc2 = p->visc2; P.visc12 = p->visc1 * p->visc2; P.dvisc = p->visc2 - p->visc1;
-    P.alpha = (p->rho2 - p->rho1) / (p->rho1 * p->rho2);
-    P.inv_Re = 1.0 / p->Re; P.inv_M = 1.0 / p->M; P.inv_Pe = 1.0 / p->Pe;
-    P.K1 = p->M * p->eta / (p->eps * p->We);
-    P.K2 = p->eps * p->eta * p->M / (2.0 * p->We);
-    P.K3 = p->eps * p->eta * p->M / p->We;
-    P.inv_Fr = p->inv_Fr; P.rho_ref = p->rho_ref; P.mob_reg = p->mob_reg;
-    P.inv_dt = 0.0;
-    int rc = QNSCH_OK;
-    for (int l = 0; l < nl; l++) {
+    memset(&x->st, 0, sizeof(x->st));
+    const double hx = g->Lx / g->m1;
+    if (hipHostMalloc((void **)&x->hd, x->nlev * sizeof(Desc), hipHostMallocDefault) != hipSuccess
+        || hipHostMalloc((void **)&x->red_host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        qnsch_destroy(x);
+        return QNSCH_ENOMEM;
+    }
+    memset((void *)x->hd, 0, x->nlev * sizeof(Desc));
+    memset(x->red_host, 0, 16 * sizeof(double));
+    void *ddp = nullptr;
+    if (hipMalloc(&ddp, x->nlev * sizeof(Desc)) != hipSuccess) { qnsch_destroy(x); return QNSCH_ENOMEM; }
+    x->allocs.push_back(ddp);
+    x->dd = (Desc *)ddp;
+    Phys P;
+    phys_of(p, P);
+    for (int l = 0; l < x->nlev && !rc; l++) {
         DLev &D = x->L[l];
         D.m1 = g->m1 >> l;
         D.m2 = g->m2 >> l;
         D.pitch = D.m1;
         D.h = hx * (double)(1 << l);
-        size_t n = D.n();
-        D.c = dalloc(x, n, &rc); D.mu = dalloc(x, n, &rc); D.p = dalloc(x, n, &rc);
-        D.ub[0] = dalloc(x, n, &rc); D.ub[1] = dalloc(x, n, &rc);
-        D.vb[0] = dalloc(x, n, &rc); D.vb[1] = dalloc(x, n, &rc);
-        D.cn = dalloc(x, n, &rc); D.un = dalloc(x, n, &rc); D.vn = dalloc(x, n, &rc);
+        const size_t n = D.n();
+        Desc &d = x->hd[l];
+        d.P = P;
+        d.c = dalloc(x, n, &rc); d.mu = dalloc(x, n, &rc); d.p = dalloc(x, n, &rc);
+        d.ub[0] = dalloc(x, n, &rc); d.ub[1] = dalloc(x, n, &rc);
+        d.vb[0] = dalloc(x, n, &rc); d.vb[1] = dalloc(x, n, &rc);
+        d.cn = dalloc(x, n, &rc); d.un = dalloc(x, n, &rc); d.vn = dalloc(x, n, &rc);
         if (l > 0) {
-            D.fc = dalloc(x, n, &rc); D.fmu = dalloc(x, n, &rc); D.fp = dalloc(x, n, &rc);
-            D.fu = dalloc(x, n, &rc); D.fv = dalloc(x, n, &rc);
-            D.c0 = dalloc(x, n, &rc); D.mu0 = dalloc(x, n, &rc); D.p0 = dalloc(x, n, &rc);
-            D.u0 = dalloc(x, n, &rc); D.v0 = dalloc(x, n, &rc);
+            d.fc = dalloc(x, n, &rc); d.fmu = dalloc(x, n, &rc); d.fp = dalloc(x, n, &rc);
+            d.fu = dalloc(x, n, &rc); d.fv = dalloc(x, n, &rc);
+            d.c0 = dalloc(x, n, &rc); d.mu0 = dalloc(x, n, &rc); d.p0 = dalloc(x, n, &rc);
+            d.u0 = dalloc(x, n, &rc); d.v0 = dalloc(x, n, &rc);
         }
-        if (rc) break;
+        d.m1 = D.m1; d.m2 = D.m2; d.pitch = D.pitch; d.bcx = g->bc_x; d.bcy = g->bc_y;
+        d.h = D.h; d.inv_h = 1.0 / D.h;
+        d.coarse = l + 1 < x->nlev ? x->dd + l + 1 : nullptr;
     }
-    size_t n0 = x->L[0].n();
     if (!rc) {
-        x->mu_save = dalloc(x, n0, &rc);
-        x->p_save = dalloc(x, n0, &rc);
-        const dim3 tg = tiles(g->m1, g->m2);
-        const size_t nbmax = std::max((size_t)nblocks((size_t)g->m1 * g->m2), (size_t)tg.x * tg.y);
-        x->partials = dalloc(x, nbmax * NRED, &rc);
-        x->red = dalloc(x, NRED, &rc);
-        x->rout = nullptr;
+        Desc &d0 = x->hd[0];
+        const size_t n0 = x->L[0].n();
+        d0.mus = dalloc(x, n0, &rc);
+        d0.ps = dalloc(x, n0, &rc);
+        const size_t np = (size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks((size_t)g->m1 * g->m2));
+        d0.partials = dalloc(x, np * NRED, &rc);
+        d0.red = dalloc(x, NRED, &rc);
+        d0.red_host = x->red_host;
+        d0.rout = nullptr;
     }
-    if (!rc && hipHostMalloc((void **)&x->hred, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
-        rc = QNSCH_ENOMEM;
+    if (!rc && hipEventCreateWithFlags(&x->ev, hipEventDisableTiming) != hipSuccess) rc = QNSCH_EDEVICE;
+    if (!rc) rc = upload_desc(x);
     if (!rc && hipStreamSynchronize(x->s) != hipSuccess) rc = QNSCH_EDEVICE;
     if (rc) {
         qnsch_destroy(x);
         return rc;
     }
-    memset(&x->st, 0, sizeof(x->st));
     *out = x;
     return QNSCH_OK;
 }
@@ -762,20 +484,21 @@ static int get(qnsch_ctx *x, double *dst, const double *src)
 static int upload(qnsch_ctx *x, const double *c, const double *mu, const double *p, const double *u, const double *v)
 {
     DLev &D = x->L[0];
+    Desc &d = x->hd[0];
     const size_t n = (size_t)D.m1 * D.m2;
-    std::vector<double> z(n, 0.0), uu(n), vv(n);
-    if (u) memcpy(uu.data(), u, n * sizeof(double)); else std::fill(uu.begin(), uu.end(), 0.0);
-    if (v) memcpy(vv.data(), v, n * sizeof(double)); else std::fill(vv.begin(), vv.end(), 0.0);
+    std::vector<double> z(n, 0.0), uu(n, 0.0), vv(n, 0.0);
+    if (u) memcpy(uu.data(), u, n * sizeof(double));
+    if (v) memcpy(vv.data(), v, n * sizeof(double));
     if (x->g.bc_x == QNSCH_BC_WALL)
         for (int j = 0; j < D.m2; j++) uu[(size_t)j * D.m1] = 0.0;
     if (x->g.bc_y == QNSCH_BC_WALL)
         for (int i = 0; i < D.m1; i++) vv[i] = 0.0;
     int rc;
-    if ((rc = put(x, D.c, c))) return rc;
-    if ((rc = put(x, D.mu, mu ? mu : z.data()))) return rc;
-    if ((rc = put(x, D.p, p ? p : z.data()))) return rc;
-    if ((rc = put(x, D.ub[D.cur], uu.data()))) return rc;
-    if ((rc = put(x, D.vb[D.cur], vv.data()))) return rc;
+    if ((rc = put(x, d.c, c))) return rc;
+    if ((rc = put(x, d.mu, mu ? mu : z.data()))) return rc;
+    if ((rc = put(x, d.p, p ? p : z.data()))) return rc;
+    if ((rc = put(x, d.ub[D.cur], uu.data()))) return rc;
+    if ((rc = put(x, d.vb[D.cur], vv.data()))) return rc;
     HIPCHK(x, hipStreamSynchronize(x->s));
     return QNSCH_OK;
 }
@@ -800,32 +523,33 @@ int qnsch_get_state(qnsch_ctx *x, double *c, double *mu, double *p, double *u, d
 {
     if (!x) return QNSCH_EINVAL;
     DLev &D = x->L[0];
+    Desc &d = x->hd[0];
     int rc;
-    if (c && (rc = get(x, c, D.c))) return rc;
-    if (mu && (rc = get(x, mu, D.mu))) return rc;
-    if (p && (rc = get(x, p, D.p))) return rc;
-    if (u && (rc = get(x, u, D.ub[D.cur]))) return rc;
-    if (v && (rc = get(x, v, D.vb[D.cur]))) return rc;
+    if (c && (rc = get(x, c, d.c))) return rc;
+    if (mu && (rc = get(x, mu, d.mu))) return rc;
+    if (p && (rc = get(x, p, d.p))) return rc;
+    if (u && (rc = get(x, u, d.ub[D.cur]))) return rc;
+    if (v && (rc = get(x, v, d.vb[D.cur]))) return rc;
     HIPCHK(x, hipStreamSynchronize(x->s));
     return QNSCH_OK;
+}
+
+static int set_dt(qnsch_ctx *x, double dt)
+{
+    x->dt = dt;
+    for (int l = 0; l < x->nlev; l++) x->hd[l].P.inv_dt = 1.0 / dt;
+    return upload_desc(x);
 }
 
 int qnsch_begin_step(qnsch_ctx *x, double dt)
 {
     if (!x || !(dt > 0)) return QNSCH_EINVAL;
-    x->dt = dt;
-    x->P.inv_dt = 1.0 / dt;
-    DLev &D = x->L[0];
-    hipLaunchKernelGGL(k_begin, dim3(nblocks((size_t)D.m1 * D.m2)), dim3(BLK), 0, x->s, view_of(x, 0), D.cn, D.un,
-                       D.vn, x->mu_save, x->p_save);
     int rc;
-    if ((rc = launch_check(x, "k_begin"))) return rc;
-    for (int l = 1; l < x->nlev; l++) {
-        DLev &F = x->L[l - 1], &C = x->L[l];
-        hipLaunchKernelGGL(k_restrict_n, dim3(nblocks((size_t)C.m1 * C.m2)), dim3(BLK), 0, x->s, F.cn, F.un, F.vn,
-                           F.pitch, C.cn, C.un, C.vn, C.m1, C.m2, C.pitch);
-        if ((rc = launch_check(x, "k_restrict_n"))) return rc;
-    }
+    if ((rc = set_dt(x, dt))) return rc;
+    std::vector<Op> prog;
+    begin_program(x->nlev, prog);
+    prog.pop_back(); // no residual here
+    if ((rc = run_ops(x, prog))) return rc;
     x->in_step = 1;
     x->st.vcycles = 0;
     return QNSCH_OK;
@@ -835,10 +559,11 @@ int qnsch_vcycle(qnsch_ctx *x)
 {
     if (!x) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "vcycle outside a step"; return QNSCH_EBUSY; }
+    std::vector<Op> prog;
+    vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, prog);
     int rc;
-    if ((rc = vcycle_rec(x, 0))) return rc;
-    // pbar mean to zero (the reduction also gives the residual norms)
-    return norms(x, nullptr, true);
+    if ((rc = run_ops(x, prog))) return rc;
+    return read_red(x);
 }
 
 int qnsch_residual(qnsch_ctx *x, double *r_out, double nrm[5])
@@ -848,15 +573,15 @@ int qnsch_residual(qnsch_ctx *x, double *r_out, double nrm[5])
     DLev &D = x->L[0];
     const size_t n = (size_t)D.m1 * D.m2;
     int rc = QNSCH_OK;
-    if (r_out && !x->rout) {
-        x->rout = dalloc(x, 5 * n, &rc);
+    if (r_out && !x->hd[0].rout) {
+        x->hd[0].rout = dalloc(x, 5 * n, &rc);
         if (rc) return rc;
+        if ((rc = upload_desc(x))) return rc;
     }
-    if ((rc = norms(x, r_out ? x->rout : nullptr, false))) return rc;
-    if (nrm) memcpy(nrm, x->hred, 5 * sizeof(double));
-    if (r_out) {
-        HIPCHK(x, hipMemcpy(r_out, x->rout, 5 * n * sizeof(double), hipMemcpyDeviceToHost));
-    }
+    if ((rc = run_ops(x, { { OP_NORM0, 0, 0 } }))) return rc;
+    if ((rc = read_red(x))) return rc;
+    if (nrm) memcpy(nrm, x->red_host, 5 * sizeof(double));
+    if (r_out) HIPCHK(x, hipMemcpy(r_out, x->hd[0].rout, 5 * n * sizeof(double), hipMemcpyDeviceToHost));
     return QNSCH_OK;
 }
 
@@ -865,7 +590,7 @@ int qnsch_halfsweep(qnsch_ctx *x, int colour)
     if (!x) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "halfsweep outside a step"; return QNSCH_EBUSY; }
     int rc;
-    if ((rc = halfsweep(x, 0, colour & 1))) return rc;
+    if ((rc = run_ops(x, { { OP_HS, 0, colour & 1 } }))) return rc;
     HIPCHK(x, hipStreamSynchronize(x->s));
     return QNSCH_OK;
 }
@@ -877,38 +602,59 @@ int qnsch_end_step(qnsch_ctx *x)
     return QNSCH_OK;
 }
 
+// decision after a residual reduction: 1 converged, 0 continue, <0 error
+static int judge(qnsch_ctx *x, int vcycles)
+{
+    double mx = 0.0;
+    bool finite = true;
+    for (int q = 0; q < 5; q++) {
+        if (!std::isfinite(x->red_host[q])) finite = false;
+        mx = x->red_host[q] > mx ? x->red_host[q] : mx;
+    }
+    if (!finite || x->red_host[6] != 0.0) {
+        x->err = "diverged: non-finite residual or c past the density pole";
+        return QNSCH_EDIVERGED;
+    }
+    if (mx <= x->opt.tol) return 1;
+    if (vcycles >= x->opt.max_vcycles) {
+        x->err = "no convergence within max_vcycles";
+        return QNSCH_ENOCONV;
+    }
+    return 0;
+}
+
 int qnsch_step(qnsch_ctx *x, double dt)
 {
+    if (!x || !(dt > 0)) return QNSCH_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     int rc;
-    if ((rc = qnsch_begin_step(x, dt))) return rc;
-    if ((rc = norms(x, nullptr, false))) return rc;
-    memcpy(x->st.res0, x->hred, 5 * sizeof(double));
+    if ((rc = set_dt(x, dt))) return rc;
+    std::vector<Op> begin, cyc;
+    begin_program(x->nlev, begin);
+    vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, cyc);
+    if ((rc = run_ops(x, begin))) return rc;
+    if ((rc = read_red(x))) return rc;
+    x->in_step = 1;
+    memcpy(x->st.res0, x->red_host, 5 * sizeof(double));
     int it = 0;
+    x->st.vcycles = 0;
     for (;;) {
-        double mx = 0.0;
-        bool finite = true;
-        for (int q = 0; q < 5; q++) {
-            if (!std::isfinite(x->hred[q])) finite = false;
-            mx = x->hred[q] > mx ? x->hred[q] : mx;
+        const int j = judge(x, it);
+        if (j < 0) {
+            const std::string msg = x->err;
+            run_ops(x, { { OP_RESTORE, 0, 0 } });
+            HIPCHK(x, hipStreamSynchronize(x->s));
+            x->err = msg;
+            x->in_step = 0;
+            return j;
         }
-        if (!finite || x->hred[6] != 0.0) {
-            restore(x);
-            x->err = "diverged: non-finite residual or c past the density pole";
-            return QNSCH_EDIVERGED;
-        }
-        if (mx <= x->opt.tol) break;
-        if (it >= x->opt.max_vcycles) {
-            restore(x);
-            x->err = "no convergence within max_vcycles";
-            return QNSCH_ENOCONV;
-        }
-        if ((rc = vcycle_rec(x, 0))) return rc;
-        if ((rc = norms(x, nullptr, true))) return rc;
+        if (j == 1) break;
+        if ((rc = run_ops(x, cyc))) return rc;
+        if ((rc = read_red(x))) return rc;
         it++;
         x->st.vcycles = it;
     }
-    memcpy(x->st.res, x->hred, 5 * sizeof(double));
+    memcpy(x->st.res, x->red_host, 5 * sizeof(double));
     x->in_step = 0;
     x->st.step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return QNSCH_OK;
@@ -916,17 +662,27 @@ int qnsch_step(qnsch_ctx *x, double dt)
 
 static int reduce_me(qnsch_ctx *x)
 {
-    DLev &D = x->L[0];
-    size_t n = (size_t)D.m1 * D.m2;
-    unsigned nb = nblocks(n);
-    hipLaunchKernelGGL(k_mass_energy, dim3(nb), dim3(BLK), 0, x->s, x->P, view_of(x, 0), D.h, x->partials);
     int rc;
-    if ((rc = launch_check(x, "k_mass_energy"))) return rc;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(BLK), 0, x->s, x->partials, (int)nb, x->red);
-    if ((rc = launch_check(x, "k_finalize"))) return rc;
-    HIPCHK(x, hipMemcpyAsync(x->hred, x->red, NRED * sizeof(double), hipMemcpyDeviceToHost, x->s));
-    HIPCHK(x, hipStreamSynchronize(x->s));
-    return QNSCH_OK;
+    if ((rc = run_ops(x, { { OP_STEPEND, 0, 0 } }))) return rc;
+    return read_red(x);
+}
+
+// mass and energy from the sums of k_mass_energy
+static void me_from_sums(const qnsch_ctx *x, const double *s, double mass[2], double en[5])
+{
+    const double h2 = x->L[0].h * x->L[0].h;
+    const qnsch_params &p = x->prm;
+    if (mass) {
+        mass[0] = h2 * s[0];
+        mass[1] = h2 * s[1];
+    }
+    if (en) {
+        en[1] = h2 * s[2];
+        en[2] = p.eps * p.eta / (2.0 * p.We) * h2 * s[3];
+        en[3] = p.eta / (p.eps * p.We) * h2 * s[4];
+        en[4] = p.inv_Fr * h2 * s[5];
+        en[0] = en[1] + en[2] + en[3] + en[4];
+    }
 }
 
 int qnsch_mass(qnsch_ctx *x, double out[2])
@@ -934,9 +690,7 @@ int qnsch_mass(qnsch_ctx *x, double out[2])
     if (!x || !out) return QNSCH_EINVAL;
     int rc;
     if ((rc = reduce_me(x))) return rc;
-    const double h2 = x->L[0].h * x->L[0].h;
-    out[0] = h2 * x->hred[0];
-    out[1] = h2 * x->hred[1];
+    me_from_sums(x, x->red_host, out, nullptr);
     return QNSCH_OK;
 }
 
@@ -945,13 +699,21 @@ int qnsch_energy(qnsch_ctx *x, double out[5])
     if (!x || !out) return QNSCH_EINVAL;
     int rc;
     if ((rc = reduce_me(x))) return rc;
-    const double h2 = x->L[0].h * x->L[0].h;
-    const qnsch_params &p = x->prm;
-    out[1] = h2 * x->hred[2];
-    out[2] = p.eps * p.eta / (2.0 * p.We) * h2 * x->hred[3];
-    out[3] = p.eta / (p.eps * p.We) * h2 * x->hred[4];
-    out[4] = p.inv_Fr * h2 * x->hred[5];
-    out[0] = out[1] + out[2] + out[3] + out[4];
+    me_from_sums(x, x->red_host, nullptr, out);
+    return QNSCH_OK;
+}
+
+int qnsch_stats(const qnsch_ctx *x, qnsch_step_stats *out)
+{
+    if (!x || !out) return QNSCH_EINVAL;
+    *out = x->st;
+    return QNSCH_OK;
+}
+
+int qnsch_synchronize(qnsch_ctx *x)
+{
+    if (!x) return QNSCH_EINVAL;
+    HIPCHK(x, hipStreamSynchronize(x->s));
     return QNSCH_OK;
 }
 
@@ -975,13 +737,6 @@ int qnsch_profile_read(qnsch_ctx *x, double out[2])
     if ((rc = prof_collect(x))) return rc;
     out[0] = (double)x->prof_n;
     out[1] = x->prof_ms;
-    return QNSCH_OK;
-}
-
-int qnsch_synchronize(qnsch_ctx *x)
-{
-    if (!x) return QNSCH_EINVAL;
-    HIPCHK(x, hipStreamSynchronize(x->s));
     return QNSCH_OK;
 }
 
@@ -1014,11 +769,304 @@ int qnsch_copy_probe(size_t n, int reps, double out[2])
     return rc;
 }
 
-int qnsch_stats(const qnsch_ctx *x, qnsch_step_stats *out)
+} // extern "C"
+
+// ===========================================================================
+// continuous-batching server
+
+namespace {
+enum { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
+
+struct Req {
+    uint64_t id = 0;
+    qnsch_grid g;
+    qnsch_params p;
+    qnsch_opts o;
+    std::vector<double> c0;
+    int nsteps = 0;
+    double dt = 0;
+    qnsch_ctx *x = nullptr;
+    int state = RQ_QUEUED, status = QNSCH_OK;
+    size_t foot = 0;
+    int step = 0, vcycles = 0;
+    std::vector<Op> prog; // operations still to issue, from pc on
+    size_t pc = 0;
+    int wait = 0;         // 1: waiting for a residual, 2: for step-end sums
+    std::chrono::steady_clock::time_point t_submit, t_admit, t_step0, t_done;
+    std::vector<double> step_ms, mass, energy;
+    std::vector<int> vc;
+    std::vector<double> out[5]; // final state
+};
+} // namespace
+
+struct qnsch_server {
+    hipStream_t s = nullptr;
+    size_t budget = 0, used = 0;
+    int max_slots = 0;
+    uint64_t next_id = 1;
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::map<uint64_t, Req *> all;
+    std::vector<double> lat_ms; // every completed step
+    double cell_steps = 0.0;
+    bool started = false;
+    std::chrono::steady_clock::time_point t_first, t_last;
+    long launches = 0, ticks = 0;
+    std::string err;
+};
+
+static double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b)
 {
-    if (!x || !out) return QNSCH_EINVAL;
-    *out = x->st;
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+static void start_step(Req *r)
+{
+    r->prog.clear();
+    r->pc = 0;
+    begin_program(r->x->nlev, r->prog);
+    r->vcycles = 0;
+    r->t_step0 = std::chrono::steady_clock::now();
+}
+
+static void finish(qnsch_server *S, Req *r, int status)
+{
+    r->status = status;
+    r->state = RQ_DONE;
+    r->t_done = std::chrono::steady_clock::now();
+    S->t_last = r->t_done;
+    if (r->x) {
+        const size_t n = (size_t)r->g.m1 * r->g.m2;
+        for (int q = 0; q < 5; q++) r->out[q].assign(n, 0.0);
+        qnsch_get_state(r->x, r->out[0].data(), r->out[1].data(), r->out[2].data(), r->out[3].data(),
+                        r->out[4].data());
+        qnsch_destroy(r->x);
+        r->x = nullptr;
+    }
+    S->used -= r->foot;
+}
+
+// act on a completed reduction of request r
+static void after_reduction(qnsch_server *S, Req *r)
+{
+    qnsch_ctx *x = r->x;
+    if (r->wait == 2) { // step-end sums: record mass and energy, next step
+        double m[2], e[5];
+        me_from_sums(x, x->red_host, m, e);
+        r->mass.insert(r->mass.end(), m, m + 2);
+        r->energy.insert(r->energy.end(), e, e + 5);
+        const double ms = ms_between(r->t_step0, std::chrono::steady_clock::now());
+        r->step_ms.push_back(ms);
+        r->vc.push_back(r->vcycles);
+        S->lat_ms.push_back(ms);
+        S->cell_steps += (double)r->g.m1 * r->g.m2;
+        r->step++;
+        r->wait = 0;
+        if (r->step >= r->nsteps) finish(S, r, QNSCH_OK);
+        else start_step(r);
+        return;
+    }
+    r->wait = 0;
+    const int j = judge(x, r->vcycles);
+    r->prog.clear();
+    r->pc = 0;
+    if (j < 0) {
+        r->prog.push_back({ OP_RESTORE, 0, 0 });
+        r->status = j;
+    } else if (j == 1) {
+        r->prog.push_back({ OP_STEPEND, 0, 0 });
+    } else {
+        vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, r->prog);
+        r->vcycles++;
+    }
+}
+
+extern "C" {
+
+size_t qnsch_footprint(const qnsch_grid *g) { return g ? footprint_of(g) : 0; }
+
+int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *stream, qnsch_server **out)
+{
+    if (!out || max_slots < 1 || hbm_budget == 0) return QNSCH_EINVAL;
+    qnsch_server *S = new qnsch_server();
+    S->budget = hbm_budget;
+    S->max_slots = max_slots;
+    S->s = (hipStream_t)stream;
+    *out = S;
     return QNSCH_OK;
 }
+
+void qnsch_server_destroy(qnsch_server *S)
+{
+    if (!S) return;
+    (void)hipStreamSynchronize(S->s);
+    for (auto &kv : S->all) {
+        if (kv.second->x) qnsch_destroy(kv.second->x);
+        delete kv.second;
+    }
+    delete S;
+}
+
+int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o,
+                        const double *c0, int32_t nsteps, double dt, uint64_t *id)
+{
+    if (!S || !g || !p || !c0 || nsteps < 1 || !(dt > 0) || !id) return QNSCH_EINVAL;
+    int rc = validate(g, p, o);
+    if (rc) return rc;
+    Req *r = new Req();
+    r->id = S->next_id++;
+    r->g = *g;
+    r->p = *p;
+    qnsch_default_opts(&r->o);
+    if (o) r->o = *o;
+    r->c0.assign(c0, c0 + (size_t)g->m1 * g->m2);
+    r->nsteps = nsteps;
+    r->dt = dt;
+    r->foot = footprint_of(g);
+    if (r->foot > S->budget) {
+        delete r;
+        return QNSCH_ENOMEM;
+    }
+    r->t_submit = std::chrono::steady_clock::now();
+    S->queue.push_back(r);
+    S->all[r->id] = r;
+    *id = r->id;
+    return QNSCH_OK;
+}
+
+int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
+{
+    if (!S) return QNSCH_EINVAL;
+    auto done = [](Req *r) { return r->state == RQ_DONE; };
+    for (int tick = 0; tick < max_ticks; tick++) {
+        // admission: first come, first served, while a slot is free and the
+        // footprint fits the budget
+        while (!S->queue.empty() && (int)S->active.size() < S->max_slots
+               && S->used + S->queue.front()->foot <= S->budget) {
+            Req *r = S->queue.front();
+            S->queue.pop_front();
+            qnsch_ctx *x = nullptr;
+            int rc = qnsch_create(&r->g, &r->p, &r->o, S->s, &x);
+            if (!rc) rc = qnsch_set_state(x, r->c0.data(), nullptr, nullptr, nullptr, nullptr);
+            if (!rc) rc = set_dt(x, r->dt);
+            r->t_admit = std::chrono::steady_clock::now();
+            if (!S->started) { S->started = true; S->t_first = r->t_admit; }
+            if (rc) {
+                if (x) qnsch_destroy(x);
+                r->status = rc;
+                r->state = RQ_DONE;
+                continue;
+            }
+            r->x = x;
+            r->state = RQ_RUNNING;
+            S->used += r->foot;
+            start_step(r);
+            S->active.push_back(r);
+        }
+        // completed reductions
+        for (Req *r : S->active)
+            if (r->wait && hipEventQuery(r->x->ev) == hipSuccess) after_reduction(S, r);
+        S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
+        // the next operation of every ready request, one launch per kind
+        // (kind, colour, coarse sweeps, relaxation factor): requests whose
+        // options differ do not share a launch
+        typedef std::tuple<int, int, int, double> Key;
+        std::map<Key, std::vector<std::pair<qnsch_ctx *, int>>> groups;
+        std::map<Key, std::vector<Req *>> owners;
+        for (Req *r : S->active) {
+            if (r->wait || r->pc >= r->prog.size()) continue;
+            const Op &o = r->prog[r->pc];
+            const Key key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega);
+            groups[key].push_back({ r->x, o.level });
+            owners[key].push_back(r);
+        }
+        bool launched = false;
+        for (auto &kv : groups) {
+            int rc = launch_op(std::get<0>(kv.first), std::get<1>(kv.first), kv.second, S->s);
+            if (rc) {
+                S->err = kv.second[0].first->err;
+                return rc;
+            }
+            S->launches++;
+            launched = true;
+            for (Req *r : owners[kv.first]) {
+                const int kind = r->prog[r->pc].kind;
+                r->pc++;
+                if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
+                    r->wait = kind == OP_STEPEND ? 2 : 1;
+                    (void)hipEventRecord(r->x->ev, S->s);
+                } else if (kind == OP_RESTORE) {
+                    (void)hipStreamSynchronize(S->s);
+                    finish(S, r, r->status);
+                }
+            }
+        }
+        S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
+        S->ticks++;
+        if (!launched) {
+            if (S->active.empty()) break; // nothing running (queue empty or waiting for budget)
+            (void)hipStreamSynchronize(S->s); // everyone waits on a reduction
+        }
+    }
+    return (int)(S->queue.size() + S->active.size());
+}
+
+int qnsch_server_poll(qnsch_server *S, uint64_t id, int32_t *state, int32_t *status)
+{
+    if (!S) return QNSCH_EINVAL;
+    auto it = S->all.find(id);
+    if (it == S->all.end()) return QNSCH_EINVAL;
+    if (state) *state = it->second->state;
+    if (status) *status = it->second->status;
+    return QNSCH_OK;
+}
+
+int qnsch_server_result(qnsch_server *S, uint64_t id, double *c, double *mu, double *p, double *u, double *v,
+                        double *mass_hist, double *energy_hist, double *step_ms, int32_t *vcycles, double *times)
+{
+    if (!S) return QNSCH_EINVAL;
+    auto it = S->all.find(id);
+    if (it == S->all.end()) return QNSCH_EINVAL;
+    Req *r = it->second;
+    if (r->state != RQ_DONE) return QNSCH_EBUSY;
+    double *dst[5] = { c, mu, p, u, v };
+    for (int q = 0; q < 5; q++)
+        if (dst[q] && !r->out[q].empty()) memcpy(dst[q], r->out[q].data(), r->out[q].size() * sizeof(double));
+    if (mass_hist && !r->mass.empty()) memcpy(mass_hist, r->mass.data(), r->mass.size() * sizeof(double));
+    if (energy_hist && !r->energy.empty()) memcpy(energy_hist, r->energy.data(), r->energy.size() * sizeof(double));
+    if (step_ms && !r->step_ms.empty()) memcpy(step_ms, r->step_ms.data(), r->step_ms.size() * sizeof(double));
+    if (vcycles && !r->vc.empty()) memcpy(vcycles, r->vc.data(), r->vc.size() * sizeof(int32_t));
+    if (times) {
+        times[0] = ms_between(r->t_submit, r->t_admit);
+        times[1] = ms_between(r->t_submit, r->t_done);
+    }
+    return r->status;
+}
+
+int qnsch_server_stats(qnsch_server *S, double out[8])
+{
+    if (!S || !out) return QNSCH_EINVAL;
+    std::vector<double> l = S->lat_ms;
+    std::sort(l.begin(), l.end());
+    auto pct = [&](double q) {
+        if (l.empty()) return 0.0;
+        const double pos = q * (l.size() - 1);
+        const size_t a = (size_t)pos;
+        const size_t b = std::min(a + 1, l.size() - 1);
+        return l[a] + (pos - a) * (l[b] - l[a]);
+    };
+    const double wall = S->started ? ms_between(S->t_first, S->t_last) * 1e-3 : 0.0;
+    out[0] = pct(0.5);
+    out[1] = pct(0.99);
+    out[2] = S->cell_steps;
+    out[3] = wall;
+    out[4] = wall > 0 ? S->cell_steps / wall : 0.0;
+    out[5] = (double)l.size();
+    out[6] = (double)S->launches;
+    out[7] = (double)S->ticks;
+    return QNSCH_OK;
+}
+
+const char *qnsch_server_last_error(const qnsch_server *S) { return S ? S->err.c_str() : "null server"; }
 
 } // extern "C"

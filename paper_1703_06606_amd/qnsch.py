@@ -20,7 +20,9 @@ FP64, MIXED = 0, 1
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
            "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
            "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_mass", "qnsch_energy", "qnsch_stats",
-           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_copy_probe")
+           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_copy_probe",
+           "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
+           "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats")
 
 
 class QnschError(RuntimeError):
@@ -84,6 +86,19 @@ def lib():
         L.qnsch_profile.argtypes = [vp, C.c_int]
         L.qnsch_profile_read.argtypes = [vp, P]
         L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
+        L.qnsch_footprint.argtypes = [C.POINTER(Grid)]
+        L.qnsch_footprint.restype = C.c_size_t
+        L.qnsch_server_create.argtypes = [C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
+        L.qnsch_server_destroy.argtypes = [vp]
+        L.qnsch_server_destroy.restype = None
+        L.qnsch_server_last_error.argtypes = [vp]
+        L.qnsch_server_last_error.restype = C.c_char_p
+        L.qnsch_server_submit.argtypes = [vp, C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), P, C.c_int32,
+                                          C.c_double, C.POINTER(C.c_uint64)]
+        L.qnsch_server_progress.argtypes = [vp, C.c_int32]
+        L.qnsch_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.qnsch_server_result.argtypes = [vp, C.c_uint64, P, P, P, P, P, P, P, P, C.POINTER(C.c_int32), P]
+        L.qnsch_server_stats.argtypes = [vp, P]
         _lib = L
     return _lib
 
@@ -212,3 +227,83 @@ class Solver:
         self.set_state(*[wn.get(k) for k in ("c", "mu", "p", "u", "v")])
         self.begin_step(dt)
         self.set_iterate(*[w.get(k) for k in ("c", "mu", "p", "u", "v")])
+
+
+def _structs(grid, params, opts):
+    g = Grid(int(grid["m1"]), int(grid["m2"]), grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
+    p = Params(*[float(params[n]) for n, _ in Params._fields_])
+    o = None
+    if opts is not None:
+        d = default_opts()
+        d.update(opts)
+        o = Opts(*[d[n] for n, _ in Opts._fields_])
+    return g, p, o
+
+
+def footprint(grid):
+    """device bytes of a context of this grid"""
+    g, _, _ = _structs(grid, dict((n, 1.0) for n, _ in Params._fields_), None)
+    return int(lib().qnsch_footprint(C.byref(g)))
+
+
+class Server:
+    """Continuous-batching server of many simulations (qnsch_server_*)."""
+
+    def __init__(self, hbm_budget, max_slots, stream=None):
+        h = C.c_void_p()
+        rc = lib().qnsch_server_create(int(hbm_budget), int(max_slots), C.c_void_p(stream) if stream else None,
+                                       C.byref(h))
+        if rc != OK:
+            raise QnschError(rc, "qnsch_server_create failed")
+        self.h = h
+        self.shapes = {}
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().qnsch_server_destroy(self.h)
+            self.h = None
+
+    def submit(self, grid, params, opts, c0, nsteps, dt):
+        g, p, o = _structs(grid, params, opts)
+        c0 = np.ascontiguousarray(c0, dtype=np.float64).reshape(int(grid["m2"]), int(grid["m1"]))
+        rid = C.c_uint64()
+        rc = lib().qnsch_server_submit(self.h, C.byref(g), C.byref(p), C.byref(o) if o is not None else None,
+                                       _ptr(c0), int(nsteps), float(dt), C.byref(rid))
+        if rc != OK:
+            raise QnschError(rc, "submit rejected")
+        self.shapes[rid.value] = (int(grid["m2"]), int(grid["m1"]), int(nsteps))
+        return rid.value
+
+    def progress(self, max_ticks=1):
+        rc = lib().qnsch_server_progress(self.h, int(max_ticks))
+        if rc < 0:
+            raise QnschError(rc, lib().qnsch_server_last_error(self.h).decode())
+        return rc
+
+    def poll(self, rid):
+        st, status = C.c_int32(), C.c_int32()
+        self_rc = lib().qnsch_server_poll(self.h, C.c_uint64(rid), C.byref(st), C.byref(status))
+        if self_rc != OK:
+            raise QnschError(self_rc, "unknown request")
+        return st.value, status.value
+
+    def result(self, rid):
+        m2, m1, ns = self.shapes[rid]
+        f = [np.zeros((m2, m1)) for _ in range(5)]
+        mass, en, ms = np.zeros((ns, 2)), np.zeros((ns, 5)), np.zeros(ns)
+        vc = (C.c_int32 * ns)()
+        times = np.zeros(2)
+        rc = lib().qnsch_server_result(self.h, C.c_uint64(rid), *[_ptr(a) for a in f], _ptr(mass), _ptr(en), _ptr(ms),
+                                       vc, _ptr(times))
+        out = dict(zip(("c", "mu", "p", "u", "v"), f))
+        out.update(status=rc, mass=mass, energy=en, step_ms=ms, vcycles=np.array(vc[:]), wait_ms=times[0],
+                   total_ms=times[1])
+        return out
+
+    def stats(self):
+        out = np.zeros(8)
+        self_rc = lib().qnsch_server_stats(self.h, _ptr(out))
+        if self_rc != OK:
+            raise QnschError(self_rc, "stats failed")
+        keys = ("p50_ms", "p99_ms", "cell_steps", "wall_s", "cell_steps_per_s", "steps", "launches", "ticks")
+        return dict(zip(keys, out))

@@ -1,0 +1,97 @@
+"""Continuous-batching server: each request's result is the same alone and in
+a mix of requests of different sizes, admission respects the HBM budget, and a
+failing request does not disturb the others."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1703_06606_amd import qnsch as Q
+from paper_1703_06606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("c", "mu", "p", "u", "v")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mix():
+    periodic = W.rising_drop(32, 32, eps=0.04)
+    periodic["grid"] = dict(periodic["grid"], bcx=1, bcy=1)
+    periodic["params"] = dict(periodic["params"], inv_Fr=0.0)
+    return [W.capillary(), W.rising_drop(64, 128, eps=0.02), W.rising_drop(16, 32, eps=0.08, radius=0.2),
+            periodic, W.rising_drop(32, 64, eps=0.04, rho_ratio=5.0, visc_ratio=3.0), W.capillary(64, 128, eps=0.02, levels=5)]
+
+
+def alone(cfg, nsteps, opts):
+    g = Q.Solver(cfg["grid"], cfg["params"], opts)
+    g.set_state(cfg["state"]["c"])
+    ms, en = [], []
+    for _ in range(nsteps):
+        assert g.step(cfg["dt"]) == Q.OK
+        ms.append(g.mass())
+        en.append(g.energy())
+    return g.get_state(), np.array(ms), np.array(en)
+
+
+def test_served_results_equal_alone():
+    say("serving: alone vs mix")
+    opts = W.default_opts(1e-10)
+    cases = mix()
+    nsteps = 3
+    ref = [alone(c, nsteps, opts) for c in cases]
+    srv = Q.Server(hbm_budget=8 << 30, max_slots=16)
+    ids = [srv.submit(c["grid"], c["params"], opts, c["state"]["c"], nsteps, c["dt"]) for c in cases]
+    left = len(ids)
+    for _ in range(100000):
+        left = srv.progress(64)
+        if left == 0:
+            break
+    assert left == 0
+    for rid, (st, ms, en), c in zip(ids, ref, cases):
+        r = srv.result(rid)
+        assert r["status"] == Q.OK, c["name"]
+        for k in FIELDS:
+            assert np.array_equal(r[k], st[k]), (c["name"], k, np.abs(r[k] - st[k]).max())
+        assert np.array_equal(r["mass"], ms), c["name"]
+        assert np.allclose(r["energy"], en, rtol=1e-15, atol=0), c["name"]
+        assert (r["vcycles"] > 0).all()
+    s = srv.stats()
+    say("serving stats", s)
+    assert s["steps"] == nsteps * len(cases)
+    assert s["launches"] < sum(ref_steps for ref_steps in [nsteps * 200]) * len(cases)
+
+
+def test_admission_by_budget_and_failure_isolation():
+    say("serving: budget and failure")
+    opts = W.default_opts(1e-10)
+    cases = [W.rising_drop(32, 64, eps=0.04) for _ in range(4)]
+    bad = W.rising_drop(32, 64, eps=0.04)
+    bad["params"] = dict(bad["params"], rho2=100.0)
+    bad["state"] = dict(c=bad["state"]["c"].copy())
+    bad["state"]["c"][5, 5] = -0.05  # past the density pole: diverges
+    ref = alone(cases[0], 2, opts)
+    # budget for two requests at a time
+    foot = Q.footprint(cases[0]["grid"])
+    assert foot > 0
+    srv = Q.Server(hbm_budget=int(2.5 * foot), max_slots=8)
+    ids = [srv.submit(c["grid"], c["params"], opts, c["state"]["c"], 2, c["dt"]) for c in cases]
+    bid = srv.submit(bad["grid"], bad["params"], opts, bad["state"]["c"], 2, bad["dt"])
+    for _ in range(100000):
+        if srv.progress(64) == 0:
+            break
+    for rid in ids:
+        r = srv.result(rid)
+        assert r["status"] == Q.OK
+        for k in FIELDS:
+            assert np.array_equal(r[k], ref[0][k])
+    waits = [srv.result(rid)["wait_ms"] for rid in ids]
+    assert max(waits) > min(waits)  # later requests waited for budget
+    rb = srv.result(bid)
+    assert rb["status"] == Q.EDIVERGED
+    with pytest.raises(Q.QnschError):
+        Q.Server(hbm_budget=1024, max_slots=2).submit(cases[0]["grid"], cases[0]["params"], opts,
+                                                      cases[0]["state"]["c"], 1, 1e-3)
