@@ -115,3 +115,27 @@ def random_state(grid, seed, amp=(0.05, 0.1, 0.1, 0.2, 0.2), base_c=0.5):
     if grid["bcy"] == WALL:
         st["v"][0, :] = 0.0
     return st
+
+
+def serving_requests(n=64, rate_hz=20.0, seed=6606, nsteps=50, dt=5e-4,
+                     sizes=((64, 128), (128, 256), (256, 512), (512, 1024))):
+    """Independent rising-droplet requests arriving as a seeded Poisson stream:
+    grid drawn uniformly from sizes on [0,1]x[0,2] (walls), drop radius
+    U[0.15, 0.3], density ratio U[2, 20], viscosity ratio U[1, 10], Re = 35,
+    We = 10, 1/Fr = 1, eps = 2.56 h (the interface resolution of the 256x512
+    droplet), nsteps steps of dt each.  Returns a list of dicts with the
+    arrival time (s) and a workload."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n):
+        t += rng.exponential(1.0 / rate_hz)
+        m1, m2 = sizes[rng.integers(len(sizes))]
+        radius = rng.uniform(0.15, 0.3)
+        rr = rng.uniform(2.0, 20.0)
+        vr = rng.uniform(1.0, 10.0)
+        eps = 2.56 / m1
+        w = rising_drop(m1, m2, eps=eps, radius=radius, rho_ratio=rr, visc_ratio=vr, dt=dt)
+        w["name"] = "request_%d_%dx%d" % (k, m1, m2)
+        out.append(dict(arrival=t, work=w, nsteps=nsteps))
+    return out
