@@ -1,16 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark of the multigrid time step on one MI355X.
 
-Workload: the 256 x 512 rising droplet on [0,1] x [0,2] (walls on all sides,
-density ratio 10, viscosity ratio 10, Re = 35, We = 10, Fr = 1, eps = 0.01,
-dt = 5e-4, 7 multigrid levels), FP64, each step solved to a residual of 1e-8.
-A step is one call of qnsch_step (all V-cycles of the time step).  The timed
-region starts from the initial droplet after W untimed warm-up steps, with all
-inputs resident in HBM, and covers exactly K steps.
+Main line (``value``): the 256 x 512 rising droplet on [0,1] x [0,2] (walls on
+all sides, density ratio 10, viscosity ratio 10, Re = 35, We = 10, Fr = 1,
+eps = 0.01, dt = 5e-4, 7 multigrid levels), FP64, each step solved to a
+residual of 1e-8.  A step is one call of qnsch_step (all V-cycles of the time
+step).  The timed region starts from the initial droplet after W untimed
+warm-up steps, with all inputs resident in HBM, and covers exactly K steps.
 
-Prints one JSON line: cell-steps/s, p50/p99 step latency, the roofline of the
-finest-level half-sweep kernel (HIP-event timing of its launches inside the
-timed region) and the FP64 CPU oracle timed on a bounded sample.
+Beside it, on the same JSON line:
+  mixed   -- the 512 x 2048 Rayleigh-Taylor run in FP64 and in mixed
+             precision (FP32 correction cycles inside FP64 defect correction),
+             the same number of steps each, with the mixed/FP64 speedup and
+             the difference of the final states;
+  served  -- 64 droplet requests of four sizes arriving as a seeded Poisson
+             stream at 20 per second, 50 steps each, through the continuous-
+             batching server in mixed precision; throughput and p50/p99 step
+             latency against the same requests run one after another;
+  roofline of the finest-level half-sweep kernel (HIP events around its
+             launches in the timed region), and a per-operation breakdown of
+             one step;
+  cpu_baseline -- the FP64 CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -29,14 +39,21 @@ from paper_1703_06606_amd import workloads as W  # noqa: E402
 
 METRIC = "cell-steps/s to MG residual 1e-8, mixed vs FP64; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
-# algorithmic bytes of one half-sweep launch per cell of the level: it reads
-# the five unknowns and the three time-n fields of every cell (the stencils of
-# the cells of one colour cover all cells), writes c, mubar, pbar of the half
-# of the cells it relaxes and both face velocities of every face (ping-pong)
+# Algorithmic bytes of one finest-level half-sweep launch per cell.  FP64: it
+# reads the five unknowns and the three time-n fields of every cell (the
+# stencils of the cells of one colour cover all cells), writes c, mubar, pbar
+# of the half of the cells it relaxes and both face velocities of every face
+# (each face belongs to one box of the colour).
 HALFSWEEP_BYTES_PER_CELL = 8 * 8 + 3 * 8 / 2 + 2 * 8
+# FP32 correction half-sweep: reads c^, the five corrections and the three
+# time-n fields of every cell, mubar^ and the three cell right-hand sides of
+# the relaxed half, u^, v^ and the two face right-hand sides of every face;
+# writes dc, dmu, dp of the relaxed half and both face corrections.
+MX_HALFSWEEP_BYTES_PER_CELL = 9 * 4 + (1 + 3) * 4 / 2 + 4 * 4 + 3 * 4 / 2 + 2 * 4
 KERNEL = "k_halfsweep_fine"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_traffic.txt")
-SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f) for f in ("qnsch_dev.hpp", "qnsch_kern.hpp", "qnsch_lib.hip")]
+SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f)
+           for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp", "qnsch_lib.hip")]
 
 
 def source_hash():
@@ -88,12 +105,141 @@ def cpu_baseline(cfg, opts, vcycles_per_step):
                       % (t_res, t_vc, cfg["grid"]["m1"], cfg["grid"]["m2"], vcycles_per_step)}
 
 
+def note(*a):
+    """progress on stderr (the JSON line is the only stdout output)"""
+    print(*a, file=sys.stderr, flush=True)
+
+
+def timed_steps(g, cfg, steps):
+    """K steps from the configuration's initial state; wall seconds, per-step
+    latencies, V-cycle counts"""
+    g.set_state(cfg["state"]["c"])
+    g.synchronize()
+    lat, nv = [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ts = time.perf_counter()
+        g.step(cfg["dt"])
+        lat.append(time.perf_counter() - ts)
+        nv.append(g.stats()["vcycles"])
+    g.synchronize()
+    return time.perf_counter() - t0, lat, nv
+
+
+def breakdown(g, cfg, steps=2):
+    """share of the step time per operation class over a few untimed steps
+    (every launch bracketed by HIP events)"""
+    g.set_state(cfg["state"]["c"])
+    g.profile(2)
+    for _ in range(steps):
+        g.step(cfg["dt"])
+    b = g.profile_breakdown()
+    g.profile(0)
+    tot = sum(ms for _, ms in b.values())
+    return {k: {"launches": n, "ms_per_step": ms / steps, "share": ms / tot}
+            for k, (n, ms) in sorted(b.items(), key=lambda kv: -kv[1][1])}
+
+
+def run_mixed(steps, tol):
+    """Rayleigh-Taylor 512 x 2048: FP64 against mixed precision, same steps"""
+    cfg = W.rayleigh_taylor()
+    cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
+    out = {"workload": cfg["name"], "steps": steps, "tol": tol}
+    res = {}
+    for name, prec in (("fp64", Q.FP64), ("mixed", Q.MIXED)):
+        note("mixed-precision comparison:", cfg["name"], name, steps, "steps")
+        g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(tol), precision=prec))
+        g.set_state(cfg["state"]["c"])
+        g.step(cfg["dt"])  # warm-up
+        g.set_state(cfg["state"]["c"])
+        m0, e0 = g.mass(), g.energy()
+        g.profile(1)
+        el, lat, nv = timed_steps(g, cfg, steps)
+        launches, kms = g.profile_read()
+        g.profile(0)
+        m1, e1 = g.mass(), g.energy()
+        res[name] = (g.get_state(), e1)
+        bpc = MX_HALFSWEEP_BYTES_PER_CELL if prec == Q.MIXED else HALFSWEEP_BYTES_PER_CELL
+        avg_ms = kms / max(launches, 1)
+        out[name] = {"cell_steps_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                     "vcycles_per_step": float(np.mean(nv)),
+                     "mass_drift": float(np.abs(m1 - m0).max() / np.abs(m0).max()),
+                     "energy_first_last": [float(e0[0]), float(e1[0])],
+                     "finest_halfsweep_us": 1e3 * avg_ms,
+                     "finest_halfsweep_GBps": bpc * cells / (avg_ms * 1e-3) / 1e9}
+        del g
+    out["speedup_mixed_vs_fp64"] = out["mixed"]["cell_steps_per_s"] / out["fp64"]["cell_steps_per_s"]
+    a, b = res["mixed"][0], res["fp64"][0]
+    out["mixed_vs_fp64_rel_err"] = {k: float(np.abs(a[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-300))
+                                    for k in ("c", "mu", "p", "u", "v")}
+    out["mixed_vs_fp64_rel_err"]["energy"] = float(abs(res["mixed"][1][0] - res["fp64"][1][0]) / abs(res["fp64"][1][0]))
+    return out
+
+
+def run_served(n, nsteps, tol, seq_steps):
+    """the request stream through the server (mixed precision), and the same
+    requests one after another alone (FP64 and mixed) on a sample of steps"""
+    reqs = W.serving_requests(n=n, nsteps=nsteps)
+    mixed = dict(W.default_opts(tol), precision=Q.MIXED)
+    fp64 = W.default_opts(tol)
+    # sequential baselines: every request alone, seq_steps steps each
+    seq = {}
+    for name, opts in (("fp64", fp64), ("mixed", mixed)):
+        note("serving: sequential baseline", name)
+        cs, t = 0.0, 0.0
+        for r in reqs:
+            w = r["work"]
+            g = Q.Solver(w["grid"], w["params"], opts)
+            g.set_state(w["state"]["c"])
+            g.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(seq_steps):
+                g.step(w["dt"])
+            g.synchronize()
+            t += time.perf_counter() - t0
+            cs += w["grid"]["m1"] * w["grid"]["m2"] * seq_steps
+            del g
+        seq[name] = cs / t
+    note("serving: %d requests through the server" % n)
+    srv = Q.Server(hbm_budget=64 << 30, max_slots=n)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        now = time.perf_counter() - t0
+        while k < len(reqs) and reqs[k]["arrival"] <= now:
+            w = reqs[k]["work"]
+            srv.submit(w["grid"], w["params"], mixed, w["state"]["c"], reqs[k]["nsteps"], w["dt"])
+            k += 1
+        left = srv.progress(32)
+        if left == 0 and k == len(reqs):
+            break
+        if left == 0:
+            time.sleep(min(1e-3, max(0.0, reqs[k]["arrival"] - (time.perf_counter() - t0))))
+    s = srv.stats()
+    return {"workload": "%d rising-droplet requests, sizes 64x128..512x1024, Poisson 20/s, %d steps each, mixed "
+                        "precision, tol %g" % (n, nsteps, tol),
+            "cell_steps_per_s": s["cell_steps_per_s"], "p50_step_ms": s["p50_ms"], "p99_step_ms": s["p99_ms"],
+            "wall_s": s["wall_s"], "steps": int(s["steps"]), "launches": int(s["launches"]),
+            "contexts_created": int(s["contexts_created"]),
+            "host_ms": {"admit": s["host_admit_ms"], "finish": s["host_finish_ms"], "wait": s["host_wait_ms"]},
+            "sequential_fp64_cell_steps_per_s": seq["fp64"], "sequential_mixed_cell_steps_per_s": seq["mixed"],
+            "sequential_sample": "each request alone, %d steps from its initial state" % seq_steps,
+            "speedup_vs_sequential_fp64": s["cell_steps_per_s"] / seq["fp64"],
+            "speedup_vs_sequential_mixed": s["cell_steps_per_s"] / seq["mixed"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--mixed-steps", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-steps", type=int, default=50)
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -105,27 +251,16 @@ def main():
     opts = W.default_opts(args.tol)
     g = Q.Solver(cfg["grid"], cfg["params"], dict(opts, precision=Q.FP64))
     cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
-    c0 = cfg["state"]["c"]
     copy_gbs, _ = Q.copy_probe(64 << 20, 10)  # 512 MiB copy: calibration and sanity figure
 
-    g.set_state(c0)
+    note("main:", cfg["name"], args.steps, "steps")
+    g.set_state(cfg["state"]["c"])
     for _ in range(args.warmup):
         g.step(cfg["dt"])
-    g.set_state(c0)
-    g.synchronize()
-    g.profile(True)
-    lat, nv = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        g.step(cfg["dt"])
-        lat.append(time.perf_counter() - ts)
-        nv.append(g.stats()["vcycles"])
-    g.synchronize()
-    elapsed = time.perf_counter() - t0
+    g.profile(1)
+    elapsed, lat, nv = timed_steps(g, cfg, args.steps)
     launches, kms = g.profile_read()
-    g.profile(False)
-
+    g.profile(0)
     value = cells * args.steps / elapsed
     avg_ms = kms / max(launches, 1)
     alg_bytes = HALFSWEEP_BYTES_PER_CELL * cells
@@ -144,8 +279,15 @@ def main():
                      "launches": launches, "avg_launch_us": 1e3 * avg_ms,
                      "alg_bytes_per_launch": alg_bytes},
         "copy_probe_GBps": copy_gbs,
+        "step_breakdown": breakdown(g, cfg),
     }
+    del g
+    if not args.no_mixed:
+        out["mixed"] = run_mixed(args.mixed_steps, args.tol)
+    if not args.no_serve:
+        out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=5)
     if not args.no_cpu_baseline:
+        note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, opts, float(np.mean(nv)))
     print(json.dumps(out), flush=True)
 

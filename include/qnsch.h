@@ -14,6 +14,14 @@
  * solved by the nonlinear FAS multigrid of sec. 7.1 (pointwise Newton update of
  * (c, mubar), Vanka box update of (u, v, pbar), red-black order, V-cycles).
  *
+ * Precision.  QNSCH_FP64: every phase in FP64.  QNSCH_MIXED: defect
+ * correction; the residual r = -N(w), the update w += delta, the stop test and
+ * the mass and energy sums are FP64, and delta comes from one FP32 multigrid
+ * V-cycle per outer iteration on the linearisation J(w) delta = r (same
+ * smoother, colour order and transfers, applied to the correction).  Both
+ * stop on the same FP64 residual norms, so both return a solution of the same
+ * discrete system to the same tolerance.
+ *
  * Grid and host array layout (all host arrays are double, m1*m2 entries,
  * row-major with x fastest, index j*m1 + i):
  *   cell (i,j): 0 <= i < m1, 0 <= j < m2, centre ((i+1/2)h, (j+1/2)h),
@@ -77,7 +85,7 @@ typedef struct {
 } qnsch_params;
 
 typedef struct {
-    int32_t precision;   /* QNSCH_FP64 or QNSCH_MIXED */
+    int32_t precision;   /* QNSCH_FP64 or QNSCH_MIXED (see above) */
     double tol;          /* stop when every per-equation norm sqrt(h^2 sum r^2) <= tol */
     int32_t max_vcycles; /* error QNSCH_ENOCONV beyond this */
     int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black) */
@@ -86,7 +94,7 @@ typedef struct {
 } qnsch_opts;
 
 typedef struct {
-    int32_t vcycles;        /* V-cycles of the last step */
+    int32_t vcycles;        /* V-cycles (mixed: outer iterations) of the last step */
     double res[5];          /* final per-equation residual norms (c, mu, p, u, v) */
     double res0[5];         /* residual norms before the first V-cycle */
     double step_ms;         /* wall time of the last step */
@@ -99,7 +107,8 @@ void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
  * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
- * device memory (roughly 120 bytes per finest cell in FP64).  Returns
+ * device memory in one allocation (qnsch_footprint: roughly 120 bytes per
+ * finest cell in FP64, 180 in mixed precision).  Returns
  * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
 int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
                  void *hip_stream, qnsch_ctx **out);
@@ -134,6 +143,13 @@ int qnsch_vcycle(qnsch_ctx *ctx);
 int qnsch_residual(qnsch_ctx *ctx, double *r_out, double norms[5]);
 int qnsch_halfsweep(qnsch_ctx *ctx, int colour);
 int qnsch_end_step(qnsch_ctx *ctx);
+/* Mixed-precision contexts, during a step: the FP32 linearisation used by the
+ * correction cycle, applied to a host correction dw (5 fields of m1*m2 in the
+ * order and layout of qnsch_residual): out = J(w) dw at the current iterate w
+ * (its FP32 rounding), 5 fields, FP32 arithmetic returned as double.  Faces on
+ * walls are not unknowns: their entries of dw are ignored and of out are 0.
+ * QNSCH_EINVAL on an FP64 context; halfsweep is QNSCH_EINVAL on a mixed one. */
+int qnsch_lin_apply(qnsch_ctx *ctx, const double *dw, double *out);
 
 /* Mass of the two components of the current state (Theorem of sec. 6.1):
  * out = {h^2 sum rho(c) c, h^2 sum rho(c) (1-c)}.  FP64, deterministic. */
@@ -145,12 +161,19 @@ int qnsch_stats(const qnsch_ctx *ctx, qnsch_step_stats *out);
 /* Block until all work of the context's stream has finished. */
 int qnsch_synchronize(qnsch_ctx *ctx);
 
-/* Measurement support.  qnsch_profile(ctx, 1) starts timing every launch of
- * the finest-level half-sweep kernel with HIP events on the context's stream
- * (and resets the counters; 0 stops); qnsch_profile_read returns
- * {launches, total milliseconds}. */
-int qnsch_profile(qnsch_ctx *ctx, int enable);
+/* Measurement support.  qnsch_profile(ctx, mode) resets the counters and
+ * times launches with HIP events on the context's stream: mode 1 every launch
+ * of the finest-level half-sweep kernel (FP64, or FP32 in mixed precision),
+ * mode 2 every launch of the step, 0 none.  qnsch_profile_read returns
+ * {finest half-sweep launches, their total milliseconds}.
+ * qnsch_profile_breakdown returns the number of timed operation classes and
+ * writes up to cap of them: kinds[k] = 2*operation + (1 if on a coarser level
+ * than the finest), out[2k] = launches, out[2k+1] = total milliseconds (the
+ * operation numbering is the library's internal one; a residual or step-end
+ * class includes its reduction launches). */
+int qnsch_profile(qnsch_ctx *ctx, int mode);
 int qnsch_profile_read(qnsch_ctx *ctx, double out[2]);
+int qnsch_profile_breakdown(qnsch_ctx *ctx, int32_t *kinds, double *out, int32_t cap);
 /* Copy-kernel probe on the current device: copies n doubles reps times
  * between two buffers it allocates and frees; out = {GB/s counting read and
  * write, milliseconds per copy}. */
@@ -175,7 +198,7 @@ typedef struct qnsch_server qnsch_server;
 
 /* Device bytes a context of this grid allocates (0 if the grid is invalid);
  * the server admits requests by this footprint. */
-size_t qnsch_footprint(const qnsch_grid *grid);
+size_t qnsch_footprint(const qnsch_grid *grid, const qnsch_opts *opts);
 
 /* hbm_budget: device bytes the admitted requests may hold together;
  * max_slots: most requests in flight; hip_stream: stream to run on (NULL =
@@ -199,8 +222,10 @@ int qnsch_server_poll(qnsch_server *srv, uint64_t id, int32_t *state, int32_t *s
 int qnsch_server_result(qnsch_server *srv, uint64_t id, double *c, double *mu, double *p, double *u, double *v,
                         double *mass_hist, double *energy_hist, double *step_ms, int32_t *vcycles, double *times);
 /* out = {p50 step ms, p99 step ms, cell-steps done, seconds from first
- * admission to last completion, cell-steps/s, steps done, launches, ticks}. */
-int qnsch_server_stats(qnsch_server *srv, double out[8]);
+ * admission to last completion, cell-steps/s, steps done, launches, ticks,
+ * host ms in admission, host ms in result download, host ms blocked waiting
+ * for the device, contexts allocated (the rest were recycled)}. */
+int qnsch_server_stats(qnsch_server *srv, double out[12]);
 
 #ifdef __cplusplus
 }

@@ -48,7 +48,8 @@ struct Rhs {
 __device__ __forceinline__ int wrapi(int k, int n) { return k < 0 ? k + n : (k >= n ? k - n : k); }
 
 // cell field: Neumann mirror or periodic image (x first, then y)
-__device__ __forceinline__ double ldc(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
+template <typename R>
+__device__ __forceinline__ R ldc(const R *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
     if (i < 0 || i >= m1) i = bcx ? wrapi(i, m1) : (i < 0 ? 0 : m1 - 1);
     if (j < 0 || j >= m2) j = bcy ? wrapi(j, m2) : (j < 0 ? 0 : m2 - 1);
@@ -56,20 +57,22 @@ __device__ __forceinline__ double ldc(const double *f, int m1, int m2, int pitch
 }
 // east-west face field at x = i h, row j: zero on (and beyond) x-walls,
 // reflected (ghost = -interior) across y-walls
-__device__ __forceinline__ double ldu(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
+template <typename R>
+__device__ __forceinline__ R ldu(const R *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
     if (bcx) i = wrapi(i, m1);
-    else if (i <= 0 || i >= m1) return 0.0;
+    else if (i <= 0 || i >= m1) return R(0);
     if (j < 0 || j >= m2) {
         if (bcy) j = wrapi(j, m2);
         else return -f[(size_t)(j < 0 ? 0 : m2 - 1) * pitch + i];
     }
     return f[(size_t)j * pitch + i];
 }
-__device__ __forceinline__ double ldv(const double *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
+template <typename R>
+__device__ __forceinline__ R ldv(const R *f, int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
 {
     if (bcy) j = wrapi(j, m2);
-    else if (j <= 0 || j >= m2) return 0.0;
+    else if (j <= 0 || j >= m2) return R(0);
     if (i < 0 || i >= m1) {
         if (bcx) i = wrapi(i, m1);
         else return -f[(size_t)j * pitch + (i < 0 ? 0 : m1 - 1)];
@@ -112,13 +115,14 @@ enum { T_C = 0, T_MU, T_P, T_U, T_V, T_CN, T_UN, T_VN, T_RN, T_MV, T_MOB, T_RS, 
 
 // A tile covers level cells i0-1 .. i0+TX+1, j0-1 .. j0+TY+1 (W = TX+3
 // columns); q(f, i, j) takes level coordinates.
-struct Tile {
-    double *s; // T_NF arrays of W*H doubles in LDS
+template <typename R> struct TileT {
+    R *s; // field arrays of W*H elements in LDS
     int i0, j0, W, H;
     __device__ __forceinline__ int idx(int i, int j) const { return (j - j0 + 1) * W + (i - i0 + 1); }
-    __device__ __forceinline__ double q(int f, int i, int j) const { return s[f * W * H + idx(i, j)]; }
-    __device__ __forceinline__ void set(int f, int i, int j, double v) const { s[f * W * H + idx(i, j)] = v; }
+    __device__ __forceinline__ R q(int f, int i, int j) const { return s[f * W * H + idx(i, j)]; }
+    __device__ __forceinline__ void set(int f, int i, int j, R v) const { s[f * W * H + idx(i, j)] = v; }
 };
+typedef TileT<double> Tile;
 
 // cooperative load of a tile (all threads of the block take part; the caller
 // synchronises afterwards).  The level may be in global memory or in LDS.
@@ -167,7 +171,8 @@ struct Ax {
     int hlf;
 };
 
-__device__ __forceinline__ Ax make_ax(const View &L, const Tile &T, int i, int j, int hlf)
+template <typename V, typename TT>
+__device__ __forceinline__ Ax make_ax(const V &L, const TT &T, int i, int j, int hlf)
 {
     Ax a;
     a.hlf = hlf;
@@ -188,9 +193,10 @@ __device__ __forceinline__ Ax make_ax(const View &L, const Tile &T, int i, int j
 }
 
 __device__ __forceinline__ double other(double x) { return __shfl_xor(x, 1, 64); }
+__device__ __forceinline__ float other(float x) { return __shfl_xor(x, 1, 64); }
 
 // element-indexed tile read
-__device__ __forceinline__ double tq(const Tile &T, int f, int e) { return T.s[f * T.W * T.H + e]; }
+template <typename R> __device__ __forceinline__ R tq(const TileT<R> &T, int f, int e) { return T.s[f * T.W * T.H + e]; }
 
 // contributions of one axis to the cell equations at cell element e
 struct CellAx {
@@ -411,23 +417,25 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     // Gaussian elimination in the order u, u, v, v, p: the velocity block has a
     // positive definite symmetric part (mass + viscous; advection is skew) and
     // the last pivot is the positive pressure Schur complement
+    double inv[5];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
-        const double inv = frcp(A[c][c]);
+        inv[c] = frcp(A[c][c]);
 #pragma unroll
         for (int r = c + 1; r < 5; r++) {
-            const double l = A[r][c] * inv;
+            const double l = A[r][c] * inv[c];
 #pragma unroll
             for (int t = c + 1; t < 5; t++) A[r][t] -= l * A[c][t];
             b[r] -= l * b[c];
         }
     }
+    inv[4] = frcp(A[4][4]);
 #pragma unroll
     for (int c = 4; c >= 0; c--) {
         double acc = b[c];
 #pragma unroll
         for (int t = c + 1; t < 5; t++) acc -= A[c][t] * b[t];
-        b[c] = acc * frcp(A[c][c]);
+        b[c] = acc * inv[c];
     }
     double *dst = hlf ? vnew : unew;
     const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];

@@ -9,6 +9,7 @@
 // not depend on what else shares the launch.
 #pragma once
 #include "qnsch_dev.hpp"
+#include "qnsch_lin.hpp"
 
 namespace qn {
 
@@ -36,6 +37,14 @@ struct Desc {
     double *red_host;                                   // reduced values (pinned host)
     double *mus, *ps;                                   // mubar, pbar of time n (finest level)
     double *rout;                                       // residual fields (finest level, optional)
+    // mixed precision: the FP32 correction hierarchy (NULL in FP64 mode; on
+    // coarse levels the FP64 arrays above are NULL instead)
+    PhysF Pf;
+    float *xc, *xmu, *xu, *xv;                          // linearisation point
+    float *dc, *dmu, *dp, *dub[2], *dvb[2];             // correction (u/v ping-pong)
+    float *rc, *rmu, *rp, *ru, *rv;                     // right-hand side
+    float *cnf, *unf, *vnf;                             // time-n data
+    float finv_h;
 };
 
 struct Items {
@@ -75,13 +84,14 @@ __device__ __forceinline__ Rhs rhs_of(const Desc &d)
 // Items start at multiples of NXCD and their tiles are renumbered so that an
 // XCD gets a contiguous band of tiles: neighbouring tiles, which read each
 // other's halos, share one L2.
-__device__ __forceinline__ Tile item_tile(double *sm, const Items &it, int k, const Desc &d)
+template <typename R>
+__device__ __forceinline__ TileT<R> item_tile(R *sm, const Items &it, int k, const Desc &d)
 {
     const int tx = it.tx[k];
     const int ty = (d.m2 + TY - 1) / TY;
     const int n = tx * ty, lin = (int)blockIdx.x - it.start[k];
     const int t = (n % NXCD == 0) ? (lin % NXCD) * (n / NXCD) + lin / NXCD : lin;
-    Tile T;
+    TileT<R> T;
     T.s = sm;
     T.i0 = (t % tx) * TX;
     T.j0 = (t / tx) * TY;
@@ -244,7 +254,7 @@ __global__ __launch_bounds__(TBLK) void k_restrict(Items it)
 }
 
 // the two cells of a tile handled by lane pair pr: (2k, lj) and (2k+1, lj)
-__device__ __forceinline__ void pair_cells(const Tile &T, int &i, int &j)
+template <typename TT> __device__ __forceinline__ void pair_cells(const TT &T, int &i, int &j)
 {
     const int pr = threadIdx.x >> 1;
     const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
@@ -371,6 +381,22 @@ __global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
         const size_t q = (size_t)j * L.m1 + i;
         v[3 + hlf] += rf * rf;
         if (d.rout) d.rout[(3 + hlf) * n + q] = rf;
+        if (d.rc) {
+            // mixed precision: the right-hand side and linearisation point of
+            // the next correction cycle, whose correction starts at zero
+            const size_t w = (size_t)j * L.pitch + i;
+            const int par = it.par[k];
+            if (hlf == 0) {
+                d.rc[w] = (float)rc; d.rmu[w] = (float)rm; d.rp[w] = (float)rp; d.ru[w] = (float)rf;
+                d.xc[w] = (float)T.q(T_C, i, j); d.xmu[w] = (float)T.q(T_MU, i, j);
+                d.xu[w] = (float)T.q(T_U, i, j);
+                d.dc[w] = 0.0f; d.dmu[w] = 0.0f; d.dp[w] = 0.0f; d.dub[par][w] = 0.0f;
+            } else {
+                d.rv[w] = (float)rf;
+                d.xv[w] = (float)T.q(T_V, i, j);
+                d.dvb[par][w] = 0.0f;
+            }
+        }
         if (hlf == 0) {
             v[0] += rc * rc; v[1] += rm * rm; v[2] += rp * rp;
             const double c = T.q(T_C, i, j), pp = T.q(T_P, i, j);
@@ -473,6 +499,11 @@ __global__ __launch_bounds__(BLK) void k_begin(Items it)
     d.vn[q] = d.vb[par][q];
     d.mus[q] = d.mu[q];
     d.ps[q] = d.p[q];
+    if (d.cnf) {
+        d.cnf[q] = (float)d.c[q];
+        d.unf[q] = (float)d.ub[par][q];
+        d.vnf[q] = (float)d.vb[par][q];
+    }
 }
 
 // time-n data of the coarser level of the item's level

@@ -21,7 +21,7 @@
 #include <vector>
 
 #include "qnsch.h"
-#include "qnsch_kern.hpp"
+#include "qnsch_mxk.hpp"
 
 using namespace qn;
 
@@ -29,7 +29,9 @@ using namespace qn;
 // operations of a time step
 
 enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, OP_COARSE, OP_PROLONG, OP_STEPEND,
-              OP_RESTORE };
+              OP_RESTORE,
+              // mixed precision: FP32 correction cycle, FP64 update
+              OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE, NOPS };
 struct Op {
     int kind, level, colour;
 };
@@ -56,11 +58,34 @@ static void vcycle_program(int L, int nu1, int nu2, std::vector<Op> &out)
     }
     out.push_back({ OP_NORM, 0, 0 });
 }
+// one outer iteration of the mixed-precision step: an FP32 correction
+// V-cycle on J(w^) delta = r, w += delta in FP64, then the FP64 residual
+// (which also prepares the next cycle) and the pbar mean removal
+static void mixed_program(int L, int nu1, int nu2, std::vector<Op> &out)
+{
+    for (int l = 0; l + 1 < L; l++) {
+        for (int s = 0; s < nu1; s++) {
+            out.push_back({ OP_MXHS, l, 0 });
+            out.push_back({ OP_MXHS, l, 1 });
+        }
+        out.push_back({ OP_MXRESTRICT, l, 0 });
+    }
+    out.push_back({ OP_MXCOARSE, L - 1, 0 });
+    for (int l = L - 2; l >= 0; l--) {
+        out.push_back({ OP_MXPROLONG, l, 0 });
+        for (int s = 0; s < nu2; s++) {
+            out.push_back({ OP_MXHS, l, 0 });
+            out.push_back({ OP_MXHS, l, 1 });
+        }
+    }
+    out.push_back({ OP_MXUPDATE, 0, 0 });
+    out.push_back({ OP_NORM, 0, 0 });
+}
 // time-n data of every level, then the residual of the initial iterate
-static void begin_program(int L, std::vector<Op> &out)
+static void begin_program(int L, bool mixed, std::vector<Op> &out)
 {
     out.push_back({ OP_BEGIN, 0, 0 });
-    for (int l = 0; l + 1 < L; l++) out.push_back({ OP_RN, l, 0 });
+    for (int l = 0; l + 1 < L; l++) out.push_back({ mixed ? OP_MXRN : OP_RN, l, 0 });
     out.push_back({ OP_NORM0, 0, 0 });
 }
 
@@ -87,19 +112,34 @@ struct qnsch_ctx {
     hipStream_t s = nullptr;
     std::vector<void *> allocs;
     double *red_host = nullptr; // pinned
+    double *stage = nullptr;    // pinned staging for state transfers (server contexts)
+    void *arena = nullptr;      // the device arrays (one allocation)
+    size_t arena_bytes = 0;
     hipEvent_t ev = nullptr;    // completion of the last host-read reduction
     size_t footprint = 0;
     std::string err;
-    // timing of the finest-level half-sweep launches (HIP events on the
-    // context's stream), enabled by qnsch_profile
+    // launch timing with HIP events on the context's stream (qnsch_profile):
+    // mode 1 the finest-level half-sweeps, mode 2 every launch, accumulated
+    // per (operation, finest or coarser level)
     int prof = 0, prof_used = 0;
     std::vector<hipEvent_t> pev;
+    std::vector<int> ptag;
     double prof_ms = 0.0;
     long prof_n = 0;
+    double tag_ms[2 * NOPS] = {};
+    long tag_n[2 * NOPS] = {};
     int in_step = 0;
     double dt = 0;
     qnsch_step_stats st;
 };
+
+static bool is_mixed(const qnsch_ctx *x) { return x->opt.precision == QNSCH_MIXED; }
+static void step_begin_program(const qnsch_ctx *x, std::vector<Op> &out) { begin_program(x->nlev, is_mixed(x), out); }
+static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
+{
+    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, out);
+    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, out);
+}
 
 #define HIPCHK(ctx, x)                                                                        \
     do {                                                                                      \
@@ -130,10 +170,10 @@ static int op_blocks(const qnsch_ctx *x, int kind, int l)
 {
     const DLev &D = x->L[l];
     switch (kind) {
-    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0:
+    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_MXHS: case OP_MXRESTRICT:
         return tiles_x(D.m1) * tiles_y(D.m2);
-    case OP_COARSE: return 1;
-    case OP_RN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
+    case OP_COARSE: case OP_MXCOARSE: return 1;
+    case OP_RN: case OP_MXRN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
     default: return (int)nblocks((size_t)D.m1 * D.m2);
     }
 }
@@ -153,6 +193,7 @@ static void add_item(ItemList &W, const qnsch_ctx *x, int kind, int l)
     it.start[k + 1] = W.blocks;
     if (l != 0) W.all_fine = false;
     if (kind == OP_COARSE) W.lds = std::max(W.lds, coarse_lds_doubles(x->L[l].m1, x->L[l].m2) * sizeof(double));
+    if (kind == OP_MXCOARSE) W.lds = std::max(W.lds, mx_coarse_lds_floats(x->L[l].m1, x->L[l].m2) * sizeof(float));
 }
 
 // finalize list: one workgroup per simulation, tx = number of partials
@@ -178,10 +219,45 @@ static int prof_collect(qnsch_ctx *x)
     for (int q = 0; q < x->prof_used; q++) {
         float ms = 0.f;
         HIPCHK(x, hipEventElapsedTime(&ms, x->pev[2 * q], x->pev[2 * q + 1]));
-        x->prof_ms += ms;
-        x->prof_n++;
+        const int tag = x->ptag[q];
+        if (tag == 2 * OP_HS || tag == 2 * OP_MXHS) {
+            x->prof_ms += ms;
+            x->prof_n++;
+        }
+        x->tag_ms[tag] += ms;
+        x->tag_n[tag]++;
     }
     x->prof_used = 0;
+    return QNSCH_OK;
+}
+
+// timing tag of a launch (-1: not timed): operation kind, and 1 for launches
+// on coarser levels than the finest
+static int prof_tag(int kind, const std::vector<std::pair<qnsch_ctx *, int>> &part)
+{
+    const qnsch_ctx *x = part[0].first;
+    if (part.size() != 1 || !x->prof) return -1;
+    const bool fine_hs = (kind == OP_HS || kind == OP_MXHS) && part[0].second == 0;
+    if (x->prof == 1 && !fine_hs) return -1;
+    return 2 * kind + (part[0].second == 0 ? 0 : 1);
+}
+
+static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end)
+{
+    if (!end) {
+        if ((size_t)(2 * x->prof_used + 2) > x->pev.size())
+            for (int q = 0; q < 64; q++) {
+                hipEvent_t ev;
+                HIPCHK(x, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+                x->pev.push_back(ev);
+            }
+        if ((size_t)x->prof_used + 1 > x->ptag.size()) x->ptag.resize(x->prof_used + 64);
+        x->ptag[x->prof_used] = tag;
+        HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
+    } else {
+        HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
+        x->prof_used++;
+    }
     return QNSCH_OK;
 }
 
@@ -198,24 +274,20 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         ItemList W;
         for (auto &pe : part) add_item(W, pe.first, kind, pe.second);
         const double omega = x0->opt.vanka_omega;
+        const int tag = prof_tag(kind, part);
+        int rc;
+        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, false))) return rc;
         switch (kind) {
-        case OP_HS: {
-            const bool tm = part.size() == 1 && part[0].second == 0 && part[0].first->prof;
-            qnsch_ctx *x = part[0].first;
-            if (tm) {
-                if ((size_t)(2 * x->prof_used + 2) > x->pev.size())
-                    for (int q = 0; q < 64; q++) {
-                        hipEvent_t ev;
-                        HIPCHK(x, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
-                        x->pev.push_back(ev);
-                    }
-                HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
-            }
-            if (W.all_fine) hipLaunchKernelGGL(k_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
-            else hipLaunchKernelGGL(k_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
-            if (tm) {
-                HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
-                x->prof_used++;
+        case OP_HS:
+        case OP_MXHS: {
+            if (kind == OP_MXHS) {
+                if (W.all_fine)
+                    hipLaunchKernelGGL(k_mx_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, (float)omega);
+                else hipLaunchKernelGGL(k_mx_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, (float)omega);
+            } else if (W.all_fine) {
+                hipLaunchKernelGGL(k_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
+            } else {
+                hipLaunchKernelGGL(k_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
             }
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
@@ -230,6 +302,18 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             break;
         }
         case OP_PROLONG: hipLaunchKernelGGL(k_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_MXRESTRICT: hipLaunchKernelGGL(k_mx_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
+        case OP_MXCOARSE: {
+            int nmax = 0;
+            for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
+            const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
+            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, x0->opt.nu_coarse,
+                               (float)omega);
+            break;
+        }
+        case OP_MXPROLONG: hipLaunchKernelGGL(k_mx_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_MXUPDATE: hipLaunchKernelGGL(k_mx_update, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_MXRN: hipLaunchKernelGGL(k_mx_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_BEGIN: hipLaunchKernelGGL(k_begin, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_RN: hipLaunchKernelGGL(k_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_RESTORE: hipLaunchKernelGGL(k_restore, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
@@ -253,6 +337,7 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         }
         default: break;
         }
+        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, true))) return rc;
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) {
             x0->err = std::string("kernel launch: ") + hipGetErrorString(err);
@@ -309,19 +394,60 @@ static int level_count(const qnsch_grid *g)
     return nl;
 }
 
+// The device arrays of a context live in one allocation, carved here: with
+// base == nullptr only the size is computed (the footprint), otherwise the
+// level descriptors get their pointers.  FP64 mode: the FP64 state, time-n
+// data and FAS arrays on every level.  Mixed mode: the FP64 state and time-n
+// data on the finest level only (one u/v buffer, both slots aliased) and the
+// FP32 correction hierarchy on every level.
+static size_t carve(const qnsch_grid *g, int nl, bool mixed, char *base, Desc *hd)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void * {
+        void *p = base ? (void *)(base + off) : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    auto dbl = [&](size_t n) { return (double *)take(n * sizeof(double)); };
+    auto flt = [&](size_t n) { return (float *)take(n * sizeof(float)); };
+    Desc scratch;
+    for (int l = 0; l < nl; l++) {
+        const size_t n = (size_t)(g->m1 >> l) * (g->m2 >> l);
+        Desc &d = hd ? hd[l] : scratch;
+        if (!mixed || l == 0) {
+            d.c = dbl(n); d.mu = dbl(n); d.p = dbl(n);
+            d.ub[0] = dbl(n); d.vb[0] = dbl(n);
+            if (mixed) { d.ub[1] = d.ub[0]; d.vb[1] = d.vb[0]; }
+            else { d.ub[1] = dbl(n); d.vb[1] = dbl(n); }
+            d.cn = dbl(n); d.un = dbl(n); d.vn = dbl(n);
+        }
+        if (!mixed && l > 0) {
+            d.fc = dbl(n); d.fmu = dbl(n); d.fp = dbl(n); d.fu = dbl(n); d.fv = dbl(n);
+            d.c0 = dbl(n); d.mu0 = dbl(n); d.p0 = dbl(n); d.u0 = dbl(n); d.v0 = dbl(n);
+        }
+        if (mixed) {
+            d.xc = flt(n); d.xmu = flt(n); d.xu = flt(n); d.xv = flt(n);
+            d.dc = flt(n); d.dmu = flt(n); d.dp = flt(n);
+            d.dub[0] = flt(n); d.dub[1] = flt(n); d.dvb[0] = flt(n); d.dvb[1] = flt(n);
+            d.rc = flt(n); d.rmu = flt(n); d.rp = flt(n); d.ru = flt(n); d.rv = flt(n);
+            d.cnf = flt(n); d.unf = flt(n); d.vnf = flt(n);
+        }
+    }
+    const size_t n0 = (size_t)g->m1 * g->m2;
+    Desc &d0 = hd ? hd[0] : scratch;
+    d0.mus = dbl(n0);
+    d0.ps = dbl(n0);
+    d0.partials = dbl((size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks(n0)) * NRED);
+    d0.red = dbl(NRED);
+    return off;
+}
+
 // device bytes of a context (the allocations of qnsch_create)
-static size_t footprint_of(const qnsch_grid *g)
+static size_t footprint_of(const qnsch_grid *g, int precision)
 {
     const int nl = level_count(g);
     if (nl < 0) return 0;
-    size_t b = 0;
-    for (int l = 0; l < nl; l++) {
-        const size_t n = (size_t)(g->m1 >> l) * (g->m2 >> l);
-        b += n * (l > 0 ? 20 : 10);
-    }
-    const size_t n0 = (size_t)g->m1 * g->m2;
-    b += 2 * n0 + (size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks(n0)) * NRED + NRED;
-    return b * sizeof(double) + (size_t)nl * sizeof(Desc);
+    return carve(g, nl, precision == QNSCH_MIXED, nullptr, nullptr) + (size_t)nl * sizeof(Desc);
 }
 
 static void phys_of(const qnsch_params *p, Phys &P)
@@ -335,6 +461,17 @@ static void phys_of(const qnsch_params *p, Phys &P)
     P.K3 = p->eps * p->eta * p->M / p->We;
     P.inv_Fr = p->inv_Fr; P.rho_ref = p->rho_ref; P.mob_reg = p->mob_reg;
     P.inv_dt = 0.0;
+}
+
+static PhysF physf_of(const Phys &P)
+{
+    PhysF F;
+    F.rho1 = (float)P.rho1; F.rho12 = (float)P.rho12; F.drho = (float)P.drho;
+    F.visc1 = (float)P.visc1; F.visc12 = (float)P.visc12; F.dvisc = (float)P.dvisc;
+    F.alpha = (float)P.alpha; F.inv_Re = (float)P.inv_Re; F.inv_M = (float)P.inv_M; F.inv_Pe = (float)P.inv_Pe;
+    F.K1 = (float)P.K1; F.K2 = (float)P.K2; F.K3 = (float)P.K3; F.mob_reg = (float)P.mob_reg;
+    F.inv_dt = 0.0f;
+    return F;
 }
 
 static int upload_desc(qnsch_ctx *x)
@@ -370,6 +507,7 @@ void qnsch_destroy(qnsch_ctx *x)
     for (hipEvent_t e : x->pev) (void)hipEventDestroy(e);
     if (x->ev) (void)hipEventDestroy(x->ev);
     if (x->red_host) (void)hipHostFree(x->red_host);
+    if (x->stage) (void)hipHostFree(x->stage);
     if (x->hd) (void)hipHostFree(x->hd);
     delete x;
 }
@@ -385,19 +523,31 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
     if (!(p->rho1 > 0) || !(p->rho2 > 0) || !(p->visc1 > 0) || !(p->visc2 > 0) || !(p->Re > 0) || !(p->We > 0)
         || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
         return QNSCH_EINVAL;
-    if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0 || o->precision != QNSCH_FP64))
+    if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0
+              || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)))
         return QNSCH_EINVAL;
     if (level_count(g) < 0) return QNSCH_EINVAL;
     return QNSCH_OK;
 }
 
-int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream, qnsch_ctx **out)
+// physical parameters of every level descriptor (host copy)
+static void set_params(qnsch_ctx *x, const qnsch_params *p)
 {
-    if (!out) return QNSCH_EINVAL;
-    *out = nullptr;
-    int rc = validate(g, p, o);
-    if (rc) return rc;
-    qnsch_ctx *x = new qnsch_ctx();
+    x->prm = *p;
+    Phys P;
+    phys_of(p, P);
+    const PhysF Pf = physf_of(P);
+    for (int l = 0; l < x->nlev; l++) {
+        x->hd[l].P = P;
+        x->hd[l].Pf = Pf;
+    }
+}
+
+// Allocate and lay out a context (validated arguments); the device arrays
+// are cleared on the stream; the descriptors are not uploaded yet.
+static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream)
+{
+    int rc = QNSCH_OK;
     x->g = *g;
     x->nlev = level_count(g);
     x->g.levels = x->nlev;
@@ -408,53 +558,50 @@ int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o
     memset(&x->st, 0, sizeof(x->st));
     const double hx = g->Lx / g->m1;
     if (hipHostMalloc((void **)&x->hd, x->nlev * sizeof(Desc), hipHostMallocDefault) != hipSuccess
-        || hipHostMalloc((void **)&x->red_host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-        qnsch_destroy(x);
+        || hipHostMalloc((void **)&x->red_host, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess)
         return QNSCH_ENOMEM;
-    }
     memset((void *)x->hd, 0, x->nlev * sizeof(Desc));
     memset(x->red_host, 0, 16 * sizeof(double));
     void *ddp = nullptr;
-    if (hipMalloc(&ddp, x->nlev * sizeof(Desc)) != hipSuccess) { qnsch_destroy(x); return QNSCH_ENOMEM; }
+    if (hipMalloc(&ddp, x->nlev * sizeof(Desc)) != hipSuccess) return QNSCH_ENOMEM;
     x->allocs.push_back(ddp);
     x->dd = (Desc *)ddp;
-    Phys P;
-    phys_of(p, P);
-    for (int l = 0; l < x->nlev && !rc; l++) {
+    const bool mixed = is_mixed(x);
+    const size_t bytes = carve(g, x->nlev, mixed, nullptr, nullptr);
+    void *arena = nullptr;
+    if (hipMalloc(&arena, bytes) != hipSuccess) return QNSCH_ENOMEM;
+    x->allocs.push_back(arena);
+    x->arena = arena;
+    x->arena_bytes = bytes;
+    x->footprint = bytes + (size_t)x->nlev * sizeof(Desc);
+    if (hipMemsetAsync(arena, 0, bytes, x->s) != hipSuccess) rc = QNSCH_EDEVICE;
+    carve(g, x->nlev, mixed, (char *)arena, x->hd);
+    for (int l = 0; l < x->nlev; l++) {
         DLev &D = x->L[l];
         D.m1 = g->m1 >> l;
         D.m2 = g->m2 >> l;
         D.pitch = D.m1;
         D.h = hx * (double)(1 << l);
-        const size_t n = D.n();
         Desc &d = x->hd[l];
-        d.P = P;
-        d.c = dalloc(x, n, &rc); d.mu = dalloc(x, n, &rc); d.p = dalloc(x, n, &rc);
-        d.ub[0] = dalloc(x, n, &rc); d.ub[1] = dalloc(x, n, &rc);
-        d.vb[0] = dalloc(x, n, &rc); d.vb[1] = dalloc(x, n, &rc);
-        d.cn = dalloc(x, n, &rc); d.un = dalloc(x, n, &rc); d.vn = dalloc(x, n, &rc);
-        if (l > 0) {
-            d.fc = dalloc(x, n, &rc); d.fmu = dalloc(x, n, &rc); d.fp = dalloc(x, n, &rc);
-            d.fu = dalloc(x, n, &rc); d.fv = dalloc(x, n, &rc);
-            d.c0 = dalloc(x, n, &rc); d.mu0 = dalloc(x, n, &rc); d.p0 = dalloc(x, n, &rc);
-            d.u0 = dalloc(x, n, &rc); d.v0 = dalloc(x, n, &rc);
-        }
         d.m1 = D.m1; d.m2 = D.m2; d.pitch = D.pitch; d.bcx = g->bc_x; d.bcy = g->bc_y;
-        d.h = D.h; d.inv_h = 1.0 / D.h;
+        d.h = D.h; d.inv_h = 1.0 / D.h; d.finv_h = (float)d.inv_h;
         d.coarse = l + 1 < x->nlev ? x->dd + l + 1 : nullptr;
     }
-    if (!rc) {
-        Desc &d0 = x->hd[0];
-        const size_t n0 = x->L[0].n();
-        d0.mus = dalloc(x, n0, &rc);
-        d0.ps = dalloc(x, n0, &rc);
-        const size_t np = (size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks((size_t)g->m1 * g->m2));
-        d0.partials = dalloc(x, np * NRED, &rc);
-        d0.red = dalloc(x, NRED, &rc);
-        d0.red_host = x->red_host;
-        d0.rout = nullptr;
-    }
+    set_params(x, p);
+    x->hd[0].red_host = x->red_host;
+    x->hd[0].rout = nullptr;
     if (!rc && hipEventCreateWithFlags(&x->ev, hipEventDisableTiming) != hipSuccess) rc = QNSCH_EDEVICE;
+    return rc;
+}
+
+int qnsch_create(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream, qnsch_ctx **out)
+{
+    if (!out) return QNSCH_EINVAL;
+    *out = nullptr;
+    int rc = validate(g, p, o);
+    if (rc) return rc;
+    qnsch_ctx *x = new qnsch_ctx();
+    rc = ctx_init(x, g, p, o, stream);
     if (!rc) rc = upload_desc(x);
     if (!rc && hipStreamSynchronize(x->s) != hipSuccess) rc = QNSCH_EDEVICE;
     if (rc) {
@@ -537,7 +684,10 @@ int qnsch_get_state(qnsch_ctx *x, double *c, double *mu, double *p, double *u, d
 static int set_dt(qnsch_ctx *x, double dt)
 {
     x->dt = dt;
-    for (int l = 0; l < x->nlev; l++) x->hd[l].P.inv_dt = 1.0 / dt;
+    for (int l = 0; l < x->nlev; l++) {
+        x->hd[l].P.inv_dt = 1.0 / dt;
+        x->hd[l].Pf.inv_dt = (float)(1.0 / dt);
+    }
     return upload_desc(x);
 }
 
@@ -547,7 +697,7 @@ int qnsch_begin_step(qnsch_ctx *x, double dt)
     int rc;
     if ((rc = set_dt(x, dt))) return rc;
     std::vector<Op> prog;
-    begin_program(x->nlev, prog);
+    step_begin_program(x, prog);
     prog.pop_back(); // no residual here
     if ((rc = run_ops(x, prog))) return rc;
     x->in_step = 1;
@@ -560,7 +710,7 @@ int qnsch_vcycle(qnsch_ctx *x)
     if (!x) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "vcycle outside a step"; return QNSCH_EBUSY; }
     std::vector<Op> prog;
-    vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, prog);
+    cycle_program(x, prog);
     int rc;
     if ((rc = run_ops(x, prog))) return rc;
     return read_red(x);
@@ -589,9 +739,47 @@ int qnsch_halfsweep(qnsch_ctx *x, int colour)
 {
     if (!x) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "halfsweep outside a step"; return QNSCH_EBUSY; }
+    if (is_mixed(x)) { x->err = "halfsweep: the nonlinear FP64 smoother needs an FP64 context"; return QNSCH_EINVAL; }
     int rc;
     if ((rc = run_ops(x, { { OP_HS, 0, colour & 1 } }))) return rc;
     HIPCHK(x, hipStreamSynchronize(x->s));
+    return QNSCH_OK;
+}
+
+int qnsch_lin_apply(qnsch_ctx *x, const double *dw, double *out)
+{
+    if (!x || !dw || !out) return QNSCH_EINVAL;
+    if (!is_mixed(x)) { x->err = "lin_apply needs a mixed-precision context"; return QNSCH_EINVAL; }
+    if (!x->in_step) { x->err = "lin_apply outside a step"; return QNSCH_EBUSY; }
+    DLev &D = x->L[0];
+    Desc &d = x->hd[0];
+    const size_t n = (size_t)D.m1 * D.m2;
+    int rc = QNSCH_OK;
+    if (!d.rout) {
+        d.rout = dalloc(x, 5 * n, &rc);
+        if (rc) return rc;
+        if ((rc = upload_desc(x))) return rc;
+    }
+    // linearisation point = the current iterate; then a zero right-hand side
+    // and the given correction
+    if ((rc = run_ops(x, { { OP_NORM0, 0, 0 } }))) return rc;
+    float *rhs[5] = { d.rc, d.rmu, d.rp, d.ru, d.rv };
+    for (int q = 0; q < 5; q++) HIPCHK(x, hipMemsetAsync(rhs[q], 0, D.n() * sizeof(float), x->s));
+    std::vector<float> f(n);
+    float *dst[5] = { d.dc, d.dmu, d.dp, d.dub[D.cur], d.dvb[D.cur] };
+    for (int q = 0; q < 5; q++) {
+        for (size_t k = 0; k < n; k++) f[k] = (float)dw[q * n + k];
+        HIPCHK(x, hipMemcpy2DAsync(dst[q], D.pitch * sizeof(float), f.data(), D.m1 * sizeof(float),
+                                   D.m1 * sizeof(float), D.m2, hipMemcpyHostToDevice, x->s));
+        HIPCHK(x, hipStreamSynchronize(x->s)); // f is reused
+    }
+    ItemList W;
+    add_item(W, x, OP_MXHS, 0);
+    hipLaunchKernelGGL(k_mx_linresid, dim3(W.blocks), dim3(TBLK), 0, x->s, W.it);
+    HIPCHK(x, hipGetLastError());
+    HIPCHK(x, hipMemcpyAsync(out, d.rout, 5 * n * sizeof(double), hipMemcpyDeviceToHost, x->s));
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    for (size_t k = 0; k < 5 * n; k++) out[k] = -out[k];
     return QNSCH_OK;
 }
 
@@ -630,8 +818,8 @@ int qnsch_step(qnsch_ctx *x, double dt)
     int rc;
     if ((rc = set_dt(x, dt))) return rc;
     std::vector<Op> begin, cyc;
-    begin_program(x->nlev, begin);
-    vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, cyc);
+    step_begin_program(x, begin);
+    cycle_program(x, cyc);
     if ((rc = run_ops(x, begin))) return rc;
     if ((rc = read_red(x))) return rc;
     x->in_step = 1;
@@ -723,9 +911,13 @@ int qnsch_profile(qnsch_ctx *x, int enable)
     HIPCHK(x, hipStreamSynchronize(x->s));
     int rc;
     if ((rc = prof_collect(x))) return rc;
-    x->prof = enable ? 1 : 0;
+    x->prof = enable < 0 || enable > 2 ? 1 : enable;
     x->prof_ms = 0.0;
     x->prof_n = 0;
+    for (int q = 0; q < 2 * NOPS; q++) {
+        x->tag_ms[q] = 0.0;
+        x->tag_n[q] = 0;
+    }
     return QNSCH_OK;
 }
 
@@ -738,6 +930,25 @@ int qnsch_profile_read(qnsch_ctx *x, double out[2])
     out[0] = (double)x->prof_n;
     out[1] = x->prof_ms;
     return QNSCH_OK;
+}
+
+int qnsch_profile_breakdown(qnsch_ctx *x, int32_t *kinds, double *out, int32_t cap)
+{
+    if (!x || (cap > 0 && (!kinds || !out))) return QNSCH_EINVAL;
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    int rc;
+    if ((rc = prof_collect(x))) return rc;
+    int k = 0;
+    for (int t = 0; t < 2 * NOPS; t++) {
+        if (!x->tag_n[t]) continue;
+        if (k < cap) {
+            kinds[k] = t;
+            out[2 * k] = (double)x->tag_n[t];
+            out[2 * k + 1] = x->tag_ms[t];
+        }
+        k++;
+    }
+    return k;
 }
 
 int qnsch_copy_probe(size_t n, int reps, double out[2])
@@ -773,9 +984,23 @@ int qnsch_copy_probe(size_t n, int reps, double out[2])
 
 // ===========================================================================
 // continuous-batching server
+//
+// Requests (independent simulations) are admitted first come, first served
+// while a slot is free and their device footprint fits the budget.  Every
+// running request holds a programme of operations (the phases of its current
+// step, then of its next V-cycle once its residual is known).  Each tick the
+// scheduler takes the largest set of ready requests whose next operations are
+// of the same kind (any level) and runs them as ONE work-list launch; the
+// requests left waiting catch up with the next largest set, which keeps the
+// population in step and the launches full.  Host round trips happen only at
+// residual and step-end reductions (events, no stream drain).  Contexts are
+// recycled by shape: a finished request's final state is downloaded through
+// pinned staging and its device arrays serve the next request of that shape,
+// so steady-state admission allocates nothing.
 
 namespace {
 enum { RQ_QUEUED = 0, RQ_RUNNING = 1, RQ_DONE = 2 };
+enum { W_NONE = 0, W_NORM = 1, W_STEPEND = 2, W_DOWNLOAD = 3 };
 
 struct Req {
     uint64_t id = 0;
@@ -791,31 +1016,42 @@ struct Req {
     int step = 0, vcycles = 0;
     std::vector<Op> prog; // operations still to issue, from pc on
     size_t pc = 0;
-    int wait = 0;         // 1: waiting for a residual, 2: for step-end sums
+    int wait = W_NONE;    // what the request's event stands for
     std::chrono::steady_clock::time_point t_submit, t_admit, t_step0, t_done;
     std::vector<double> step_ms, mass, energy;
     std::vector<int> vc;
     std::vector<double> out[5]; // final state
 };
+
+// what fixes the device layout of a context
+typedef std::tuple<int, int, double, double, int, int, int, int> Shape;
+Shape shape_of(const qnsch_grid &g, int precision)
+{
+    return Shape(g.m1, g.m2, g.Lx, g.Ly, g.bc_x, g.bc_y, level_count(&g), precision);
+}
+
+typedef std::chrono::steady_clock Clock;
 } // namespace
 
 struct qnsch_server {
     hipStream_t s = nullptr;
-    size_t budget = 0, used = 0;
+    size_t budget = 0, used = 0, pooled = 0; // bytes of running / idle contexts
     int max_slots = 0;
     uint64_t next_id = 1;
     std::deque<Req *> queue;
     std::vector<Req *> active;
     std::map<uint64_t, Req *> all;
-    std::vector<double> lat_ms; // every completed step
+    std::multimap<Shape, qnsch_ctx *> pool; // idle contexts for reuse
+    std::vector<double> lat_ms;             // every completed step
     double cell_steps = 0.0;
     bool started = false;
-    std::chrono::steady_clock::time_point t_first, t_last;
-    long launches = 0, ticks = 0;
+    Clock::time_point t_first, t_last;
+    long launches = 0, ticks = 0, created = 0;
+    double host_admit_ms = 0, host_finish_ms = 0, host_wait_ms = 0;
     std::string err;
 };
 
-static double ms_between(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b)
+static double ms_between(Clock::time_point a, Clock::time_point b)
 {
     return std::chrono::duration<double, std::milli>(b - a).count();
 }
@@ -824,49 +1060,128 @@ static void start_step(Req *r)
 {
     r->prog.clear();
     r->pc = 0;
-    begin_program(r->x->nlev, r->prog);
+    step_begin_program(r->x, r->prog);
     r->vcycles = 0;
-    r->t_step0 = std::chrono::steady_clock::now();
+    r->t_step0 = Clock::now();
 }
 
-static void finish(qnsch_server *S, Req *r, int status)
+// a context for request r: an idle one of the same shape, else a new one
+// (idle contexts of other shapes are released first if the budget needs it);
+// parameters, options, dt and the initial state are set, all asynchronously
+static int admit(qnsch_server *S, Req *r)
 {
-    r->status = status;
-    r->state = RQ_DONE;
-    r->t_done = std::chrono::steady_clock::now();
-    S->t_last = r->t_done;
-    if (r->x) {
+    const auto t0 = Clock::now();
+    const Shape key = shape_of(r->g, r->o.precision);
+    qnsch_ctx *x = nullptr;
+    int rc = QNSCH_OK;
+    auto it = S->pool.find(key);
+    if (it != S->pool.end()) {
+        x = it->second;
+        S->pool.erase(it);
+        S->pooled -= x->footprint;
+        x->opt = r->o;
+        set_params(x, &r->p);
+        for (int l = 0; l < x->nlev; l++) x->L[l].cur = 0;
+        x->in_step = 0;
+        memset(&x->st, 0, sizeof(x->st));
+        if (hipMemsetAsync(x->arena, 0, x->arena_bytes, S->s) != hipSuccess) rc = QNSCH_EDEVICE;
+    } else {
+        while (!S->pool.empty() && S->used + S->pooled + r->foot > S->budget) {
+            auto v = S->pool.begin();
+            S->pooled -= v->second->footprint;
+            qnsch_destroy(v->second);
+            S->pool.erase(v);
+        }
+        x = new qnsch_ctx();
+        S->created++;
+        rc = ctx_init(x, &r->g, &r->p, &r->o, S->s);
         const size_t n = (size_t)r->g.m1 * r->g.m2;
-        for (int q = 0; q < 5; q++) r->out[q].assign(n, 0.0);
-        qnsch_get_state(r->x, r->out[0].data(), r->out[1].data(), r->out[2].data(), r->out[3].data(),
-                        r->out[4].data());
-        qnsch_destroy(r->x);
-        r->x = nullptr;
+        if (!rc && hipHostMalloc((void **)&x->stage, 5 * n * sizeof(double), hipHostMallocDefault) != hipSuccess)
+            rc = QNSCH_ENOMEM;
     }
+    if (!rc) {
+        x->dt = r->dt;
+        for (int l = 0; l < x->nlev; l++) {
+            x->hd[l].P.inv_dt = 1.0 / r->dt;
+            x->hd[l].Pf.inv_dt = (float)(1.0 / r->dt);
+        }
+        // hd and stage are pinned and not touched again before this
+        // context's next admission, long after these copies have run
+        rc = upload_desc(x);
+    }
+    if (!rc) {
+        const DLev &D = x->L[0];
+        memcpy(x->stage, r->c0.data(), (size_t)D.m1 * D.m2 * sizeof(double));
+        if (hipMemcpy2DAsync(x->hd[0].c, D.pitch * sizeof(double), x->stage, D.m1 * sizeof(double),
+                             D.m1 * sizeof(double), D.m2, hipMemcpyHostToDevice, S->s) != hipSuccess)
+            rc = QNSCH_EDEVICE;
+    }
+    r->x = x;
+    S->host_admit_ms += ms_between(t0, Clock::now());
+    return rc;
+}
+
+// queue the download of the final state; the request completes when the
+// copies have run
+static void begin_finish(qnsch_server *S, Req *r, int status)
+{
+    const auto t0 = Clock::now();
+    r->status = status;
+    r->prog.clear();
+    r->pc = 0;
+    qnsch_ctx *x = r->x;
+    const DLev &D = x->L[0];
+    const Desc &d = x->hd[0];
+    const size_t n = (size_t)D.m1 * D.m2;
+    const double *src[5] = { d.c, d.mu, d.p, d.ub[D.cur], d.vb[D.cur] };
+    bool ok = true;
+    for (int q = 0; q < 5; q++)
+        ok = ok && hipMemcpy2DAsync(x->stage + q * n, D.m1 * sizeof(double), src[q], D.pitch * sizeof(double),
+                                    D.m1 * sizeof(double), D.m2, hipMemcpyDeviceToHost, S->s) == hipSuccess;
+    ok = ok && hipEventRecord(x->ev, S->s) == hipSuccess;
+    if (!ok && r->status == QNSCH_OK) r->status = QNSCH_EDEVICE;
+    r->wait = W_DOWNLOAD;
+    S->host_finish_ms += ms_between(t0, Clock::now());
+}
+
+static void complete_finish(qnsch_server *S, Req *r)
+{
+    const auto t0 = Clock::now();
+    qnsch_ctx *x = r->x;
+    const size_t n = (size_t)r->g.m1 * r->g.m2;
+    for (int q = 0; q < 5; q++) r->out[q].assign(x->stage + q * n, x->stage + (q + 1) * n);
+    r->state = RQ_DONE;
+    r->wait = W_NONE;
+    r->t_done = Clock::now();
+    S->t_last = r->t_done;
     S->used -= r->foot;
+    S->pool.insert({ shape_of(r->g, r->o.precision), x });
+    S->pooled += x->footprint;
+    r->x = nullptr;
+    S->host_finish_ms += ms_between(t0, Clock::now());
 }
 
 // act on a completed reduction of request r
 static void after_reduction(qnsch_server *S, Req *r)
 {
     qnsch_ctx *x = r->x;
-    if (r->wait == 2) { // step-end sums: record mass and energy, next step
+    if (r->wait == W_STEPEND) { // step-end sums: record mass and energy, next step
         double m[2], e[5];
         me_from_sums(x, x->red_host, m, e);
         r->mass.insert(r->mass.end(), m, m + 2);
         r->energy.insert(r->energy.end(), e, e + 5);
-        const double ms = ms_between(r->t_step0, std::chrono::steady_clock::now());
+        const double ms = ms_between(r->t_step0, Clock::now());
         r->step_ms.push_back(ms);
         r->vc.push_back(r->vcycles);
         S->lat_ms.push_back(ms);
         S->cell_steps += (double)r->g.m1 * r->g.m2;
         r->step++;
-        r->wait = 0;
-        if (r->step >= r->nsteps) finish(S, r, QNSCH_OK);
+        r->wait = W_NONE;
+        if (r->step >= r->nsteps) begin_finish(S, r, QNSCH_OK);
         else start_step(r);
         return;
     }
-    r->wait = 0;
+    r->wait = W_NONE;
     const int j = judge(x, r->vcycles);
     r->prog.clear();
     r->pc = 0;
@@ -876,14 +1191,17 @@ static void after_reduction(qnsch_server *S, Req *r)
     } else if (j == 1) {
         r->prog.push_back({ OP_STEPEND, 0, 0 });
     } else {
-        vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, r->prog);
+        cycle_program(x, r->prog);
         r->vcycles++;
     }
 }
 
 extern "C" {
 
-size_t qnsch_footprint(const qnsch_grid *g) { return g ? footprint_of(g) : 0; }
+size_t qnsch_footprint(const qnsch_grid *g, const qnsch_opts *o)
+{
+    return g ? footprint_of(g, o ? o->precision : QNSCH_FP64) : 0;
+}
 
 int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *stream, qnsch_server **out)
 {
@@ -904,6 +1222,7 @@ void qnsch_server_destroy(qnsch_server *S)
         if (kv.second->x) qnsch_destroy(kv.second->x);
         delete kv.second;
     }
+    for (auto &kv : S->pool) qnsch_destroy(kv.second);
     delete S;
 }
 
@@ -922,12 +1241,12 @@ int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params
     r->c0.assign(c0, c0 + (size_t)g->m1 * g->m2);
     r->nsteps = nsteps;
     r->dt = dt;
-    r->foot = footprint_of(g);
+    r->foot = footprint_of(g, r->o.precision);
     if (r->foot > S->budget) {
         delete r;
         return QNSCH_ENOMEM;
     }
-    r->t_submit = std::chrono::steady_clock::now();
+    r->t_submit = Clock::now();
     S->queue.push_back(r);
     S->all[r->id] = r;
     *id = r->id;
@@ -939,74 +1258,77 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
     if (!S) return QNSCH_EINVAL;
     auto done = [](Req *r) { return r->state == RQ_DONE; };
     for (int tick = 0; tick < max_ticks; tick++) {
-        // admission: first come, first served, while a slot is free and the
-        // footprint fits the budget
         while (!S->queue.empty() && (int)S->active.size() < S->max_slots
                && S->used + S->queue.front()->foot <= S->budget) {
             Req *r = S->queue.front();
             S->queue.pop_front();
-            qnsch_ctx *x = nullptr;
-            int rc = qnsch_create(&r->g, &r->p, &r->o, S->s, &x);
-            if (!rc) rc = qnsch_set_state(x, r->c0.data(), nullptr, nullptr, nullptr, nullptr);
-            if (!rc) rc = set_dt(x, r->dt);
-            r->t_admit = std::chrono::steady_clock::now();
+            r->t_admit = Clock::now();
             if (!S->started) { S->started = true; S->t_first = r->t_admit; }
+            const int rc = admit(S, r);
             if (rc) {
-                if (x) qnsch_destroy(x);
+                if (r->x) qnsch_destroy(r->x);
+                r->x = nullptr;
                 r->status = rc;
                 r->state = RQ_DONE;
+                r->t_done = Clock::now();
                 continue;
             }
-            r->x = x;
-            r->state = RQ_RUNNING;
             S->used += r->foot;
+            r->state = RQ_RUNNING;
             start_step(r);
             S->active.push_back(r);
         }
-        // completed reductions
-        for (Req *r : S->active)
-            if (r->wait && hipEventQuery(r->x->ev) == hipSuccess) after_reduction(S, r);
-        S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
-        // the next operation of every ready request, one launch per kind
-        // (kind, colour, coarse sweeps, relaxation factor): requests whose
-        // options differ do not share a launch
-        typedef std::tuple<int, int, int, double> Key;
-        std::map<Key, std::vector<std::pair<qnsch_ctx *, int>>> groups;
-        std::map<Key, std::vector<Req *>> owners;
+        // completed events: reductions and downloads
         for (Req *r : S->active) {
-            if (r->wait || r->pc >= r->prog.size()) continue;
-            const Op &o = r->prog[r->pc];
-            const Key key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega);
-            groups[key].push_back({ r->x, o.level });
-            owners[key].push_back(r);
-        }
-        bool launched = false;
-        for (auto &kv : groups) {
-            int rc = launch_op(std::get<0>(kv.first), std::get<1>(kv.first), kv.second, S->s);
-            if (rc) {
-                S->err = kv.second[0].first->err;
-                return rc;
-            }
-            S->launches++;
-            launched = true;
-            for (Req *r : owners[kv.first]) {
-                const int kind = r->prog[r->pc].kind;
-                r->pc++;
-                if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
-                    r->wait = kind == OP_STEPEND ? 2 : 1;
-                    (void)hipEventRecord(r->x->ev, S->s);
-                } else if (kind == OP_RESTORE) {
-                    (void)hipStreamSynchronize(S->s);
-                    finish(S, r, r->status);
-                }
-            }
+            if (r->wait == W_NONE || hipEventQuery(r->x->ev) != hipSuccess) continue;
+            if (r->wait == W_DOWNLOAD) complete_finish(S, r);
+            else after_reduction(S, r);
         }
         S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
-        S->ticks++;
-        if (!launched) {
-            if (S->active.empty()) break; // nothing running (queue empty or waiting for budget)
-            (void)hipStreamSynchronize(S->s); // everyone waits on a reduction
+        // the largest set of ready requests with the same next operation
+        // (kind, colour, coarse sweeps, relaxation factor)
+        typedef std::tuple<int, int, int, double> Key;
+        std::map<Key, std::vector<Req *>> groups;
+        for (Req *r : S->active) {
+            if (r->wait != W_NONE || r->pc >= r->prog.size()) continue;
+            const Op &o = r->prog[r->pc];
+            groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega)].push_back(r);
         }
+        if (groups.empty()) {
+            if (S->active.empty()) break; // nothing running (queue empty or waiting for budget)
+            // everyone waits for an event: block on the oldest one
+            const auto t0 = Clock::now();
+            for (Req *r : S->active)
+                if (r->wait != W_NONE) {
+                    (void)hipEventSynchronize(r->x->ev);
+                    break;
+                }
+            S->host_wait_ms += ms_between(t0, Clock::now());
+            S->ticks++;
+            continue;
+        }
+        auto best = groups.begin();
+        for (auto g = groups.begin(); g != groups.end(); ++g)
+            if (g->second.size() > best->second.size()) best = g;
+        std::vector<std::pair<qnsch_ctx *, int>> items;
+        for (Req *r : best->second) items.push_back({ r->x, r->prog[r->pc].level });
+        const int kind = std::get<0>(best->first);
+        int rc = launch_op(kind, std::get<1>(best->first), items, S->s);
+        if (rc) {
+            S->err = items[0].first->err;
+            return rc;
+        }
+        S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
+        for (Req *r : best->second) {
+            r->pc++;
+            if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
+                r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
+                (void)hipEventRecord(r->x->ev, S->s);
+            } else if (kind == OP_RESTORE) {
+                begin_finish(S, r, r->status);
+            }
+        }
+        S->ticks++;
     }
     return (int)(S->queue.size() + S->active.size());
 }
@@ -1043,7 +1365,7 @@ int qnsch_server_result(qnsch_server *S, uint64_t id, double *c, double *mu, dou
     return r->status;
 }
 
-int qnsch_server_stats(qnsch_server *S, double out[8])
+int qnsch_server_stats(qnsch_server *S, double out[12])
 {
     if (!S || !out) return QNSCH_EINVAL;
     std::vector<double> l = S->lat_ms;
@@ -1064,6 +1386,10 @@ int qnsch_server_stats(qnsch_server *S, double out[8])
     out[5] = (double)l.size();
     out[6] = (double)S->launches;
     out[7] = (double)S->ticks;
+    out[8] = S->host_admit_ms;
+    out[9] = S->host_finish_ms;
+    out[10] = S->host_wait_ms;
+    out[11] = (double)S->created;
     return QNSCH_OK;
 }
 

@@ -1,0 +1,348 @@
+// qnsch_lin.hpp -- FP32 linearised smoother of the mixed-precision step.
+//
+// Mixed precision solves the nonlinear system N(w) = 0 of sec. 6.1 by defect
+// correction: the residual r = -N(w) and the update w += delta are FP64, and
+// delta comes from one multigrid V-cycle on the linearisation
+//     J(w^) delta = r,   w^ = w rounded to FP32,
+// run entirely in FP32.  J is the exact Jacobian of the discrete equations
+// (the same equations as the FP64 smoother, differentiated by hand), so the
+// outer iteration is an inexact Newton method whose inner solve has the
+// colour ordering, box smoother and transfers of the FP64 V-cycle (sec. 7.1).
+//
+// Nonlinear terms of N and their linearisations (rho* = rho(c), rho' =
+// -alpha rho^2; every other coefficient is time-n data and constant):
+//   phase    rho*(c)(c - c^n)/dt                     -> Jcc dc (pointwise)
+//   chem.    rho* mubar, the bulk terms in c          -> pointwise in dc, dmu
+//            |grad c|^2 r(c)                          -> 5-point in dc
+//            div(A rho* grad c) (App. A.6)            -> 5-point in dc
+//   momentum (A rho* - A rho^n) u/(2 dt)              -> faces: du, and dc of
+//                                                        the two adjacent cells
+// The rest (advection with time-n velocity, viscous, pressure, surface-tension
+// and mass-equation terms) is linear in the unknowns and is applied to delta
+// with the FP64 formulas; gravity and time-n sources drop out.
+//
+// Tile layout: the field indices of the FP64 tile are kept for the fields that
+// play the same role (so the axis descriptor Ax is shared), with the
+// unknowns replaced by their corrections.
+#pragma once
+#include "qnsch_dev.hpp"
+
+namespace qn {
+
+struct PhysF {
+    float rho1, rho12, drho, visc1, visc12, dvisc;
+    float alpha, inv_Re, inv_M, inv_Pe, K1, K2, K3, mob_reg, inv_dt;
+};
+
+// one level of the correction problem
+struct LView {
+    const float *c, *mu, *u, *v;          // linearisation point (cells; faces)
+    float *dc, *dmu, *dp;                 // correction of the cell unknowns
+    const float *du, *dv;                 // correction of the faces (buffer being read)
+    const float *cn, *un, *vn;            // time-n data
+    const float *rc, *rmu, *rp, *ru, *rv; // right-hand side
+    int m1, m2, pitch, bcx, bcy;
+    float inv_h;
+};
+
+// tile fields: L_C holds c^ (the linearisation point), L_MU, L_P, L_U, L_V
+// the corrections dmu, dp, du, dv; L_DC the correction dc and L_DRS the
+// induced change of density rho'(c^) dc
+enum { L_C = T_C, L_MU = T_MU, L_P = T_P, L_U = T_U, L_V = T_V, L_CN = T_CN, L_UN = T_UN, L_VN = T_VN, L_RN = T_RN,
+       L_MV = T_MV, L_MOB = T_MOB, L_RS = T_RS, L_DC = T_NF, L_DRS, L_NF };
+typedef TileT<float> TileF;
+
+__device__ __forceinline__ float frcpf(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rhof(const PhysF &P, float c) { return P.rho12 * frcpf(P.drho * c + P.rho1); }
+__device__ __forceinline__ float viscf(const PhysF &P, float c) { return P.visc12 * frcpf(P.dvisc * c + P.visc1); }
+__device__ __forceinline__ float mobf(const PhysF &P, float c)
+{
+    const float q = c * (1.0f - c);
+    return __builtin_sqrtf(q * q + P.mob_reg);
+}
+
+__device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const TileF &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        float *s = T.s + e;
+        if (i > L.m1 + 1 || j > L.m2 + 1) {
+            for (int f = 0; f < L_NF; f++) s[f * n] = 0.0f;
+            continue;
+        }
+        const float c = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        const float cn = ldc(L.cn, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        const float dc = ldc(L.dc, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_C * n] = c;
+        s[L_DC * n] = dc;
+        s[L_MU * n] = ldc(L.dmu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_P * n] = ldc(L.dp, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_U * n] = ldu(L.du, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_V * n] = ldv(L.dv, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_CN * n] = cn;
+        s[L_UN * n] = ldu(L.un, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_VN * n] = ldv(L.vn, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_RN * n] = rhof(P, cn);
+        s[L_MV * n] = viscf(P, cn);
+        s[L_MOB * n] = mobf(P, cn);
+        const float rs = rhof(P, c);
+        s[L_RS * n] = rs;
+        s[L_DRS * n] = -P.alpha * rs * rs * dc;
+    }
+}
+
+// one axis of the linearised cell equations at element e: the linear terms
+// applied to the corrections, the linearised gradient-energy and
+// capillary-divergence terms (dG, dL), and the values at c^ that the local
+// Jacobian needs
+struct LCellAx {
+    float adv, div, Lmu, Lp, Sm, Gc, Gn, dG, dL, dGc, dLra, dLrb;
+};
+
+__device__ __forceinline__ LCellAx lcell_axis(const TileF &T, const Ax &a, int e, float ih)
+{
+    const float ih2 = ih * ih;
+    const float wP = (a.per || a.ia < a.ma - 1) ? 1.0f : 0.0f, wM = (a.per || a.ia > 0) ? 1.0f : 0.0f;
+    const int eP = e + a.dn, eM = e - a.dn;
+    const float c = tq(T, L_C, e), cP = tq(T, L_C, eP), cM = tq(T, L_C, eM);
+    const float n = tq(T, L_CN, e), nP = tq(T, L_CN, eP), nM = tq(T, L_CN, eM);
+    const float dc = tq(T, L_DC, e), dcP = tq(T, L_DC, eP), dcM = tq(T, L_DC, eM);
+    const float mu = tq(T, L_MU, e), p = tq(T, L_P, e);
+    const float rnP = tq(T, L_RN, eP), rnM = tq(T, L_RN, eM), rn = tq(T, L_RN, e);
+    const float rs = tq(T, L_RS, e);
+    const float m0 = tq(T, L_MOB, e);
+    const float mP = 0.5f * (tq(T, L_MOB, eP) + m0) * wP, mM = 0.5f * (tq(T, L_MOB, eM) + m0) * wM;
+    const float uP = tq(T, a.FN, eP), u0 = tq(T, a.FN, e);
+    LCellAx x;
+    x.adv = 0.5f * ih * (rnP * (nP - n) * uP + rnM * (n - nM) * u0);
+    x.div = ih * (uP - u0);
+    x.Lmu = ih2 * (mP * (tq(T, L_MU, eP) - mu) - mM * (mu - tq(T, L_MU, eM)));
+    x.Lp = ih2 * (mP * (tq(T, L_P, eP) - p) - mM * (p - tq(T, L_P, eM)));
+    x.Sm = ih2 * (mP + mM);
+    const float dP = cP - c, dM = c - cM, gP = nP - n, gM = n - nM;
+    x.Gc = 0.5f * ih2 * (dP * dP + dM * dM);
+    x.Gn = 0.5f * ih2 * (gP * gP + gM * gM);
+    // d(Gc) = ih2 (dP d(dP) + dM d(dM)); across a wall the mirrored ghost
+    // makes both dP and d(dP) vanish
+    x.dG = ih2 * (dP * (dcP - dc) + dM * (dc - dcM));
+    const float rh = 0.5f * (rs + rn);
+    const float kP = 0.5f * (0.5f * (tq(T, L_RS, eP) + rnP) + rh) * wP;
+    const float kM = 0.5f * (0.5f * (tq(T, L_RS, eM) + rnM) + rh) * wM;
+    const float hP = 0.5f * (dP + gP), hM = 0.5f * (dM + gM);
+    const float drs = tq(T, L_DRS, e);
+    const float dkP = 0.25f * (tq(T, L_DRS, eP) + drs) * wP, dkM = 0.25f * (tq(T, L_DRS, eM) + drs) * wM;
+    x.dL = ih2 * (dkP * hP + kP * 0.5f * (dcP - dc) - dkM * hM - kM * 0.5f * (dc - dcM));
+    x.dGc = ih2 * (wP * (-dP) + wM * dM);
+    x.dLra = ih2 * (wP * hP - wM * hM);
+    x.dLrb = ih2 * (kP + kM);
+    return x;
+}
+
+__device__ __forceinline__ LCellAx lcell_sum(const LCellAx &x)
+{
+    LCellAx s;
+    s.adv = x.adv + other(x.adv);
+    s.div = x.div + other(x.div);
+    s.Lmu = x.Lmu + other(x.Lmu);
+    s.Lp = x.Lp + other(x.Lp);
+    s.Sm = x.Sm + other(x.Sm);
+    s.Gc = x.Gc + other(x.Gc);
+    s.Gn = x.Gn + other(x.Gn);
+    s.dG = x.dG + other(x.dG);
+    s.dL = x.dL + other(x.dL);
+    s.dGc = x.dGc + other(x.dGc);
+    s.dLra = x.dLra + other(x.dLra);
+    s.dLrb = x.dLrb + other(x.dLrb);
+    return s;
+}
+
+// J delta for the three cell equations and the local 2x2 Jacobian in
+// (c_ij, mubar_ij) at c^ (the matrix of the FP64 point smoother)
+struct LCellEq {
+    float Nc, Nmu, Np;
+    float Jcc, Jcm, Jmc, Jmm, Jpp;
+};
+
+__device__ __forceinline__ LCellEq lcell_eq(const PhysF &P, const TileF &T, int e, const LCellAx &s, float muh)
+{
+    const float c = tq(T, L_C, e), n = tq(T, L_CN, e);
+    const float rs = tq(T, L_RS, e), rn = tq(T, L_RN, e);
+    const float dc = tq(T, L_DC, e), dmu = tq(T, L_MU, e);
+    const float drs = -P.alpha * rs * rs;
+    LCellEq q;
+    q.Jcc = (drs * (c - n) + rs) * P.inv_dt;
+    q.Nc = q.Jcc * dc + s.adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp;
+    q.Np = s.div - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp;
+    const float rh = 0.5f * (rs + rn);
+    const float q1 = c * (c - 1.0f), q0 = n * (n - 1.0f);
+    const float g = 0.25f * (q1 + q0) * (c + n - 1.0f);
+    const float Fh = 0.5f * (0.25f * q1 * q1 + 0.25f * q0 * q0);
+    const float r = -P.alpha * rs * rn;
+    const float Gh = 0.5f * (s.Gc + s.Gn);
+    const float dg = 0.25f * ((2.0f * c - 1.0f) * (c + n - 1.0f) + q1 + q0);
+    const float f1 = q1 * (c - 0.5f);
+    const float dr = P.alpha * P.alpha * rs * rs * rn;
+    // derivative in the cell's own c of every term that is pointwise in it
+    const float Jpw = drs * muh - P.K1 * (0.5f * drs * g + rh * dg + 0.5f * f1 * r + Fh * dr) - P.K2 * Gh * dr;
+    q.Nmu = rs * dmu + Jpw * dc - P.K2 * 0.5f * s.dG * r + P.K3 * s.dL;
+    q.Jcm = P.inv_Pe * s.Sm;
+    q.Jmm = rs;
+    const float dLr = 0.25f * drs * s.dLra - 0.5f * s.dLrb;
+    q.Jmc = Jpw - P.K2 * 0.5f * s.dGc * r + P.K3 * dLr;
+    q.Jpp = P.alpha * P.alpha * P.inv_Pe * s.Sm;
+    return q;
+}
+
+struct FaceEqF {
+    float N, diag;
+};
+
+// J delta for the momentum equation on the face at element ef, and the
+// derivative in the face's own velocity at w^ (uh = that face's velocity at
+// w^, which multiplies the change of the density average)
+__device__ __forceinline__ FaceEqF lface_eq(const PhysF &P, const TileF &T, const Ax &a, int ef, int it, float ih,
+                                            float uh)
+{
+    const float ih2 = ih * ih;
+    const int eL = ef - a.dn, eR = ef, dt = a.dt;
+    const float rL = tq(T, L_RN, eL), rR = tq(T, L_RN, eR);
+    const float Rt = 0.25f * (rL + rR + tq(T, L_RN, eL + dt) + tq(T, L_RN, eR + dt));
+    const float Rb = 0.25f * (rL + rR + tq(T, L_RN, eL - dt) + tq(T, L_RN, eR - dt));
+    const float mvL = tq(T, L_MV, eL), mvR = tq(T, L_MV, eR);
+    const float nut = 0.25f * (mvL + mvR + tq(T, L_MV, eL + dt) + tq(T, L_MV, eR + dt));
+    const float nub = 0.25f * (mvL + mvR + tq(T, L_MV, eL - dt) + tq(T, L_MV, eR - dt));
+    const float Arn = 0.5f * (rL + rR);
+    const float Ars = 0.5f * (tq(T, L_RS, eL) + tq(T, L_RS, eR));
+    const float dArs = 0.5f * (tq(T, L_DRS, eL) + tq(T, L_DRS, eR));
+    const float un0 = tq(T, a.FNN, ef);
+    const float wL = rL * 0.5f * (tq(T, a.FNN, ef - a.dn) + un0);
+    const float wR = rR * 0.5f * (un0 + tq(T, a.FNN, ef + a.dn));
+    const float Vt = 0.5f * (tq(T, a.FTN, eL + dt) + tq(T, a.FTN, eR + dt));
+    const float Vb = 0.5f * (tq(T, a.FTN, eL) + tq(T, a.FTN, eR));
+    const float u0 = tq(T, a.FN, ef), uE = tq(T, a.FN, ef + a.dn), uW = tq(T, a.FN, ef - a.dn);
+    const float uN = tq(T, a.FN, ef + dt), uS = tq(T, a.FN, ef - dt);
+    const float thR = ih * (uE - u0 + tq(T, a.FT, eR + dt) - tq(T, a.FT, eR));
+    const float thL = ih * (u0 - uW + tq(T, a.FT, eL + dt) - tq(T, a.FT, eL));
+    const float nL = tq(T, L_CN, eL), nR = tq(T, L_CN, eR);
+    FaceEqF q;
+    q.N = Arn * u0 * P.inv_dt
+        + 0.5f * ih * (wR * uE - wL * uW + Rt * Vt * uN - Rb * Vb * uS)
+        + 0.5f * (Ars - Arn) * P.inv_dt * u0 + 0.5f * dArs * P.inv_dt * uh
+        + P.inv_M * ih * (tq(T, L_P, eR) - tq(T, L_P, eL))
+        - P.inv_M * ih * 0.5f * (rR * tq(T, L_MU, eL) + rL * tq(T, L_MU, eR)) * (nR - nL)
+        - P.inv_Re * ih2 * (mvR * (uE - u0) - mvL * (u0 - uW) + nut * (uN - u0) - nub * (u0 - uS))
+        - (P.inv_Re / 3.0f) * ih * (mvR * thR - mvL * thL);
+    const float gt = (!a.pert && it == a.mt - 1) ? 1.0f : 0.0f, gb = (!a.pert && it == 0) ? 1.0f : 0.0f;
+    q.diag = 0.5f * (Arn + Ars) * P.inv_dt + (4.0f / 3.0f) * P.inv_Re * ih2 * (mvL + mvR)
+           + P.inv_Re * ih2 * (nut * (1.0f + gt) + nub * (1.0f + gb)) + 0.5f * ih * (gb * Rb * Vb - gt * Rt * Vt);
+    return q;
+}
+
+// the velocity at w^ on the face of element ef's row: the west face of cell
+// (i, j) (x lane) or its south face (y lane), or the next one along the axis
+__device__ __forceinline__ float face_point(const LView &L, int hlf, size_t k) { return (hlf ? L.v : L.u)[k]; }
+
+// one cell of the current colour: the FP64 smoother's two steps applied to
+// the correction equation J(w^) delta = r.  Step 1 is a 2x2 solve for
+// (dc, dmu) of the cell; step 2 the 5x5 Vanka box for its four faces and dp.
+__device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, const TileF &T, float *dunew,
+                                            float *dvnew, int i, int j, int hlf, float omega)
+{
+    const size_t k = (size_t)j * L.pitch + i;
+    const float ih = L.inv_h, ih2 = ih * ih;
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    // ---- step 1
+    const LCellAx s = lcell_sum(lcell_axis(T, a, e, ih));
+    const LCellEq q = lcell_eq(P, T, e, s, L.mu[k]);
+    const float r1 = L.rc[k] - q.Nc, r2 = L.rmu[k] - q.Nmu;
+    const float idet = frcpf(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
+    const float c0 = tq(T, L_DC, e), m0 = tq(T, L_MU, e);
+    const float cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
+    const float mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
+    if (hlf == 0) {
+        L.dc[k] = cnew;
+        L.dmu[k] = mnew;
+    }
+    const int st = T.W * T.H;
+    const float rs = tq(T, L_RS, e);
+    T.s[L_DC * st + e] = cnew;
+    T.s[L_MU * st + e] = mnew;
+    T.s[L_DRS * st + e] = -P.alpha * rs * rs * cnew;
+    // ---- step 2
+    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
+    const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
+    const size_t khi = (size_t)jhi * L.pitch + ihi;
+    const FaceEqF flo = lface_eq(P, T, a, e, a.it, ih, face_point(L, hlf, k));
+    const FaceEqF fhi = lface_eq(P, T, a, e + a.dn, a.it, ih, face_point(L, hlf, khi));
+    const float *rN = hlf ? L.rv : L.ru;
+    const float blo = hlo ? rN[k] - flo.N : 0.0f, dlo = hlo ? flo.diag : 1.0f;
+    const float bhi = hhi ? rN[khi] - fhi.N : 0.0f, dhi = hhi ? fhi.diag : 1.0f;
+    const float Lmu_new = s.Lmu - s.Sm * (mnew - m0);
+    const float bp = L.rp[k] - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
+    const float w_ax = tq(T, L_RN, e) * 0.5f * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
+    const float mv0 = tq(T, L_MV, e);
+    const float vis = (4.0f / 3.0f) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0f;
+    const float gp = P.inv_M * ih;
+    const float o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const int o_hlo = __shfl_xor((int)hlo, 1, 64), o_hhi = __shfl_xor((int)hhi, 1, 64);
+    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
+    const float wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
+    float A[5][5], b[5];
+    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi; b[4] = bp;
+    const float d0 = hlf ? o_dlo : dlo, d1 = hlf ? o_dhi : dhi, d2 = hlf ? dlo : o_dlo, d3 = hlf ? dhi : o_dhi;
+    const float mW = xl ? 1.0f : 0.0f, mE = xh ? 1.0f : 0.0f, mS = yl ? 1.0f : 0.0f, mN = yh ? 1.0f : 0.0f;
+    A[0][0] = d0; A[0][1] = mW * (0.5f * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd; A[0][4] = mW * gp;
+    A[1][1] = d1; A[1][0] = mE * (-0.5f * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd; A[1][4] = -mE * gp;
+    A[2][2] = d2; A[2][3] = mS * (0.5f * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
+    A[3][3] = d3; A[3][2] = mN * (-0.5f * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
+    A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
+    float inv[5];
+#pragma unroll
+    for (int cc = 0; cc < 4; cc++) {
+        inv[cc] = frcpf(A[cc][cc]);
+#pragma unroll
+        for (int r = cc + 1; r < 5; r++) {
+            const float l = A[r][cc] * inv[cc];
+#pragma unroll
+            for (int t = cc + 1; t < 5; t++) A[r][t] -= l * A[cc][t];
+            b[r] -= l * b[cc];
+        }
+    }
+    inv[4] = frcpf(A[4][4]);
+#pragma unroll
+    for (int cc = 4; cc >= 0; cc--) {
+        float acc = b[cc];
+#pragma unroll
+        for (int t = cc + 1; t < 5; t++) acc -= A[cc][t] * b[t];
+        b[cc] = acc * inv[cc];
+    }
+    float *dst = hlf ? dvnew : dunew;
+    const float dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
+    if (hlo) dst[k] = tq(T, a.FN, e) + omega * dl;
+    if (hhi) dst[khi] = tq(T, a.FN, e + a.dn) + omega * dh;
+    if (hlf == 0) L.dp[k] = tq(T, L_P, e) + omega * b[4];
+}
+
+// residual of the correction equation r - J(w^) delta for the five equations
+// attached to cell (i, j) (cell equations; west face on lane 0, south face on
+// lane 1, zero for a face on a wall)
+__device__ __forceinline__ void lresid_pair(const PhysF &P, const LView &L, const TileF &T, int i, int j, int hlf,
+                                            float &rc, float &rm, float &rp, float &rf)
+{
+    const size_t k = (size_t)j * L.pitch + i;
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    const LCellAx s = lcell_sum(lcell_axis(T, a, e, L.inv_h));
+    const LCellEq q = lcell_eq(P, T, e, s, L.mu[k]);
+    rc = L.rc[k] - q.Nc;
+    rm = L.rmu[k] - q.Nmu;
+    rp = L.rp[k] - q.Np;
+    const bool hlo = a.per || a.ia >= 1;
+    const FaceEqF f = lface_eq(P, T, a, e, a.it, L.inv_h, face_point(L, hlf, k));
+    rf = hlo ? (hlf ? L.rv : L.ru)[k] - f.N : 0.0f;
+}
+
+} // namespace qn

@@ -1,0 +1,273 @@
+// qnsch_mxk.hpp -- work-list kernels of the mixed-precision step: one FP32
+// multigrid V-cycle on the correction equation J(w^) delta = r (see
+// qnsch_lin.hpp), with the FP64 residual, update and reductions done by the
+// kernels of qnsch_kern.hpp.
+//
+// Correction cycle on a hierarchy of levels (the coarse-grid correction
+// scheme for a linear problem; sec. 7.1 gives the smoother and transfers):
+//   smooth (nu1 red-black sweeps), restrict r - J delta and the linearisation
+//   point to the next level with delta_H = 0, recurse, solve the coarsest
+//   level in LDS, prolongate delta_H and add it, smooth (nu2 sweeps);
+// then w += delta in FP64.  The coarse operators are the rediscretised
+// Jacobians J_H(R w^).
+#pragma once
+#include "qnsch_kern.hpp"
+
+namespace qn {
+
+#define LTILE_FLOATS (L_NF * (TX + 3) * (TY + 3))
+static_assert(LTILE_FLOATS * 4 <= 65536, "FP32 tile exceeds 64 KiB of LDS");
+
+__device__ __forceinline__ LView lview_of(const Desc &d, int par)
+{
+    LView V;
+    V.c = d.xc; V.mu = d.xmu; V.u = d.xu; V.v = d.xv;
+    V.dc = d.dc; V.dmu = d.dmu; V.dp = d.dp;
+    V.du = d.dub[par]; V.dv = d.dvb[par];
+    V.cn = d.cnf; V.un = d.unf; V.vn = d.vnf;
+    V.rc = d.rc; V.rmu = d.rmu; V.rp = d.rp; V.ru = d.ru; V.rv = d.rv;
+    V.m1 = d.m1; V.m2 = d.m2; V.pitch = d.pitch;
+    V.bcx = d.bcx; V.bcy = d.bcy;
+    V.inv_h = d.finv_h;
+    return V;
+}
+
+// one colour half-sweep of the correction smoother; the correction faces are
+// read from buffer par and written to par^1
+__device__ __forceinline__ void mx_halfsweep_body(const Items &it, int colour, float omega)
+{
+    __shared__ float sm[LTILE_FLOATS];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const int par = it.par[k];
+    const LView L = lview_of(d, par);
+    const TileF T = item_tile(sm, it, k, d);
+    ltile_load(d.Pf, L, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
+    const int j = T.j0 + lj;
+    const int i = T.i0 + 2 * kk + ((j + colour) & 1);
+    if (i < L.m1 && j < L.m2) lrelax_pair(d.Pf, L, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, hlf, omega);
+}
+__global__ __launch_bounds__(TBLK) void k_mx_halfsweep(Items it, int colour, float omega)
+{
+    mx_halfsweep_body(it, colour, omega);
+}
+// finest-level launches under their own name (profiles)
+__global__ __launch_bounds__(TBLK) void k_mx_halfsweep_fine(Items it, int colour, float omega)
+{
+    mx_halfsweep_body(it, colour, omega);
+}
+
+// r - J delta on the item's level, restricted to the next coarser level
+// (cells: mean of four; faces: mean of the two coincident fine faces),
+// together with the linearisation point; the coarse correction starts at 0
+__global__ __launch_bounds__(TBLK) void k_mx_restrict(Items it)
+{
+    __shared__ float sm[LTILE_FLOATS];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const Desc &C = *d.coarse;
+    const LView Lf = lview_of(d, it.par[k]);
+    const TileF T = item_tile(sm, it, k, d);
+    ltile_load(d.Pf, Lf, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    if (pr >= (TX / 2) * (TY / 2)) return;
+    const int I = T.i0 / 2 + pr % (TX / 2), J = T.j0 / 2 + pr / (TX / 2);
+    if (I >= C.m1 || J >= C.m2) return;
+    float rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sf = 0;
+#pragma unroll
+    for (int b = 0; b < 2; b++)
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            const int i = 2 * I + a, j = 2 * J + b;
+            const size_t q = (size_t)j * Lf.pitch + i;
+            float xc, xm, xp, xf;
+            lresid_pair(d.Pf, Lf, T, i, j, hlf, xc, xm, xp, xf);
+            rc += xc; rm += xm; rp += xp;
+            if ((hlf ? b : a) == 0) { rf += xf; sf += (hlf ? Lf.v : Lf.u)[q]; }
+            sc += T.q(L_C, i, j); smu += Lf.mu[q];
+        }
+    const size_t q = (size_t)J * C.pitch + I;
+    const int cp = it.cpar[k];
+    if (hlf == 0) {
+        C.xc[q] = 0.25f * sc;
+        C.xmu[q] = 0.25f * smu;
+        C.xu[q] = 0.5f * sf;
+        C.rc[q] = 0.25f * rc;
+        C.rmu[q] = 0.25f * rm;
+        C.rp[q] = 0.25f * rp;
+        C.ru[q] = 0.5f * rf;
+        C.dc[q] = 0.0f; C.dmu[q] = 0.0f; C.dp[q] = 0.0f;
+        C.dub[cp][q] = 0.0f;
+    } else {
+        C.xv[q] = 0.5f * sf;
+        C.rv[q] = 0.5f * rf;
+        C.dvb[cp][q] = 0.0f;
+    }
+}
+
+// delta_h += P delta_H: cells piecewise constant; faces copy the coincident
+// coarse face and average the two coarse faces across the coarse cell
+__global__ __launch_bounds__(BLK) void k_mx_prolong(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const Desc &C = *d.coarse;
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I, kf = (size_t)j * d.pitch + i;
+    const float *Cu = C.dub[it.cpar[k]], *Cv = C.dvb[it.cpar[k]];
+    float *uf = d.dub[it.par[k]], *vf = d.dvb[it.par[k]];
+    d.dc[kf] += C.dc[kc];
+    d.dmu[kf] += C.dmu[kc];
+    d.dp[kf] += C.dp[kc];
+    if (d.bcx || i >= 1) {
+        float du = Cu[kc];
+        if (i & 1) {
+            float e = 0.0f;
+            if (I + 1 < C.m1) e = Cu[kc + 1];
+            else if (d.bcx) e = Cu[(size_t)J * C.pitch];
+            du = 0.5f * (du + e);
+        }
+        uf[kf] += du;
+    }
+    if (d.bcy || j >= 1) {
+        float dv = Cv[kc];
+        if (j & 1) {
+            float e = 0.0f;
+            if (J + 1 < C.m2) e = Cv[kc + C.pitch];
+            else if (d.bcy) e = Cv[I];
+            dv = 0.5f * (dv + e);
+        }
+        vf[kf] += dv;
+    }
+}
+
+// LDS floats of the coarsest-level correction solve: 19 level arrays + a tile
+__host__ __device__ inline size_t mx_coarse_lds_floats(int m1, int m2)
+{
+    return (size_t)19 * m1 * m2 + (size_t)L_NF * (m1 + 3) * (m2 + 3);
+}
+
+// all correction sweeps of the coarsest level in one workgroup per item, the
+// level resident in LDS; an even number of half-sweeps keeps the result in
+// buffer par
+__global__ __launch_bounds__(512) void k_mx_coarse_solve(Items it, int sweeps, float omega)
+{
+    extern __shared__ float smf[];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int par = it.par[k];
+    const LView L = lview_of(d, par);
+    float *ua = d.dub[par], *va = d.dvb[par];
+    const int m1 = L.m1, m2 = L.m2, n = m1 * m2;
+    float *hxc = smf, *hxmu = smf + n, *hxu = smf + 2 * n, *hxv = smf + 3 * n, *hdc = smf + 4 * n,
+          *hdmu = smf + 5 * n, *hdp = smf + 6 * n, *uA = smf + 7 * n, *vA = smf + 8 * n, *uB = smf + 9 * n,
+          *vB = smf + 10 * n, *hcn = smf + 11 * n, *hun = smf + 12 * n, *hvn = smf + 13 * n, *hr = smf + 14 * n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t q = (size_t)j * L.pitch + i;
+        hxc[e] = L.c[q]; hxmu[e] = L.mu[q]; hxu[e] = L.u[q]; hxv[e] = L.v[q];
+        hdc[e] = L.dc[q]; hdmu[e] = L.dmu[q]; hdp[e] = L.dp[q]; uA[e] = ua[q]; vA[e] = va[q];
+        hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
+        hr[e] = L.rc[q]; hr[n + e] = L.rmu[q]; hr[2 * n + e] = L.rp[q]; hr[3 * n + e] = L.ru[q];
+        hr[4 * n + e] = L.rv[q];
+    }
+    __syncthreads();
+    LView H = L;
+    H.c = hxc; H.mu = hxmu; H.u = hxu; H.v = hxv; H.dc = hdc; H.dmu = hdmu; H.dp = hdp;
+    H.cn = hcn; H.un = hun; H.vn = hvn;
+    H.rc = hr; H.rmu = hr + n; H.rp = hr + 2 * n; H.ru = hr + 3 * n; H.rv = hr + 4 * n;
+    H.pitch = m1;
+    TileF T;
+    T.s = smf + 19 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    const int half = m1 >> 1;
+    for (int s = 0; s < 2 * sweeps; s++) {
+        const int colour = s & 1;
+        float *uw, *vw;
+        if (s & 1) { H.du = uB; H.dv = vB; uw = uA; vw = vA; }
+        else { H.du = uA; H.dv = vA; uw = uB; vw = vB; }
+        ltile_load(d.Pf, H, T);
+        __syncthreads();
+        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
+            const int pr = t >> 1;
+            const int j = pr / half;
+            const int i = 2 * (pr - j * half) + ((j + colour) & 1);
+            lrelax_pair(d.Pf, H, T, uw, vw, i, j, t & 1, omega);
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int j = e / m1, i = e - j * m1;
+        const size_t q = (size_t)j * L.pitch + i;
+        L.dc[q] = hdc[e]; L.dmu[q] = hdmu[e]; L.dp[q] = hdp[e]; ua[q] = uA[e]; va[q] = vA[e];
+    }
+}
+
+// w += delta on the finest level (FP64 state, single u/v buffer in mixed
+// mode); faces on walls are not unknowns
+__global__ __launch_bounds__(BLK) void k_mx_update(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const size_t q = (size_t)j * d.pitch + i;
+    const int par = it.par[k];
+    d.c[q] += (double)d.dc[q];
+    d.mu[q] += (double)d.dmu[q];
+    d.p[q] += (double)d.dp[q];
+    if (d.bcx || i >= 1) d.ub[0][q] += (double)d.dub[par][q];
+    if (d.bcy || j >= 1) d.vb[0][q] += (double)d.dvb[par][q];
+}
+
+// FP32 time-n data of the next coarser level
+__global__ __launch_bounds__(BLK) void k_mx_restrict_n(Items it)
+{
+    const int k = find_item(it);
+    const Desc &F = *it.d[k];
+    const Desc &C = *F.coarse;
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= C.m1 * C.m2) return;
+    const int J = t / C.m1, I = t - J * C.m1;
+    const size_t f = (size_t)(2 * J) * F.pitch + 2 * I, q = (size_t)J * C.pitch + I;
+    C.cnf[q] = 0.25f * (F.cnf[f] + F.cnf[f + 1] + F.cnf[f + F.pitch] + F.cnf[f + F.pitch + 1]);
+    C.unf[q] = 0.5f * (F.unf[f] + F.unf[f + F.pitch]);
+    C.vnf[q] = 0.5f * (F.vnf[f] + F.vnf[f + 1]);
+}
+
+// r - J delta on a level into the FP64 residual-field buffer (m1 x m2 per
+// field, packed), for checking the linearisation
+__global__ __launch_bounds__(TBLK) void k_mx_linresid(Items it)
+{
+    __shared__ float sm[LTILE_FLOATS];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const LView L = lview_of(d, it.par[k]);
+    const TileF T = item_tile(sm, it, k, d);
+    ltile_load(d.Pf, L, T);
+    __syncthreads();
+    const size_t n = (size_t)L.m1 * L.m2;
+    const int hlf = threadIdx.x & 1;
+    int i, j;
+    pair_cells(T, i, j);
+    for (int a = 0; a < 2; a++, i++) {
+        if (i >= L.m1 || j >= L.m2) continue;
+        float rc, rm, rp, rf;
+        lresid_pair(d.Pf, L, T, i, j, hlf, rc, rm, rp, rf);
+        const size_t q = (size_t)j * L.m1 + i;
+        d.rout[(3 + hlf) * n + q] = rf;
+        if (hlf == 0) { d.rout[q] = rc; d.rout[n + q] = rm; d.rout[2 * n + q] = rp; }
+    }
+}
+
+} // namespace qn

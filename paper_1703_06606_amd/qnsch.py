@@ -19,10 +19,16 @@ FP64, MIXED = 0, 1
 # every exported symbol declared in include/qnsch.h
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
            "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
-           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_mass", "qnsch_energy", "qnsch_stats",
-           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_copy_probe",
+           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy", "qnsch_stats",
+           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats")
+
+
+# operation classes of qnsch_profile_breakdown, in the library's numbering
+OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
+            "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
+            "mx_prolong", "mx_update")
 
 
 class QnschError(RuntimeError):
@@ -79,14 +85,16 @@ def lib():
         L.qnsch_residual.argtypes = [vp, P, P]
         L.qnsch_halfsweep.argtypes = [vp, C.c_int]
         L.qnsch_end_step.argtypes = [vp]
+        L.qnsch_lin_apply.argtypes = [vp, P, P]
         L.qnsch_mass.argtypes = [vp, P]
         L.qnsch_energy.argtypes = [vp, P]
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.qnsch_synchronize.argtypes = [vp]
         L.qnsch_profile.argtypes = [vp, C.c_int]
         L.qnsch_profile_read.argtypes = [vp, P]
+        L.qnsch_profile_breakdown.argtypes = [vp, C.POINTER(C.c_int32), P, C.c_int32]
         L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
-        L.qnsch_footprint.argtypes = [C.POINTER(Grid)]
+        L.qnsch_footprint.argtypes = [C.POINTER(Grid), C.POINTER(Opts)]
         L.qnsch_footprint.restype = C.c_size_t
         L.qnsch_server_create.argtypes = [C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
         L.qnsch_server_destroy.argtypes = [vp]
@@ -192,6 +200,14 @@ class Solver:
     def end_step(self):
         self._chk(lib().qnsch_end_step(self.h))
 
+    def lin_apply(self, dw):
+        """J(w) dw at the current iterate (mixed-precision contexts), shape
+        (5, m2, m1)"""
+        dw = np.ascontiguousarray(dw, dtype=np.float64).reshape(5, self.m2, self.m1)
+        out = np.zeros_like(dw)
+        self._chk(lib().qnsch_lin_apply(self.h, _ptr(dw), _ptr(out)))
+        return out
+
     def mass(self):
         out = np.zeros(2)
         self._chk(lib().qnsch_mass(self.h, _ptr(out)))
@@ -210,13 +226,30 @@ class Solver:
     def synchronize(self):
         self._chk(lib().qnsch_synchronize(self.h))
 
-    def profile(self, enable):
-        self._chk(lib().qnsch_profile(self.h, 1 if enable else 0))
+    def profile(self, mode):
+        """0 off, 1 (or True) finest half-sweeps, 2 every launch"""
+        self._chk(lib().qnsch_profile(self.h, int(mode)))
 
     def profile_read(self):
         out = np.zeros(2)
         self._chk(lib().qnsch_profile_read(self.h, _ptr(out)))
         return int(out[0]), float(out[1])
+
+    def profile_breakdown(self):
+        """{operation name: (launches, ms)} of the launches timed since
+        profile(2)"""
+        cap = 2 * len(OP_NAMES)
+        kinds = (C.c_int32 * cap)()
+        out = np.zeros(2 * cap)
+        n = lib().qnsch_profile_breakdown(self.h, kinds, _ptr(out), cap)
+        if n < 0:
+            self._chk(n)
+        res = {}
+        for k in range(min(n, cap)):
+            t = kinds[k]
+            name = OP_NAMES[t // 2] + ("_coarse" if t % 2 else "_fine")
+            res[name] = (int(out[2 * k]), float(out[2 * k + 1]))
+        return res
 
     def set_iterate(self, c, mu=None, p=None, u=None, v=None):
         arrs = [self._f(a) for a in (c, mu, p, u, v)]
@@ -240,10 +273,10 @@ def _structs(grid, params, opts):
     return g, p, o
 
 
-def footprint(grid):
-    """device bytes of a context of this grid"""
-    g, _, _ = _structs(grid, dict((n, 1.0) for n, _ in Params._fields_), None)
-    return int(lib().qnsch_footprint(C.byref(g)))
+def footprint(grid, opts=None):
+    """device bytes of a context of this grid (and precision)"""
+    g, _, o = _structs(grid, dict((n, 1.0) for n, _ in Params._fields_), opts)
+    return int(lib().qnsch_footprint(C.byref(g), C.byref(o) if o is not None else None))
 
 
 class Server:
@@ -301,9 +334,10 @@ class Server:
         return out
 
     def stats(self):
-        out = np.zeros(8)
+        out = np.zeros(12)
         self_rc = lib().qnsch_server_stats(self.h, _ptr(out))
         if self_rc != OK:
             raise QnschError(self_rc, "stats failed")
-        keys = ("p50_ms", "p99_ms", "cell_steps", "wall_s", "cell_steps_per_s", "steps", "launches", "ticks")
+        keys = ("p50_ms", "p99_ms", "cell_steps", "wall_s", "cell_steps_per_s", "steps", "launches", "ticks",
+                "host_admit_ms", "host_finish_ms", "host_wait_ms", "contexts_created")
         return dict(zip(keys, out))

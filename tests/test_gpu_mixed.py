@@ -1,0 +1,155 @@
+"""Mixed precision (FP32 correction cycles inside FP64 defect correction)
+against the FP64 CPU oracle, through the C ABI.
+
+The mixed solver stops on the same FP64 residual norms as the FP64 one, so a
+converged mixed step is a solution of the same discrete system: it is compared
+with the oracle's FP64 solution at 1e-6 relative.  The FP32 linearisation the
+correction cycle smooths is compared with the oracle's exact Jacobian-vector
+product (complex step) at FP32 accuracy.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as OR
+from paper_1703_06606_amd import qnsch as Q
+from paper_1703_06606_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+FIELDS = ("c", "mu", "p", "u", "v")
+MIXED_TOL = 1e-6  # relative, converged fields against the FP64 oracle
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b, floor=1e-12):
+    return np.abs(a - b).max() / max(np.abs(b).max(), floor)
+
+
+def grid_(m1, m2, bcx, bcy, levels=0):
+    return dict(m1=m1, m2=m2, Lx=1.0, Ly=m2 / m1, bcx=bcx, bcy=bcy, levels=levels)
+
+
+def par_O1(**kw):
+    p = dict(rho1=1.0, rho2=2.5, visc1=1.0, visc2=1.8, Re=3.0, We=2.0, inv_Fr=0.7, Pe=2.0, M=0.8,
+             eps=0.5, eta=0.9, mob_reg=0.05, rho_ref=0.0)
+    p.update(kw)
+    return p
+
+
+def mixed(opts):
+    return dict(opts, precision=Q.MIXED)
+
+
+SHAPES = [(16, 24, 0, 0), (16, 24, 1, 0), (16, 16, 1, 1), (40, 24, 0, 0), (72, 40, 1, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
+def test_linearisation_matches_oracle_jvp(shape):
+    """J(w) dw in FP32 against the oracle's complex-step J(w) dw, per field,
+    relative to the field's largest entry; also linear in dw"""
+    m1, m2, bx, by = shape
+    say("linearisation", shape)
+    cfg = dict(grid=grid_(m1, m2, bx, by), params=par_O1(rho2=3.0))
+    g = Q.Solver(cfg["grid"], cfg["params"], mixed(W.default_opts()))
+    o = OR.Oracle(cfg["grid"], cfg["params"], W.default_opts())
+    w, wn = W.random_state(cfg["grid"], 31), W.random_state(cfg["grid"], 32)
+    d = W.random_state(cfg["grid"], 33, base_c=0.0)
+    dw = np.stack([d[k] for k in FIELDS])
+    for s in (g, o):
+        s.set_time_n_and_iterate(wn, w, 0.3)
+    jg = g.lin_apply(dw)
+    jo = o.jvp(dw)
+    for q, k in enumerate(FIELDS):
+        assert rel(jg[q], jo[q]) < 2e-5, (k, rel(jg[q], jo[q]))
+    # linear in dw, up to FP32 rounding
+    jg2 = g.lin_apply(-2.0 * dw)
+    for q, k in enumerate(FIELDS):
+        assert rel(jg2[q], -2.0 * jg[q]) < 1e-5, k
+
+
+def _cases():
+    per = W.rising_drop(32, 32, eps=0.04)
+    per["grid"] = grid_(32, 32, 1, 1)
+    per["params"] = dict(per["params"], inv_Fr=0.0)
+    return {
+        "capillary_32x64": W.capillary(),
+        "drop_32x64": W.rising_drop(32, 64, eps=0.04),
+        "drop_40x24_ragged": W.rising_drop(40, 24, eps=0.05, radius=0.2),
+        "periodic_box_32x32": per,
+    }
+
+
+@pytest.mark.parametrize("name", list(_cases()))
+def test_mixed_step_matches_fp64_oracle(name):
+    cfg = _cases()[name]
+    say("mixed step parity", name)
+    opts = W.default_opts(1e-10)
+    g = Q.Solver(cfg["grid"], cfg["params"], mixed(opts))
+    o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+    m0, e0 = g.mass(), g.energy()
+    for step in range(2):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (step, k, rel(a[k], b[k], 1e-9))
+        st = g.stats()
+        assert max(st["res"]) <= 1e-10
+        say(name, "step", step, "outer iterations", st["vcycles"], "oracle V-cycles", o.stats()[0])
+        m1 = g.mass()
+        assert np.abs(m1 - m0).max() <= 1e-8 * np.abs(m0).max()
+        e1 = g.energy()
+        assert np.allclose(e1, o.energy(), rtol=1e-6, atol=1e-12)
+        assert e1[0] <= e0[0] + 1e-12
+        m0, e0 = m1, e1
+
+
+def test_mixed_full_size_rising_drop():
+    """256 x 512 rising droplet, three steps in mixed precision and in FP64 on
+    the GPU (the FP64 path is the one pinned to the oracle); the oracle's own
+    residual at the mixed solution of the first step"""
+    cfg = W.rising_drop()
+    say("mixed full size", cfg["name"])
+    opts = W.default_opts(1e-8)
+    gm = Q.Solver(cfg["grid"], cfg["params"], mixed(opts))
+    gd = Q.Solver(cfg["grid"], cfg["params"], opts)
+    for s in (gm, gd):
+        s.set_state(cfg["state"]["c"])
+    m0 = gm.mass()
+    for step in range(3):
+        assert gm.step(cfg["dt"]) == Q.OK
+        assert gd.step(cfg["dt"]) == Q.OK
+        if step == 0:
+            s = gm.get_state()
+            o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+            o.set_time_n_and_iterate(dict(c=cfg["state"]["c"]), s, cfg["dt"])
+            _, no = o.residual()
+            assert no.max() <= 2e-8, no
+        say("step", step, "mixed outer", gm.stats()["vcycles"], "fp64 V-cycles", gd.stats()["vcycles"])
+    a, b = gm.get_state(), gd.get_state()
+    for k in FIELDS:
+        assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (k, rel(a[k], b[k], 1e-9))
+    assert np.abs(gm.mass() - m0).max() <= 1e-8 * np.abs(m0).max()
+    assert abs(gm.energy()[0] - gd.energy()[0]) <= 1e-6 * abs(gd.energy()[0])
+
+
+def test_mixed_rejects_fp64_only_phases():
+    cfg = W.rising_drop(16, 32, eps=0.08)
+    g = Q.Solver(cfg["grid"], cfg["params"], mixed(W.default_opts()))
+    g.set_state(cfg["state"]["c"])
+    g.begin_step(cfg["dt"])
+    with pytest.raises(Q.QnschError):
+        g.halfsweep(0)
+    d = Q.Solver(cfg["grid"], cfg["params"], W.default_opts())
+    d.set_state(cfg["state"]["c"])
+    d.begin_step(cfg["dt"])
+    with pytest.raises(Q.QnschError):
+        d.lin_apply(np.zeros((5, 32, 16)))
+    assert Q.footprint(cfg["grid"], mixed(W.default_opts())) > 0

@@ -38,13 +38,18 @@ def alone(cfg, nsteps, opts):
 
 
 def test_served_results_equal_alone():
+    """FP64 and mixed-precision requests of several shapes in one server, the
+    list submitted twice through three slots (so that contexts are recycled):
+    every result bit-identical to the same request run alone"""
     say("serving: alone vs mix")
-    opts = W.default_opts(1e-10)
-    cases = mix()
+    fp64 = W.default_opts(1e-10)
+    mixed = dict(fp64, precision=Q.MIXED)
+    cases = mix() * 2
+    opts = [mixed if k % 2 else fp64 for k in range(len(mix()))] * 2
     nsteps = 3
-    ref = [alone(c, nsteps, opts) for c in cases]
-    srv = Q.Server(hbm_budget=8 << 30, max_slots=16)
-    ids = [srv.submit(c["grid"], c["params"], opts, c["state"]["c"], nsteps, c["dt"]) for c in cases]
+    ref = [alone(c, nsteps, o) for c, o in zip(cases, opts)]
+    srv = Q.Server(hbm_budget=8 << 30, max_slots=3)
+    ids = [srv.submit(c["grid"], c["params"], o, c["state"]["c"], nsteps, c["dt"]) for c, o in zip(cases, opts)]
     left = len(ids)
     for _ in range(100000):
         left = srv.progress(64)
@@ -62,7 +67,8 @@ def test_served_results_equal_alone():
     s = srv.stats()
     say("serving stats", s)
     assert s["steps"] == nsteps * len(cases)
-    assert s["launches"] < sum(ref_steps for ref_steps in [nsteps * 200]) * len(cases)
+    assert s["launches"] < nsteps * 200 * len(cases)
+    assert s["contexts_created"] < len(cases)  # the second round reuses contexts
 
 
 def test_admission_by_budget_and_failure_isolation():
