@@ -156,6 +156,26 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
     }
 }
 
+// reload of the fields a sweep changes (the unknowns and rho(c)) into a tile
+// that tile_load filled before; the time-n fields stay
+__device__ __forceinline__ void tile_refresh(const Phys &P, const View &L, const Tile &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        if (i > L.m1 + 1 || j > L.m2 + 1) continue;
+        double *s = T.s + e;
+        const double c = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_C * n] = c;
+        s[T_MU * n] = ldc(L.mu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_P * n] = ldc(L.p, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_U * n] = ldu(L.u, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_V * n] = ldv(L.v, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[T_RS * n] = rho_of(P, c);
+    }
+}
+
 // --------------------------------------------------------------------------
 // Lane pairs.  Each cell (or box) is handled by two adjacent lanes: lane 0
 // takes every x-direction contribution, lane 1 the same code on transposed
@@ -192,8 +212,16 @@ __device__ __forceinline__ Ax make_ax(const V &L, const TT &T, int i, int j, int
     return a;
 }
 
-__device__ __forceinline__ double other(double x) { return __shfl_xor(x, 1, 64); }
-__device__ __forceinline__ float other(float x) { return __shfl_xor(x, 1, 64); }
+// value of the partner lane (lane ^ 1): a DPP quad permutation [1,0,3,2]
+// within the wave's registers, no LDS round trip
+__device__ __forceinline__ int other(int x) { return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ float other(float x) { return __int_as_float(other(__float_as_int(x))); }
+__device__ __forceinline__ double other(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = other((int)(b & 0xffffffffll)), hi = other((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 
 // element-indexed tile read
 template <typename R> __device__ __forceinline__ R tq(const TileT<R> &T, int f, int e) { return T.s[f * T.W * T.H + e]; }
@@ -400,7 +428,7 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     const double gp = P.inv_M * ih;
     // exchange: the pair now holds the x rows (lane 0) and the y rows (lane 1)
     const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
-    const int o_hlo = __shfl_xor((int)hlo, 1, 64), o_hhi = __shfl_xor((int)hhi, 1, 64);
+    const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
     const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
     const double wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
     double A[5][5], b[5];

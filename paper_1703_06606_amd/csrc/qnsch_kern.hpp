@@ -15,9 +15,27 @@ namespace qn {
 
 #define BLK 256
 #define NRED 8 // reduction slots
-#define TX 32
-#define TY 16
+// Tile of cells per workgroup (one lane pair per cell of a colour).  16 x 16
+// cells and 256 lanes: small levels spread over more CUs, and two or three
+// workgroups share a CU on large ones (measured against 32 x 16 and 32 x 8).
+#ifndef QN_TX
+#define QN_TX 16
+#endif
+#ifndef QN_TY
+#define QN_TY 16
+#endif
+#define TX QN_TX
+#define TY QN_TY
 #define TBLK (TX * TY)
+// The FP64 finest-level half-sweep is register-limited to 2 waves per SIMD at
+// its natural allocation; asking for 3 costs a few spilled registers and buys
+// a third resident workgroup per CU (18 % faster on 512 x 2048).  Coarser
+// levels, which run few workgroups, keep the natural allocation.
+#ifndef QN_FINE_WAVES
+#define QN_FINE_WAVES 3
+#endif
+#define HS_ATTR __launch_bounds__(TBLK)
+#define FINE_ATTR __launch_bounds__(TBLK) __attribute__((amdgpu_waves_per_eu(QN_FINE_WAVES)))
 #define TILE_DOUBLES (T_NF * (TX + 3) * (TY + 3))
 #define NXCD 8
 #define MAXITEMS 64
@@ -124,13 +142,13 @@ __device__ __forceinline__ void halfsweep_body(const Items &it, int colour, doub
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
     if (i < L.m1 && j < L.m2) relax_pair(d.P, L, T, rhs_of(d), d.ub[par ^ 1], d.vb[par ^ 1], i, j, hlf, omega);
 }
-__global__ __launch_bounds__(TBLK) void k_halfsweep(Items it, int colour, double omega)
+__global__ HS_ATTR void k_halfsweep(Items it, int colour, double omega)
 {
     halfsweep_body(it, colour, omega);
 }
 // the same kernel under its own name for launches whose items are all finest
 // levels, so that profiles tell the finest level apart
-__global__ __launch_bounds__(TBLK) void k_halfsweep_fine(Items it, int colour, double omega)
+__global__ FINE_ATTR void k_halfsweep_fine(Items it, int colour, double omega)
 {
     halfsweep_body(it, colour, omega);
 }
@@ -184,7 +202,8 @@ __global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, doub
         double *uw, *vw;
         if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
         else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
-        tile_load(d.P, H, T);
+        if (s == 0) tile_load(d.P, H, T);
+        else tile_refresh(d.P, H, T);
         __syncthreads();
         for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
             const int pr = t >> 1;
@@ -223,9 +242,10 @@ __global__ __launch_bounds__(TBLK) void k_restrict(Items it)
     double rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sp = 0, sf = 0;
     const int fN = hlf ? T_V : T_U;
     const Rhs F = rhs_of(d);
-#pragma unroll
+    // not unrolled: four inlined residual evaluations would need 256 VGPRs
+#pragma unroll 1
     for (int b = 0; b < 2; b++)
-#pragma unroll
+#pragma unroll 1
         for (int a = 0; a < 2; a++) {
             const int i = 2 * I + a, j = 2 * J + b;
             double xc, xm, xp, xf;

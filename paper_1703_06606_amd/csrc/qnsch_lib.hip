@@ -7,6 +7,7 @@
 // level, then run FAS V-cycles (red-black CH point Newton + Vanka box
 // smoothing, residual restriction, coarse-grid correction) until every
 // per-equation residual norm is below tol.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -242,7 +243,7 @@ static int prof_tag(int kind, const std::vector<std::pair<qnsch_ctx *, int>> &pa
     return 2 * kind + (part[0].second == 0 ? 0 : 1);
 }
 
-static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end)
+static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stamped = false)
 {
     if (!end) {
         if ((size_t)(2 * x->prof_used + 2) > x->pev.size())
@@ -253,9 +254,11 @@ static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end)
             }
         if ((size_t)x->prof_used + 1 > x->ptag.size()) x->ptag.resize(x->prof_used + 64);
         x->ptag[x->prof_used] = tag;
-        HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
+        // a launch that carries the events itself records nothing here
+        if (!(x->prof == 1 && (tag == 2 * OP_HS || tag == 2 * OP_MXHS)))
+            HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
     } else {
-        HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
+        if (!stamped) HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
         x->prof_used++;
     }
     return QNSCH_OK;
@@ -275,19 +278,29 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         for (auto &pe : part) add_item(W, pe.first, kind, pe.second);
         const double omega = x0->opt.vanka_omega;
         const int tag = prof_tag(kind, part);
+        // half-sweeps timed alone (mode 1) take the kernel's own start and end
+        // timestamps; other timed launches are bracketed by event records
+        const bool stamp = tag >= 0 && (kind == OP_HS || kind == OP_MXHS) && part[0].first->prof == 1;
         int rc;
         if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, false))) return rc;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (stamp) {
+            qnsch_ctx *x = part[0].first;
+            e0 = x->pev[2 * x->prof_used];
+            e1 = x->pev[2 * x->prof_used + 1];
+        }
         switch (kind) {
         case OP_HS:
         case OP_MXHS: {
+            const dim3 gr(W.blocks), bl(TBLK);
             if (kind == OP_MXHS) {
                 if (W.all_fine)
-                    hipLaunchKernelGGL(k_mx_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, (float)omega);
-                else hipLaunchKernelGGL(k_mx_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, (float)omega);
+                    hipExtLaunchKernelGGL(k_mx_halfsweep_fine, gr, bl, 0, s, e0, e1, 0, W.it, colour, (float)omega);
+                else hipExtLaunchKernelGGL(k_mx_halfsweep, gr, bl, 0, s, e0, e1, 0, W.it, colour, (float)omega);
             } else if (W.all_fine) {
-                hipLaunchKernelGGL(k_halfsweep_fine, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
+                hipExtLaunchKernelGGL(k_halfsweep_fine, gr, bl, 0, s, e0, e1, 0, W.it, colour, omega);
             } else {
-                hipLaunchKernelGGL(k_halfsweep, dim3(W.blocks), dim3(TBLK), 0, s, W.it, colour, omega);
+                hipExtLaunchKernelGGL(k_halfsweep, gr, bl, 0, s, e0, e1, 0, W.it, colour, omega);
             }
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
@@ -337,7 +350,7 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         }
         default: break;
         }
-        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, true))) return rc;
+        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, true, stamp))) return rc;
         hipError_t err = hipGetLastError();
         if (err != hipSuccess) {
             x0->err = std::string("kernel launch: ") + hipGetErrorString(err);

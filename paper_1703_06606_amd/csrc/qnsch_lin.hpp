@@ -93,6 +93,28 @@ __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const
     }
 }
 
+// reload of the corrections (and the density change they induce) into a
+// tile that ltile_load filled before; the linearisation point and time-n
+// fields stay
+__device__ __forceinline__ void ltile_refresh(const PhysF &P, const LView &L, const TileF &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        if (i > L.m1 + 1 || j > L.m2 + 1) continue;
+        float *s = T.s + e;
+        const float dc = ldc(L.dc, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        const float rs = s[L_RS * n];
+        s[L_DC * n] = dc;
+        s[L_MU * n] = ldc(L.dmu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_P * n] = ldc(L.dp, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_U * n] = ldu(L.du, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_V * n] = ldv(L.dv, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        s[L_DRS * n] = -P.alpha * rs * rs * dc;
+    }
+}
+
 // one axis of the linearised cell equations at element e: the linear terms
 // applied to the corrections, the linearised gradient-energy and
 // capillary-divergence terms (dG, dL), and the values at c^ that the local
@@ -287,7 +309,7 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
     const float vis = (4.0f / 3.0f) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0f;
     const float gp = P.inv_M * ih;
     const float o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
-    const int o_hlo = __shfl_xor((int)hlo, 1, 64), o_hhi = __shfl_xor((int)hhi, 1, 64);
+    const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
     const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
     const float wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
     float A[5][5], b[5];

@@ -51,12 +51,12 @@ __device__ __forceinline__ void mx_halfsweep_body(const Items &it, int colour, f
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
     if (i < L.m1 && j < L.m2) lrelax_pair(d.Pf, L, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, hlf, omega);
 }
-__global__ __launch_bounds__(TBLK) void k_mx_halfsweep(Items it, int colour, float omega)
+__global__ HS_ATTR void k_mx_halfsweep(Items it, int colour, float omega)
 {
     mx_halfsweep_body(it, colour, omega);
 }
 // finest-level launches under their own name (profiles)
-__global__ __launch_bounds__(TBLK) void k_mx_halfsweep_fine(Items it, int colour, float omega)
+__global__ HS_ATTR void k_mx_halfsweep_fine(Items it, int colour, float omega)
 {
     mx_halfsweep_body(it, colour, omega);
 }
@@ -194,7 +194,8 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(Items it, int sweeps, f
         float *uw, *vw;
         if (s & 1) { H.du = uB; H.dv = vB; uw = uA; vw = vA; }
         else { H.du = uA; H.dv = vA; uw = uB; vw = vB; }
-        ltile_load(d.Pf, H, T);
+        if (s == 0) ltile_load(d.Pf, H, T);
+        else ltile_refresh(d.Pf, H, T);
         __syncthreads();
         for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
             const int pr = t >> 1;
