@@ -177,15 +177,15 @@ def run_mixed(steps, tol):
     return out
 
 
-def run_served(n, nsteps, tol, seq_steps):
+def run_served(n, nsteps, tol, seq_steps, lanes):
     """the request stream through the server (mixed precision), and the same
     requests one after another alone (FP64 and mixed) on a sample of steps"""
     reqs = W.serving_requests(n=n, nsteps=nsteps)
     mixed = dict(W.default_opts(tol), precision=Q.MIXED)
     fp64 = W.default_opts(tol)
     # sequential baselines: every request alone, seq_steps steps each
-    seq = {}
-    for name, opts in (("fp64", fp64), ("mixed", mixed)):
+    seq = {"fp64": float("nan"), "mixed": float("nan")}
+    for name, opts in (("fp64", fp64), ("mixed", mixed)) if seq_steps else ():
         note("serving: sequential baseline", name)
         cs, t = 0.0, 0.0
         for r in reqs:
@@ -202,7 +202,7 @@ def run_served(n, nsteps, tol, seq_steps):
             del g
         seq[name] = cs / t
     note("serving: %d requests through the server" % n)
-    srv = Q.Server(hbm_budget=64 << 30, max_slots=n)
+    srv = Q.Server(hbm_budget=64 << 30, max_slots=n, lanes=lanes)
     t0 = time.perf_counter()
     k = 0
     while True:
@@ -219,6 +219,7 @@ def run_served(n, nsteps, tol, seq_steps):
     s = srv.stats()
     return {"workload": "%d rising-droplet requests, sizes 64x128..512x1024, Poisson 20/s, %d steps each, mixed "
                         "precision, tol %g" % (n, nsteps, tol),
+            "lanes": lanes,
             "cell_steps_per_s": s["cell_steps_per_s"], "p50_step_ms": s["p50_ms"], "p99_step_ms": s["p99_ms"],
             "wall_s": s["wall_s"], "steps": int(s["steps"]), "launches": int(s["launches"]),
             "contexts_created": int(s["contexts_created"]),
@@ -227,6 +228,70 @@ def run_served(n, nsteps, tol, seq_steps):
             "sequential_sample": "each request alone, %d steps from its initial state" % seq_steps,
             "speedup_vs_sequential_fp64": s["cell_steps_per_s"] / seq["fp64"],
             "speedup_vs_sequential_mixed": s["cell_steps_per_s"] / seq["mixed"]}
+
+
+def run_served_at_scale(nbig, big, nsteps, tol, lanes):
+    """nbig periodic drop boxes of big x big cells submitted at once, with a
+    Poisson background stream of 256 x 256 boxes while they run, through the
+    server in mixed precision; the plain-FP64 sequential baseline is each kind
+    of request alone (one big box for 2 steps, one background box for 5)"""
+    bigs, bg = W.serving_at_scale(nbig=nbig, big=big, nsteps=nsteps)
+    mixed = dict(W.default_opts(tol), precision=Q.MIXED)
+    fp64 = W.default_opts(tol)
+    seq = {}
+    for name, r, k in (("big", bigs[0], 2), ("background", next(W.serving_at_scale(1, 64, nsteps)[1]), 5)):
+        w = r["work"]
+        g = Q.Solver(w["grid"], w["params"], fp64)
+        g.set_state(w["state"]["c"])
+        g.step(w["dt"])
+        g.set_state(w["state"]["c"])
+        g.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            g.step(w["dt"])
+        g.synchronize()
+        seq[name] = w["grid"]["m1"] * w["grid"]["m2"] * k / (time.perf_counter() - t0)
+        del g
+    note("serving at scale: %d boxes of %dx%d with a background stream" % (nbig, big, big))
+    srv = Q.Server(hbm_budget=128 << 30, max_slots=nbig + 64, lanes=lanes)
+    ids_big = [srv.submit(r["work"]["grid"], r["work"]["params"], mixed, r["work"]["state"]["c"], r["nsteps"],
+                          r["work"]["dt"]) for r in bigs]
+    ids_bg, shapes = [], {}
+    nxt = next(bg)
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while nxt["arrival"] <= now:
+            w = nxt["work"]
+            ids_bg.append(srv.submit(w["grid"], w["params"], mixed, w["state"]["c"], nxt["nsteps"], w["dt"]))
+            nxt = next(bg)
+        srv.progress(32)
+        if all(srv.poll(i)[0] == 2 for i in ids_big):
+            break
+    # let the background requests already admitted finish; stop arrivals
+    while srv.progress(32) > 0:
+        pass
+    s = srv.stats()
+    rb = [srv.result(i) for i in ids_big]
+    rg = [srv.result(i) for i in ids_bg]
+    big_cells = big * big * nsteps * nbig
+    bg_cells = sum(256 * 256 * nsteps for _ in rg)
+    seq_s = big_cells / seq["big"] + bg_cells / seq["background"]
+    return {"workload": "%d periodic %dx%d boxes with 40 drops (density ratio 100) at t=0 + 256x256 5-drop boxes "
+                        "arriving Poisson 20/s, %d steps each, mixed precision, tol %g" % (nbig, big, big, nsteps, tol),
+            "lanes": lanes, "status_ok": all(r["status"] == Q.OK for r in rb + rg),
+            "cell_steps_per_s": s["cell_steps_per_s"], "wall_s": s["wall_s"], "steps": int(s["steps"]),
+            "p50_step_ms": s["p50_ms"], "p99_step_ms": s["p99_ms"],
+            "big_done_s": max(r["total_ms"] for r in rb) / 1e3,
+            "background_requests": len(rg),
+            "background_p50_total_ms": float(np.percentile([r["total_ms"] for r in rg], 50)) if rg else None,
+            "background_p99_total_ms": float(np.percentile([r["total_ms"] for r in rg], 99)) if rg else None,
+            "mass_drift_max": float(max(np.abs(r["mass"][-1] - r["mass"][0]).max() / np.abs(r["mass"][0]).max()
+                                        for r in rb + rg)),
+            "vcycles_per_step_big": float(np.mean([r["vcycles"].mean() for r in rb])),
+            "sequential_fp64_estimate_s": seq_s,
+            "speedup_vs_sequential_fp64": seq_s / s["wall_s"] if s["wall_s"] > 0 else None,
+            "sequential_sample": "one %dx%d box alone for 2 steps and one background box for 5, FP64" % (big, big)}
 
 
 def main():
@@ -238,6 +303,11 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=50)
+    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--no-seq", action="store_true", help="skip the sequential baselines of the served run")
+    ap.add_argument("--serve-scale", action="store_true", help="also run the serving-at-scale workload")
+    ap.add_argument("--scale-boxes", type=int, default=16)
+    ap.add_argument("--scale-size", type=int, default=2048)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -285,7 +355,10 @@ def main():
     if not args.no_mixed:
         out["mixed"] = run_mixed(args.mixed_steps, args.tol)
     if not args.no_serve:
-        out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=5)
+        out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=0 if args.no_seq else 5,
+                                   lanes=args.serve_lanes)
+    if args.serve_scale:
+        out["served_at_scale"] = run_served_at_scale(args.scale_boxes, args.scale_size, 20, args.tol, args.serve_lanes)
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, opts, float(np.mean(nv)))

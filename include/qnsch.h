@@ -157,6 +157,27 @@ int qnsch_mass(qnsch_ctx *ctx, double out[2]);
 /* Discrete energy of the current state (Theorem of sec. 6.1 with the norms of
  * App. A.7): out = {E, kinetic, gradient, bulk (double well), potential}. */
 int qnsch_energy(qnsch_ctx *ctx, double out[5]);
+/* Dissipation of the step just taken (Theorem of sec. 6.1, norms of App.
+ * A.7), from the new state and the time-n data of that step:
+ *   out[0] = dt/Re ||sqrt(mu) grad_d u||^2,  out[1] = dt/(3Re) ||sqrt(mu) div_d u||^2,
+ *   out[2] = dt/(M Pe) ||sqrt(m) grad_D mu_c||^2 (mu_c = mubar + alpha pbar),
+ *   out[3] = 1/2 ||sqrt(rho^n)(u^{n+1} - u^n)||^2;
+ * mu, m, rho at c^n; the vertex norm weights each vertex by a quarter of
+ * each adjacent cell.  With walls in y the energy law reads
+ * E^{n+1} - E^n + sum(out) = 0 at the converged solution.  QNSCH_EBUSY
+ * before the first step. */
+int qnsch_dissipation(qnsch_ctx *ctx, double out[4]);
+/* Physical diagnostics of the current state (sec. 8):
+ *   out[0] = V_c = sum(c v) / sum(c), v at the cell the mean of its south and
+ *            north faces (rising velocity of the c = 1 phase);
+ *   out[1] = h^2 sum c;  out[2] = max |div_d u|;  out[3] = ||div_d u||_{2,h};
+ *   out[4] / out[5] = highest / lowest height of a c = 1/2 crossing between
+ *            vertically adjacent cells (linear interpolation; the tips of
+ *            the rising and the falling fluid), NaN if none;
+ *   out[6] = highest crossing in the first column x = h/2 (the interface
+ *            height of a capillary wave at its crest), NaN if none;
+ *   out[7] = h^2 sum div_d u (zero with walls or periodic boundaries). */
+int qnsch_diagnostics(qnsch_ctx *ctx, double out[8]);
 int qnsch_stats(const qnsch_ctx *ctx, qnsch_step_stats *out);
 /* Block until all work of the context's stream has finished. */
 int qnsch_synchronize(qnsch_ctx *ctx);
@@ -200,10 +221,14 @@ typedef struct qnsch_server qnsch_server;
  * the server admits requests by this footprint. */
 size_t qnsch_footprint(const qnsch_grid *grid, const qnsch_opts *opts);
 
-/* hbm_budget: device bytes the admitted requests may hold together;
- * max_slots: most requests in flight; hip_stream: stream to run on (NULL =
- * default). */
-int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *hip_stream, qnsch_server **out);
+/* hbm_budget: device bytes the admitted requests may hold together (idle
+ * contexts kept for reuse count too and are released first when a new shape
+ * needs room); max_slots: most requests in flight; lanes: number of HIP
+ * streams the requests are spread over (1..16; each admitted request joins the
+ * least loaded lane and stays there; launches of different lanes overlap on
+ * the device); hip_stream: used as the first lane if not NULL (the others are
+ * created non-blocking). */
+int qnsch_server_create(size_t hbm_budget, int32_t max_slots, int32_t lanes, void *hip_stream, qnsch_server **out);
 void qnsch_server_destroy(qnsch_server *srv);
 const char *qnsch_server_last_error(const qnsch_server *srv);
 /* Queue a request; c0 (m1*m2, host) is copied.  QNSCH_ENOMEM if its footprint

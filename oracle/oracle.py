@@ -66,6 +66,7 @@ def lib():
         L.orc_mass.argtypes = [C.c_void_p, P]
         L.orc_energy.argtypes = [C.c_void_p, P]
         L.orc_dissipation.argtypes = [C.c_void_p, P]
+        L.orc_diagnostics.argtypes = [C.c_void_p, P]
         L.orc_num_unknowns.argtypes = [C.c_void_p]
         L.orc_dense.argtypes = [C.c_void_p, P, P]
         L.orc_add_unknowns.argtypes = [C.c_void_p, P]
@@ -156,6 +157,12 @@ class Oracle:
         out = np.zeros(4)
         lib().orc_dissipation(self.h, _ptr(out))
         return out
+
+    def diagnostics(self):
+        out = np.zeros(8)
+        lib().orc_diagnostics(self.h, _ptr(out))
+        return dict(zip(("V_c", "c_integral", "div_max", "div_l2", "y_top", "y_bottom", "y_col0", "div_integral"),
+                        out))
 
     def dense(self, jacobian=True):
         n = lib().orc_num_unknowns(self.h)

@@ -947,6 +947,50 @@ void orc_dissipation(orc_ctx *o, double out[4])
     out[3] = 0.5 * h2 * g4;
 }
 
+/* Physical diagnostics of the current state (sec. 8), by their definitions:
+ *   out[0] rising velocity V_c = int(v c) / int(c), v at a cell centre the
+ *          mean of the cell's two v faces;
+ *   out[1] int(c);  out[2] max |div_d u|;  out[3] ||div_d u||_{2,h};
+ *   out[4], out[5] highest and lowest height where c crosses 1/2 between two
+ *          vertically adjacent cells (linear interpolation between centres;
+ *          across a periodic y boundary too), NaN if none;
+ *   out[6] highest such crossing in the first column, NaN if none;
+ *   out[7] int(div_d u). */
+void orc_diagnostics(orc_ctx *o, double out[8])
+{
+    Level *L = &o->lev[0];
+    double h = L->h, cv = 0.0, cs = 0.0, dmax = 0.0, d2 = 0.0, dsum = 0.0;
+    double top = -INFINITY, bot = INFINITY, col0 = -INFINITY;
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++) {
+            double c = creal(cellv(o, L, F_C, i, j));
+            double vc = 0.5 * (creal(vv(o, L, F_V, i, j)) + creal(vv(o, L, F_V, i, j + 1)));
+            cv += c * vc;
+            cs += c;
+            double div = creal(d_x(o, L, F_U, i, j)) + creal(d_y(o, L, F_V, i, j));
+            if (fabs(div) > dmax) dmax = fabs(div);
+            d2 += div * div;
+            dsum += div;
+            if (j + 1 < L->m2 || o->g.bcy == ORC_PERIODIC) {
+                double c2 = creal(cellv(o, L, F_C, i, j + 1));
+                if ((c - 0.5) * (c2 - 0.5) < 0.0) {
+                    double y = (j + 0.5) * h + h * (0.5 - c) / (c2 - c);
+                    if (y > top) top = y;
+                    if (y < bot) bot = y;
+                    if (i == 0 && y > col0) col0 = y;
+                }
+            }
+        }
+    out[0] = cs != 0.0 ? cv / cs : NAN;
+    out[1] = h * h * cs;
+    out[2] = dmax;
+    out[3] = sqrt(h * h * d2);
+    out[4] = isinf(top) ? NAN : top;
+    out[5] = isinf(bot) ? NAN : bot;
+    out[6] = isinf(col0) ? NAN : col0;
+    out[7] = h * h * dsum;
+}
+
 /* ------------------------------------------------------------------------- */
 /* dense pieces for small grids and unit tests                                 */
 

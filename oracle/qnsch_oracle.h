@@ -50,6 +50,7 @@ int orc_stats(const orc_ctx *, double *hist);
 void orc_mass(orc_ctx *, double out[2]);
 void orc_energy(orc_ctx *, double out[5]);
 void orc_dissipation(orc_ctx *, double out[4]);
+void orc_diagnostics(orc_ctx *, double out[8]);
 int orc_num_unknowns(const orc_ctx *);
 int orc_dense(orc_ctx *, double *Nvec, double *Jmat);
 void orc_add_unknowns(orc_ctx *, const double *dx);

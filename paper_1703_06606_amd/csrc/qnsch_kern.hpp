@@ -462,9 +462,138 @@ __global__ __launch_bounds__(BLK) void k_mass_energy(Items it)
     block_sum_store(v, d.partials + (size_t)b * NRED);
 }
 
+// Dissipation of the step just taken (Theorem of sec. 6.1 with the norms of
+// App. A.7), from the new iterate and the time-n data still held by the
+// level: partial sums, per cell, of
+//   0: mu(c^n) (|d_x u|^2 + |d_y v|^2 + 1/4 sum over the 4 corners of
+//      |calD_y u|^2 + |calD_x v|^2)        (viscous gradient norm)
+//   1: mu(c^n) (d_x u + d_y v)^2           (viscous divergence norm)
+//   2: A m(c^n) |D mu_c|^2 on the west and south faces, mu_c = mubar + alpha pbar
+//   3: A rho^n |u - u^n|^2 on the west and south faces (unknown faces only)
+// One thread per cell.
+__global__ __launch_bounds__(BLK) void k_dissipation(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const View L = view_of(d, it.par[k]);
+    const Phys &P = d.P;
+    const int b = (int)blockIdx.x - it.start[k];
+    const int t = b * BLK + threadIdx.x;
+    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (t < L.m1 * L.m2) {
+        const int j = t / L.m1, i = t - j * L.m1;
+        const int m1 = L.m1, m2 = L.m2, pt = L.pitch, bx = L.bcx, by = L.bcy;
+        const double ih = L.inv_h;
+        auto U = [&](int a, int c) { return ldu(L.u, m1, m2, pt, bx, by, a, c); };
+        auto V = [&](int a, int c) { return ldv(L.v, m1, m2, pt, bx, by, a, c); };
+        auto CN = [&](int a, int c) { return ldc(L.cn, m1, m2, pt, bx, by, a, c); };
+        const double mv = visc_of(P, CN(i, j));
+        const double dxu = (U(i + 1, j) - U(i, j)) * ih, dyv = (V(i, j + 1) - V(i, j)) * ih;
+        double sv = 0.0;
+#pragma unroll
+        for (int a = 0; a <= 1; a++)
+#pragma unroll
+            for (int c = 0; c <= 1; c++) {
+                const double dyu = (U(i + a, j + c) - U(i + a, j + c - 1)) * ih;
+                const double dxv = (V(i + a, j + c) - V(i + a - 1, j + c)) * ih;
+                sv += dyu * dyu + dxv * dxv;
+            }
+        v[0] = mv * (dxu * dxu + dyv * dyv + 0.25 * sv);
+        v[1] = mv * (dxu + dyv) * (dxu + dyv);
+        const double c0 = CN(i, j), mob0 = mob_of(P, c0), r0 = rho_of(P, c0);
+        const double mu0 = ldc(L.mu, m1, m2, pt, bx, by, i, j), p0 = ldc(L.p, m1, m2, pt, bx, by, i, j);
+        const size_t q = (size_t)j * pt + i;
+        if (bx || i > 0) {
+            const double cw = CN(i - 1, j);
+            const double g = (mu0 - ldc(L.mu, m1, m2, pt, bx, by, i - 1, j)) * ih
+                           + P.alpha * (p0 - ldc(L.p, m1, m2, pt, bx, by, i - 1, j)) * ih;
+            v[2] += 0.5 * (mob0 + mob_of(P, cw)) * g * g;
+            const double du = L.u[q] - L.un[q];
+            v[3] += 0.5 * (r0 + rho_of(P, cw)) * du * du;
+        }
+        if (by || j > 0) {
+            const double cs = CN(i, j - 1);
+            const double g = (mu0 - ldc(L.mu, m1, m2, pt, bx, by, i, j - 1)) * ih
+                           + P.alpha * (p0 - ldc(L.p, m1, m2, pt, bx, by, i, j - 1)) * ih;
+            v[2] += 0.5 * (mob0 + mob_of(P, cs)) * g * g;
+            const double dv = L.v[q] - L.vn[q];
+            v[3] += 0.5 * (r0 + rho_of(P, cs)) * dv * dv;
+        }
+    }
+    block_sum_store(v, d.partials + (size_t)b * NRED);
+}
+
+// Physical diagnostics of the current state (sec. 8), per-block partials:
+//   0: sum c v_cell (v_cell = mean of the cell's south and north faces)
+//   1: sum c
+//   2: max |div_d u|            3: sum (div_d u)^2          4: sum div_d u
+//   5: max height of a c = 1/2 crossing between vertically adjacent cells
+//      (linear interpolation; walls in y: interior pairs only)
+//   6: min height of such a crossing
+//   7: max height of a crossing in the first column (x = h/2)
+// (5-7 hold -inf / +inf where there is none.)
+#define DIAG_NONE 1e300
+__global__ __launch_bounds__(BLK) void k_diagnostics(Items it)
+{
+    __shared__ double sh[BLK / 64][NRED];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const View L = view_of(d, it.par[k]);
+    const int b = (int)blockIdx.x - it.start[k];
+    const int t = b * BLK + threadIdx.x;
+    double v[NRED] = { 0, 0, 0, 0, 0, -DIAG_NONE, DIAG_NONE, -DIAG_NONE };
+    if (t < L.m1 * L.m2) {
+        const int j = t / L.m1, i = t - j * L.m1;
+        const int m1 = L.m1, m2 = L.m2, pt = L.pitch, bx = L.bcx, by = L.bcy;
+        const size_t q = (size_t)j * pt + i;
+        const double c = L.c[q];
+        const double vs = ldv(L.v, m1, m2, pt, bx, by, i, j), vn = ldv(L.v, m1, m2, pt, bx, by, i, j + 1);
+        const double us = ldu(L.u, m1, m2, pt, bx, by, i, j), ue = ldu(L.u, m1, m2, pt, bx, by, i + 1, j);
+        v[0] = c * 0.5 * (vs + vn);
+        v[1] = c;
+        const double dv = (ue - us + vn - vs) * L.inv_h;
+        v[2] = fabs(dv);
+        v[3] = dv * dv;
+        v[4] = dv;
+        if (by || j + 1 < m2) {
+            const double cn = L.c[(size_t)(j + 1 < m2 ? j + 1 : 0) * pt + i];
+            if ((c - 0.5) * (cn - 0.5) < 0.0) {
+                const double y = (j + 0.5 + (0.5 - c) / (cn - c)) * d.h;
+                v[5] = y;
+                v[6] = y;
+                if (i == 0) v[7] = y;
+            }
+        }
+    }
+    // wave and block reductions: sums for 0, 1, 3, 4; max for 2, 5, 7; min for 6
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+        for (int r = 0; r < NRED; r++) {
+            const double w = __shfl_xor(v[r], o, 64);
+            v[r] = (r == 2 || r == 5 || r == 7) ? fmax(v[r], w) : (r == 6 ? fmin(v[r], w) : v[r] + w);
+        }
+    }
+    const int wv = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0)
+#pragma unroll
+        for (int r = 0; r < NRED; r++) sh[wv][r] = v[r];
+    __syncthreads();
+    if (threadIdx.x < NRED) {
+        const int r = threadIdx.x;
+        double acc = sh[0][r];
+        for (int ww = 1; ww < BLK / 64; ww++) {
+            const double w = sh[ww][r];
+            acc = (r == 2 || r == 5 || r == 7) ? fmax(acc, w) : (r == 6 ? fmin(acc, w) : acc + w);
+        }
+        d.partials[(size_t)b * NRED + r] = acc;
+    }
+}
+
 // fixed-order sum of a simulation's partials (one workgroup per item); the
 // norms become sqrt(h^2 sum r^2); written to device and pinned host memory.
-// mode 0: residual reduction (5 norms, sum p, bad count); 1: plain sums.
+// mode 0: residual reduction (5 norms, sum p, bad count); 1: plain sums;
+// 2: the diagnostics slots (sum, max or min per slot as in k_diagnostics).
 __global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
 {
     __shared__ double sh[BLK][NRED];
@@ -472,17 +601,22 @@ __global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
     if (k >= it.n) return;
     const Desc &d = *it.d[k];
     const int nblk = it.tx[k];
-    double s[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    // slot q combines by sum, or (diagnostics) by max (op 1) or min (op 2)
+    auto op = [&](int q) { return mode != 2 ? 0 : (q == 2 || q == 5 || q == 7) ? 1 : (q == 6 ? 2 : 0); };
+    auto comb = [&](int q, double a, double b) { const int o = op(q); return o == 0 ? a + b : (o == 1 ? fmax(a, b) : fmin(a, b)); };
+    double s[NRED];
+#pragma unroll
+    for (int q = 0; q < NRED; q++) s[q] = op(q) == 0 ? 0.0 : (op(q) == 1 ? -DIAG_NONE : DIAG_NONE);
     for (int b = threadIdx.x; b < nblk; b += BLK)
 #pragma unroll
-        for (int q = 0; q < NRED; q++) s[q] += d.partials[(size_t)b * NRED + q];
+        for (int q = 0; q < NRED; q++) s[q] = comb(q, s[q], d.partials[(size_t)b * NRED + q]);
 #pragma unroll
     for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] = s[q];
     __syncthreads();
     for (int o = BLK / 2; o > 0; o >>= 1) {
         if ((int)threadIdx.x < o)
 #pragma unroll
-            for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] += sh[threadIdx.x + o][q];
+            for (int q = 0; q < NRED; q++) sh[threadIdx.x][q] = comb(q, sh[threadIdx.x][q], sh[threadIdx.x + o][q]);
         __syncthreads();
     }
     if (threadIdx.x < NRED) {

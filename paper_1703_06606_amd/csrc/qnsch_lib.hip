@@ -32,7 +32,9 @@ using namespace qn;
 enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, OP_COARSE, OP_PROLONG, OP_STEPEND,
               OP_RESTORE,
               // mixed precision: FP32 correction cycle, FP64 update
-              OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE, NOPS };
+              OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE,
+              // diagnostics of the current state
+              OP_DISSIP, OP_DIAG, NOPS };
 struct Op {
     int kind, level, colour;
 };
@@ -348,6 +350,18 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
             break;
         }
+        case OP_DISSIP: {
+            hipLaunchKernelGGL(k_dissipation, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            ItemList F = finalize_list(part, OP_DISSIP);
+            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
+            break;
+        }
+        case OP_DIAG: {
+            hipLaunchKernelGGL(k_diagnostics, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            ItemList F = finalize_list(part, OP_DIAG);
+            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 2);
+            break;
+        }
         default: break;
         }
         if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, true, stamp))) return rc;
@@ -373,9 +387,23 @@ static int run_ops(qnsch_ctx *x, const std::vector<Op> &prog)
 }
 
 // wait for the context's stream (the reduced values are then in red_host)
+// wait for the context's stream (the reduced values are then in red_host).
+// The host polls the completion of an event for a while before blocking: a
+// step waits here once per V-cycle, and a blocking wait wakes up tens of
+// microseconds late, during which the device has nothing queued.
 static int read_red(qnsch_ctx *x)
 {
-    HIPCHK(x, hipStreamSynchronize(x->s));
+    HIPCHK(x, hipEventRecord(x->ev, x->s));
+    const auto t0 = std::chrono::steady_clock::now();
+    for (;;) {
+        const hipError_t q = hipEventQuery(x->ev);
+        if (q == hipSuccess) break;
+        if (q != hipErrorNotReady) HIPCHK(x, q);
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(50)) {
+            HIPCHK(x, hipEventSynchronize(x->ev));
+            break;
+        }
+    }
     return prof_collect(x);
 }
 
@@ -904,6 +932,41 @@ int qnsch_energy(qnsch_ctx *x, double out[5])
     return QNSCH_OK;
 }
 
+int qnsch_dissipation(qnsch_ctx *x, double out[4])
+{
+    if (!x || !out) return QNSCH_EINVAL;
+    if (!(x->dt > 0)) { x->err = "dissipation before any step"; return QNSCH_EBUSY; }
+    int rc;
+    if ((rc = run_ops(x, { { OP_DISSIP, 0, 0 } }))) return rc;
+    if ((rc = read_red(x))) return rc;
+    const double h2 = x->L[0].h * x->L[0].h;
+    const qnsch_params &p = x->prm;
+    out[0] = x->dt / p.Re * h2 * x->red_host[0];
+    out[1] = x->dt / (3.0 * p.Re) * h2 * x->red_host[1];
+    out[2] = x->dt / (p.M * p.Pe) * h2 * x->red_host[2];
+    out[3] = 0.5 * h2 * x->red_host[3];
+    return QNSCH_OK;
+}
+
+int qnsch_diagnostics(qnsch_ctx *x, double out[8])
+{
+    if (!x || !out) return QNSCH_EINVAL;
+    int rc;
+    if ((rc = run_ops(x, { { OP_DIAG, 0, 0 } }))) return rc;
+    if ((rc = read_red(x))) return rc;
+    const double h = x->L[0].h, *r = x->red_host;
+    const double nan = std::nan("");
+    out[0] = r[1] != 0.0 ? r[0] / r[1] : nan;
+    out[1] = h * h * r[1];
+    out[2] = r[2];
+    out[3] = sqrt(h * h * r[3]);
+    out[4] = r[5] > -1e299 ? r[5] : nan;
+    out[5] = r[6] < 1e299 ? r[6] : nan;
+    out[6] = r[7] > -1e299 ? r[7] : nan;
+    out[7] = h * h * r[4];
+    return QNSCH_OK;
+}
+
 int qnsch_stats(const qnsch_ctx *x, qnsch_step_stats *out)
 {
     if (!x || !out) return QNSCH_EINVAL;
@@ -999,13 +1062,16 @@ int qnsch_copy_probe(size_t n, int reps, double out[2])
 // continuous-batching server
 //
 // Requests (independent simulations) are admitted first come, first served
-// while a slot is free and their device footprint fits the budget.  Every
-// running request holds a programme of operations (the phases of its current
-// step, then of its next V-cycle once its residual is known).  Each tick the
-// scheduler takes the largest set of ready requests whose next operations are
-// of the same kind (any level) and runs them as ONE work-list launch; the
-// requests left waiting catch up with the next largest set, which keeps the
-// population in step and the launches full.  Host round trips happen only at
+// while a slot is free and their device footprint fits the budget, each into
+// one of several lanes (HIP streams; the least loaded).  Every running request
+// holds a programme of operations (the phases of its current step, then of
+// its next V-cycle once its residual is known).  Each tick the scheduler takes,
+// in every lane, the largest set of ready requests whose next operations are
+// of the same kind (any level) and runs them as ONE work-list launch on that
+// lane's stream; the requests left waiting catch up with the next largest
+// set, which keeps a lane's population in step and its launches full, while
+// the lanes overlap on the device (one lane's single-workgroup coarsest
+// solves leave most CUs to the others).  Host round trips happen only at
 // residual and step-end reductions (events, no stream drain).  Contexts are
 // recycled by shape: a finished request's final state is downloaded through
 // pinned staging and its device arrays serve the next request of that shape,
@@ -1026,6 +1092,7 @@ struct Req {
     qnsch_ctx *x = nullptr;
     int state = RQ_QUEUED, status = QNSCH_OK;
     size_t foot = 0;
+    int lane = 0;
     int step = 0, vcycles = 0;
     std::vector<Op> prog; // operations still to issue, from pc on
     size_t pc = 0;
@@ -1047,7 +1114,9 @@ typedef std::chrono::steady_clock Clock;
 } // namespace
 
 struct qnsch_server {
-    hipStream_t s = nullptr;
+    std::vector<hipStream_t> lanes; // streams the requests run on
+    std::vector<int> lane_load;     // running requests per lane
+    std::vector<bool> own;          // streams created by the server
     size_t budget = 0, used = 0, pooled = 0; // bytes of running / idle contexts
     int max_slots = 0;
     uint64_t next_id = 1;
@@ -1087,17 +1156,20 @@ static int admit(qnsch_server *S, Req *r)
     const Shape key = shape_of(r->g, r->o.precision);
     qnsch_ctx *x = nullptr;
     int rc = QNSCH_OK;
+    r->lane = (int)(std::min_element(S->lane_load.begin(), S->lane_load.end()) - S->lane_load.begin());
+    hipStream_t st = S->lanes[r->lane];
     auto it = S->pool.find(key);
     if (it != S->pool.end()) {
         x = it->second;
         S->pool.erase(it);
         S->pooled -= x->footprint;
+        x->s = st; // its earlier work has completed (its download was observed)
         x->opt = r->o;
         set_params(x, &r->p);
         for (int l = 0; l < x->nlev; l++) x->L[l].cur = 0;
         x->in_step = 0;
         memset(&x->st, 0, sizeof(x->st));
-        if (hipMemsetAsync(x->arena, 0, x->arena_bytes, S->s) != hipSuccess) rc = QNSCH_EDEVICE;
+        if (hipMemsetAsync(x->arena, 0, x->arena_bytes, st) != hipSuccess) rc = QNSCH_EDEVICE;
     } else {
         while (!S->pool.empty() && S->used + S->pooled + r->foot > S->budget) {
             auto v = S->pool.begin();
@@ -1107,7 +1179,7 @@ static int admit(qnsch_server *S, Req *r)
         }
         x = new qnsch_ctx();
         S->created++;
-        rc = ctx_init(x, &r->g, &r->p, &r->o, S->s);
+        rc = ctx_init(x, &r->g, &r->p, &r->o, st);
         const size_t n = (size_t)r->g.m1 * r->g.m2;
         if (!rc && hipHostMalloc((void **)&x->stage, 5 * n * sizeof(double), hipHostMallocDefault) != hipSuccess)
             rc = QNSCH_ENOMEM;
@@ -1126,7 +1198,7 @@ static int admit(qnsch_server *S, Req *r)
         const DLev &D = x->L[0];
         memcpy(x->stage, r->c0.data(), (size_t)D.m1 * D.m2 * sizeof(double));
         if (hipMemcpy2DAsync(x->hd[0].c, D.pitch * sizeof(double), x->stage, D.m1 * sizeof(double),
-                             D.m1 * sizeof(double), D.m2, hipMemcpyHostToDevice, S->s) != hipSuccess)
+                             D.m1 * sizeof(double), D.m2, hipMemcpyHostToDevice, st) != hipSuccess)
             rc = QNSCH_EDEVICE;
     }
     r->x = x;
@@ -1150,8 +1222,8 @@ static void begin_finish(qnsch_server *S, Req *r, int status)
     bool ok = true;
     for (int q = 0; q < 5; q++)
         ok = ok && hipMemcpy2DAsync(x->stage + q * n, D.m1 * sizeof(double), src[q], D.pitch * sizeof(double),
-                                    D.m1 * sizeof(double), D.m2, hipMemcpyDeviceToHost, S->s) == hipSuccess;
-    ok = ok && hipEventRecord(x->ev, S->s) == hipSuccess;
+                                    D.m1 * sizeof(double), D.m2, hipMemcpyDeviceToHost, x->s) == hipSuccess;
+    ok = ok && hipEventRecord(x->ev, x->s) == hipSuccess;
     if (!ok && r->status == QNSCH_OK) r->status = QNSCH_EDEVICE;
     r->wait = W_DOWNLOAD;
     S->host_finish_ms += ms_between(t0, Clock::now());
@@ -1168,6 +1240,7 @@ static void complete_finish(qnsch_server *S, Req *r)
     r->t_done = Clock::now();
     S->t_last = r->t_done;
     S->used -= r->foot;
+    S->lane_load[r->lane]--;
     S->pool.insert({ shape_of(r->g, r->o.precision), x });
     S->pooled += x->footprint;
     r->x = nullptr;
@@ -1216,13 +1289,27 @@ size_t qnsch_footprint(const qnsch_grid *g, const qnsch_opts *o)
     return g ? footprint_of(g, o ? o->precision : QNSCH_FP64) : 0;
 }
 
-int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *stream, qnsch_server **out)
+int qnsch_server_create(size_t hbm_budget, int32_t max_slots, int32_t lanes, void *stream, qnsch_server **out)
 {
-    if (!out || max_slots < 1 || hbm_budget == 0) return QNSCH_EINVAL;
+    if (!out || max_slots < 1 || hbm_budget == 0 || lanes < 1 || lanes > 16) return QNSCH_EINVAL;
+    *out = nullptr;
     qnsch_server *S = new qnsch_server();
     S->budget = hbm_budget;
     S->max_slots = max_slots;
-    S->s = (hipStream_t)stream;
+    for (int l = 0; l < lanes; l++) {
+        hipStream_t st = nullptr;
+        bool own = true;
+        if (l == 0 && stream) {
+            st = (hipStream_t)stream;
+            own = false;
+        } else if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            qnsch_server_destroy(S);
+            return QNSCH_EDEVICE;
+        }
+        S->lanes.push_back(st);
+        S->own.push_back(own);
+        S->lane_load.push_back(0);
+    }
     *out = S;
     return QNSCH_OK;
 }
@@ -1230,12 +1317,14 @@ int qnsch_server_create(size_t hbm_budget, int32_t max_slots, void *stream, qnsc
 void qnsch_server_destroy(qnsch_server *S)
 {
     if (!S) return;
-    (void)hipStreamSynchronize(S->s);
+    for (hipStream_t st : S->lanes) (void)hipStreamSynchronize(st);
     for (auto &kv : S->all) {
         if (kv.second->x) qnsch_destroy(kv.second->x);
         delete kv.second;
     }
     for (auto &kv : S->pool) qnsch_destroy(kv.second);
+    for (size_t l = 0; l < S->lanes.size(); l++)
+        if (S->own[l]) (void)hipStreamDestroy(S->lanes[l]);
     delete S;
 }
 
@@ -1287,6 +1376,7 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
                 continue;
             }
             S->used += r->foot;
+            S->lane_load[r->lane]++;
             r->state = RQ_RUNNING;
             start_step(r);
             S->active.push_back(r);
@@ -1298,16 +1388,44 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
             else after_reduction(S, r);
         }
         S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
-        // the largest set of ready requests with the same next operation
-        // (kind, colour, coarse sweeps, relaxation factor)
+        // per lane, the largest set of ready requests with the same next
+        // operation (kind, colour, coarse sweeps, relaxation factor)
         typedef std::tuple<int, int, int, double> Key;
-        std::map<Key, std::vector<Req *>> groups;
-        for (Req *r : S->active) {
-            if (r->wait != W_NONE || r->pc >= r->prog.size()) continue;
-            const Op &o = r->prog[r->pc];
-            groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega)].push_back(r);
+        bool launched = false;
+        for (size_t lane = 0; lane < S->lanes.size(); lane++) {
+            std::map<Key, std::vector<Req *>> groups;
+            for (Req *r : S->active) {
+                if (r->lane != (int)lane || r->wait != W_NONE || r->pc >= r->prog.size()) continue;
+                const Op &o = r->prog[r->pc];
+                groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega)].push_back(r);
+            }
+            if (groups.empty()) continue;
+            auto best = groups.begin();
+            for (auto g = groups.begin(); g != groups.end(); ++g)
+                if (g->second.size() > best->second.size()) best = g;
+            std::vector<std::pair<qnsch_ctx *, int>> items;
+            for (Req *r : best->second) items.push_back({ r->x, r->prog[r->pc].level });
+            const int kind = std::get<0>(best->first);
+            hipStream_t st = S->lanes[lane];
+            int rc = launch_op(kind, std::get<1>(best->first), items, st);
+            if (rc) {
+                S->err = items[0].first->err;
+                return rc;
+            }
+            launched = true;
+            S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
+            for (Req *r : best->second) {
+                r->pc++;
+                if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
+                    r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
+                    (void)hipEventRecord(r->x->ev, st);
+                } else if (kind == OP_RESTORE) {
+                    begin_finish(S, r, r->status);
+                }
+            }
         }
-        if (groups.empty()) {
+        S->ticks++;
+        if (!launched) {
             if (S->active.empty()) break; // nothing running (queue empty or waiting for budget)
             // everyone waits for an event: block on the oldest one
             const auto t0 = Clock::now();
@@ -1317,31 +1435,7 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
                     break;
                 }
             S->host_wait_ms += ms_between(t0, Clock::now());
-            S->ticks++;
-            continue;
         }
-        auto best = groups.begin();
-        for (auto g = groups.begin(); g != groups.end(); ++g)
-            if (g->second.size() > best->second.size()) best = g;
-        std::vector<std::pair<qnsch_ctx *, int>> items;
-        for (Req *r : best->second) items.push_back({ r->x, r->prog[r->pc].level });
-        const int kind = std::get<0>(best->first);
-        int rc = launch_op(kind, std::get<1>(best->first), items, S->s);
-        if (rc) {
-            S->err = items[0].first->err;
-            return rc;
-        }
-        S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
-        for (Req *r : best->second) {
-            r->pc++;
-            if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
-                r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
-                (void)hipEventRecord(r->x->ev, S->s);
-            } else if (kind == OP_RESTORE) {
-                begin_finish(S, r, r->status);
-            }
-        }
-        S->ticks++;
     }
     return (int)(S->queue.size() + S->active.size());
 }

@@ -19,7 +19,8 @@ FP64, MIXED = 0, 1
 # every exported symbol declared in include/qnsch.h
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
            "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
-           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy", "qnsch_stats",
+           "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy",
+           "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
            "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats")
@@ -28,7 +29,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
 # operation classes of qnsch_profile_breakdown, in the library's numbering
 OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
             "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
-            "mx_prolong", "mx_update")
+            "mx_prolong", "mx_update", "dissipation", "diagnostics")
 
 
 class QnschError(RuntimeError):
@@ -88,6 +89,8 @@ def lib():
         L.qnsch_lin_apply.argtypes = [vp, P, P]
         L.qnsch_mass.argtypes = [vp, P]
         L.qnsch_energy.argtypes = [vp, P]
+        L.qnsch_dissipation.argtypes = [vp, P]
+        L.qnsch_diagnostics.argtypes = [vp, P]
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.qnsch_synchronize.argtypes = [vp]
         L.qnsch_profile.argtypes = [vp, C.c_int]
@@ -96,7 +99,7 @@ def lib():
         L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
         L.qnsch_footprint.argtypes = [C.POINTER(Grid), C.POINTER(Opts)]
         L.qnsch_footprint.restype = C.c_size_t
-        L.qnsch_server_create.argtypes = [C.c_size_t, C.c_int32, vp, C.POINTER(vp)]
+        L.qnsch_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
         L.qnsch_server_destroy.argtypes = [vp]
         L.qnsch_server_destroy.restype = None
         L.qnsch_server_last_error.argtypes = [vp]
@@ -218,6 +221,20 @@ class Solver:
         self._chk(lib().qnsch_energy(self.h, _ptr(out)))
         return out
 
+    def dissipation(self):
+        out = np.zeros(4)
+        self._chk(lib().qnsch_dissipation(self.h, _ptr(out)))
+        return out
+
+    def diagnostics(self):
+        """dict: rising velocity V_c, integral of c, max and L2 norm of the
+        discrete divergence, highest/lowest c = 1/2 crossing, crossing in
+        the first column, integral of the divergence"""
+        out = np.zeros(8)
+        self._chk(lib().qnsch_diagnostics(self.h, _ptr(out)))
+        return dict(zip(("V_c", "c_integral", "div_max", "div_l2", "y_top", "y_bottom", "y_col0", "div_integral"),
+                        out))
+
     def stats(self):
         s = StepStats()
         self._chk(lib().qnsch_stats(self.h, C.byref(s)))
@@ -282,10 +299,10 @@ def footprint(grid, opts=None):
 class Server:
     """Continuous-batching server of many simulations (qnsch_server_*)."""
 
-    def __init__(self, hbm_budget, max_slots, stream=None):
+    def __init__(self, hbm_budget, max_slots, lanes=2, stream=None):
         h = C.c_void_p()
-        rc = lib().qnsch_server_create(int(hbm_budget), int(max_slots), C.c_void_p(stream) if stream else None,
-                                       C.byref(h))
+        rc = lib().qnsch_server_create(int(hbm_budget), int(max_slots), int(lanes),
+                                       C.c_void_p(stream) if stream else None, C.byref(h))
         if rc != OK:
             raise QnschError(rc, "qnsch_server_create failed")
         self.h = h

@@ -139,3 +139,101 @@ def serving_requests(n=64, rate_hz=20.0, seed=6606, nsteps=50, dt=5e-4,
         w["name"] = "request_%d_%dx%d" % (k, m1, m2)
         out.append(dict(arrival=t, work=w, nsteps=nsteps))
     return out
+
+
+def _periodic_drops(m, ndrops, r_lo, r_hi, eps, rng):
+    """c on an m x m periodic unit box: the maximum over ndrops circular drops
+    (fluid 1) of the tanh profile, radii U[r_lo, r_hi], centres uniform,
+    accepted only if the periodic distance to every earlier drop is at least
+    the sum of the radii plus 4 eps"""
+    centres, radii = [], []
+    while len(centres) < ndrops:
+        x, y, R = rng.uniform(), rng.uniform(), rng.uniform(r_lo, r_hi)
+        ok = True
+        for (a, b), Rb in zip(centres, radii):
+            dx = min(abs(x - a), 1 - abs(x - a))
+            dy = min(abs(y - b), 1 - abs(y - b))
+            if math.hypot(dx, dy) < R + Rb + 4 * eps:
+                ok = False
+                break
+        if ok:
+            centres.append((x, y))
+            radii.append(R)
+    # each profile is evaluated within R + 30 eps of its centre (beyond that it
+    # is below 1e-9 and taken as 0)
+    h = 1.0 / m
+    c = np.zeros((m, m))
+    for (a, b), R in zip(centres, radii):
+        w = int(math.ceil((R + 30 * eps) / h)) + 1
+        ia = int(a / h)
+        jb = int(b / h)
+        ii = np.arange(ia - w, ia + w + 1) if 2 * w + 1 < m else np.arange(m)
+        jj = np.arange(jb - w, jb + w + 1) if 2 * w + 1 < m else np.arange(m)
+        xi, yj = (ii + 0.5) * h, (jj + 0.5) * h
+        dx = np.abs(xi - a)
+        dx = np.minimum(dx % 1.0, 1 - dx % 1.0)
+        dy = np.abs(yj - b)
+        dy = np.minimum(dy % 1.0, 1 - dy % 1.0)
+        r = np.sqrt(dx[None, :] ** 2 + dy[:, None] ** 2)
+        prof = 0.5 * (1.0 - np.tanh((r - R) / (2.0 * math.sqrt(2.0) * eps)))
+        sub = np.ix_(jj % m, ii % m)
+        c[sub] = np.maximum(c[sub], prof)
+    return c
+
+
+def drops_box(m, ndrops, r_lo, r_hi, eps, seed, rho_ratio=100.0, visc_ratio=50.0, Re=500.0, We=50.0,
+              inv_Fr=1.0, dt=1e-4):
+    """Light drops (fluid 1, c = 1) in a heavy fluid on the periodic unit box
+    (seeded rejection sampling, see _periodic_drops); gravity along -y in
+    buoyancy form: the force is measured against the mean density of the box,
+    which the scheme conserves, so that a fully periodic box has no net body
+    force."""
+    grid = dict(m1=m, m2=m, Lx=1.0, Ly=1.0, bcx=PERIODIC, bcy=PERIODIC, levels=0)
+    c = _periodic_drops(m, ndrops, r_lo, r_hi, eps, np.random.default_rng(seed))
+    par = params(1.0, rho_ratio, 1.0, visc_ratio, Re=Re, We=We, inv_Fr=inv_Fr, eps=eps)
+    rho = par["rho1"] * par["rho2"] / ((par["rho2"] - par["rho1"]) * c + par["rho1"])
+    par["rho_ref"] = float(rho.mean())
+    return dict(name="drops_box_%dx%d_%d" % (m, m, ndrops), grid=grid, params=par, dt=dt, state=dict(c=c))
+
+
+def serving_at_scale(nbig=16, big=2048, nsteps=20, bg_rate_hz=20.0, bg_size=256, duration_s=None, seed_bg=6607):
+    """nbig periodic boxes of big x big cells with 40 drops each (R U[0.02,
+    0.05], eps = 0.002, seeds 1000 + k) submitted at time 0, and a background
+    Poisson stream of bg_size x bg_size boxes with 5 drops (R U[0.05, 0.1],
+    eps = 0.01) at bg_rate_hz; all nsteps steps of dt = 1e-4, density ratio
+    100, viscosity ratio 50, Re = 500, We = 50, 1/Fr = 1.  Background arrivals
+    cover duration_s seconds (None: the caller stops submitting when the big
+    runs are done).  Returns (big requests, background request generator)."""
+    bigs = [dict(arrival=0.0, work=drops_box(big, 40, 0.02, 0.05, 0.002, 1000 + k), nsteps=nsteps)
+            for k in range(nbig)]
+    for k, r in enumerate(bigs):
+        r["work"]["name"] = "box_%d_%dx%d" % (k, big, big)
+
+    def background():
+        rng = np.random.default_rng(seed_bg)
+        t, k = 0.0, 0
+        while duration_s is None or t < duration_s:
+            t += rng.exponential(1.0 / bg_rate_hz)
+            w = drops_box(bg_size, 5, 0.05, 0.1, 0.01, int(rng.integers(1 << 30)))
+            w["name"] = "bg_%d_%dx%d" % (k, bg_size, bg_size)
+            yield dict(arrival=t, work=w, nsteps=nsteps)
+            k += 1
+
+    return bigs, background()
+
+
+def convergence_case(m, amp=0.2, eps=0.1, T=0.25):
+    """Cauchy convergence study of sec. 9 on the unit square with walls:
+    c = 0.5 + amp (cos 2 pi x + cos 2 pi y) (bounded away from the density
+    pole, unlike the printed cos 2 pi x + cos 2 pi y), everything else zero,
+    density ratio 3, equal viscosities, Re = We = 10, gravity 1/Fr = 1, M = eps,
+    Pe = 1/eps; time step dt = (1/16)(16/m)^2 as in the printed schedule, run
+    to time T."""
+    h = 1.0 / m
+    grid = dict(m1=m, m2=m, Lx=1.0, Ly=1.0, bcx=WALL, bcy=WALL, levels=0)
+    par = params(1.0, 3.0, 1.0, 1.0, Re=10.0, We=10.0, inv_Fr=1.0, eps=eps)
+    X, Y = _centres(m, m, h)
+    c = 0.5 + amp * (np.cos(2 * np.pi * X) + np.cos(2 * np.pi * Y))
+    dt = (1.0 / 16.0) * (16.0 / m) ** 2
+    return dict(name="convergence_%dx%d" % (m, m), grid=grid, params=par, dt=dt, nsteps=int(round(T / dt)),
+                state=dict(c=c))

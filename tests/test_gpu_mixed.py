@@ -153,3 +153,43 @@ def test_mixed_rejects_fp64_only_phases():
     with pytest.raises(Q.QnschError):
         d.lin_apply(np.zeros((5, 32, 16)))
     assert Q.footprint(cfg["grid"], mixed(W.default_opts())) > 0
+
+
+def test_mixed_outer_factor_is_mesh_independent():
+    """The mixed outer iteration contracts like the FP64 V-cycle, at every
+    size from 32x64 to 256x512 (rising droplet, eps = 0.02), and takes at most
+    one outer iteration more than FP64 V-cycles"""
+    for m1 in (32, 64, 128, 256):
+        cfg = W.rising_drop(m1, 2 * m1, eps=0.02)
+        n = {}
+        for prec in (Q.FP64, Q.MIXED):
+            g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(1e-10), precision=prec))
+            g.set_state(cfg["state"]["c"])
+            assert g.step(cfg["dt"]) == Q.OK
+            st = g.stats()
+            n[prec] = st["vcycles"]
+            mf = (max(st["res"]) / max(st["res0"])) ** (1.0 / st["vcycles"])
+            assert mf < 0.3, (m1, prec, mf)
+        say("mesh", m1, "fp64 V-cycles", n[Q.FP64], "mixed outer iterations", n[Q.MIXED])
+        assert n[Q.MIXED] <= n[Q.FP64] + 1
+
+
+def test_mixed_periodic_drops_box_density_ratio_100():
+    """Mixed precision on the fully periodic box with drops at density ratio
+    100 (buoyancy form of gravity): converged steps against the FP64 oracle,
+    mass drift below 1e-8"""
+    cfg = W.drops_box(32, 3, 0.08, 0.15, 0.03, 11)
+    say("mixed step parity", cfg["name"])
+    opts = W.default_opts(1e-10)
+    g = Q.Solver(cfg["grid"], cfg["params"], mixed(opts))
+    o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+    m0 = g.mass()
+    for step in range(3):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (step, k, rel(a[k], b[k], 1e-9))
+        assert np.abs(g.mass() - m0).max() <= 1e-8 * np.abs(m0).max()

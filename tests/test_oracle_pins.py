@@ -409,6 +409,100 @@ def test_hydrostatic_closed_form():
 
 
 # ---------------------------------------------------------------------------
+# discrete operators on periodic Fourier modes (App. A.2): round-off exact
+
+@pytest.mark.parametrize("k", [1, 3, 5])
+def test_fourier_mode_closed_forms(k):
+    """Equal densities (alpha = 0), uniform c = 1/2 at both times (so rho, the
+    mobility m and the viscosity are constants, g(c, c) = f(1/2) = 0 and the
+    time derivatives vanish), periodic box.  Then single equations reduce to
+    single difference operators whose action on cos(kappa x) is known in
+    closed form:
+      div u            d_x of u = cos(kappa x_face): -(2/h) sin(kappa h/2) sin(kappa x_cell)
+      -L_m(mubar)/Pe   with mubar = cos(kappa x): (4 m / (Pe h^2)) sin^2(kappa h/2) cos(kappa x)
+      chemical eq.     rho mubar (all other terms vanish)
+      -visc Lap u/Re   with u = cos(kappa y_cell), time-n u equal: (4 visc/(Re h^2)) sin^2(kappa h/2) cos(kappa y)"""
+    m = 16
+    grid = grid_(m, m, 1, 1)
+    P = par_O1(rho1=1.7, rho2=1.7, visc1=1.3, visc2=1.3, inv_Fr=0.0)
+    h = 1.0 / m
+    kap = 2 * math.pi * k
+    xc = (np.arange(m) + 0.5) * h
+    xf = np.arange(m) * h
+    X = np.broadcast_to(xc[None, :], (m, m))
+    Xf = np.broadcast_to(xf[None, :], (m, m))
+    Y = np.broadcast_to(xc[:, None], (m, m))
+    half = np.full((m, m), 0.5)
+    zero = np.zeros((m, m))
+    mob = math.sqrt(0.0625 + P["mob_reg"])
+    s2 = math.sin(kap * h / 2) ** 2
+
+    def N(w):
+        o = mk(grid, P)
+        wn = dict(c=half, mu=zero, p=zero, u=w.get("un", zero), v=zero)
+        o.set_time_n_and_iterate(wn, dict(c=half, mu=w.get("mu", zero), p=zero, u=w.get("u", zero), v=zero), 0.1)
+        r, _ = o.residual()
+        return -r  # N = -r on the finest level (no right-hand side)
+
+    # divergence of a face field
+    u = np.cos(kap * Xf)
+    n = N(dict(u=u, un=zero))
+    assert np.abs(n[2] - (-(2 / h) * math.sin(kap * h / 2) * np.sin(kap * X))).max() < 1e-10
+    # mobility Laplacian in the phase equation; chemical equation = rho mubar
+    mu = np.cos(kap * X)
+    n = N(dict(mu=mu))
+    assert np.abs(n[0] - 4 * mob / (P["Pe"] * h * h) * s2 * mu).max() < 1e-9
+    assert np.abs(n[1] - 1.7 * mu).max() < 1e-12
+    # viscous operator on a shear flow (advection and divergence terms vanish)
+    u = np.cos(kap * Y)
+    n = N(dict(u=u, un=u))
+    assert np.abs(n[3] - 4 * 1.3 / (P["Re"] * h * h) * s2 * u).max() < 1e-9
+    assert np.abs(n[4]).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# physical diagnostics of sec. 8: closed forms
+
+def test_physical_diagnostics_closed_forms():
+    m = 16
+    h = 1.0 / m
+    xc = (np.arange(m) + 0.5) * h
+    xf = np.arange(m) * h
+    P = par_O1()
+    # uniform velocity in a periodic box: V_c is that velocity, no divergence
+    o = mk(grid_(m, m, 1, 1), P)
+    c = 0.3 + 0.2 * np.random.default_rng(5).uniform(size=(m, m))
+    o.set_state(c, u=np.full((m, m), 0.7), v=np.full((m, m), -0.45))
+    d = o.diagnostics()
+    assert d["V_c"] == pytest.approx(-0.45, rel=1e-14)
+    assert d["c_integral"] == pytest.approx(c.sum() * h * h, rel=1e-14)
+    assert d["div_max"] < 1e-13 and d["div_l2"] < 1e-13
+    # walls: u = sin(pi x) on the faces; d_x u has the closed form of a
+    # difference quotient, and its integral telescopes to zero
+    o = mk(grid_(m, m, 0, 0), P)
+    u = np.broadcast_to(np.sin(np.pi * xf)[None, :], (m, m)).copy()
+    o.set_state(np.full((m, m), 0.5), u=u)
+    d = o.diagnostics()
+    div = (np.sin(np.pi * (xf + h)) - np.sin(np.pi * xf)) / h
+    assert d["div_max"] == pytest.approx(np.abs(div).max(), rel=1e-12)
+    assert d["div_l2"] == pytest.approx(math.sqrt(h * h * m * (div ** 2).sum()), rel=1e-12)
+    assert abs(d["div_integral"]) < 1e-13
+    # a phase field linear in y across the tilted line y = 0.4 + 0.1 x: the
+    # interpolated crossings lie exactly on it
+    o = mk(grid_(m, m, 0, 0), P)
+    Y = ((np.arange(m) + 0.5) * h)[:, None]
+    y0 = 0.4 + 0.1 * xc[None, :]
+    o.set_state(0.5 + 0.8 * (y0 - Y))
+    d = o.diagnostics()
+    assert d["y_top"] == pytest.approx(0.4 + 0.1 * xc[-1], rel=1e-13)
+    assert d["y_bottom"] == pytest.approx(0.4 + 0.1 * xc[0], rel=1e-13)
+    assert d["y_col0"] == pytest.approx(0.4 + 0.1 * xc[0], rel=1e-13)
+    # no crossing at all
+    o.set_state(np.full((m, m), 0.9))
+    assert math.isnan(o.diagnostics()["y_top"])
+
+
+# ---------------------------------------------------------------------------
 # diagnostics: closed forms
 
 def test_mass_energy_closed_forms():
@@ -599,6 +693,47 @@ def test_vcycle_contracts_and_is_deterministic():
         assert (mx[2:] / mx[1:-1] < 0.3).all()
     for k in FIELDS:
         assert np.array_equal(runs[0][0][k], runs[1][0][k])
+
+
+def test_periodic_box_buoyancy_conserves_mass():
+    """Fully periodic box, drops at density ratio 100, gravity measured
+    against the mean density: both component masses (Theorem of sec. 6.1) are
+    conserved to round-off over converged steps, and the mean density the
+    force is measured against is therefore constant"""
+    w = W.drops_box(32, 3, 0.08, 0.15, 0.03, 11)
+    o = mk(w["grid"], w["params"], W.default_opts(1e-10))
+    o.set_state(w["state"]["c"])
+    m0 = o.mass()
+    assert (m0.sum()) == pytest.approx(w["params"]["rho_ref"], rel=1e-12)  # unit box: total mass = mean density
+    for _ in range(2):
+        assert o.step(w["dt"]) == OR.OK
+        assert np.abs(o.mass() - m0).max() <= 1e-12 * np.abs(m0).max()
+
+
+def _mean_factor(hist):
+    """geometric mean of the per-cycle contraction of the largest residual
+    norm, from the first cycle on (the initial residual is dominated by the
+    time-step change, not by the multigrid error)"""
+    mx = hist.max(axis=1)
+    q = mx[2:] / mx[1:-1]
+    return float(np.exp(np.log(q).mean())), q
+
+
+def test_vcycle_factor_is_mesh_independent():
+    """The paper prints no iteration counts (parity unpinned for the factor
+    itself); what a multigrid must show is a factor below 1 that does not
+    degrade with h: capillary wave at 32x64 and 64x128, same physics."""
+    f = []
+    for m1 in (32, 64):
+        c = W.capillary(m1, 2 * m1, eps=0.02, levels=0)
+        o = mk(c["grid"], c["params"], W.default_opts(1e-11))
+        o.set_state(c["state"]["c"])
+        assert o.step(c["dt"]) == OR.OK
+        nv, hist = o.stats()
+        mf, q = _mean_factor(hist)
+        assert (q < 0.6).all(), q
+        f.append(mf)
+    assert max(f) < 0.35 and max(f) / min(f) < 2.0, f
 
 
 def test_failure_paths_leave_state_at_time_n():
