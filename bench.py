@@ -230,16 +230,17 @@ def run_served(n, nsteps, tol, seq_steps, lanes):
             "speedup_vs_sequential_mixed": s["cell_steps_per_s"] / seq["mixed"]}
 
 
-def run_served_at_scale(nbig, big, nsteps, tol, lanes):
+def run_served_at_scale(nbig, big, nsteps, tol, lanes, max_vcycles):
     """nbig periodic drop boxes of big x big cells submitted at once, with a
     Poisson background stream of 256 x 256 boxes while they run, through the
     server in mixed precision; the plain-FP64 sequential baseline is each kind
     of request alone (one big box for 2 steps, one background box for 5)"""
     bigs, bg = W.serving_at_scale(nbig=nbig, big=big, nsteps=nsteps)
-    mixed = dict(W.default_opts(tol), precision=Q.MIXED)
-    fp64 = W.default_opts(tol)
+    mixed = dict(W.default_opts(tol), precision=Q.MIXED, max_vcycles=max_vcycles)
+    fp64 = dict(W.default_opts(tol), max_vcycles=max_vcycles)
     seq = {}
     for name, r, k in (("big", bigs[0], 2), ("background", next(W.serving_at_scale(1, 64, nsteps)[1]), 5)):
+        note("serving at scale: sequential FP64 baseline,", name)
         w = r["work"]
         g = Q.Solver(w["grid"], w["params"], fp64)
         g.set_state(w["state"]["c"])
@@ -278,7 +279,8 @@ def run_served_at_scale(nbig, big, nsteps, tol, lanes):
     bg_cells = sum(256 * 256 * nsteps for _ in rg)
     seq_s = big_cells / seq["big"] + bg_cells / seq["background"]
     return {"workload": "%d periodic %dx%d boxes with 40 drops (density ratio 100) at t=0 + 256x256 5-drop boxes "
-                        "arriving Poisson 20/s, %d steps each, mixed precision, tol %g" % (nbig, big, big, nsteps, tol),
+                        "arriving Poisson 20/s, %d steps each, mixed precision, tol %g, at most %d V-cycles"
+                        % (nbig, big, big, nsteps, tol, max_vcycles),
             "lanes": lanes, "status_ok": all(r["status"] == Q.OK for r in rb + rg),
             "cell_steps_per_s": s["cell_steps_per_s"], "wall_s": s["wall_s"], "steps": int(s["steps"]),
             "p50_step_ms": s["p50_ms"], "p99_step_ms": s["p99_ms"],
@@ -308,6 +310,8 @@ def main():
     ap.add_argument("--serve-scale", action="store_true", help="also run the serving-at-scale workload")
     ap.add_argument("--scale-boxes", type=int, default=16)
     ap.add_argument("--scale-size", type=int, default=2048)
+    ap.add_argument("--scale-steps", type=int, default=20)
+    ap.add_argument("--scale-max-vcycles", type=int, default=150)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -358,7 +362,8 @@ def main():
         out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=0 if args.no_seq else 5,
                                    lanes=args.serve_lanes)
     if args.serve_scale:
-        out["served_at_scale"] = run_served_at_scale(args.scale_boxes, args.scale_size, 20, args.tol, args.serve_lanes)
+        out["served_at_scale"] = run_served_at_scale(args.scale_boxes, args.scale_size, args.scale_steps, args.tol,
+                                                     args.serve_lanes, args.scale_max_vcycles)
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(cfg, opts, float(np.mean(nv)))

@@ -126,9 +126,53 @@ typedef TileT<double> Tile;
 
 // cooperative load of a tile (all threads of the block take part; the caller
 // synchronises afterwards).  The level may be in global memory or in LDS.
+// true if every element of the tile (halo included) is an interior element
+// of the level for every field, so that no boundary image is involved: cells
+// and faces 1 .. m-1 in each direction
+__device__ __forceinline__ bool tile_inner(int m1, int m2, int i0, int j0, int W, int H)
+{
+    return i0 >= 2 && j0 >= 2 && i0 + W - 2 <= m1 - 1 && j0 + H - 2 <= m2 - 1;
+}
+
 __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Tile &T)
 {
     const int n = T.W * T.H;
+    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)blockDim.x) {
+        // no boundary images: plain strided loads, the two elements of a
+        // thread loaded together (the second one clamped to a valid element
+        // and stored only if it exists) so that all loads are in flight at once
+        const int e0 = threadIdx.x, e1r = threadIdx.x + blockDim.x, e1 = e1r < n ? e1r : n - 1;
+        auto at = [&](int e) {
+            const int b = e / T.W, a = e - b * T.W;
+            return (size_t)(T.j0 - 1 + b) * L.pitch + (T.i0 - 1 + a);
+        };
+        const size_t q0 = at(e0 < n ? e0 : n - 1), q1 = at(e1);
+        double v0[8], v1[8];
+        const double *src[8] = { L.c, L.mu, L.p, L.u, L.v, L.cn, L.un, L.vn };
+#pragma unroll
+        for (int f = 0; f < 8; f++) {
+            v0[f] = src[f][q0];
+            v1[f] = src[f][q1];
+        }
+        auto put = [&](int e, const double *v) {
+            double *s = T.s + e;
+            s[T_C * n] = v[0];
+            s[T_MU * n] = v[1];
+            s[T_P * n] = v[2];
+            s[T_U * n] = v[3];
+            s[T_V * n] = v[4];
+            s[T_CN * n] = v[5];
+            s[T_UN * n] = v[6];
+            s[T_VN * n] = v[7];
+            s[T_RN * n] = rho_of(P, v[5]);
+            s[T_MV * n] = visc_of(P, v[5]);
+            s[T_MOB * n] = mob_of(P, v[5]);
+            s[T_RS * n] = rho_of(P, v[0]);
+        };
+        if (e0 < n) put(e0, v0);
+        if (e1r < n) put(e1r, v1);
+        return;
+    }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;

@@ -64,6 +64,44 @@ __device__ __forceinline__ float mobf(const PhysF &P, float c)
 __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const TileF &T)
 {
     const int n = T.W * T.H;
+    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)blockDim.x) {
+        // no boundary images: plain strided loads, a thread's two elements
+        // loaded together (see tile_load)
+        const int e0 = threadIdx.x, e1r = threadIdx.x + blockDim.x, e1 = e1r < n ? e1r : n - 1;
+        auto at = [&](int e) {
+            const int b = e / T.W, a = e - b * T.W;
+            return (size_t)(T.j0 - 1 + b) * L.pitch + (T.i0 - 1 + a);
+        };
+        const size_t q0 = at(e0 < n ? e0 : n - 1), q1 = at(e1);
+        float v0[9], v1[9];
+        const float *src[9] = { L.c, L.dc, L.dmu, L.dp, L.du, L.dv, L.cn, L.un, L.vn };
+#pragma unroll
+        for (int f = 0; f < 9; f++) {
+            v0[f] = src[f][q0];
+            v1[f] = src[f][q1];
+        }
+        auto put = [&](int e, const float *v) {
+            float *s = T.s + e;
+            s[L_C * n] = v[0];
+            s[L_DC * n] = v[1];
+            s[L_MU * n] = v[2];
+            s[L_P * n] = v[3];
+            s[L_U * n] = v[4];
+            s[L_V * n] = v[5];
+            s[L_CN * n] = v[6];
+            s[L_UN * n] = v[7];
+            s[L_VN * n] = v[8];
+            s[L_RN * n] = rhof(P, v[6]);
+            s[L_MV * n] = viscf(P, v[6]);
+            s[L_MOB * n] = mobf(P, v[6]);
+            const float rs = rhof(P, v[0]);
+            s[L_RS * n] = rs;
+            s[L_DRS * n] = -P.alpha * rs * rs * v[1];
+        };
+        if (e0 < n) put(e0, v0);
+        if (e1r < n) put(e1r, v1);
+        return;
+    }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
