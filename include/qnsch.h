@@ -12,7 +12,8 @@
  * App. A.5-A.6 and the boundary conditions of App. A.4): given the state at
  * time n, find w = (c, mubar, pbar, u, v) at time n+1 with N(w) = 0.  It is
  * solved by the nonlinear FAS multigrid of sec. 7.1 (pointwise Newton update of
- * (c, mubar), Vanka box update of (u, v, pbar), red-black order, V-cycles).
+ * (c, mubar) and Vanka box update of (u, v, pbar), or the two in one coupled
+ * box, red-black order, V-cycles).
  *
  * Precision.  QNSCH_FP64: every phase in FP64.  QNSCH_MIXED: defect
  * correction; the residual r = -N(w), the update w += delta, the stop test and
@@ -63,12 +64,22 @@ enum {
 
 enum { QNSCH_BC_WALL = 0, QNSCH_BC_PERIODIC = 1 };
 enum { QNSCH_FP64 = 0, QNSCH_MIXED = 1 };
+/* Smoother of the V-cycle (sec. 7.1).  SEGREGATED: the two steps of sec. 7.1,
+ * a pointwise Newton step on (c, mubar) of the cell, then the Vanka box of its
+ * four faces and pbar.  COUPLED (default): one Newton step on the seven
+ * unknowns of the cell (four faces, pbar, c, mubar) with the five cell and
+ * face equations plus the phase and chemical-potential equations of the cell;
+ * the faces and pbar take the vanka_omega-relaxed step, c and mubar the full
+ * one.  Both have the same fixed point, the solution of sec. 6.1; the coupled
+ * box keeps the V-cycle factor bounded under refinement at density ratios
+ * where the segregated one degrades. */
+enum { QNSCH_SMOOTH_SEGREGATED = 0, QNSCH_SMOOTH_COUPLED = 1 };
 
 typedef struct {
     int32_t m1, m2;     /* cells in x and y; both even, divisible by 2^levels */
     double Lx, Ly;      /* domain size; Lx/m1 must equal Ly/m2 */
     int32_t bc_x, bc_y; /* QNSCH_BC_WALL (no-slip u, Neumann c, mu, p) or PERIODIC */
-    int32_t levels;     /* multigrid levels; 0 = coarsen to a smallest dimension of 4 */
+    int32_t levels;     /* multigrid levels; 0 = coarsen while the coarsest level has > 32 cells */
 } qnsch_grid;
 
 /* Non-dimensional parameters of sec. 2.2; fluid 1 is c = 1 (rho(1) = rho1). */
@@ -91,6 +102,7 @@ typedef struct {
     int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black) */
     int32_t nu_coarse;   /* sweeps on the coarsest level */
     double vanka_omega;  /* relaxation factor of the box update (1 = exact box solve) */
+    int32_t smoother;    /* QNSCH_SMOOTH_COUPLED or QNSCH_SMOOTH_SEGREGATED */
 } qnsch_opts;
 
 typedef struct {
@@ -102,7 +114,8 @@ typedef struct {
 
 typedef struct qnsch_ctx qnsch_ctx;
 
-/* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 30 coarse sweeps, omega 1. */
+/* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 30 coarse sweeps, omega 1,
+ * coupled smoother. */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to

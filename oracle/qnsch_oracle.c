@@ -389,7 +389,7 @@ static void norms_level(const Level *L, double *r[NSTATE], double out[NSTATE])
 /* local solves                                                                */
 
 /* Gaussian elimination with partial pivoting on an n x n system, in place */
-static int gepp(int n, double A[5][5], double b[5])
+static int gepp(int n, double A[7][7], double b[7])
 {
     for (int k = 0; k < n; k++) {
         int piv = k;
@@ -427,7 +427,7 @@ static void unperturb(orc_ctx *o) { o->plev = NULL; o->pf = -1; o->ph = 0.0; o->
 static void ch_point(orc_ctx *o, Level *L, int i, int j)
 {
     size_t k = (size_t)j * L->m1 + i;
-    double J[5][5], b[5];
+    double J[7][7], b[7];
     int fl[2] = { F_C, F_MU };
     for (int col = 0; col < 2; col++) {
         perturb(o, L, fl[col], i, j);
@@ -446,10 +446,13 @@ static void ch_point(orc_ctx *o, Level *L, int i, int j)
  * two north-south faces and the pressure of the cell.  The box equations are
  * linear in these unknowns, so one Newton step with the exact (complex-step)
  * Jacobian is the exact box solve.  Velocities are read from the snapshot
- * (the field arrays) and the corrections are written to unew/vnew. */
+ * (the field arrays) and the corrections are written to unew/vnew.
+ * Coupled smoother (the default; a reading, see halfsweep): the cell's c and
+ * mubar join the box with the phase and chemical-potential equations of the
+ * cell, and one Newton step on the seven equations replaces step 1. */
 static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *vnew)
 {
-    int fld[5], ci[5], cj[5], n = 0;
+    int fld[7], ci[7], cj[7], n = 0;
     int ie = (i + 1 == L->m1) ? (o->g.bcx == ORC_PERIODIC ? 0 : -1) : i + 1;
     int jn = (j + 1 == L->m2) ? (o->g.bcy == ORC_PERIODIC ? 0 : -1) : j + 1;
     if (u_unknown(o, L, i)) { fld[n] = F_U; ci[n] = i; cj[n] = j; n++; }
@@ -457,21 +460,26 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
     if (v_unknown(o, L, j)) { fld[n] = F_V; ci[n] = i; cj[n] = j; n++; }
     if (jn >= 0 && v_unknown(o, L, jn)) { fld[n] = F_V; ci[n] = i; cj[n] = jn; n++; }
     fld[n] = F_P; ci[n] = i; cj[n] = j; n++;
-    double J[5][5], b[5];
+    if (o->o.smoother == ORC_SMOOTH_COUPLED) {
+        fld[n] = F_C; ci[n] = i; cj[n] = j; n++;
+        fld[n] = F_MU; ci[n] = i; cj[n] = j; n++;
+    }
+    double J[7][7], b[7];
     for (int col = 0; col < n; col++) {
         perturb(o, L, fld[col], ci[col], cj[col]);
         for (int row = 0; row < n; row++) {
             size_t kr = (size_t)cj[row] * L->m1 + ci[row];
             cx r;
-            /* the equation attached to each unknown: momentum at a face, mass at the cell */
-            if (fld[row] == F_U) r = res_u(o, L, ci[row], cj[row]);
-            else if (fld[row] == F_V) r = res_v(o, L, ci[row], cj[row]);
-            else r = res_p(o, L, ci[row], cj[row]);
+            /* the equation attached to each unknown: momentum at a face, mass,
+             * phase and chemical potential at the cell */
+            int rf;
+            if (fld[row] == F_U) { r = res_u(o, L, ci[row], cj[row]); rf = 3; }
+            else if (fld[row] == F_V) { r = res_v(o, L, ci[row], cj[row]); rf = 4; }
+            else if (fld[row] == F_C) { r = res_c(o, L, ci[row], cj[row]); rf = 0; }
+            else if (fld[row] == F_MU) { r = res_mu(o, L, ci[row], cj[row]); rf = 1; }
+            else { r = res_p(o, L, ci[row], cj[row]); rf = 2; }
             J[row][col] = cimag(r) / CSTEP;
-            if (col == 0) {
-                double f = fld[row] == F_U ? L->rhs[3][kr] : fld[row] == F_V ? L->rhs[4][kr] : L->rhs[2][kr];
-                b[row] = f - creal(r);
-            }
+            if (col == 0) b[row] = L->rhs[rf][kr] - creal(r);
         }
     }
     unperturb(o);
@@ -481,23 +489,30 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
         double d = o->o.vanka_omega * b[q];
         if (fld[q] == F_U) unew[kq] = L->f[F_U][kq] + d;
         else if (fld[q] == F_V) vnew[kq] = L->f[F_V][kq] + d;
+        else if (fld[q] == F_C) L->f[F_C][kq] += b[q];
+        else if (fld[q] == F_MU) L->f[F_MU][kq] += b[q];
         else L->f[F_P][kq] += d;
     }
 }
 
-/* One colour half-sweep (reading of sec. 7.1): colour = (i+j) mod 2.  First
- * the pointwise CH update at every cell of the colour (these are independent:
- * their stencils only reach cells of the other colour), then the Vanka box of
- * every cell of the colour, all boxes reading the same velocity snapshot
- * (Jacobi within a colour, Gauss-Seidel across colours); the pressure of a
- * box is read by no other box of its colour and is updated in place. */
+/* One colour half-sweep (reading of sec. 7.1): colour = (i+j) mod 2.
+ * Segregated smoother (the paper's two steps): first the pointwise CH update
+ * at every cell of the colour (these are independent: their stencils only
+ * reach cells of the other colour), then the Vanka box of every cell of the
+ * colour.  Coupled smoother: the box alone, with c and mubar of the cell in
+ * it (the phase and mass equations depend on mubar and pbar only through
+ * mubar + alpha pbar, which the segregated steps update in turn).  All boxes
+ * read the same velocity snapshot (Jacobi within a colour, Gauss-Seidel
+ * across colours); c, mubar and pbar of a box are read by no other box of
+ * its colour and are updated in place. */
 static void halfsweep(orc_ctx *o, int l, int colour)
 {
     Level *L = &o->lev[l];
     size_t n = (size_t)L->m1 * L->m2;
-    for (int j = 0; j < L->m2; j++)
-        for (int i = 0; i < L->m1; i++)
-            if (((i + j) & 1) == colour) ch_point(o, L, i, j);
+    if (o->o.smoother == ORC_SMOOTH_SEGREGATED)
+        for (int j = 0; j < L->m2; j++)
+            for (int i = 0; i < L->m1; i++)
+                if (((i + j) & 1) == colour) ch_point(o, L, i, j);
     double *unew = malloc(n * sizeof(double)), *vnew = malloc(n * sizeof(double));
     memcpy(unew, L->f[F_U], n * sizeof(double));
     memcpy(vnew, L->f[F_V], n * sizeof(double));
@@ -669,13 +684,13 @@ orc_ctx *orc_create(const orc_grid *g, const orc_params *p, const orc_opts *opt)
     o->K3 = p->eps * p->eta * p->M / p->We;
     o->pf = -1;
     /* levels: each level halves both dimensions, every level keeps even
-     * dimensions (the red-black colouring needs them); auto = coarsen until the
-     * smaller dimension of the coarsest level is 4 */
+     * dimensions (the red-black colouring needs them); auto = coarsen while the
+     * coarsest level has more than 32 cells */
     int nl = g->levels;
     if (nl <= 0) {
         nl = 1;
         while (nl < ORC_MAXLEV && g->m1 % (1 << (nl + 1)) == 0 && g->m2 % (1 << (nl + 1)) == 0
-               && (g->m1 >> nl) >= 4 && (g->m2 >> nl) >= 4)
+               && (g->m1 >> (nl - 1)) * (g->m2 >> (nl - 1)) > 32)
             nl++;
     }
     if (nl > ORC_MAXLEV || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) { free(o); return NULL; }

@@ -27,10 +27,13 @@ typedef struct {
     double rho_ref; /* density the gravity term is measured against */
 } orc_params;
 
+enum { ORC_SMOOTH_SEGREGATED = 0, ORC_SMOOTH_COUPLED = 1 };
+
 typedef struct {
     double tol;
     int max_vcycles, nu1, nu2, nu_coarse;
     double vanka_omega;
+    int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED */
 } orc_opts;
 
 typedef struct orc_ctx orc_ctx;

@@ -27,6 +27,7 @@ struct Phys {
     double visc1, visc2, visc12, dvisc;
     double alpha, inv_Re, inv_M, inv_Pe, K1, K2, K3, inv_Fr, rho_ref, mob_reg;
     double inv_dt;
+    int coupled; // smoother: 1 = one Newton step on the seven-unknown box, 0 = the two steps
 };
 
 struct View {
@@ -425,11 +426,26 @@ __device__ __forceinline__ double ldf(const double *f, const View &L, int i, int
 
 // --------------------------------------------------------------------------
 // smoother for one cell of the current colour (sec. 7.1), run by a lane pair.
-// Step 1: Newton on (N_c, N_mu) in (c_ij, mubar_ij).  Step 2: Vanka box on
-// (uW, uE, vS, vN, p).  Velocities come from the tile (the snapshot of this
-// colour); the box faces go to unew/vnew, c, mubar, pbar to the level arrays.
-// c, mubar and rho(c) of the cell are also written to the tile (identical
-// values from both lanes), which no other pair of this colour reads.
+// Segregated (P.coupled = 0): step 1 is Newton on (N_c, N_mu) in (c_ij,
+// mubar_ij); step 2 the Vanka box on (uW, uE, vS, vN, p).  Coupled: one Newton
+// step on all seven unknowns of the cell with the box equations plus N_c and
+// N_mu of the cell.  Its matrix is the 5x5 box matrix bordered by
+//   face rows:  dN_f/dc = rho'(c) u_f / (4 dt),  dN_f/dmubar = -a_f / M,
+//   mass row:   dN_p/dmubar = alpha Sm / Pe,
+//   phase row:  dN_c/du_f = a_f (the advection weights of App. A.5),
+//               dN_c/dp = alpha Sm / Pe, Jcc, Jcm,
+//   chem. row:  Jmc, Jmm,
+// with a_f = rho^n (c^n jump across the face) / (2h), signed along the axis.
+// mubar and c are eliminated first (N_mu, then N_c; the pivots are Jmm = rho
+// and Jcc - Jcm Jmc / Jmm, which exceeds Jcc where the gradient-energy term
+// makes Jmc negative, as on any grid that resolves the interface), which
+// leaves a rank-one update of the 5x5 box matrix; after its solve, c and mubar
+// follow by back substitution.
+// Velocities come from the tile (the snapshot of this colour); the box faces
+// go to unew/vnew, c, mubar, pbar to the level arrays.  In the segregated
+// form c, mubar and rho(c) of the cell are also written to the tile between
+// the steps (identical values from both lanes), which no other pair of this
+// colour reads.
 __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
                                            double *vnew, int i, int j, int hlf, double omega)
 {
@@ -437,23 +453,40 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     const double ih = L.inv_h, ih2 = ih * ih;
     const int e = T.idx(i, j);
     const Ax a = make_ax(L, T, i, j, hlf);
-    // ---- step 1
+    const bool cpl = P.coupled;
     CellAx x = cell_axis(T, a, e, ih);
     CellAx s = cell_sum(x);
     CellEq q = cell_eq(P, T, e, s);
     const double r1 = ldf(F.fc, L, i, j) - q.Nc, r2 = ldf(F.fmu, L, i, j) - q.Nmu;
-    const double idet = frcp(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
     const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e);
-    const double cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
-    const double mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
-    if (hlf == 0) {
-        L.c[k] = cnew;
-        L.mu[k] = mnew;
+    double cnew = c0, mnew = m0;
+    // coupled box: mubar eliminated by N_mu (pivot Jmm), then c by N_c (pivot
+    // 1/icc); what the box needs of the cell rows afterwards
+    double imm = 0.0, kmc = 0.0, kbm = 0.0, icc = 0.0, bc = 0.0, Jcp = 0.0, gc = 0.0;
+    if (cpl) {
+        imm = frcp(q.Jmm);
+        kmc = q.Jmc * imm;
+        kbm = r2 * imm;
+        icc = frcp(q.Jcc - q.Jcm * kmc);
+        bc = r1 - q.Jcm * kbm;
+        Jcp = P.alpha * P.inv_Pe * s.Sm; // dN_c/dpbar = dN_p/dmubar
+        const double rs = tq(T, T_RS, e);
+        gc = 0.25 * (-P.alpha * rs * rs) * P.inv_dt; // dN_f/dc per unit u_f
     }
-    T.s[T_C * T.W * T.H + e] = cnew;
-    T.s[T_MU * T.W * T.H + e] = mnew;
-    T.s[T_RS * T.W * T.H + e] = rho_of(P, cnew);
-    // ---- step 2: this lane's two faces along its axis
+    if (!cpl) {
+        // ---- step 1
+        const double idet = frcp(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
+        cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
+        mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
+        if (hlf == 0) {
+            L.c[k] = cnew;
+            L.mu[k] = mnew;
+        }
+        T.s[T_C * T.W * T.H + e] = cnew;
+        T.s[T_MU * T.W * T.H + e] = mnew;
+        T.s[T_RS * T.W * T.H + e] = rho_of(P, cnew);
+    }
+    // ---- the box: this lane's two faces along its axis
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const FaceEq flo = face_eq(P, T, a, e, a.it, ih);
     const FaceEq fhi = face_eq(P, T, a, e + a.dn, a.it, ih);
@@ -470,6 +503,17 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     const double mv0 = tq(T, T_MV, e);
     const double vis = (4.0 / 3.0) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0;
     const double gp = P.inv_M * ih;
+    // periodic axis of two cells: the next face beyond each box face is the
+    // box's other face, which so enters each face row a second time (through
+    // the other cell's advection weight and viscosity)
+    double xlo = 0.0, xhi = 0.0;
+    if (a.per && a.ma == 2) {
+        const double w_o = tq(T, T_RN, e - a.dn) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
+        const double v_o = (4.0 / 3.0) * P.inv_Re * ih2 * tq(T, T_MV, e - a.dn);
+        xlo = -0.5 * ih * w_o - v_o;
+        xhi = 0.5 * ih * w_o - v_o;
+    }
+    const double o_xlo = other(xlo), o_xhi = other(xhi);
     // exchange: the pair now holds the x rows (lane 0) and the y rows (lane 1)
     const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
     const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
@@ -486,6 +530,36 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     A[2][2] = d2; A[2][3] = mS * (0.5 * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
     A[3][3] = d3; A[3][2] = mN * (-0.5 * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
     A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
+    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    // coupled box: border of the c and mubar rows and columns, eliminated
+    // into the 5x5 system (see above)
+    double ac[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
+    if (cpl) {
+        const int e1 = e + a.dn;
+        const double alo = hlo ? 0.5 * ih * tq(T, T_RN, e - a.dn) * (tq(T, T_CN, e) - tq(T, T_CN, e - a.dn)) : 0.0;
+        const double ahi = hhi ? 0.5 * ih * tq(T, T_RN, e1) * (tq(T, T_CN, e1) - tq(T, T_CN, e)) : 0.0;
+        const double ulo = hlo ? tq(T, a.FN, e) : 0.0, uhi = hhi ? tq(T, a.FN, e1) : 0.0;
+        const double o_alo = other(alo), o_ahi = other(ahi), o_ulo = other(ulo), o_uhi = other(uhi);
+        ac[0] = hlf ? o_alo : alo; ac[1] = hlf ? o_ahi : ahi; ac[2] = hlf ? alo : o_alo; ac[3] = hlf ? ahi : o_ahi;
+        const double uf[4] = { hlf ? o_ulo : ulo, hlf ? o_uhi : uhi, hlf ? ulo : o_ulo, hlf ? uhi : o_uhi };
+        ac[4] = Jcp;
+        double gam[5];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            const double lam = -P.inv_M * ac[f];
+            gam[f] = gc * uf[f] - lam * kmc;
+            b[f] -= lam * kbm;
+        }
+        gam[4] = -Jcp * kmc;
+        b[4] -= Jcp * kbm;
+#pragma unroll
+        for (int r = 0; r < 5; r++) {
+            const double t = gam[r] * icc;
+#pragma unroll
+            for (int cc = 0; cc < 5; cc++) A[r][cc] -= t * ac[cc];
+            b[r] -= t * bc;
+        }
+    }
     // Gaussian elimination in the order u, u, v, v, p: the velocity block has a
     // positive definite symmetric part (mass + viscous; advection is skew) and
     // the last pivot is the positive pressure Schur complement
@@ -508,6 +582,14 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
 #pragma unroll
         for (int t = c + 1; t < 5; t++) acc -= A[c][t] * b[t];
         b[c] = acc * inv[c];
+    }
+    if (cpl && hlf == 0) {
+        double acc = bc;
+#pragma unroll
+        for (int t = 0; t < 5; t++) acc -= ac[t] * b[t];
+        const double dc = acc * icc;
+        L.c[k] = c0 + dc;
+        L.mu[k] = m0 + kbm - kmc * dc;
     }
     double *dst = hlf ? vnew : unew;
     const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];

@@ -27,12 +27,14 @@ namespace qn {
 #define TX QN_TX
 #define TY QN_TY
 #define TBLK (TX * TY)
-// The FP64 finest-level half-sweep is register-limited to 2 waves per SIMD at
-// its natural allocation; asking for 3 costs a few spilled registers and buys
-// a third resident workgroup per CU (18 % faster on 512 x 2048).  Coarser
-// levels, which run few workgroups, keep the natural allocation.
+// The FP64 finest-level half-sweep is register-limited to 2 waves per SIMD.
+// With the segregated smoother alone, asking for 3 cost a few spilled
+// registers and bought a third resident workgroup per CU (18 % faster on
+// 512 x 2048); the coupled box needs some 25 more registers, whose spills at 3
+// waves cost more than the third workgroup gains, so the finest level keeps 2.
+// The attribute stays separate so that the trade can be re-measured.
 #ifndef QN_FINE_WAVES
-#define QN_FINE_WAVES 3
+#define QN_FINE_WAVES 2
 #endif
 #define HS_ATTR __launch_bounds__(TBLK)
 #define FINE_ATTR __launch_bounds__(TBLK) __attribute__((amdgpu_waves_per_eu(QN_FINE_WAVES)))

@@ -425,9 +425,13 @@ static int level_count(const qnsch_grid *g)
 {
     int nl = g->levels;
     if (nl <= 0) {
+        // coarsen while the coarsest level has more than 32 cells and the next
+        // one keeps even dimensions: the coarsest solve is a fixed number of
+        // sweeps, which converge on a few dozen cells but not on an elongated
+        // grid of 64 or more
         nl = 1;
-        while (nl < 16 && g->m1 % (1 << (nl + 1)) == 0 && g->m2 % (1 << (nl + 1)) == 0 && (g->m1 >> nl) >= 4
-               && (g->m2 >> nl) >= 4)
+        while (nl < 16 && g->m1 % (1 << (nl + 1)) == 0 && g->m2 % (1 << (nl + 1)) == 0
+               && (g->m1 >> (nl - 1)) * (g->m2 >> (nl - 1)) > 32)
             nl++;
     }
     if (nl > 16 || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) return -1;
@@ -502,6 +506,7 @@ static void phys_of(const qnsch_params *p, Phys &P)
     P.K3 = p->eps * p->eta * p->M / p->We;
     P.inv_Fr = p->inv_Fr; P.rho_ref = p->rho_ref; P.mob_reg = p->mob_reg;
     P.inv_dt = 0.0;
+    P.coupled = 1;
 }
 
 static PhysF physf_of(const Phys &P)
@@ -512,6 +517,7 @@ static PhysF physf_of(const Phys &P)
     F.alpha = (float)P.alpha; F.inv_Re = (float)P.inv_Re; F.inv_M = (float)P.inv_M; F.inv_Pe = (float)P.inv_Pe;
     F.K1 = (float)P.K1; F.K2 = (float)P.K2; F.K3 = (float)P.K3; F.mob_reg = (float)P.mob_reg;
     F.inv_dt = 0.0f;
+    F.coupled = P.coupled;
     return F;
 }
 
@@ -535,6 +541,7 @@ void qnsch_default_opts(qnsch_opts *o)
     o->nu2 = 2;
     o->nu_coarse = 30;
     o->vanka_omega = 1.0;
+    o->smoother = QNSCH_SMOOTH_COUPLED;
 }
 
 const char *qnsch_last_error(const qnsch_ctx *x) { return x ? x->err.c_str() : "null context"; }
@@ -565,7 +572,8 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
         || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
         return QNSCH_EINVAL;
     if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0
-              || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)))
+              || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)
+              || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)))
         return QNSCH_EINVAL;
     if (level_count(g) < 0) return QNSCH_EINVAL;
     return QNSCH_OK;
@@ -577,6 +585,7 @@ static void set_params(qnsch_ctx *x, const qnsch_params *p)
     x->prm = *p;
     Phys P;
     phys_of(p, P);
+    P.coupled = x->opt.smoother == QNSCH_SMOOTH_COUPLED;
     const PhysF Pf = physf_of(P);
     for (int l = 0; l < x->nlev; l++) {
         x->hd[l].P = P;

@@ -32,6 +32,7 @@ namespace qn {
 struct PhysF {
     float rho1, rho12, drho, visc1, visc12, dvisc;
     float alpha, inv_Re, inv_M, inv_Pe, K1, K2, K3, mob_reg, inv_dt;
+    int coupled; // smoother as in Phys
 };
 
 // one level of the correction problem
@@ -304,9 +305,12 @@ __device__ __forceinline__ FaceEqF lface_eq(const PhysF &P, const TileF &T, cons
 // (i, j) (x lane) or its south face (y lane), or the next one along the axis
 __device__ __forceinline__ float face_point(const LView &L, int hlf, size_t k) { return (hlf ? L.v : L.u)[k]; }
 
-// one cell of the current colour: the FP64 smoother's two steps applied to
-// the correction equation J(w^) delta = r.  Step 1 is a 2x2 solve for
-// (dc, dmu) of the cell; step 2 the 5x5 Vanka box for its four faces and dp.
+// one cell of the current colour: the FP64 smoother applied to the
+// correction equation J(w^) delta = r.  Segregated: step 1 is a 2x2 solve for
+// (dc, dmu) of the cell, step 2 the 5x5 Vanka box for its four faces and dp.
+// Coupled: the seven-unknown box of the FP64 smoother with the entries of J at
+// w^ (the face rows' dc entry multiplies the face velocity at w^), eliminated
+// the same way.
 __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, const TileF &T, float *dunew,
                                             float *dvnew, int i, int j, int hlf, float omega)
 {
@@ -314,29 +318,34 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
     const float ih = L.inv_h, ih2 = ih * ih;
     const int e = T.idx(i, j);
     const Ax a = make_ax(L, T, i, j, hlf);
-    // ---- step 1
+    const bool cpl = P.coupled;
     const LCellAx s = lcell_sum(lcell_axis(T, a, e, ih));
     const LCellEq q = lcell_eq(P, T, e, s, L.mu[k]);
     const float r1 = L.rc[k] - q.Nc, r2 = L.rmu[k] - q.Nmu;
-    const float idet = frcpf(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
     const float c0 = tq(T, L_DC, e), m0 = tq(T, L_MU, e);
-    const float cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
-    const float mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
-    if (hlf == 0) {
-        L.dc[k] = cnew;
-        L.dmu[k] = mnew;
-    }
     const int st = T.W * T.H;
     const float rs = tq(T, L_RS, e);
-    T.s[L_DC * st + e] = cnew;
-    T.s[L_MU * st + e] = mnew;
-    T.s[L_DRS * st + e] = -P.alpha * rs * rs * cnew;
-    // ---- step 2
+    float mnew = m0;
+    if (!cpl) {
+        // ---- step 1
+        const float idet = frcpf(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
+        const float cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
+        mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
+        if (hlf == 0) {
+            L.dc[k] = cnew;
+            L.dmu[k] = mnew;
+        }
+        T.s[L_DC * st + e] = cnew;
+        T.s[L_MU * st + e] = mnew;
+        T.s[L_DRS * st + e] = -P.alpha * rs * rs * cnew;
+    }
+    // ---- the box
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
     const size_t khi = (size_t)jhi * L.pitch + ihi;
-    const FaceEqF flo = lface_eq(P, T, a, e, a.it, ih, face_point(L, hlf, k));
-    const FaceEqF fhi = lface_eq(P, T, a, e + a.dn, a.it, ih, face_point(L, hlf, khi));
+    const float uhlo = face_point(L, hlf, k), uhhi = face_point(L, hlf, khi);
+    const FaceEqF flo = lface_eq(P, T, a, e, a.it, ih, uhlo);
+    const FaceEqF fhi = lface_eq(P, T, a, e + a.dn, a.it, ih, uhhi);
     const float *rN = hlf ? L.rv : L.ru;
     const float blo = hlo ? rN[k] - flo.N : 0.0f, dlo = hlo ? flo.diag : 1.0f;
     const float bhi = hhi ? rN[khi] - fhi.N : 0.0f, dhi = hhi ? fhi.diag : 1.0f;
@@ -346,6 +355,15 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
     const float mv0 = tq(T, L_MV, e);
     const float vis = (4.0f / 3.0f) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0f;
     const float gp = P.inv_M * ih;
+    // periodic axis of two cells: the box faces meet twice (as in relax_pair)
+    float xlo = 0.0f, xhi = 0.0f;
+    if (a.per && a.ma == 2) {
+        const float w_o = tq(T, L_RN, e - a.dn) * 0.5f * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
+        const float v_o = (4.0f / 3.0f) * P.inv_Re * ih2 * tq(T, L_MV, e - a.dn);
+        xlo = -0.5f * ih * w_o - v_o;
+        xhi = 0.5f * ih * w_o - v_o;
+    }
+    const float o_xlo = other(xlo), o_xhi = other(xhi);
     const float o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
     const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
     const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
@@ -359,6 +377,40 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
     A[2][2] = d2; A[2][3] = mS * (0.5f * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
     A[3][3] = d3; A[3][2] = mN * (-0.5f * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
     A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
+    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    float ac[5] = { 0.0f, 0.0f, 0.0f, 0.0f, 0.0f }, icc = 0.0f, bc = 0.0f, imm = 0.0f;
+    if (cpl) {
+        const int e1 = e + a.dn;
+        const float alo = hlo ? 0.5f * ih * tq(T, L_RN, e - a.dn) * (tq(T, L_CN, e) - tq(T, L_CN, e - a.dn)) : 0.0f;
+        const float ahi = hhi ? 0.5f * ih * tq(T, L_RN, e1) * (tq(T, L_CN, e1) - tq(T, L_CN, e)) : 0.0f;
+        const float ulo = hlo ? uhlo : 0.0f, uhi = hhi ? uhhi : 0.0f;
+        const float o_alo = other(alo), o_ahi = other(ahi), o_ulo = other(ulo), o_uhi = other(uhi);
+        ac[0] = hlf ? o_alo : alo; ac[1] = hlf ? o_ahi : ahi; ac[2] = hlf ? alo : o_alo; ac[3] = hlf ? ahi : o_ahi;
+        const float uf[4] = { hlf ? o_ulo : ulo, hlf ? o_uhi : uhi, hlf ? ulo : o_ulo, hlf ? uhi : o_uhi };
+        const float gc = 0.25f * (-P.alpha * rs * rs) * P.inv_dt;
+        const float Jcp = P.alpha * P.inv_Pe * s.Sm;
+        ac[4] = Jcp;
+        imm = frcpf(q.Jmm);
+        const float kmc = q.Jmc * imm, kbm = r2 * imm;
+        icc = frcpf(q.Jcc - q.Jcm * kmc);
+        bc = r1 - q.Jcm * kbm;
+        float gam[5];
+#pragma unroll
+        for (int f = 0; f < 4; f++) {
+            const float lam = -P.inv_M * ac[f];
+            gam[f] = gc * uf[f] - lam * kmc;
+            b[f] -= lam * kbm;
+        }
+        gam[4] = -Jcp * kmc;
+        b[4] -= Jcp * kbm;
+#pragma unroll
+        for (int r = 0; r < 5; r++) {
+            const float t = gam[r] * icc;
+#pragma unroll
+            for (int cc = 0; cc < 5; cc++) A[r][cc] -= t * ac[cc];
+            b[r] -= t * bc;
+        }
+    }
     float inv[5];
 #pragma unroll
     for (int cc = 0; cc < 4; cc++) {
@@ -378,6 +430,14 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
 #pragma unroll
         for (int t = cc + 1; t < 5; t++) acc -= A[cc][t] * b[t];
         b[cc] = acc * inv[cc];
+    }
+    if (cpl && hlf == 0) {
+        float acc = bc;
+#pragma unroll
+        for (int t = 0; t < 5; t++) acc -= ac[t] * b[t];
+        const float dc = acc * icc;
+        L.dc[k] = c0 + dc;
+        L.dmu[k] = m0 + (r2 - q.Jmc * dc) * imm;
     }
     float *dst = hlf ? dvnew : dunew;
     const float dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];

@@ -51,8 +51,11 @@ def _centres(m1, m2, h):
     return np.meshgrid(x, y)  # (m2, m1)
 
 
+SMOOTH_SEGREGATED, SMOOTH_COUPLED = 0, 1
+
+
 def default_opts(tol=1e-10):
-    return dict(tol=tol, max_vcycles=50, nu1=2, nu2=2, nu_coarse=30, vanka_omega=1.0)
+    return dict(tol=tol, max_vcycles=50, nu1=2, nu2=2, nu_coarse=30, vanka_omega=1.0, smoother=SMOOTH_COUPLED)
 
 
 def params(rho1, rho2, visc1, visc2, Re, We, inv_Fr, eps, M=None, Pe=None, eta=None, mob_reg=None, rho_ref=0.0):
@@ -222,15 +225,13 @@ def serving_at_scale(nbig=16, big=2048, nsteps=20, bg_rate_hz=20.0, bg_size=256,
     return bigs, background()
 
 
-def convergence_case(m, amp=0.2, eps=0.1, T=0.25, rho_ratio=1.0, visc_ratio=3.0):
+def convergence_case(m, amp=0.2, eps=0.1, T=0.25, rho_ratio=3.0, visc_ratio=3.0):
     """Cauchy convergence study of sec. 9 on the unit square with walls:
     c = 0.5 + amp (cos 2 pi x + cos 2 pi y) (bounded away from the density
     pole, unlike the printed cos 2 pi x + cos 2 pi y), everything else zero,
-    equal densities by default (the multigrid contracts by ~0.1 per cycle at
-    every mesh there; with a density contrast its factor grows with
-    refinement at dt ~ h^2), viscosity ratio 3, Re = We = 10, gravity
-    1/Fr = 1, M = eps, Pe = 1/eps; time step dt = (1/16)(16/m)^2 as in the
-    printed schedule, run to time T."""
+    density and viscosity ratios 3 (the paper does not state them), Re = We =
+    10, gravity 1/Fr = 1, M = eps, Pe = 1/eps; time step dt = (1/16)(16/m)^2 as
+    in the printed schedule, run to time T."""
     h = 1.0 / m
     grid = dict(m1=m, m2=m, Lx=1.0, Ly=1.0, bcx=WALL, bcy=WALL, levels=0)
     par = params(1.0, rho_ratio, 1.0, visc_ratio, Re=10.0, We=10.0, inv_Fr=1.0, eps=eps)

@@ -81,6 +81,7 @@ def _cases():
         "drop_32x64": W.rising_drop(32, 64, eps=0.04),
         "drop_40x24_ragged": W.rising_drop(40, 24, eps=0.05, radius=0.2),
         "periodic_box_32x32": per,
+        "rayleigh_taylor_32x128": W.rayleigh_taylor(32, 128, eps=0.04),
     }
 
 

@@ -63,12 +63,13 @@ def test_residual_matches_oracle(shape):
     assert np.allclose(ng, no, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
-def test_halfsweeps_match_oracle(shape):
+def test_halfsweeps_match_oracle(shape, smoother):
     m1, m2, bx, by = shape
-    say("halfsweep parity", shape)
+    say("halfsweep parity", shape, "smoother", smoother)
     cfg = dict(grid=grid_(m1, m2, bx, by, levels=0), params=par_O1(rho2=3.0))
-    g, o = pair(cfg, W.default_opts())
+    g, o = pair(cfg, dict(W.default_opts(), smoother=smoother))
     w, wn = W.random_state(cfg["grid"], 23), W.random_state(cfg["grid"], 24)
     for s in (g, o):
         s.set_time_n_and_iterate(wn, w, 0.3)
@@ -93,6 +94,8 @@ def _cases():
         "drop_32x64": W.rising_drop(32, 64, eps=0.04),
         "drop_40x24_ragged": W.rising_drop(40, 24, eps=0.05, radius=0.2),
         "periodic_box_32x32": _periodic_drop(),
+        # elongated: the automatic hierarchy ends on a 2 x 8 coarsest level
+        "rayleigh_taylor_16x64": W.rayleigh_taylor(16, 64, eps=0.08),
     }
 
 
@@ -298,9 +301,10 @@ def _to_fine(c):
 
 def test_cauchy_convergence_is_second_order():
     """Cauchy study of sec. 9 (mesh 16..256, dt = (1/16)(16/m)^2, bounded
-    initial phase field): the L2 difference of c between successive meshes,
-    the coarse solution interpolated to the fine mesh, falls with rate -> 2
-    (first order in time with dt ~ h^2, second order in space)"""
+    initial phase field, density ratio 3): the L2 difference of c between
+    successive meshes, the coarse solution interpolated to the fine mesh,
+    falls with rate -> 2 (first order in time with dt ~ h^2, second order in
+    space); the V-cycle count per step stays bounded as the mesh is refined"""
     sols = {}
     for m in (16, 32, 64, 128, 256):
         cfg = W.convergence_case(m)
@@ -308,10 +312,13 @@ def test_cauchy_convergence_is_second_order():
         # round-off floor of residuals scaled by 1/dt = 4096
         g = Q.Solver(cfg["grid"], cfg["params"], W.default_opts(1e-9))
         g.set_state(cfg["state"]["c"])
+        vc = 0
         for _ in range(cfg["nsteps"]):
             assert g.step(cfg["dt"]) == Q.OK
+            vc = max(vc, g.stats()["vcycles"])
         sols[m] = g.get_state()["c"]
-        say("convergence mesh", m, "steps", cfg["nsteps"])
+        say("convergence mesh", m, "steps", cfg["nsteps"], "most V-cycles in a step", vc)
+        assert vc <= 12, (m, vc)
     errs = []
     for m in (16, 32, 64, 128):
         d = _to_fine(sols[m]) - sols[2 * m]

@@ -558,8 +558,9 @@ def test_mass_conservation_and_energy_law(cfg):
 # ---------------------------------------------------------------------------
 # the solver reaches the root of N (dense Newton on the same system)
 
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("case", ["walls", "periodic_x"])
-def test_multigrid_root_equals_dense_newton(case):
+def test_multigrid_root_equals_dense_newton(case, smoother):
     if case == "walls":
         c = W.rising_drop(8, 16, eps=0.1)
     else:
@@ -567,7 +568,7 @@ def test_multigrid_root_equals_dense_newton(case):
     P = dict(c["params"], inv_Fr=1.0)
     dt = 0.01
     # MG
-    o = mk(c["grid"], P, W.default_opts(1e-12))
+    o = mk(c["grid"], P, dict(W.default_opts(1e-12), smoother=smoother))
     o.set_state(c["state"]["c"])
     assert o.step(dt) == OR.OK
     smg = o.get_state()
@@ -601,13 +602,17 @@ def test_multigrid_root_equals_dense_newton(case):
 # ---------------------------------------------------------------------------
 # smoother semantics (sec. 7.1)
 
+SEG = dict(W.default_opts(), smoother=W.SMOOTH_SEGREGATED)
+
+
 def test_vanka_box_is_exact_local_solve():
-    """After a half-sweep every box of the colour satisfies its five equations
-    (momentum at its faces, mass at its cell) with its own new unknowns and the
-    velocity snapshot elsewhere (Jacobi within a colour)."""
+    """Segregated smoother (the paper's steps): after a half-sweep every box
+    of the colour satisfies its five equations (momentum at its faces, mass at
+    its cell) with its own new unknowns and the velocity snapshot elsewhere
+    (Jacobi within a colour)."""
     grid = grid_(8, 8, 0, 0)
     P = par_O1(rho2=3.0)
-    o = mk(grid, P)
+    o = mk(grid, P, SEG)
     w, wn = rand_state(grid, 15), rand_state(grid, 16)
     o.set_time_n_and_iterate(wn, w, 0.3)
     before = o.get_state()
@@ -629,10 +634,10 @@ def test_vanka_box_is_exact_local_solve():
             if j + 1 < 8:
                 hyb["v"][j + 1, i] = after["v"][j + 1, i]; rows.append((4, j + 1, i))
             rows.append((2, j, i))
-            o2 = mk(grid, P)
+            o2 = mk(grid, P, SEG)
             o2.set_time_n_and_iterate(wn, hyb, 0.3)
             r, _ = o2.residual()
-            o3 = mk(grid, P)
+            o3 = mk(grid, P, SEG)
             o3.set_time_n_and_iterate(wn, before, 0.3)
             r0, _ = o3.residual()
             for q, jj, ii in rows:
@@ -643,14 +648,68 @@ def test_vanka_box_is_exact_local_solve():
         assert (after[k][odd] == before[k][odd]).all()
 
 
-def test_ch_point_update_is_a_newton_step():
-    """Step 1 of sec. 7.1 is one Newton step on (N_c, N_mu) in (c_ij, mubar_ij):
-    near a root the local residual after the update is quadratic in the
-    distance from the root."""
+def test_coupled_box_is_a_newton_step():
+    """Coupled smoother: the box of a cell is one Newton step on its seven
+    equations (momentum at its four faces, mass, phase and chemical potential
+    at the cell) in its seven unknowns, the rest frozen (the velocity
+    snapshot): near a root the box residual after the update is quadratic in
+    the distance from the root, and the other colour is untouched."""
     c = W.rising_drop(8, 8, eps=0.1)
     c["grid"]["Ly"] = 1.0
     P = c["params"]
     o = mk(c["grid"], P, W.default_opts(1e-12))
+    o.set_state(c["state"]["c"])
+    dt = 0.01
+    assert o.step(dt) == OR.OK
+    root = o.get_state()
+    wn = dict(c=c["state"]["c"])
+    red = (np.add.outer(np.arange(8), np.arange(8)) % 2) == 0
+    res = []
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal((5, 8, 8))
+    for s in (1e-3, 1e-4):
+        w = {k: v + s * d[q] * (red if k in ("c", "mu", "p") else 1.0) for q, (k, v) in enumerate(root.items())}
+        w["u"][:, 0] = 0.0
+        w["v"][0, :] = 0.0
+        o2 = mk(c["grid"], P)
+        o2.set_time_n_and_iterate(wn, w, dt)
+        o2.halfsweep(0)
+        after = o2.get_state()
+        worst = 0.0
+        for j in range(8):
+            for i in range(8):
+                if (i + j) % 2:
+                    continue
+                hyb = {k: w[k].copy() for k in w}
+                for k in ("c", "mu", "p"):
+                    hyb[k][j, i] = after[k][j, i]
+                rows = [(0, j, i), (1, j, i), (2, j, i)]
+                if i > 0:
+                    hyb["u"][j, i] = after["u"][j, i]; rows.append((3, j, i))
+                if i + 1 < 8:
+                    hyb["u"][j, i + 1] = after["u"][j, i + 1]; rows.append((3, j, i + 1))
+                if j > 0:
+                    hyb["v"][j, i] = after["v"][j, i]; rows.append((4, j, i))
+                if j + 1 < 8:
+                    hyb["v"][j + 1, i] = after["v"][j + 1, i]; rows.append((4, j + 1, i))
+                o3 = mk(c["grid"], P)
+                o3.set_time_n_and_iterate(wn, hyb, dt)
+                r, _ = o3.residual()
+                worst = max(worst, max(abs(r[q, jj, ii]) for q, jj, ii in rows))
+        res.append(worst)
+        for k in ("c", "mu", "p"):
+            assert (after[k][~red] == w[k][~red]).all()
+    assert res[1] < res[0] / 50.0, res
+
+
+def test_ch_point_update_is_a_newton_step():
+    """Segregated smoother, step 1 of sec. 7.1: one Newton step on (N_c, N_mu)
+    in (c_ij, mubar_ij): near a root the local residual after the update is
+    quadratic in the distance from the root."""
+    c = W.rising_drop(8, 8, eps=0.1)
+    c["grid"]["Ly"] = 1.0
+    P = c["params"]
+    o = mk(c["grid"], P, dict(W.default_opts(1e-12), smoother=W.SMOOTH_SEGREGATED))
     o.set_state(c["state"]["c"])
     dt = 0.01
     assert o.step(dt) == OR.OK
@@ -664,12 +723,12 @@ def test_ch_point_update_is_a_newton_step():
         w = {k: v.copy() for k, v in root.items()}
         w["c"] += s * d1 * red
         w["mu"] += s * d2 * red
-        o2 = mk(c["grid"], P)
+        o2 = mk(c["grid"], P, SEG)
         o2.set_time_n_and_iterate(wn, w, dt)
         o2.halfsweep(0)
         after = o2.get_state()
         hyb = dict(w, c=after["c"], mu=after["mu"])
-        o3 = mk(c["grid"], P)
+        o3 = mk(c["grid"], P, SEG)
         o3.set_time_n_and_iterate(wn, hyb, dt)
         r, _ = o3.residual()
         res.append(max(np.abs(r[0][red]).max(), np.abs(r[1][red]).max()))
