@@ -82,6 +82,14 @@ typedef struct {
     int32_t levels;     /* multigrid levels; 0 = coarsen while the coarsest level has > 32 cells */
 } qnsch_grid;
 
+/* Interface ratio parameter eta of sec. 8.1, which matches the phase-field
+ * surface tension to the sharp-interface one for the density pair:
+ *   eta = (rho2 - rho1)^3 / (2 sqrt2 rho1 rho2 (rho2^2 - rho1^2 - 2 rho1 rho2 ln(rho2/rho1))),
+ * evaluated through a series in x = rho2/rho1 - 1 for |x| < 0.05 (the direct
+ * form cancels there), with the equal-density limit 3/(2 sqrt2 rho1).
+ * Host-only; returns NaN unless both densities are positive. */
+double qnsch_default_eta(double rho1, double rho2);
+
 /* Non-dimensional parameters of sec. 2.2; fluid 1 is c = 1 (rho(1) = rho1). */
 typedef struct {
     double rho1, rho2;   /* densities, > 0 */

@@ -1036,6 +1036,24 @@ int qnsch_profile_breakdown(qnsch_ctx *x, int32_t *kinds, double *out, int32_t c
     return k;
 }
 
+double qnsch_default_eta(double rho1, double rho2)
+{
+    if (!(rho1 > 0) || !(rho2 > 0)) return NAN;
+    const double x = rho2 / rho1 - 1.0;
+    if (fabs(x) < 0.05) {
+        // f(x) = (1+x)^2 - 1 - 2(1+x) ln(1+x) = sum_{k>=3} (-1)^(k+1) 2 x^k / (k(k-1));
+        // eta = x^3 / (2 sqrt2 rho1 (1+x) f(x)), f(x)/x^3 summed to x^14
+        double s = 0.0, xp = 1.0;
+        for (int k = 3; k <= 17; k++) {
+            s += ((k & 1) ? 2.0 : -2.0) * xp / (k * (k - 1.0));
+            xp *= x;
+        }
+        return 1.0 / (2.0 * sqrt(2.0) * rho1 * (1.0 + x) * s);
+    }
+    const double d = rho2 - rho1;
+    return d * d * d / (2.0 * sqrt(2.0) * rho1 * rho2 * (rho2 * rho2 - rho1 * rho1 - 2.0 * rho1 * rho2 * log(rho2 / rho1)));
+}
+
 int qnsch_copy_probe(size_t n, int reps, double out[2])
 {
     if (n == 0 || reps < 1 || !out) return QNSCH_EINVAL;

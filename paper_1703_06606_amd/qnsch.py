@@ -23,7 +23,8 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
            "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
-           "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats")
+           "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
+           "qnsch_default_eta")
 
 
 # operation classes of qnsch_profile_breakdown, in the library's numbering
@@ -72,6 +73,8 @@ def lib():
         vp = C.c_void_p
         L.qnsch_default_opts.argtypes = [C.POINTER(Opts)]
         L.qnsch_default_opts.restype = None
+        L.qnsch_default_eta.argtypes = [C.c_double, C.c_double]
+        L.qnsch_default_eta.restype = C.c_double
         L.qnsch_create.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.POINTER(Opts), vp, C.POINTER(vp)]
         L.qnsch_destroy.argtypes = [vp]
         L.qnsch_destroy.restype = None
@@ -126,6 +129,11 @@ def copy_probe(n_doubles, reps=20):
     if rc != OK:
         raise QnschError(rc, "copy probe failed")
     return float(out[0]), float(out[1])
+
+
+def default_eta(rho1, rho2):
+    """interface ratio parameter of sec. 8.1 for the density pair"""
+    return float(lib().qnsch_default_eta(C.c_double(rho1), C.c_double(rho2)))
 
 
 def default_opts():

@@ -36,3 +36,29 @@ def test_binding_refuses_to_run_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(Q, "_lib", None)
     with pytest.raises(RuntimeError):
         Q.lib()
+
+
+@pytest.mark.skipif(not os.path.exists(Q.LIB), reason="HIP library not built")
+def test_default_eta_is_the_matching_formula():
+    """qnsch_default_eta (host only) against the formula of sec. 8.1 written
+    out here, its equal-density limit 3/(2 sqrt2 rho1), and continuity across
+    the switch to the series (|rho2/rho1 - 1| = 0.05)"""
+    import math
+
+    def direct(r1, r2):
+        d = r2 - r1
+        return d ** 3 / (2 * math.sqrt(2) * r1 * r2 * (r2 * r2 - r1 * r1 - 2 * r1 * r2 * math.log(r2 / r1)))
+
+    for r1, r2 in ((1.0, 3.0), (1.0, 10.0), (1.0, 100.0), (2.0, 0.5), (1.0, 1.3)):
+        assert math.isclose(Q.default_eta(r1, r2), direct(r1, r2), rel_tol=1e-13)
+    # the workloads' values at ratios 3, 10 and 100
+    assert abs(Q.default_eta(1.0, 3.0) - 0.66945) < 5e-6
+    assert abs(Q.default_eta(1.0, 10.0) - 0.48678) < 5e-6
+    assert abs(Q.default_eta(1.0, 100.0) - 0.37790) < 5e-6
+    for r1 in (1.0, 2.5):
+        assert math.isclose(Q.default_eta(r1, r1), 3 / (2 * math.sqrt(2) * r1), rel_tol=1e-15)
+    # on both sides of the switch: the series and the direct form agree
+    # (the direct form loses about 6 digits to cancellation there)
+    for x in (0.0499999, 0.0500001, -0.0499999, -0.0500001):
+        assert math.isclose(Q.default_eta(1.0, 1.0 + x), direct(1.0, 1.0 + x), rel_tol=1e-9)
+    assert math.isnan(Q.default_eta(0.0, 1.0))
