@@ -37,7 +37,8 @@ class _Params(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_vcycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
-                ("nu_coarse", C.c_int), ("vanka_omega", C.c_double), ("smoother", C.c_int)]
+                ("nu_coarse", C.c_int), ("vanka_omega", C.c_double), ("smoother", C.c_int),
+                ("scheme", C.c_int)]
 
 
 _lib = None
@@ -66,6 +67,7 @@ def lib():
         L.orc_mass.argtypes = [C.c_void_p, P]
         L.orc_energy.argtypes = [C.c_void_p, P]
         L.orc_dissipation.argtypes = [C.c_void_p, P]
+        L.orc_velocity_np1.argtypes = [C.c_void_p, P, P]
         L.orc_diagnostics.argtypes = [C.c_void_p, P]
         L.orc_num_unknowns.argtypes = [C.c_void_p]
         L.orc_dense.argtypes = [C.c_void_p, P, P]
@@ -92,7 +94,7 @@ class Oracle:
         g = _Grid(grid["m1"], grid["m2"], grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
         p = _Params(*[float(params[n]) for n, _ in _Params._fields_])
         o = _Opts(opts["tol"], opts["max_vcycles"], opts["nu1"], opts["nu2"], opts["nu_coarse"], opts["vanka_omega"],
-                  opts.get("smoother", 1))
+                  opts.get("smoother", 1), opts.get("scheme", 0))
         self.h = lib().orc_create(C.byref(g), C.byref(p), C.byref(o))
         if not self.h:
             raise ValueError("oracle rejected the grid")
@@ -155,9 +157,15 @@ class Oracle:
         return out
 
     def dissipation(self):
-        out = np.zeros(4)
+        out = np.zeros(5)
         lib().orc_dissipation(self.h, _ptr(out))
         return out
+
+    def velocity_np1(self):
+        """projection scheme: the velocity of time n+1 of the current iterate"""
+        u, v = np.zeros((self.m2, self.m1)), np.zeros((self.m2, self.m1))
+        lib().orc_velocity_np1(self.h, _ptr(u), _ptr(v))
+        return u, v
 
     def diagnostics(self):
         out = np.zeros(8)

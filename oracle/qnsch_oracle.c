@@ -35,6 +35,14 @@
  *   v(i,j) = y-velocity on the south face of cell (i,j), at ((i+1/2)h, j h).
  * Ghost values are never stored: the accessors apply the boundary conditions of
  * App. A.4 (Neumann/periodic cells; no-slip/periodic edges).
+ *
+ * The projection scheme (sec. 6.2, eqs. (pj-num-mx)-(pj-num-chem)) is the
+ * second option (opts.scheme).  Its unknowns are c, mubar, pbar and the
+ * intermediate velocity u~ (stored in the face fields during a step); the
+ * velocity of time n+1 is eliminated through the projection equation
+ * (pj-num-pjx), which gives it face by face from u~ and the cell unknowns
+ * (ufin, vfin).  Its smoother is the four steps of sec. 7.2 (see halfsweep).
+ * After a converged step the face fields hold the velocity of time n+1.
  */
 #include <complex.h>
 #include <math.h>
@@ -74,6 +82,12 @@ struct orc_ctx {
     int pf, pi, pj;
     double ph;
     const double *pdir[NSTATE];
+    /* projection scheme: the velocity of time n+1 frozen on level fzlev
+     * (during the point update of c, mubar), and the intermediate velocity of
+     * the last completed step on the finest level */
+    const Level *fzlev;
+    double *ufz, *vfz;
+    double *ut_save[2];
     /* statistics of the last step */
     int nv;
     double hist[ORC_MAXV + 1][NSTATE];
@@ -118,6 +132,8 @@ static cx raw(const orc_ctx *o, const Level *L, int fld, int i, int j)
     }
     return v;
 }
+
+static int projection(const orc_ctx *o) { return o->o.scheme == ORC_PROJECTION; }
 
 static void die(const char *msg, int a, int b)
 {
@@ -247,6 +263,39 @@ static cx cell_rho_ay_vn(const orc_ctx *o, const Level *L, int i, int j) { retur
 static cx theta(const orc_ctx *o, const Level *L, int i, int j) { return d_x(o, L, F_U, i, j) + d_y(o, L, F_V, i, j); }
 
 /* ------------------------------------------------------------------------- */
+/* projection scheme: velocity of time n+1 from the projection equation       */
+/* (pj-num-pjx), A rho (u - u~)/dt = -D pbar/M + A(rho_ew mubar) D c/M, with   */
+/* rho = rho(c) and c, mubar of the iterate (time n+1) in the surface-tension */
+/* form of App. A.6, and gravity in the projection equation as in the         */
+/* time-discrete scheme (pj-pj), -(1/Fr)(A_y rho - rho_ref) on north-south     */
+/* faces.  Zero on wall faces (normal velocity, (pj-dis-bc3)); only faces of  */
+/* interior rows are asked for.                                                */
+
+/* east-west face (i,j), 0 <= i <= m1 */
+static cx ufin(const orc_ctx *o, const Level *L, int i, int j)
+{
+    if (o->g.bcx == ORC_PERIODIC) i = wrap(i, L->m1);
+    else if (i <= 0 || i >= L->m1) return 0.0;
+    if (L == o->fzlev) return o->ufz[(size_t)j * L->m1 + i];
+    cx Ar = A_xc(o, L, F_C, 1, i, j);
+    cx st = 0.5 * (rho_c(o, L, F_C, i, j) * cellv(o, L, F_MU, i - 1, j) + rho_c(o, L, F_C, i - 1, j) * cellv(o, L, F_MU, i, j))
+          * D_xc(o, L, F_C, i, j);
+    return uv(o, L, F_U, i, j) + o->dt / Ar * (st - D_xc(o, L, F_P, i, j)) / o->p.M;
+}
+/* north-south face (i,j), 0 <= j <= m2 */
+static cx vfin(const orc_ctx *o, const Level *L, int i, int j)
+{
+    if (o->g.bcy == ORC_PERIODIC) j = wrap(j, L->m2);
+    else if (j <= 0 || j >= L->m2) return 0.0;
+    if (L == o->fzlev) return o->vfz[(size_t)j * L->m1 + i];
+    cx Ar = A_yc(o, L, F_C, 1, i, j);
+    cx st = 0.5 * (rho_c(o, L, F_C, i, j) * cellv(o, L, F_MU, i, j - 1) + rho_c(o, L, F_C, i, j - 1) * cellv(o, L, F_MU, i, j))
+          * D_yc(o, L, F_C, i, j);
+    cx grav = o->p.inv_Fr * (Ar - o->p.rho_ref);
+    return vv(o, L, F_V, i, j) + o->dt / Ar * ((st - D_yc(o, L, F_P, i, j)) / o->p.M - grav);
+}
+
+/* ------------------------------------------------------------------------- */
 /* residuals: left side minus right side of each equation                      */
 
 /* x-momentum (pm-num-mx), first row, at the east-west face (i,j) */
@@ -267,8 +316,11 @@ static cx res_u(const orc_ctx *o, const Level *L, int i, int j)
     cx visc = (visc_n(o, L, i, j) * d_x(o, L, F_U, i, j) - visc_n(o, L, i - 1, j) * d_x(o, L, F_U, i - 1, j)) / h + (vx_visc(o, L, i, j + 1) - vx_visc(o, L, i, j)) / h;
     /* D_x(mu div_d u) */
     cx gd = (visc_n(o, L, i, j) * theta(o, L, i, j) - visc_n(o, L, i - 1, j) * theta(o, L, i - 1, j)) / h;
-    return Arn * (u - un) / dt + adv + (Ars - Arn) / (2.0 * dt) * u + 0.5 * div * u
-         + D_xc(o, L, F_P, i, j) / o->p.M - st / o->p.M - visc / o->p.Re - gd / (3.0 * o->p.Re);
+    cx N = Arn * (u - un) / dt + adv + (Ars - Arn) / (2.0 * dt) * u + 0.5 * div * u - visc / o->p.Re - gd / (3.0 * o->p.Re);
+    /* (pj-num-mx) for the intermediate velocity has neither pressure nor
+     * surface tension; they act in the projection equation */
+    if (!projection(o)) N += D_xc(o, L, F_P, i, j) / o->p.M - st / o->p.M;
+    return N;
 }
 
 /* y-momentum (pm-num-mx), second row, at the north-south face (i,j) */
@@ -288,8 +340,9 @@ static cx res_v(const orc_ctx *o, const Level *L, int i, int j)
     cx gd = (visc_n(o, L, i, j) * theta(o, L, i, j) - visc_n(o, L, i, j - 1) * theta(o, L, i, j - 1)) / h;
     /* gravity -(1/Fr) A_y rho^n j, measured against a reference density */
     cx grav = o->p.inv_Fr * (Arn - o->p.rho_ref);
-    return Arn * (v - vn) / dt + adv + (Ars - Arn) / (2.0 * dt) * v + 0.5 * div * v
-         + D_yc(o, L, F_P, i, j) / o->p.M - st / o->p.M - visc / o->p.Re - gd / (3.0 * o->p.Re) + grav;
+    cx N = Arn * (v - vn) / dt + adv + (Ars - Arn) / (2.0 * dt) * v + 0.5 * div * v - visc / o->p.Re - gd / (3.0 * o->p.Re);
+    if (!projection(o)) N += D_yc(o, L, F_P, i, j) / o->p.M - st / o->p.M + grav;
+    return N;
 }
 
 /* variable-coefficient diffusion div_d(A k grad_D phi) at cell (i,j); the
@@ -317,12 +370,14 @@ static cx divAkgrad(const orc_ctx *o, const Level *L, int kc, int fld, int i, in
     return (fe - fw) / h + (fn - fs) / h;
 }
 
-/* mass equation (pm-num-mass) at cell (i,j) */
+/* mass equation (pm-num-mass) at cell (i,j); projection scheme (pj-num-mass)
+ * with the velocity of time n+1 */
 static cx res_p(const orc_ctx *o, const Level *L, int i, int j)
 {
     double a = o->alpha, Pe = o->p.Pe;
-    return d_x(o, L, F_U, i, j) + d_y(o, L, F_V, i, j)
-         - a / Pe * divAkgrad(o, L, 0, F_MU, i, j) - a * a / Pe * divAkgrad(o, L, 0, F_P, i, j);
+    cx div = projection(o) ? (ufin(o, L, i + 1, j) - ufin(o, L, i, j)) / L->h + (vfin(o, L, i, j + 1) - vfin(o, L, i, j)) / L->h
+                           : d_x(o, L, F_U, i, j) + d_y(o, L, F_V, i, j);
+    return div - a / Pe * divAkgrad(o, L, 0, F_MU, i, j) - a * a / Pe * divAkgrad(o, L, 0, F_P, i, j);
 }
 
 /* phase equation (pm-num-phase) with the advection form (e1e2), App. A.5 */
@@ -331,6 +386,16 @@ static cx res_c(const orc_ctx *o, const Level *L, int i, int j)
     const double h = L->h;
     double a = o->alpha, Pe = o->p.Pe;
     cx c = cellv(o, L, F_C, i, j), cn = cellv(o, L, F_CN, i, j);
+    if (projection(o)) {
+        /* (pj-num-phase): rho^n (c - c^n)/dt + rho^{n+1} u^{n+1} . grad c^{n+1} in
+         * the form (e1e2) of App. A.5 with every factor at time n+1 */
+        cx ax = 0.5 * (rho_c(o, L, F_C, i + 1, j) * (cellv(o, L, F_C, i + 1, j) - c) / h * ufin(o, L, i + 1, j)
+                     + rho_c(o, L, F_C, i - 1, j) * (c - cellv(o, L, F_C, i - 1, j)) / h * ufin(o, L, i, j));
+        cx ay = 0.5 * (rho_c(o, L, F_C, i, j + 1) * (cellv(o, L, F_C, i, j + 1) - c) / h * vfin(o, L, i, j + 1)
+                     + rho_c(o, L, F_C, i, j - 1) * (c - cellv(o, L, F_C, i, j - 1)) / h * vfin(o, L, i, j));
+        return rho_of(o, cn) * (c - cn) / o->dt + ax + ay
+             - divAkgrad(o, L, 0, F_MU, i, j) / Pe - a / Pe * divAkgrad(o, L, 0, F_P, i, j);
+    }
     cx advx = 0.5 * (rho_c(o, L, F_CN, i + 1, j) * (cellv(o, L, F_CN, i + 1, j) - cn) / h * uv(o, L, F_U, i + 1, j)
                    + rho_c(o, L, F_CN, i - 1, j) * (cn - cellv(o, L, F_CN, i - 1, j)) / h * uv(o, L, F_U, i, j));
     cx advy = 0.5 * (rho_c(o, L, F_CN, i, j + 1) * (cellv(o, L, F_CN, i, j + 1) - cn) / h * vv(o, L, F_V, i, j + 1)
@@ -355,7 +420,9 @@ static cx res_mu(const orc_ctx *o, const Level *L, int i, int j)
     cx rhalf = 0.5 * (rs + rn), Fhalf = 0.5 * (Fdw(c) + Fdw(cn));
     cx Ghalf = 0.5 * (gradsq(o, L, F_C, i, j) + gradsq(o, L, F_CN, i, j));
     cx r = rsec(o, c, cn);
-    return rs * mu - o->K1 * (rhalf * gsec(c, cn) + Fhalf * r) - o->K2 * Ghalf * r + o->K3 * divAkgrad(o, L, 1, -1, i, j);
+    /* (pj-num-chem) has rho^n mubar where (pm-num-chem) has rho^{n+1} mubar */
+    cx rm = projection(o) ? rn : rs;
+    return rm * mu - o->K1 * (rhalf * gsec(c, cn) + Fhalf * r) - o->K2 * Ghalf * r + o->K3 * divAkgrad(o, L, 1, -1, i, j);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -459,8 +526,10 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
     if (ie >= 0 && u_unknown(o, L, ie)) { fld[n] = F_U; ci[n] = ie; cj[n] = j; n++; }
     if (v_unknown(o, L, j)) { fld[n] = F_V; ci[n] = i; cj[n] = j; n++; }
     if (jn >= 0 && v_unknown(o, L, jn)) { fld[n] = F_V; ci[n] = i; cj[n] = jn; n++; }
-    fld[n] = F_P; ci[n] = i; cj[n] = j; n++;
-    if (o->o.smoother == ORC_SMOOTH_COUPLED) {
+    /* projection scheme (sec. 7.2, step 2): the four intermediate-velocity
+     * faces alone, on the momentum equations (pj-num-mx) */
+    if (!projection(o)) { fld[n] = F_P; ci[n] = i; cj[n] = j; n++; }
+    if (!projection(o) && o->o.smoother == ORC_SMOOTH_COUPLED) {
         fld[n] = F_C; ci[n] = i; cj[n] = j; n++;
         fld[n] = F_MU; ci[n] = i; cj[n] = j; n++;
     }
@@ -495,6 +564,64 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
     }
 }
 
+/* Projection scheme, step 3 of sec. 7.2 at cell (i,j): one Newton step on the
+ * mass equation (pj-num-mass) in pbar of the cell, the velocity of time n+1
+ * taken from the projection of the current unknowns (through which pbar acts
+ * on the four faces); exact, the equation being linear in pbar. */
+static void p_point(orc_ctx *o, Level *L, int i, int j)
+{
+    size_t k = (size_t)j * L->m1 + i;
+    perturb(o, L, F_P, i, j);
+    cx r = res_p(o, L, i, j);
+    unperturb(o);
+    double J = cimag(r) / CSTEP;
+    if (J == 0.0) return;
+    L->f[F_P][k] += (L->rhs[2][k] - creal(r)) / J;
+}
+
+/* Projection scheme, one colour (sec. 7.2, steps per cell of the colour):
+ *   1. one Newton step on (N_c, N_mu) in (c, mubar), the velocity of time n+1
+ *      frozen at its value before the half-sweep (the stored velocity of the
+ *      paper's sequential sweep);
+ *   2. the Vanka box of the four intermediate-velocity faces (exact: the
+ *      momentum equations are linear in u~), Jacobi within the colour as in
+ *      the primitive scheme;
+ *   3. the pbar update above, with the new u~, c and mubar;
+ *   4. the velocity of time n+1 is not stored: it is the projection of the
+ *      current unknowns wherever it is used.
+ * Steps 2 and 3 of one cell read only its own box faces and cells of the
+ * other colour besides its own c, mubar, pbar, so all boxes of the colour
+ * may take step 2 before any takes step 3. */
+static void halfsweep_pj(orc_ctx *o, int l, int colour)
+{
+    Level *L = &o->lev[l];
+    size_t n = (size_t)L->m1 * L->m2;
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++) {
+            size_t k = (size_t)j * L->m1 + i;
+            o->ufz[k] = u_unknown(o, L, i) ? creal(ufin(o, L, i, j)) : 0.0;
+            o->vfz[k] = v_unknown(o, L, j) ? creal(vfin(o, L, i, j)) : 0.0;
+        }
+    o->fzlev = L;
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++)
+            if (((i + j) & 1) == colour) ch_point(o, L, i, j);
+    o->fzlev = NULL;
+    double *unew = malloc(n * sizeof(double)), *vnew = malloc(n * sizeof(double));
+    memcpy(unew, L->f[F_U], n * sizeof(double));
+    memcpy(vnew, L->f[F_V], n * sizeof(double));
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++)
+            if (((i + j) & 1) == colour) vanka_box(o, L, i, j, unew, vnew);
+    memcpy(L->f[F_U], unew, n * sizeof(double));
+    memcpy(L->f[F_V], vnew, n * sizeof(double));
+    free(unew);
+    free(vnew);
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++)
+            if (((i + j) & 1) == colour) p_point(o, L, i, j);
+}
+
 /* One colour half-sweep (reading of sec. 7.1): colour = (i+j) mod 2.
  * Segregated smoother (the paper's two steps): first the pointwise CH update
  * at every cell of the colour (these are independent: their stencils only
@@ -507,6 +634,7 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
  * its colour and are updated in place. */
 static void halfsweep(orc_ctx *o, int l, int colour)
 {
+    if (projection(o)) { halfsweep_pj(o, l, colour); return; }
     Level *L = &o->lev[l];
     size_t n = (size_t)L->m1 * L->m2;
     if (o->o.smoother == ORC_SMOOTH_SEGREGATED)
@@ -706,6 +834,10 @@ orc_ctx *orc_create(const orc_grid *g, const orc_params *p, const orc_opts *opt)
     }
     size_t n0 = (size_t)g->m1 * g->m2;
     for (int q = 0; q < NSTATE; q++) o->save[q] = zalloc(n0);
+    o->ufz = zalloc(n0);
+    o->vfz = zalloc(n0);
+    o->ut_save[0] = zalloc(n0);
+    o->ut_save[1] = zalloc(n0);
     return o;
 }
 
@@ -718,6 +850,7 @@ void orc_destroy(orc_ctx *o)
         for (int q = 0; q < NSTATE; q++) { free(L->rhs[q]); free(L->w0[q]); free(L->r[q]); }
     }
     for (int q = 0; q < NSTATE; q++) free(o->save[q]);
+    free(o->ufz); free(o->vfz); free(o->ut_save[0]); free(o->ut_save[1]);
     free(o);
 }
 
@@ -813,6 +946,42 @@ static void restore(orc_ctx *o)
     for (int q = 0; q < NSTATE; q++) memcpy(L->f[q], o->save[q], n * sizeof(double));
 }
 
+/* projection scheme, end of a converged step: the face fields take the
+ * velocity of time n+1; the intermediate velocity is kept for the
+ * dissipation */
+static void project_final(orc_ctx *o)
+{
+    Level *L = &o->lev[0];
+    size_t n = (size_t)L->m1 * L->m2;
+    double *uf = zalloc(n), *vf = zalloc(n);
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++) {
+            size_t k = (size_t)j * L->m1 + i;
+            if (u_unknown(o, L, i)) uf[k] = creal(ufin(o, L, i, j));
+            if (v_unknown(o, L, j)) vf[k] = creal(vfin(o, L, i, j));
+        }
+    memcpy(o->ut_save[0], L->f[F_U], n * sizeof(double));
+    memcpy(o->ut_save[1], L->f[F_V], n * sizeof(double));
+    memcpy(L->f[F_U], uf, n * sizeof(double));
+    memcpy(L->f[F_V], vf, n * sizeof(double));
+    free(uf);
+    free(vf);
+}
+
+/* projection scheme: the velocity of time n+1 from the current iterate of
+ * the finest level (zero on wall faces; u(i,j) on the west face of cell
+ * (i,j), v(i,j) on its south face) */
+void orc_velocity_np1(orc_ctx *o, double *u, double *v)
+{
+    Level *L = &o->lev[0];
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++) {
+            size_t k = (size_t)j * L->m1 + i;
+            u[k] = u_unknown(o, L, i) ? creal(ufin(o, L, i, j)) : 0.0;
+            v[k] = v_unknown(o, L, j) ? creal(vfin(o, L, i, j)) : 0.0;
+        }
+}
+
 int orc_solve(orc_ctx *o)
 {
     double nr[NSTATE];
@@ -831,6 +1000,7 @@ int orc_solve(orc_ctx *o)
         for (int e = 0; e < NSTATE; e++) o->hist[it][e] = nr[e];
         o->nv = it;
     }
+    if (projection(o)) project_final(o);
     o->in_step = 0;
     return ORC_OK;
 }
@@ -912,9 +1082,40 @@ void orc_energy(orc_ctx *o, double out[5])
  *   out[1] = dt/(3Re) ||sqrt(mu) div_d u||^2
  *   out[2] = dt/(M Pe) ||sqrt(m) grad_D mu_c||^2,  mu_c = mubar + alpha pbar
  *   out[3] = 1/2 ||sqrt(rho^n)(u^{n+1} - u^n)||^2
+ *   out[4] = 0
  * with the vertex inner product <phi f, g>_vc = (phi, calA(f g))_2, i.e. each
- * vertex weighted by a quarter of each adjacent interior cell. */
-void orc_dissipation(orc_ctx *o, double out[4])
+ * vertex weighted by a quarter of each adjacent interior cell.  Projection
+ * scheme (Theorem of sec. 6.2): out[0], out[1], out[3] on the intermediate
+ * velocity u~ in place of u^{n+1}, and
+ *   out[4] = 1/2 ||sqrt(rho^{n+1})(u^{n+1} - u~)||^2  (face weights A rho(c^{n+1})). */
+static void dissipation_of(orc_ctx *o, double out[4]);
+void orc_dissipation(orc_ctx *o, double out[5])
+{
+    Level *L = &o->lev[0];
+    out[4] = 0.0;
+    if (!projection(o)) { dissipation_of(o, out); return; }
+    double *uf = L->f[F_U], *vf = L->f[F_V];
+    L->f[F_U] = o->ut_save[0];
+    L->f[F_V] = o->ut_save[1];
+    dissipation_of(o, out);
+    L->f[F_U] = uf;
+    L->f[F_V] = vf;
+    double g5 = 0.0;
+    for (int j = 0; j < L->m2; j++)
+        for (int i = 0; i < L->m1; i++) {
+            size_t k = (size_t)j * L->m1 + i;
+            if (u_unknown(o, L, i)) {
+                double d = uf[k] - o->ut_save[0][k];
+                g5 += creal(A_xc(o, L, F_C, 1, i, j)) * d * d;
+            }
+            if (v_unknown(o, L, j)) {
+                double d = vf[k] - o->ut_save[1][k];
+                g5 += creal(A_yc(o, L, F_C, 1, i, j)) * d * d;
+            }
+        }
+    out[4] = 0.5 * L->h * L->h * g5;
+}
+static void dissipation_of(orc_ctx *o, double out[4])
 {
     Level *L = &o->lev[0];
     double h = L->h, h2 = h * h;

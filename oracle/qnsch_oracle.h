@@ -28,12 +28,14 @@ typedef struct {
 } orc_params;
 
 enum { ORC_SMOOTH_SEGREGATED = 0, ORC_SMOOTH_COUPLED = 1 };
+enum { ORC_PRIMITIVE = 0, ORC_PROJECTION = 1 };
 
 typedef struct {
     double tol;
     int max_vcycles, nu1, nu2, nu_coarse;
     double vanka_omega;
-    int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED */
+    int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED (primitive scheme) */
+    int scheme;   /* ORC_PRIMITIVE (sec. 6.1) or ORC_PROJECTION (sec. 6.2) */
 } orc_opts;
 
 typedef struct orc_ctx orc_ctx;
@@ -52,12 +54,13 @@ int orc_step(orc_ctx *, double dt);
 int orc_stats(const orc_ctx *, double *hist);
 void orc_mass(orc_ctx *, double out[2]);
 void orc_energy(orc_ctx *, double out[5]);
-void orc_dissipation(orc_ctx *, double out[4]);
+void orc_dissipation(orc_ctx *, double out[5]);
 void orc_diagnostics(orc_ctx *, double out[8]);
 int orc_num_unknowns(const orc_ctx *);
 int orc_dense(orc_ctx *, double *Nvec, double *Jmat);
 void orc_add_unknowns(orc_ctx *, const double *dx);
 void orc_jvp(orc_ctx *, const double *d, double *out);
+void orc_velocity_np1(orc_ctx *, double *u, double *v);
 void orc_material(const orc_ctx *, double c1, double c0, double out[6]);
 
 #endif

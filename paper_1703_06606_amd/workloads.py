@@ -52,6 +52,7 @@ def _centres(m1, m2, h):
 
 
 SMOOTH_SEGREGATED, SMOOTH_COUPLED = 0, 1
+PRIMITIVE, PROJECTION = 0, 1
 
 
 def default_opts(tol=1e-10):
