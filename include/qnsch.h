@@ -74,6 +74,22 @@ enum { QNSCH_FP64 = 0, QNSCH_MIXED = 1 };
  * box keeps the V-cycle factor bounded under refinement at density ratios
  * where the segregated one degrades. */
 enum { QNSCH_SMOOTH_SEGREGATED = 0, QNSCH_SMOOTH_COUPLED = 1 };
+/* Scheme.  PRIMITIVE (default): the primitive-variable scheme of sec. 6.1.
+ * PROJECTION: the projection scheme of sec. 6.2, eqs. (pj-num-mx)-(pj-num-chem):
+ * an intermediate velocity u~ from the momentum equation without pressure,
+ * surface tension and gravity, the velocity of time n+1 from the projection
+ * equation (pj-num-pjx) (gravity acting there, as in the time-discrete scheme
+ * (pj-pj)), and the mass, phase and chemical-potential equations with it
+ * (rho^n in the time derivative of c and in rho^n mubar, the advection of c at
+ * time n+1).  The velocity of time n+1 is eliminated, so the unknowns are c,
+ * mubar, pbar and u~; the smoother is the one of sec. 7.2 (per cell a Newton
+ * step on (c, mubar) with the velocity of time n+1 held, the Vanka box of the
+ * four u~ faces, a Newton step in pbar on the mass equation), whatever
+ * `smoother` says.  During a step the velocity arguments and results of the
+ * phase calls are u~; after a completed step (qnsch_step, or qnsch_end_step
+ * after phases) they are the velocity of time n+1.  FP64 only; the server
+ * accepts primitive requests only. */
+enum { QNSCH_PRIMITIVE = 0, QNSCH_PROJECTION = 1 };
 
 typedef struct {
     int32_t m1, m2;     /* cells in x and y; both even, divisible by 2^levels */
@@ -111,6 +127,7 @@ typedef struct {
     int32_t nu_coarse;   /* sweeps on the coarsest level */
     double vanka_omega;  /* relaxation factor of the box update (1 = exact box solve) */
     int32_t smoother;    /* QNSCH_SMOOTH_COUPLED or QNSCH_SMOOTH_SEGREGATED */
+    int32_t scheme;      /* QNSCH_PRIMITIVE or QNSCH_PROJECTION */
 } qnsch_opts;
 
 typedef struct {
@@ -123,7 +140,7 @@ typedef struct {
 typedef struct qnsch_ctx qnsch_ctx;
 
 /* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 30 coarse sweeps, omega 1,
- * coupled smoother. */
+ * coupled smoother, primitive scheme. */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
@@ -158,7 +175,8 @@ int qnsch_step(qnsch_ctx *ctx, double dt);
  * pbar to zero; residual returns r = -N(w) of the current iterate (5 fields of
  * m1*m2, order c, mu, p, u, v; NULL to skip) and its norms; halfsweep runs one
  * colour half-sweep (colour 0: (i+j) even) on the finest level; end_step
- * commits the iterate as the new state. */
+ * commits the iterate as the new state (projection scheme: replaces u~ by the
+ * velocity of time n+1). */
 int qnsch_begin_step(qnsch_ctx *ctx, double dt);
 int qnsch_vcycle(qnsch_ctx *ctx);
 int qnsch_residual(qnsch_ctx *ctx, double *r_out, double norms[5]);
@@ -182,12 +200,14 @@ int qnsch_energy(qnsch_ctx *ctx, double out[5]);
  * A.7), from the new state and the time-n data of that step:
  *   out[0] = dt/Re ||sqrt(mu) grad_d u||^2,  out[1] = dt/(3Re) ||sqrt(mu) div_d u||^2,
  *   out[2] = dt/(M Pe) ||sqrt(m) grad_D mu_c||^2 (mu_c = mubar + alpha pbar),
- *   out[3] = 1/2 ||sqrt(rho^n)(u^{n+1} - u^n)||^2;
+ *   out[3] = 1/2 ||sqrt(rho^n)(u^{n+1} - u^n)||^2,  out[4] = 0;
  * mu, m, rho at c^n; the vertex norm weights each vertex by a quarter of
- * each adjacent cell.  With walls in y the energy law reads
- * E^{n+1} - E^n + sum(out) = 0 at the converged solution.  QNSCH_EBUSY
- * before the first step. */
-int qnsch_dissipation(qnsch_ctx *ctx, double out[4]);
+ * each adjacent cell.  Projection scheme (Theorem of sec. 6.2): out[0], out[1]
+ * and out[3] on the intermediate velocity u~ in place of u^{n+1}, and
+ * out[4] = 1/2 ||sqrt(rho(c^{n+1}))(u^{n+1} - u~)||^2.  With walls in y the
+ * energy law reads E^{n+1} - E^n + sum(out) = 0 at the converged solution.
+ * QNSCH_EBUSY before the first step. */
+int qnsch_dissipation(qnsch_ctx *ctx, double out[5]);
 /* Physical diagnostics of the current state (sec. 8):
  *   out[0] = V_c = sum(c v) / sum(c), v at the cell the mean of its south and
  *            north faces (rising velocity of the c = 1 phase);

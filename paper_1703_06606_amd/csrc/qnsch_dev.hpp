@@ -5,7 +5,8 @@
 // "left side minus right side", N(w) = 0 at time n+1.  The smoother is the
 // one of sec. 7.1: per cell a Newton step on the Cahn-Hilliard pair
 // (c, mubar), then a Vanka box solve for the four faces and the pressure of
-// the cell, in red-black order.
+// the cell (or one Newton step on all seven), in red-black order.  The
+// projection scheme of sec. 6.2 is the second option (P.scheme, end of file).
 //
 // Layout: every field of a level is an m2 x pitch array of doubles, row j,
 // column i.  Cell fields at cell (i,j); u(i,j) on the west face of cell (i,j)
@@ -26,8 +27,9 @@ struct Phys {
     double rho1, rho2, rho12, drho;  // rho(c) = rho12 / (drho c + rho1)
     double visc1, visc2, visc12, dvisc;
     double alpha, inv_Re, inv_M, inv_Pe, K1, K2, K3, inv_Fr, rho_ref, mob_reg;
-    double inv_dt;
+    double inv_dt, dt;
     int coupled; // smoother: 1 = one Newton step on the seven-unknown box, 0 = the two steps
+    int scheme;  // 0 = primitive scheme (sec. 6.1), 1 = projection scheme (sec. 6.2)
 };
 
 struct View {
@@ -380,7 +382,8 @@ struct FaceEq {
     double N, diag;
 };
 
-__device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax &a, int ef, int it, double ih)
+__device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax &a, int ef, int it, double ih,
+                                          bool proj = false)
 {
     const double ih2 = ih * ih;
     const int eL = ef - a.dn, eR = ef, dt = a.dt;
@@ -406,11 +409,14 @@ __device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax
     q.N = Arn * (u0 - un0) * P.inv_dt
         + 0.5 * ih * (wR * uE - wL * uW + Rt * Vt * uN - Rb * Vb * uS)
         + 0.5 * (Ars - Arn) * P.inv_dt * u0
-        + P.inv_M * ih * (tq(T, T_P, eR) - tq(T, T_P, eL))
-        - P.inv_M * ih * 0.5 * (rR * tq(T, T_MU, eL) + rL * tq(T, T_MU, eR)) * (nR - nL)
         - P.inv_Re * ih2 * (mvR * (uE - u0) - mvL * (u0 - uW) + nut * (uN - u0) - nub * (u0 - uS))
-        - (P.inv_Re / 3.0) * ih * (mvR * thR - mvL * thL)
-        + a.grav * P.inv_Fr * (Arn - P.rho_ref);
+        - (P.inv_Re / 3.0) * ih * (mvR * thR - mvL * thL);
+    // the projection scheme's intermediate velocity (pj-num-mx) has neither
+    // pressure, surface tension nor gravity: they act in (pj-num-pjx)
+    if (!proj)
+        q.N += P.inv_M * ih * (tq(T, T_P, eR) - tq(T, T_P, eL))
+             - P.inv_M * ih * 0.5 * (rR * tq(T, T_MU, eL) + rL * tq(T, T_MU, eR)) * (nR - nL)
+             + a.grav * P.inv_Fr * (Arn - P.rho_ref);
     // own-face derivative; across a tangential wall the reflected ghost doubles
     // the viscous coupling and the advection coefficient enters with a sign flip
     const double gt = (!a.pert && it == a.mt - 1) ? 1.0 : 0.0, gb = (!a.pert && it == 0) ? 1.0 : 0.0;
@@ -422,6 +428,15 @@ __device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax
 __device__ __forceinline__ double ldf(const double *f, const View &L, int i, int j)
 {
     return f ? f[(size_t)j * L.pitch + i] : 0.0;
+}
+
+// face right-hand side of the lane's axis: the select is taken on the pointer
+// values (a select between the two struct members made the compiler stage
+// them in scratch memory)
+__device__ __forceinline__ const double *face_rhs(const Rhs &F, int hlf)
+{
+    const uintptr_t a = (uintptr_t)F.fu, b = (uintptr_t)F.fv;
+    return (const double *)(hlf ? b : a);
 }
 
 // --------------------------------------------------------------------------
@@ -446,9 +461,18 @@ __device__ __forceinline__ double ldf(const double *f, const View &L, int i, int
 // form c, mubar and rho(c) of the cell are also written to the tile between
 // the steps (identical values from both lanes), which no other pair of this
 // colour reads.
+__device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
+                              int i, int j, int hlf, double omega);
+__device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j, int hlf,
+                              double &rc, double &rm, double &rp, double &rf);
+
 __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
                                            double *vnew, int i, int j, int hlf, double omega)
 {
+    if (P.scheme) {
+        relax_pair_pj(P, L, T, F, unew, vnew, i, j, hlf, omega);
+        return;
+    }
     const size_t k = (size_t)j * L.pitch + i;
     const double ih = L.inv_h, ih2 = ih * ih;
     const int e = T.idx(i, j);
@@ -490,7 +514,7 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const FaceEq flo = face_eq(P, T, a, e, a.it, ih);
     const FaceEq fhi = face_eq(P, T, a, e + a.dn, a.it, ih);
-    const double *fN = hlf ? F.fv : F.fu;
+    const double *fN = face_rhs(F, hlf);
     const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
     const size_t khi = (size_t)jhi * L.pitch + ihi;
     const double blo = hlo ? ldf(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
@@ -591,10 +615,15 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
         L.c[k] = c0 + dc;
         L.mu[k] = m0 + kbm - kmc * dc;
     }
-    double *dst = hlf ? vnew : unew;
     const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
-    if (hlo) dst[k] = tq(T, a.FN, e) + omega * dl;
-    if (hhi) dst[khi] = tq(T, a.FN, e + a.dn) + omega * dh;
+    const double nlo = tq(T, a.FN, e) + omega * dl, nhi = tq(T, a.FN, e + a.dn) + omega * dh;
+    if (hlf) {
+        if (hlo) vnew[k] = nlo;
+        if (hhi) vnew[khi] = nhi;
+    } else {
+        if (hlo) unew[k] = nlo;
+        if (hhi) unew[khi] = nhi;
+    }
     if (hlf == 0) L.p[k] = tq(T, T_P, e) + omega * b[4];
 }
 
@@ -605,6 +634,10 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
 __device__ __forceinline__ void resid_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j,
                                            int hlf, double &rc, double &rm, double &rp, double &rf)
 {
+    if (P.scheme) {
+        resid_pair_pj(P, L, T, F, i, j, hlf, rc, rm, rp, rf);
+        return;
+    }
     const int e = T.idx(i, j);
     const Ax a = make_ax(L, T, i, j, hlf);
     const CellAx s = cell_sum(cell_axis(T, a, e, L.inv_h));
@@ -614,7 +647,186 @@ __device__ __forceinline__ void resid_pair(const Phys &P, const View &L, const T
     rp = ldf(F.fp, L, i, j) - q.Np;
     const bool hlo = a.per || a.ia >= 1;
     const FaceEq f = face_eq(P, T, a, e, a.it, L.inv_h);
-    rf = hlo ? ldf(hlf ? F.fv : F.fu, L, i, j) - f.N : 0.0;
+    rf = hlo ? ldf(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
+}
+
+// --------------------------------------------------------------------------
+// Projection scheme (sec. 6.2).  The unknowns are c, mubar, pbar and the
+// intermediate velocity u~, which the face fields (T_U, T_V) hold during a
+// step.  The velocity of time n+1 is eliminated through the projection
+// equation (pj-num-pjx): on the face at element ef of the lane's axis,
+//   u = u~ + dt / A rho (A(rho_ew mubar) D c / M - D pbar / M - grav),
+// rho = rho(c) and c, mubar of the iterate, grav = (1/Fr)(A_y rho - rho_ref)
+// on north-south faces (gravity acts in the projection equation, as in the
+// time-discrete scheme (pj-pj)); zero on a wall face.  ut is u~ on the face.
+__device__ __forceinline__ double face_final(const Phys &P, const Tile &T, const Ax &a, int ef, double ih, bool unk,
+                                             double ut)
+{
+    const int eL = ef - a.dn;
+    const double rL = tq(T, T_RS, eL), rR = tq(T, T_RS, ef), Ar = 0.5 * (rL + rR);
+    const double st = 0.5 * (rR * tq(T, T_MU, eL) + rL * tq(T, T_MU, ef)) * (tq(T, T_C, ef) - tq(T, T_C, eL)) * ih;
+    const double f = P.inv_M * (st - (tq(T, T_P, ef) - tq(T, T_P, eL)) * ih) - a.grav * P.inv_Fr * (Ar - P.rho_ref);
+    return unk ? ut + P.dt * frcp(Ar) * f : 0.0;
+}
+
+// axis parts of the projection cell equations from the velocity of time n+1
+// on the lane's two faces (ulo, uhi): the advection of (pj-num-phase) in the
+// form (e1e2) of App. A.5 at time n+1, its derivative in the cell's own c (the
+// velocities held fixed), and the divergence of (pj-num-mass)
+struct PjAx {
+    double adv, dadv, div;
+};
+__device__ __forceinline__ PjAx pj_axis(const Tile &T, const Ax &a, int e, double ih, double ulo, double uhi)
+{
+    const int eP = e + a.dn, eM = e - a.dn;
+    const double c = tq(T, T_C, e), rP = tq(T, T_RS, eP), rM = tq(T, T_RS, eM);
+    PjAx x;
+    x.adv = 0.5 * ih * (rP * (tq(T, T_C, eP) - c) * uhi + rM * (c - tq(T, T_C, eM)) * ulo);
+    x.dadv = 0.5 * ih * (rM * ulo - rP * uhi);
+    x.div = ih * (uhi - ulo);
+    return x;
+}
+
+// Smoother of sec. 7.2 for one cell of the current colour, by a lane pair:
+//  1. one Newton step on (N_c, N_mu) in (c, mubar) of the cell, the velocity
+//     of time n+1 on its faces held at its value before the update;
+//  2. the Vanka box of the four intermediate-velocity faces on (pj-num-mx),
+//     exact (linear in u~), Jacobi within the colour;
+//  3. one Newton step in pbar on the mass equation (pj-num-mass) with the
+//     velocity of time n+1 from the new u~, c, mubar (exact: linear in pbar);
+//  4. the velocity of time n+1 is never stored, so nothing is left to update.
+// (pj-num-phase) and (pj-num-chem) differ from the primitive equations in
+// rho^n (c - c^n)/dt, the advection at time n+1 and rho^n mubar.  The tile
+// entries of the cell (c, mubar, rho(c)) are updated after step 1; no other
+// pair of this colour reads them.
+__device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
+                              int i, int j, int hlf, double omega)
+{
+    const size_t k = (size_t)j * L.pitch + i;
+    const double ih = L.inv_h, ih2 = ih * ih;
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
+    const int st = T.W * T.H;
+    // ---- step 1
+    const double ulo0 = face_final(P, T, a, e, ih, hlo, tq(T, a.FN, e));
+    const double uhi0 = face_final(P, T, a, e + a.dn, ih, hhi, tq(T, a.FN, e + a.dn));
+    const PjAx x0 = pj_axis(T, a, e, ih, ulo0, uhi0);
+    const CellAx s = cell_sum(cell_axis(T, a, e, ih));
+    const CellEq q = cell_eq(P, T, e, s);
+    const double adv = x0.adv + other(x0.adv), dadv = x0.dadv + other(x0.dadv);
+    const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e), n0 = tq(T, T_CN, e);
+    const double rs = tq(T, T_RS, e), rn = tq(T, T_RN, e), drs = -P.alpha * rs * rs;
+    const double Nc = rn * (c0 - n0) * P.inv_dt + adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp;
+    const double Nmu = q.Nmu - (rs - rn) * m0;
+    const double Jcc = rn * P.inv_dt + dadv, Jcm = q.Jcm, Jmm = rn, Jmc = q.Jmc - drs * m0;
+    const double r1 = ldf(F.fc, L, i, j) - Nc, r2 = ldf(F.fmu, L, i, j) - Nmu;
+    const double idet = frcp(Jcc * Jmm - Jcm * Jmc);
+    const double cnew = c0 + (Jmm * r1 - Jcm * r2) * idet;
+    const double mnew = m0 + (Jcc * r2 - Jmc * r1) * idet;
+    if (hlf == 0) {
+        L.c[k] = cnew;
+        L.mu[k] = mnew;
+    }
+    T.s[T_C * st + e] = cnew;
+    T.s[T_MU * st + e] = mnew;
+    T.s[T_RS * st + e] = rho_of(P, cnew);
+    // ---- step 2: the intermediate-velocity box
+    const FaceEq flo = face_eq(P, T, a, e, a.it, ih, true);
+    const FaceEq fhi = face_eq(P, T, a, e + a.dn, a.it, ih, true);
+    const double *fN = face_rhs(F, hlf);
+    const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
+    const size_t khi = (size_t)jhi * L.pitch + ihi;
+    const double blo = hlo ? ldf(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
+    const double bhi = hhi ? ldf(fN, L, ihi, jhi) - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
+    const double w_ax = tq(T, T_RN, e) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
+    const double mv0 = tq(T, T_MV, e);
+    const double vis = (4.0 / 3.0) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0;
+    double xlo = 0.0, xhi = 0.0;
+    if (a.per && a.ma == 2) {
+        const double w_o = tq(T, T_RN, e - a.dn) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
+        const double v_o = (4.0 / 3.0) * P.inv_Re * ih2 * tq(T, T_MV, e - a.dn);
+        xlo = -0.5 * ih * w_o - v_o;
+        xhi = 0.5 * ih * w_o - v_o;
+    }
+    const double o_xlo = other(xlo), o_xhi = other(xhi);
+    const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
+    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
+    const double wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
+    double A[4][4], b[4];
+    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi;
+    const double mW = xl ? 1.0 : 0.0, mE = xh ? 1.0 : 0.0, mS = yl ? 1.0 : 0.0, mN = yh ? 1.0 : 0.0;
+    A[0][0] = hlf ? o_dlo : dlo; A[0][1] = mW * (0.5 * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd;
+    A[1][1] = hlf ? o_dhi : dhi; A[1][0] = mE * (-0.5 * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd;
+    A[2][2] = hlf ? dlo : o_dlo; A[2][3] = mS * (0.5 * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd;
+    A[3][3] = hlf ? dhi : o_dhi; A[3][2] = mN * (-0.5 * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd;
+    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    double inv[4];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        inv[c] = frcp(A[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < 4; r++) {
+            const double l = A[r][c] * inv[c];
+#pragma unroll
+            for (int t = c + 1; t < 4; t++) A[r][t] -= l * A[c][t];
+            b[r] -= l * b[c];
+        }
+    }
+    inv[3] = frcp(A[3][3]);
+#pragma unroll
+    for (int c = 3; c >= 0; c--) {
+        double acc = b[c];
+#pragma unroll
+        for (int t = c + 1; t < 4; t++) acc -= A[c][t] * b[t];
+        b[c] = acc * inv[c];
+    }
+    const double ulo = tq(T, a.FN, e) + omega * (hlf ? b[2] : b[0]);
+    const double uhi = tq(T, a.FN, e + a.dn) + omega * (hlf ? b[3] : b[1]);
+    if (hlf) {
+        if (hlo) vnew[k] = ulo;
+        if (hhi) vnew[khi] = uhi;
+    } else {
+        if (hlo) unew[k] = ulo;
+        if (hhi) unew[khi] = uhi;
+    }
+    // ---- step 3: pbar from the mass equation with the new u~ (passed by
+    // value: the tile keeps the snapshot that other boxes of this colour read)
+    const double ulo1 = face_final(P, T, a, e, ih, hlo, ulo), uhi1 = face_final(P, T, a, e + a.dn, ih, hhi, uhi);
+    const double Alo = 0.5 * (tq(T, T_RS, e - a.dn) + tq(T, T_RS, e)), Ahi = 0.5 * (tq(T, T_RS, e) + tq(T, T_RS, e + a.dn));
+    const double jax = P.dt * P.inv_M * ih2 * ((hlo ? frcp(Alo) : 0.0) + (hhi ? frcp(Ahi) : 0.0));
+    const double dv = ih * (uhi1 - ulo1);
+    const double div = dv + other(dv), jp = jax + other(jax);
+    const double Lmu_new = s.Lmu - s.Sm * (mnew - m0);
+    const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp;
+    const double Jp = jp + q.Jpp;
+    if (hlf == 0) L.p[k] = tq(T, T_P, e) + (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+}
+
+// residuals of the projection scheme's five equations attached to cell (i,j)
+// (as resid_pair: rf is the intermediate-velocity momentum residual of this
+// lane's west or south face)
+__device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j, int hlf,
+                              double &rc, double &rm, double &rp, double &rf)
+{
+    const double ih = L.inv_h;
+    const int e = T.idx(i, j);
+    const Ax a = make_ax(L, T, i, j, hlf);
+    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
+    const double ulo = face_final(P, T, a, e, ih, hlo, tq(T, a.FN, e));
+    const double uhi = face_final(P, T, a, e + a.dn, ih, hhi, tq(T, a.FN, e + a.dn));
+    const PjAx x = pj_axis(T, a, e, ih, ulo, uhi);
+    const CellAx s = cell_sum(cell_axis(T, a, e, ih));
+    const CellEq q = cell_eq(P, T, e, s);
+    const double adv = x.adv + other(x.adv), div = x.div + other(x.div);
+    const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e), n0 = tq(T, T_CN, e);
+    const double rs = tq(T, T_RS, e), rn = tq(T, T_RN, e);
+    rc = ldf(F.fc, L, i, j) - (rn * (c0 - n0) * P.inv_dt + adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp);
+    rm = ldf(F.fmu, L, i, j) - (q.Nmu - (rs - rn) * m0);
+    rp = ldf(F.fp, L, i, j) - (div - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp);
+    const FaceEq f = face_eq(P, T, a, e, a.it, ih, true);
+    rf = hlo ? ldf(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
 }
 
 } // namespace qn

@@ -477,7 +477,12 @@ __global__ __launch_bounds__(BLK) void k_dissipation(Items it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
-    const View L = view_of(d, it.par[k]);
+    // projection scheme: the viscous parts and the time-difference part are
+    // taken on the intermediate velocity (the other face buffer), and slot 4
+    // sums A rho(c) (u^{n+1} - u~)^2 over the faces
+    const bool pj = d.P.scheme != 0;
+    const View L = view_of(d, pj ? it.par[k] ^ 1 : it.par[k]);
+    const double *uf = d.ub[it.par[k]], *vf = d.vb[it.par[k]];
     const Phys &P = d.P;
     const int b = (int)blockIdx.x - it.start[k];
     const int t = b * BLK + threadIdx.x;
@@ -512,6 +517,10 @@ __global__ __launch_bounds__(BLK) void k_dissipation(Items it)
             v[2] += 0.5 * (mob0 + mob_of(P, cw)) * g * g;
             const double du = L.u[q] - L.un[q];
             v[3] += 0.5 * (r0 + rho_of(P, cw)) * du * du;
+            if (pj) {
+                const double dp = uf[q] - L.u[q];
+                v[4] += 0.5 * (rho_of(P, L.c[q]) + rho_of(P, ldc(L.c, m1, m2, pt, bx, by, i - 1, j))) * dp * dp;
+            }
         }
         if (by || j > 0) {
             const double cs = CN(i, j - 1);
@@ -520,9 +529,47 @@ __global__ __launch_bounds__(BLK) void k_dissipation(Items it)
             v[2] += 0.5 * (mob0 + mob_of(P, cs)) * g * g;
             const double dv = L.v[q] - L.vn[q];
             v[3] += 0.5 * (r0 + rho_of(P, cs)) * dv * dv;
+            if (pj) {
+                const double dp = vf[q] - L.v[q];
+                v[4] += 0.5 * (rho_of(P, L.c[q]) + rho_of(P, ldc(L.c, m1, m2, pt, bx, by, i, j - 1))) * dp * dp;
+            }
         }
     }
     block_sum_store(v, d.partials + (size_t)b * NRED);
+}
+
+// Projection scheme, end of a converged step: the velocity of time n+1 from
+// the projection equation (pj-num-pjx) (as face_final) on every west and
+// south face, written to the other face buffer, which becomes the current
+// one; the intermediate velocity stays in buffer par for the dissipation.
+__global__ __launch_bounds__(BLK) void k_pj_final(Items it)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int par = it.par[k];
+    const View L = view_of(d, par);
+    const Phys &P = d.P;
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= L.m1 * L.m2) return;
+    const int j = t / L.m1, i = t - j * L.m1;
+    const int m1 = L.m1, m2 = L.m2, pt = L.pitch, bx = L.bcx, by = L.bcy;
+    const double ih = L.inv_h;
+    const size_t q = (size_t)j * pt + i;
+    const double c0 = L.c[q], mu0 = L.mu[q], p0 = L.p[q], r0 = rho_of(P, c0);
+    double uf = 0.0, vf = 0.0;
+    if (bx || i > 0) {
+        const double cw = ldc(L.c, m1, m2, pt, bx, by, i - 1, j), rw = rho_of(P, cw), Ar = 0.5 * (rw + r0);
+        const double st = 0.5 * (r0 * ldc(L.mu, m1, m2, pt, bx, by, i - 1, j) + rw * mu0) * (c0 - cw) * ih;
+        uf = L.u[q] + P.dt * frcp(Ar) * (P.inv_M * (st - (p0 - ldc(L.p, m1, m2, pt, bx, by, i - 1, j)) * ih));
+    }
+    if (by || j > 0) {
+        const double cs = ldc(L.c, m1, m2, pt, bx, by, i, j - 1), rs = rho_of(P, cs), Ar = 0.5 * (rs + r0);
+        const double st = 0.5 * (r0 * ldc(L.mu, m1, m2, pt, bx, by, i, j - 1) + rs * mu0) * (c0 - cs) * ih;
+        vf = L.v[q] + P.dt * frcp(Ar)
+                        * (P.inv_M * (st - (p0 - ldc(L.p, m1, m2, pt, bx, by, i, j - 1)) * ih) - P.inv_Fr * (Ar - P.rho_ref));
+    }
+    d.ub[par ^ 1][q] = uf;
+    d.vb[par ^ 1][q] = vf;
 }
 
 // Physical diagnostics of the current state (sec. 8), per-block partials:

@@ -34,7 +34,7 @@ enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, O
               // mixed precision: FP32 correction cycle, FP64 update
               OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE,
               // diagnostics of the current state
-              OP_DISSIP, OP_DIAG, NOPS };
+              OP_DISSIP, OP_DIAG, OP_PJFINAL, NOPS };
 struct Op {
     int kind, level, colour;
 };
@@ -356,6 +356,11 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
             break;
         }
+        case OP_PJFINAL: {
+            hipLaunchKernelGGL(k_pj_final, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            for (auto &pe : part) pe.first->L[0].cur ^= 1;
+            break;
+        }
         case OP_DIAG: {
             hipLaunchKernelGGL(k_diagnostics, dim3(W.blocks), dim3(BLK), 0, s, W.it);
             ItemList F = finalize_list(part, OP_DIAG);
@@ -506,7 +511,9 @@ static void phys_of(const qnsch_params *p, Phys &P)
     P.K3 = p->eps * p->eta * p->M / p->We;
     P.inv_Fr = p->inv_Fr; P.rho_ref = p->rho_ref; P.mob_reg = p->mob_reg;
     P.inv_dt = 0.0;
+    P.dt = 0.0;
     P.coupled = 1;
+    P.scheme = 0;
 }
 
 static PhysF physf_of(const Phys &P)
@@ -542,6 +549,7 @@ void qnsch_default_opts(qnsch_opts *o)
     o->nu_coarse = 30;
     o->vanka_omega = 1.0;
     o->smoother = QNSCH_SMOOTH_COUPLED;
+    o->scheme = QNSCH_PRIMITIVE;
 }
 
 const char *qnsch_last_error(const qnsch_ctx *x) { return x ? x->err.c_str() : "null context"; }
@@ -573,7 +581,9 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
         return QNSCH_EINVAL;
     if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0
               || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)
-              || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)))
+              || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)
+              || (o->scheme != QNSCH_PRIMITIVE && o->scheme != QNSCH_PROJECTION)
+              || (o->scheme == QNSCH_PROJECTION && o->precision != QNSCH_FP64)))
         return QNSCH_EINVAL;
     if (level_count(g) < 0) return QNSCH_EINVAL;
     return QNSCH_OK;
@@ -586,6 +596,7 @@ static void set_params(qnsch_ctx *x, const qnsch_params *p)
     Phys P;
     phys_of(p, P);
     P.coupled = x->opt.smoother == QNSCH_SMOOTH_COUPLED;
+    P.scheme = x->opt.scheme == QNSCH_PROJECTION;
     const PhysF Pf = physf_of(P);
     for (int l = 0; l < x->nlev; l++) {
         x->hd[l].P = P;
@@ -736,6 +747,7 @@ static int set_dt(qnsch_ctx *x, double dt)
     x->dt = dt;
     for (int l = 0; l < x->nlev; l++) {
         x->hd[l].P.inv_dt = 1.0 / dt;
+        x->hd[l].P.dt = dt;
         x->hd[l].Pf.inv_dt = (float)(1.0 / dt);
     }
     return upload_desc(x);
@@ -833,11 +845,21 @@ int qnsch_lin_apply(qnsch_ctx *x, const double *dw, double *out)
     return QNSCH_OK;
 }
 
+// projection scheme: the velocity of time n+1 replaces the intermediate one
+// in the current face buffer (the latter kept for the dissipation)
+static int pj_final(qnsch_ctx *x)
+{
+    if (x->opt.scheme != QNSCH_PROJECTION) return QNSCH_OK;
+    return run_ops(x, { { OP_PJFINAL, 0, 0 } });
+}
+
 int qnsch_end_step(qnsch_ctx *x)
 {
     if (!x) return QNSCH_EINVAL;
+    int rc = QNSCH_OK;
+    if (x->in_step) rc = pj_final(x);
     x->in_step = 0;
-    return QNSCH_OK;
+    return rc;
 }
 
 // decision after a residual reduction: 1 converged, 0 continue, <0 error
@@ -893,6 +915,7 @@ int qnsch_step(qnsch_ctx *x, double dt)
         x->st.vcycles = it;
     }
     memcpy(x->st.res, x->red_host, 5 * sizeof(double));
+    if ((rc = pj_final(x))) return rc;
     x->in_step = 0;
     x->st.step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return QNSCH_OK;
@@ -941,7 +964,7 @@ int qnsch_energy(qnsch_ctx *x, double out[5])
     return QNSCH_OK;
 }
 
-int qnsch_dissipation(qnsch_ctx *x, double out[4])
+int qnsch_dissipation(qnsch_ctx *x, double out[5])
 {
     if (!x || !out) return QNSCH_EINVAL;
     if (!(x->dt > 0)) { x->err = "dissipation before any step"; return QNSCH_EBUSY; }
@@ -954,6 +977,7 @@ int qnsch_dissipation(qnsch_ctx *x, double out[4])
     out[1] = x->dt / (3.0 * p.Re) * h2 * x->red_host[1];
     out[2] = x->dt / (p.M * p.Pe) * h2 * x->red_host[2];
     out[3] = 0.5 * h2 * x->red_host[3];
+    out[4] = 0.5 * h2 * x->red_host[4];
     return QNSCH_OK;
 }
 
@@ -1215,6 +1239,7 @@ static int admit(qnsch_server *S, Req *r)
         x->dt = r->dt;
         for (int l = 0; l < x->nlev; l++) {
             x->hd[l].P.inv_dt = 1.0 / r->dt;
+            x->hd[l].P.dt = r->dt;
             x->hd[l].Pf.inv_dt = (float)(1.0 / r->dt);
         }
         // hd and stage are pinned and not touched again before this
@@ -1361,6 +1386,10 @@ int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params
     if (!S || !g || !p || !c0 || nsteps < 1 || !(dt > 0) || !id) return QNSCH_EINVAL;
     int rc = validate(g, p, o);
     if (rc) return rc;
+    if (o && o->scheme != QNSCH_PRIMITIVE) {
+        S->err = "the server runs the primitive scheme only";
+        return QNSCH_EINVAL;
+    }
     Req *r = new Req();
     r->id = S->next_id++;
     r->g = *g;

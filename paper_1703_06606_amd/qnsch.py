@@ -15,6 +15,7 @@ LIB = os.path.join(PKG, "libqnsch_hip.so")
 OK, EINVAL, ENOMEM, ENOCONV, EDIVERGED, EDEVICE, EBUSY = 0, -1, -2, -3, -4, -5, -6
 WALL, PERIODIC = 0, 1
 FP64, MIXED = 0, 1
+PRIMITIVE, PROJECTION = 0, 1
 
 # every exported symbol declared in include/qnsch.h
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
@@ -30,7 +31,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
 # operation classes of qnsch_profile_breakdown, in the library's numbering
 OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
             "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
-            "mx_prolong", "mx_update", "dissipation", "diagnostics")
+            "mx_prolong", "mx_update", "dissipation", "diagnostics", "pj_final")
 
 
 class QnschError(RuntimeError):
@@ -52,7 +53,7 @@ class Params(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_vcycles", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("nu_coarse", C.c_int32), ("vanka_omega", C.c_double),
-                ("smoother", C.c_int32)]
+                ("smoother", C.c_int32), ("scheme", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -231,7 +232,7 @@ class Solver:
         return out
 
     def dissipation(self):
-        out = np.zeros(4)
+        out = np.zeros(5)
         self._chk(lib().qnsch_dissipation(self.h, _ptr(out)))
         return out
 
