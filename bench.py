@@ -9,6 +9,9 @@ step).  The timed region starts from the initial droplet after W untimed
 warm-up steps, with all inputs resident in HBM, and covers exactly K steps.
 
 Beside it, on the same JSON line:
+  projection -- the same droplet steps in the projection scheme of sec. 6.2
+             (FP64), with its speedup over the primitive scheme, V-cycles,
+             total-mass drift and the energy law of its theorem;
   mixed   -- the 512 x 2048 Rayleigh-Taylor run in FP64 and in mixed
              precision (FP32 correction cycles inside FP64 defect correction),
              the same number of steps each, with the mixed/FP64 speedup and
@@ -177,6 +180,39 @@ def run_mixed(steps, tol):
     return out
 
 
+def run_projection(steps, warmup, tol, primitive_value):
+    """the same droplet workload in the projection scheme of sec. 6.2 (FP64):
+    throughput against the primitive scheme, V-cycles, the finest smoother's
+    launch time, total-mass drift and the energy law over the timed steps"""
+    cfg = W.rising_drop()
+    cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
+    note("projection scheme:", cfg["name"], steps, "steps")
+    g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(tol), scheme=Q.PROJECTION))
+    g.set_state(cfg["state"]["c"])
+    for _ in range(warmup):
+        g.step(cfg["dt"])
+    g.profile(1)
+    el, lat, nv = timed_steps(g, cfg, steps)
+    launches, kms = g.profile_read()
+    g.profile(0)
+    # untimed: mass and the energy law E^{n+1} - E^n + D = 0 step by step
+    g.set_state(cfg["state"]["c"])
+    m0 = g.mass()
+    law = 0.0
+    for _ in range(5):
+        e0 = g.energy()[0]
+        g.step(cfg["dt"])
+        law = max(law, abs(g.energy()[0] - e0 + g.dissipation().sum()))
+    drift = abs(g.mass().sum() - m0.sum()) / abs(m0.sum())
+    value = cells * steps / el
+    return {"workload": cfg["name"], "scheme": "projection (sec. 6.2)", "steps": steps, "tol": tol,
+            "cell_steps_per_s": value, "ms_per_step": 1e3 * el / steps,
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "vcycles_per_step": float(np.mean(nv)), "speedup_vs_primitive": value / primitive_value,
+            "finest_halfsweep_us": 1e3 * kms / max(launches, 1),
+            "total_mass_drift_5_steps": drift, "energy_law_max_abs_5_steps": law}
+
+
 def run_served(n, nsteps, tol, seq_steps, lanes):
     """the request stream through the server (mixed precision), and the same
     requests one after another alone (FP64 and mixed) on a sample of steps"""
@@ -313,6 +349,7 @@ def main():
     ap.add_argument("--scale-steps", type=int, default=20)
     ap.add_argument("--scale-max-vcycles", type=int, default=150)
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -356,6 +393,8 @@ def main():
         "step_breakdown": breakdown(g, cfg),
     }
     del g
+    if not args.no_projection:
+        out["projection"] = run_projection(args.steps, args.warmup, args.tol, value)
     if not args.no_mixed:
         out["mixed"] = run_mixed(args.mixed_steps, args.tol)
     if not args.no_serve:
