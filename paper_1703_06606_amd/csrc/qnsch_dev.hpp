@@ -82,6 +82,51 @@ __device__ __forceinline__ R ldv(const R *f, int m1, int m2, int pitch, int bcx,
     }
     return f[(size_t)j * pitch + i];
 }
+// Where a tile element (i, j) comes from, for each kind of field: the array
+// index and a sign (1; -1 for a reflected tangential ghost of a face field;
+// 0 for a wall face, which is zero) as ldc, ldu, ldv resolve them; beyond the
+// reach of any cell of the level (a tile larger than the level) every sign
+// is 0 and the element is all zero.  Computing all sources first lets a
+// thread issue all its loads at once.
+struct TileSrc {
+    int c, u, v;    // array indices (always valid)
+    int sc, su, sv; // signs
+};
+__device__ __forceinline__ TileSrc tile_src(int m1, int m2, int pitch, int bcx, int bcy, int i, int j)
+{
+    TileSrc s;
+    if (i > m1 + 1 || j > m2 + 1) {
+        s.c = s.u = s.v = 0;
+        s.sc = s.su = s.sv = 0;
+        return s;
+    }
+    int ic = i, jc = j;
+    if (ic < 0 || ic >= m1) ic = bcx ? wrapi(ic, m1) : (ic < 0 ? 0 : m1 - 1);
+    if (jc < 0 || jc >= m2) jc = bcy ? wrapi(jc, m2) : (jc < 0 ? 0 : m2 - 1);
+    s.c = jc * pitch + ic;
+    s.sc = 1;
+    int iu = i, ju = j;
+    s.su = 1;
+    if (bcx) iu = wrapi(iu, m1);
+    else if (iu <= 0 || iu >= m1) { s.su = 0; iu = 0; }
+    if (ju < 0 || ju >= m2) {
+        if (bcy) ju = wrapi(ju, m2);
+        else { s.su = -s.su; ju = ju < 0 ? 0 : m2 - 1; }
+    }
+    s.u = ju * pitch + iu;
+    int iv = i, jv = j;
+    s.sv = 1;
+    if (bcy) jv = wrapi(jv, m2);
+    else if (jv <= 0 || jv >= m2) { s.sv = 0; jv = 0; }
+    if (iv < 0 || iv >= m1) {
+        if (bcx) iv = wrapi(iv, m1);
+        else { s.sv = -s.sv; iv = iv < 0 ? 0 : m1 - 1; }
+    }
+    s.v = jv * pitch + iv;
+    return s;
+}
+template <typename R> __device__ __forceinline__ R signed_val(int sg, R x) { return sg > 0 ? x : (sg < 0 ? -x : R(0)); }
+
 __device__ __forceinline__ bool u_unk(const View &L, int i) { return L.bcx || (i >= 1 && i <= L.m1 - 1); }
 __device__ __forceinline__ bool v_unk(const View &L, int j) { return L.bcy || (j >= 1 && j <= L.m2 - 1); }
 
@@ -174,6 +219,42 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
         };
         if (e0 < n) put(e0, v0);
         if (e1r < n) put(e1r, v1);
+        return;
+    }
+    if (n <= 2 * (int)blockDim.x) {
+        // boundary images: the sources of both elements of the thread first,
+        // then all sixteen loads together, then the signs and cell functions
+        const int e0 = threadIdx.x, e1 = threadIdx.x + blockDim.x;
+        auto src = [&](int e) {
+            const int b = e / T.W, a = e - b * T.W;
+            TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, T.i0 - 1 + a, T.j0 - 1 + b);
+            if (e >= n) q.sc = q.su = q.sv = 0;
+            return q;
+        };
+        const TileSrc s0 = src(e0 < n ? e0 : 0), s1 = src(e1 < n ? e1 : 0);
+        const double v0[8] = { L.c[s0.c], L.mu[s0.c], L.p[s0.c], L.u[s0.u], L.v[s0.v], L.cn[s0.c], L.un[s0.u], L.vn[s0.v] };
+        const double v1[8] = { L.c[s1.c], L.mu[s1.c], L.p[s1.c], L.u[s1.u], L.v[s1.v], L.cn[s1.c], L.un[s1.u], L.vn[s1.v] };
+        auto put = [&](int e, const TileSrc &q, const double *v) {
+            double *s = T.s + e;
+            if (q.sc == 0) {
+                for (int f = 0; f < T_NF; f++) s[f * n] = 0.0;
+                return;
+            }
+            s[T_C * n] = v[0];
+            s[T_MU * n] = v[1];
+            s[T_P * n] = v[2];
+            s[T_U * n] = signed_val(q.su, v[3]);
+            s[T_V * n] = signed_val(q.sv, v[4]);
+            s[T_CN * n] = v[5];
+            s[T_UN * n] = signed_val(q.su, v[6]);
+            s[T_VN * n] = signed_val(q.sv, v[7]);
+            s[T_RN * n] = rho_of(P, v[5]);
+            s[T_MV * n] = visc_of(P, v[5]);
+            s[T_MOB * n] = mob_of(P, v[5]);
+            s[T_RS * n] = rho_of(P, v[0]);
+        };
+        if (e0 < n) put(e0, s0, v0);
+        if (e1 < n) put(e1, s1, v1);
         return;
     }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {

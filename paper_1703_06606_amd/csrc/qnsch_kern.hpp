@@ -167,8 +167,10 @@ __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
     return (size_t)15 * m1 * m2 + (size_t)T_NF * (m1 + 3) * (m2 + 3);
 }
 
-// all sweeps of the coarsest level in one workgroup per item, with the whole
-// level resident in LDS; the u/v buffers alternate, the number of half-sweeps
+// all sweeps of a level in one workgroup per item, with the whole level
+// resident in LDS: the solve of the coarsest level, and the pre- and
+// post-smoothing of coarse levels small enough (the same arithmetic as the
+// half-sweep launches); the u/v buffers alternate, the number of half-sweeps
 // is even, so the result stays in buffer par
 __global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, double omega)
 {

@@ -34,52 +34,59 @@ enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, O
               // mixed precision: FP32 correction cycle, FP64 update
               OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE,
               // diagnostics of the current state
-              OP_DISSIP, OP_DIAG, OP_PJFINAL, NOPS };
+              OP_DISSIP, OP_DIAG, OP_PJFINAL,
+              // colour field = number of sweeps: all sweeps of a small level
+              // in one workgroup with the level resident in LDS
+              OP_SMOOTH, OP_MXSMOOTH, NOPS };
 struct Op {
     int kind, level, colour;
 };
 
+// nu sweeps of level l: one launch per colour half-sweep, or, on a coarse
+// level that fits in LDS (l >= small), all of them in one workgroup (the
+// same arithmetic in the same order)
+static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, std::vector<Op> &out)
+{
+    if (nu <= 0) return;
+    if (l > 0 && l >= small) {
+        out.push_back({ lds_kind, l, nu });
+        return;
+    }
+    for (int s = 0; s < nu; s++) {
+        out.push_back({ hs_kind, l, 0 });
+        out.push_back({ hs_kind, l, 1 });
+    }
+}
+
 // one V-cycle of a hierarchy of L levels, ending with the residual norms and
 // the pbar mean removal
-static void vcycle_program(int L, int nu1, int nu2, std::vector<Op> &out)
+static void vcycle_program(int L, int nu1, int nu2, int small, std::vector<Op> &out)
 {
     for (int l = 0; l + 1 < L; l++) {
-        for (int s = 0; s < nu1; s++) {
-            out.push_back({ OP_HS, l, 0 });
-            out.push_back({ OP_HS, l, 1 });
-        }
+        smooth_ops(l, nu1, small, OP_HS, OP_SMOOTH, out);
         out.push_back({ OP_RESTRICT, l, 0 });
         out.push_back({ OP_CRHS, l + 1, 0 });
     }
     out.push_back({ OP_COARSE, L - 1, 0 });
     for (int l = L - 2; l >= 0; l--) {
         out.push_back({ OP_PROLONG, l, 0 });
-        for (int s = 0; s < nu2; s++) {
-            out.push_back({ OP_HS, l, 0 });
-            out.push_back({ OP_HS, l, 1 });
-        }
+        smooth_ops(l, nu2, small, OP_HS, OP_SMOOTH, out);
     }
     out.push_back({ OP_NORM, 0, 0 });
 }
 // one outer iteration of the mixed-precision step: an FP32 correction
 // V-cycle on J(w^) delta = r, w += delta in FP64, then the FP64 residual
 // (which also prepares the next cycle) and the pbar mean removal
-static void mixed_program(int L, int nu1, int nu2, std::vector<Op> &out)
+static void mixed_program(int L, int nu1, int nu2, int small, std::vector<Op> &out)
 {
     for (int l = 0; l + 1 < L; l++) {
-        for (int s = 0; s < nu1; s++) {
-            out.push_back({ OP_MXHS, l, 0 });
-            out.push_back({ OP_MXHS, l, 1 });
-        }
+        smooth_ops(l, nu1, small, OP_MXHS, OP_MXSMOOTH, out);
         out.push_back({ OP_MXRESTRICT, l, 0 });
     }
     out.push_back({ OP_MXCOARSE, L - 1, 0 });
     for (int l = L - 2; l >= 0; l--) {
         out.push_back({ OP_MXPROLONG, l, 0 });
-        for (int s = 0; s < nu2; s++) {
-            out.push_back({ OP_MXHS, l, 0 });
-            out.push_back({ OP_MXHS, l, 1 });
-        }
+        smooth_ops(l, nu2, small, OP_MXHS, OP_MXSMOOTH, out);
     }
     out.push_back({ OP_MXUPDATE, 0, 0 });
     out.push_back({ OP_NORM, 0, 0 });
@@ -138,10 +145,26 @@ struct qnsch_ctx {
 
 static bool is_mixed(const qnsch_ctx *x) { return x->opt.precision == QNSCH_MIXED; }
 static void step_begin_program(const qnsch_ctx *x, std::vector<Op> &out) { begin_program(x->nlev, is_mixed(x), out); }
+// LDS of one workgroup that the level-resident smoothing may use
+#define SMALL_LEVEL_LDS 65536
+// first level from which every coarser level fits in LDS for the
+// level-resident smoothing (nlev if none)
+static int small_level(const qnsch_ctx *x)
+{
+    int small = x->nlev;
+    for (int l = x->nlev - 1; l >= 1; l--) {
+        const int m1 = x->L[l].m1, m2 = x->L[l].m2;
+        const size_t b = is_mixed(x) ? mx_coarse_lds_floats(m1, m2) * sizeof(float)
+                                     : coarse_lds_doubles(m1, m2) * sizeof(double);
+        if (b > SMALL_LEVEL_LDS) break;
+        small = l;
+    }
+    return small;
+}
 static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
 {
-    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, out);
-    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, out);
+    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), out);
+    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), out);
 }
 
 #define HIPCHK(ctx, x)                                                                        \
@@ -175,7 +198,7 @@ static int op_blocks(const qnsch_ctx *x, int kind, int l)
     switch (kind) {
     case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_MXHS: case OP_MXRESTRICT:
         return tiles_x(D.m1) * tiles_y(D.m2);
-    case OP_COARSE: case OP_MXCOARSE: return 1;
+    case OP_COARSE: case OP_MXCOARSE: case OP_SMOOTH: case OP_MXSMOOTH: return 1;
     case OP_RN: case OP_MXRN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
     default: return (int)nblocks((size_t)D.m1 * D.m2);
     }
@@ -195,8 +218,10 @@ static void add_item(ItemList &W, const qnsch_ctx *x, int kind, int l)
     it.n = k + 1;
     it.start[k + 1] = W.blocks;
     if (l != 0) W.all_fine = false;
-    if (kind == OP_COARSE) W.lds = std::max(W.lds, coarse_lds_doubles(x->L[l].m1, x->L[l].m2) * sizeof(double));
-    if (kind == OP_MXCOARSE) W.lds = std::max(W.lds, mx_coarse_lds_floats(x->L[l].m1, x->L[l].m2) * sizeof(float));
+    if (kind == OP_COARSE || kind == OP_SMOOTH)
+        W.lds = std::max(W.lds, coarse_lds_doubles(x->L[l].m1, x->L[l].m2) * sizeof(double));
+    if (kind == OP_MXCOARSE || kind == OP_MXSMOOTH)
+        W.lds = std::max(W.lds, mx_coarse_lds_floats(x->L[l].m1, x->L[l].m2) * sizeof(float));
 }
 
 // finalize list: one workgroup per simulation, tx = number of partials
@@ -309,21 +334,24 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         }
         case OP_RESTRICT: hipLaunchKernelGGL(k_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
         case OP_CRHS: hipLaunchKernelGGL(k_coarse_rhs, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
-        case OP_COARSE: {
+        case OP_COARSE:
+        case OP_SMOOTH: {
             int nmax = 0;
             for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
             const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
-            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, x0->opt.nu_coarse, omega);
+            const int sweeps = kind == OP_SMOOTH ? colour : x0->opt.nu_coarse;
+            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, omega);
             break;
         }
         case OP_PROLONG: hipLaunchKernelGGL(k_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_MXRESTRICT: hipLaunchKernelGGL(k_mx_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
-        case OP_MXCOARSE: {
+        case OP_MXCOARSE:
+        case OP_MXSMOOTH: {
             int nmax = 0;
             for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
             const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
-            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, x0->opt.nu_coarse,
-                               (float)omega);
+            const int sweeps = kind == OP_MXSMOOTH ? colour : x0->opt.nu_coarse;
+            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, (float)omega);
             break;
         }
         case OP_MXPROLONG: hipLaunchKernelGGL(k_mx_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;

@@ -103,6 +103,46 @@ __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const
         if (e1r < n) put(e1r, v1);
         return;
     }
+    if (n <= 2 * (int)blockDim.x) {
+        // boundary images: sources first, then all loads together (see tile_load)
+        const int e0 = threadIdx.x, e1 = threadIdx.x + blockDim.x;
+        auto src = [&](int e) {
+            const int b = e / T.W, a = e - b * T.W;
+            TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, T.i0 - 1 + a, T.j0 - 1 + b);
+            if (e >= n) q.sc = q.su = q.sv = 0;
+            return q;
+        };
+        const TileSrc s0 = src(e0 < n ? e0 : 0), s1 = src(e1 < n ? e1 : 0);
+        const float v0[9] = { L.c[s0.c], L.dc[s0.c], L.dmu[s0.c], L.dp[s0.c], L.du[s0.u], L.dv[s0.v],
+                              L.cn[s0.c], L.un[s0.u], L.vn[s0.v] };
+        const float v1[9] = { L.c[s1.c], L.dc[s1.c], L.dmu[s1.c], L.dp[s1.c], L.du[s1.u], L.dv[s1.v],
+                              L.cn[s1.c], L.un[s1.u], L.vn[s1.v] };
+        auto put = [&](int e, const TileSrc &q, const float *v) {
+            float *s = T.s + e;
+            if (q.sc == 0) {
+                for (int f = 0; f < L_NF; f++) s[f * n] = 0.0f;
+                return;
+            }
+            s[L_C * n] = v[0];
+            s[L_DC * n] = v[1];
+            s[L_MU * n] = v[2];
+            s[L_P * n] = v[3];
+            s[L_U * n] = signed_val(q.su, v[4]);
+            s[L_V * n] = signed_val(q.sv, v[5]);
+            s[L_CN * n] = v[6];
+            s[L_UN * n] = signed_val(q.su, v[7]);
+            s[L_VN * n] = signed_val(q.sv, v[8]);
+            s[L_RN * n] = rhof(P, v[6]);
+            s[L_MV * n] = viscf(P, v[6]);
+            s[L_MOB * n] = mobf(P, v[6]);
+            const float rs = rhof(P, v[0]);
+            s[L_RS * n] = rs;
+            s[L_DRS * n] = -P.alpha * rs * rs * v[1];
+        };
+        if (e0 < n) put(e0, s0, v0);
+        if (e1 < n) put(e1, s1, v1);
+        return;
+    }
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;

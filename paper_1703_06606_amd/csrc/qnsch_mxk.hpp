@@ -156,9 +156,9 @@ __host__ __device__ inline size_t mx_coarse_lds_floats(int m1, int m2)
     return (size_t)19 * m1 * m2 + (size_t)L_NF * (m1 + 3) * (m2 + 3);
 }
 
-// all correction sweeps of the coarsest level in one workgroup per item, the
-// level resident in LDS; an even number of half-sweeps keeps the result in
-// buffer par
+// all correction sweeps of a level in one workgroup per item, the level
+// resident in LDS (the coarsest level, and the smoothing of small coarse
+// levels); an even number of half-sweeps keeps the result in buffer par
 __global__ __launch_bounds__(512) void k_mx_coarse_solve(Items it, int sweeps, float omega)
 {
     extern __shared__ float smf[];
