@@ -38,7 +38,7 @@ class _Params(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_vcycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("nu_coarse", C.c_int), ("vanka_omega", C.c_double), ("smoother", C.c_int),
-                ("scheme", C.c_int)]
+                ("scheme", C.c_int), ("coarse_omega", C.c_double)]
 
 
 _lib = None
@@ -94,7 +94,7 @@ class Oracle:
         g = _Grid(grid["m1"], grid["m2"], grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
         p = _Params(*[float(params[n]) for n, _ in _Params._fields_])
         o = _Opts(opts["tol"], opts["max_vcycles"], opts["nu1"], opts["nu2"], opts["nu_coarse"], opts["vanka_omega"],
-                  opts.get("smoother", 1), opts.get("scheme", 0))
+                  opts.get("smoother", 1), opts.get("scheme", 0), opts.get("coarse_omega", 1.6))
         self.h = lib().orc_create(C.byref(g), C.byref(p), C.byref(o))
         if not self.h:
             raise ValueError("oracle rejected the grid")

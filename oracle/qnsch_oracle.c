@@ -88,6 +88,8 @@ struct orc_ctx {
     const Level *fzlev;
     double *ufz, *vfz;
     double *ut_save[2];
+    /* set while the coarsest-level solve of a V-cycle runs */
+    int in_coarse;
     /* statistics of the last step */
     int nv;
     double hist[ORC_MAXV + 1][NSTATE];
@@ -553,9 +555,14 @@ static void vanka_box(orc_ctx *o, Level *L, int i, int j, double *unew, double *
     }
     unperturb(o);
     if (gepp(n, J, b) != 0) return;
+    /* faces and pbar take the relaxed step: vanka_omega, or coarse_omega on
+     * the coarsest-level solve of the primitive scheme (over-relaxation; a
+     * reading: the cycle is left to the multigrid references of sec. 7);
+     * c and mubar the full Newton step */
+    double om = (!projection(o) && o->in_coarse) ? o->o.coarse_omega : o->o.vanka_omega;
     for (int q = 0; q < n; q++) {
         size_t kq = (size_t)cj[q] * L->m1 + ci[q];
-        double d = o->o.vanka_omega * b[q];
+        double d = om * b[q];
         if (fld[q] == F_U) unew[kq] = L->f[F_U][kq] + d;
         else if (fld[q] == F_V) vnew[kq] = L->f[F_V][kq] + d;
         else if (fld[q] == F_C) L->f[F_C][kq] += b[q];
@@ -576,7 +583,10 @@ static void p_point(orc_ctx *o, Level *L, int i, int j)
     unperturb(o);
     double J = cimag(r) / CSTEP;
     if (J == 0.0) return;
-    L->f[F_P][k] += (L->rhs[2][k] - creal(r)) / J;
+    /* over-relaxed by coarse_omega in the coarsest-level solve (as the
+     * primitive box's pressure and velocity there) */
+    double om = o->in_coarse ? o->o.coarse_omega : 1.0;
+    L->f[F_P][k] += om * (L->rhs[2][k] - creal(r)) / J;
 }
 
 /* Projection scheme, one colour (sec. 7.2, steps per cell of the colour):
@@ -745,7 +755,9 @@ static void residual_at(orc_ctx *o, int l, double *r[NSTATE])
 static void vcycle(orc_ctx *o, int l)
 {
     if (l == o->nlev - 1) {
+        o->in_coarse = 1;
         for (int s = 0; s < o->o.nu_coarse; s++) sweep(o, l);
+        o->in_coarse = 0;
         return;
     }
     Level *F = &o->lev[l], *C = &o->lev[l + 1];

@@ -36,6 +36,7 @@ typedef struct {
     double vanka_omega;
     int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED (primitive scheme) */
     int scheme;   /* ORC_PRIMITIVE (sec. 6.1) or ORC_PROJECTION (sec. 6.2) */
+    double coarse_omega; /* relaxation of the velocity/pressure updates on the coarsest level */
 } orc_opts;
 
 typedef struct orc_ctx orc_ctx;

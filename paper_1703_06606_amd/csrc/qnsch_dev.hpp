@@ -543,15 +543,17 @@ __device__ __forceinline__ const double *face_rhs(const Rhs &F, int hlf)
 // the steps (identical values from both lanes), which no other pair of this
 // colour reads.
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
-                              int i, int j, int hlf, double omega);
+                              int i, int j, int hlf, double omega, double pomega);
 __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j, int hlf,
                               double &rc, double &rm, double &rp, double &rf);
 
+// omega relaxes the box's velocity and pressure updates; pomega the
+// projection scheme's separate pressure step
 __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
-                                           double *vnew, int i, int j, int hlf, double omega)
+                                           double *vnew, int i, int j, int hlf, double omega, double pomega)
 {
     if (P.scheme) {
-        relax_pair_pj(P, L, T, F, unew, vnew, i, j, hlf, omega);
+        relax_pair_pj(P, L, T, F, unew, vnew, i, j, hlf, omega, pomega);
         return;
     }
     const size_t k = (size_t)j * L.pitch + i;
@@ -781,7 +783,7 @@ __device__ __forceinline__ PjAx pj_axis(const Tile &T, const Ax &a, int e, doubl
 // entries of the cell (c, mubar, rho(c)) are updated after step 1; no other
 // pair of this colour reads them.
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
-                              int i, int j, int hlf, double omega)
+                              int i, int j, int hlf, double omega, double pomega)
 {
     const size_t k = (size_t)j * L.pitch + i;
     const double ih = L.inv_h, ih2 = ih * ih;
@@ -882,7 +884,7 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double Lmu_new = s.Lmu - s.Sm * (mnew - m0);
     const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp;
     const double Jp = jp + q.Jpp;
-    if (hlf == 0) L.p[k] = tq(T, T_P, e) + (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+    if (hlf == 0) L.p[k] = tq(T, T_P, e) + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
 }
 
 // residuals of the projection scheme's five equations attached to cell (i,j)

@@ -142,7 +142,7 @@ __device__ __forceinline__ void halfsweep_body(const Items &it, int colour, doub
     const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
     const int j = T.j0 + lj;
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
-    if (i < L.m1 && j < L.m2) relax_pair(d.P, L, T, rhs_of(d), d.ub[par ^ 1], d.vb[par ^ 1], i, j, hlf, omega);
+    if (i < L.m1 && j < L.m2) relax_pair(d.P, L, T, rhs_of(d), d.ub[par ^ 1], d.vb[par ^ 1], i, j, hlf, omega, 1.0);
 }
 __global__ HS_ATTR void k_halfsweep(Items it, int colour, double omega)
 {
@@ -172,7 +172,7 @@ __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
 // post-smoothing of coarse levels small enough (the same arithmetic as the
 // half-sweep launches); the u/v buffers alternate, the number of half-sweeps
 // is even, so the result stays in buffer par
-__global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, double omega)
+__global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, double omega, double pomega)
 {
     extern __shared__ double sm[];
     const int k = find_item(it);
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, doub
             const int pr = t >> 1;
             const int j = pr / half;
             const int i = 2 * (pr - j * half) + ((j + colour) & 1);
-            relax_pair(d.P, H, T, FH, uw, vw, i, j, t & 1, omega);
+            relax_pair(d.P, H, T, FH, uw, vw, i, j, t & 1, omega, pomega);
         }
         __syncthreads();
     }

@@ -339,8 +339,13 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             int nmax = 0;
             for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
             const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
-            const int sweeps = kind == OP_SMOOTH ? colour : x0->opt.nu_coarse;
-            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, omega);
+            // the coarsest level over-relaxes the velocity and pressure
+            // updates (the primitive box, the projection pressure step)
+            const bool coarsest = kind == OP_COARSE, pj = x0->opt.scheme == QNSCH_PROJECTION;
+            const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
+            const double om = coarsest && !pj ? x0->opt.coarse_omega : omega;
+            const double pom = coarsest && pj ? x0->opt.coarse_omega : 1.0;
+            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, om, pom);
             break;
         }
         case OP_PROLONG: hipLaunchKernelGGL(k_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
@@ -350,8 +355,10 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             int nmax = 0;
             for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
             const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
-            const int sweeps = kind == OP_MXSMOOTH ? colour : x0->opt.nu_coarse;
-            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, (float)omega);
+            const bool coarsest = kind == OP_MXCOARSE;
+            const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
+            const double om = coarsest ? x0->opt.coarse_omega : omega;
+            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, (float)om);
             break;
         }
         case OP_MXPROLONG: hipLaunchKernelGGL(k_mx_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
@@ -574,10 +581,11 @@ void qnsch_default_opts(qnsch_opts *o)
     o->max_vcycles = 50;
     o->nu1 = 2;
     o->nu2 = 2;
-    o->nu_coarse = 30;
+    o->nu_coarse = 6;
     o->vanka_omega = 1.0;
     o->smoother = QNSCH_SMOOTH_COUPLED;
     o->scheme = QNSCH_PRIMITIVE;
+    o->coarse_omega = 1.6;
 }
 
 const char *qnsch_last_error(const qnsch_ctx *x) { return x ? x->err.c_str() : "null context"; }
@@ -611,7 +619,8 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
               || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)
               || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)
               || (o->scheme != QNSCH_PRIMITIVE && o->scheme != QNSCH_PROJECTION)
-              || (o->scheme == QNSCH_PROJECTION && o->precision != QNSCH_FP64)))
+              || (o->scheme == QNSCH_PROJECTION && o->precision != QNSCH_FP64)
+              || !(o->coarse_omega > 0.0 && o->coarse_omega < 2.0) || !(o->vanka_omega > 0.0 && o->vanka_omega < 2.0)))
         return QNSCH_EINVAL;
     if (level_count(g) < 0) return QNSCH_EINVAL;
     return QNSCH_OK;
@@ -1474,14 +1483,15 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
         S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
         // per lane, the largest set of ready requests with the same next
         // operation (kind, colour, coarse sweeps, relaxation factor)
-        typedef std::tuple<int, int, int, double> Key;
+        typedef std::tuple<int, int, int, double, double> Key;
         bool launched = false;
         for (size_t lane = 0; lane < S->lanes.size(); lane++) {
             std::map<Key, std::vector<Req *>> groups;
             for (Req *r : S->active) {
                 if (r->lane != (int)lane || r->wait != W_NONE || r->pc >= r->prog.size()) continue;
                 const Op &o = r->prog[r->pc];
-                groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega)].push_back(r);
+                groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega, r->x->opt.coarse_omega)]
+                    .push_back(r);
             }
             if (groups.empty()) continue;
             auto best = groups.begin();

@@ -53,7 +53,7 @@ class Params(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_vcycles", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("nu_coarse", C.c_int32), ("vanka_omega", C.c_double),
-                ("smoother", C.c_int32), ("scheme", C.c_int32)]
+                ("smoother", C.c_int32), ("scheme", C.c_int32), ("coarse_omega", C.c_double)]
 
 
 class StepStats(C.Structure):
