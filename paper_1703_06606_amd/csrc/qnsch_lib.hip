@@ -141,14 +141,13 @@ struct qnsch_ctx {
     int in_step = 0;
     double dt = 0;
     qnsch_step_stats st;
+    size_t lds_max = 65536; // LDS a level-resident workgroup may use on this device
 };
 
 static bool is_mixed(const qnsch_ctx *x) { return x->opt.precision == QNSCH_MIXED; }
 static void step_begin_program(const qnsch_ctx *x, std::vector<Op> &out) { begin_program(x->nlev, is_mixed(x), out); }
-// LDS of one workgroup that the level-resident smoothing may use
-#define SMALL_LEVEL_LDS 65536
 // first level from which every coarser level fits in LDS for the
-// level-resident smoothing (nlev if none)
+// level-resident smoothing (nlev if none); lds_max is set at context creation
 static int small_level(const qnsch_ctx *x)
 {
     int small = x->nlev;
@@ -156,7 +155,7 @@ static int small_level(const qnsch_ctx *x)
         const int m1 = x->L[l].m1, m2 = x->L[l].m2;
         const size_t b = is_mixed(x) ? mx_coarse_lds_floats(m1, m2) * sizeof(float)
                                      : coarse_lds_doubles(m1, m2) * sizeof(double);
-        if (b > SMALL_LEVEL_LDS) break;
+        if (b > x->lds_max) break;
         small = l;
     }
     return small;
@@ -643,6 +642,27 @@ static void set_params(qnsch_ctx *x, const qnsch_params *p)
 
 // Allocate and lay out a context (validated arguments); the device arrays
 // are cleared on the stream; the descriptors are not uploaded yet.
+// LDS one workgroup may allocate on the current device (160 KiB on gfx950),
+// with the level-resident kernels allowed to use it; 64 KiB if the device
+// does not report more or the attribute cannot be set.  Once per device.
+static size_t device_lds_max()
+{
+    static size_t cache[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 65536;
+    if (cache[dev]) return cache[dev];
+    int v = 0;
+    size_t r = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 65536
+        && hipFuncSetAttribute((const void *)k_coarse_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess
+        && hipFuncSetAttribute((const void *)k_mx_coarse_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v)
+               == hipSuccess)
+        r = (size_t)v;
+    (void)hipGetLastError();
+    cache[dev] = r;
+    return r;
+}
+
 static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream)
 {
     int rc = QNSCH_OK;
@@ -652,6 +672,7 @@ static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, co
     x->prm = *p;
     qnsch_default_opts(&x->opt);
     if (o) x->opt = *o;
+    x->lds_max = device_lds_max();
     x->s = (hipStream_t)stream;
     memset(&x->st, 0, sizeof(x->st));
     const double hx = g->Lx / g->m1;

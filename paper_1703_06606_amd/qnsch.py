@@ -162,10 +162,11 @@ class Solver:
         if rc != OK:
             raise QnschError(rc, "qnsch_create rejected the configuration")
         self.h = h
+        self._L = lib()  # kept for __del__, which may run after the module's globals are cleared
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().qnsch_destroy(self.h)
+        if getattr(self, "h", None) and getattr(self, "_L", None) is not None:
+            self._L.qnsch_destroy(self.h)
             self.h = None
 
     def _chk(self, rc):
@@ -316,11 +317,12 @@ class Server:
         if rc != OK:
             raise QnschError(rc, "qnsch_server_create failed")
         self.h = h
+        self._L = lib()
         self.shapes = {}
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().qnsch_server_destroy(self.h)
+        if getattr(self, "h", None) and getattr(self, "_L", None) is not None:
+            self._L.qnsch_server_destroy(self.h)
             self.h = None
 
     def submit(self, grid, params, opts, c0, nsteps, dt):

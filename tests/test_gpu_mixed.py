@@ -194,3 +194,51 @@ def test_mixed_periodic_drops_box_density_ratio_100():
         for k in FIELDS:
             assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (step, k, rel(a[k], b[k], 1e-9))
         assert np.abs(g.mass() - m0).max() <= 1e-8 * np.abs(m0).max()
+
+
+def test_mixed_full_size_rayleigh_taylor():
+    """512 x 2048 Rayleigh-Taylor (the mixed-precision comparison workload) at
+    full size: two mixed steps against two FP64 GPU steps (1e-6 relative),
+    the oracle's own residual at the first mixed solution (<= 2e-8 at tol
+    1e-8), total mass to 1e-8"""
+    cfg = W.rayleigh_taylor()
+    say("mixed full size", cfg["name"])
+    opts = W.default_opts(1e-8)
+    gm = Q.Solver(cfg["grid"], cfg["params"], mixed(opts))
+    gd = Q.Solver(cfg["grid"], cfg["params"], opts)
+    for s in (gm, gd):
+        s.set_state(cfg["state"]["c"])
+    m0 = gm.mass()
+    for step in range(2):
+        assert gm.step(cfg["dt"]) == Q.OK
+        assert gd.step(cfg["dt"]) == Q.OK
+        if step == 0:
+            o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+            o.set_time_n_and_iterate(dict(c=cfg["state"]["c"]), gm.get_state(), cfg["dt"])
+            _, no = o.residual()
+            assert no.max() <= 2e-8, no
+            del o
+        say("step", step, "mixed outer", gm.stats()["vcycles"], "fp64 V-cycles", gd.stats()["vcycles"])
+    a, b = gm.get_state(), gd.get_state()
+    for k in FIELDS:
+        assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (k, rel(a[k], b[k], 1e-9))
+    assert np.abs(gm.mass() - m0).max() <= 1e-8 * np.abs(m0).max()
+
+
+def test_mixed_full_size_periodic_drops_box_2048():
+    """one 2048 x 2048 box of the serving-at-scale workload (40 drops,
+    density ratio 100, eps = 0.002, buoyancy gravity): a mixed step to 1e-8
+    with the oracle's residual at the GPU's solution and both masses to 1e-8"""
+    cfg = W.drops_box(2048, 40, 0.02, 0.05, 0.002, 1000)
+    say("mixed full size", cfg["name"])
+    opts = dict(W.default_opts(1e-8), max_vcycles=150)
+    g = Q.Solver(cfg["grid"], cfg["params"], mixed(opts))
+    g.set_state(cfg["state"]["c"])
+    m0 = g.mass()
+    assert g.step(cfg["dt"]) == Q.OK
+    say("outer iterations", g.stats()["vcycles"])
+    o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+    o.set_time_n_and_iterate(dict(c=cfg["state"]["c"]), g.get_state(), cfg["dt"])
+    _, no = o.residual()
+    assert no.max() <= 2e-8, no
+    assert np.abs(g.mass() - m0).max() <= 1e-8 * np.abs(m0).max()
