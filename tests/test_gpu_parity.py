@@ -99,11 +99,12 @@ def _cases():
     }
 
 
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("name", list(_cases()))
-def test_vcycles_match_oracle(name):
+def test_vcycles_match_oracle(name, smoother):
     cfg = _cases()[name]
-    say("vcycle parity", name)
-    g, o = pair(cfg, W.default_opts())
+    say("vcycle parity", name, "smoother", smoother)
+    g, o = pair(cfg, dict(W.default_opts(), smoother=smoother))
     for s in (g, o):
         s.set_state(cfg["state"]["c"])
         s.begin_step(cfg["dt"])
