@@ -55,6 +55,11 @@ HALFSWEEP_BYTES_PER_CELL = 8 * 8 + 3 * 8 / 2 + 2 * 8
 MX_HALFSWEEP_BYTES_PER_CELL = 9 * 4 + (1 + 3) * 4 / 2 + 4 * 4 + 3 * 4 / 2 + 2 * 4
 KERNEL = "k_halfsweep_fine"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_traffic.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_valu.txt")
+# vector issue capacity: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
+# every 4 cycles at 2.4 GHz; FP64 vector peak 78.6 TFLOP/s
+VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
+FP64_PEAK_TFLOPS = 78.6
 SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f)
            for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp", "qnsch_lib.hip")]
 
@@ -66,22 +71,43 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the kernel from the committed counter summary,
-    only if it was taken on the current kernel source"""
-    if not os.path.exists(TRAFFIC_FILE):
+def _profile_values(path):
+    """key: value lines of a committed counter summary, only if it was taken
+    on the current kernel source"""
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != source_hash():
-        return None
+    return kv if kv.get("source_hash") == source_hash() else None
+
+
+def traffic_from_profile():
+    """HBM bytes per launch of the kernel from the committed counter summary"""
+    kv = _profile_values(TRAFFIC_FILE)
     try:
-        return float(kv["hbm_bytes_per_launch"])
+        return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
+
+
+def valu_from_profile(avg_launch_us):
+    """vector-ALU view of the same kernel from the committed SQ counter
+    summary: wave instructions per launch, the issue time they need at full
+    rate, and the executed FP64 rate against the FP64 vector peak"""
+    kv = _profile_values(VALU_FILE)
+    if not kv:
+        return None
+    try:
+        insts, flops = float(kv["valu_wave_insts_per_launch"]), float(kv["fp64_flops_per_launch"])
+    except (KeyError, ValueError):
+        return None
+    floor_us = insts / VALU_WAVE_INSTS_PER_S * 1e6
+    tf = flops / (avg_launch_us * 1e-6) / 1e12
+    return {"valu_wave_insts_per_launch": insts, "issue_floor_us": floor_us, "issue_frac": floor_us / avg_launch_us,
+            "fp64_flops_per_launch": flops, "fp64_tflops": tf, "fp64_frac": tf / FP64_PEAK_TFLOPS}
 
 
 def cpu_baseline(cfg, opts, vcycles_per_step):
@@ -387,6 +413,7 @@ def main():
         "vcycles_per_step": float(np.mean(nv)),
         "roofline": {"bound": "hbm", "kernel": KERNEL, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profile(),
+                     "valu": valu_from_profile(1e3 * avg_ms),
                      "launches": launches, "avg_launch_us": 1e3 * avg_ms,
                      "alg_bytes_per_launch": alg_bytes},
         "copy_probe_GBps": copy_gbs,
