@@ -17,7 +17,8 @@
  * multigrid (sec. 7.1): per cell a pointwise Newton (Gauss-Seidel) update of
  * (c, mubar) on the phase and chemical-potential equations, then a Vanka box
  * update of the four faces and the pressure of the cell on the momentum and
- * mass equations, in red-black order, inside a V-cycle.  The paper leaves the
+ * mass equations (or, by default, one Newton step on all seven unknowns of the
+ * cell), in red-black order, inside a V-cycle.  The paper leaves the
  * V-cycle, transfers and sweep semantics to its references; the readings used
  * here are stated where they are implemented.
  *
