@@ -131,7 +131,25 @@ typedef struct {
     double coarse_omega; /* relaxation factor of the velocity and pressure updates on the
                             coarsest level (the primitive box's faces and pbar; the
                             projection scheme's pressure step); in (0, 2) */
+    int32_t accel;       /* depth m (0..3) of the acceleration of the cycle iteration
+                            below; 0 = plain cycles */
 } qnsch_opts;
+
+/* Acceleration of the cycle iteration (not part of the paper, whose sec. 7.1
+ * asks only for a standard FAS V-cycle; the discrete system, its root and the
+ * stop test are unchanged).  The cycle results w_k (after the pbar mean
+ * removal) and their residuals r_k = -N(w_k) are kept for the last m + 1
+ * cycles of a step.  Before the next cycle the iterate becomes
+ *   w = w_k + sum_i g_i (w_k - w_{k-i}),  i = 1..n,
+ * with g minimising the linearised residual || r_k + sum_i g_i (r_k - r_{k-i}) ||
+ * (plain sum of squares over the five fields; normal equations solved by
+ * Cholesky), the nonlinear Krylov acceleration of multigrid of Washio and
+ * Oosterlee (ETNA 6, 1997).  n = min(m, number of earlier results), cut to
+ * the leading block whose Cholesky pivots exceed 1e-12 times the diagonal;
+ * a result whose largest residual norm is not below that of the result
+ * before it starts a new history (n = 0 next).  In mixed precision the next
+ * correction cycle solves for the same combination of the residuals at the
+ * combined iterate. */
 
 typedef struct {
     int32_t vcycles;        /* V-cycles (mixed: outer iterations) of the last step */
@@ -144,7 +162,8 @@ typedef struct qnsch_ctx qnsch_ctx;
 
 /* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 6 coarsest sweeps
  * over-relaxed by coarse_omega = 1.6 (as accurate as 30 plain sweeps on the
- * workloads of sec. 8), omega 1, coupled smoother, primitive scheme. */
+ * workloads of sec. 8), omega 1, coupled smoother, primitive scheme,
+ * acceleration depth 2. */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
@@ -175,14 +194,19 @@ int qnsch_get_state(qnsch_ctx *ctx, double *c, double *mu, double *p, double *u,
 int qnsch_step(qnsch_ctx *ctx, double dt);
 
 /* Phases of a step, for inspection: begin_step fixes the time-n data (the
- * current state) on every level; vcycle runs one V-cycle and fixes the mean of
- * pbar to zero; residual returns r = -N(w) of the current iterate (5 fields of
- * m1*m2, order c, mu, p, u, v; NULL to skip) and its norms; halfsweep runs one
- * colour half-sweep (colour 0: (i+j) even) on the finest level; end_step
- * commits the iterate as the new state (projection scheme: replaces u~ by the
- * velocity of time n+1). */
+ * current state) on every level; vcycle runs one V-cycle, fixes the mean of
+ * pbar to zero and (accel > 0) records the result and its residual for the
+ * acceleration; accelerate replaces the iterate by the combination of the
+ * recorded results (see above; no change after the first cycle of a step or
+ * with accel = 0); a step is vcycle, then accelerate and vcycle until the
+ * tolerance is met.  residual returns r = -N(w) of the current iterate (5
+ * fields of m1*m2, order c, mu, p, u, v; NULL to skip) and its norms;
+ * halfsweep runs one colour half-sweep (colour 0: (i+j) even) on the finest
+ * level; end_step commits the iterate as the new state (projection scheme:
+ * replaces u~ by the velocity of time n+1). */
 int qnsch_begin_step(qnsch_ctx *ctx, double dt);
 int qnsch_vcycle(qnsch_ctx *ctx);
+int qnsch_accelerate(qnsch_ctx *ctx);
 int qnsch_residual(qnsch_ctx *ctx, double *r_out, double norms[5]);
 int qnsch_halfsweep(qnsch_ctx *ctx, int colour);
 int qnsch_end_step(qnsch_ctx *ctx);

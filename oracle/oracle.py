@@ -38,7 +38,7 @@ class _Params(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_vcycles", C.c_int), ("nu1", C.c_int), ("nu2", C.c_int),
                 ("nu_coarse", C.c_int), ("vanka_omega", C.c_double), ("smoother", C.c_int),
-                ("scheme", C.c_int), ("coarse_omega", C.c_double)]
+                ("scheme", C.c_int), ("coarse_omega", C.c_double), ("accel", C.c_int)]
 
 
 _lib = None
@@ -61,6 +61,8 @@ def lib():
         L.orc_residual.argtypes = [C.c_void_p, P, P]
         L.orc_halfsweep.argtypes = [C.c_void_p, C.c_int]
         L.orc_vcycle.argtypes = [C.c_void_p]
+        L.orc_accelerate.argtypes = [C.c_void_p]
+        L.orc_accel_coeffs.argtypes = [C.c_void_p, P]
         L.orc_solve.argtypes = [C.c_void_p]
         L.orc_step.argtypes = [C.c_void_p, C.c_double]
         L.orc_stats.argtypes = [C.c_void_p, P]
@@ -94,7 +96,7 @@ class Oracle:
         g = _Grid(grid["m1"], grid["m2"], grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
         p = _Params(*[float(params[n]) for n, _ in _Params._fields_])
         o = _Opts(opts["tol"], opts["max_vcycles"], opts["nu1"], opts["nu2"], opts["nu_coarse"], opts["vanka_omega"],
-                  opts.get("smoother", 1), opts.get("scheme", 0), opts.get("coarse_omega", 1.6))
+                  opts.get("smoother", 1), opts.get("scheme", 0), opts.get("coarse_omega", 1.6), opts.get("accel", 2))
         self.h = lib().orc_create(C.byref(g), C.byref(p), C.byref(o))
         if not self.h:
             raise ValueError("oracle rejected the grid")
@@ -134,6 +136,15 @@ class Oracle:
 
     def vcycle(self):
         lib().orc_vcycle(self.h)
+
+    def accelerate(self):
+        lib().orc_accelerate(self.h)
+
+    def accel_coeffs(self):
+        """coefficients of the pending combination (the used ones)"""
+        g = np.zeros(3)
+        n = lib().orc_accel_coeffs(self.h, _ptr(g))
+        return g[:n].copy()
 
     def solve(self):
         return lib().orc_solve(self.h)

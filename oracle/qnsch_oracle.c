@@ -91,6 +91,12 @@ struct orc_ctx {
     double *ut_save[2];
     /* set while the coarsest-level solve of a V-cycle runs */
     int in_coarse;
+    /* acceleration of the cycle iteration: the last nh cycle results of the
+     * step (hw) and their residuals (hr), index 0 the newest; the pending
+     * combination uses acc_use of the earlier ones with coefficients acc_g */
+    double *hw[ORC_MAXACC + 1][NSTATE], *hr[ORC_MAXACC + 1][NSTATE];
+    int nh, acc_use, acc_pending;
+    double acc_g[ORC_MAXACC], acc_last, acc_nr[NSTATE];
     /* statistics of the last step */
     int nv;
     double hist[ORC_MAXV + 1][NSTATE];
@@ -801,6 +807,108 @@ static void remove_p_mean(orc_ctx *o)
 }
 
 /* ------------------------------------------------------------------------- */
+/* Acceleration of the cycle iteration.  Not in the paper (sec. 7.1 asks only  */
+/* for a standard FAS V-cycle): the nonlinear Krylov acceleration of          */
+/* multigrid of Washio and Oosterlee (ETNA 6, 1997).  With results w_0 (the    */
+/* newest), w_1, ... and residuals r_k = rhs - N(w_k), the next cycle starts   */
+/* from w_0 + sum_a g_a (w_0 - w_{a+1}), g minimising the linearised residual  */
+/* || r_0 + sum_a g_a (r_0 - r_{a+1}) ||_2 (plain sum over all fields).        */
+
+/* g from the normal equations H g = -b, H_ab = (e_a, e_b), b_a = (e_a, r_0),
+ * e_a = r_0 - r_{a+1}, by Cholesky; only the leading block whose pivots stay
+ * above 1e-12 of their diagonal entry is used.  Returns its size. */
+static int acc_coefficients(const orc_ctx *o, int n, double g[ORC_MAXACC])
+{
+    const Level *L = &o->lev[0];
+    size_t nc = (size_t)L->m1 * L->m2;
+    double H[ORC_MAXACC][ORC_MAXACC] = { { 0 } }, b[ORC_MAXACC] = { 0 };
+    for (int a = 0; a < n; a++) {
+        for (int c = 0; c < n; c++) {
+            double s = 0.0;
+            for (int q = 0; q < NSTATE; q++)
+                for (size_t k = 0; k < nc; k++)
+                    s += (o->hr[0][q][k] - o->hr[a + 1][q][k]) * (o->hr[0][q][k] - o->hr[c + 1][q][k]);
+            H[a][c] = s;
+        }
+        double s = 0.0;
+        for (int q = 0; q < NSTATE; q++)
+            for (size_t k = 0; k < nc; k++) s += (o->hr[0][q][k] - o->hr[a + 1][q][k]) * o->hr[0][q][k];
+        b[a] = s;
+    }
+    /* H = C C^T, C lower triangular */
+    double C[ORC_MAXACC][ORC_MAXACC] = { { 0 } };
+    int use = 0;
+    for (int c = 0; c < n; c++) {
+        double piv = H[c][c];
+        for (int k = 0; k < c; k++) piv -= C[c][k] * C[c][k];
+        if (!(piv > 1e-12 * H[c][c]) || !isfinite(piv)) break;
+        C[c][c] = sqrt(piv);
+        for (int r = c + 1; r < n; r++) {
+            double s = H[r][c];
+            for (int k = 0; k < c; k++) s -= C[r][k] * C[c][k];
+            C[r][c] = s / C[c][c];
+        }
+        use = c + 1;
+    }
+    double y[ORC_MAXACC] = { 0 };
+    for (int a = 0; a < ORC_MAXACC; a++) g[a] = 0.0;
+    for (int a = 0; a < use; a++) {
+        double s = -b[a];
+        for (int k = 0; k < a; k++) s -= C[a][k] * y[k];
+        y[a] = s / C[a][a];
+    }
+    for (int a = use - 1; a >= 0; a--) {
+        double s = y[a];
+        for (int k = a + 1; k < use; k++) s -= C[k][a] * g[k];
+        g[a] = s / C[a][a];
+    }
+    return use;
+}
+
+/* record the cycle result just computed (iterate of the finest level, its
+ * residual in lev[0].r with norms nr) and fix the pending combination; a
+ * result whose largest norm is not below the previous one's starts a new
+ * history */
+static void acc_record(orc_ctx *o, const double nr[NSTATE])
+{
+    const int m = o->o.accel;
+    Level *L = &o->lev[0];
+    size_t nb = (size_t)L->m1 * L->m2 * sizeof(double);
+    double mx = 0.0;
+    for (int q = 0; q < NSTATE; q++) mx = nr[q] > mx ? nr[q] : mx;
+    int keep = o->nh < m + 1 ? o->nh + 1 : m + 1;
+    if (o->nh > 0 && !(mx < o->acc_last)) keep = 1;
+    /* the buffers of the oldest result take the new one */
+    for (int q = 0; q < NSTATE; q++) {
+        double *tw = o->hw[m][q], *tr = o->hr[m][q];
+        for (int k = m; k > 0; k--) { o->hw[k][q] = o->hw[k - 1][q]; o->hr[k][q] = o->hr[k - 1][q]; }
+        o->hw[0][q] = tw;
+        o->hr[0][q] = tr;
+        memcpy(o->hw[0][q], L->f[q], nb);
+        memcpy(o->hr[0][q], L->r[q], nb);
+    }
+    o->nh = keep;
+    o->acc_use = acc_coefficients(o, keep - 1, o->acc_g);
+    o->acc_pending = 1;
+    o->acc_last = mx;
+}
+
+/* the pending combination replaces the iterate of the finest level */
+static void acc_apply(orc_ctx *o)
+{
+    if (!o->acc_pending) return;
+    o->acc_pending = 0;
+    Level *L = &o->lev[0];
+    size_t nc = (size_t)L->m1 * L->m2;
+    for (int q = 0; q < NSTATE; q++)
+        for (size_t k = 0; k < nc; k++) {
+            double w = o->hw[0][q][k];
+            for (int a = 0; a < o->acc_use; a++) w += o->acc_g[a] * (o->hw[0][q][k] - o->hw[a + 1][q][k]);
+            L->f[q][k] = w;
+        }
+}
+
+/* ------------------------------------------------------------------------- */
 /* public API                                                                  */
 
 static double *zalloc(size_t n)
@@ -851,6 +959,9 @@ orc_ctx *orc_create(const orc_grid *g, const orc_params *p, const orc_opts *opt)
     o->vfz = zalloc(n0);
     o->ut_save[0] = zalloc(n0);
     o->ut_save[1] = zalloc(n0);
+    if (opt->accel < 0 || opt->accel > ORC_MAXACC) { orc_destroy(o); return NULL; }
+    for (int k = 0; k <= opt->accel; k++)
+        for (int q = 0; q < NSTATE; q++) { o->hw[k][q] = zalloc(n0); o->hr[k][q] = zalloc(n0); }
     return o;
 }
 
@@ -864,6 +975,8 @@ void orc_destroy(orc_ctx *o)
     }
     for (int q = 0; q < NSTATE; q++) free(o->save[q]);
     free(o->ufz); free(o->vfz); free(o->ut_save[0]); free(o->ut_save[1]);
+    for (int k = 0; k <= ORC_MAXACC; k++)
+        for (int q = 0; q < NSTATE; q++) { free(o->hw[k][q]); free(o->hr[k][q]); }
     free(o);
 }
 
@@ -917,6 +1030,10 @@ void orc_begin_step(orc_ctx *o, double dt)
     }
     o->nv = 0;
     o->in_step = 1;
+    o->nh = 0;
+    o->acc_use = 0;
+    o->acc_pending = 0;
+    o->acc_last = 0.0;
 }
 
 void orc_residual(orc_ctx *o, double *r_out /* 5*m1*m2 or NULL */, double norms[5])
@@ -932,10 +1049,28 @@ void orc_residual(orc_ctx *o, double *r_out /* 5*m1*m2 or NULL */, double norms[
 
 void orc_halfsweep(orc_ctx *o, int colour) { halfsweep(o, 0, colour & 1); }
 
+/* one cycle: V-cycle, pbar mean removal and, with acceleration, the record
+ * of the result (a pending combination that was not applied is dropped) */
 void orc_vcycle(orc_ctx *o)
 {
+    o->acc_pending = 0;
     vcycle(o, 0);
     remove_p_mean(o);
+    if (o->o.accel > 0) {
+        Level *L = &o->lev[0];
+        residual_level(o, L, L->r);
+        norms_level(L, L->r, o->acc_nr);
+        acc_record(o, o->acc_nr);
+    }
+}
+
+void orc_accelerate(orc_ctx *o) { acc_apply(o); }
+
+/* coefficients of the pending combination; returns how many are used */
+int orc_accel_coeffs(const orc_ctx *o, double g[ORC_MAXACC])
+{
+    for (int a = 0; a < ORC_MAXACC; a++) g[a] = o->acc_g[a];
+    return o->acc_pending ? o->acc_use : 0;
 }
 
 static int state_ok(const orc_ctx *o)
@@ -1007,9 +1142,11 @@ int orc_solve(orc_ctx *o)
         if (!isfinite(mx) || !state_ok(o)) { restore(o); return ORC_EDIVERGED; }
         if (mx <= o->o.tol) break;
         if (it >= o->o.max_vcycles) { restore(o); return ORC_ENOCONV; }
+        if (it > 0) orc_accelerate(o);
         orc_vcycle(o);
         it++;
-        orc_residual(o, NULL, nr);
+        if (o->o.accel > 0) memcpy(nr, o->acc_nr, sizeof(nr));
+        else orc_residual(o, NULL, nr);
         for (int e = 0; e < NSTATE; e++) o->hist[it][e] = nr[e];
         o->nv = it;
     }

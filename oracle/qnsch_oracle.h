@@ -9,6 +9,7 @@
 
 #define ORC_MAXLEV 12
 #define ORC_MAXV 200
+#define ORC_MAXACC 3
 
 enum { ORC_WALL = 0, ORC_PERIODIC = 1 };
 enum { ORC_OK = 0, ORC_ENOCONV = -3, ORC_EDIVERGED = -4 };
@@ -37,6 +38,7 @@ typedef struct {
     int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED (primitive scheme) */
     int scheme;   /* ORC_PRIMITIVE (sec. 6.1) or ORC_PROJECTION (sec. 6.2) */
     double coarse_omega; /* relaxation of the velocity/pressure updates on the coarsest level */
+    int accel;           /* depth (0..ORC_MAXACC) of the acceleration of the cycle iteration; 0 = off */
 } orc_opts;
 
 typedef struct orc_ctx orc_ctx;
@@ -50,6 +52,8 @@ void orc_begin_step(orc_ctx *, double dt);
 void orc_residual(orc_ctx *, double *r_out, double norms[5]);
 void orc_halfsweep(orc_ctx *, int colour);
 void orc_vcycle(orc_ctx *);
+void orc_accelerate(orc_ctx *);
+int orc_accel_coeffs(const orc_ctx *, double g[ORC_MAXACC]);
 int orc_solve(orc_ctx *);
 int orc_step(orc_ctx *, double dt);
 int orc_stats(const orc_ctx *, double *hist);

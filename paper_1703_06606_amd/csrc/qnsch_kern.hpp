@@ -14,7 +14,7 @@
 namespace qn {
 
 #define BLK 256
-#define NRED 8 // reduction slots
+#define NRED 16 // reduction slots
 // Tile of cells per workgroup (one lane pair per cell of a colour).  16 x 16
 // cells and 256 lanes: small levels spread over more CUs, and two or three
 // workgroups share a CU on large ones (measured against 32 x 16 and 32 x 8).
@@ -57,6 +57,11 @@ struct Desc {
     double *red_host;                                   // reduced values (pinned host)
     double *mus, *ps;                                   // mubar, pbar of time n (finest level)
     double *rout;                                       // residual fields (finest level, optional)
+    // acceleration history (finest level): a ring of am slots, each holding
+    // a cycle result (aw, pbar before its mean removal) and its residual (ar)
+    // as 5 fields of pitch*m2, and the pbar mean removed from it (amean)
+    double *aw, *ar, *amean;
+    int am;
     // mixed precision: the FP32 correction hierarchy (NULL in FP64 mode; on
     // coarse levels the FP64 arrays above are NULL instead)
     PhysF Pf;
@@ -74,6 +79,7 @@ struct Items {
     short par[MAXITEMS];      // current u/v buffer of that level
     short cpar[MAXITEMS];     // current u/v buffer of the next coarser level
     int tx[MAXITEMS];         // tiles per row (tile kernels); partial count (k_finalize)
+    short acc[MAXITEMS];      // acceleration ring slot s | (earlier results used) << 4; -1 none
 };
 
 __device__ __forceinline__ int find_item(const Items &it)
@@ -378,6 +384,46 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out)
     }
 }
 
+// Acceleration of the cycle iteration, recording of a cycle result in ring
+// slot s: the residual and the iterate of the cell at index w (lane 0: c,
+// mubar, pbar and the west face; lane 1: the south face).
+template <typename TT>
+__device__ __forceinline__ void acc_put(const Desc &d, int s, size_t w, int hlf, double rc, double rm, double rp,
+                                        double rf, const TT &T, int i, int j)
+{
+    const size_t st = (size_t)d.pitch * d.m2;
+    double *ar = d.ar + (size_t)s * 5 * st + w, *aw = d.aw + (size_t)s * 5 * st + w;
+    if (hlf == 0) {
+        ar[0] = rc; ar[st] = rm; ar[2 * st] = rp; ar[3 * st] = rf;
+        aw[0] = T.q(T_C, i, j); aw[st] = T.q(T_MU, i, j); aw[2 * st] = T.q(T_P, i, j); aw[3 * st] = T.q(T_U, i, j);
+    } else {
+        ar[4 * st] = rf;
+        aw[4 * st] = T.q(T_V, i, j);
+    }
+}
+// ... and the lane's share of the normal equations of
+// min || r + sum_a g_a (r - r_a) ||, r_a the residual a + 1 slots back
+// (a < np): v[7 + b(b+1)/2 + a] += e_a e_b (a <= b), v[13 + a] += e_a r,
+// e_a = r - r_a.  Reads back what acc_put of the same lane wrote.
+__device__ __forceinline__ void acc_dots(const Desc &d, int ac, size_t w, int hlf, double (&v)[NRED])
+{
+    const int s = ac & 15, np = ac >> 4, R = d.am;
+    const size_t st = (size_t)d.pitch * d.m2;
+    for (int f = hlf ? 4 : 0; f < (hlf ? 5 : 4); f++) {
+        const double x = d.ar[(size_t)(s * 5 + f) * st + w];
+        double e[3] = { 0.0, 0.0, 0.0 };
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            if (a < np) e[a] = x - d.ar[(size_t)(((s - 1 - a + R) % R) * 5 + f) * st + w];
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int a = 0; a <= b; a++) v[7 + b * (b + 1) / 2 + a] += e[a] * e[b];
+#pragma unroll
+        for (int a = 0; a < 3; a++) v[13 + a] += e[a] * x;
+    }
+}
+
 // residual norms of a finest level: per tile sums of r^2 for the five
 // equations, the sum of pbar, and the count of cells that are non-finite or
 // past the density pole (partials indexed by the tile's place in the band
@@ -392,7 +438,7 @@ __global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
     const Tile T = item_tile(sm, it, k, d);
     tile_load(d.P, L, T);
     __syncthreads();
-    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    double v[NRED] = {};
     const size_t n = (size_t)L.m1 * L.m2;
     const int hlf = threadIdx.x & 1;
     const Rhs F = rhs_of(d);
@@ -430,6 +476,14 @@ __global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
             v[6] += ok ? 0.0 : 1.0;
             if (d.rout) { d.rout[q] = rc; d.rout[n + q] = rm; d.rout[2 * n + q] = rp; }
         }
+        if (it.acc[k] >= 0 && d.ar) acc_put(d, it.acc[k] & 15, (size_t)j * L.pitch + i, hlf, rc, rm, rp, rf, T, i, j);
+    }
+    // the normal equations after the residuals, whose registers are free by now
+    if (it.acc[k] >= 0 && d.ar && (it.acc[k] >> 4) > 0) {
+        pair_cells(T, i, j);
+#pragma unroll 1
+        for (int a = 0; a < 2; a++, i++)
+            if (i < L.m1 && j < L.m2) acc_dots(d, it.acc[k], (size_t)j * L.pitch + i, hlf, v);
     }
     const int tl = (T.j0 / TY) * it.tx[k] + T.i0 / TX;
     block_sum_store(v, d.partials + (size_t)tl * NRED);
@@ -444,7 +498,7 @@ __global__ __launch_bounds__(BLK) void k_mass_energy(Items it)
     const Phys &P = d.P;
     const int b = (int)blockIdx.x - it.start[k];
     const int t = b * BLK + threadIdx.x;
-    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    double v[NRED] = {};
     if (t < L.m1 * L.m2) {
         const int j = t / L.m1, i = t - j * L.m1;
         const size_t q = (size_t)j * L.pitch + i;
@@ -488,7 +542,7 @@ __global__ __launch_bounds__(BLK) void k_dissipation(Items it)
     const Phys &P = d.P;
     const int b = (int)blockIdx.x - it.start[k];
     const int t = b * BLK + threadIdx.x;
-    double v[NRED] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    double v[NRED] = {};
     if (t < L.m1 * L.m2) {
         const int j = t / L.m1, i = t - j * L.m1;
         const int m1 = L.m1, m2 = L.m2, pt = L.pitch, bx = L.bcx, by = L.bcy;
@@ -675,6 +729,9 @@ __global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
         if (mode == 0 && threadIdx.x < 5) x = sqrt(d.h * d.h * x);
         d.red[threadIdx.x] = x;
         d.red_host[threadIdx.x] = x;
+        // a recorded cycle result: the pbar mean k_shift_p removes from it
+        if (mode == 0 && threadIdx.x == 5 && it.acc[k] >= 0 && d.amean)
+            d.amean[it.acc[k] & 15] = x / (double)(d.m1 * d.m2);
     }
 }
 
@@ -687,6 +744,60 @@ __global__ __launch_bounds__(BLK) void k_shift_p(Items it)
     if (t >= d.m1 * d.m2) return;
     const int j = t / d.m1, i = t - j * d.m1;
     d.p[(size_t)j * d.pitch + i] -= d.red[5] / (double)(d.m1 * d.m2);
+}
+
+// coefficients of the accelerated combination, per item
+struct AccCoef {
+    double g[MAXITEMS][3];
+};
+
+// Acceleration step of the cycle iteration: the current iterate w (the last
+// cycle result, recorded in ring slot s) becomes w + sum_a g_a (w - w_a), w_a
+// the result a + 1 slots back (a < np; its pbar less the mean removed from it,
+// which makes it the iterate that result was).  Mixed precision: the next
+// correction cycle's right-hand side becomes the same combination of the
+// recorded residuals, its linearisation point the combined iterate.
+__global__ __launch_bounds__(BLK) void k_accel(Items it, AccCoef G)
+{
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
+    if (t >= d.m1 * d.m2 || !d.aw || it.acc[k] < 0) return;
+    const int j = t / d.m1, i = t - j * d.m1;
+    const size_t q = (size_t)j * d.pitch + i, st = (size_t)d.pitch * d.m2;
+    const int ac = it.acc[k], s = ac & 15, np = ac >> 4, R = d.am, par = it.par[k];
+    int sl[3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) sl[b] = (s - 1 - b + R) % R;
+    double *const live[5] = { d.c, d.mu, d.p, d.ub[par], d.vb[par] };
+    double y[5];
+#pragma unroll
+    for (int f = 0; f < 5; f++) {
+        const double x = live[f][q];
+        double a = x;
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+            if (b < np) {
+                const double wb = d.aw[(size_t)(sl[b] * 5 + f) * st + q] - (f == 2 ? d.amean[sl[b]] : 0.0);
+                a += G.g[k][b] * (x - wb);
+            }
+        y[f] = a;
+        live[f][q] = a;
+    }
+    if (d.rc) {
+        float r[5];
+#pragma unroll
+        for (int f = 0; f < 5; f++) {
+            const double x = d.ar[(size_t)(s * 5 + f) * st + q];
+            double a = x;
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+                if (b < np) a += G.g[k][b] * (x - d.ar[(size_t)(sl[b] * 5 + f) * st + q]);
+            r[f] = (float)a;
+        }
+        d.rc[q] = r[0]; d.rmu[q] = r[1]; d.rp[q] = r[2]; d.ru[q] = r[3]; d.rv[q] = r[4];
+        d.xc[q] = (float)y[0]; d.xmu[q] = (float)y[1]; d.xu[q] = (float)y[3]; d.xv[q] = (float)y[4];
+    }
 }
 
 // time-n data of the finest level = current iterate; keep mubar, pbar of time n

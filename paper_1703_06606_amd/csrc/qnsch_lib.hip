@@ -37,7 +37,10 @@ enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, O
               OP_DISSIP, OP_DIAG, OP_PJFINAL,
               // colour field = number of sweeps: all sweeps of a small level
               // in one workgroup with the level resident in LDS
-              OP_SMOOTH, OP_MXSMOOTH, NOPS };
+              OP_SMOOTH, OP_MXSMOOTH,
+              // acceleration of the cycle iteration: residual norms that also
+              // record the result, and the combination before the next cycle
+              OP_NORMACC, OP_ACCEL, NOPS };
 struct Op {
     int kind, level, colour;
 };
@@ -60,7 +63,7 @@ static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, std:
 
 // one V-cycle of a hierarchy of L levels, ending with the residual norms and
 // the pbar mean removal
-static void vcycle_program(int L, int nu1, int nu2, int small, std::vector<Op> &out)
+static void vcycle_program(int L, int nu1, int nu2, int small, bool acc, std::vector<Op> &out)
 {
     for (int l = 0; l + 1 < L; l++) {
         smooth_ops(l, nu1, small, OP_HS, OP_SMOOTH, out);
@@ -72,12 +75,12 @@ static void vcycle_program(int L, int nu1, int nu2, int small, std::vector<Op> &
         out.push_back({ OP_PROLONG, l, 0 });
         smooth_ops(l, nu2, small, OP_HS, OP_SMOOTH, out);
     }
-    out.push_back({ OP_NORM, 0, 0 });
+    out.push_back({ acc ? OP_NORMACC : OP_NORM, 0, 0 });
 }
 // one outer iteration of the mixed-precision step: an FP32 correction
 // V-cycle on J(w^) delta = r, w += delta in FP64, then the FP64 residual
 // (which also prepares the next cycle) and the pbar mean removal
-static void mixed_program(int L, int nu1, int nu2, int small, std::vector<Op> &out)
+static void mixed_program(int L, int nu1, int nu2, int small, bool acc, std::vector<Op> &out)
 {
     for (int l = 0; l + 1 < L; l++) {
         smooth_ops(l, nu1, small, OP_MXHS, OP_MXSMOOTH, out);
@@ -89,7 +92,7 @@ static void mixed_program(int L, int nu1, int nu2, int small, std::vector<Op> &o
         smooth_ops(l, nu2, small, OP_MXHS, OP_MXSMOOTH, out);
     }
     out.push_back({ OP_MXUPDATE, 0, 0 });
-    out.push_back({ OP_NORM, 0, 0 });
+    out.push_back({ acc ? OP_NORMACC : OP_NORM, 0, 0 });
 }
 // time-n data of every level, then the residual of the initial iterate
 static void begin_program(int L, bool mixed, std::vector<Op> &out)
@@ -142,6 +145,15 @@ struct qnsch_ctx {
     double dt = 0;
     qnsch_step_stats st;
     size_t lds_max = 65536; // LDS a level-resident workgroup may use on this device
+    // acceleration of the cycle iteration (opt.accel = m > 0): ring of m + 1
+    // recorded results on the device
+    int acc_pos = 0;      // slot of the latest recorded result
+    int acc_cnt = 0;      // results in the current history, the latest included
+    int acc_dots = 0;     // earlier results the latest one's reduction paired it with
+    int acc_use = 0;      // earlier results the pending combination uses (0: none pending)
+    bool acc_wait = false;  // a recording reduction is in flight
+    double acc_g[3] = { 0.0, 0.0, 0.0 };
+    double acc_last = 0.0;  // largest residual norm of the latest result
 };
 
 static bool is_mixed(const qnsch_ctx *x) { return x->opt.precision == QNSCH_MIXED; }
@@ -162,8 +174,8 @@ static int small_level(const qnsch_ctx *x)
 }
 static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
 {
-    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), out);
-    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), out);
+    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), x->opt.accel > 0, out);
+    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), x->opt.accel > 0, out);
 }
 
 #define HIPCHK(ctx, x)                                                                        \
@@ -195,7 +207,8 @@ static int op_blocks(const qnsch_ctx *x, int kind, int l)
 {
     const DLev &D = x->L[l];
     switch (kind) {
-    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_MXHS: case OP_MXRESTRICT:
+    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_NORMACC: case OP_MXHS:
+    case OP_MXRESTRICT:
         return tiles_x(D.m1) * tiles_y(D.m2);
     case OP_COARSE: case OP_MXCOARSE: case OP_SMOOTH: case OP_MXSMOOTH: return 1;
     case OP_RN: case OP_MXRN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
@@ -213,6 +226,7 @@ static void add_item(ItemList &W, const qnsch_ctx *x, int kind, int l)
     it.par[k] = (short)x->L[l].cur;
     it.cpar[k] = (short)(l + 1 < x->nlev ? x->L[l + 1].cur : 0);
     it.tx[k] = tiles_x(x->L[l].m1);
+    it.acc[k] = -1;
     W.blocks = start + op_blocks(x, kind, l);
     it.n = k + 1;
     it.start[k + 1] = W.blocks;
@@ -233,6 +247,7 @@ static ItemList finalize_list(const std::vector<std::pair<qnsch_ctx *, int>> &v,
         F.it.d[k] = x->dd;
         F.it.par[k] = (short)x->L[0].cur;
         F.it.tx[k] = op_blocks(x, partial_kind, 0);
+        F.it.acc[k] = -1;
         F.it.start[k] = k;
         F.it.n = k + 1;
         F.it.start[k + 1] = k + 1;
@@ -288,6 +303,83 @@ static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stampe
         x->prof_used++;
     }
     return QNSCH_OK;
+}
+
+// ---------------------------------------------------------------------------
+// acceleration of the cycle iteration (host side)
+
+// a recording residual reduction is being launched: the result goes to the
+// next ring slot, paired with up to m earlier results of the history
+static void acc_record_launch(qnsch_ctx *x, short &acc)
+{
+    const int m = x->opt.accel, R = m + 1;
+    x->acc_pos = (x->acc_pos + 1) % R;
+    x->acc_dots = std::min(x->acc_cnt, m);
+    acc = (short)(x->acc_pos | (x->acc_dots << 4));
+    x->acc_wait = true;
+    x->acc_use = 0;
+}
+
+// Normal equations H g = -b of the combination (H packed by columns in
+// v[0..5], b in v[6..8]) over the n earliest-paired results, solved by
+// Cholesky; the leading block whose pivots exceed 1e-12 times their diagonal
+// entry is used.  Returns the number of coefficients (the rest are 0).
+static int acc_solve(const double *v, int n, double g[3])
+{
+    auto H = [&](int i, int j) { return i <= j ? v[j * (j + 1) / 2 + i] : v[i * (i + 1) / 2 + j]; };
+    double Lf[3][3] = {};
+    int use = 0;
+    for (int c = 0; c < n; c++) {
+        double dg = H(c, c);
+        for (int k = 0; k < c; k++) dg -= Lf[c][k] * Lf[c][k];
+        if (!(dg > 1e-12 * H(c, c)) || !std::isfinite(dg)) break;
+        Lf[c][c] = sqrt(dg);
+        for (int r = c + 1; r < n; r++) {
+            double a = H(c, r);
+            for (int k = 0; k < c; k++) a -= Lf[r][k] * Lf[c][k];
+            Lf[r][c] = a / Lf[c][c];
+        }
+        use = c + 1;
+    }
+    double y[3] = { 0.0, 0.0, 0.0 };
+    for (int i = 0; i < use; i++) {
+        double a = -v[6 + i];
+        for (int k = 0; k < i; k++) a -= Lf[i][k] * y[k];
+        y[i] = a / Lf[i][i];
+    }
+    for (int b = 0; b < 3; b++) g[b] = 0.0;
+    for (int i = use - 1; i >= 0; i--) {
+        double a = y[i];
+        for (int k = i + 1; k < use; k++) a -= Lf[k][i] * g[k];
+        g[i] = a / Lf[i][i];
+    }
+    return use;
+}
+
+// after a recording reduction (norms and normal equations in red_host): the
+// coefficients of the next combination.  A result whose largest norm does
+// not improve on the previous one starts a new history.
+static void acc_after(qnsch_ctx *x)
+{
+    x->acc_wait = false;
+    double mx = 0.0;
+    for (int q = 0; q < 5; q++) mx = std::max(mx, x->red_host[q]);
+    int n = x->acc_dots;
+    if (n > 0 && !(mx < x->acc_last)) n = 0;
+    x->acc_use = n > 0 ? acc_solve(x->red_host + 7, n, x->acc_g) : 0;
+    if (x->acc_use == 0)
+        for (int b = 0; b < 3; b++) x->acc_g[b] = 0.0;
+    x->acc_cnt = n + 1;
+    x->acc_last = mx;
+}
+
+static void acc_reset(qnsch_ctx *x)
+{
+    x->acc_cnt = 0;
+    x->acc_dots = 0;
+    x->acc_use = 0;
+    x->acc_wait = false;
+    x->acc_last = 0.0;
 }
 
 // Launch one operation for a set of (context, level) entries, in lists of at
@@ -367,11 +459,15 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         case OP_RN: hipLaunchKernelGGL(k_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_RESTORE: hipLaunchKernelGGL(k_restore, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
         case OP_NORM0:
-        case OP_NORM: {
+        case OP_NORM:
+        case OP_NORMACC: {
+            if (kind == OP_NORMACC)
+                for (size_t q = 0; q < part.size(); q++) acc_record_launch(part[q].first, W.it.acc[q]);
             hipLaunchKernelGGL(k_resid_norm, dim3(W.blocks), dim3(TBLK), 0, s, W.it);
             ItemList F = finalize_list(part, OP_NORM);
+            for (size_t q = 0; q < part.size(); q++) F.it.acc[q] = W.it.acc[q];
             hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 0);
-            if (kind == OP_NORM) {
+            if (kind != OP_NORM0) {
                 ItemList S;
                 for (auto &pe : part) add_item(S, pe.first, OP_BEGIN, 0);
                 hipLaunchKernelGGL(k_shift_p, dim3(S.blocks), dim3(BLK), 0, s, S.it);
@@ -388,6 +484,18 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             hipLaunchKernelGGL(k_dissipation, dim3(W.blocks), dim3(BLK), 0, s, W.it);
             ItemList F = finalize_list(part, OP_DISSIP);
             hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
+            break;
+        }
+        case OP_ACCEL: {
+            AccCoef G;
+            memset(&G, 0, sizeof(G));
+            for (size_t q = 0; q < part.size(); q++) {
+                qnsch_ctx *x = part[q].first;
+                W.it.acc[q] = (short)(x->acc_pos | (x->acc_use << 4));
+                for (int b = 0; b < 3; b++) G.g[q][b] = x->acc_g[b];
+                x->acc_use = 0;
+            }
+            hipLaunchKernelGGL(k_accel, dim3(W.blocks), dim3(BLK), 0, s, W.it, G);
             break;
         }
         case OP_PJFINAL: {
@@ -484,7 +592,7 @@ static int level_count(const qnsch_grid *g)
 // data and FAS arrays on every level.  Mixed mode: the FP64 state and time-n
 // data on the finest level only (one u/v buffer, both slots aliased) and the
 // FP32 correction hierarchy on every level.
-static size_t carve(const qnsch_grid *g, int nl, bool mixed, char *base, Desc *hd)
+static size_t carve(const qnsch_grid *g, int nl, bool mixed, int accel, char *base, Desc *hd)
 {
     size_t off = 0;
     auto take = [&](size_t bytes) -> void * {
@@ -523,15 +631,21 @@ static size_t carve(const qnsch_grid *g, int nl, bool mixed, char *base, Desc *h
     d0.ps = dbl(n0);
     d0.partials = dbl((size_t)std::max(tiles_x(g->m1) * tiles_y(g->m2), (int)nblocks(n0)) * NRED);
     d0.red = dbl(NRED);
+    if (accel > 0) {
+        d0.am = accel + 1;
+        d0.aw = dbl((size_t)5 * d0.am * n0);
+        d0.ar = dbl((size_t)5 * d0.am * n0);
+        d0.amean = dbl((size_t)d0.am);
+    }
     return off;
 }
 
 // device bytes of a context (the allocations of qnsch_create)
-static size_t footprint_of(const qnsch_grid *g, int precision)
+static size_t footprint_of(const qnsch_grid *g, const qnsch_opts &o)
 {
     const int nl = level_count(g);
     if (nl < 0) return 0;
-    return carve(g, nl, precision == QNSCH_MIXED, nullptr, nullptr) + (size_t)nl * sizeof(Desc);
+    return carve(g, nl, o.precision == QNSCH_MIXED, o.accel, nullptr, nullptr) + (size_t)nl * sizeof(Desc);
 }
 
 static void phys_of(const qnsch_params *p, Phys &P)
@@ -585,6 +699,7 @@ void qnsch_default_opts(qnsch_opts *o)
     o->smoother = QNSCH_SMOOTH_COUPLED;
     o->scheme = QNSCH_PRIMITIVE;
     o->coarse_omega = 1.6;
+    o->accel = 2;
 }
 
 const char *qnsch_last_error(const qnsch_ctx *x) { return x ? x->err.c_str() : "null context"; }
@@ -619,7 +734,8 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
               || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)
               || (o->scheme != QNSCH_PRIMITIVE && o->scheme != QNSCH_PROJECTION)
               || (o->scheme == QNSCH_PROJECTION && o->precision != QNSCH_FP64)
-              || !(o->coarse_omega > 0.0 && o->coarse_omega < 2.0) || !(o->vanka_omega > 0.0 && o->vanka_omega < 2.0)))
+              || !(o->coarse_omega > 0.0 && o->coarse_omega < 2.0) || !(o->vanka_omega > 0.0 && o->vanka_omega < 2.0)
+              || o->accel < 0 || o->accel > 3))
         return QNSCH_EINVAL;
     if (level_count(g) < 0) return QNSCH_EINVAL;
     return QNSCH_OK;
@@ -686,7 +802,7 @@ static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, co
     x->allocs.push_back(ddp);
     x->dd = (Desc *)ddp;
     const bool mixed = is_mixed(x);
-    const size_t bytes = carve(g, x->nlev, mixed, nullptr, nullptr);
+    const size_t bytes = carve(g, x->nlev, mixed, x->opt.accel, nullptr, nullptr);
     void *arena = nullptr;
     if (hipMalloc(&arena, bytes) != hipSuccess) return QNSCH_ENOMEM;
     x->allocs.push_back(arena);
@@ -694,7 +810,7 @@ static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, co
     x->arena_bytes = bytes;
     x->footprint = bytes + (size_t)x->nlev * sizeof(Desc);
     if (hipMemsetAsync(arena, 0, bytes, x->s) != hipSuccess) rc = QNSCH_EDEVICE;
-    carve(g, x->nlev, mixed, (char *)arena, x->hd);
+    carve(g, x->nlev, mixed, x->opt.accel, (char *)arena, x->hd);
     for (int l = 0; l < x->nlev; l++) {
         DLev &D = x->L[l];
         D.m1 = g->m1 >> l;
@@ -819,6 +935,7 @@ int qnsch_begin_step(qnsch_ctx *x, double dt)
     std::vector<Op> prog;
     step_begin_program(x, prog);
     prog.pop_back(); // no residual here
+    acc_reset(x);
     if ((rc = run_ops(x, prog))) return rc;
     x->in_step = 1;
     x->st.vcycles = 0;
@@ -830,10 +947,24 @@ int qnsch_vcycle(qnsch_ctx *x)
     if (!x) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "vcycle outside a step"; return QNSCH_EBUSY; }
     std::vector<Op> prog;
+    x->acc_use = 0; // a combination not applied by qnsch_accelerate is dropped
     cycle_program(x, prog);
     int rc;
     if ((rc = run_ops(x, prog))) return rc;
-    return read_red(x);
+    if ((rc = read_red(x))) return rc;
+    if (x->acc_wait) acc_after(x);
+    return QNSCH_OK;
+}
+
+int qnsch_accelerate(qnsch_ctx *x)
+{
+    if (!x) return QNSCH_EINVAL;
+    if (!x->in_step) { x->err = "accelerate outside a step"; return QNSCH_EBUSY; }
+    if (x->acc_use == 0) return QNSCH_OK;
+    int rc;
+    if ((rc = run_ops(x, { { OP_ACCEL, 0, 0 } }))) return rc;
+    HIPCHK(x, hipStreamSynchronize(x->s));
+    return QNSCH_OK;
 }
 
 int qnsch_residual(qnsch_ctx *x, double *r_out, double nrm[5])
@@ -947,9 +1078,11 @@ int qnsch_step(qnsch_ctx *x, double dt)
     auto t0 = std::chrono::steady_clock::now();
     int rc;
     if ((rc = set_dt(x, dt))) return rc;
-    std::vector<Op> begin, cyc;
+    std::vector<Op> begin, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
     step_begin_program(x, begin);
     cycle_program(x, cyc);
+    cyc_acc.insert(cyc_acc.end(), cyc.begin(), cyc.end());
+    acc_reset(x);
     if ((rc = run_ops(x, begin))) return rc;
     if ((rc = read_red(x))) return rc;
     x->in_step = 1;
@@ -967,8 +1100,9 @@ int qnsch_step(qnsch_ctx *x, double dt)
             return j;
         }
         if (j == 1) break;
-        if ((rc = run_ops(x, cyc))) return rc;
+        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return rc;
         if ((rc = read_red(x))) return rc;
+        if (x->acc_wait) acc_after(x);
         it++;
         x->st.vcycles = it;
     }
@@ -1214,9 +1348,9 @@ struct Req {
 
 // what fixes the device layout of a context
 typedef std::tuple<int, int, double, double, int, int, int, int> Shape;
-Shape shape_of(const qnsch_grid &g, int precision)
+Shape shape_of(const qnsch_grid &g, const qnsch_opts &o)
 {
-    return Shape(g.m1, g.m2, g.Lx, g.Ly, g.bc_x, g.bc_y, level_count(&g), precision);
+    return Shape(g.m1, g.m2, g.Lx, g.Ly, g.bc_x, g.bc_y, level_count(&g), o.precision * 16 + o.accel);
 }
 
 typedef std::chrono::steady_clock Clock;
@@ -1252,6 +1386,7 @@ static void start_step(Req *r)
     r->prog.clear();
     r->pc = 0;
     step_begin_program(r->x, r->prog);
+    acc_reset(r->x);
     r->vcycles = 0;
     r->t_step0 = Clock::now();
 }
@@ -1262,7 +1397,7 @@ static void start_step(Req *r)
 static int admit(qnsch_server *S, Req *r)
 {
     const auto t0 = Clock::now();
-    const Shape key = shape_of(r->g, r->o.precision);
+    const Shape key = shape_of(r->g, r->o);
     qnsch_ctx *x = nullptr;
     int rc = QNSCH_OK;
     r->lane = (int)(std::min_element(S->lane_load.begin(), S->lane_load.end()) - S->lane_load.begin());
@@ -1351,7 +1486,7 @@ static void complete_finish(qnsch_server *S, Req *r)
     S->t_last = r->t_done;
     S->used -= r->foot;
     S->lane_load[r->lane]--;
-    S->pool.insert({ shape_of(r->g, r->o.precision), x });
+    S->pool.insert({ shape_of(r->g, r->o), x });
     S->pooled += x->footprint;
     r->x = nullptr;
     S->host_finish_ms += ms_between(t0, Clock::now());
@@ -1378,6 +1513,7 @@ static void after_reduction(qnsch_server *S, Req *r)
         return;
     }
     r->wait = W_NONE;
+    if (x->acc_wait) acc_after(x);
     const int j = judge(x, r->vcycles);
     r->prog.clear();
     r->pc = 0;
@@ -1387,6 +1523,7 @@ static void after_reduction(qnsch_server *S, Req *r)
     } else if (j == 1) {
         r->prog.push_back({ OP_STEPEND, 0, 0 });
     } else {
+        if (x->acc_use > 0) r->prog.push_back({ OP_ACCEL, 0, 0 });
         cycle_program(x, r->prog);
         r->vcycles++;
     }
@@ -1396,7 +1533,9 @@ extern "C" {
 
 size_t qnsch_footprint(const qnsch_grid *g, const qnsch_opts *o)
 {
-    return g ? footprint_of(g, o ? o->precision : QNSCH_FP64) : 0;
+    qnsch_opts d;
+    qnsch_default_opts(&d);
+    return g ? footprint_of(g, o ? *o : d) : 0;
 }
 
 int qnsch_server_create(size_t hbm_budget, int32_t max_slots, int32_t lanes, void *stream, qnsch_server **out)
@@ -1457,7 +1596,7 @@ int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params
     r->c0.assign(c0, c0 + (size_t)g->m1 * g->m2);
     r->nsteps = nsteps;
     r->dt = dt;
-    r->foot = footprint_of(g, r->o.precision);
+    r->foot = footprint_of(g, r->o);
     if (r->foot > S->budget) {
         delete r;
         return QNSCH_ENOMEM;
@@ -1531,7 +1670,7 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
             S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
             for (Req *r : best->second) {
                 r->pc++;
-                if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_STEPEND) {
+                if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_NORMACC || kind == OP_STEPEND) {
                     r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
                     (void)hipEventRecord(r->x->ev, st);
                 } else if (kind == OP_RESTORE) {

@@ -20,6 +20,7 @@ PRIMITIVE, PROJECTION = 0, 1
 # every exported symbol declared in include/qnsch.h
 SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_error", "qnsch_levels",
            "qnsch_set_state", "qnsch_set_iterate", "qnsch_get_state", "qnsch_step", "qnsch_begin_step", "qnsch_vcycle",
+           "qnsch_accelerate",
            "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy",
            "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
            "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
@@ -31,7 +32,8 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
 # operation classes of qnsch_profile_breakdown, in the library's numbering
 OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
             "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
-            "mx_prolong", "mx_update", "dissipation", "diagnostics", "pj_final", "smooth", "mx_smooth")
+            "mx_prolong", "mx_update", "dissipation", "diagnostics", "pj_final", "smooth", "mx_smooth", "residual_acc",
+            "accelerate")
 
 
 class QnschError(RuntimeError):
@@ -53,7 +55,8 @@ class Params(C.Structure):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_vcycles", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("nu_coarse", C.c_int32), ("vanka_omega", C.c_double),
-                ("smoother", C.c_int32), ("scheme", C.c_int32), ("coarse_omega", C.c_double)]
+                ("smoother", C.c_int32), ("scheme", C.c_int32), ("coarse_omega", C.c_double),
+                ("accel", C.c_int32)]
 
 
 class StepStats(C.Structure):
@@ -88,6 +91,7 @@ def lib():
         L.qnsch_step.argtypes = [vp, C.c_double]
         L.qnsch_begin_step.argtypes = [vp, C.c_double]
         L.qnsch_vcycle.argtypes = [vp]
+        L.qnsch_accelerate.argtypes = [vp]
         L.qnsch_residual.argtypes = [vp, P, P]
         L.qnsch_halfsweep.argtypes = [vp, C.c_int]
         L.qnsch_end_step.argtypes = [vp]
@@ -201,6 +205,9 @@ class Solver:
 
     def vcycle(self):
         self._chk(lib().qnsch_vcycle(self.h))
+
+    def accelerate(self):
+        self._chk(lib().qnsch_accelerate(self.h))
 
     def residual(self):
         r = np.zeros((5, self.m2, self.m1))

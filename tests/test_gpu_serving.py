@@ -82,11 +82,13 @@ def test_served_results_equal_alone(lanes):
     # energy(); a served step has one).  FP64 and mixed requests alternate
     # and never share a launch, and requests of one kind are at different
     # points of their steps, so the saving is well short of the 3x of three
-    # slots: at least 10 % on one lane (about 20 % measured)
+    # slots: at least 5 % on one lane (7 % measured with the default
+    # acceleration, whose combination adds an operation to each cycle; 20 %
+    # with plain cycles)
     alone_launches = sum(count) - nsteps * len(cases)
     say("launches served", s["launches"], "alone", alone_launches)
     if lanes == 1:
-        assert s["launches"] < 0.9 * alone_launches
+        assert s["launches"] < 0.95 * alone_launches
     else:
         assert s["launches"] <= alone_launches
     assert s["contexts_created"] < len(cases)  # the second round reuses contexts

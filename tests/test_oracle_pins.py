@@ -558,9 +558,10 @@ def test_mass_conservation_and_energy_law(cfg):
 # ---------------------------------------------------------------------------
 # the solver reaches the root of N (dense Newton on the same system)
 
+@pytest.mark.parametrize("accel", [0, 2], ids=["plain", "accelerated"])
 @pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("case", ["walls", "periodic_x"])
-def test_multigrid_root_equals_dense_newton(case, smoother):
+def test_multigrid_root_equals_dense_newton(case, smoother, accel):
     if case == "walls":
         c = W.rising_drop(8, 16, eps=0.1)
     else:
@@ -568,7 +569,7 @@ def test_multigrid_root_equals_dense_newton(case, smoother):
     P = dict(c["params"], inv_Fr=1.0)
     dt = 0.01
     # MG
-    o = mk(c["grid"], P, dict(W.default_opts(1e-12), smoother=smoother))
+    o = mk(c["grid"], P, dict(W.default_opts(1e-12), smoother=smoother, accel=accel))
     o.set_state(c["state"]["c"])
     assert o.step(dt) == OR.OK
     smg = o.get_state()
@@ -742,7 +743,7 @@ def test_vcycle_contracts_and_is_deterministic():
     c = W.capillary()
     runs = []
     for _ in range(2):
-        o = mk(c["grid"], c["params"], W.default_opts(1e-10))
+        o = mk(c["grid"], c["params"], dict(W.default_opts(1e-10), accel=0))
         o.set_state(c["state"]["c"])
         assert o.step(c["dt"]) == OR.OK
         nv, hist = o.stats()
@@ -785,7 +786,7 @@ def test_vcycle_factor_is_mesh_independent():
     f = []
     for m1 in (32, 64):
         c = W.capillary(m1, 2 * m1, eps=0.02, levels=0)
-        o = mk(c["grid"], c["params"], W.default_opts(1e-11))
+        o = mk(c["grid"], c["params"], dict(W.default_opts(1e-11), accel=0))
         o.set_state(c["state"]["c"])
         assert o.step(c["dt"]) == OR.OK
         nv, hist = o.stats()
