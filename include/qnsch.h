@@ -139,7 +139,9 @@ typedef struct {
  * asks only for a standard FAS V-cycle; the discrete system, its root and the
  * stop test are unchanged).  The cycle results w_k (after the pbar mean
  * removal) and their residuals r_k = -N(w_k) are kept for the last m + 1
- * cycles of a step.  Before the next cycle the iterate becomes
+ * cycles of a step, from its second cycle on (the first result's residual
+ * is dominated by the change of the time-n data).  Before the next cycle
+ * the iterate becomes
  *   w = w_k + sum_i g_i (w_k - w_{k-i}),  i = 1..n,
  * with g minimising the linearised residual || r_k + sum_i g_i (r_k - r_{k-i}) ||
  * (plain sum of squares over the five fields; normal equations solved by
@@ -195,11 +197,12 @@ int qnsch_step(qnsch_ctx *ctx, double dt);
 
 /* Phases of a step, for inspection: begin_step fixes the time-n data (the
  * current state) on every level; vcycle runs one V-cycle, fixes the mean of
- * pbar to zero and (accel > 0) records the result and its residual for the
- * acceleration; accelerate replaces the iterate by the combination of the
- * recorded results (see above; no change after the first cycle of a step or
- * with accel = 0); a step is vcycle, then accelerate and vcycle until the
- * tolerance is met.  residual returns r = -N(w) of the current iterate (5
+ * pbar to zero and (accel > 0, from the second call of the step on) records
+ * the result and its residual for the acceleration; accelerate replaces the
+ * iterate by the combination of the recorded results (see above; no change
+ * before two results are recorded or with accel = 0; a combination not
+ * applied before the next vcycle is dropped); a step is vcycle, then
+ * accelerate and vcycle until the tolerance is met.  residual returns r = -N(w) of the current iterate (5
  * fields of m1*m2, order c, mu, p, u, v; NULL to skip) and its norms;
  * halfsweep runs one colour half-sweep (colour 0: (i+j) even) on the finest
  * level; end_step commits the iterate as the new state (projection scheme:

@@ -95,7 +95,7 @@ struct orc_ctx {
      * step (hw) and their residuals (hr), index 0 the newest; the pending
      * combination uses acc_use of the earlier ones with coefficients acc_g */
     double *hw[ORC_MAXACC + 1][NSTATE], *hr[ORC_MAXACC + 1][NSTATE];
-    int nh, acc_use, acc_pending;
+    int nh, acc_use, acc_pending, ncycle;
     double acc_g[ORC_MAXACC], acc_last, acc_nr[NSTATE];
     /* statistics of the last step */
     int nv;
@@ -1034,6 +1034,7 @@ void orc_begin_step(orc_ctx *o, double dt)
     o->acc_use = 0;
     o->acc_pending = 0;
     o->acc_last = 0.0;
+    o->ncycle = 0;
 }
 
 void orc_residual(orc_ctx *o, double *r_out /* 5*m1*m2 or NULL */, double norms[5])
@@ -1049,14 +1050,15 @@ void orc_residual(orc_ctx *o, double *r_out /* 5*m1*m2 or NULL */, double norms[
 
 void orc_halfsweep(orc_ctx *o, int colour) { halfsweep(o, 0, colour & 1); }
 
-/* one cycle: V-cycle, pbar mean removal and, with acceleration, the record
- * of the result (a pending combination that was not applied is dropped) */
+/* one cycle: V-cycle, pbar mean removal and, with acceleration, from the
+ * second cycle of the step on, the record of the result (a pending
+ * combination that was not applied is dropped) */
 void orc_vcycle(orc_ctx *o)
 {
     o->acc_pending = 0;
     vcycle(o, 0);
     remove_p_mean(o);
-    if (o->o.accel > 0) {
+    if (o->o.accel > 0 && o->ncycle++ > 0) {
         Level *L = &o->lev[0];
         residual_level(o, L, L->r);
         norms_level(L, L->r, o->acc_nr);
@@ -1145,7 +1147,7 @@ int orc_solve(orc_ctx *o)
         if (it > 0) orc_accelerate(o);
         orc_vcycle(o);
         it++;
-        if (o->o.accel > 0) memcpy(nr, o->acc_nr, sizeof(nr));
+        if (o->o.accel > 0 && it > 1) memcpy(nr, o->acc_nr, sizeof(nr));
         else orc_residual(o, NULL, nr);
         for (int e = 0; e < NSTATE; e++) o->hist[it][e] = nr[e];
         o->nv = it;

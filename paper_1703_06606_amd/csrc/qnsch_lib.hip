@@ -152,6 +152,7 @@ struct qnsch_ctx {
     int acc_dots = 0;     // earlier results the latest one's reduction paired it with
     int acc_use = 0;      // earlier results the pending combination uses (0: none pending)
     bool acc_wait = false;  // a recording reduction is in flight
+    int acc_cycles = 0;     // cycles of the step so far (phase calls)
     double acc_g[3] = { 0.0, 0.0, 0.0 };
     double acc_last = 0.0;  // largest residual norm of the latest result
 };
@@ -172,10 +173,15 @@ static int small_level(const qnsch_ctx *x)
     }
     return small;
 }
-static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
+// one cycle; with acceleration the results from the second cycle of a step
+// on are recorded (the first one's residual direction is dominated by the
+// change of the time-n data; leaving it out costs no cycle on the droplet,
+// Rayleigh-Taylor and drop-box workloads and saves its recording)
+static void cycle_program(const qnsch_ctx *x, bool first, std::vector<Op> &out)
 {
-    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), x->opt.accel > 0, out);
-    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), x->opt.accel > 0, out);
+    const bool rec = x->opt.accel > 0 && !first;
+    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), rec, out);
+    else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), rec, out);
 }
 
 #define HIPCHK(ctx, x)                                                                        \
@@ -380,6 +386,7 @@ static void acc_reset(qnsch_ctx *x)
     x->acc_use = 0;
     x->acc_wait = false;
     x->acc_last = 0.0;
+    x->acc_cycles = 0;
 }
 
 // Launch one operation for a set of (context, level) entries, in lists of at
@@ -948,7 +955,8 @@ int qnsch_vcycle(qnsch_ctx *x)
     if (!x->in_step) { x->err = "vcycle outside a step"; return QNSCH_EBUSY; }
     std::vector<Op> prog;
     x->acc_use = 0; // a combination not applied by qnsch_accelerate is dropped
-    cycle_program(x, prog);
+    cycle_program(x, x->acc_cycles == 0, prog);
+    x->acc_cycles++;
     int rc;
     if ((rc = run_ops(x, prog))) return rc;
     if ((rc = read_red(x))) return rc;
@@ -1078,9 +1086,10 @@ int qnsch_step(qnsch_ctx *x, double dt)
     auto t0 = std::chrono::steady_clock::now();
     int rc;
     if ((rc = set_dt(x, dt))) return rc;
-    std::vector<Op> begin, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
+    std::vector<Op> begin, cyc1, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
     step_begin_program(x, begin);
-    cycle_program(x, cyc);
+    cycle_program(x, true, cyc1);
+    cycle_program(x, false, cyc);
     cyc_acc.insert(cyc_acc.end(), cyc.begin(), cyc.end());
     acc_reset(x);
     if ((rc = run_ops(x, begin))) return rc;
@@ -1100,7 +1109,7 @@ int qnsch_step(qnsch_ctx *x, double dt)
             return j;
         }
         if (j == 1) break;
-        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return rc;
+        if ((rc = run_ops(x, it == 0 ? cyc1 : (x->acc_use > 0 ? cyc_acc : cyc)))) return rc;
         if ((rc = read_red(x))) return rc;
         if (x->acc_wait) acc_after(x);
         it++;
@@ -1524,7 +1533,7 @@ static void after_reduction(qnsch_server *S, Req *r)
         r->prog.push_back({ OP_STEPEND, 0, 0 });
     } else {
         if (x->acc_use > 0) r->prog.push_back({ OP_ACCEL, 0, 0 });
-        cycle_program(x, r->prog);
+        cycle_program(x, r->vcycles == 0, r->prog);
         r->vcycles++;
     }
 }
