@@ -81,8 +81,20 @@ struct Items {
     int tx[MAXITEMS];         // tiles per row (tile kernels); partial count (k_finalize)
     short acc[MAXITEMS];      // acceleration ring slot s | (earlier results used) << 4; -1 none
 };
+// The same for a list of one item (a simulation run on its own): 32 bytes
+// of kernel arguments instead of 1.4 KB, which a dependent launch pays for
+// (about 1.5 us measured per launch).  Kernels are instantiated for both.
+struct Item1 {
+    int n;
+    int start[2];
+    const Desc *d[1];
+    short par[1];
+    short cpar[1];
+    int tx[1];
+    short acc[1];
+};
 
-__device__ __forceinline__ int find_item(const Items &it)
+template <typename IT> __device__ __forceinline__ int find_item(const IT &it)
 {
     int k = 0;
     while (k + 1 < it.n && (int)blockIdx.x >= it.start[k + 1]) k++;
@@ -110,8 +122,8 @@ __device__ __forceinline__ Rhs rhs_of(const Desc &d)
 // Items start at multiples of NXCD and their tiles are renumbered so that an
 // XCD gets a contiguous band of tiles: neighbouring tiles, which read each
 // other's halos, share one L2.
-template <typename R>
-__device__ __forceinline__ TileT<R> item_tile(R *sm, const Items &it, int k, const Desc &d)
+template <typename R, typename IT>
+__device__ __forceinline__ TileT<R> item_tile(R *sm, const IT &it, int k, const Desc &d)
 {
     const int tx = it.tx[k];
     const int ty = (d.m2 + TY - 1) / TY;
@@ -125,7 +137,7 @@ __device__ __forceinline__ TileT<R> item_tile(R *sm, const Items &it, int k, con
     T.H = TY + 3;
     return T;
 }
-__device__ __forceinline__ bool tile_valid(const Items &it, int k, const Desc &d)
+template <typename IT> __device__ __forceinline__ bool tile_valid(const IT &it, int k, const Desc &d)
 {
     return (int)blockIdx.x - it.start[k] < it.tx[k] * ((d.m2 + TY - 1) / TY);
 }
@@ -133,7 +145,7 @@ __device__ __forceinline__ bool tile_valid(const Items &it, int k, const Desc &d
 // --------------------------------------------------------------------------
 // one colour half-sweep (sec. 7.1) on a tile: a lane pair per cell of the
 // colour.  The u/v snapshot is buffer par, the new faces go to buffer par^1.
-__device__ __forceinline__ void halfsweep_body(const Items &it, int colour, double omega)
+template <typename IT> __device__ __forceinline__ void halfsweep_body(const IT &it, int colour, double omega)
 {
     __shared__ double sm[TILE_DOUBLES];
     const int k = find_item(it);
@@ -150,13 +162,13 @@ __device__ __forceinline__ void halfsweep_body(const Items &it, int colour, doub
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
     if (i < L.m1 && j < L.m2) relax_pair(d.P, L, T, rhs_of(d), d.ub[par ^ 1], d.vb[par ^ 1], i, j, hlf, omega, 1.0);
 }
-__global__ HS_ATTR void k_halfsweep(Items it, int colour, double omega)
+template <typename IT> __global__ HS_ATTR void k_halfsweep(IT it, int colour, double omega)
 {
     halfsweep_body(it, colour, omega);
 }
 // the same kernel under its own name for launches whose items are all finest
 // levels, so that profiles tell the finest level apart
-__global__ FINE_ATTR void k_halfsweep_fine(Items it, int colour, double omega)
+template <typename IT> __global__ FINE_ATTR void k_halfsweep_fine(IT it, int colour, double omega)
 {
     halfsweep_body(it, colour, omega);
 }
@@ -178,7 +190,7 @@ __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
 // post-smoothing of coarse levels small enough (the same arithmetic as the
 // half-sweep launches); the u/v buffers alternate, the number of half-sweeps
 // is even, so the result stays in buffer par
-__global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, double omega, double pomega)
+template <typename IT> __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double omega, double pomega)
 {
     extern __shared__ double sm[];
     const int k = find_item(it);
@@ -234,7 +246,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(Items it, int sweeps, doub
 // iterate (cells: mean of the four children; faces: mean of the two coincident
 // fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w).
 // A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane pair each.
-__global__ __launch_bounds__(TBLK) void k_restrict(Items it)
+template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
     const int k = find_item(it);
@@ -294,7 +306,7 @@ template <typename TT> __device__ __forceinline__ void pair_cells(const TT &T, i
 
 // f_H = N_H(R w) + R r (FAS coarse right-hand side) on the coarse level the
 // item names; walls carry no equation
-__global__ __launch_bounds__(TBLK) void k_coarse_rhs(Items it)
+template <typename IT> __global__ __launch_bounds__(TBLK) void k_coarse_rhs(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
     const int k = find_item(it);
@@ -327,7 +339,7 @@ __global__ __launch_bounds__(TBLK) void k_coarse_rhs(Items it)
 // w_h += P(w_H - R w_h) on the level the item names: cells piecewise
 // constant; faces copy the coincident coarse face and average the two coarse
 // faces across the coarse cell.  One thread per fine cell.
-__global__ __launch_bounds__(BLK) void k_prolong(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_prolong(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -428,7 +440,7 @@ __device__ __forceinline__ void acc_dots(const Desc &d, int ac, size_t w, int hl
 // equations, the sum of pbar, and the count of cells that are non-finite or
 // past the density pole (partials indexed by the tile's place in the band
 // order); optionally the residual fields themselves
-__global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
+template <typename IT> __global__ __launch_bounds__(TBLK) void k_resid_norm(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
     const int k = find_item(it);
@@ -490,7 +502,7 @@ __global__ __launch_bounds__(TBLK) void k_resid_norm(Items it)
 }
 
 // mass and energy partial sums of the current state, one thread per cell
-__global__ __launch_bounds__(BLK) void k_mass_energy(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_mass_energy(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -529,7 +541,7 @@ __global__ __launch_bounds__(BLK) void k_mass_energy(Items it)
 //   2: A m(c^n) |D mu_c|^2 on the west and south faces, mu_c = mubar + alpha pbar
 //   3: A rho^n |u - u^n|^2 on the west and south faces (unknown faces only)
 // One thread per cell.
-__global__ __launch_bounds__(BLK) void k_dissipation(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_dissipation(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -598,7 +610,7 @@ __global__ __launch_bounds__(BLK) void k_dissipation(Items it)
 // the projection equation (pj-num-pjx) (as face_final) on every west and
 // south face, written to the other face buffer, which becomes the current
 // one; the intermediate velocity stays in buffer par for the dissipation.
-__global__ __launch_bounds__(BLK) void k_pj_final(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_pj_final(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -638,7 +650,7 @@ __global__ __launch_bounds__(BLK) void k_pj_final(Items it)
 //   7: max height of a crossing in the first column (x = h/2)
 // (5-7 hold -inf / +inf where there is none.)
 #define DIAG_NONE 1e300
-__global__ __launch_bounds__(BLK) void k_diagnostics(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_diagnostics(IT it)
 {
     __shared__ double sh[BLK / 64][NRED];
     const int k = find_item(it);
@@ -699,7 +711,7 @@ __global__ __launch_bounds__(BLK) void k_diagnostics(Items it)
 // norms become sqrt(h^2 sum r^2); written to device and pinned host memory.
 // mode 0: residual reduction (5 norms, sum p, bad count); 1: plain sums;
 // 2: the diagnostics slots (sum, max or min per slot as in k_diagnostics).
-__global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_finalize(IT it, int mode)
 {
     __shared__ double sh[BLK][NRED];
     const int k = blockIdx.x;
@@ -736,7 +748,7 @@ __global__ __launch_bounds__(BLK) void k_finalize(Items it, int mode)
 }
 
 // pbar -= mean(pbar), the mean from the reduced sums
-__global__ __launch_bounds__(BLK) void k_shift_p(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_shift_p(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -747,8 +759,8 @@ __global__ __launch_bounds__(BLK) void k_shift_p(Items it)
 }
 
 // coefficients of the accelerated combination, per item
-struct AccCoef {
-    double g[MAXITEMS][3];
+template <int N> struct AccCoef {
+    double g[N][3];
 };
 
 // Acceleration step of the cycle iteration: the current iterate w (the last
@@ -757,7 +769,7 @@ struct AccCoef {
 // which makes it the iterate that result was).  Mixed precision: the next
 // correction cycle's right-hand side becomes the same combination of the
 // recorded residuals, its linearisation point the combined iterate.
-__global__ __launch_bounds__(BLK) void k_accel(Items it, AccCoef G)
+template <typename IT, int N> __global__ __launch_bounds__(BLK) void k_accel(IT it, AccCoef<N> G)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -801,7 +813,7 @@ __global__ __launch_bounds__(BLK) void k_accel(Items it, AccCoef G)
 }
 
 // time-n data of the finest level = current iterate; keep mubar, pbar of time n
-__global__ __launch_bounds__(BLK) void k_begin(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_begin(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -823,7 +835,7 @@ __global__ __launch_bounds__(BLK) void k_begin(Items it)
 }
 
 // time-n data of the coarser level of the item's level
-__global__ __launch_bounds__(BLK) void k_restrict_n(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_restrict_n(IT it)
 {
     const int k = find_item(it);
     const Desc &F = *it.d[k];
@@ -838,7 +850,7 @@ __global__ __launch_bounds__(BLK) void k_restrict_n(Items it)
 }
 
 // restore the state of time n on the finest level (failed step)
-__global__ __launch_bounds__(BLK) void k_restore(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_restore(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];

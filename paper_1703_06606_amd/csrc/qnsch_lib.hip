@@ -389,6 +389,35 @@ static void acc_reset(qnsch_ctx *x)
     x->acc_cycles = 0;
 }
 
+// a work list of one item in its compact form
+static Item1 one_of(const Items &a)
+{
+    Item1 b;
+    memset(&b, 0, sizeof(b));
+    b.n = 1;
+    b.start[0] = a.start[0];
+    b.start[1] = a.start[1];
+    b.d[0] = a.d[0];
+    b.par[0] = a.par[0];
+    b.cpar[0] = a.cpar[0];
+    b.tx[0] = a.tx[0];
+    b.acc[0] = a.acc[0];
+    return b;
+}
+// launch kernel template K on list L (ItemList): the one-item instantiation
+// when the list has a single item
+#define KLAUNCH(K, L, GRID, BLOCK, LDS, ST, ...)                                                     \
+    do {                                                                                           \
+        if ((L).it.n == 1) hipLaunchKernelGGL(K<Item1>, GRID, BLOCK, LDS, ST, one_of((L).it), ##__VA_ARGS__); \
+        else hipLaunchKernelGGL(K<Items>, GRID, BLOCK, LDS, ST, (L).it, ##__VA_ARGS__);            \
+    } while (0)
+#define KLAUNCH_EV(K, L, GRID, BLOCK, ST, E0, E1, ...)                                               \
+    do {                                                                                           \
+        if ((L).it.n == 1)                                                                         \
+            hipExtLaunchKernelGGL(K<Item1>, GRID, BLOCK, 0, ST, E0, E1, 0, one_of((L).it), ##__VA_ARGS__); \
+        else hipExtLaunchKernelGGL(K<Items>, GRID, BLOCK, 0, ST, E0, E1, 0, (L).it, ##__VA_ARGS__); \
+    } while (0)
+
 // Launch one operation for a set of (context, level) entries, in lists of at
 // most MAXITEMS; all entries share the kind and colour.  Errors are reported
 // on the first context.
@@ -420,18 +449,18 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             const dim3 gr(W.blocks), bl(TBLK);
             if (kind == OP_MXHS) {
                 if (W.all_fine)
-                    hipExtLaunchKernelGGL(k_mx_halfsweep_fine, gr, bl, 0, s, e0, e1, 0, W.it, colour, (float)omega);
-                else hipExtLaunchKernelGGL(k_mx_halfsweep, gr, bl, 0, s, e0, e1, 0, W.it, colour, (float)omega);
+                    KLAUNCH_EV(k_mx_halfsweep_fine, W, gr, bl, s, e0, e1, colour, (float)omega);
+                else KLAUNCH_EV(k_mx_halfsweep, W, gr, bl, s, e0, e1, colour, (float)omega);
             } else if (W.all_fine) {
-                hipExtLaunchKernelGGL(k_halfsweep_fine, gr, bl, 0, s, e0, e1, 0, W.it, colour, omega);
+                KLAUNCH_EV(k_halfsweep_fine, W, gr, bl, s, e0, e1, colour, omega);
             } else {
-                hipExtLaunchKernelGGL(k_halfsweep, gr, bl, 0, s, e0, e1, 0, W.it, colour, omega);
+                KLAUNCH_EV(k_halfsweep, W, gr, bl, s, e0, e1, colour, omega);
             }
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
-        case OP_RESTRICT: hipLaunchKernelGGL(k_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
-        case OP_CRHS: hipLaunchKernelGGL(k_coarse_rhs, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
+        case OP_RESTRICT: KLAUNCH(k_restrict, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
+        case OP_CRHS: KLAUNCH(k_coarse_rhs, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
         case OP_COARSE:
         case OP_SMOOTH: {
             int nmax = 0;
@@ -443,11 +472,11 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
             const double om = coarsest && !pj ? x0->opt.coarse_omega : omega;
             const double pom = coarsest && pj ? x0->opt.coarse_omega : 1.0;
-            hipLaunchKernelGGL(k_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, om, pom);
+            KLAUNCH(k_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, om, pom);
             break;
         }
-        case OP_PROLONG: hipLaunchKernelGGL(k_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_MXRESTRICT: hipLaunchKernelGGL(k_mx_restrict, dim3(W.blocks), dim3(TBLK), 0, s, W.it); break;
+        case OP_PROLONG: KLAUNCH(k_prolong, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_MXRESTRICT: KLAUNCH(k_mx_restrict, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
         case OP_MXCOARSE:
         case OP_MXSMOOTH: {
             int nmax = 0;
@@ -456,45 +485,45 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             const bool coarsest = kind == OP_MXCOARSE;
             const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
             const double om = coarsest ? x0->opt.coarse_omega : omega;
-            hipLaunchKernelGGL(k_mx_coarse_solve, dim3(W.blocks), dim3(th), W.lds, s, W.it, sweeps, (float)om);
+            KLAUNCH(k_mx_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, (float)om);
             break;
         }
-        case OP_MXPROLONG: hipLaunchKernelGGL(k_mx_prolong, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_MXUPDATE: hipLaunchKernelGGL(k_mx_update, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_MXRN: hipLaunchKernelGGL(k_mx_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_BEGIN: hipLaunchKernelGGL(k_begin, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_RN: hipLaunchKernelGGL(k_restrict_n, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
-        case OP_RESTORE: hipLaunchKernelGGL(k_restore, dim3(W.blocks), dim3(BLK), 0, s, W.it); break;
+        case OP_MXPROLONG: KLAUNCH(k_mx_prolong, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_MXUPDATE: KLAUNCH(k_mx_update, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_MXRN: KLAUNCH(k_mx_restrict_n, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_BEGIN: KLAUNCH(k_begin, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_RN: KLAUNCH(k_restrict_n, W, dim3(W.blocks), dim3(BLK), 0, s); break;
+        case OP_RESTORE: KLAUNCH(k_restore, W, dim3(W.blocks), dim3(BLK), 0, s); break;
         case OP_NORM0:
         case OP_NORM:
         case OP_NORMACC: {
             if (kind == OP_NORMACC)
                 for (size_t q = 0; q < part.size(); q++) acc_record_launch(part[q].first, W.it.acc[q]);
-            hipLaunchKernelGGL(k_resid_norm, dim3(W.blocks), dim3(TBLK), 0, s, W.it);
+            KLAUNCH(k_resid_norm, W, dim3(W.blocks), dim3(TBLK), 0, s);
             ItemList F = finalize_list(part, OP_NORM);
             for (size_t q = 0; q < part.size(); q++) F.it.acc[q] = W.it.acc[q];
-            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 0);
+            KLAUNCH(k_finalize, F, dim3(F.blocks), dim3(BLK), 0, s, 0);
             if (kind != OP_NORM0) {
                 ItemList S;
                 for (auto &pe : part) add_item(S, pe.first, OP_BEGIN, 0);
-                hipLaunchKernelGGL(k_shift_p, dim3(S.blocks), dim3(BLK), 0, s, S.it);
+                KLAUNCH(k_shift_p, S, dim3(S.blocks), dim3(BLK), 0, s);
             }
             break;
         }
         case OP_STEPEND: {
-            hipLaunchKernelGGL(k_mass_energy, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            KLAUNCH(k_mass_energy, W, dim3(W.blocks), dim3(BLK), 0, s);
             ItemList F = finalize_list(part, OP_STEPEND);
-            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
+            KLAUNCH(k_finalize, F, dim3(F.blocks), dim3(BLK), 0, s, 1);
             break;
         }
         case OP_DISSIP: {
-            hipLaunchKernelGGL(k_dissipation, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            KLAUNCH(k_dissipation, W, dim3(W.blocks), dim3(BLK), 0, s);
             ItemList F = finalize_list(part, OP_DISSIP);
-            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 1);
+            KLAUNCH(k_finalize, F, dim3(F.blocks), dim3(BLK), 0, s, 1);
             break;
         }
         case OP_ACCEL: {
-            AccCoef G;
+            AccCoef<MAXITEMS> G;
             memset(&G, 0, sizeof(G));
             for (size_t q = 0; q < part.size(); q++) {
                 qnsch_ctx *x = part[q].first;
@@ -502,18 +531,24 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
                 for (int b = 0; b < 3; b++) G.g[q][b] = x->acc_g[b];
                 x->acc_use = 0;
             }
-            hipLaunchKernelGGL(k_accel, dim3(W.blocks), dim3(BLK), 0, s, W.it, G);
+            if (W.it.n == 1) {
+                AccCoef<1> G1;
+                for (int b = 0; b < 3; b++) G1.g[0][b] = G.g[0][b];
+                hipLaunchKernelGGL((k_accel<Item1, 1>), dim3(W.blocks), dim3(BLK), 0, s, one_of(W.it), G1);
+            } else {
+                hipLaunchKernelGGL((k_accel<Items, MAXITEMS>), dim3(W.blocks), dim3(BLK), 0, s, W.it, G);
+            }
             break;
         }
         case OP_PJFINAL: {
-            hipLaunchKernelGGL(k_pj_final, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            KLAUNCH(k_pj_final, W, dim3(W.blocks), dim3(BLK), 0, s);
             for (auto &pe : part) pe.first->L[0].cur ^= 1;
             break;
         }
         case OP_DIAG: {
-            hipLaunchKernelGGL(k_diagnostics, dim3(W.blocks), dim3(BLK), 0, s, W.it);
+            KLAUNCH(k_diagnostics, W, dim3(W.blocks), dim3(BLK), 0, s);
             ItemList F = finalize_list(part, OP_DIAG);
-            hipLaunchKernelGGL(k_finalize, dim3(F.blocks), dim3(BLK), 0, s, F.it, 2);
+            KLAUNCH(k_finalize, F, dim3(F.blocks), dim3(BLK), 0, s, 2);
             break;
         }
         default: break;
@@ -777,8 +812,11 @@ static size_t device_lds_max()
     int v = 0;
     size_t r = 65536;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 65536
-        && hipFuncSetAttribute((const void *)k_coarse_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess
-        && hipFuncSetAttribute((const void *)k_mx_coarse_solve, hipFuncAttributeMaxDynamicSharedMemorySize, v)
+        && hipFuncSetAttribute((const void *)k_coarse_solve<Items>, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess
+        && hipFuncSetAttribute((const void *)k_coarse_solve<Item1>, hipFuncAttributeMaxDynamicSharedMemorySize, v) == hipSuccess
+        && hipFuncSetAttribute((const void *)k_mx_coarse_solve<Items>, hipFuncAttributeMaxDynamicSharedMemorySize, v)
+               == hipSuccess
+        && hipFuncSetAttribute((const void *)k_mx_coarse_solve<Item1>, hipFuncAttributeMaxDynamicSharedMemorySize, v)
                == hipSuccess)
         r = (size_t)v;
     (void)hipGetLastError();
@@ -1034,7 +1072,7 @@ int qnsch_lin_apply(qnsch_ctx *x, const double *dw, double *out)
     }
     ItemList W;
     add_item(W, x, OP_MXHS, 0);
-    hipLaunchKernelGGL(k_mx_linresid, dim3(W.blocks), dim3(TBLK), 0, x->s, W.it);
+    KLAUNCH(k_mx_linresid, W, dim3(W.blocks), dim3(TBLK), 0, x->s);
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipMemcpyAsync(out, d.rout, 5 * n * sizeof(double), hipMemcpyDeviceToHost, x->s));
     HIPCHK(x, hipStreamSynchronize(x->s));

@@ -34,7 +34,7 @@ __device__ __forceinline__ LView lview_of(const Desc &d, int par)
 
 // one colour half-sweep of the correction smoother; the correction faces are
 // read from buffer par and written to par^1
-__device__ __forceinline__ void mx_halfsweep_body(const Items &it, int colour, float omega)
+template <typename IT> __device__ __forceinline__ void mx_halfsweep_body(const IT &it, int colour, float omega)
 {
     __shared__ float sm[LTILE_FLOATS];
     const int k = find_item(it);
@@ -51,12 +51,12 @@ __device__ __forceinline__ void mx_halfsweep_body(const Items &it, int colour, f
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
     if (i < L.m1 && j < L.m2) lrelax_pair(d.Pf, L, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, hlf, omega);
 }
-__global__ HS_ATTR void k_mx_halfsweep(Items it, int colour, float omega)
+template <typename IT> __global__ HS_ATTR void k_mx_halfsweep(IT it, int colour, float omega)
 {
     mx_halfsweep_body(it, colour, omega);
 }
 // finest-level launches under their own name (profiles)
-__global__ HS_ATTR void k_mx_halfsweep_fine(Items it, int colour, float omega)
+template <typename IT> __global__ HS_ATTR void k_mx_halfsweep_fine(IT it, int colour, float omega)
 {
     mx_halfsweep_body(it, colour, omega);
 }
@@ -64,7 +64,7 @@ __global__ HS_ATTR void k_mx_halfsweep_fine(Items it, int colour, float omega)
 // r - J delta on the item's level, restricted to the next coarser level
 // (cells: mean of four; faces: mean of the two coincident fine faces),
 // together with the linearisation point; the coarse correction starts at 0
-__global__ __launch_bounds__(TBLK) void k_mx_restrict(Items it)
+template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_restrict(IT it)
 {
     __shared__ float sm[LTILE_FLOATS];
     const int k = find_item(it);
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(TBLK) void k_mx_restrict(Items it)
 
 // delta_h += P delta_H: cells piecewise constant; faces copy the coincident
 // coarse face and average the two coarse faces across the coarse cell
-__global__ __launch_bounds__(BLK) void k_mx_prolong(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_prolong(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -159,7 +159,7 @@ __host__ __device__ inline size_t mx_coarse_lds_floats(int m1, int m2)
 // all correction sweeps of a level in one workgroup per item, the level
 // resident in LDS (the coarsest level, and the smoothing of small coarse
 // levels); an even number of half-sweeps keeps the result in buffer par
-__global__ __launch_bounds__(512) void k_mx_coarse_solve(Items it, int sweeps, float omega)
+template <typename IT> __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, float omega)
 {
     extern __shared__ float smf[];
     const int k = find_item(it);
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(Items it, int sweeps, f
 
 // w += delta on the finest level (FP64 state, single u/v buffer in mixed
 // mode); faces on walls are not unknowns
-__global__ __launch_bounds__(BLK) void k_mx_update(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_update(IT it)
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLK) void k_mx_update(Items it)
 }
 
 // FP32 time-n data of the next coarser level
-__global__ __launch_bounds__(BLK) void k_mx_restrict_n(Items it)
+template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_restrict_n(IT it)
 {
     const int k = find_item(it);
     const Desc &F = *it.d[k];
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(BLK) void k_mx_restrict_n(Items it)
 
 // r - J delta on a level into the FP64 residual-field buffer (m1 x m2 per
 // field, packed), for checking the linearisation
-__global__ __launch_bounds__(TBLK) void k_mx_linresid(Items it)
+template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_linresid(IT it)
 {
     __shared__ float sm[LTILE_FLOATS];
     const int k = find_item(it);
