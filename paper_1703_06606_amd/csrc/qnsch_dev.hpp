@@ -304,6 +304,51 @@ __device__ __forceinline__ void tile_refresh(const Phys &P, const View &L, const
     }
 }
 
+// A level resident in LDS is refreshed into its tile after every half-sweep.
+// Where each element comes from is fixed, so it is computed once (4 ints per
+// element: the cell, u and v source indices as tile_src gives them, and a
+// word with the u and v signs, a beyond-reach flag (such elements keep their
+// loaded values) and the colour of the source cell).
+__device__ __forceinline__ void tile_map_build(const View &L, const Tile &T, int *map)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        const TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        const int ic = q.c % L.pitch, jc = q.c / L.pitch;
+        int fl = (q.su + 1) | ((q.sv + 1) << 2) | (((ic + jc) & 1) << 5);
+        if (i > L.m1 + 1 || j > L.m2 + 1) fl |= 16;
+        map[4 * e] = q.c;
+        map[4 * e + 1] = q.u;
+        map[4 * e + 2] = q.v;
+        map[4 * e + 3] = fl;
+    }
+}
+// the refresh after a half-sweep of the given colour: all face velocities
+// (the new buffer), and c, mubar, pbar, rho(c) of the elements whose source
+// cell has that colour (the others did not change); the values equal what
+// tile_refresh reads
+__device__ __forceinline__ void tile_refresh_map(const Phys &P, const View &L, const Tile &T, const int *map,
+                                                 int colour)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int fl = map[4 * e + 3];
+        if (fl & 16) continue;
+        double *s = T.s + e;
+        s[T_U * n] = signed_val((fl & 3) - 1, L.u[map[4 * e + 1]]);
+        s[T_V * n] = signed_val(((fl >> 2) & 3) - 1, L.v[map[4 * e + 2]]);
+        if (((fl >> 5) & 1) != colour) continue;
+        const int q = map[4 * e];
+        const double c = L.c[q];
+        s[T_C * n] = c;
+        s[T_MU * n] = L.mu[q];
+        s[T_P * n] = L.p[q];
+        s[T_RS * n] = rho_of(P, c);
+    }
+}
+
 // --------------------------------------------------------------------------
 // Lane pairs.  Each cell (or box) is handled by two adjacent lanes: lane 0
 // takes every x-direction contribution, lane 1 the same code on transposed

@@ -179,10 +179,11 @@ __global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a
     for (size_t q = (size_t)blockIdx.x * BLK + threadIdx.x; q < n; q += (size_t)gridDim.x * BLK) b[q] = a[q];
 }
 
-// LDS doubles of the coarsest-level solve: 15 level arrays + one tile
+// LDS doubles of the coarsest-level solve: 15 level arrays + one tile + the
+// tile's source map (4 ints per element)
 __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
 {
-    return (size_t)15 * m1 * m2 + (size_t)T_NF * (m1 + 3) * (m2 + 3);
+    return (size_t)15 * m1 * m2 + (size_t)(T_NF + 2) * (m1 + 3) * (m2 + 3);
 }
 
 // all sweeps of a level in one workgroup per item, with the whole level
@@ -218,6 +219,8 @@ template <typename IT> __global__ __launch_bounds__(512) void k_coarse_solve(IT 
     const Rhs FH = { hf, hf + n, hf + 2 * n, hf + 3 * n, hf + 4 * n };
     Tile T;
     T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    int *map = (int *)(T.s + (size_t)T_NF * T.W * T.H);
+    tile_map_build(H, T, map);
     const int half = m1 >> 1;
     for (int s = 0; s < 2 * sweeps; s++) {
         const int colour = s & 1;
@@ -225,7 +228,7 @@ template <typename IT> __global__ __launch_bounds__(512) void k_coarse_solve(IT 
         if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
         else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
         if (s == 0) tile_load(d.P, H, T);
-        else tile_refresh(d.P, H, T);
+        else tile_refresh_map(d.P, H, T, map, colour ^ 1);
         __syncthreads();
         for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
             const int pr = t >> 1;
