@@ -64,6 +64,14 @@ SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f)
            for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp", "qnsch_lib.hip")]
 
 
+# depth of the acceleration of the cycle iteration for every leg (--accel)
+ACCEL = 2
+
+
+def base_opts(tol):
+    return dict(W.default_opts(tol), accel=ACCEL)
+
+
 def source_hash():
     h = hashlib.sha256()
     for f in SOURCES:
@@ -177,7 +185,7 @@ def run_mixed(steps, tol):
     res = {}
     for name, prec in (("fp64", Q.FP64), ("mixed", Q.MIXED)):
         note("mixed-precision comparison:", cfg["name"], name, steps, "steps")
-        g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(tol), precision=prec))
+        g = Q.Solver(cfg["grid"], cfg["params"], dict(base_opts(tol), precision=prec))
         g.set_state(cfg["state"]["c"])
         g.step(cfg["dt"])  # warm-up
         g.set_state(cfg["state"]["c"])
@@ -213,7 +221,7 @@ def run_projection(steps, warmup, tol, primitive_value):
     cfg = W.rising_drop()
     cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
     note("projection scheme:", cfg["name"], steps, "steps")
-    g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(tol), scheme=Q.PROJECTION))
+    g = Q.Solver(cfg["grid"], cfg["params"], dict(base_opts(tol), scheme=Q.PROJECTION))
     g.set_state(cfg["state"]["c"])
     for _ in range(warmup):
         g.step(cfg["dt"])
@@ -243,8 +251,8 @@ def run_served(n, nsteps, tol, seq_steps, lanes):
     """the request stream through the server (mixed precision), and the same
     requests one after another alone (FP64 and mixed) on a sample of steps"""
     reqs = W.serving_requests(n=n, nsteps=nsteps)
-    mixed = dict(W.default_opts(tol), precision=Q.MIXED)
-    fp64 = W.default_opts(tol)
+    mixed = dict(base_opts(tol), precision=Q.MIXED)
+    fp64 = base_opts(tol)
     # sequential baselines: every request alone, seq_steps steps each
     seq = {"fp64": float("nan"), "mixed": float("nan")}
     for name, opts in (("fp64", fp64), ("mixed", mixed)) if seq_steps else ():
@@ -310,8 +318,8 @@ def run_served_at_scale(nbig, big, nsteps, tol, lanes, max_vcycles):
     server in mixed precision; the plain-FP64 sequential baseline is each kind
     of request alone (one big box for 2 steps, one background box for 5)"""
     bigs, bg = W.serving_at_scale(nbig=nbig, big=big, nsteps=nsteps)
-    mixed = dict(W.default_opts(tol), precision=Q.MIXED, max_vcycles=max_vcycles)
-    fp64 = dict(W.default_opts(tol), max_vcycles=max_vcycles)
+    mixed = dict(base_opts(tol), precision=Q.MIXED, max_vcycles=max_vcycles)
+    fp64 = dict(base_opts(tol), max_vcycles=max_vcycles)
     seq = {}
     for name, r, k in (("big", bigs[0], 2), ("background", next(W.serving_at_scale(1, 64, nsteps)[1]), 5)):
         note("serving at scale: sequential FP64 baseline,", name)
@@ -376,6 +384,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--accel", type=int, default=2, help="acceleration depth of the cycle iteration (0 = plain cycles)")
     ap.add_argument("--mixed-steps", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=50)
@@ -393,11 +402,13 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the time step of one simulation is a single-GPU "
-              "kernel pipeline here (multi-GPU sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "kernel pipeline here (how it would shard over several GPUs is documented, not built)", file=sys.stderr)
         sys.exit(2)
 
     cfg = W.rising_drop()
-    opts = W.default_opts(args.tol)
+    global ACCEL
+    ACCEL = args.accel
+    opts = base_opts(args.tol)
     g = Q.Solver(cfg["grid"], cfg["params"], dict(opts, precision=Q.FP64))
     cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
     copy_gbs, _ = Q.copy_probe(64 << 20, 10)  # 512 MiB copy: calibration and sanity figure
@@ -419,7 +430,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["grid"]["m1"], cfg["grid"]["m2"]], "levels": g.levels,
-                   "dt": cfg["dt"], "tol": args.tol, "precision": "fp64", "cycle": "V(2,2)",
+                   "dt": cfg["dt"], "tol": args.tol, "precision": "fp64", "cycle": "V(2,2)", "accel": ACCEL,
                    "parallelism": "none"},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "vcycles_per_step": float(np.mean(nv)),

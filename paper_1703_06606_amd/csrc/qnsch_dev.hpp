@@ -309,7 +309,7 @@ __device__ __forceinline__ void tile_refresh(const Phys &P, const View &L, const
 // element: the cell, u and v source indices as tile_src gives them, and a
 // word with the u and v signs, a beyond-reach flag (such elements keep their
 // loaded values) and the colour of the source cell).
-__device__ __forceinline__ void tile_map_build(const View &L, const Tile &T, int *map)
+template <typename V, typename TT> __device__ __forceinline__ void tile_map_build(const V &L, const TT &T, int *map)
 {
     const int n = T.W * T.H;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {

@@ -152,7 +152,7 @@ struct qnsch_ctx {
     int acc_dots = 0;     // earlier results the latest one's reduction paired it with
     int acc_use = 0;      // earlier results the pending combination uses (0: none pending)
     bool acc_wait = false;  // a recording reduction is in flight
-    int acc_cycles = 0;     // cycles of the step so far (phase calls)
+    bool acc_first = true;  // the next cycle is the first of its step (not recorded)
     double acc_g[3] = { 0.0, 0.0, 0.0 };
     double acc_last = 0.0;  // largest residual norm of the latest result
 };
@@ -173,13 +173,15 @@ static int small_level(const qnsch_ctx *x)
     }
     return small;
 }
-// one cycle; with acceleration the results from the second cycle of a step
-// on are recorded (the first one's residual direction is dominated by the
-// change of the time-n data; leaving it out costs no cycle on the droplet,
-// Rayleigh-Taylor and drop-box workloads and saves its recording)
-static void cycle_program(const qnsch_ctx *x, bool first, std::vector<Op> &out)
+// one cycle; with acceleration its residual reduction records the result,
+// from the second cycle of a step on (acc_record_launch skips the first: its
+// residual direction is dominated by the change of the time-n data; leaving
+// it out costs no cycle on the droplet, Rayleigh-Taylor and drop-box
+// workloads and saves its recording).  Every cycle has the same operations,
+// so served requests at different cycles of their steps share launches.
+static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
 {
-    const bool rec = x->opt.accel > 0 && !first;
+    const bool rec = x->opt.accel > 0;
     if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), rec, out);
     else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), rec, out);
 }
@@ -318,6 +320,12 @@ static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stampe
 // next ring slot, paired with up to m earlier results of the history
 static void acc_record_launch(qnsch_ctx *x, short &acc)
 {
+    if (x->acc_first) {
+        x->acc_first = false;
+        acc = -1;
+        x->acc_use = 0;
+        return;
+    }
     const int m = x->opt.accel, R = m + 1;
     x->acc_pos = (x->acc_pos + 1) % R;
     x->acc_dots = std::min(x->acc_cnt, m);
@@ -386,7 +394,7 @@ static void acc_reset(qnsch_ctx *x)
     x->acc_use = 0;
     x->acc_wait = false;
     x->acc_last = 0.0;
-    x->acc_cycles = 0;
+    x->acc_first = true;
 }
 
 // a work list of one item in its compact form
@@ -993,8 +1001,7 @@ int qnsch_vcycle(qnsch_ctx *x)
     if (!x->in_step) { x->err = "vcycle outside a step"; return QNSCH_EBUSY; }
     std::vector<Op> prog;
     x->acc_use = 0; // a combination not applied by qnsch_accelerate is dropped
-    cycle_program(x, x->acc_cycles == 0, prog);
-    x->acc_cycles++;
+    cycle_program(x, prog);
     int rc;
     if ((rc = run_ops(x, prog))) return rc;
     if ((rc = read_red(x))) return rc;
@@ -1124,10 +1131,9 @@ int qnsch_step(qnsch_ctx *x, double dt)
     auto t0 = std::chrono::steady_clock::now();
     int rc;
     if ((rc = set_dt(x, dt))) return rc;
-    std::vector<Op> begin, cyc1, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
+    std::vector<Op> begin, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
     step_begin_program(x, begin);
-    cycle_program(x, true, cyc1);
-    cycle_program(x, false, cyc);
+    cycle_program(x, cyc);
     cyc_acc.insert(cyc_acc.end(), cyc.begin(), cyc.end());
     acc_reset(x);
     if ((rc = run_ops(x, begin))) return rc;
@@ -1147,7 +1153,7 @@ int qnsch_step(qnsch_ctx *x, double dt)
             return j;
         }
         if (j == 1) break;
-        if ((rc = run_ops(x, it == 0 ? cyc1 : (x->acc_use > 0 ? cyc_acc : cyc)))) return rc;
+        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return rc;
         if ((rc = read_red(x))) return rc;
         if (x->acc_wait) acc_after(x);
         it++;
@@ -1571,7 +1577,7 @@ static void after_reduction(qnsch_server *S, Req *r)
         r->prog.push_back({ OP_STEPEND, 0, 0 });
     } else {
         if (x->acc_use > 0) r->prog.push_back({ OP_ACCEL, 0, 0 });
-        cycle_program(x, r->vcycles == 0, r->prog);
+        cycle_program(x, r->prog);
         r->vcycles++;
     }
 }

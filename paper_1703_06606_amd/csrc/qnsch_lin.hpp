@@ -194,6 +194,30 @@ __device__ __forceinline__ void ltile_refresh(const PhysF &P, const LView &L, co
     }
 }
 
+// the same after a half-sweep of the given colour with the sources computed
+// once (tile_map_build): all face corrections, and the cell corrections and
+// the density change of the elements whose source cell has that colour
+__device__ __forceinline__ void ltile_refresh_map(const PhysF &P, const LView &L, const TileF &T, const int *map,
+                                                  int colour)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int fl = map[4 * e + 3];
+        if (fl & 16) continue;
+        float *s = T.s + e;
+        s[L_U * n] = signed_val((fl & 3) - 1, L.du[map[4 * e + 1]]);
+        s[L_V * n] = signed_val(((fl >> 2) & 3) - 1, L.dv[map[4 * e + 2]]);
+        if (((fl >> 5) & 1) != colour) continue;
+        const int q = map[4 * e];
+        const float dc = L.dc[q];
+        const float rs = s[L_RS * n];
+        s[L_DC * n] = dc;
+        s[L_MU * n] = L.dmu[q];
+        s[L_P * n] = L.dp[q];
+        s[L_DRS * n] = -P.alpha * rs * rs * dc;
+    }
+}
+
 // one axis of the linearised cell equations at element e: the linear terms
 // applied to the corrections, the linearised gradient-energy and
 // capillary-divergence terms (dG, dL), and the values at c^ that the local

@@ -151,9 +151,10 @@ template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_prolong(IT it
 }
 
 // LDS floats of the coarsest-level correction solve: 19 level arrays + a tile
+// + the tile's source map (4 ints per element)
 __host__ __device__ inline size_t mx_coarse_lds_floats(int m1, int m2)
 {
-    return (size_t)19 * m1 * m2 + (size_t)L_NF * (m1 + 3) * (m2 + 3);
+    return (size_t)19 * m1 * m2 + (size_t)(L_NF + 4) * (m1 + 3) * (m2 + 3);
 }
 
 // all correction sweeps of a level in one workgroup per item, the level
@@ -188,6 +189,8 @@ template <typename IT> __global__ __launch_bounds__(512) void k_mx_coarse_solve(
     H.pitch = m1;
     TileF T;
     T.s = smf + 19 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    int *map = (int *)(T.s + (size_t)L_NF * T.W * T.H);
+    tile_map_build(H, T, map);
     const int half = m1 >> 1;
     for (int s = 0; s < 2 * sweeps; s++) {
         const int colour = s & 1;
@@ -195,7 +198,7 @@ template <typename IT> __global__ __launch_bounds__(512) void k_mx_coarse_solve(
         if (s & 1) { H.du = uB; H.dv = vB; uw = uA; vw = vA; }
         else { H.du = uA; H.dv = vA; uw = uB; vw = vB; }
         if (s == 0) ltile_load(d.Pf, H, T);
-        else ltile_refresh(d.Pf, H, T);
+        else ltile_refresh_map(d.Pf, H, T, map, colour ^ 1);
         __syncthreads();
         for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
             const int pr = t >> 1;
