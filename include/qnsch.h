@@ -123,7 +123,7 @@ typedef struct {
     int32_t precision;   /* QNSCH_FP64 or QNSCH_MIXED (see above) */
     double tol;          /* stop when every per-equation norm sqrt(h^2 sum r^2) <= tol */
     int32_t max_vcycles; /* error QNSCH_ENOCONV beyond this */
-    int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black) */
+    int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black), 0..15 */
     int32_t nu_coarse;   /* sweeps on the coarsest level */
     double vanka_omega;  /* relaxation factor of the box update (1 = exact box solve) */
     int32_t smoother;    /* QNSCH_SMOOTH_COUPLED or QNSCH_SMOOTH_SEGREGATED */

@@ -179,6 +179,48 @@ __global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a
     for (size_t q = (size_t)blockIdx.x * BLK + threadIdx.x; q < n; q += (size_t)gridDim.x * BLK) b[q] = a[q];
 }
 
+// P(w_H - R w_h) at fine cell (i, j) of level d: cells piecewise constant;
+// faces copy the coincident coarse face and average the two coarse faces
+// across the coarse cell; hu/hv false for a face on a wall (no unknown)
+struct PCorr {
+    double c, mu, p, u, v;
+    bool hu, hv;
+};
+__device__ __forceinline__ PCorr prolong_corr(const Desc &d, const Desc &C, int cpar, int i, int j)
+{
+    PCorr r;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I;
+    const double *Cu = C.ub[cpar], *Cv = C.vb[cpar];
+    r.c = C.c[kc] - C.c0[kc];
+    r.mu = C.mu[kc] - C.mu0[kc];
+    r.p = C.p[kc] - C.p0[kc];
+    r.hu = d.bcx || i >= 1;
+    r.hv = d.bcy || j >= 1;
+    r.u = r.v = 0.0;
+    if (r.hu) {
+        double du = Cu[kc] - C.u0[kc];
+        if (i & 1) {
+            double e = 0.0;
+            if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
+            else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
+            du = 0.5 * (du + e);
+        }
+        r.u = du;
+    }
+    if (r.hv) {
+        double dv = Cv[kc] - C.v0[kc];
+        if (j & 1) {
+            double e = 0.0;
+            if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
+            else if (d.bcy) e = Cv[I] - C.v0[I];
+            dv = 0.5 * (dv + e);
+        }
+        r.v = dv;
+    }
+    return r;
+}
+
 // LDS doubles of the coarsest-level solve: 15 level arrays + one tile + the
 // tile's source map (4 ints per element)
 __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
@@ -190,8 +232,11 @@ __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
 // resident in LDS: the solve of the coarsest level, and the pre- and
 // post-smoothing of coarse levels small enough (the same arithmetic as the
 // half-sweep launches); the u/v buffers alternate, the number of half-sweeps
-// is even, so the result stays in buffer par
-template <typename IT> __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double omega, double pomega)
+// is even, so the result stays in buffer par.  With prolong set the level
+// first takes the coarse-grid correction (k_prolong's arithmetic) as it is
+// loaded.
+template <typename IT>
+__global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double omega, double pomega, int prolong)
 {
     extern __shared__ double sm[];
     const int k = find_item(it);
@@ -206,6 +251,12 @@ template <typename IT> __global__ __launch_bounds__(512) void k_coarse_solve(IT 
         const int j = e / m1, i = e - j * m1;
         const size_t q = (size_t)j * L.pitch + i;
         hc[e] = L.c[q]; hmu[e] = L.mu[q]; hp[e] = L.p[q]; uA[e] = ua[q]; vA[e] = va[q];
+        if (prolong) {
+            const PCorr r = prolong_corr(d, *d.coarse, it.cpar[k], i, j);
+            hc[e] += r.c; hmu[e] += r.mu; hp[e] += r.p;
+            if (r.hu) uA[e] += r.u;
+            if (r.hv) vA[e] += r.v;
+        }
         hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
         hf[e] = d.fc ? d.fc[q] : 0.0;
         hf[n + e] = d.fmu ? d.fmu[q] : 0.0;
@@ -339,9 +390,7 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_coarse_rhs(IT i
     }
 }
 
-// w_h += P(w_H - R w_h) on the level the item names: cells piecewise
-// constant; faces copy the coincident coarse face and average the two coarse
-// faces across the coarse cell.  One thread per fine cell.
+// w_h += P(w_H - R w_h) on the level the item names, one thread per fine cell
 template <typename IT> __global__ __launch_bounds__(BLK) void k_prolong(IT it)
 {
     const int k = find_item(it);
@@ -350,33 +399,13 @@ template <typename IT> __global__ __launch_bounds__(BLK) void k_prolong(IT it)
     const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
     if (t >= d.m1 * d.m2) return;
     const int j = t / d.m1, i = t - j * d.m1;
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I, kf = (size_t)j * d.pitch + i;
-    const double *Cu = C.ub[it.cpar[k]], *Cv = C.vb[it.cpar[k]];
-    double *uf = d.ub[it.par[k]], *vf = d.vb[it.par[k]];
-    d.c[kf] += C.c[kc] - C.c0[kc];
-    d.mu[kf] += C.mu[kc] - C.mu0[kc];
-    d.p[kf] += C.p[kc] - C.p0[kc];
-    if (d.bcx || i >= 1) {
-        double du = Cu[kc] - C.u0[kc];
-        if (i & 1) {
-            double e = 0.0;
-            if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
-            else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
-            du = 0.5 * (du + e);
-        }
-        uf[kf] += du;
-    }
-    if (d.bcy || j >= 1) {
-        double dv = Cv[kc] - C.v0[kc];
-        if (j & 1) {
-            double e = 0.0;
-            if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
-            else if (d.bcy) e = Cv[I] - C.v0[I];
-            dv = 0.5 * (dv + e);
-        }
-        vf[kf] += dv;
-    }
+    const size_t kf = (size_t)j * d.pitch + i;
+    const PCorr r = prolong_corr(d, C, it.cpar[k], i, j);
+    d.c[kf] += r.c;
+    d.mu[kf] += r.mu;
+    d.p[kf] += r.p;
+    if (r.hu) d.ub[it.par[k]][kf] += r.u;
+    if (r.hv) d.vb[it.par[k]][kf] += r.v;
 }
 
 // wave64 + LDS block sum of NRED values (blocks of up to 16 waves)

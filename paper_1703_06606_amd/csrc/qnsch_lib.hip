@@ -60,6 +60,19 @@ static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, std:
         out.push_back({ hs_kind, l, 1 });
     }
 }
+// prolongation onto level l, then its post-smoothing; a level-resident
+// smoothing takes the correction as it loads the level (colour field
+// nu + PROLONG_FIRST), which saves the prolongation launch
+#define PROLONG_FIRST 16
+static void prolong_smooth_ops(int l, int nu, int small, int pr_kind, int hs_kind, int lds_kind, std::vector<Op> &out)
+{
+    if (nu > 0 && nu < PROLONG_FIRST && l > 0 && l >= small) {
+        out.push_back({ lds_kind, l, nu + PROLONG_FIRST });
+        return;
+    }
+    out.push_back({ pr_kind, l, 0 });
+    smooth_ops(l, nu, small, hs_kind, lds_kind, out);
+}
 
 // one V-cycle of a hierarchy of L levels, ending with the residual norms and
 // the pbar mean removal
@@ -71,10 +84,7 @@ static void vcycle_program(int L, int nu1, int nu2, int small, bool acc, std::ve
         out.push_back({ OP_CRHS, l + 1, 0 });
     }
     out.push_back({ OP_COARSE, L - 1, 0 });
-    for (int l = L - 2; l >= 0; l--) {
-        out.push_back({ OP_PROLONG, l, 0 });
-        smooth_ops(l, nu2, small, OP_HS, OP_SMOOTH, out);
-    }
+    for (int l = L - 2; l >= 0; l--) prolong_smooth_ops(l, nu2, small, OP_PROLONG, OP_HS, OP_SMOOTH, out);
     out.push_back({ acc ? OP_NORMACC : OP_NORM, 0, 0 });
 }
 // one outer iteration of the mixed-precision step: an FP32 correction
@@ -87,10 +97,7 @@ static void mixed_program(int L, int nu1, int nu2, int small, bool acc, std::vec
         out.push_back({ OP_MXRESTRICT, l, 0 });
     }
     out.push_back({ OP_MXCOARSE, L - 1, 0 });
-    for (int l = L - 2; l >= 0; l--) {
-        out.push_back({ OP_MXPROLONG, l, 0 });
-        smooth_ops(l, nu2, small, OP_MXHS, OP_MXSMOOTH, out);
-    }
+    for (int l = L - 2; l >= 0; l--) prolong_smooth_ops(l, nu2, small, OP_MXPROLONG, OP_MXHS, OP_MXSMOOTH, out);
     out.push_back({ OP_MXUPDATE, 0, 0 });
     out.push_back({ acc ? OP_NORMACC : OP_NORM, 0, 0 });
 }
@@ -477,10 +484,11 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             // the coarsest level over-relaxes the velocity and pressure
             // updates (the primitive box, the projection pressure step)
             const bool coarsest = kind == OP_COARSE, pj = x0->opt.scheme == QNSCH_PROJECTION;
-            const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
+            const int sweeps = coarsest ? x0->opt.nu_coarse : colour % PROLONG_FIRST;
+            const int prolong = coarsest ? 0 : colour / PROLONG_FIRST;
             const double om = coarsest && !pj ? x0->opt.coarse_omega : omega;
             const double pom = coarsest && pj ? x0->opt.coarse_omega : 1.0;
-            KLAUNCH(k_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, om, pom);
+            KLAUNCH(k_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, om, pom, prolong);
             break;
         }
         case OP_PROLONG: KLAUNCH(k_prolong, W, dim3(W.blocks), dim3(BLK), 0, s); break;
@@ -491,9 +499,10 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             for (auto &pe : part) nmax = std::max(nmax, pe.first->L[pe.second].m1 * pe.first->L[pe.second].m2 / 2);
             const unsigned th = (unsigned)(2 * nmax < 512 ? ((2 * nmax + 63) / 64) * 64 : 512);
             const bool coarsest = kind == OP_MXCOARSE;
-            const int sweeps = coarsest ? x0->opt.nu_coarse : colour;
+            const int sweeps = coarsest ? x0->opt.nu_coarse : colour % PROLONG_FIRST;
+            const int prolong = coarsest ? 0 : colour / PROLONG_FIRST;
             const double om = coarsest ? x0->opt.coarse_omega : omega;
-            KLAUNCH(k_mx_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, (float)om);
+            KLAUNCH(k_mx_coarse_solve, W, dim3(W.blocks), dim3(th), W.lds, s, sweeps, (float)om, prolong);
             break;
         }
         case OP_MXPROLONG: KLAUNCH(k_mx_prolong, W, dim3(W.blocks), dim3(BLK), 0, s); break;
@@ -779,7 +788,8 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
     if (!(p->rho1 > 0) || !(p->rho2 > 0) || !(p->visc1 > 0) || !(p->visc2 > 0) || !(p->Re > 0) || !(p->We > 0)
         || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
         return QNSCH_EINVAL;
-    if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu_coarse < 1 || o->max_vcycles < 0
+    if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu1 >= PROLONG_FIRST || o->nu2 >= PROLONG_FIRST || o->nu_coarse < 1
+              || o->max_vcycles < 0
               || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)
               || (o->smoother != QNSCH_SMOOTH_SEGREGATED && o->smoother != QNSCH_SMOOTH_COUPLED)
               || (o->scheme != QNSCH_PRIMITIVE && o->scheme != QNSCH_PROJECTION)

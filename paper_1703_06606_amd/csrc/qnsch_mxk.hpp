@@ -111,8 +111,48 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_restrict(IT 
     }
 }
 
-// delta_h += P delta_H: cells piecewise constant; faces copy the coincident
-// coarse face and average the two coarse faces across the coarse cell
+// P delta_H at fine cell (i, j) of level d (the FP32 correction; cells
+// piecewise constant, faces as in prolong_corr); hu/hv false on walls
+struct PCorrF {
+    float c, mu, p, u, v;
+    bool hu, hv;
+};
+__device__ __forceinline__ PCorrF mx_prolong_corr(const Desc &d, const Desc &C, int cpar, int i, int j)
+{
+    PCorrF r;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I;
+    const float *Cu = C.dub[cpar], *Cv = C.dvb[cpar];
+    r.c = C.dc[kc];
+    r.mu = C.dmu[kc];
+    r.p = C.dp[kc];
+    r.hu = d.bcx || i >= 1;
+    r.hv = d.bcy || j >= 1;
+    r.u = r.v = 0.0f;
+    if (r.hu) {
+        float du = Cu[kc];
+        if (i & 1) {
+            float e = 0.0f;
+            if (I + 1 < C.m1) e = Cu[kc + 1];
+            else if (d.bcx) e = Cu[(size_t)J * C.pitch];
+            du = 0.5f * (du + e);
+        }
+        r.u = du;
+    }
+    if (r.hv) {
+        float dv = Cv[kc];
+        if (j & 1) {
+            float e = 0.0f;
+            if (J + 1 < C.m2) e = Cv[kc + C.pitch];
+            else if (d.bcy) e = Cv[I];
+            dv = 0.5f * (dv + e);
+        }
+        r.v = dv;
+    }
+    return r;
+}
+
+// delta_h += P delta_H, one thread per fine cell
 template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_prolong(IT it)
 {
     const int k = find_item(it);
@@ -121,33 +161,13 @@ template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_prolong(IT it
     const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
     if (t >= d.m1 * d.m2) return;
     const int j = t / d.m1, i = t - j * d.m1;
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I, kf = (size_t)j * d.pitch + i;
-    const float *Cu = C.dub[it.cpar[k]], *Cv = C.dvb[it.cpar[k]];
-    float *uf = d.dub[it.par[k]], *vf = d.dvb[it.par[k]];
-    d.dc[kf] += C.dc[kc];
-    d.dmu[kf] += C.dmu[kc];
-    d.dp[kf] += C.dp[kc];
-    if (d.bcx || i >= 1) {
-        float du = Cu[kc];
-        if (i & 1) {
-            float e = 0.0f;
-            if (I + 1 < C.m1) e = Cu[kc + 1];
-            else if (d.bcx) e = Cu[(size_t)J * C.pitch];
-            du = 0.5f * (du + e);
-        }
-        uf[kf] += du;
-    }
-    if (d.bcy || j >= 1) {
-        float dv = Cv[kc];
-        if (j & 1) {
-            float e = 0.0f;
-            if (J + 1 < C.m2) e = Cv[kc + C.pitch];
-            else if (d.bcy) e = Cv[I];
-            dv = 0.5f * (dv + e);
-        }
-        vf[kf] += dv;
-    }
+    const size_t kf = (size_t)j * d.pitch + i;
+    const PCorrF r = mx_prolong_corr(d, C, it.cpar[k], i, j);
+    d.dc[kf] += r.c;
+    d.dmu[kf] += r.mu;
+    d.dp[kf] += r.p;
+    if (r.hu) d.dub[it.par[k]][kf] += r.u;
+    if (r.hv) d.dvb[it.par[k]][kf] += r.v;
 }
 
 // LDS floats of the coarsest-level correction solve: 19 level arrays + a tile
@@ -160,7 +180,8 @@ __host__ __device__ inline size_t mx_coarse_lds_floats(int m1, int m2)
 // all correction sweeps of a level in one workgroup per item, the level
 // resident in LDS (the coarsest level, and the smoothing of small coarse
 // levels); an even number of half-sweeps keeps the result in buffer par
-template <typename IT> __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, float omega)
+template <typename IT>
+__global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, float omega, int prolong)
 {
     extern __shared__ float smf[];
     const int k = find_item(it);
@@ -177,6 +198,12 @@ template <typename IT> __global__ __launch_bounds__(512) void k_mx_coarse_solve(
         const size_t q = (size_t)j * L.pitch + i;
         hxc[e] = L.c[q]; hxmu[e] = L.mu[q]; hxu[e] = L.u[q]; hxv[e] = L.v[q];
         hdc[e] = L.dc[q]; hdmu[e] = L.dmu[q]; hdp[e] = L.dp[q]; uA[e] = ua[q]; vA[e] = va[q];
+        if (prolong) {
+            const PCorrF r = mx_prolong_corr(d, *d.coarse, it.cpar[k], i, j);
+            hdc[e] += r.c; hdmu[e] += r.mu; hdp[e] += r.p;
+            if (r.hu) uA[e] += r.u;
+            if (r.hv) vA[e] += r.v;
+        }
         hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
         hr[e] = L.rc[q]; hr[n + e] = L.rmu[q]; hr[2 * n + e] = L.rp[q]; hr[3 * n + e] = L.ru[q];
         hr[4 * n + e] = L.rv[q];
