@@ -171,7 +171,8 @@ void qnsch_default_opts(qnsch_opts *opts);
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
  * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
  * device memory in one allocation (qnsch_footprint: roughly 150 bytes per
- * finest cell in FP64, 182 in mixed precision).  Returns
+ * finest cell in FP64, 182 in mixed precision, plus 80 (accel + 1) for the
+ * acceleration's history).  Returns
  * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
 int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
                  void *hip_stream, qnsch_ctx **out);
