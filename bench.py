@@ -60,8 +60,10 @@ VALU_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512
 # every 4 cycles at 2.4 GHz; FP64 vector peak 78.6 TFLOP/s
 VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
 FP64_PEAK_TFLOPS = 78.6
+# the device code (kernels and the functions they inline); the host library
+# around it does not change what a kernel reads and writes
 SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f)
-           for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp", "qnsch_lib.hip")]
+           for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp")]
 
 
 # depth of the acceleration of the cycle iteration for every leg (--accel)

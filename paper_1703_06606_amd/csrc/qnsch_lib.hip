@@ -1115,7 +1115,7 @@ int qnsch_end_step(qnsch_ctx *x)
 }
 
 // decision after a residual reduction: 1 converged, 0 continue, <0 error
-static int judge(qnsch_ctx *x, int vcycles)
+static int stop_test(qnsch_ctx *x, int vcycles)
 {
     double mx = 0.0;
     bool finite = true;
@@ -1153,7 +1153,7 @@ int qnsch_step(qnsch_ctx *x, double dt)
     int it = 0;
     x->st.vcycles = 0;
     for (;;) {
-        const int j = judge(x, it);
+        const int j = stop_test(x, it);
         if (j < 0) {
             const std::string msg = x->err;
             run_ops(x, { { OP_RESTORE, 0, 0 } });
@@ -1577,7 +1577,7 @@ static void after_reduction(qnsch_server *S, Req *r)
     }
     r->wait = W_NONE;
     if (x->acc_wait) acc_after(x);
-    const int j = judge(x, r->vcycles);
+    const int j = stop_test(x, r->vcycles);
     r->prog.clear();
     r->pc = 0;
     if (j < 0) {
