@@ -303,6 +303,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
 template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
+    __shared__ double part[(TX / 2) * (TY / 2)][2][8];
     const int k = find_item(it);
     const Desc &d = *it.d[k];
     if (!tile_valid(it, k, d)) return;
@@ -311,41 +312,51 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
     const Tile T = item_tile(sm, it, k, d);
     tile_load(d.P, Lf, T);
     __syncthreads();
+    // lane pair pr: coarse cell cc of the tile, fine row b of it (both
+    // halves of the workgroup busy); the b = 1 pairs hand their sums to the
+    // b = 0 pairs through LDS
     const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
-    if (pr >= (TX / 2) * (TY / 2)) return;
-    const int I = T.i0 / 2 + pr % (TX / 2), J = T.j0 / 2 + pr / (TX / 2);
-    if (I >= C.m1 || J >= C.m2) return;
-    double rc = 0, rm = 0, rp = 0, rf = 0, sc = 0, smu = 0, sp = 0, sf = 0;
-    const int fN = hlf ? T_V : T_U;
-    const Rhs F = rhs_of(d);
-    // not unrolled: four inlined residual evaluations would need 256 VGPRs
-#pragma unroll 1
-    for (int b = 0; b < 2; b++)
-#pragma unroll 1
+    const int NC = (TX / 2) * (TY / 2);
+    const int cc = pr % NC, b = pr / NC;
+    const int I = T.i0 / 2 + cc % (TX / 2), J = T.j0 / 2 + cc / (TX / 2);
+    const bool on = b < 2 && I < C.m1 && J < C.m2;
+    double v[8] = { 0, 0, 0, 0, 0, 0, 0, 0 }; // rc, rm, rp, rf, sc, smu, sp, sf
+    if (on) {
+        const int fN = hlf ? T_V : T_U;
+        const Rhs F = rhs_of(d);
+#pragma unroll
         for (int a = 0; a < 2; a++) {
             const int i = 2 * I + a, j = 2 * J + b;
             double xc, xm, xp, xf;
             resid_pair(d.P, Lf, T, F, i, j, hlf, xc, xm, xp, xf);
-            rc += xc; rm += xm; rp += xp;
+            v[0] += xc; v[1] += xm; v[2] += xp;
             // the lane's faces of the coarse cell: west faces (a = 0) on the
             // x lane, south faces (b = 0) on the y lane
-            if ((hlf ? b : a) == 0) { rf += xf; sf += T.q(fN, i, j); }
-            sc += T.q(T_C, i, j); smu += T.q(T_MU, i, j); sp += T.q(T_P, i, j);
+            if ((hlf ? b : a) == 0) { v[3] += xf; v[7] += T.q(fN, i, j); }
+            v[4] += T.q(T_C, i, j); v[5] += T.q(T_MU, i, j); v[6] += T.q(T_P, i, j);
         }
+        if (b == 1)
+#pragma unroll
+            for (int q = 0; q < 8; q++) part[cc][hlf][q] = v[q];
+    }
+    __syncthreads();
+    if (!on || b != 0) return;
+#pragma unroll
+    for (int q = 0; q < 8; q++) v[q] += part[cc][hlf][q];
     const size_t q = (size_t)J * C.pitch + I;
     const int cp = it.cpar[k];
     if (hlf == 0) {
-        C.c[q] = C.c0[q] = 0.25 * sc;
-        C.mu[q] = C.mu0[q] = 0.25 * smu;
-        C.p[q] = C.p0[q] = 0.25 * sp;
-        C.fc[q] = 0.25 * rc;
-        C.fmu[q] = 0.25 * rm;
-        C.fp[q] = 0.25 * rp;
-        C.ub[cp][q] = C.u0[q] = 0.5 * sf;
-        C.fu[q] = 0.5 * rf;
+        C.c[q] = C.c0[q] = 0.25 * v[4];
+        C.mu[q] = C.mu0[q] = 0.25 * v[5];
+        C.p[q] = C.p0[q] = 0.25 * v[6];
+        C.fc[q] = 0.25 * v[0];
+        C.fmu[q] = 0.25 * v[1];
+        C.fp[q] = 0.25 * v[2];
+        C.ub[cp][q] = C.u0[q] = 0.5 * v[7];
+        C.fu[q] = 0.5 * v[3];
     } else {
-        C.vb[cp][q] = C.v0[q] = 0.5 * sf;
-        C.fv[q] = 0.5 * rf;
+        C.vb[cp][q] = C.v0[q] = 0.5 * v[7];
+        C.fv[q] = 0.5 * v[3];
     }
 }
 
