@@ -385,8 +385,10 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_coarse_rhs(IT i
     int i, j;
     pair_cells(T, i, j);
     const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
+    // the pair's two cells are both inside or both outside (even m1)
+    if (i >= C.m1 || j >= C.m2) return;
+#pragma unroll
     for (int a = 0; a < 2; a++, i++) {
-        if (i >= C.m1 || j >= C.m2) continue;
         double rc, rm, rp, rf;
         resid_pair(C.P, Lc, T, Z, i, j, hlf, rc, rm, rp, rf); // r = -N_H(R w)
         const size_t q = (size_t)j * C.pitch + i;
