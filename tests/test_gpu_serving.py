@@ -94,6 +94,32 @@ def test_served_results_equal_alone(lanes):
     assert s["contexts_created"] < len(cases)  # the second round reuses contexts
 
 
+def test_plain_and_accelerated_requests_share_a_server():
+    """Requests with plain cycles (as the served benchmark submits them) and
+    with the acceleration, FP64 and mixed, in one server: each result
+    bit-identical to the request run alone with its own options"""
+    say("serving: plain and accelerated requests")
+    base = W.default_opts(1e-10)
+    cases, opts = [], []
+    for k, c in enumerate(mix()[:3]):
+        for accel in (0, 2):
+            cases.append(c)
+            opts.append(dict(base, accel=accel, precision=Q.MIXED if k % 2 else Q.FP64))
+    nsteps = 2
+    ref = [alone(c, nsteps, o) for c, o in zip(cases, opts)]
+    srv = Q.Server(hbm_budget=8 << 30, max_slots=6, lanes=1)
+    ids = [srv.submit(c["grid"], c["params"], o, c["state"]["c"], nsteps, c["dt"]) for c, o in zip(cases, opts)]
+    for _ in range(100000):
+        if srv.progress(64) == 0:
+            break
+    for rid, (st, ms, en), c, o in zip(ids, ref, cases, opts):
+        r = srv.result(rid)
+        assert r["status"] == Q.OK, (c["name"], o["accel"])
+        for k in FIELDS:
+            assert np.array_equal(r[k], st[k]), (c["name"], o["accel"], k)
+        assert np.array_equal(r["mass"], ms), c["name"]
+
+
 def test_admission_by_budget_and_failure_isolation():
     say("serving: budget and failure")
     opts = W.default_opts(1e-10)
