@@ -401,10 +401,10 @@ def main():
     ap.add_argument("--serve-steps", type=int, default=50)
     ap.add_argument("--serve-lanes", type=int, default=2)
     ap.add_argument("--no-seq", action="store_true", help="skip the sequential baselines of the served run")
-    ap.add_argument("--serve-scale", action="store_true", help="also run the serving-at-scale workload")
+    ap.add_argument("--no-serve-scale", action="store_true", help="skip the serving-at-scale workload")
     ap.add_argument("--scale-boxes", type=int, default=16)
     ap.add_argument("--scale-size", type=int, default=2048)
-    ap.add_argument("--scale-steps", type=int, default=20)
+    ap.add_argument("--scale-steps", type=int, default=3)
     ap.add_argument("--scale-max-vcycles", type=int, default=150)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
@@ -461,7 +461,7 @@ def main():
     if not args.no_serve:
         out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=0 if args.no_seq else 5,
                                    lanes=args.serve_lanes)
-    if args.serve_scale:
+    if not args.no_serve_scale:
         out["served_at_scale"] = run_served_at_scale(args.scale_boxes, args.scale_size, args.scale_steps, args.tol,
                                                      args.serve_lanes, args.scale_max_vcycles)
     if not args.no_cpu_baseline:
