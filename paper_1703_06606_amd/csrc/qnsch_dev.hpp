@@ -284,26 +284,6 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
     }
 }
 
-// reload of the fields a sweep changes (the unknowns and rho(c)) into a tile
-// that tile_load filled before; the time-n fields stay
-__device__ __forceinline__ void tile_refresh(const Phys &P, const View &L, const Tile &T)
-{
-    const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int b = e / T.W, a = e - b * T.W;
-        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
-        if (i > L.m1 + 1 || j > L.m2 + 1) continue;
-        double *s = T.s + e;
-        const double c = ldc(L.c, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[T_C * n] = c;
-        s[T_MU * n] = ldc(L.mu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[T_P * n] = ldc(L.p, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[T_U * n] = ldu(L.u, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[T_V * n] = ldv(L.v, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[T_RS * n] = rho_of(P, c);
-    }
-}
-
 // A level resident in LDS is refreshed into its tile after every half-sweep.
 // Where each element comes from is fixed, so it is computed once (4 ints per
 // element: the cell, u and v source indices as tile_src gives them, and a
@@ -327,8 +307,8 @@ template <typename V, typename TT> __device__ __forceinline__ void tile_map_buil
 }
 // the refresh after a half-sweep of the given colour: all face velocities
 // (the new buffer), and c, mubar, pbar, rho(c) of the elements whose source
-// cell has that colour (the others did not change); the values equal what
-// tile_refresh reads
+// cell has that colour (the others did not change), with the boundary images
+// of ldc, ldu, ldv
 __device__ __forceinline__ void tile_refresh_map(const Phys &P, const View &L, const Tile &T, const int *map,
                                                  int colour)
 {

@@ -172,31 +172,11 @@ __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const
     }
 }
 
-// reload of the corrections (and the density change they induce) into a
-// tile that ltile_load filled before; the linearisation point and time-n
-// fields stay
-__device__ __forceinline__ void ltile_refresh(const PhysF &P, const LView &L, const TileF &T)
-{
-    const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int b = e / T.W, a = e - b * T.W;
-        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
-        if (i > L.m1 + 1 || j > L.m2 + 1) continue;
-        float *s = T.s + e;
-        const float dc = ldc(L.dc, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        const float rs = s[L_RS * n];
-        s[L_DC * n] = dc;
-        s[L_MU * n] = ldc(L.dmu, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[L_P * n] = ldc(L.dp, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[L_U * n] = ldu(L.du, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[L_V * n] = ldv(L.dv, L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
-        s[L_DRS * n] = -P.alpha * rs * rs * dc;
-    }
-}
-
-// the same after a half-sweep of the given colour with the sources computed
-// once (tile_map_build): all face corrections, and the cell corrections and
-// the density change of the elements whose source cell has that colour
+// reload of the corrections into a tile that ltile_load filled before, after
+// a half-sweep of the given colour, with the sources computed once
+// (tile_map_build): all face corrections, and the cell corrections and the
+// density change of the elements whose source cell has that colour (the
+// linearisation point and time-n fields stay)
 __device__ __forceinline__ void ltile_refresh_map(const PhysF &P, const LView &L, const TileF &T, const int *map,
                                                   int colour)
 {
