@@ -99,3 +99,31 @@ def test_acceleration_on_density_ratio_100_box(precision):
     assert res[2][0] < 0.8 * res[0][0], (res[0][0], res[2][0])
     for k in FIELDS:
         assert rel(res[2][1][k], res[0][1][k], 1e-3) < 1e-6, (k, rel(res[2][1][k], res[0][1][k], 1e-3))
+
+
+def test_history_restart_matches_oracle():
+    """The iterate disturbed in the middle of a step (the history kept): the
+    next result does not improve, the history restarts, and every later
+    cycle and combination matches the oracle's"""
+    cfg = W.rising_drop(16, 32, eps=0.08)
+    say("accelerated cycles with a restart")
+    opts = dict(W.default_opts(1e-14), accel=2)
+    g = Q.Solver(cfg["grid"], cfg["params"], opts)
+    o = OR.Oracle(cfg["grid"], cfg["params"], opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+        s.begin_step(cfg["dt"])
+    for _ in range(4):
+        g.vcycle(); o.vcycle()
+        g.accelerate(); o.accelerate()
+    st = o.get_state()
+    rng = np.random.default_rng(5)
+    dist = {k: st[k] + (0.05 * rng.standard_normal(st[k].shape) if k in ("u", "v") else 0.0) for k in FIELDS}
+    g.set_iterate(*[dist[k] for k in FIELDS])
+    o.set_state(*[dist[k] for k in FIELDS])
+    for it in range(4):
+        g.vcycle(); o.vcycle()
+        g.accelerate(); o.accelerate()
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k]) < 1e-10, (it, k, rel(a[k], b[k]))

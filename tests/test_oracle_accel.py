@@ -101,3 +101,38 @@ def test_acceleration_reaches_the_same_root_in_fewer_cycles():
     for k in FIELDS:
         scale = max(np.abs(res[0][1][k]).max(), 1e-3)
         assert np.abs(res[0][1][k] - res[2][1][k]).max() < 1e-8 * scale, k
+
+
+def test_history_restarts_when_a_result_does_not_improve():
+    """A cycle result whose largest residual norm is not below its
+    predecessor's starts a new history: no combination after it, and the next
+    one uses that result and its successor only (checked against numpy's
+    least squares on the two)"""
+    c = W.rising_drop(16, 32, eps=0.08)
+    o = OR.Oracle(c["grid"], c["params"], dict(W.default_opts(1e-14), accel=2))
+    o.set_state(c["state"]["c"])
+    o.begin_step(c["dt"])
+    for _ in range(4):
+        o.vcycle()
+        o.accelerate()
+    _, n_before = o.residual()
+    # disturb the iterate (time-n data and the history stay)
+    st = o.get_state()
+    rng = np.random.default_rng(5)
+    o.set_state(*[st[k] + (0.05 * rng.standard_normal(st[k].shape) if k in ("u", "v") else 0.0)
+                  for k in FIELDS])
+    o.vcycle()
+    _, n_after = o.residual()
+    assert n_after.max() >= n_before.max()
+    assert o.accel_coeffs().size == 0
+    o.accelerate()
+    w1, (r1, _) = _stack(o.get_state()), o.residual()
+    o.vcycle()
+    w2, (r2, _) = _stack(o.get_state()), o.residual()
+    g = o.accel_coeffs()
+    assert g.size == 1
+    A = (r2 - r1).ravel()[:, None]
+    gl, *_ = np.linalg.lstsq(A, -r2.ravel(), rcond=None)
+    assert np.allclose(g, gl, rtol=1e-7)
+    o.accelerate()
+    assert np.allclose(_stack(o.get_state()), w2 + g[0] * (w2 - w1), rtol=0, atol=1e-13 * np.abs(w2).max())
