@@ -342,9 +342,10 @@ static void acc_record_launch(qnsch_ctx *x, short &acc)
 }
 
 // Normal equations H g = -b of the combination (H packed by columns in
-// v[0..5], b in v[6..8]) over the n earliest-paired results, solved by
-// Cholesky; the leading block whose pivots exceed 1e-12 times their diagonal
-// entry is used.  Returns the number of coefficients (the rest are 0).
+// v[0..5], b in v[6..8]) over the n earlier results the newest one was paired
+// with (the most recent first), solved by Cholesky; the leading block whose
+// pivots exceed 1e-12 times their diagonal entry is used.  Returns the number
+// of coefficients (the rest are 0).
 static int acc_solve(const double *v, int n, double g[3])
 {
     auto H = [&](int i, int j) { return i <= j ? v[j * (j + 1) / 2 + i] : v[i * (i + 1) / 2 + j]; };
