@@ -327,12 +327,14 @@ def run_served_at_scale(nbig, big, nsteps, tol, lanes, max_vcycles):
     """nbig periodic drop boxes of big x big cells submitted at once, with a
     Poisson background stream of 256 x 256 boxes while they run, through the
     server in mixed precision; the plain-FP64 sequential baseline is each kind
-    of request alone (one big box for 2 steps, one background box for 5)"""
+    of request alone for all its steps (one big box, one background box; the
+    first steps of a box take the most cycles, so a shorter sample would
+    overstate the sequential time)"""
     bigs, bg = W.serving_at_scale(nbig=nbig, big=big, nsteps=nsteps)
     mixed = dict(base_opts(tol), precision=Q.MIXED, max_vcycles=max_vcycles)
     fp64 = dict(base_opts(tol), max_vcycles=max_vcycles)
     seq = {}
-    for name, r, k in (("big", bigs[0], 2), ("background", next(W.serving_at_scale(1, 64, nsteps)[1]), 5)):
+    for name, r, k in (("big", bigs[0], nsteps), ("background", next(W.serving_at_scale(1, 64, nsteps)[1]), nsteps)):
         note("serving at scale: sequential FP64 baseline,", name)
         w = r["work"]
         g = Q.Solver(w["grid"], w["params"], fp64)
@@ -386,7 +388,8 @@ def run_served_at_scale(nbig, big, nsteps, tol, lanes, max_vcycles):
             "vcycles_per_step_big": float(np.mean([r["vcycles"].mean() for r in rb])),
             "sequential_fp64_estimate_s": seq_s,
             "speedup_vs_sequential_fp64": seq_s / s["wall_s"] if s["wall_s"] > 0 else None,
-            "sequential_sample": "one %dx%d box alone for 2 steps and one background box for 5, FP64" % (big, big)}
+            "sequential_sample": "one %dx%d box and one background box alone for %d steps each, FP64"
+                                 % (big, big, nsteps)}
 
 
 def main():
@@ -404,7 +407,7 @@ def main():
     ap.add_argument("--no-serve-scale", action="store_true", help="skip the serving-at-scale workload")
     ap.add_argument("--scale-boxes", type=int, default=16)
     ap.add_argument("--scale-size", type=int, default=2048)
-    ap.add_argument("--scale-steps", type=int, default=3)
+    ap.add_argument("--scale-steps", type=int, default=20)
     ap.add_argument("--scale-max-vcycles", type=int, default=150)
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-projection", action="store_true")
