@@ -264,7 +264,9 @@ def run_served(n, nsteps, tol, seq_steps, lanes):
     mixed = dict(base_opts(tol), precision=Q.MIXED)
     fp64 = base_opts(tol)
     served = dict(mixed, accel=SERVED_ACCEL)
-    # sequential baselines: every request alone, seq_steps steps each
+    # sequential baselines: every request alone for all its steps (the first
+    # steps of a request take the most cycles, so a shorter sample would
+    # overstate the sequential time)
     seq = {"fp64": float("nan"), "mixed": float("nan")}
     for name, opts in (("fp64", fp64), ("mixed", mixed)) if seq_steps else ():
         note("serving: sequential baseline", name)
@@ -462,7 +464,7 @@ def main():
     if not args.no_mixed:
         out["mixed"] = run_mixed(args.mixed_steps, args.tol)
     if not args.no_serve:
-        out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=0 if args.no_seq else 5,
+        out["served"] = run_served(args.serve_requests, args.serve_steps, args.tol, seq_steps=0 if args.no_seq else args.serve_steps,
                                    lanes=args.serve_lanes)
     if not args.no_serve_scale:
         out["served_at_scale"] = run_served_at_scale(args.scale_boxes, args.scale_size, args.scale_steps, args.tol,
