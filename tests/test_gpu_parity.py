@@ -307,30 +307,43 @@ def _to_fine(c):
     return f
 
 
-def test_cauchy_convergence_is_second_order():
+@pytest.mark.parametrize("scheme", ["primitive", "projection"])
+def test_cauchy_convergence_is_second_order(scheme):
     """Cauchy study of sec. 9 (mesh 16..256, dt = (1/16)(16/m)^2, bounded
-    initial phase field, density ratio 3): the L2 difference of c between
-    successive meshes, the coarse solution interpolated to the fine mesh,
-    falls with rate -> 2 (first order in time with dt ~ h^2, second order in
-    space); the V-cycle count per step stays bounded as the mesh is refined"""
+    initial phase field, density ratio 3), for both schemes: the L2 difference
+    of c between successive meshes, the coarse solution interpolated to the
+    fine mesh, falls with rate -> 2 (first order in time with dt ~ h^2, second
+    order in space), and the finest rate is within 0.15 of the one Table 1
+    prints for the scheme (tests/golden); the V-cycle count per step stays
+    bounded as the mesh is refined"""
+    import json
+    import os
+    table = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                        "table1_cauchy_convergence.json")))[scheme]
     sols = {}
     for m in (16, 32, 64, 128, 256):
         cfg = W.convergence_case(m)
         # tol far below the Cauchy differences (1e-3 .. 1e-5) and above the
         # round-off floor of residuals scaled by 1/dt = 4096
-        g = Q.Solver(cfg["grid"], cfg["params"], W.default_opts(1e-9))
+        opts = dict(W.default_opts(1e-9), scheme=Q.PROJECTION if scheme == "projection" else Q.PRIMITIVE)
+        g = Q.Solver(cfg["grid"], cfg["params"], opts)
         g.set_state(cfg["state"]["c"])
         vc = 0
         for _ in range(cfg["nsteps"]):
             assert g.step(cfg["dt"]) == Q.OK
             vc = max(vc, g.stats()["vcycles"])
         sols[m] = g.get_state()["c"]
-        say("convergence mesh", m, "steps", cfg["nsteps"], "most V-cycles in a step", vc)
-        assert vc <= 12, (m, vc)
+        say("convergence", scheme, "mesh", m, "steps", cfg["nsteps"], "most V-cycles in a step", vc)
+        # the projection scheme's smoother (sec. 7.2, its pressure step apart
+        # from the box) needs more cycles as the mesh is refined with dt ~ h^2
+        # (7, 7, 13, 27 from 32 to 256), as the segregated primitive smoother
+        # does; the bound only guards against a breakdown there
+        assert vc <= (12 if scheme == "primitive" else 40), (m, vc)
     errs = []
     for m in (16, 32, 64, 128):
         d = _to_fine(sols[m]) - sols[2 * m]
         errs.append(np.sqrt((d * d).mean()))
     rates = [np.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
-    say("cauchy errors", errs, "rates", rates)
+    say("cauchy errors", scheme, errs, "rates", rates, "printed", table["rate"])
     assert rates[-1] > 1.7, rates
+    assert abs(rates[-1] - table["rate"][-1]) < 0.15, (rates, table["rate"])
