@@ -596,10 +596,44 @@ static void p_point(orc_ctx *o, Level *L, int i, int j)
     L->f[F_P][k] += om * (L->rhs[2][k] - creal(r)) / J;
 }
 
+/* Projection scheme, coupled form of step 1 (a reading, see halfsweep_pj):
+ * one Newton step on (N_c, N_mu, N_p) in (c, mubar, pbar) of the cell.  The
+ * c and mubar columns of the local Jacobian take the velocity of time n+1
+ * held (as step 1 of sec. 7.2), the pbar column lets it follow pbar through
+ * the projection equation (pj-num-pjx); the residuals are those of the
+ * current iterate.  Complex-step derivatives as everywhere. */
+static void cmp_point(orc_ctx *o, Level *L, int i, int j)
+{
+    size_t k = (size_t)j * L->m1 + i;
+    double J[7][7], b[7];
+    int fl[3] = { F_C, F_MU, F_P };
+    const Level *fz = o->fzlev;
+    for (int col = 0; col < 3; col++) {
+        o->fzlev = col < 2 ? fz : NULL;
+        perturb(o, L, fl[col], i, j);
+        cx rc = res_c(o, L, i, j), rm = res_mu(o, L, i, j), rp = res_p(o, L, i, j);
+        J[0][col] = cimag(rc) / CSTEP;
+        J[1][col] = cimag(rm) / CSTEP;
+        J[2][col] = cimag(rp) / CSTEP;
+        if (col == 0) { b[0] = L->rhs[0][k] - creal(rc); b[1] = L->rhs[1][k] - creal(rm); b[2] = L->rhs[2][k] - creal(rp); }
+    }
+    unperturb(o);
+    o->fzlev = fz;
+    if (gepp(3, J, b) != 0) return;
+    L->f[F_C][k] += b[0];
+    L->f[F_MU][k] += b[1];
+    L->f[F_P][k] += b[2];
+}
+
 /* Projection scheme, one colour (sec. 7.2, steps per cell of the colour):
  *   1. one Newton step on (N_c, N_mu) in (c, mubar), the velocity of time n+1
  *      frozen at its value before the half-sweep (the stored velocity of the
- *      paper's sequential sweep);
+ *      paper's sequential sweep); with the coupled smoother (the default, a
+ *      reading) the step also takes pbar with the mass equation (cmp_point):
+ *      held apart, mubar and pbar are updated in turn although the phase and
+ *      mass equations see them together (through mubar + alpha pbar), which
+ *      stalls the cycles under refinement (58 V-cycles on the 256 x 256
+ *      convergence case of sec. 9 against 10 coupled);
  *   2. the Vanka box of the four intermediate-velocity faces (exact: the
  *      momentum equations are linear in u~), Jacobi within the colour as in
  *      the primitive scheme;
@@ -622,7 +656,10 @@ static void halfsweep_pj(orc_ctx *o, int l, int colour)
     o->fzlev = L;
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++)
-            if (((i + j) & 1) == colour) ch_point(o, L, i, j);
+            if (((i + j) & 1) == colour) {
+                if (o->o.smoother == ORC_SMOOTH_COUPLED) cmp_point(o, L, i, j);
+                else ch_point(o, L, i, j);
+            }
     o->fzlev = NULL;
     double *unew = malloc(n * sizeof(double)), *vnew = malloc(n * sizeof(double));
     memcpy(unew, L->f[F_U], n * sizeof(double));

@@ -35,7 +35,7 @@ typedef struct {
     double tol;
     int max_vcycles, nu1, nu2, nu_coarse;
     double vanka_omega;
-    int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED (primitive scheme) */
+    int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED; projection scheme: step 1 with or without pbar */
     int scheme;   /* ORC_PRIMITIVE (sec. 6.1) or ORC_PROJECTION (sec. 6.2) */
     double coarse_omega; /* relaxation of the velocity/pressure updates on the coarsest level */
     int accel;           /* depth (0..ORC_MAXACC) of the acceleration of the cycle iteration; 0 = off */

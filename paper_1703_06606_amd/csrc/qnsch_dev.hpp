@@ -797,7 +797,10 @@ __device__ __forceinline__ PjAx pj_axis(const Tile &T, const Ax &a, int e, doubl
 
 // Smoother of sec. 7.2 for one cell of the current colour, by a lane pair:
 //  1. one Newton step on (N_c, N_mu) in (c, mubar) of the cell, the velocity
-//     of time n+1 on its faces held at its value before the update;
+//     of time n+1 on its faces held at its value before the update; with the
+//     coupled smoother (P.coupled, the default) pbar and the mass equation
+//     join this step, the velocity of time n+1 following pbar in its column
+//     only;
 //  2. the Vanka box of the four intermediate-velocity faces on (pj-num-mx),
 //     exact (linear in u~), Jacobi within the colour;
 //  3. one Newton step in pbar on the mass equation (pj-num-mass) with the
@@ -829,9 +832,38 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double Nmu = q.Nmu - (rs - rn) * m0;
     const double Jcc = rn * P.inv_dt + dadv, Jcm = q.Jcm, Jmm = rn, Jmc = q.Jmc - drs * m0;
     const double r1 = ldf(F.fc, L, i, j) - Nc, r2 = ldf(F.fmu, L, i, j) - Nmu;
-    const double idet = frcp(Jcc * Jmm - Jcm * Jmc);
-    const double cnew = c0 + (Jmm * r1 - Jcm * r2) * idet;
-    const double mnew = m0 + (Jcc * r2 - Jmc * r1) * idet;
+    const double p0 = tq(T, T_P, e);
+    double cnew, mnew, pnew = p0;
+    if (P.coupled) {
+        // pbar joins the step with the mass equation: its column lets the
+        // velocity of time n+1 follow pbar through (pj-num-pjx) (on the lo
+        // face D pbar falls by pbar/h, on the hi face it rises), the c and
+        // mubar columns hold it
+        const double dlo = hlo ? -P.dt * P.inv_M * ih * frcp(0.5 * (tq(T, T_RS, e - a.dn) + rs)) : 0.0;
+        const double dhi = hhi ? P.dt * P.inv_M * ih * frcp(0.5 * (rs + tq(T, T_RS, e + a.dn))) : 0.0;
+        const double cl = 0.5 * ih * (tq(T, T_RS, e - a.dn) * (c0 - tq(T, T_C, e - a.dn)) * dlo
+                                      + tq(T, T_RS, e + a.dn) * (tq(T, T_C, e + a.dn) - c0) * dhi);
+        const double jx = ih * (dhi - dlo), dv = x0.div;
+        const double Jcp = cl + other(cl) + P.alpha * P.inv_Pe * s.Sm, Jpm = P.alpha * P.inv_Pe * s.Sm;
+        const double Jpp = jx + other(jx) + q.Jpp;
+        const double Np = dv + other(dv) - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp;
+        const double r3 = ldf(F.fp, L, i, j) - Np;
+        // eliminate pbar by the mass row (pivot Jpp), then mubar by the
+        // chemical row (pivot Jmm): a 2x2 system in c and mubar remains
+        const double ipp = frcp(Jpp);
+        const double kcm = Jcm - Jcp * Jpm * ipp, rc1 = r1 - Jcp * r3 * ipp;
+        const double idet = frcp(Jcc * Jmm - kcm * Jmc);
+        const double dc = (Jmm * rc1 - kcm * r2) * idet;
+        const double dm = (Jcc * r2 - Jmc * rc1) * idet;
+        cnew = c0 + dc;
+        mnew = m0 + dm;
+        pnew = p0 + (r3 - Jpm * dm) * ipp;
+        T.s[T_P * st + e] = pnew;
+    } else {
+        const double idet = frcp(Jcc * Jmm - Jcm * Jmc);
+        cnew = c0 + (Jmm * r1 - Jcm * r2) * idet;
+        mnew = m0 + (Jcc * r2 - Jmc * r1) * idet;
+    }
     if (hlf == 0) {
         L.c[k] = cnew;
         L.mu[k] = mnew;
@@ -906,10 +938,10 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double jax = P.dt * P.inv_M * ih2 * ((hlo ? frcp(Alo) : 0.0) + (hhi ? frcp(Ahi) : 0.0));
     const double dv = ih * (uhi1 - ulo1);
     const double div = dv + other(dv), jp = jax + other(jax);
-    const double Lmu_new = s.Lmu - s.Sm * (mnew - m0);
-    const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp;
+    const double Lmu_new = s.Lmu - s.Sm * (mnew - m0), Lp_new = s.Lp - s.Sm * (pnew - p0);
+    const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * Lp_new;
     const double Jp = jp + q.Jpp;
-    if (hlf == 0) L.p[k] = tq(T, T_P, e) + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+    if (hlf == 0) L.p[k] = pnew + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
 }
 
 // residuals of the projection scheme's five equations attached to cell (i,j)

@@ -65,12 +65,13 @@ def test_projection_residual_matches_oracle(shape):
     assert np.allclose(ng, no, rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "%dx%d_bc%d%d" % s)
-def test_projection_halfsweeps_match_oracle(shape):
+def test_projection_halfsweeps_match_oracle(shape, smoother):
     m1, m2, bx, by = shape
-    say("projection halfsweep parity", shape)
+    say("projection halfsweep parity", shape, "smoother", smoother)
     cfg = dict(grid=grid_(m1, m2, bx, by), params=par_O1(rho2=3.0))
-    g, o = pair(cfg, pj())
+    g, o = pair(cfg, pj(smoother=smoother))
     w, wn = W.random_state(cfg["grid"], 23), W.random_state(cfg["grid"], 24)
     for s in (g, o):
         s.set_time_n_and_iterate(wn, w, 0.3)
@@ -99,11 +100,12 @@ def _cases():
     }
 
 
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
 @pytest.mark.parametrize("name", list(_cases()))
-def test_projection_vcycles_match_oracle(name):
+def test_projection_vcycles_match_oracle(name, smoother):
     cfg = _cases()[name]
-    say("projection vcycle parity", name)
-    g, o = pair(cfg, pj())
+    say("projection vcycle parity", name, "smoother", smoother)
+    g, o = pair(cfg, pj(smoother=smoother))
     for s in (g, o):
         s.set_state(cfg["state"]["c"])
         s.begin_step(cfg["dt"])
