@@ -133,7 +133,23 @@ typedef struct {
                             projection scheme's pressure step); in (0, 2) */
     int32_t accel;       /* depth m (0..3) of the acceleration of the cycle iteration
                             below; 0 = plain cycles */
+    int32_t blocking;    /* temporal blocking of the smoothing (below): 0 = off,
+                            1 = coarse levels, 2 = the finest level too */
 } qnsch_opts;
+
+/* Temporal blocking (a performance variant of the smoother of sec. 7.1; the
+ * iterates are those of the plain half-sweeps up to rounding).  On the levels
+ * that are smoothed by launches over many workgroups (not those resident in
+ * one workgroup's LDS) and have at most two 16 x 16 tiles per compute unit
+ * (where launch latency, not throughput, sets the time), a red and the
+ * following black half-sweep run in one launch: each tile relaxes the red
+ * cells of its tile widened by two cells on every side in LDS, then its own
+ * black cells.  Sweeps go in pairs (an odd last sweep takes two half-sweep
+ * launches).  Needs a second set of
+ * c, mubar, pbar per level (24 bytes per cell of every level); FP64 primitive
+ * scheme only (ignored in mixed precision and for the projection scheme); a
+ * level with a periodic axis shorter than 19 cells keeps the half-sweep
+ * launches. */
 
 /* Acceleration of the cycle iteration (not part of the paper, whose sec. 7.1
  * asks only for a standard FAS V-cycle; the discrete system, its root and the
@@ -165,14 +181,15 @@ typedef struct qnsch_ctx qnsch_ctx;
 /* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 6 coarsest sweeps
  * over-relaxed by coarse_omega = 1.6 (as accurate as 30 plain sweeps on the
  * workloads of sec. 8), omega 1, coupled smoother, primitive scheme,
- * acceleration depth 2. */
+ * acceleration depth 2, temporal blocking of the coarse levels (1). */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
  * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
  * device memory in one allocation (qnsch_footprint: roughly 150 bytes per
  * finest cell in FP64, 182 in mixed precision, plus 80 (accel + 1) for the
- * acceleration's history).  Returns
+ * acceleration's history and 32 for the second cell set of temporal
+ * blocking).  Returns
  * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
 int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
                  void *hip_stream, qnsch_ctx **out);
@@ -257,9 +274,10 @@ int qnsch_synchronize(qnsch_ctx *ctx);
 
 /* Measurement support.  qnsch_profile(ctx, mode) resets the counters and
  * times launches with HIP events on the context's stream: mode 1 every launch
- * of the finest-level half-sweep kernel (FP64, or FP32 in mixed precision),
- * mode 2 every launch of the step, 0 none.  qnsch_profile_read returns
- * {finest half-sweep launches, their total milliseconds}.
+ * of the finest-level half-sweep kernel (FP64, or FP32 in mixed precision;
+ * the fused sweep kernel where blocking covers the finest level), mode 2
+ * every launch of the step, 0 none.  qnsch_profile_read returns {finest
+ * half-sweep (or fused sweep) launches, their total milliseconds}.
  * qnsch_profile_breakdown returns the number of timed operation classes and
  * writes up to cap of them: kinds[k] = 2*operation + (1 if on a coarser level
  * than the finest), out[2k] = launches, out[2k+1] = total milliseconds (the

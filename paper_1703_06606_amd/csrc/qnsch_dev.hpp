@@ -574,16 +574,23 @@ __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, cons
 
 // omega relaxes the box's velocity and pressure updates; pomega the
 // projection scheme's separate pressure step
-__device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
-                                           double *vnew, int i, int j, int hlf, double omega, double pomega)
+// With TO set (primitive scheme only), the cell sits at tile position (ti,
+// tj), which differs from its level position (i, j) at a periodic image, and
+// the results stay in the tile: c, mubar, pbar and rho(c) in place (no other
+// cell of the colour reads them), the box faces in the fields T_NF (u) and
+// T_NF + 1 (v), whose elements only this cell's box writes.
+template <bool TO>
+__device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
+                                           double *vnew, int i, int j, int ti, int tj, int hlf, double omega,
+                                           double pomega)
 {
-    if (P.scheme) {
+    if (!TO && P.scheme) {
         relax_pair_pj(P, L, T, F, unew, vnew, i, j, hlf, omega, pomega);
         return;
     }
     const size_t k = (size_t)j * L.pitch + i;
     const double ih = L.inv_h, ih2 = ih * ih;
-    const int e = T.idx(i, j);
+    const int e = T.idx(ti, tj);
     const Ax a = make_ax(L, T, i, j, hlf);
     const bool cpl = P.coupled;
     CellAx x = cell_axis(T, a, e, ih);
@@ -610,7 +617,7 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
         const double idet = frcp(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
         cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
         mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
-        if (hlf == 0) {
+        if (!TO && hlf == 0) {
             L.c[k] = cnew;
             L.mu[k] = mnew;
         }
@@ -720,11 +727,26 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
 #pragma unroll
         for (int t = 0; t < 5; t++) acc -= ac[t] * b[t];
         const double dc = acc * icc;
-        L.c[k] = c0 + dc;
-        L.mu[k] = m0 + kbm - kmc * dc;
+        if (TO) {
+            const int n = T.W * T.H;
+            T.s[T_C * n + e] = c0 + dc;
+            T.s[T_MU * n + e] = m0 + kbm - kmc * dc;
+            T.s[T_RS * n + e] = rho_of(P, c0 + dc);
+        } else {
+            L.c[k] = c0 + dc;
+            L.mu[k] = m0 + kbm - kmc * dc;
+        }
     }
     const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
     const double nlo = tq(T, a.FN, e) + omega * dl, nhi = tq(T, a.FN, e + a.dn) + omega * dh;
+    if (TO) {
+        const int n = T.W * T.H;
+        double *fo = T.s + (T_NF + hlf) * n;
+        if (hlo) fo[e] = nlo;
+        if (hhi) fo[e + a.dn] = nhi;
+        if (hlf == 0) T.s[T_P * n + e] = tq(T, T_P, e) + omega * b[4];
+        return;
+    }
     if (hlf) {
         if (hlo) vnew[k] = nlo;
         if (hhi) vnew[khi] = nhi;
@@ -733,6 +755,11 @@ __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const T
         if (hhi) unew[khi] = nhi;
     }
     if (hlf == 0) L.p[k] = tq(T, T_P, e) + omega * b[4];
+}
+__device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
+                                           double *vnew, int i, int j, int hlf, double omega, double pomega)
+{
+    relax_cell<false>(P, L, T, F, unew, vnew, i, j, i, j, hlf, omega, pomega);
 }
 
 // residuals r = f - N(w) of the five equations attached to cell (i,j): the

@@ -56,6 +56,7 @@ struct Desc {
     double *red;                                        // reduced values (device)
     double *red_host;                                   // reduced values (pinned host)
     double *mus, *ps;                                   // mubar, pbar of time n (finest level)
+    double *c2, *mu2, *p2;                              // second set of cell unknowns (fused sweeps; else NULL)
     double *rout;                                       // residual fields (finest level, optional)
     // acceleration history (finest level): a ring of am slots, each holding
     // a cycle result (aw, pbar before its mean removal) and its residual (ar)
@@ -171,6 +172,137 @@ template <typename IT> __global__ HS_ATTR void k_halfsweep(IT it, int colour, do
 template <typename IT> __global__ FINE_ATTR void k_halfsweep_fine(IT it, int colour, double omega)
 {
     halfsweep_body(it, colour, omega);
+}
+
+// --------------------------------------------------------------------------
+// temporal blocking: one sweep (red, then black half-sweep of sec. 7.1, the
+// same arithmetic as two k_halfsweep launches) in one launch.  A workgroup
+// relaxes the red cells of its tile widened by two cells on every side (the
+// red results its black cells read; neighbouring workgroups compute the
+// overlap again), keeps them in LDS, then relaxes the black cells of its
+// tile.  Workgroups still read their neighbours' cells as halo while others
+// write, so the cell unknowns go from one set to the other (dir 0: c, mu, p
+// to c2, mu2, p2; dir 1 back) and the faces from buffer par to par ^ 1.
+#define FUSED_W (TX + 7)
+#define FUSED_H (TY + 7)
+#define FBLK (2 * TBLK)
+#define FUSED_DOUBLES ((T_NF + 2) * FUSED_W * FUSED_H)
+static_assert(FUSED_DOUBLES * 8 <= 65536, "fused tile exceeds 64 KiB of LDS");
+static_assert((TX + 4) * (TY + 4) <= FBLK, "widened red region exceeds the workgroup");
+
+// the widened tile: every field at tile positions i0-1 .. i0+W-2 (level
+// coordinates; periodic images at their unwrapped positions), plus copies of
+// u and v in the fields T_NF, T_NF + 1 that the red pass overwrites.  A
+// periodic axis needs m >= TX + 3 so that a single wrap reaches every position.
+__device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        if (L.bcx) i = wrapi(i, L.m1);
+        if (L.bcy) j = wrapi(j, L.m2);
+        const TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        double *s = T.s + e;
+        if (q.sc == 0) {
+            for (int f = 0; f < T_NF + 2; f++) s[f * n] = 0.0;
+            continue;
+        }
+        const double v[8] = { L.c[q.c], L.mu[q.c], L.p[q.c], L.u[q.u], L.v[q.v], L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        s[T_C * n] = v[0];
+        s[T_MU * n] = v[1];
+        s[T_P * n] = v[2];
+        s[T_U * n] = s[T_NF * n] = signed_val(q.su, v[3]);
+        s[T_V * n] = s[(T_NF + 1) * n] = signed_val(q.sv, v[4]);
+        s[T_CN * n] = v[5];
+        s[T_UN * n] = signed_val(q.su, v[6]);
+        s[T_VN * n] = signed_val(q.sv, v[7]);
+        s[T_RN * n] = rho_of(P, v[5]);
+        s[T_MV * n] = visc_of(P, v[5]);
+        s[T_MOB * n] = mob_of(P, v[5]);
+        s[T_RS * n] = rho_of(P, v[0]);
+    }
+}
+// after the red pass: the new faces become the snapshot of the black pass,
+// and the images across walls follow their sources (ldc clamps a cell to the
+// wall row; ldu, ldv zero a face on or beyond a wall and reflect a
+// tangential ghost).  Periodic images were relaxed in place.
+__device__ __forceinline__ void fused_refresh(const View &L, const Tile &T)
+{
+    const int n = T.W * T.H;
+    const double *un = T.s + T_NF * n, *vn = T.s + (T_NF + 1) * n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        const bool gx = !L.bcx && (i < 0 || i >= L.m1), gy = !L.bcy && (j < 0 || j >= L.m2);
+        const int si = gx ? (i < 0 ? 0 : L.m1 - 1) : i, sj = gy ? (j < 0 ? 0 : L.m2 - 1) : j;
+        const int su = (!L.bcx && (i <= 0 || i >= L.m1)) ? 0 : (gy ? -1 : 1);
+        const int sv = (!L.bcy && (j <= 0 || j >= L.m2)) ? 0 : (gx ? -1 : 1);
+        T.s[T_U * n + e] = signed_val(su, un[T.idx(i, sj)]);
+        T.s[T_V * n + e] = signed_val(sv, vn[T.idx(si, j)]);
+        if (gx || gy) {
+            const int q = T.idx(si, sj);
+            T.s[T_C * n + e] = T.s[T_C * n + q];
+            T.s[T_MU * n + e] = T.s[T_MU * n + q];
+            T.s[T_P * n + e] = T.s[T_P * n + q];
+            T.s[T_RS * n + e] = T.s[T_RS * n + q];
+        }
+    }
+}
+template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it, int dir, double omega)
+{
+    __shared__ double sm[FUSED_DOUBLES];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d) || d.P.scheme) return;
+    const int par = it.par[k];
+    View L = view_of(d, par);
+    View O = L; // where the sweep's cell results go
+    if (dir) {
+        L.c = d.c2; L.mu = d.mu2; L.p = d.p2;
+    } else {
+        O.c = d.c2; O.mu = d.mu2; O.p = d.p2;
+    }
+    const Tile T0 = item_tile(sm, it, k, d);
+    Tile T;
+    T.s = sm; T.i0 = T0.i0 - 2; T.j0 = T0.j0 - 2; T.W = FUSED_W; T.H = FUSED_H;
+    fused_load(d.P, L, T);
+    __syncthreads();
+    const Rhs F = rhs_of(d);
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    {
+        // red: cells with i + j even of i0-2 .. i0+TX+1, j0-2 .. j0+TY+1
+        const int lj = pr / ((TX + 4) / 2), kk = pr - lj * ((TX + 4) / 2);
+        const int tj = T0.j0 - 2 + lj;
+        const int ti = T0.i0 - 2 + 2 * kk + (tj & 1);
+        const bool in = lj < TY + 4 && (L.bcx || (ti >= 0 && ti < L.m1)) && (L.bcy || (tj >= 0 && tj < L.m2));
+        if (in) {
+            const int i = L.bcx ? wrapi(ti, L.m1) : ti, j = L.bcy ? wrapi(tj, L.m2) : tj;
+            relax_cell<true>(d.P, L, T, F, nullptr, nullptr, i, j, ti, tj, hlf, omega, 1.0);
+        }
+    }
+    __syncthreads();
+    fused_refresh(L, T);
+    __syncthreads();
+    if (threadIdx.x < TBLK) {
+        // black cells of the tile: the box faces go to buffer par ^ 1
+        const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
+        const int j = T0.j0 + lj;
+        const int i = T0.i0 + 2 * kk + ((j + 1) & 1);
+        if (i < L.m1 && j < L.m2) relax_cell<false>(d.P, O, T, F, d.ub[par ^ 1], d.vb[par ^ 1], i, j, i, j, hlf, omega, 1.0);
+    } else {
+        // red cells of the tile: their final values
+        const int q = pr - TBLK / 2;
+        const int lj = q / (TX / 2), kk = q - lj * (TX / 2);
+        const int j = T0.j0 + lj;
+        const int i = T0.i0 + 2 * kk + (j & 1);
+        if (i < L.m1 && j < L.m2) {
+            const int e = T.idx(i, j), n = T.W * T.H;
+            const size_t g = (size_t)j * L.pitch + i;
+            if (hlf == 0) { O.c[g] = T.s[T_C * n + e]; O.mu[g] = T.s[T_MU * n + e]; }
+            else O.p[g] = T.s[T_P * n + e];
+        }
+    }
 }
 
 // plain copy, used to measure the copy bandwidth and to calibrate counters

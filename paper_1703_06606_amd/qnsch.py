@@ -33,7 +33,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
 OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
             "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
             "mx_prolong", "mx_update", "dissipation", "diagnostics", "pj_final", "smooth", "mx_smooth", "residual_acc",
-            "accelerate")
+            "accelerate", "fused_sweep")
 
 
 class QnschError(RuntimeError):
@@ -56,7 +56,7 @@ class Opts(C.Structure):
     _fields_ = [("precision", C.c_int32), ("tol", C.c_double), ("max_vcycles", C.c_int32), ("nu1", C.c_int32),
                 ("nu2", C.c_int32), ("nu_coarse", C.c_int32), ("vanka_omega", C.c_double),
                 ("smoother", C.c_int32), ("scheme", C.c_int32), ("coarse_omega", C.c_double),
-                ("accel", C.c_int32)]
+                ("accel", C.c_int32), ("blocking", C.c_int32)]
 
 
 class StepStats(C.Structure):
