@@ -146,10 +146,11 @@ typedef struct {
  * cells of its tile widened by two cells on every side in LDS, then its own
  * black cells.  Sweeps go in pairs (an odd last sweep takes two half-sweep
  * launches).  Needs a second set of
- * c, mubar, pbar per level (24 bytes per cell of every level); FP64 primitive
- * scheme only (ignored in mixed precision and for the projection scheme); a
- * level with a periodic axis shorter than 19 cells keeps the half-sweep
- * launches. */
+ * c, mubar, pbar per level (24 bytes per cell of every level), in mixed
+ * precision of the FP32 corrections dc, dmu, dp (12 bytes), whose smoother is
+ * fused the same way; primitive scheme only (ignored for the projection
+ * scheme); a level with a periodic axis shorter than 19 cells keeps the
+ * half-sweep launches. */
 
 /* Acceleration of the cycle iteration (not part of the paper, whose sec. 7.1
  * asks only for a standard FAS V-cycle; the discrete system, its root and the
@@ -188,8 +189,8 @@ void qnsch_default_opts(qnsch_opts *opts);
  * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
  * device memory in one allocation (qnsch_footprint: roughly 150 bytes per
  * finest cell in FP64, 182 in mixed precision, plus 80 (accel + 1) for the
- * acceleration's history and 32 for the second cell set of temporal
- * blocking).  Returns
+ * acceleration's history and 32 (16 in mixed precision) for the second cell
+ * set of temporal blocking).  Returns
  * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
 int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
                  void *hip_stream, qnsch_ctx **out);
@@ -323,7 +324,8 @@ int qnsch_server_create(size_t hbm_budget, int32_t max_slots, int32_t lanes, voi
 void qnsch_server_destroy(qnsch_server *srv);
 const char *qnsch_server_last_error(const qnsch_server *srv);
 /* Queue a request; c0 (m1*m2, host) is copied.  QNSCH_ENOMEM if its footprint
- * exceeds the whole budget; QNSCH_EINVAL as for qnsch_create. */
+ * exceeds the whole budget; QNSCH_EINVAL as for qnsch_create.  opts.blocking
+ * is ignored (0): the server's merged launches already fill the device. */
 int qnsch_server_submit(qnsch_server *srv, const qnsch_grid *grid, const qnsch_params *params,
                         const qnsch_opts *opts, const double *c0, int32_t nsteps, double dt, uint64_t *id);
 /* Run up to max_ticks scheduler ticks; returns the number of unfinished

@@ -69,6 +69,7 @@ struct Desc {
     float *xc, *xmu, *xu, *xv;                          // linearisation point
     float *dc, *dmu, *dp, *dub[2], *dvb[2];             // correction (u/v ping-pong)
     float *rc, *rmu, *rp, *ru, *rv;                     // right-hand side
+    float *dc2, *dmu2, *dp2;                            // second set of cell corrections (fused sweeps)
     float *cnf, *unf, *vnf;                             // time-n data
     float finv_h;
 };

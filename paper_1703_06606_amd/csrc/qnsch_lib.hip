@@ -43,7 +43,7 @@ enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, O
               OP_NORMACC, OP_ACCEL,
               // one red + black sweep of a level in one launch (temporal
               // blocking); colour field = direction of the cell sets
-              OP_FUSED, NOPS };
+              OP_FUSED, OP_MXFUSED, NOPS };
 struct Op {
     int kind, level, colour;
 };
@@ -55,6 +55,7 @@ struct Op {
 // two half-sweeps), all with the same arithmetic in the same order
 static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, unsigned fuse, std::vector<Op> &out)
 {
+    const int fused_kind = hs_kind == OP_MXHS ? OP_MXFUSED : OP_FUSED;
     if (nu <= 0) return;
     if (l > 0 && l >= small) {
         out.push_back({ lds_kind, l, nu });
@@ -63,8 +64,8 @@ static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, unsi
     int s = 0;
     if ((fuse >> l) & 1)
         for (; s + 1 < nu; s += 2) {
-            out.push_back({ OP_FUSED, l, 0 });
-            out.push_back({ OP_FUSED, l, 1 });
+            out.push_back({ fused_kind, l, 0 });
+            out.push_back({ fused_kind, l, 1 });
         }
     for (; s < nu; s++) {
         out.push_back({ hs_kind, l, 0 });
@@ -102,15 +103,15 @@ static void vcycle_program(int L, int nu1, int nu2, int small, unsigned fuse, bo
 // one outer iteration of the mixed-precision step: an FP32 correction
 // V-cycle on J(w^) delta = r, w += delta in FP64, then the FP64 residual
 // (which also prepares the next cycle) and the pbar mean removal
-static void mixed_program(int L, int nu1, int nu2, int small, bool acc, std::vector<Op> &out)
+static void mixed_program(int L, int nu1, int nu2, int small, unsigned fuse, bool acc, std::vector<Op> &out)
 {
     for (int l = 0; l + 1 < L; l++) {
-        smooth_ops(l, nu1, small, OP_MXHS, OP_MXSMOOTH, 0u, out);
+        smooth_ops(l, nu1, small, OP_MXHS, OP_MXSMOOTH, fuse, out);
         out.push_back({ OP_MXRESTRICT, l, 0 });
     }
     out.push_back({ OP_MXCOARSE, L - 1, 0 });
     for (int l = L - 2; l >= 0; l--)
-        prolong_smooth_ops(l, nu2, small, OP_MXPROLONG, OP_MXHS, OP_MXSMOOTH, 0u, out);
+        prolong_smooth_ops(l, nu2, small, OP_MXPROLONG, OP_MXHS, OP_MXSMOOTH, fuse, out);
     out.push_back({ OP_MXUPDATE, 0, 0 });
     out.push_back({ acc ? OP_NORMACC : OP_NORM, 0, 0 });
 }
@@ -194,10 +195,11 @@ static int small_level(const qnsch_ctx *x)
     }
     return small;
 }
-// whether the opts give the FP64 levels a second set of cell unknowns
+// whether the opts give the levels a second set of cell unknowns (FP64) or
+// cell corrections (mixed precision)
 static bool two_sets(const qnsch_opts &o)
 {
-    return o.blocking > 0 && o.precision == QNSCH_FP64 && o.scheme == QNSCH_PRIMITIVE;
+    return o.blocking > 0 && o.scheme == QNSCH_PRIMITIVE;
 }
 // levels whose sweeps run fused (bit l): those smoothed by half-sweep
 // launches (below small), the finest one only with blocking 2, with at most
@@ -232,7 +234,7 @@ static unsigned fused_levels(const qnsch_ctx *x)
 static void cycle_program(const qnsch_ctx *x, std::vector<Op> &out)
 {
     const bool rec = x->opt.accel > 0;
-    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), rec, out);
+    if (is_mixed(x)) mixed_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), fused_levels(x), rec, out);
     else vcycle_program(x->nlev, x->opt.nu1, x->opt.nu2, small_level(x), fused_levels(x), rec, out);
 }
 
@@ -266,7 +268,7 @@ static int op_blocks(const qnsch_ctx *x, int kind, int l)
     const DLev &D = x->L[l];
     switch (kind) {
     case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_NORMACC: case OP_MXHS:
-    case OP_MXRESTRICT: case OP_FUSED:
+    case OP_MXRESTRICT: case OP_FUSED: case OP_MXFUSED:
         return tiles_x(D.m1) * tiles_y(D.m2);
     case OP_COARSE: case OP_MXCOARSE: case OP_SMOOTH: case OP_MXSMOOTH: return 1;
     case OP_RN: case OP_MXRN: return (int)nblocks((size_t)x->L[l + 1].m1 * x->L[l + 1].m2);
@@ -320,7 +322,7 @@ static int prof_collect(qnsch_ctx *x)
         float ms = 0.f;
         HIPCHK(x, hipEventElapsedTime(&ms, x->pev[2 * q], x->pev[2 * q + 1]));
         const int tag = x->ptag[q];
-        if (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED) {
+        if (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED || tag == 2 * OP_MXFUSED) {
             x->prof_ms += ms;
             x->prof_n++;
         }
@@ -337,7 +339,7 @@ static int prof_tag(int kind, const std::vector<std::pair<qnsch_ctx *, int>> &pa
 {
     const qnsch_ctx *x = part[0].first;
     if (part.size() != 1 || !x->prof) return -1;
-    const bool fine_hs = (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED) && part[0].second == 0;
+    const bool fine_hs = (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED || kind == OP_MXFUSED) && part[0].second == 0;
     if (x->prof == 1 && !fine_hs) return -1;
     return 2 * kind + (part[0].second == 0 ? 0 : 1);
 }
@@ -354,7 +356,7 @@ static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stampe
         if ((size_t)x->prof_used + 1 > x->ptag.size()) x->ptag.resize(x->prof_used + 64);
         x->ptag[x->prof_used] = tag;
         // a launch that carries the events itself records nothing here
-        if (!(x->prof == 1 && (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED)))
+        if (!(x->prof == 1 && (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED || tag == 2 * OP_MXFUSED)))
             HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
     } else {
         if (!stamped) HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
@@ -493,7 +495,8 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         const int tag = prof_tag(kind, part);
         // half-sweeps timed alone (mode 1) take the kernel's own start and end
         // timestamps; other timed launches are bracketed by event records
-        const bool stamp = tag >= 0 && (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED) && part[0].first->prof == 1;
+        const bool stamp = tag >= 0 && (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED || kind == OP_MXFUSED)
+                           && part[0].first->prof == 1;
         int rc;
         if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, false))) return rc;
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -520,6 +523,11 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         }
         case OP_FUSED: {
             KLAUNCH_EV(k_hs_fused, W, dim3(W.blocks), dim3(FBLK), s, e0, e1, colour, omega);
+            for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
+            break;
+        }
+        case OP_MXFUSED: {
+            KLAUNCH_EV(k_mx_fused, W, dim3(W.blocks), dim3(FBLK), s, e0, e1, colour, (float)omega);
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
@@ -722,6 +730,7 @@ static size_t carve(const qnsch_grid *g, int nl, bool mixed, int accel, bool two
             d.cn = dbl(n); d.un = dbl(n); d.vn = dbl(n);
         }
         if (two && !mixed) { d.c2 = dbl(n); d.mu2 = dbl(n); d.p2 = dbl(n); }
+        if (two && mixed) { d.dc2 = flt(n); d.dmu2 = flt(n); d.dp2 = flt(n); }
         if (!mixed && l > 0) {
             d.fc = dbl(n); d.fmu = dbl(n); d.fp = dbl(n); d.fu = dbl(n); d.fv = dbl(n);
             d.c0 = dbl(n); d.mu0 = dbl(n); d.p0 = dbl(n); d.u0 = dbl(n); d.v0 = dbl(n);
@@ -1714,6 +1723,11 @@ int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params
     r->p = *p;
     qnsch_default_opts(&r->o);
     if (o) r->o = *o;
+    // no temporal blocking in a server: its launches merge the same sweep of
+    // many requests and so fill the device, where a fused sweep's redundant
+    // red work costs more than the launch it saves (measured on one MI355X,
+    // the served droplet stream: 5 % lower throughput with it)
+    r->o.blocking = 0;
     r->c0.assign(c0, c0 + (size_t)g->m1 * g->m2);
     r->nsteps = nsteps;
     r->dt = dt;

@@ -355,12 +355,16 @@ __device__ __forceinline__ float face_point(const LView &L, int hlf, size_t k) {
 // Coupled: the seven-unknown box of the FP64 smoother with the entries of J at
 // w^ (the face rows' dc entry multiplies the face velocity at w^), eliminated
 // the same way.
-__device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, const TileF &T, float *dunew,
-                                            float *dvnew, int i, int j, int hlf, float omega)
+// With TO set, as relax_cell: the cell at tile position (ti, tj), results
+// kept in the tile (dc, dmu, dp and the density change in place, the face
+// corrections in the fields L_NF (u) and L_NF + 1 (v)).
+template <bool TO>
+__device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, const TileF &T, float *dunew,
+                                            float *dvnew, int i, int j, int ti, int tj, int hlf, float omega)
 {
     const size_t k = (size_t)j * L.pitch + i;
     const float ih = L.inv_h, ih2 = ih * ih;
-    const int e = T.idx(i, j);
+    const int e = T.idx(ti, tj);
     const Ax a = make_ax(L, T, i, j, hlf);
     const bool cpl = P.coupled;
     const LCellAx s = lcell_sum(lcell_axis(T, a, e, ih));
@@ -375,7 +379,7 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
         const float idet = frcpf(q.Jcc * q.Jmm - q.Jcm * q.Jmc);
         const float cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
         mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
-        if (hlf == 0) {
+        if (!TO && hlf == 0) {
             L.dc[k] = cnew;
             L.dmu[k] = mnew;
         }
@@ -480,14 +484,32 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
 #pragma unroll
         for (int t = 0; t < 5; t++) acc -= ac[t] * b[t];
         const float dc = acc * icc;
-        L.dc[k] = c0 + dc;
-        L.dmu[k] = m0 + (r2 - q.Jmc * dc) * imm;
+        if (TO) {
+            T.s[L_DC * st + e] = c0 + dc;
+            T.s[L_MU * st + e] = m0 + (r2 - q.Jmc * dc) * imm;
+            T.s[L_DRS * st + e] = -P.alpha * rs * rs * (c0 + dc);
+        } else {
+            L.dc[k] = c0 + dc;
+            L.dmu[k] = m0 + (r2 - q.Jmc * dc) * imm;
+        }
+    }
+    const float dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
+    if (TO) {
+        float *fo = T.s + (L_NF + hlf) * st;
+        if (hlo) fo[e] = tq(T, a.FN, e) + omega * dl;
+        if (hhi) fo[e + a.dn] = tq(T, a.FN, e + a.dn) + omega * dh;
+        if (hlf == 0) T.s[L_P * st + e] = tq(T, L_P, e) + omega * b[4];
+        return;
     }
     float *dst = hlf ? dvnew : dunew;
-    const float dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
     if (hlo) dst[k] = tq(T, a.FN, e) + omega * dl;
     if (hhi) dst[khi] = tq(T, a.FN, e + a.dn) + omega * dh;
     if (hlf == 0) L.dp[k] = tq(T, L_P, e) + omega * b[4];
+}
+__device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, const TileF &T, float *dunew,
+                                            float *dvnew, int i, int j, int hlf, float omega)
+{
+    lrelax_cell<false>(P, L, T, dunew, dvnew, i, j, i, j, hlf, omega);
 }
 
 // residual of the correction equation r - J(w^) delta for the five equations

@@ -61,6 +61,121 @@ template <typename IT> __global__ HS_ATTR void k_mx_halfsweep_fine(IT it, int co
     mx_halfsweep_body(it, colour, omega);
 }
 
+// temporal blocking of the correction smoother: one red + black sweep per
+// launch, as k_hs_fused (the widened tile in LDS, the cell corrections from
+// one set to the other, the face corrections from buffer par to par ^ 1)
+#define MX_FUSED_FLOATS ((L_NF + 2) * FUSED_W * FUSED_H)
+static_assert(MX_FUSED_FLOATS * 4 <= 65536, "fused FP32 tile exceeds 64 KiB of LDS");
+
+__device__ __forceinline__ void mx_fused_load(const PhysF &P, const LView &L, const TileF &T)
+{
+    const int n = T.W * T.H;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        if (L.bcx) i = wrapi(i, L.m1);
+        if (L.bcy) j = wrapi(j, L.m2);
+        const TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
+        float *s = T.s + e;
+        if (q.sc == 0) {
+            for (int f = 0; f < L_NF + 2; f++) s[f * n] = 0.0f;
+            continue;
+        }
+        const float v[9] = { L.c[q.c], L.dc[q.c], L.dmu[q.c], L.dp[q.c], L.du[q.u], L.dv[q.v],
+                             L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        s[L_C * n] = v[0];
+        s[L_DC * n] = v[1];
+        s[L_MU * n] = v[2];
+        s[L_P * n] = v[3];
+        s[L_U * n] = s[L_NF * n] = signed_val(q.su, v[4]);
+        s[L_V * n] = s[(L_NF + 1) * n] = signed_val(q.sv, v[5]);
+        s[L_CN * n] = v[6];
+        s[L_UN * n] = signed_val(q.su, v[7]);
+        s[L_VN * n] = signed_val(q.sv, v[8]);
+        s[L_RN * n] = rhof(P, v[6]);
+        s[L_MV * n] = viscf(P, v[6]);
+        s[L_MOB * n] = mobf(P, v[6]);
+        const float rs = rhof(P, v[0]);
+        s[L_RS * n] = rs;
+        s[L_DRS * n] = -P.alpha * rs * rs * v[1];
+    }
+}
+// after the red pass (as fused_refresh): the new face corrections become the
+// black pass's snapshot, and the wall images follow their sources
+__device__ __forceinline__ void mx_fused_refresh(const LView &L, const TileF &T)
+{
+    const int n = T.W * T.H;
+    const float *un = T.s + L_NF * n, *vn = T.s + (L_NF + 1) * n;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
+        const bool gx = !L.bcx && (i < 0 || i >= L.m1), gy = !L.bcy && (j < 0 || j >= L.m2);
+        const int si = gx ? (i < 0 ? 0 : L.m1 - 1) : i, sj = gy ? (j < 0 ? 0 : L.m2 - 1) : j;
+        const int su = (!L.bcx && (i <= 0 || i >= L.m1)) ? 0 : (gy ? -1 : 1);
+        const int sv = (!L.bcy && (j <= 0 || j >= L.m2)) ? 0 : (gx ? -1 : 1);
+        T.s[L_U * n + e] = signed_val(su, un[T.idx(i, sj)]);
+        T.s[L_V * n + e] = signed_val(sv, vn[T.idx(si, j)]);
+        if (gx || gy) {
+            const int q = T.idx(si, sj);
+            T.s[L_DC * n + e] = T.s[L_DC * n + q];
+            T.s[L_MU * n + e] = T.s[L_MU * n + q];
+            T.s[L_P * n + e] = T.s[L_P * n + q];
+            T.s[L_DRS * n + e] = T.s[L_DRS * n + q];
+        }
+    }
+}
+template <typename IT> __global__ __launch_bounds__(FBLK) void k_mx_fused(IT it, int dir, float omega)
+{
+    __shared__ float sm[MX_FUSED_FLOATS];
+    const int k = find_item(it);
+    const Desc &d = *it.d[k];
+    if (!tile_valid(it, k, d)) return;
+    const int par = it.par[k];
+    LView L = lview_of(d, par);
+    LView O = L;
+    if (dir) {
+        L.dc = d.dc2; L.dmu = d.dmu2; L.dp = d.dp2;
+    } else {
+        O.dc = d.dc2; O.dmu = d.dmu2; O.dp = d.dp2;
+    }
+    const TileF T0 = item_tile(sm, it, k, d);
+    TileF T;
+    T.s = sm; T.i0 = T0.i0 - 2; T.j0 = T0.j0 - 2; T.W = FUSED_W; T.H = FUSED_H;
+    mx_fused_load(d.Pf, L, T);
+    __syncthreads();
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    {
+        const int lj = pr / ((TX + 4) / 2), kk = pr - lj * ((TX + 4) / 2);
+        const int tj = T0.j0 - 2 + lj;
+        const int ti = T0.i0 - 2 + 2 * kk + (tj & 1);
+        const bool in = lj < TY + 4 && (L.bcx || (ti >= 0 && ti < L.m1)) && (L.bcy || (tj >= 0 && tj < L.m2));
+        if (in) {
+            const int i = L.bcx ? wrapi(ti, L.m1) : ti, j = L.bcy ? wrapi(tj, L.m2) : tj;
+            lrelax_cell<true>(d.Pf, L, T, nullptr, nullptr, i, j, ti, tj, hlf, omega);
+        }
+    }
+    __syncthreads();
+    mx_fused_refresh(L, T);
+    __syncthreads();
+    if (threadIdx.x < TBLK) {
+        const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
+        const int j = T0.j0 + lj;
+        const int i = T0.i0 + 2 * kk + ((j + 1) & 1);
+        if (i < L.m1 && j < L.m2) lrelax_cell<false>(d.Pf, O, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, i, j, hlf, omega);
+    } else {
+        const int q = pr - TBLK / 2;
+        const int lj = q / (TX / 2), kk = q - lj * (TX / 2);
+        const int j = T0.j0 + lj;
+        const int i = T0.i0 + 2 * kk + (j & 1);
+        if (i < L.m1 && j < L.m2) {
+            const int e = T.idx(i, j), n = T.W * T.H;
+            const size_t g = (size_t)j * L.pitch + i;
+            if (hlf == 0) { O.dc[g] = T.s[L_DC * n + e]; O.dmu[g] = T.s[L_MU * n + e]; }
+            else O.dp[g] = T.s[L_P * n + e];
+        }
+    }
+}
+
 // r - J delta on the item's level, restricted to the next coarser level
 // (cells: mean of four; faces: mean of the two coincident fine faces),
 // together with the linearisation point; the coarse correction starts at 0
