@@ -51,7 +51,9 @@ def test_served_results_equal_alone(lanes):
     on one stream and spread over four: every result bit-identical to the
     same request run alone"""
     say("serving: alone vs mix, lanes", lanes)
-    fp64 = W.default_opts(1e-10)
+    # a server runs its requests without temporal blocking; the requests
+    # alone take the same options so that launches compare like with like
+    fp64 = dict(W.default_opts(1e-10), blocking=0)
     mixed = dict(fp64, precision=Q.MIXED)
     cases = mix() * 2
     opts = [mixed if k % 2 else fp64 for k in range(len(mix()))] * 2
@@ -99,7 +101,7 @@ def test_plain_and_accelerated_requests_share_a_server():
     with the acceleration, FP64 and mixed, in one server: each result
     bit-identical to the request run alone with its own options"""
     say("serving: plain and accelerated requests")
-    base = W.default_opts(1e-10)
+    base = dict(W.default_opts(1e-10), blocking=0)
     cases, opts = [], []
     for k, c in enumerate(mix()[:3]):
         for accel in (0, 2):
