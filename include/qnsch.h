@@ -148,9 +148,9 @@ typedef struct {
  * launches).  Needs a second set of
  * c, mubar, pbar per level (24 bytes per cell of every level), in mixed
  * precision of the FP32 corrections dc, dmu, dp (12 bytes), whose smoother is
- * fused the same way; primitive scheme only (ignored for the projection
- * scheme); a level with a periodic axis shorter than 19 cells keeps the
- * half-sweep launches. */
+ * fused the same way, as is the projection scheme's smoother of sec. 7.2; a
+ * level with a periodic axis shorter than 19 cells keeps the half-sweep
+ * launches. */
 
 /* Acceleration of the cycle iteration (not part of the paper, whose sec. 7.1
  * asks only for a standard FAS V-cycle; the discrete system, its root and the

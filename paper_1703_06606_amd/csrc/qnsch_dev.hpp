@@ -567,8 +567,9 @@ __device__ __forceinline__ const double *face_rhs(const Rhs &F, int hlf)
 // form c, mubar and rho(c) of the cell are also written to the tile between
 // the steps (identical values from both lanes), which no other pair of this
 // colour reads.
+template <bool TO>
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
-                              int i, int j, int hlf, double omega, double pomega);
+                              int i, int j, int ti, int tj, int hlf, double omega, double pomega);
 __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j, int hlf,
                               double &rc, double &rm, double &rp, double &rf);
 
@@ -584,8 +585,8 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
                                            double *vnew, int i, int j, int ti, int tj, int hlf, double omega,
                                            double pomega)
 {
-    if (!TO && P.scheme) {
-        relax_pair_pj(P, L, T, F, unew, vnew, i, j, hlf, omega, pomega);
+    if (P.scheme) {
+        relax_pair_pj<TO>(P, L, T, F, unew, vnew, i, j, ti, tj, hlf, omega, pomega);
         return;
     }
     const size_t k = (size_t)j * L.pitch + i;
@@ -837,12 +838,13 @@ __device__ __forceinline__ PjAx pj_axis(const Tile &T, const Ax &a, int e, doubl
 // rho^n (c - c^n)/dt, the advection at time n+1 and rho^n mubar.  The tile
 // entries of the cell (c, mubar, rho(c)) are updated after step 1; no other
 // pair of this colour reads them.
+template <bool TO>
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
-                              int i, int j, int hlf, double omega, double pomega)
+                              int i, int j, int ti, int tj, int hlf, double omega, double pomega)
 {
     const size_t k = (size_t)j * L.pitch + i;
     const double ih = L.inv_h, ih2 = ih * ih;
-    const int e = T.idx(i, j);
+    const int e = T.idx(ti, tj);
     const Ax a = make_ax(L, T, i, j, hlf);
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const int st = T.W * T.H;
@@ -891,7 +893,7 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         cnew = c0 + (Jmm * r1 - Jcm * r2) * idet;
         mnew = m0 + (Jcc * r2 - Jmc * r1) * idet;
     }
-    if (hlf == 0) {
+    if (!TO && hlf == 0) {
         L.c[k] = cnew;
         L.mu[k] = mnew;
     }
@@ -951,7 +953,11 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     }
     const double ulo = tq(T, a.FN, e) + omega * (hlf ? b[2] : b[0]);
     const double uhi = tq(T, a.FN, e + a.dn) + omega * (hlf ? b[3] : b[1]);
-    if (hlf) {
+    if (TO) {
+        double *fo = T.s + (T_NF + hlf) * st;
+        if (hlo) fo[e] = ulo;
+        if (hhi) fo[e + a.dn] = uhi;
+    } else if (hlf) {
         if (hlo) vnew[k] = ulo;
         if (hhi) vnew[khi] = uhi;
     } else {
@@ -968,7 +974,11 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double Lmu_new = s.Lmu - s.Sm * (mnew - m0), Lp_new = s.Lp - s.Sm * (pnew - p0);
     const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * Lp_new;
     const double Jp = jp + q.Jpp;
-    if (hlf == 0) L.p[k] = pnew + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+    if (hlf == 0) {
+        const double pf = pnew + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+        if (TO) T.s[T_P * st + e] = pf;
+        else L.p[k] = pf;
+    }
 }
 
 // residuals of the projection scheme's five equations attached to cell (i,j)

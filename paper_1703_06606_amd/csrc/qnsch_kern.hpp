@@ -255,7 +255,7 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it,
     __shared__ double sm[FUSED_DOUBLES];
     const int k = find_item(it);
     const Desc &d = *it.d[k];
-    if (!tile_valid(it, k, d) || d.P.scheme) return;
+    if (!tile_valid(it, k, d)) return;
     const int par = it.par[k];
     View L = view_of(d, par);
     View O = L; // where the sweep's cell results go

@@ -197,10 +197,7 @@ static int small_level(const qnsch_ctx *x)
 }
 // whether the opts give the levels a second set of cell unknowns (FP64) or
 // cell corrections (mixed precision)
-static bool two_sets(const qnsch_opts &o)
-{
-    return o.blocking > 0 && o.scheme == QNSCH_PRIMITIVE;
-}
+static bool two_sets(const qnsch_opts &o) { return o.blocking > 0; }
 // levels whose sweeps run fused (bit l): those smoothed by half-sweep
 // launches (below small), the finest one only with blocking 2, with at most
 // two tiles per compute unit, and a periodic axis at least TX + 3 (TY + 3)
