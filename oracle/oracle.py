@@ -76,6 +76,8 @@ def lib():
         L.orc_add_unknowns.argtypes = [C.c_void_p, P]
         L.orc_jvp.argtypes = [C.c_void_p, P, P]
         L.orc_material.argtypes = [C.c_void_p, C.c_double, C.c_double, P]
+        L.orc_restrict.argtypes = [C.c_void_p, C.c_int, P, P]
+        L.orc_prolong.argtypes = [C.c_void_p, C.c_int, P, P]
         _lib = L
     return _lib
 
@@ -206,6 +208,27 @@ class Oracle:
         self.set_state(*[wn.get(k) for k in ("c", "mu", "p", "u", "v")])
         self.begin_step(dt)
         self.set_state(*[w.get(k) for k in ("c", "mu", "p", "u", "v")])
+
+    def level_shape(self, l):
+        """(m2, m1) of level l"""
+        return self.m2 >> l, self.m1 >> l
+
+    def restrict(self, l, fine):
+        """the V-cycle's restriction of 5 fields of level l (shape (5, m2_l, m1_l))
+        to level l + 1"""
+        f = np.ascontiguousarray(fine, dtype=np.float64).reshape((5,) + self.level_shape(l))
+        out = np.zeros((5,) + self.level_shape(l + 1))
+        lib().orc_restrict(self.h, l, _ptr(f), _ptr(out))
+        return out
+
+    def prolong(self, l, e, fine=None):
+        """fine + P e: the V-cycle's prolongation of a correction e of level
+        l + 1 (shape (5, m2_l+1, m1_l+1)) added to 5 fields of level l"""
+        e = np.ascontiguousarray(e, dtype=np.float64).reshape((5,) + self.level_shape(l + 1))
+        out = np.zeros((5,) + self.level_shape(l)) if fine is None else \
+            np.array(fine, dtype=np.float64).reshape((5,) + self.level_shape(l))
+        lib().orc_prolong(self.h, l, _ptr(e), _ptr(out))
+        return out
 
     def jvp(self, d):
         d = np.ascontiguousarray(d, dtype=np.float64).reshape(5, self.m2, self.m1)

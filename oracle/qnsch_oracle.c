@@ -1484,6 +1484,34 @@ void orc_jvp(orc_ctx *o, const double *d, double *out)
     unperturb(o);
 }
 
+/* The grid transfers of the V-cycle between levels l and l+1, exposed for
+ * unit tests.  orc_restrict: fine = 5 fields (c, mu, p, u, v) of level l,
+ * packed m1_l*m2_l each; coarse = the same 5 fields of level l+1, as the
+ * V-cycle restricts the iterate and the residual.  orc_prolong: fine += P e
+ * for a coarse correction e (5 fields of level l+1), as the V-cycle corrects
+ * the iterate; faces that are not unknowns of level l are left unchanged. */
+void orc_restrict(const orc_ctx *o, int l, const double *fine, double *coarse)
+{
+    const Level *F = &o->lev[l], *C = &o->lev[l + 1];
+    size_t nf = (size_t)F->m1 * F->m2, nc = (size_t)C->m1 * C->m2;
+    double *f[NSTATE], *c[NSTATE];
+    for (int q = 0; q < NSTATE; q++) { f[q] = (double *)fine + q * nf; c[q] = coarse + q * nc; }
+    restrict_fields(o, F, C, f, c);
+}
+void orc_prolong(orc_ctx *o, int l, const double *e, double *fine)
+{
+    Level F = o->lev[l], C = o->lev[l + 1];
+    size_t nf = (size_t)F.m1 * F.m2, nc = (size_t)C.m1 * C.m2;
+    double *zero = zalloc(nc);
+    for (int q = 0; q < NSTATE; q++) {
+        F.f[q] = fine + q * nf;
+        C.f[q] = (double *)e + q * nc;
+        C.w0[q] = zero;
+    }
+    prolong_correct(o, &F, &C);
+    free(zero);
+}
+
 /* material laws at a pair (c1, c0), for identity checks:
  * out = {rho(c1), visc(c1), m(c1), F(c1), g(c1,c0), r(c1,c0)} */
 void orc_material(const orc_ctx *o, double c1, double c0, double out[6])

@@ -813,3 +813,327 @@ def test_failure_paths_leave_state_at_time_n():
     o.set_state(cc)
     assert o.step(c["dt"]) == OR.EDIVERGED
     assert np.array_equal(o.get_state()["c"], cc)
+
+
+# ---------------------------------------------------------------------------
+# the directional derivative orc_jvp, the checker of the FP32 linearisation of
+# the mixed-precision path (the Jacobian of the sec. 6.1 system)
+
+def _unknown_masks(grid):
+    """per field, the boolean (m2, m1) mask of the entries that are unknowns
+    (faces on walls are not: App. A.4)"""
+    m1, m2 = grid["m1"], grid["m2"]
+    mk_ = {k: np.ones((m2, m1), bool) for k in FIELDS}
+    if grid["bcx"] == W.WALL:
+        mk_["u"][:, 0] = False
+    if grid["bcy"] == W.WALL:
+        mk_["v"][0, :] = False
+    return mk_
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (1, 1)])
+def test_jvp_equals_dense_jacobian_and_central_difference(bc):
+    """J(w) d by one complex step along d (orc_jvp) equals (i) the dense
+    Jacobian built column by column, one unknown at a time, times d, and
+    (ii) a central difference of the residual along d.  A wrong mapping of the
+    direction's fields to the unknowns fails (i); a wrong sign or scale of
+    the step fails (ii)."""
+    grid = grid_(6, 8, *bc)
+    m1, m2 = grid["m1"], grid["m2"]
+    P = par_O1(rho2=3.0)
+    dt = 0.4
+    wn, w = rand_state(grid, 11), rand_state(grid, 12)
+    o = mk(grid, P)
+    o.set_time_n_and_iterate(wn, w, dt)
+    _, J = o.dense()
+    B, n = _blocks(o, grid)
+    masks = _unknown_masks(grid)
+    rng = np.random.default_rng(13)
+    d = rng.standard_normal((5, m2, m1))
+    for q, k in enumerate(FIELDS):
+        d[q][~masks[k]] = 0.0
+    jv = o.jvp(d)
+    dvec = np.zeros(n)
+    for q, k in enumerate(FIELDS):
+        dvec[B[k]] = d[q][masks[k]]
+    Jd = J @ dvec
+    scale = np.abs(Jd).max()
+    for q, k in enumerate(FIELDS):
+        assert np.abs(jv[q][masks[k]] - Jd[B[k]]).max() < 1e-12 * scale, k
+        assert (jv[q][~masks[k]] == 0.0).all()
+    # (ii): r = -N on the finest level, so J d = -(r(w + e d) - r(w - e d)) / (2 e)
+    e = 1e-6
+    rr = []
+    for s in (1.0, -1.0):
+        ws = {k: w[k] + s * e * d[q] for q, k in enumerate(FIELDS)}
+        o.set_time_n_and_iterate(wn, ws, dt)
+        rr.append(o.residual()[0])
+    cd = -(rr[0] - rr[1]) / (2 * e)
+    for q, k in enumerate(FIELDS):
+        assert np.abs(jv[q][masks[k]] - cd[q][masks[k]]).max() < 1e-7 * scale, k
+
+
+# ---------------------------------------------------------------------------
+# grid transfers of the V-cycle (reading R11: cells by the mean of the four
+# children and piecewise-constant prolongation; faces by the mean of the two
+# coincident fine faces and prolongation linear across the coarse cell,
+# constant along the face)
+
+def _centres(m1, m2, h):
+    x = (np.arange(m1) + 0.5) * h
+    y = (np.arange(m2) + 0.5) * h
+    return np.meshgrid(x, y)
+
+
+def _div(u, v, h, bcx, bcy):
+    """d_x u + d_y v of App. A.2 at every cell (east/north face of the last
+    cell: the periodic image or the wall, where the velocity is zero)"""
+    ue = np.roll(u, -1, axis=1)
+    vn = np.roll(v, -1, axis=0)
+    if bcx == W.WALL:
+        ue[:, -1] = 0.0
+    if bcy == W.WALL:
+        vn[-1, :] = 0.0
+    return (ue - u) / h + (vn - v) / h
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (1, 1)])
+def test_restriction_conserves_and_is_exact_on_linear_fields(bc):
+    grid = grid_(16, 12, *bc)
+    o = mk(grid, par_O1())
+    m1, m2, h = 16, 12, 1.0 / 16
+    H = 2 * h
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal((5, m2, m1))
+    mks = _unknown_masks(grid)
+    f[3][~mks["u"]] = 0.0
+    f[4][~mks["v"]] = 0.0
+    r = o.restrict(0, f)
+    # cells: the integral h^2 sum is conserved
+    for q in range(3):
+        assert H * H * r[q].sum() == pytest.approx(h * h * f[q].sum(), rel=1e-13, abs=1e-13)
+    # faces: the flux through every grid line of the coarse level is conserved
+    # (u through the vertical line x = I H, v through the line y = J H)
+    for I in range(m1 // 2):
+        assert H * r[3][:, I].sum() == pytest.approx(h * f[3][:, 2 * I].sum(), rel=1e-13, abs=1e-13)
+    for J in range(m2 // 2):
+        assert H * r[4][J, :].sum() == pytest.approx(h * f[4][2 * J, :].sum(), rel=1e-13, abs=1e-13)
+    # the coarse divergence of the restricted velocity is the mean of the
+    # fine divergences of the four children
+    dF = _div(f[3], f[4], h, grid["bcx"], grid["bcy"])
+    dC = _div(r[3], r[4], H, grid["bcx"], grid["bcy"])
+    dFm = 0.25 * (dF[0::2, 0::2] + dF[0::2, 1::2] + dF[1::2, 0::2] + dF[1::2, 1::2])
+    assert np.abs(dC - dFm).max() < 1e-12 * np.abs(dFm).max()
+    # fields linear in x and y sampled at their own positions restrict to
+    # the same linear field at the coarse positions
+    a, bx, by = 0.3, -1.7, 2.9
+    lin = lambda x, y: a + bx * x + by * y
+    X, Y = _centres(m1, m2, h)
+    XC, YC = _centres(m1 // 2, m2 // 2, H)
+    g = np.zeros((5, m2, m1))
+    for q in range(3):
+        g[q] = lin(X, Y)
+    g[3] = lin(X - 0.5 * h, Y)   # west faces at (i h, (j + 1/2) h)
+    g[4] = lin(X, Y - 0.5 * h)   # south faces at ((i + 1/2) h, j h)
+    r = o.restrict(0, g)
+    for q in range(3):
+        assert np.abs(r[q] - lin(XC, YC)).max() < 1e-13
+    assert np.abs(r[3] - lin(XC - 0.5 * H, YC)).max() < 1e-13
+    assert np.abs(r[4] - lin(XC, YC - 0.5 * H)).max() < 1e-13
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (1, 1)])
+def test_prolongation_exact_on_constants_and_linear_across_cells(bc):
+    grid = grid_(16, 12, *bc)
+    o = mk(grid, par_O1())
+    m1, m2, h = 16, 12, 1.0 / 16
+    H = 2 * h
+    c1, c2 = m1 // 2, m2 // 2
+    mks = _unknown_masks(grid)
+    wall_x, wall_y = grid["bcx"] == W.WALL, grid["bcy"] == W.WALL
+    # fine faces whose interpolation reaches a wall face of the coarse level
+    # (there the correction is zero): the first and last midline column / row
+    u_last = np.zeros((m2, m1), bool)
+    v_last = np.zeros((m2, m1), bool)
+    u_last[:, m1 - 1] = True
+    v_last[m2 - 1, :] = True
+    u_wall = u_last.copy()
+    v_wall = v_last.copy()
+    u_wall[:, 1] = True
+    v_wall[1, :] = True
+    # a constant correction: cells take it everywhere, faces at every unknown
+    # face that does not reach a coarse wall face
+    e = np.zeros((5, c2, c1))
+    e[:] = np.array([0.7, -1.1, 2.3, 0.4, -0.9])[:, None, None]
+    ce = e.copy()
+    if wall_x:
+        ce[3][:, 0] = 0.0
+    if wall_y:
+        ce[4][0, :] = 0.0
+    f = o.prolong(0, ce)
+    for q in range(3):
+        assert np.abs(f[q] - e[q, 0, 0]).max() == 0.0
+    um = mks["u"] & ~(u_wall & wall_x)
+    vm = mks["v"] & ~(v_wall & wall_y)
+    assert np.abs(f[3][um] - 0.4).max() < 1e-15 and np.abs(f[4][vm] + 0.9).max() < 1e-15
+    if wall_x:
+        # half of it next to a wall, whose face holds zero; the wall face
+        # itself is not an unknown
+        assert np.abs(f[3][:, [1, m1 - 1]] - 0.2).max() < 1e-15
+        assert (f[3][:, 0] == 0.0).all()
+    if wall_y:
+        assert np.abs(f[4][[1, m2 - 1], :] + 0.45).max() < 1e-15
+        assert (f[4][0, :] == 0.0).all()
+    # a face correction linear across the coarse cell (u in x, v in y) is
+    # reproduced at every fine face; along the face it is piecewise constant.
+    # Taking the west instead of the east coarse neighbour on a midline face
+    # fails here.
+    XC = np.arange(c1) * H                 # coarse u faces at x = I H
+    YC = np.arange(c2) * H                 # coarse v faces at y = J H
+    a, b = 0.25, 1.5
+    e = np.zeros((5, c2, c1))
+    e[3] = (a + b * XC)[None, :] + 0.3 * np.arange(c2)[:, None]
+    e[4] = (a - b * YC)[:, None] + 0.2 * np.arange(c1)[None, :]
+    if wall_x:
+        e[3][:, 0] = 0.0
+    if wall_y:
+        e[4][0, :] = 0.0
+    f = o.prolong(0, e)
+    xf = np.arange(m1) * h
+    yf = np.arange(m2) * h
+    jc = np.arange(m2) // 2
+    ic = np.arange(m1) // 2
+    exp_u = (a + b * xf)[None, :] + 0.3 * jc[:, None]
+    exp_v = (a - b * yf)[:, None] + 0.2 * ic[None, :]
+    sel_u = mks["u"] & ~u_last
+    sel_v = mks["v"] & ~v_last
+    if wall_x:
+        sel_u[:, 1] = False     # midline next to the west wall: its west neighbour is the wall face
+    if wall_y:
+        sel_v[1, :] = False
+    # the midline face i = 1 interpolates coarse faces 0 and 1; with a wall at
+    # face 0 it takes half of the face-1 value
+    assert np.abs(f[3][sel_u] - exp_u[sel_u]).max() < 1e-14
+    assert np.abs(f[4][sel_v] - exp_v[sel_v]).max() < 1e-14
+    if wall_x:
+        assert np.abs(f[3][:, 1] - 0.5 * e[3][jc, 1]).max() < 1e-14
+    # periodic axis: a shift of the correction by one coarse cell shifts the
+    # result by two fine cells (the wrap-around midline included)
+    rng = np.random.default_rng(22)
+    e = rng.standard_normal((5, c2, c1))
+    if wall_x:
+        e[3][:, 0] = 0.0
+    if wall_y:
+        e[4][0, :] = 0.0
+    f = o.prolong(0, e)
+    if not wall_x:
+        fs = o.prolong(0, np.roll(e, 1, axis=2))
+        assert np.array_equal(fs, np.roll(f, 2, axis=2))
+    if not wall_y:
+        fs = o.prolong(0, np.roll(e, 1, axis=1))
+        assert np.array_equal(fs, np.roll(f, 2, axis=1))
+    # restriction undoes prolongation (cells: mean of four equal children;
+    # faces: the coincident fine faces take the coarse value)
+    r = o.restrict(0, f)
+    assert np.abs(r - e).max() < 1e-14
+    # cells: restriction is a quarter of the transpose of prolongation
+    g = rng.standard_normal((5, m2, m1))
+    for q in range(3):
+        ee = np.zeros((5, c2, c1))
+        ee[q] = e[q]
+        lhs = (g[q] * o.prolong(0, ee)[q]).sum()
+        rhs = 4.0 * (o.restrict(0, g)[q] * e[q]).sum()
+        assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the parts of the dissipation (Theorem of sec. 6.1 with the norms of
+# App. A.7), each on a field where it has a closed form
+
+def _diss(grid, P, wn, w, dt):
+    o = mk(grid, P)
+    o.set_time_n_and_iterate(wn, w, dt)
+    return o, o.dissipation()
+
+
+def test_dissipation_viscous_part_on_a_shear_flow():
+    """u = U sin(2 pi y) in a periodic box, v = 0, viscosity varying in x:
+    only the vertex part of ||sqrt(mu) grad_d u||^2 is non-zero; with the
+    vertex product weighting each vertex by a quarter of each adjacent cell,
+    it is dt/Re * 2 U^2 m2 sin^2(pi h) * sum_i mu_i."""
+    m = 16
+    grid = grid_(m, m, 1, 1)
+    P = par_O1(visc1=1.0, visc2=4.0)
+    h, U, dt = 1.0 / m, 0.8, 0.05
+    X, Y = _centres(m, m, h)
+    cn = 0.5 + 0.3 * np.cos(2 * np.pi * X)
+    u = U * np.sin(2 * np.pi * Y)           # u faces sit at the cell-centre heights
+    wn = dict(c=cn, u=u)
+    w = dict(c=cn + 0.01, u=u)
+    o, D = _diss(grid, P, wn, w, dt)
+    mu_i = np.array([o.material(cn[0, i], cn[0, i])["visc"] for i in range(m)])
+    exp0 = dt / P["Re"] * 2 * U * U * m * np.sin(np.pi * h) ** 2 * mu_i.sum()
+    assert D[0] == pytest.approx(exp0, rel=1e-12)
+    assert D[1] == 0.0 and D[2] == 0.0 and D[3] == 0.0 and D[4] == 0.0
+
+
+def test_dissipation_divergence_part_on_a_compression_mode():
+    """u = U sin(2 pi x) on the west faces (x = i h), v = 0, uniform c^n:
+    d_x u = 2 U cos(2 pi (i + 1/2) h) sin(pi h) / h, so
+    ||sqrt(mu) div_d u||^2 = 2 mu U^2 m1 m2 sin^2(pi h) / h^2 and the gradient
+    part equals it (no vertex part): out[0] = 3 out[1]."""
+    m1, m2 = 16, 8
+    grid = grid_(m1, m2, 1, 1)
+    P = par_O1(visc1=1.0, visc2=4.0)
+    h, U, dt, c0 = 1.0 / m1, 0.6, 0.05, 0.35
+    X, Y = _centres(m1, m2, h)
+    u = U * np.sin(2 * np.pi * (X - 0.5 * h))
+    wn = dict(c=np.full((m2, m1), c0), u=u)
+    o, D = _diss(grid, P, wn, dict(wn), dt)
+    mu = o.material(c0, c0)["visc"]
+    exp1 = dt / (3 * P["Re"]) * 2 * mu * U * U * m1 * m2 * np.sin(np.pi * h) ** 2
+    assert D[1] == pytest.approx(exp1, rel=1e-12)
+    assert D[0] == pytest.approx(3 * exp1, rel=1e-12)
+    assert D[2] == 0.0 and D[3] == 0.0
+
+
+def test_dissipation_mobility_part_on_a_linear_chemical_potential():
+    """mubar and pbar linear in x and y with walls: mu_c = mubar + alpha pbar
+    has D_x mu_c = a + alpha b on the m1 - 1 interior x faces per row and
+    D_y mu_c = a' + alpha b' on the m2 - 1 interior y faces per column (wall
+    faces carry no flux), with the uniform mobility m(c0)."""
+    m1, m2 = 8, 12
+    grid = grid_(m1, m2, 0, 0)
+    P = par_O1(rho1=1.0, rho2=3.0)
+    al = (3.0 - 1.0) / 3.0
+    h, dt, c0 = 1.0 / m1, 0.05, 0.4
+    a, b, a2, b2 = 0.7, -0.3, -0.4, 0.9
+    X, Y = _centres(m1, m2, h)
+    wn = dict(c=np.full((m2, m1), c0))
+    w = dict(c=np.full((m2, m1), c0), mu=a * X + a2 * Y, p=b * X + b2 * Y)
+    o, D = _diss(grid, P, wn, w, dt)
+    mob = o.material(c0, c0)["mob"]
+    s = (a + al * b) ** 2 * (m1 - 1) * m2 + (a2 + al * b2) ** 2 * m1 * (m2 - 1)
+    exp2 = dt / (P["M"] * P["Pe"]) * h * h * mob * s
+    assert D[2] == pytest.approx(exp2, rel=1e-12)
+    assert D[0] == 0.0 and D[1] == 0.0 and D[3] == 0.0
+
+
+def test_dissipation_kinetic_part_on_a_uniform_velocity_change():
+    """u - u^n = du on every unknown u face, v - v^n = dv on every unknown v
+    face, density varying in x, walls: the face densities are the averages of
+    the two cells, so the x sum is the trapezoid sum of rho over each row."""
+    m1, m2 = 8, 6
+    grid = grid_(m1, m2, 0, 0)
+    P = par_O1(rho1=1.0, rho2=5.0)
+    h, dt, du, dv = 1.0 / m1, 0.05, 0.3, -0.2
+    X, Y = _centres(m1, m2, h)
+    cn = 0.2 + 0.6 * X
+    mks = _unknown_masks(grid)
+    wn = dict(c=cn)
+    w = dict(c=cn, u=np.where(mks["u"], du, 0.0), v=np.where(mks["v"], dv, 0.0))
+    o, D = _diss(grid, P, wn, w, dt)
+    rho = np.array([o.material(cn[0, i], cn[0, i])["rho"] for i in range(m1)])
+    trap = rho.sum() - 0.5 * (rho[0] + rho[-1])
+    exp3 = 0.5 * h * h * (du * du * trap * m2 + dv * dv * rho.sum() * (m2 - 1))
+    assert D[3] == pytest.approx(exp3, rel=1e-12)
