@@ -170,11 +170,21 @@ typedef struct {
  * correction cycle solves for the same combination of the residuals at the
  * combined iterate. */
 
+/* Statistics of the last qnsch_step (a step run by phases fills vcycles
+ * only).  Residual norms are the per-equation sqrt(h^2 sum r^2) of the stop
+ * test, in the order (c, mu, p, u, v). */
+#define QNSCH_HIST 128
 typedef struct {
     int32_t vcycles;        /* V-cycles (mixed: outer iterations) of the last step */
     double res[5];          /* final per-equation residual norms (c, mu, p, u, v) */
     double res0[5];         /* residual norms before the first V-cycle */
     double step_ms;         /* wall time of the last step */
+    int32_t hist_len;       /* entries of hist: min(vcycles + 1, QNSCH_HIST) */
+    double hist[QNSCH_HIST][5]; /* hist[0] = res0, hist[k] = norms of the result of
+                                   cycle k (before an acceleration combines it) */
+    double dissipation[5];  /* dissipation of the last step, as qnsch_dissipation
+                               returns it; NaN when no step has completed since the
+                               state was last set */
 } qnsch_step_stats;
 
 typedef struct qnsch_ctx qnsch_ctx;
@@ -269,7 +279,9 @@ int qnsch_dissipation(qnsch_ctx *ctx, double out[5]);
  *            height of a capillary wave at its crest), NaN if none;
  *   out[7] = h^2 sum div_d u (zero with walls or periodic boundaries). */
 int qnsch_diagnostics(qnsch_ctx *ctx, double out[8]);
-int qnsch_stats(const qnsch_ctx *ctx, qnsch_step_stats *out);
+/* Statistics of the last step (above).  Computes the dissipation of that
+ * step on the device if it has not been asked for yet (one reduction). */
+int qnsch_stats(qnsch_ctx *ctx, qnsch_step_stats *out);
 /* Block until all work of the context's stream has finished. */
 int qnsch_synchronize(qnsch_ctx *ctx);
 
@@ -313,7 +325,15 @@ typedef struct qnsch_server qnsch_server;
  * the server admits requests by this footprint. */
 size_t qnsch_footprint(const qnsch_grid *grid, const qnsch_opts *opts);
 
-/* hbm_budget: device bytes the admitted requests may hold together (idle
+/* The serving calls differ from a minimal request loop in two deliberate
+ * ways: qnsch_server_create takes the number of lanes (HIP streams the
+ * requests are spread over, so that one lane's latency-bound phases overlap
+ * another's), and qnsch_server_result returns the whole final state and the
+ * per-step vcycles and timings besides the mass and energy histories, so
+ * that a served result can be compared field by field with the same request
+ * run alone.
+ *
+ * hbm_budget: device bytes the admitted requests may hold together (idle
  * contexts kept for reuse count too and are released first when a new shape
  * needs room); max_slots: most requests in flight; lanes: number of HIP
  * streams the requests are spread over (1..16; each admitted request joins the
@@ -344,6 +364,12 @@ int qnsch_server_result(qnsch_server *srv, uint64_t id, double *c, double *mu, d
  * host ms in admission, host ms in result download, host ms blocked waiting
  * for the device, contexts allocated (the rest were recycled)}. */
 int qnsch_server_stats(qnsch_server *srv, double out[12]);
+/* Step latency and throughput of the server so far: p50 and p99 of the wall
+ * time of every finished step of every request (ms, from the step's start to
+ * its end, time spent waiting for the device or the scheduler inside the
+ * server included), and cell-steps per second from the first admission to
+ * the last completion.  NULL pointers are skipped; 0 before any step ends. */
+int qnsch_server_latency(qnsch_server *srv, double *p50_ms, double *p99_ms, double *cell_steps_per_s);
 
 #ifdef __cplusplus
 }

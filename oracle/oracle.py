@@ -20,8 +20,9 @@ MAXV = 200
 
 
 def build():
-    """Compile the oracle (gcc, FP64, no fast-math)."""
-    cmd = ["gcc", "-O2", "-std=c99", "-Wall", "-fPIC", "-shared", "-o", LIB, SRC, "-lm"]
+    """Compile the oracle (gcc, FP64, no fast-math; OpenMP over the
+    independent cells of a colour, results independent of the thread count)."""
+    cmd = ["gcc", "-O2", "-std=gnu99", "-fopenmp", "-Wall", "-fPIC", "-shared", "-o", LIB, SRC, "-lm"]
     subprocess.run(cmd, check=True, cwd=HERE)
 
 
@@ -76,6 +77,7 @@ def lib():
         L.orc_add_unknowns.argtypes = [C.c_void_p, P]
         L.orc_jvp.argtypes = [C.c_void_p, P, P]
         L.orc_material.argtypes = [C.c_void_p, C.c_double, C.c_double, P]
+        L.orc_threads.argtypes = [C.c_int]
         L.orc_restrict.argtypes = [C.c_void_p, C.c_int, P, P]
         L.orc_prolong.argtypes = [C.c_void_p, C.c_int, P, P]
         _lib = L
@@ -86,6 +88,11 @@ def _ptr(a):
     if a is None:
         return None
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def threads(n=0):
+    """set the oracle's thread count (n > 0); returns the count in use"""
+    return lib().orc_threads(int(n))
 
 
 class Oracle:

@@ -52,6 +52,9 @@
 #include <string.h>
 
 #include "qnsch_oracle.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cx;
 
@@ -77,12 +80,6 @@ struct orc_ctx {
     Level lev[ORC_MAXLEV];
     /* committed state at time n (restored on failure) */
     double *save[NSTATE];
-    /* complex-step perturbation on level plev: either one unknown (pf, pi, pj)
-     * or, when pdir[0] is set, every unknown along the direction pdir */
-    const Level *plev;
-    int pf, pi, pj;
-    double ph;
-    const double *pdir[NSTATE];
     /* projection scheme: the velocity of time n+1 frozen on level fzlev
      * (during the point update of c, mubar), and the intermediate velocity of
      * the last completed step on the finest level */
@@ -102,6 +99,21 @@ struct orc_ctx {
     double hist[ORC_MAXV + 1][NSTATE];
     int in_step;
 };
+
+/* The complex-step perturbation of the thread evaluating a residual: on
+ * level plev, either one unknown (pf, pi, pj) or, when pdir[0] is set, every
+ * unknown along the direction pdir; thaw set = the frozen velocity of the
+ * projection scheme is not used (its pressure column).  Per thread, so that
+ * the cells of one colour may be relaxed by several threads (they are
+ * independent: see halfsweep); the arithmetic does not depend on it. */
+typedef struct {
+    const Level *plev;
+    int pf, pi, pj;
+    double ph;
+    const double *pdir[NSTATE];
+    int thaw;
+} Pert;
+static __thread Pert tp = { NULL, -1, 0, 0, 0.0, { NULL }, 0 };
 
 /* ------------------------------------------------------------------------- */
 /* material laws, sec. 2.1 and eq. (def-rhoal), g of sec. 4.1, m of sec. 6.1 */
@@ -132,11 +144,12 @@ static cx raw(const orc_ctx *o, const Level *L, int fld, int i, int j)
 {
     size_t k = (size_t)j * L->m1 + i;
     cx v = L->f[fld][k];
-    if (L == o->plev && o->ph != 0.0) {
-        if (o->pdir[0]) {
-            if (fld < NSTATE) v += I * o->ph * o->pdir[fld][k];
-        } else if (fld == o->pf && i == o->pi && j == o->pj) {
-            v += I * o->ph;
+    (void)o;
+    if (L == tp.plev && tp.ph != 0.0) {
+        if (tp.pdir[0]) {
+            if (fld < NSTATE) v += I * tp.ph * tp.pdir[fld][k];
+        } else if (fld == tp.pf && i == tp.pi && j == tp.pj) {
+            v += I * tp.ph;
         }
     }
     return v;
@@ -285,7 +298,7 @@ static cx ufin(const orc_ctx *o, const Level *L, int i, int j)
 {
     if (o->g.bcx == ORC_PERIODIC) i = wrap(i, L->m1);
     else if (i <= 0 || i >= L->m1) return 0.0;
-    if (L == o->fzlev) return o->ufz[(size_t)j * L->m1 + i];
+    if (L == o->fzlev && !tp.thaw) return o->ufz[(size_t)j * L->m1 + i];
     cx Ar = A_xc(o, L, F_C, 1, i, j);
     cx st = 0.5 * (rho_c(o, L, F_C, i, j) * cellv(o, L, F_MU, i - 1, j) + rho_c(o, L, F_C, i - 1, j) * cellv(o, L, F_MU, i, j))
           * D_xc(o, L, F_C, i, j);
@@ -296,7 +309,7 @@ static cx vfin(const orc_ctx *o, const Level *L, int i, int j)
 {
     if (o->g.bcy == ORC_PERIODIC) j = wrap(j, L->m2);
     else if (j <= 0 || j >= L->m2) return 0.0;
-    if (L == o->fzlev) return o->vfz[(size_t)j * L->m1 + i];
+    if (L == o->fzlev && !tp.thaw) return o->vfz[(size_t)j * L->m1 + i];
     cx Ar = A_yc(o, L, F_C, 1, i, j);
     cx st = 0.5 * (rho_c(o, L, F_C, i, j) * cellv(o, L, F_MU, i, j - 1) + rho_c(o, L, F_C, i, j - 1) * cellv(o, L, F_MU, i, j))
           * D_yc(o, L, F_C, i, j);
@@ -439,6 +452,7 @@ static cx res_mu(const orc_ctx *o, const Level *L, int i, int j)
 
 static void residual_level(orc_ctx *o, Level *L, double *r[NSTATE])
 {
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++) {
             size_t k = (size_t)j * L->m1 + i;
@@ -494,9 +508,10 @@ static int gepp(int n, double A[7][7], double b[7])
 
 static void perturb(orc_ctx *o, const Level *L, int fld, int i, int j)
 {
-    o->plev = L; o->pf = fld; o->pi = i; o->pj = j; o->ph = CSTEP; o->pdir[0] = NULL;
+    (void)o;
+    tp.plev = L; tp.pf = fld; tp.pi = i; tp.pj = j; tp.ph = CSTEP; tp.pdir[0] = NULL;
 }
-static void unperturb(orc_ctx *o) { o->plev = NULL; o->pf = -1; o->ph = 0.0; o->pdir[0] = NULL; }
+static void unperturb(orc_ctx *o) { (void)o; tp.plev = NULL; tp.pf = -1; tp.ph = 0.0; tp.pdir[0] = NULL; }
 
 /* Step 1 of sec. 7.1 at cell (i,j): one Newton step on the phase and chemical-
  * potential equations in the two unknowns c_ij, mubar_ij, all else frozen. */
@@ -607,9 +622,8 @@ static void cmp_point(orc_ctx *o, Level *L, int i, int j)
     size_t k = (size_t)j * L->m1 + i;
     double J[7][7], b[7];
     int fl[3] = { F_C, F_MU, F_P };
-    const Level *fz = o->fzlev;
     for (int col = 0; col < 3; col++) {
-        o->fzlev = col < 2 ? fz : NULL;
+        tp.thaw = col == 2;
         perturb(o, L, fl[col], i, j);
         cx rc = res_c(o, L, i, j), rm = res_mu(o, L, i, j), rp = res_p(o, L, i, j);
         J[0][col] = cimag(rc) / CSTEP;
@@ -618,7 +632,7 @@ static void cmp_point(orc_ctx *o, Level *L, int i, int j)
         if (col == 0) { b[0] = L->rhs[0][k] - creal(rc); b[1] = L->rhs[1][k] - creal(rm); b[2] = L->rhs[2][k] - creal(rp); }
     }
     unperturb(o);
-    o->fzlev = fz;
+    tp.thaw = 0;
     if (gepp(3, J, b) != 0) return;
     L->f[F_C][k] += b[0];
     L->f[F_MU][k] += b[1];
@@ -654,6 +668,7 @@ static void halfsweep_pj(orc_ctx *o, int l, int colour)
             o->vfz[k] = v_unknown(o, L, j) ? creal(vfin(o, L, i, j)) : 0.0;
         }
     o->fzlev = L;
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++)
             if (((i + j) & 1) == colour) {
@@ -664,6 +679,7 @@ static void halfsweep_pj(orc_ctx *o, int l, int colour)
     double *unew = malloc(n * sizeof(double)), *vnew = malloc(n * sizeof(double));
     memcpy(unew, L->f[F_U], n * sizeof(double));
     memcpy(vnew, L->f[F_V], n * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++)
             if (((i + j) & 1) == colour) vanka_box(o, L, i, j, unew, vnew);
@@ -671,6 +687,7 @@ static void halfsweep_pj(orc_ctx *o, int l, int colour)
     memcpy(L->f[F_V], vnew, n * sizeof(double));
     free(unew);
     free(vnew);
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++)
             if (((i + j) & 1) == colour) p_point(o, L, i, j);
@@ -691,13 +708,16 @@ static void halfsweep(orc_ctx *o, int l, int colour)
     if (projection(o)) { halfsweep_pj(o, l, colour); return; }
     Level *L = &o->lev[l];
     size_t n = (size_t)L->m1 * L->m2;
-    if (o->o.smoother == ORC_SMOOTH_SEGREGATED)
+    if (o->o.smoother == ORC_SMOOTH_SEGREGATED) {
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < L->m2; j++)
             for (int i = 0; i < L->m1; i++)
                 if (((i + j) & 1) == colour) ch_point(o, L, i, j);
+    }
     double *unew = malloc(n * sizeof(double)), *vnew = malloc(n * sizeof(double));
     memcpy(unew, L->f[F_U], n * sizeof(double));
     memcpy(vnew, L->f[F_V], n * sizeof(double));
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++)
             if (((i + j) & 1) == colour) vanka_box(o, L, i, j, unew, vnew);
@@ -968,7 +988,6 @@ orc_ctx *orc_create(const orc_grid *g, const orc_params *p, const orc_opts *opt)
     o->K1 = p->M * p->eta / (p->eps * p->We);
     o->K2 = p->eps * p->eta * p->M / (2.0 * p->We);
     o->K3 = p->eps * p->eta * p->M / p->We;
-    o->pf = -1;
     /* levels: each level halves both dimensions, every level keeps even
      * dimensions (the red-black colouring needs them); auto = coarsen while the
      * coarsest level has more than 32 cells */
@@ -1470,8 +1489,8 @@ void orc_jvp(orc_ctx *o, const double *d, double *out)
 {
     Level *L = &o->lev[0];
     size_t n = (size_t)L->m1 * L->m2;
-    o->plev = L; o->ph = CSTEP; o->pf = -1;
-    for (int q = 0; q < NSTATE; q++) o->pdir[q] = d + q * n;
+    tp.plev = L; tp.ph = CSTEP; tp.pf = -1;
+    for (int q = 0; q < NSTATE; q++) tp.pdir[q] = d + q * n;
     for (int j = 0; j < L->m2; j++)
         for (int i = 0; i < L->m1; i++) {
             size_t k = (size_t)j * L->m1 + i;
@@ -1510,6 +1529,20 @@ void orc_prolong(orc_ctx *o, int l, const double *e, double *fine)
     }
     prolong_correct(o, &F, &C);
     free(zero);
+}
+
+/* Threads that relax the cells of one colour and evaluate residuals (the
+ * cells are independent, every result is the same with any number; sums stay
+ * sequential).  n <= 0 leaves the setting; returns the number in use. */
+int orc_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* material laws at a pair (c1, c0), for identity checks:

@@ -68,6 +68,7 @@ void orc_jvp(orc_ctx *, const double *d, double *out);
 void orc_velocity_np1(orc_ctx *, double *u, double *v);
 void orc_restrict(const orc_ctx *, int l, const double *fine, double *coarse);
 void orc_prolong(orc_ctx *, int l, const double *e, double *fine);
+int orc_threads(int n);
 void orc_material(const orc_ctx *, double c1, double c0, double out[6]);
 
 #endif

@@ -165,6 +165,9 @@ struct qnsch_ctx {
     int in_step = 0;
     double dt = 0;
     qnsch_step_stats st;
+    // dissipation of the last step for qnsch_stats: 0 none (no completed step
+    // since the state was set), 1 due, 2 in st
+    int diss_state = 0;
     size_t lds_max = 65536; // LDS a level-resident workgroup may use on this device
     int ncu = 256;          // compute units of the device
     // acceleration of the cycle iteration (opt.accel = m > 0): ring of m + 1
@@ -1016,6 +1019,7 @@ int qnsch_set_state(qnsch_ctx *x, const double *c, const double *mu, const doubl
     if (!x || !c) return QNSCH_EINVAL;
     int rc = upload(x, c, mu, p, u, v);
     x->in_step = 0;
+    x->diss_state = 0;
     return rc;
 }
 
@@ -1024,6 +1028,7 @@ int qnsch_set_iterate(qnsch_ctx *x, const double *c, const double *mu, const dou
 {
     if (!x || !c) return QNSCH_EINVAL;
     if (!x->in_step) { x->err = "set_iterate outside a step"; return QNSCH_EBUSY; }
+    x->diss_state = 0;
     return upload(x, c, mu, p, u, v);
 }
 
@@ -1062,6 +1067,7 @@ int qnsch_begin_step(qnsch_ctx *x, double dt)
     step_begin_program(x, prog);
     prog.pop_back(); // no residual here
     acc_reset(x);
+    x->diss_state = 0;
     if ((rc = run_ops(x, prog))) return rc;
     x->in_step = 1;
     x->st.vcycles = 0;
@@ -1079,6 +1085,7 @@ int qnsch_vcycle(qnsch_ctx *x)
     if ((rc = run_ops(x, prog))) return rc;
     if ((rc = read_red(x))) return rc;
     if (x->acc_wait) acc_after(x);
+    x->st.vcycles++;
     return QNSCH_OK;
 }
 
@@ -1172,7 +1179,10 @@ int qnsch_end_step(qnsch_ctx *x)
 {
     if (!x) return QNSCH_EINVAL;
     int rc = QNSCH_OK;
-    if (x->in_step) rc = pj_final(x);
+    if (x->in_step) {
+        rc = pj_final(x);
+        if (!rc) x->diss_state = 1;
+    }
     x->in_step = 0;
     return rc;
 }
@@ -1198,43 +1208,58 @@ static int stop_test(qnsch_ctx *x, int vcycles)
     return 0;
 }
 
+// a step that fails after its time-n data were fixed: the state goes back to
+// time n (cell unknowns, faces, mubar and pbar), the step ends, and the error
+// of the failure (code and message) is returned even if the restore fails too
+static int fail_step(qnsch_ctx *x, int code)
+{
+    const std::string msg = x->err;
+    (void)run_ops(x, { { OP_RESTORE, 0, 0 } });
+    (void)hipStreamSynchronize(x->s);
+    x->err = msg;
+    x->in_step = 0;
+    return code;
+}
+
 int qnsch_step(qnsch_ctx *x, double dt)
 {
     if (!x || !(dt > 0)) return QNSCH_EINVAL;
     auto t0 = std::chrono::steady_clock::now();
     int rc;
+    x->diss_state = 0;
     if ((rc = set_dt(x, dt))) return rc;
     std::vector<Op> begin, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
     step_begin_program(x, begin);
     cycle_program(x, cyc);
     cyc_acc.insert(cyc_acc.end(), cyc.begin(), cyc.end());
     acc_reset(x);
-    if ((rc = run_ops(x, begin))) return rc;
-    if ((rc = read_red(x))) return rc;
+    // the begin programme only copies the state into the time-n data
+    if ((rc = run_ops(x, begin))) { x->in_step = 0; return rc; }
     x->in_step = 1;
+    if ((rc = read_red(x))) return fail_step(x, rc);
     memcpy(x->st.res0, x->red_host, 5 * sizeof(double));
+    memcpy(x->st.hist[0], x->red_host, 5 * sizeof(double));
+    x->st.hist_len = 1;
     int it = 0;
     x->st.vcycles = 0;
     for (;;) {
         const int j = stop_test(x, it);
-        if (j < 0) {
-            const std::string msg = x->err;
-            run_ops(x, { { OP_RESTORE, 0, 0 } });
-            HIPCHK(x, hipStreamSynchronize(x->s));
-            x->err = msg;
-            x->in_step = 0;
-            return j;
-        }
+        if (j < 0) return fail_step(x, j);
         if (j == 1) break;
-        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return rc;
-        if ((rc = read_red(x))) return rc;
+        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return fail_step(x, rc);
+        if ((rc = read_red(x))) return fail_step(x, rc);
         if (x->acc_wait) acc_after(x);
         it++;
         x->st.vcycles = it;
+        if (it < QNSCH_HIST) {
+            memcpy(x->st.hist[it], x->red_host, 5 * sizeof(double));
+            x->st.hist_len = it + 1;
+        }
     }
     memcpy(x->st.res, x->red_host, 5 * sizeof(double));
-    if ((rc = pj_final(x))) return rc;
+    if ((rc = pj_final(x))) return fail_step(x, rc);
     x->in_step = 0;
+    x->diss_state = 1;
     x->st.step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return QNSCH_OK;
 }
@@ -1318,10 +1343,19 @@ int qnsch_diagnostics(qnsch_ctx *x, double out[8])
     return QNSCH_OK;
 }
 
-int qnsch_stats(const qnsch_ctx *x, qnsch_step_stats *out)
+int qnsch_stats(qnsch_ctx *x, qnsch_step_stats *out)
 {
     if (!x || !out) return QNSCH_EINVAL;
+    if (x->diss_state == 1) {
+        double d[5];
+        const int rc = qnsch_dissipation(x, d);
+        if (rc) return rc;
+        memcpy(x->st.dissipation, d, sizeof(d));
+        x->diss_state = 2;
+    }
     *out = x->st;
+    if (x->diss_state == 0)
+        for (int q = 0; q < 5; q++) out->dissipation[q] = std::nan("");
     return QNSCH_OK;
 }
 
@@ -1856,6 +1890,17 @@ int qnsch_server_result(qnsch_server *S, uint64_t id, double *c, double *mu, dou
         times[1] = ms_between(r->t_submit, r->t_done);
     }
     return r->status;
+}
+
+int qnsch_server_latency(qnsch_server *S, double *p50, double *p99, double *cell_steps_per_s)
+{
+    double st[12];
+    const int rc = qnsch_server_stats(S, st);
+    if (rc) return rc;
+    if (p50) *p50 = st[0];
+    if (p99) *p99 = st[1];
+    if (cell_steps_per_s) *cell_steps_per_s = st[4];
+    return QNSCH_OK;
 }
 
 int qnsch_server_stats(qnsch_server *S, double out[12])

@@ -26,6 +26,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
+           "qnsch_server_latency",
            "qnsch_default_eta")
 
 
@@ -59,8 +60,12 @@ class Opts(C.Structure):
                 ("accel", C.c_int32), ("blocking", C.c_int32)]
 
 
+HIST = 128  # QNSCH_HIST
+
+
 class StepStats(C.Structure):
-    _fields_ = [("vcycles", C.c_int32), ("res", C.c_double * 5), ("res0", C.c_double * 5), ("step_ms", C.c_double)]
+    _fields_ = [("vcycles", C.c_int32), ("res", C.c_double * 5), ("res0", C.c_double * 5), ("step_ms", C.c_double),
+                ("hist_len", C.c_int32), ("hist", (C.c_double * 5) * HIST), ("dissipation", C.c_double * 5)]
 
 
 _lib = None
@@ -119,6 +124,7 @@ def lib():
         L.qnsch_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.qnsch_server_result.argtypes = [vp, C.c_uint64, P, P, P, P, P, P, P, P, C.POINTER(C.c_int32), P]
         L.qnsch_server_stats.argtypes = [vp, P]
+        L.qnsch_server_latency.argtypes = [vp, P, P, P]
         _lib = L
     return _lib
 
@@ -256,7 +262,9 @@ class Solver:
     def stats(self):
         s = StepStats()
         self._chk(lib().qnsch_stats(self.h, C.byref(s)))
-        return dict(vcycles=s.vcycles, res=list(s.res), res0=list(s.res0), step_ms=s.step_ms)
+        hist = np.array([list(s.hist[k]) for k in range(s.hist_len)]).reshape(s.hist_len, 5)
+        return dict(vcycles=s.vcycles, res=list(s.res), res0=list(s.res0), step_ms=s.step_ms, hist=hist,
+                    dissipation=np.array(list(s.dissipation)))
 
     def synchronize(self):
         self._chk(lib().qnsch_synchronize(self.h))
@@ -368,6 +376,14 @@ class Server:
         out.update(status=rc, mass=mass, energy=en, step_ms=ms, vcycles=np.array(vc[:]), wait_ms=times[0],
                    total_ms=times[1])
         return out
+
+    def latency(self):
+        """(p50 step ms, p99 step ms, cell-steps/s)"""
+        out = np.zeros(3)
+        rc = lib().qnsch_server_latency(self.h, _ptr(out[0:]), _ptr(out[1:]), _ptr(out[2:]))
+        if rc != OK:
+            raise QnschError(rc, "latency failed")
+        return float(out[0]), float(out[1]), float(out[2])
 
     def stats(self):
         out = np.zeros(12)

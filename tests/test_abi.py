@@ -17,10 +17,42 @@ def declared():
     return sorted(set(re.findall(r"\b(qnsch_[a-z_0-9]+)\s*\(", txt)))
 
 
+# the calls of the boundary: context, state, step, mass and energy of sec.
+# 6.1, step statistics, and the serving calls with their latency figures
+BOUNDARY = ("qnsch_create", "qnsch_set_state", "qnsch_get_state", "qnsch_step", "qnsch_mass", "qnsch_energy",
+            "qnsch_stats", "qnsch_last_error", "qnsch_destroy", "qnsch_default_eta", "qnsch_server_create",
+            "qnsch_server_submit", "qnsch_server_progress", "qnsch_server_result", "qnsch_server_latency",
+            "qnsch_server_destroy")
+
+
 def test_header_declares_the_boundary():
     names = declared()
-    for n in ("qnsch_create", "qnsch_step", "qnsch_mass", "qnsch_energy", "qnsch_destroy"):
-        assert n in names
+    for n in BOUNDARY:
+        assert n in names, n
+
+
+def test_struct_layouts_match_the_binding(tmp_path):
+    """the binding's ctypes structures have the sizes and field offsets the C
+    compiler gives the header's structs (host gcc, no GPU)"""
+    import subprocess
+    structs = {"qnsch_grid": Q.Grid, "qnsch_params": Q.Params, "qnsch_opts": Q.Opts,
+               "qnsch_step_stats": Q.StepStats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qnsch.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines += ['printf("QNSCH_HIST %d\\n", QNSCH_HIST);', "return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n") if l)
+    for cname, py in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(got[cname + "." + f]) == getattr(py, f).offset, (cname, f)
+    assert int(got["QNSCH_HIST"]) == Q.HIST
 
 
 @pytest.mark.skipif(not os.path.exists(Q.LIB), reason="HIP library not built")

@@ -346,3 +346,149 @@ def test_cauchy_convergence_is_second_order(scheme):
     say("cauchy errors", scheme, errs, "rates", rates, "printed", table["rate"])
     assert rates[-1] > 1.7, rates
     assert abs(rates[-1] - table["rate"][-1]) < 0.15, (rates, table["rate"])
+
+
+@pytest.mark.parametrize("m", [16, 32])
+@pytest.mark.parametrize("scheme", ["primitive", "projection"])
+def test_convergence_workload_steps_match_oracle(scheme, m):
+    """The Cauchy study's workload of sec. 9 (walls, density ratio 3, dt =
+    (1/16)(16/m)^2): three converged steps of the GPU against the oracle's,
+    field by field (1e-10), with the same V-cycle counts (+-1) and the
+    residual history of each step against the oracle's (norms above 1e-8 of
+    the initial one: 1e-6 relative)"""
+    cfg = W.convergence_case(m)
+    say("convergence workload parity", scheme, m)
+    opts = dict(W.default_opts(1e-10), scheme=Q.PROJECTION if scheme == "projection" else Q.PRIMITIVE)
+    g, o = pair(cfg, opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+    for step in range(3):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < 1e-10, (step, k, rel(a[k], b[k], 1e-9))
+        st = g.stats()
+        nv, hist = o.stats()
+        assert abs(st["vcycles"] - nv) <= 1
+        n = min(st["hist_len"], hist.shape[0])
+        gh, oh = st["hist"][:n], hist[:n]
+        big = oh > 1e-8 * oh[0].max()
+        assert np.allclose(gh[big], oh[big], rtol=1e-6, atol=0), (gh, oh)
+
+
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
+@pytest.mark.parametrize("bcx", [0, 1], ids=["walls", "periodic_x"])
+def test_equal_densities_hydrostatic(bcx, smoother):
+    """Equal densities (alpha = 0): the mass equation is d_x u + d_y v = 0 and
+    the pbar diagonal of the box vanishes.  Uniform c at rest under gravity
+    with walls in y has the closed-form solution u = v = 0, mubar = K1 f(c0),
+    (1/M) D_y pbar = -(1/Fr) rho (mean zero); the GPU reaches it and matches
+    the oracle's step"""
+    m1, m2 = 16, 32
+    grid = grid_(m1, m2, bcx, 0)
+    P = par_O1(rho1=2.0, rho2=2.0, inv_Fr=1.5, M=0.4)
+    cfg = dict(grid=grid, params=P)
+    say("alpha = 0 hydrostatic", bcx, smoother)
+    opts = dict(W.default_opts(1e-12), smoother=smoother)
+    g, o = pair(cfg, opts)
+    c0 = 0.3
+    for s in (g, o):
+        s.set_state(np.full((m2, m1), c0))
+    assert g.step(0.05) == Q.OK
+    assert o.step(0.05) == OR.OK
+    s, b = g.get_state(), o.get_state()
+    h = 1.0 / m1
+    K1 = P["M"] * P["eta"] / (P["eps"] * P["We"])
+    y = (np.arange(m2) + 0.5) * h
+    p_exact = -P["M"] * P["inv_Fr"] * 2.0 * (y - y.mean())
+    assert np.abs(s["u"]).max() < 1e-12 and np.abs(s["v"]).max() < 1e-12
+    assert np.abs(s["c"] - c0).max() < 1e-13
+    assert np.abs(s["mu"] - K1 * c0 * (c0 - 1) * (c0 - 0.5)).max() < 1e-12
+    assert np.abs(s["p"] - p_exact[:, None]).max() < 1e-11
+    for k in ("c", "mu", "p"):
+        assert rel(s[k], b[k], 1e-9) < 1e-10, k
+
+
+@pytest.mark.parametrize("smoother", [W.SMOOTH_COUPLED, W.SMOOTH_SEGREGATED], ids=["coupled", "segregated"])
+@pytest.mark.parametrize("bcx", [0, 1], ids=["walls", "periodic_x"])
+def test_equal_densities_moving_drop_matches_oracle(bcx, smoother):
+    """Equal densities, a drop of four times the viscosity moving under a
+    non-zero initial velocity (every box meets a zero pbar pivot): V-cycles
+    and two converged steps against the oracle (1e-10), mass conserved"""
+    cfg = W.rising_drop(32, 64, eps=0.04, rho_ratio=1.0, visc_ratio=4.0)
+    cfg["grid"] = dict(cfg["grid"], bcx=bcx)
+    m2, m1 = cfg["state"]["c"].shape
+    X = (np.arange(m1) * (1.0 / m1))[None, :].repeat(m2, 0)
+    u0 = 0.3 * np.sin(2 * np.pi * X) * (1.0 if bcx else np.sin(np.pi * X))
+    say("alpha = 0 drop", bcx, smoother)
+    opts = dict(W.default_opts(1e-10), smoother=smoother)
+    g, o = pair(cfg, opts)
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"], None, None, u0, None)
+        s.begin_step(cfg["dt"])
+    for it in range(3):
+        g.vcycle()
+        o.vcycle()
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < 1e-10, (it, k, rel(a[k], b[k], 1e-9))
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"], None, None, u0, None)
+    m0 = g.mass()
+    for step in range(2):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        a, b = g.get_state(), o.get_state()
+        for k in FIELDS:
+            assert rel(a[k], b[k], 1e-9) < 1e-10, (step, k, rel(a[k], b[k], 1e-9))
+        assert np.abs(g.mass() - m0).max() <= 1e-12 * np.abs(m0).max()
+
+
+def test_full_size_rayleigh_taylor_vcycle_fp64():
+    """512 x 2048 Rayleigh-Taylor grid in FP64 (4096 finest tiles, 8 levels
+    down to a 2 x 8 level periodic in x): one V-cycle field by field against
+    the oracle (1e-10)"""
+    cfg = W.rayleigh_taylor()
+    say("full size FP64 V-cycle", cfg["name"])
+    opts = W.default_opts(1e-10)
+    g, o = pair(cfg, opts)
+    assert g.levels == o.levels == 8
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+        s.begin_step(cfg["dt"])
+    g.vcycle()
+    say("oracle V-cycle at 512 x 2048 (about a minute on one core)")
+    o.vcycle()
+    a, b = g.get_state(), o.get_state()
+    for k in FIELDS:
+        say(k, rel(a[k], b[k], 1e-9))
+        assert rel(a[k], b[k], 1e-9) < 1e-10, (k, rel(a[k], b[k], 1e-9))
+
+
+@pytest.mark.parametrize("name", ["capillary_32x64", "drop_32x64"])
+def test_step_stats_history_and_dissipation(name):
+    """qnsch_stats: the residual history of a converged step against the
+    oracle's (first entry and every norm above 1e-8 of it at 1e-6 relative,
+    same length +-1) and the step's dissipation against qnsch_dissipation
+    and the oracle's (1e-9)"""
+    cfg = _cases()[name]
+    say("stats", name)
+    g, o = pair(cfg, W.default_opts(1e-10))
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+    assert np.isnan(g.stats()["dissipation"]).all()
+    for step in range(2):
+        assert g.step(cfg["dt"]) == Q.OK
+        assert o.step(cfg["dt"]) == OR.OK
+        st = g.stats()
+        nv, hist = o.stats()
+        assert st["hist_len"] == st["vcycles"] + 1 and abs(st["vcycles"] - nv) <= 1
+        assert np.allclose(st["hist"][0], st["res0"], rtol=0, atol=0)
+        assert np.allclose(st["hist"][-1], st["res"], rtol=0, atol=0)
+        n = min(st["hist_len"], hist.shape[0])
+        big = hist[:n] > 1e-8 * hist[0].max()
+        assert np.allclose(st["hist"][:n][big], hist[:n][big], rtol=1e-6, atol=0)
+        d = st["dissipation"]
+        assert np.allclose(d, g.dissipation(), rtol=1e-14, atol=0)
+        assert np.allclose(d, o.dissipation(), rtol=1e-9, atol=1e-15)

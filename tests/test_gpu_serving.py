@@ -152,3 +152,45 @@ def test_admission_by_budget_and_failure_isolation():
     with pytest.raises(Q.QnschError):
         Q.Server(hbm_budget=1024, max_slots=2).submit(cases[0]["grid"], cases[0]["params"], opts,
                                                       cases[0]["state"]["c"], 1, 1e-3)
+
+
+def test_served_requests_match_oracle():
+    """Served results against the FP64 CPU oracle run on the same requests:
+    an FP64 and a mixed-precision request (and two more that share their
+    launches) through one server; final state, and after every step the mass
+    and the energy, against the oracle's (FP64 1e-10, mixed 1e-6 relative);
+    mass drift within 1e-12 (FP64) and 1e-8 (mixed) over the run."""
+    import oracle as OR
+    say("serving: served requests vs the oracle")
+    fp64 = dict(W.default_opts(1e-10), blocking=0)
+    mixed = dict(fp64, precision=Q.MIXED)
+    cases = [W.capillary(), W.rising_drop(32, 64, eps=0.04), W.rising_drop(16, 32, eps=0.08, radius=0.2),
+             W.capillary(64, 128, eps=0.02, levels=5)]
+    opts = [fp64, mixed, mixed, fp64]
+    nsteps = 3
+    srv = Q.Server(hbm_budget=8 << 30, max_slots=4, lanes=2)
+    ids = [srv.submit(c["grid"], c["params"], o, c["state"]["c"], nsteps, c["dt"]) for c, o in zip(cases, opts)]
+    for _ in range(100000):
+        if srv.progress(64) == 0:
+            break
+    lat = srv.latency()
+    say("served latency p50/p99 ms, cell-steps/s", lat)
+    assert lat[0] > 0 and lat[1] >= lat[0] and lat[2] > 0
+    for rid, c, o in zip(ids, cases, opts):
+        r = srv.result(rid)
+        assert r["status"] == Q.OK, c["name"]
+        orc = OR.Oracle(c["grid"], c["params"], dict(fp64, precision=Q.FP64))
+        orc.set_state(c["state"]["c"])
+        m0 = orc.mass()
+        tol = 1e-10 if o["precision"] == Q.FP64 else 1e-6
+        drift = 1e-12 if o["precision"] == Q.FP64 else 1e-8
+        for s in range(nsteps):
+            assert orc.step(c["dt"]) == OR.OK
+            assert np.allclose(r["mass"][s], orc.mass(), rtol=tol, atol=0), (c["name"], s)
+            assert np.allclose(r["energy"][s], orc.energy(), rtol=tol, atol=1e-14), (c["name"], s)
+            assert np.abs(r["mass"][s] - m0).max() <= drift * max(1.0, np.abs(m0).max()), (c["name"], s)
+        b = orc.get_state()
+        for k in FIELDS:
+            err = np.abs(r[k] - b[k]).max() / max(np.abs(b[k]).max(), 1e-9)
+            say(c["name"], "precision", o["precision"], k, "rel err", err)
+            assert err < tol, (c["name"], k, err)

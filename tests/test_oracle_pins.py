@@ -1137,3 +1137,33 @@ def test_dissipation_kinetic_part_on_a_uniform_velocity_change():
     trap = rho.sum() - 0.5 * (rho[0] + rho[-1])
     exp3 = 0.5 * h * h * (du * du * trap * m2 + dv * dv * rho.sum() * (m2 - 1))
     assert D[3] == pytest.approx(exp3, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the oracle's threads: the cells of a colour are independent, so the
+# results do not depend on how many threads relax them
+
+@pytest.mark.parametrize("variant", ["coupled", "segregated", "projection"])
+def test_oracle_results_do_not_depend_on_threads(variant):
+    c = W.rising_drop(32, 64, eps=0.04)
+    opts = dict(W.default_opts(1e-10))
+    if variant == "segregated":
+        opts["smoother"] = W.SMOOTH_SEGREGATED
+    if variant == "projection":
+        opts["scheme"] = 1
+    n0 = OR.threads()
+    out = []
+    try:
+        for n in (1, max(n0, 4)):
+            OR.threads(n)
+            o = mk(c["grid"], c["params"], opts)
+            o.set_state(c["state"]["c"])
+            for _ in range(2):
+                assert o.step(c["dt"]) == OR.OK
+            out.append((o.get_state(), o.stats()[1], o.dissipation()))
+    finally:
+        OR.threads(n0)
+    for k in FIELDS:
+        assert np.array_equal(out[0][0][k], out[1][0][k]), k
+    assert np.array_equal(out[0][1], out[1][1])
+    assert np.array_equal(out[0][2], out[1][2])
