@@ -371,7 +371,7 @@ def test_convergence_workload_steps_match_oracle(scheme, m):
         st = g.stats()
         nv, hist = o.stats()
         assert abs(st["vcycles"] - nv) <= 1
-        n = min(st["hist_len"], hist.shape[0])
+        n = min(st["hist"].shape[0], hist.shape[0])
         gh, oh = st["hist"][:n], hist[:n]
         big = oh > 1e-8 * oh[0].max()
         assert np.allclose(gh[big], oh[big], rtol=1e-6, atol=0), (gh, oh)
@@ -419,13 +419,20 @@ def test_equal_densities_moving_drop_matches_oracle(bcx, smoother):
     cfg = W.rising_drop(32, 64, eps=0.04, rho_ratio=1.0, visc_ratio=4.0)
     cfg["grid"] = dict(cfg["grid"], bcx=bcx)
     m2, m1 = cfg["state"]["c"].shape
-    X = (np.arange(m1) * (1.0 / m1))[None, :].repeat(m2, 0)
-    u0 = 0.3 * np.sin(2 * np.pi * X) * (1.0 if bcx else np.sin(np.pi * X))
+    h = 1.0 / m1
+    # discretely divergence-free initial velocity from a stream function at
+    # the vertices, zero on the walls: u = D_y psi, v = -D_x psi
+    xv = np.arange(m1 + 1) * h
+    yv = np.arange(m2 + 1) * h
+    fx = np.cos(2 * np.pi * xv) if bcx else np.sin(np.pi * xv) ** 2
+    psi = 0.05 * np.sin(np.pi * yv / (m2 * h))[:, None] ** 2 * fx[None, :]
+    u0 = (psi[1:, :m1] - psi[:-1, :m1]) / h
+    v0 = -(psi[:m2, 1:] - psi[:m2, :-1]) / h
     say("alpha = 0 drop", bcx, smoother)
     opts = dict(W.default_opts(1e-10), smoother=smoother)
     g, o = pair(cfg, opts)
     for s in (g, o):
-        s.set_state(cfg["state"]["c"], None, None, u0, None)
+        s.set_state(cfg["state"]["c"], None, None, u0, v0)
         s.begin_step(cfg["dt"])
     for it in range(3):
         g.vcycle()
@@ -434,7 +441,7 @@ def test_equal_densities_moving_drop_matches_oracle(bcx, smoother):
         for k in FIELDS:
             assert rel(a[k], b[k], 1e-9) < 1e-10, (it, k, rel(a[k], b[k], 1e-9))
     for s in (g, o):
-        s.set_state(cfg["state"]["c"], None, None, u0, None)
+        s.set_state(cfg["state"]["c"], None, None, u0, v0)
     m0 = g.mass()
     for step in range(2):
         assert g.step(cfg["dt"]) == Q.OK
@@ -446,14 +453,14 @@ def test_equal_densities_moving_drop_matches_oracle(bcx, smoother):
 
 
 def test_full_size_rayleigh_taylor_vcycle_fp64():
-    """512 x 2048 Rayleigh-Taylor grid in FP64 (4096 finest tiles, 8 levels
+    """512 x 2048 Rayleigh-Taylor grid in FP64 (4096 finest tiles, 9 levels
     down to a 2 x 8 level periodic in x): one V-cycle field by field against
     the oracle (1e-10)"""
     cfg = W.rayleigh_taylor()
     say("full size FP64 V-cycle", cfg["name"])
     opts = W.default_opts(1e-10)
     g, o = pair(cfg, opts)
-    assert g.levels == o.levels == 8
+    assert g.levels == o.levels == 9
     for s in (g, o):
         s.set_state(cfg["state"]["c"])
         s.begin_step(cfg["dt"])
@@ -483,10 +490,10 @@ def test_step_stats_history_and_dissipation(name):
         assert o.step(cfg["dt"]) == OR.OK
         st = g.stats()
         nv, hist = o.stats()
-        assert st["hist_len"] == st["vcycles"] + 1 and abs(st["vcycles"] - nv) <= 1
+        assert st["hist"].shape[0] == st["vcycles"] + 1 and abs(st["vcycles"] - nv) <= 1
         assert np.allclose(st["hist"][0], st["res0"], rtol=0, atol=0)
         assert np.allclose(st["hist"][-1], st["res"], rtol=0, atol=0)
-        n = min(st["hist_len"], hist.shape[0])
+        n = min(st["hist"].shape[0], hist.shape[0])
         big = hist[:n] > 1e-8 * hist[0].max()
         assert np.allclose(st["hist"][:n][big], hist[:n][big], rtol=1e-6, atol=0)
         d = st["dissipation"]
