@@ -20,13 +20,20 @@ Beside it, on the same JSON line:
              stream at 20 per second, 50 steps each, through the continuous-
              batching server in mixed precision; throughput and p50/p99 step
              latency against the same requests run one after another;
-  roofline of the finest-level half-sweep kernel (HIP events around its
-             launches in the timed region), and a per-operation breakdown of
-             one step;
-  cpu_baseline -- the FP64 CPU oracle timed on a bounded sample.
+  roofline   -- of the kernel that takes the most time in the step (by a
+             breakdown of two untimed steps, every launch between HIP
+             events), measured over the timed region by HIP events that
+             carry that kernel's own start and end, against its algorithmic
+             bytes; the same for the finest-level half-sweep; the whole
+             step's algorithmic bytes over its time;
+  capillary -- the 32 x 64 capillary wave, FP64 to 1e-10: 100 repeats of
+             one step, p50/p99 latency;
+  paper_smoother -- the droplet with the printed smoother of sec. 7.1 and
+             plain cycles;
+  cpu_baseline -- the FP64 CPU oracle on the host's cores: the capillary
+             step in full and full droplet steps.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -42,33 +49,106 @@ from paper_1703_06606_amd import workloads as W  # noqa: E402
 
 METRIC = "cell-steps/s to MG residual 1e-8, mixed vs FP64; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of one finest-level half-sweep launch per cell.  FP64: it
-# reads the five unknowns and the three time-n fields of every cell (the
-# stencils of the cells of one colour cover all cells), writes c, mubar, pbar
-# of the half of the cells it relaxes and both face velocities of every face
-# (each face belongs to one box of the colour).
-HALFSWEEP_BYTES_PER_CELL = 8 * 8 + 3 * 8 / 2 + 2 * 8
-# FP32 correction half-sweep: reads c^, the five corrections and the three
-# time-n fields of every cell, mubar^ and the three cell right-hand sides of
-# the relaxed half, u^, v^ and the two face right-hand sides of every face;
-# writes dc, dmu, dp of the relaxed half and both face corrections.
-MX_HALFSWEEP_BYTES_PER_CELL = 9 * 4 + (1 + 3) * 4 / 2 + 4 * 4 + 3 * 4 / 2 + 2 * 4
-KERNEL = "k_halfsweep_fine"
-# one fused red + black sweep of a level (temporal blocking of the finest
-# level, --blocking 2): the same reads once, every cell's c, mubar, pbar and
-# both faces written once
-FUSED_BYTES_PER_CELL = 8 * 8 + 3 * 8 + 2 * 8
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_traffic.txt")
-VALU_FILE = os.path.join(ROOT, "profiles", "k_halfsweep_fine_rising_drop_256x512_valu.txt")
+# Algorithmic bytes (what the method must move, FP64, per cell of the level
+# a launch works on).  One smoothing sweep reads the five unknowns and the
+# three time-n fields and writes the five unknowns: 13 doubles = 104 B per
+# cell; a coarse level also reads the five FAS right-hand sides: 144 B.  A
+# colour half-sweep is half a sweep (52 / 72 B).  A residual moves as much
+# as a sweep; a restriction or a prolongation about 100 B per fine cell.
+SWEEP_B = {True: 104.0, False: 144.0}      # finest level: True
+RESID_B = {True: 104.0, False: 144.0}
+TRANSFER_B = 100.0
+# FP32 correction smoother (mixed precision): per sweep it reads the
+# linearisation point (4), the five corrections, the three time-n fields
+# and the five right-hand sides and writes the five corrections, in FP32:
+# 22 floats = 88 B per cell
+MX_SWEEP_B = 88.0
+TRAFFIC_WORKLOAD = "rising_drop_256x512"
 # vector issue capacity: 256 CUs x 4 SIMDs, one wave64 VALU instruction per SIMD
 # every 4 cycles at 2.4 GHz; FP64 vector peak 78.6 TFLOP/s
 VALU_WAVE_INSTS_PER_S = 1024 * 2.4e9 / 4
 FP64_PEAK_TFLOPS = 78.6
-# the device code (kernels and the functions they inline); the host library
-# around it does not change what a kernel reads and writes
-SOURCES = [os.path.join(ROOT, "paper_1703_06606_amd", "csrc", f)
-           for f in ("qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp")]
 
+# kernel launched by each operation of the library's breakdown, on the finest
+# level and on coarser ones (the residual operations also launch the
+# reduction's finalisation and, after a cycle, the pbar shift)
+OP_KERNEL = {
+    "halfsweep": ("k_halfsweep_fine", "k_halfsweep"), "fused_sweep": ("k_hs_fused", "k_hs_fused"),
+    "smooth": ("k_coarse_solve", "k_coarse_solve"), "coarse_solve": ("k_coarse_solve", "k_coarse_solve"),
+    "restrict": ("k_restrict", "k_restrict"), "coarse_rhs": ("k_coarse_rhs", "k_coarse_rhs"),
+    "prolong": ("k_prolong", "k_prolong"), "residual": ("k_resid_norm",) * 2, "residual0": ("k_resid_norm",) * 2,
+    "residual_acc": ("k_resid_norm",) * 2, "accelerate": ("k_accel",) * 2, "begin": ("k_begin",) * 2,
+    "restrict_n": ("k_restrict_n",) * 2, "mx_halfsweep": ("k_mx_halfsweep_fine", "k_mx_halfsweep"),
+    "mx_fused_sweep": ("k_mx_fused",) * 2, "mx_smooth": ("k_mx_coarse_solve",) * 2,
+    "mx_coarse_solve": ("k_mx_coarse_solve",) * 2, "mx_restrict": ("k_mx_restrict",) * 2,
+    "mx_prolong": ("k_mx_prolong",) * 2, "mx_update": ("k_mx_update",) * 2, "mx_restrict_n": ("k_mx_restrict_n",) * 2,
+    "pj_final": ("k_pj_final",) * 2,
+}
+
+
+# kernels one operation launches (the residual reductions: the residual with
+# partial sums, their finalisation and, after a cycle, the pbar shift)
+KERNELS_PER_OP = {"residual": 3, "residual_acc": 3, "residual0": 2, "step_end": 2, "dissipation": 2,
+                  "diagnostics": 2}
+
+
+def kernel_of(op, lev):
+    k = OP_KERNEL.get(op)
+    return (k[0] if lev == 0 else k[1]) if k else op
+
+
+def class_bytes(op, lev, launches, cells, opts):
+    """algorithmic bytes of `launches` launches of operation op on level lev
+    (cells[l] = cells of level l); None for operations outside a step's
+    arithmetic"""
+    n, fine = cells[lev], lev == 0
+    if op == "halfsweep":
+        return launches * 0.5 * SWEEP_B[fine] * n
+    if op == "fused_sweep":
+        return launches * SWEEP_B[fine] * n
+    if op == "smooth":
+        # level-resident smoothing: pre- and post-smoothing launches alternate,
+        # nu1 and nu2 sweeps, the post-smoothing taking the prolongation too
+        half = launches / 2.0
+        return (half * opts["nu1"] + half * opts["nu2"]) * SWEEP_B[False] * n + half * TRANSFER_B * n
+    if op == "coarse_solve":
+        return launches * opts["nu_coarse"] * SWEEP_B[False] * n
+    if op in ("restrict", "prolong"):
+        return launches * TRANSFER_B * n
+    if op == "coarse_rhs":
+        return launches * RESID_B[False] * n
+    if op in ("residual", "residual0", "residual_acc"):
+        return launches * RESID_B[True] * n
+    if op == "accelerate":
+        return launches * 8.0 * 5 * (2 + opts.get("accel", 2)) * n
+    if op == "begin":
+        return launches * 80.0 * n
+    if op == "restrict_n":
+        return launches * 48.0 * n
+    if op == "mx_halfsweep":
+        return launches * 0.5 * MX_SWEEP_B * n
+    if op == "mx_fused_sweep":
+        return launches * MX_SWEEP_B * n
+    return None
+
+
+def level_cells(cfg, nlev):
+    return [(cfg["grid"]["m1"] >> l) * (cfg["grid"]["m2"] >> l) for l in range(nlev)]
+
+
+def kernel_table(bd, cells, opts):
+    """{kernel: {launches, ms, alg_bytes}} from a per-(operation, level)
+    breakdown; alg_bytes None if some class of it has no algorithmic count"""
+    out = {}
+    for (op, lev), (n, ms) in bd.items():
+        k = kernel_of(op, lev)
+        e = out.setdefault(k, {"launches": 0, "ms": 0.0, "alg_bytes": 0.0, "ops": set()})
+        e["launches"] += n
+        e["ms"] += ms
+        e["ops"].add(op)
+        b = class_bytes(op, lev, n, cells, opts)
+        e["alg_bytes"] = None if (b is None or e["alg_bytes"] is None) else e["alg_bytes"] + b
+    return out
 
 # depth of the acceleration of the cycle iteration for every leg (--accel)
 ACCEL = 2
@@ -84,10 +164,8 @@ def base_opts(tol):
 
 
 def source_hash():
-    h = hashlib.sha256()
-    for f in SOURCES:
-        h.update(open(f, "rb").read())
-    return h.hexdigest()[:16]
+    from paper_1703_06606_amd.build import device_source_hash
+    return device_source_hash()
 
 
 def _profile_values(path):
@@ -103,20 +181,25 @@ def _profile_values(path):
     return kv if kv.get("source_hash") == source_hash() else None
 
 
-def traffic_from_profile():
-    """HBM bytes per launch of the kernel from the committed counter summary"""
-    kv = _profile_values(TRAFFIC_FILE)
+def traffic_file(kernel):
+    return os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, TRAFFIC_WORKLOAD))
+
+
+def traffic_from_profile(kernel):
+    """HBM bytes per launch of the kernel (mean over its dispatches, every
+    level) from the committed counter summary"""
+    kv = _profile_values(traffic_file(kernel))
     try:
         return float(kv["hbm_bytes_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
 
 
-def valu_from_profile(avg_launch_us):
+def valu_from_profile(kernel, avg_launch_us):
     """vector-ALU view of the same kernel from the committed SQ counter
     summary: wave instructions per launch, the issue time they need at full
     rate, and the executed FP64 rate against the FP64 vector peak"""
-    kv = _profile_values(VALU_FILE)
+    kv = _profile_values(os.path.join(ROOT, "profiles", "%s_%s_valu.txt" % (kernel, TRAFFIC_WORKLOAD)))
     if not kv:
         return None
     try:
@@ -129,28 +212,63 @@ def valu_from_profile(avg_launch_us):
             "fp64_flops_per_launch": flops, "fp64_tflops": tf, "fp64_frac": tf / FP64_PEAK_TFLOPS}
 
 
-def cpu_baseline(cfg, opts, vcycles_per_step):
-    """The FP64 oracle as it stands, single-threaded, on a bounded sample of
-    the same workload: one residual evaluation and one V-cycle of the first
-    step, extrapolated to a step with the mean V-cycle count of the GPU run
-    (same algorithm, same count)."""
+def host_cpu():
+    """CPU model and the cores this process may run on"""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    return model, ncpu
+
+
+def cpu_baseline(c1_repeats=3, c2_steps=2):
+    """The FP64 oracle as it stands on the host's cores (its cells of a
+    colour and residuals spread over OpenMP threads, sums sequential): the
+    capillary 32 x 64 step (tol 1e-10) in full, c1_repeats times from the
+    same state, and c2_steps full steps of the 256 x 512 droplet at the
+    metric's tolerance 1e-8 from its initial state.  value: droplet
+    cell-steps/s."""
     sys.path.insert(0, os.path.join(ROOT, "oracle"))
     import oracle as OR
-    o = OR.Oracle(cfg["grid"], cfg["params"], opts)
-    o.set_state(cfg["state"]["c"])
-    o.begin_step(cfg["dt"])
+    model, ncpu = host_cpu()
+    threads = OR.threads()
+    c1 = W.capillary()
+    o = OR.Oracle(c1["grid"], c1["params"], W.default_opts(1e-10))
+    lat1, nv1 = [], []
+    for _ in range(c1_repeats):
+        o.set_state(c1["state"]["c"])
+        t0 = time.perf_counter()
+        assert o.step(c1["dt"]) == OR.OK
+        lat1.append(time.perf_counter() - t0)
+        nv1.append(o.stats()[0])
+    c2 = W.rising_drop()
+    o = OR.Oracle(c2["grid"], c2["params"], dict(W.default_opts(1e-8), accel=ACCEL))
+    o.set_state(c2["state"]["c"])
     t0 = time.perf_counter()
-    o.residual()
-    t_res = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    o.vcycle()
-    t_vc = time.perf_counter() - t0
-    t_step = t_res + vcycles_per_step * (t_vc + t_res)
-    cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
-    return {"value": cells / t_step, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "one residual (%.2f s) and one V-cycle (%.2f s) of the first %dx%d step on the FP64 C oracle, "
-                      "single thread, extrapolated to %.2f V-cycles per step (the GPU run's mean)"
-                      % (t_res, t_vc, cfg["grid"]["m1"], cfg["grid"]["m2"], vcycles_per_step)}
+    nv2 = []
+    for _ in range(c2_steps):
+        assert o.step(c2["dt"]) == OR.OK
+        nv2.append(o.stats()[0])
+    t2 = time.perf_counter() - t0
+    cells = c2["grid"]["m1"] * c2["grid"]["m2"]
+    return {"value": cells * c2_steps / t2, "unit": "cell-steps/s", "cores": threads, "kind": "oracle",
+            "cpu": model, "cpus_available": ncpu,
+            "sample": "FP64 C oracle on %d OpenMP threads of a %s (%d cpus available): %d full steps of the %dx%d "
+                      "droplet from its initial state at tol 1e-8 (%.2f s, %s V-cycles), and the capillary 32x64 "
+                      "step at tol 1e-10 in full, %d times (%s V-cycles)"
+                      % (threads, model, ncpu, c2_steps, c2["grid"]["m1"], c2["grid"]["m2"], t2, nv2, c1_repeats,
+                         nv1),
+            "capillary_32x64": {"p50_ms": 1e3 * float(np.percentile(lat1, 50)),
+                                "cell_steps_per_s": 2048 / float(np.mean(lat1))},
+            "rising_drop_256x512": {"s_per_step": t2 / c2_steps, "vcycles": nv2}}
 
 
 def note(*a):
@@ -174,20 +292,6 @@ def timed_steps(g, cfg, steps):
     return time.perf_counter() - t0, lat, nv
 
 
-def breakdown(g, cfg, steps=2):
-    """share of the step time per operation class over a few untimed steps
-    (every launch bracketed by HIP events)"""
-    g.set_state(cfg["state"]["c"])
-    g.profile(2)
-    for _ in range(steps):
-        g.step(cfg["dt"])
-    b = g.profile_breakdown()
-    g.profile(0)
-    tot = sum(ms for _, ms in b.values())
-    return {k: {"launches": n, "ms_per_step": ms / steps, "share": ms / tot}
-            for k, (n, ms) in sorted(b.items(), key=lambda kv: -kv[1][1])}
-
-
 def run_mixed(steps, tol):
     """Rayleigh-Taylor 512 x 2048: FP64 against mixed precision, same steps"""
     cfg = W.rayleigh_taylor()
@@ -207,7 +311,7 @@ def run_mixed(steps, tol):
         g.profile(0)
         m1, e1 = g.mass(), g.energy()
         res[name] = (g.get_state(), e1)
-        bpc = MX_HALFSWEEP_BYTES_PER_CELL if prec == Q.MIXED else HALFSWEEP_BYTES_PER_CELL
+        bpc = 0.5 * (MX_SWEEP_B if prec == Q.MIXED else SWEEP_B[True])
         avg_ms = kms / max(launches, 1)
         out[name] = {"cell_steps_per_s": cells * steps / el, "ms_per_step": 1e3 * el / steps,
                      "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
@@ -223,6 +327,55 @@ def run_mixed(steps, tol):
                                     for k in ("c", "mu", "p", "u", "v")}
     out["mixed_vs_fp64_rel_err"]["energy"] = float(abs(res["mixed"][1][0] - res["fp64"][1][0]) / abs(res["fp64"][1][0]))
     return out
+
+
+def run_capillary(repeats=100, warmup=3):
+    """capillary 32 x 64 (periodic in x, walls in y, 4 levels), FP64 to a
+    residual of 1e-10: the same step from the same state `repeats` times after
+    `warmup` untimed ones; latency percentiles of one step"""
+    cfg = W.capillary()
+    note("capillary:", cfg["name"], repeats, "repeats of one step")
+    g = Q.Solver(cfg["grid"], cfg["params"], base_opts(1e-10))
+    lat, nv = [], []
+    for k in range(warmup + repeats):
+        g.set_state(cfg["state"]["c"])
+        g.synchronize()
+        t0 = time.perf_counter()
+        g.step(cfg["dt"])
+        t = time.perf_counter() - t0
+        if k >= warmup:
+            lat.append(t)
+            nv.append(g.stats()["vcycles"])
+    cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
+    return {"workload": cfg["name"], "precision": "fp64", "tol": 1e-10, "levels": g.levels, "repeats": repeats,
+            "warmup": warmup, "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+            "p99_ms": 1e3 * float(np.percentile(lat, 99)), "mean_ms": 1e3 * float(np.mean(lat)),
+            "cell_steps_per_s": cells / float(np.mean(lat)), "vcycles_per_step": float(np.mean(nv))}
+
+
+def run_paper_smoother(steps, warmup, tol, primitive_value):
+    """the droplet with the smoother of sec. 7.1 as printed (the Newton step
+    on (c, mubar), then the Vanka box) and plain V-cycles (no acceleration):
+    what the coupled box and the acceleration buy"""
+    cfg = W.rising_drop()
+    cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
+    note("paper's smoother:", cfg["name"], steps, "steps")
+    g = Q.Solver(cfg["grid"], cfg["params"], dict(base_opts(tol), smoother=W.SMOOTH_SEGREGATED, accel=0))
+    g.set_state(cfg["state"]["c"])
+    for _ in range(warmup):
+        g.step(cfg["dt"])
+    g.profile(1)
+    el, lat, nv = timed_steps(g, cfg, steps)
+    launches, kms = g.profile_read()
+    g.profile(0)
+    value = cells * steps / el
+    avg_ms = kms / max(launches, 1)
+    return {"workload": cfg["name"], "smoother": "segregated (sec. 7.1)", "accel": 0, "steps": steps, "tol": tol,
+            "cell_steps_per_s": value, "ms_per_step": 1e3 * el / steps,
+            "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "vcycles_per_step": float(np.mean(nv)), "headline_speedup_over_it": primitive_value / value,
+            "finest_halfsweep_us": 1e3 * avg_ms,
+            "finest_halfsweep_GBps": 0.5 * SWEEP_B[True] * cells / (avg_ms * 1e-3) / 1e9}
 
 
 def run_projection(steps, warmup, tol, primitive_value):
@@ -426,6 +579,8 @@ def main():
     ap.add_argument("--no-projection", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-capillary", action="store_true")
+    ap.add_argument("--no-paper-smoother", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the time step of one simulation is a single-GPU "
@@ -439,40 +594,94 @@ def main():
     opts = base_opts(args.tol)
     g = Q.Solver(cfg["grid"], cfg["params"], dict(opts, precision=Q.FP64))
     cells = cfg["grid"]["m1"] * cfg["grid"]["m2"]
+    lc = level_cells(cfg, g.levels)
     copy_gbs, _ = Q.copy_probe(64 << 20, 10)  # 512 MiB copy: calibration and sanity figure
 
-    note("main:", cfg["name"], args.steps, "steps")
+    # which kernel dominates the step: every launch of two untimed steps
+    # bracketed by events, grouped by kernel
+    note("main: breakdown of", cfg["name"])
     g.set_state(cfg["state"]["c"])
     for _ in range(args.warmup):
         g.step(cfg["dt"])
-    g.profile(1)
+    g.set_state(cfg["state"]["c"])
+    g.profile(2)
+    nv_bd = []
+    for _ in range(2):
+        g.step(cfg["dt"])
+        nv_bd.append(g.stats()["vcycles"])
+    bd = g.profile_breakdown(by_level=True)
+    g.profile(0)
+    ktab = kernel_table(bd, lc, opts)
+    smoothers = [k for k in ktab if ktab[k]["alg_bytes"] is not None]
+    dominant = max(smoothers, key=lambda k: ktab[k]["ms"])
+    fine_fused = BLOCKING is not None and BLOCKING >= 2
+    finest = "k_hs_fused" if fine_fused else "k_halfsweep_fine"
+    timed_ops = sorted(ktab[dominant]["ops"] | (ktab[finest]["ops"] if finest in ktab else set()))
+
+    note("main:", cfg["name"], args.steps, "steps; launches of", dominant, "and", finest, "carry HIP events")
+    g.set_state(cfg["state"]["c"])
+    for _ in range(args.warmup):
+        g.step(cfg["dt"])
+    g.profile_ops(timed_ops)
     elapsed, lat, nv = timed_steps(g, cfg, args.steps)
-    launches, kms = g.profile_read()
+    tbd = g.profile_breakdown(by_level=True)
     g.profile(0)
     value = cells * args.steps / elapsed
-    avg_ms = kms / max(launches, 1)
-    fine_fused = BLOCKING is not None and BLOCKING >= 2
-    kernel = "k_hs_fused" if fine_fused else KERNEL
-    alg_bytes = (FUSED_BYTES_PER_CELL if fine_fused else HALFSWEEP_BYTES_PER_CELL) * cells
-    achieved = alg_bytes / (avg_ms * 1e-3) / 1e9
+    ttab = kernel_table(tbd, lc, opts)
+
+    def roof(k):
+        e = ttab[k]
+        avg_us = 1e3 * e["ms"] / e["launches"]
+        per_launch = e["alg_bytes"] / e["launches"]
+        ach = e["alg_bytes"] / (e["ms"] * 1e-3) / 1e9
+        tr = traffic_from_profile(k)
+        r = {"bound": "hbm", "kernel": k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+             "frac": ach / HBM_PEAK_GBS, "traffic": tr, "traffic_vs_algorithmic": tr / per_launch if tr else None,
+             "launches": e["launches"], "avg_launch_us": avg_us, "alg_bytes_per_launch": per_launch,
+             "levels": sorted({lev for (op, lev) in tbd if kernel_of(op, lev) == k})}
+        v = valu_from_profile(k, avg_us)
+        if v:
+            r["valu"] = v
+        return r
+
+    rf = roof(dominant)
+    rf["share_of_step"] = ktab[dominant]["ms"] / sum(e["ms"] for e in ktab.values())
+    if finest != dominant and finest in ttab:
+        rf["finest"] = roof(finest)
+    # the whole step against the same bytes: the algorithmic bytes of every
+    # operation of the two breakdown steps per V-cycle, times the timed
+    # steps' mean V-cycle count, over the timed ms_per_step
+    per_cycle = sum(e["alg_bytes"] for e in ktab.values() if e["alg_bytes"] is not None) / max(1, sum(nv_bd))
+    step_bytes = per_cycle * float(np.mean(nv))
+    ms_step = 1e3 * elapsed / args.steps
+    rf["step"] = {"alg_bytes_per_vcycle": per_cycle, "alg_bytes_per_finest_cell_per_vcycle": per_cycle / cells,
+                  "alg_bytes_per_step": step_bytes, "alg_GBps": step_bytes / (ms_step * 1e-3) / 1e9,
+                  "frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    tot = sum(e["ms"] for e in ktab.values())
+    kernels = {k: {"launches": e["launches"], "ms_per_step": e["ms"] / 2.0, "share": e["ms"] / tot,
+                   "avg_us": 1e3 * e["ms"] / e["launches"],
+                   "alg_GBps": (e["alg_bytes"] / (e["ms"] * 1e-3) / 1e9) if e["alg_bytes"] else None}
+               for k, e in sorted(ktab.items(), key=lambda kv: -kv[1]["ms"])}
     out = {
         "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["grid"]["m1"], cfg["grid"]["m2"]], "levels": g.levels,
                    "dt": cfg["dt"], "tol": args.tol, "precision": "fp64", "cycle": "V(2,2)", "accel": ACCEL,
                    "parallelism": "none"},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "vcycles_per_step": float(np.mean(nv)),
-        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None if fine_fused else traffic_from_profile(),
-                     "valu": None if fine_fused else valu_from_profile(1e3 * avg_ms),
-                     "launches": launches, "avg_launch_us": 1e3 * avg_ms,
-                     "alg_bytes_per_launch": alg_bytes},
+        "roofline": rf,
         "copy_probe_GBps": copy_gbs,
-        "step_breakdown": breakdown(g, cfg),
+        "step_breakdown": kernels,
+        "kernel_launches_per_vcycle": sum(n * KERNELS_PER_OP.get(op, 1) for (op, lev), (n, _) in bd.items())
+                                      / max(1, sum(nv_bd)),
     }
     del g
+    if not args.no_capillary:
+        out["capillary"] = run_capillary()
+    if not args.no_paper_smoother:
+        out["paper_smoother"] = run_paper_smoother(min(args.steps, 30), args.warmup, args.tol, value)
     if not args.no_projection:
         out["projection"] = run_projection(args.steps, args.warmup, args.tol, value)
     if not args.no_mixed:
@@ -485,7 +694,7 @@ def main():
                                                      args.serve_lanes, args.scale_max_vcycles)
     if not args.no_cpu_baseline:
         note("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(cfg, opts, float(np.mean(nv)))
+        out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
 
 

@@ -183,8 +183,7 @@ typedef struct {
     double hist[QNSCH_HIST][5]; /* hist[0] = res0, hist[k] = norms of the result of
                                    cycle k (before an acceleration combines it) */
     double dissipation[5];  /* dissipation of the last step, as qnsch_dissipation
-                               returns it; NaN when no step has completed since the
-                               state was last set */
+                               returned it for that step; NaN until it was asked for */
 } qnsch_step_stats;
 
 typedef struct qnsch_ctx qnsch_ctx;
@@ -279,24 +278,28 @@ int qnsch_dissipation(qnsch_ctx *ctx, double out[5]);
  *            height of a capillary wave at its crest), NaN if none;
  *   out[7] = h^2 sum div_d u (zero with walls or periodic boundaries). */
 int qnsch_diagnostics(qnsch_ctx *ctx, double out[8]);
-/* Statistics of the last step (above).  Computes the dissipation of that
- * step on the device if it has not been asked for yet (one reduction). */
+/* Statistics of the last step (above); launches nothing. */
 int qnsch_stats(qnsch_ctx *ctx, qnsch_step_stats *out);
 /* Block until all work of the context's stream has finished. */
 int qnsch_synchronize(qnsch_ctx *ctx);
 
 /* Measurement support.  qnsch_profile(ctx, mode) resets the counters and
  * times launches with HIP events on the context's stream: mode 1 every launch
- * of the finest-level half-sweep kernel (FP64, or FP32 in mixed precision;
- * the fused sweep kernel where blocking covers the finest level), mode 2
- * every launch of the step, 0 none.  qnsch_profile_read returns {finest
- * half-sweep (or fused sweep) launches, their total milliseconds}.
- * qnsch_profile_breakdown returns the number of timed operation classes and
- * writes up to cap of them: kinds[k] = 2*operation + (1 if on a coarser level
- * than the finest), out[2k] = launches, out[2k+1] = total milliseconds (the
- * operation numbering is the library's internal one; a residual or step-end
- * class includes its reduction launches). */
+ * of the finest-level smoothing kernel (FP64 half-sweep, or FP32 in mixed
+ * precision; the fused sweep kernel where blocking covers the finest level),
+ * mode 2 every launch, 0 none.  qnsch_profile_ops(ctx, op_mask) resets them
+ * and times every launch of the operations whose bit is set in op_mask (bit =
+ * the library's operation number, as in the breakdown below), on every
+ * level.  Launches timed by mode 1 or by op_mask carry the events themselves
+ * (the kernel's own start and end; an operation that launches several
+ * kernels, a residual or step-end reduction, is bracketed by event records
+ * instead); mode 2 brackets every launch.  qnsch_profile_read returns
+ * {finest smoothing launches timed, their total milliseconds}.
+ * qnsch_profile_breakdown returns the number of timed classes and writes up
+ * to cap of them: kinds[k] = 16 * operation + level, out[2k] = launches,
+ * out[2k+1] = total milliseconds. */
 int qnsch_profile(qnsch_ctx *ctx, int mode);
+int qnsch_profile_ops(qnsch_ctx *ctx, uint64_t op_mask);
 int qnsch_profile_read(qnsch_ctx *ctx, double out[2]);
 int qnsch_profile_breakdown(qnsch_ctx *ctx, int32_t *kinds, double *out, int32_t cap);
 /* Copy-kernel probe on the current device: copies n doubles reps times

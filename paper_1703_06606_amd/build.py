@@ -16,6 +16,21 @@ HIPFLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-ffp-contra
             "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
+# the device code: the kernels and the functions they inline (the host
+# library around them does not change what a kernel reads and writes)
+DEVICE_SOURCES = ["qnsch_dev.hpp", "qnsch_lin.hpp", "qnsch_kern.hpp", "qnsch_mxk.hpp"]
+
+
+def device_source_hash():
+    """short hash of the device code; profile summaries taken on other
+    device code are stale"""
+    import hashlib
+    h = hashlib.sha256()
+    for f in DEVICE_SOURCES:
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose=False):
     objs = []
     bdir = os.path.join(PKG, "_build")

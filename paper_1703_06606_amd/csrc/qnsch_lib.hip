@@ -47,6 +47,16 @@ enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, O
 struct Op {
     int kind, level, colour;
 };
+// timing tags: operation * PROF_LEVELS + level
+#define PROF_LEVELS 16
+static bool is_smoother_op(int kind) { return kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED || kind == OP_MXFUSED; }
+// operations that launch one kernel (timed by the kernel's own timestamps);
+// the reductions launch two or three
+static bool single_kernel_op(int kind)
+{
+    return !(kind == OP_NORM0 || kind == OP_NORM || kind == OP_NORMACC || kind == OP_STEPEND || kind == OP_DISSIP
+             || kind == OP_DIAG);
+}
 
 // nu sweeps of level l: one launch per colour half-sweep, or, on a coarse
 // level that fits in LDS (l >= small), all of them in one workgroup, or, on a
@@ -152,21 +162,27 @@ struct qnsch_ctx {
     hipEvent_t ev = nullptr;    // completion of the last host-read reduction
     size_t footprint = 0;
     std::string err;
-    // launch timing with HIP events on the context's stream (qnsch_profile):
-    // mode 1 the finest-level half-sweeps, mode 2 every launch, accumulated
-    // per (operation, finest or coarser level)
+    // launch timing with HIP events on the context's stream (qnsch_profile,
+    // qnsch_profile_ops): mode 1 the launches of the operations in prof_mask
+    // (on the finest level only if prof_fine_only), carrying the events
+    // themselves (the kernel's own start and end; event records around the
+    // operations that launch several kernels), mode 2 every launch between
+    // event records; accumulated per (operation, level)
     int prof = 0, prof_used = 0;
+    uint64_t prof_mask = 0;
+    bool prof_fine_only = false;
     std::vector<hipEvent_t> pev;
     std::vector<int> ptag;
     double prof_ms = 0.0;
     long prof_n = 0;
-    double tag_ms[2 * NOPS] = {};
-    long tag_n[2 * NOPS] = {};
+    double tag_ms[NOPS * PROF_LEVELS] = {};
+    long tag_n[NOPS * PROF_LEVELS] = {};
     int in_step = 0;
     double dt = 0;
     qnsch_step_stats st;
-    // dissipation of the last step for qnsch_stats: 0 none (no completed step
-    // since the state was set), 1 due, 2 in st
+    // dissipation of the last step in st: 0 no completed step since the
+    // state was set, 1 a completed step whose dissipation was not asked for
+    // yet, 2 in st (qnsch_dissipation keeps it there)
     int diss_state = 0;
     size_t lds_max = 65536; // LDS a level-resident workgroup may use on this device
     int ncu = 256;          // compute units of the device
@@ -322,7 +338,7 @@ static int prof_collect(qnsch_ctx *x)
         float ms = 0.f;
         HIPCHK(x, hipEventElapsedTime(&ms, x->pev[2 * q], x->pev[2 * q + 1]));
         const int tag = x->ptag[q];
-        if (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED || tag == 2 * OP_MXFUSED) {
+        if (is_smoother_op(tag / PROF_LEVELS) && tag % PROF_LEVELS == 0) {
             x->prof_ms += ms;
             x->prof_n++;
         }
@@ -333,31 +349,47 @@ static int prof_collect(qnsch_ctx *x)
     return QNSCH_OK;
 }
 
-// timing tag of a launch (-1: not timed): operation kind, and 1 for launches
-// on coarser levels than the finest
+// timing tag of a launch (-1: not timed)
 static int prof_tag(int kind, const std::vector<std::pair<qnsch_ctx *, int>> &part)
 {
     const qnsch_ctx *x = part[0].first;
-    if (part.size() != 1 || !x->prof) return -1;
-    const bool fine_hs = (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED || kind == OP_MXFUSED) && part[0].second == 0;
-    if (x->prof == 1 && !fine_hs) return -1;
-    return 2 * kind + (part[0].second == 0 ? 0 : 1);
+    const int l = part[0].second;
+    if (part.size() != 1 || !x->prof || l >= PROF_LEVELS) return -1;
+    if (x->prof == 1 && (!((x->prof_mask >> kind) & 1u) || (x->prof_fine_only && l != 0))) return -1;
+    return kind * PROF_LEVELS + l;
+}
+
+// timed launches whose events are kept before they are read back
+#define PROF_POOL 4096
+static int prof_grow(qnsch_ctx *x, int launches)
+{
+    for (int q = 0; q < 2 * launches; q++) {
+        hipEvent_t ev;
+        HIPCHK(x, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
+        x->pev.push_back(ev);
+    }
+    return QNSCH_OK;
 }
 
 static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stamped = false)
 {
     if (!end) {
-        if ((size_t)(2 * x->prof_used + 2) > x->pev.size())
-            for (int q = 0; q < 64; q++) {
-                hipEvent_t ev;
-                HIPCHK(x, hipEventCreateWithFlags(&ev, hipEventDisableSystemFence));
-                x->pev.push_back(ev);
+        // the pool is read back only when it is full (or the counters are
+        // read): a full pool waits for its last launch once
+        if ((size_t)(2 * x->prof_used + 2) > x->pev.size()) {
+            if (x->pev.size() >= 2 * PROF_POOL) {
+                HIPCHK(x, hipStreamSynchronize(s));
+                int rc;
+                if ((rc = prof_collect(x))) return rc;
+            } else {
+                int rc;
+                if ((rc = prof_grow(x, 64))) return rc;
             }
+        }
         if ((size_t)x->prof_used + 1 > x->ptag.size()) x->ptag.resize(x->prof_used + 64);
         x->ptag[x->prof_used] = tag;
         // a launch that carries the events itself records nothing here
-        if (!(x->prof == 1 && (tag == 2 * OP_HS || tag == 2 * OP_MXHS || tag == 2 * OP_FUSED || tag == 2 * OP_MXFUSED)))
-            HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
+        if (!stamped) HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used], s));
     } else {
         if (!stamped) HIPCHK(x, hipEventRecord(x->pev[2 * x->prof_used + 1], s));
         x->prof_used++;
@@ -466,17 +498,17 @@ static Item1 one_of(const Items &a)
     return b;
 }
 // launch kernel template K on list L (ItemList): the one-item instantiation
-// when the list has a single item
+// when the list has a single item; a timed launch (e0 set in the calling
+// scope) carries the events that take the kernel's own start and end
 #define KLAUNCH(K, L, GRID, BLOCK, LDS, ST, ...)                                                     \
     do {                                                                                           \
-        if ((L).it.n == 1) hipLaunchKernelGGL(K<Item1>, GRID, BLOCK, LDS, ST, one_of((L).it), ##__VA_ARGS__); \
+        if (e0) {                                                                                  \
+            if ((L).it.n == 1)                                                                     \
+                hipExtLaunchKernelGGL(K<Item1>, GRID, BLOCK, LDS, ST, e0, e1, 0, one_of((L).it), ##__VA_ARGS__); \
+            else hipExtLaunchKernelGGL(K<Items>, GRID, BLOCK, LDS, ST, e0, e1, 0, (L).it, ##__VA_ARGS__); \
+        } else if ((L).it.n == 1)                                                                  \
+            hipLaunchKernelGGL(K<Item1>, GRID, BLOCK, LDS, ST, one_of((L).it), ##__VA_ARGS__);     \
         else hipLaunchKernelGGL(K<Items>, GRID, BLOCK, LDS, ST, (L).it, ##__VA_ARGS__);            \
-    } while (0)
-#define KLAUNCH_EV(K, L, GRID, BLOCK, ST, E0, E1, ...)                                               \
-    do {                                                                                           \
-        if ((L).it.n == 1)                                                                         \
-            hipExtLaunchKernelGGL(K<Item1>, GRID, BLOCK, 0, ST, E0, E1, 0, one_of((L).it), ##__VA_ARGS__); \
-        else hipExtLaunchKernelGGL(K<Items>, GRID, BLOCK, 0, ST, E0, E1, 0, (L).it, ##__VA_ARGS__); \
     } while (0)
 
 // Launch one operation for a set of (context, level) entries, in lists of at
@@ -493,12 +525,11 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
         for (auto &pe : part) add_item(W, pe.first, kind, pe.second);
         const double omega = x0->opt.vanka_omega;
         const int tag = prof_tag(kind, part);
-        // half-sweeps timed alone (mode 1) take the kernel's own start and end
+        // launches timed in mode 1 take the kernel's own start and end
         // timestamps; other timed launches are bracketed by event records
-        const bool stamp = tag >= 0 && (kind == OP_HS || kind == OP_MXHS || kind == OP_FUSED || kind == OP_MXFUSED)
-                           && part[0].first->prof == 1;
+        const bool stamp = tag >= 0 && single_kernel_op(kind) && part[0].first->prof == 1;
         int rc;
-        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, false))) return rc;
+        if (tag >= 0 && (rc = prof_mark(part[0].first, s, tag, false, stamp))) return rc;
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (stamp) {
             qnsch_ctx *x = part[0].first;
@@ -511,23 +542,23 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             const dim3 gr(W.blocks), bl(TBLK);
             if (kind == OP_MXHS) {
                 if (W.all_fine)
-                    KLAUNCH_EV(k_mx_halfsweep_fine, W, gr, bl, s, e0, e1, colour, (float)omega);
-                else KLAUNCH_EV(k_mx_halfsweep, W, gr, bl, s, e0, e1, colour, (float)omega);
+                    KLAUNCH(k_mx_halfsweep_fine, W, gr, bl, 0, s, colour, (float)omega);
+                else KLAUNCH(k_mx_halfsweep, W, gr, bl, 0, s, colour, (float)omega);
             } else if (W.all_fine) {
-                KLAUNCH_EV(k_halfsweep_fine, W, gr, bl, s, e0, e1, colour, omega);
+                KLAUNCH(k_halfsweep_fine, W, gr, bl, 0, s, colour, omega);
             } else {
-                KLAUNCH_EV(k_halfsweep, W, gr, bl, s, e0, e1, colour, omega);
+                KLAUNCH(k_halfsweep, W, gr, bl, 0, s, colour, omega);
             }
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
         case OP_FUSED: {
-            KLAUNCH_EV(k_hs_fused, W, dim3(W.blocks), dim3(FBLK), s, e0, e1, colour, omega);
+            KLAUNCH(k_hs_fused, W, dim3(W.blocks), dim3(FBLK), 0, s, colour, omega);
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
         case OP_MXFUSED: {
-            KLAUNCH_EV(k_mx_fused, W, dim3(W.blocks), dim3(FBLK), s, e0, e1, colour, (float)omega);
+            KLAUNCH(k_mx_fused, W, dim3(W.blocks), dim3(FBLK), 0, s, colour, (float)omega);
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
@@ -608,7 +639,10 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             if (W.it.n == 1) {
                 AccCoef<1> G1;
                 for (int b = 0; b < 3; b++) G1.g[0][b] = G.g[0][b];
-                hipLaunchKernelGGL((k_accel<Item1, 1>), dim3(W.blocks), dim3(BLK), 0, s, one_of(W.it), G1);
+                if (e0) hipExtLaunchKernelGGL((k_accel<Item1, 1>), dim3(W.blocks), dim3(BLK), 0, s, e0, e1, 0, one_of(W.it), G1);
+                else hipLaunchKernelGGL((k_accel<Item1, 1>), dim3(W.blocks), dim3(BLK), 0, s, one_of(W.it), G1);
+            } else if (e0) {
+                hipExtLaunchKernelGGL((k_accel<Items, MAXITEMS>), dim3(W.blocks), dim3(BLK), 0, s, e0, e1, 0, W.it, G);
             } else {
                 hipLaunchKernelGGL((k_accel<Items, MAXITEMS>), dim3(W.blocks), dim3(BLK), 0, s, W.it, G);
             }
@@ -667,7 +701,7 @@ static int read_red(qnsch_ctx *x)
             break;
         }
     }
-    return prof_collect(x);
+    return QNSCH_OK;
 }
 
 static double *dalloc(qnsch_ctx *x, size_t n, int *rc)
@@ -1159,6 +1193,7 @@ int qnsch_lin_apply(qnsch_ctx *x, const double *dw, double *out)
     }
     ItemList W;
     add_item(W, x, OP_MXHS, 0);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     KLAUNCH(k_mx_linresid, W, dim3(W.blocks), dim3(TBLK), 0, x->s);
     HIPCHK(x, hipGetLastError());
     HIPCHK(x, hipMemcpyAsync(out, d.rout, 5 * n * sizeof(double), hipMemcpyDeviceToHost, x->s));
@@ -1321,6 +1356,10 @@ int qnsch_dissipation(qnsch_ctx *x, double out[5])
     out[2] = x->dt / (p.M * p.Pe) * h2 * x->red_host[2];
     out[3] = 0.5 * h2 * x->red_host[3];
     out[4] = 0.5 * h2 * x->red_host[4];
+    if (x->diss_state == 1) {
+        memcpy(x->st.dissipation, out, 5 * sizeof(double));
+        x->diss_state = 2;
+    }
     return QNSCH_OK;
 }
 
@@ -1346,15 +1385,8 @@ int qnsch_diagnostics(qnsch_ctx *x, double out[8])
 int qnsch_stats(qnsch_ctx *x, qnsch_step_stats *out)
 {
     if (!x || !out) return QNSCH_EINVAL;
-    if (x->diss_state == 1) {
-        double d[5];
-        const int rc = qnsch_dissipation(x, d);
-        if (rc) return rc;
-        memcpy(x->st.dissipation, d, sizeof(d));
-        x->diss_state = 2;
-    }
     *out = x->st;
-    if (x->diss_state == 0)
+    if (x->diss_state != 2)
         for (int q = 0; q < 5; q++) out->dissipation[q] = std::nan("");
     return QNSCH_OK;
 }
@@ -1366,20 +1398,36 @@ int qnsch_synchronize(qnsch_ctx *x)
     return QNSCH_OK;
 }
 
-int qnsch_profile(qnsch_ctx *x, int enable)
+static int profile_reset(qnsch_ctx *x, int mode, uint64_t mask, bool fine_only)
 {
-    if (!x) return QNSCH_EINVAL;
     HIPCHK(x, hipStreamSynchronize(x->s));
     int rc;
     if ((rc = prof_collect(x))) return rc;
-    x->prof = enable < 0 || enable > 2 ? 1 : enable;
+    x->prof = mode;
+    x->prof_mask = mask;
+    x->prof_fine_only = fine_only;
+    if (mode && x->pev.size() < 2 * PROF_POOL && (rc = prof_grow(x, PROF_POOL - (int)x->pev.size() / 2))) return rc;
     x->prof_ms = 0.0;
     x->prof_n = 0;
-    for (int q = 0; q < 2 * NOPS; q++) {
+    for (int q = 0; q < NOPS * PROF_LEVELS; q++) {
         x->tag_ms[q] = 0.0;
         x->tag_n[q] = 0;
     }
     return QNSCH_OK;
+}
+
+int qnsch_profile(qnsch_ctx *x, int enable)
+{
+    if (!x) return QNSCH_EINVAL;
+    const int mode = enable < 0 || enable > 2 ? 1 : enable;
+    const uint64_t smoothers = (1ull << OP_HS) | (1ull << OP_MXHS) | (1ull << OP_FUSED) | (1ull << OP_MXFUSED);
+    return profile_reset(x, mode, mode == 1 ? smoothers : 0, mode == 1);
+}
+
+int qnsch_profile_ops(qnsch_ctx *x, uint64_t op_mask)
+{
+    if (!x) return QNSCH_EINVAL;
+    return profile_reset(x, op_mask ? 1 : 0, op_mask, false);
 }
 
 int qnsch_profile_read(qnsch_ctx *x, double out[2])
@@ -1400,7 +1448,7 @@ int qnsch_profile_breakdown(qnsch_ctx *x, int32_t *kinds, double *out, int32_t c
     int rc;
     if ((rc = prof_collect(x))) return rc;
     int k = 0;
-    for (int t = 0; t < 2 * NOPS; t++) {
+    for (int t = 0; t < NOPS * PROF_LEVELS; t++) {
         if (!x->tag_n[t]) continue;
         if (k < cap) {
             kinds[k] = t;

@@ -23,7 +23,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_accelerate",
            "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy",
            "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
-           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
+           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_ops", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
            "qnsch_server_latency",
@@ -108,6 +108,7 @@ def lib():
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.qnsch_synchronize.argtypes = [vp]
         L.qnsch_profile.argtypes = [vp, C.c_int]
+        L.qnsch_profile_ops.argtypes = [vp, C.c_uint64]
         L.qnsch_profile_read.argtypes = [vp, P]
         L.qnsch_profile_breakdown.argtypes = [vp, C.POINTER(C.c_int32), P, C.c_int32]
         L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
@@ -278,10 +279,19 @@ class Solver:
         self._chk(lib().qnsch_profile_read(self.h, _ptr(out)))
         return int(out[0]), float(out[1])
 
-    def profile_breakdown(self):
-        """{operation name: (launches, ms)} of the launches timed since
-        profile(2)"""
-        cap = 2 * len(OP_NAMES)
+    def profile_ops(self, names):
+        """time every launch of the named operations (OP_NAMES) on every level,
+        with the kernels' own timestamps where an operation is one kernel"""
+        mask = 0
+        for n in names:
+            mask |= 1 << OP_NAMES.index(n)
+        self._chk(lib().qnsch_profile_ops(self.h, mask))
+
+    def profile_breakdown(self, by_level=False):
+        """launches and milliseconds timed since profile(2) or profile_ops:
+        {operation name + "_fine" or "_coarse": (launches, ms)}, or with
+        by_level {(operation name, level): (launches, ms)}"""
+        cap = 16 * len(OP_NAMES)
         kinds = (C.c_int32 * cap)()
         out = np.zeros(2 * cap)
         n = lib().qnsch_profile_breakdown(self.h, kinds, _ptr(out), cap)
@@ -290,8 +300,10 @@ class Solver:
         res = {}
         for k in range(min(n, cap)):
             t = kinds[k]
-            name = OP_NAMES[t // 2] + ("_coarse" if t % 2 else "_fine")
-            res[name] = (int(out[2 * k]), float(out[2 * k + 1]))
+            op, lev = OP_NAMES[t // 16], t % 16
+            key = (op, lev) if by_level else op + ("_coarse" if lev else "_fine")
+            a, b = res.get(key, (0, 0.0))
+            res[key] = (a + int(out[2 * k]), b + float(out[2 * k + 1]))
         return res
 
     def set_iterate(self, c, mu=None, p=None, u=None, v=None):

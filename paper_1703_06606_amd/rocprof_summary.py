@@ -1,0 +1,152 @@
+"""Summaries of rocprofv3 runs of bench.py for one kernel and workload.
+
+Reads the CSV output of three rocprofv3 runs of the same bench command
+(``--kernel-trace --stats``, ``--pmc FETCH_SIZE``, ``--pmc WRITE_SIZE``, each
+``-f csv -d <dir>``) and writes, for each named kernel:
+
+* ``<kernel>_<workload>.md``: the trace statistics of the kernel per grid
+  size (one grid size per level), the kernel's average duration over all its
+  dispatches, its HBM bytes per dispatch from the counters, and the table of
+  every kernel of the run by total time;
+* ``<kernel>_<workload>_traffic.txt``: ``hbm_bytes_per_launch`` (mean over
+  the kernel's dispatches of FETCH_SIZE and WRITE_SIZE, KiB, each scaled by
+  what the counter reads for the copy-probe kernel that bench.py runs first:
+  it reads and writes 512 MiB), and the hash of the device code the counters
+  were taken on (bench.py ignores a summary of other device code).
+
+Usage: python -m paper_1703_06606_amd.rocprof_summary --trace DIR --fetch DIR
+--write DIR --workload NAME --out DIR --command "..." KERNEL [KERNEL ...]
+"""
+import argparse
+import csv
+import glob
+import os
+import re
+import statistics
+
+from paper_1703_06606_amd.build import device_source_hash
+
+COPY_BYTES = 64 << 23  # k_copy_probe: 64 Mi doubles read and as many written
+
+
+def _rows(d, suffix):
+    out = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            out.extend(csv.DictReader(fh))
+    return out
+
+
+def _name(row):
+    return row.get("Kernel_Name") or row.get("Name") or ""
+
+
+def _match(kernel):
+    return re.compile(r"\b%s\b(?!_)" % re.escape(kernel))
+
+
+def _grid(row):
+    for k in ("Grid_Size", "Grid_Size_X"):
+        if row.get(k):
+            g = int(row[k])
+            for k2 in ("Grid_Size_Y", "Grid_Size_Z"):
+                if row.get(k2):
+                    g *= int(row[k2])
+            return g
+    return 0
+
+
+def short(name):
+    m = re.search(r"\b(k_[a-z0-9_]+)", name)
+    return m.group(1) if m else name
+
+
+def counters(d, counter):
+    """{dispatch id: (kernel name, grid, value)} of one counter"""
+    out = {}
+    for r in _rows(d, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r.get("Process_Id"), r.get("Dispatch_Id"))
+        v = float(r["Counter_Value"])
+        if key in out:
+            out[key] = (out[key][0], out[key][1], out[key][2] + v)
+        else:
+            out[key] = (_name(r), _grid(r), v)
+    return out
+
+
+def copy_scale(c, factor_bytes):
+    vals = [v for (n, g, v) in c.values() if _match("k_copy_probe").search(n)]
+    if not vals:
+        return None
+    return factor_bytes / (statistics.median(vals) * 1024.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command", action="append", default=[], help="commands that made the runs (repeatable)")
+    ap.add_argument("kernels", nargs="+")
+    a = ap.parse_args()
+    os.makedirs(a.out, exist_ok=True)
+    trace = _rows(a.trace, "kernel_trace.csv")
+    durs = {}
+    for r in trace:
+        n = _name(r)
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        durs.setdefault((short(n), _grid(r)), []).append(d)
+    fetch, write = counters(a.fetch, "FETCH_SIZE"), counters(a.write, "WRITE_SIZE")
+    fs, ws = copy_scale(fetch, COPY_BYTES), copy_scale(write, COPY_BYTES)
+    table = sorted(((k, g, len(v), statistics.mean(v), statistics.median(v), min(v), sum(v) * 1e-3)
+                    for (k, g), v in durs.items()), key=lambda t: -t[6])
+    h = device_source_hash()
+    for kern in a.kernels:
+        rx = _match(kern)
+        mine = [(g, v) for (k, g), v in durs.items() if k == kern]
+        alld = [x for _, v in mine for x in v]
+        fv = [(g, v) for (n, g, v) in fetch.values() if rx.search(n)]
+        wv = [(g, v) for (n, g, v) in write.values() if rx.search(n)]
+        lines = ["# %s, %s" % (kern, a.workload), ""]
+        lines += ["command: `%s`" % c for c in a.command]
+        lines += ["summarised by: `python -m paper_1703_06606_amd.rocprof_summary` (device code %s)" % h, ""]
+        if alld:
+            lines.append("%s over all its dispatches in the trace run: %d dispatches, average %.2f us, median %.2f us"
+                         % (kern, len(alld), statistics.mean(alld), statistics.median(alld)))
+        hbm = None
+        if fv and wv and fs and ws:
+            hbm = statistics.mean(v for _, v in fv) * 1024 * fs + statistics.mean(v for _, v in wv) * 1024 * ws
+            lines.append("HBM bytes per dispatch (mean of FETCH_SIZE x %.4f + WRITE_SIZE x %.4f over %d / %d "
+                         "dispatches, KiB -> bytes): %.0f" % (fs, ws, len(fv), len(wv), hbm))
+        lines += ["", "## %s per grid size (work-items; one per level)" % kern, "",
+                  "| grid | dispatches | avg us | median us | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|---|---|---|"]
+        for g, v in sorted(mine, key=lambda t: -t[0]):
+            f1 = [x for gg, x in fv if gg == g]
+            w1 = [x for gg, x in wv if gg == g]
+            lines.append("| %d | %d | %.2f | %.2f | %s | %s |" % (
+                g, len(v), statistics.mean(v), statistics.median(v),
+                "%.0f" % statistics.mean(f1) if f1 else "-", "%.0f" % statistics.mean(w1) if w1 else "-"))
+        lines += ["", "## every kernel of the trace run, by total time", "",
+                  "| kernel | grid | dispatches | avg us | median us | min us | total ms |", "|---|---|---|---|---|---|---|"]
+        for k, g, n, av, med, mn, tot in table:
+            lines.append("| %s | %d | %d | %.2f | %.2f | %.2f | %.3f |" % (k, g, n, av, med, mn, tot))
+        if fs and ws:
+            lines += ["", "counter calibration: k_copy_probe reads and writes %d bytes; FETCH_SIZE scale %.4f, "
+                      "WRITE_SIZE scale %.4f" % (COPY_BYTES, fs, ws)]
+        with open(os.path.join(a.out, "%s_%s.md" % (kern, a.workload)), "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        if hbm is not None:
+            with open(os.path.join(a.out, "%s_%s_traffic.txt" % (kern, a.workload)), "w") as fh:
+                fh.write("# HBM bytes per dispatch of %s on %s, mean over its dispatches (every level), FETCH_SIZE\n"
+                         "# and WRITE_SIZE copy-kernel scaled; from the runs of %s_%s.md;\n"
+                         "# valid for the device code with this hash\n" % (kern, a.workload, kern, a.workload))
+                fh.write("source_hash: %s\nhbm_bytes_per_launch: %.0f\nfetch_scale: %.4f\nwrite_scale: %.4f\n"
+                         "dispatches: %d\n" % (h, hbm, fs, ws, len(fv)))
+
+
+if __name__ == "__main__":
+    main()
