@@ -302,6 +302,28 @@ int qnsch_profile(qnsch_ctx *ctx, int mode);
 int qnsch_profile_ops(qnsch_ctx *ctx, uint64_t op_mask);
 int qnsch_profile_read(qnsch_ctx *ctx, double out[2]);
 int qnsch_profile_breakdown(qnsch_ctx *ctx, int32_t *kinds, double *out, int32_t cap);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that must not call the allocator): the residual
+ * norms of qnsch_residual for an iterate and time-n data held in the
+ * caller's device memory, without a context.  c, mu, p, u, v (the iterate)
+ * and cn, un, vn (the state at time n) are device arrays of m1*m2 doubles
+ * in the host layout above (wall faces zero); norms (host) receives the five
+ * per-equation norms sqrt(h^2 sum r^2) of r = -N(w) for the step dt.  The
+ * reduction's partial sums and the level descriptor go to a static device
+ * array of the library (about 2.6 MB on every device it runs on, held until
+ * the process ends), so the call allocates nothing; grids of more than
+ * 4194304 cells or more than 20480 tiles of 16 x 16 cells are rejected
+ * (QNSCH_EINVAL).  Runs on hip_stream (NULL: the
+ * default stream) and returns when the norms are on the host.  Calls that
+ * overlap on one device race on that array.  QNSCH_EINVAL for NULL
+ * arguments, dt <= 0 or a grid or parameters qnsch_create would reject;
+ * QNSCH_EDEVICE on a HIP error; qnsch_residual_noalloc_error() gives the
+ * message of the last failure. */
+int qnsch_residual_noalloc(const qnsch_grid *grid, const qnsch_params *params, double dt, const double *c,
+                           const double *mu, const double *p, const double *u, const double *v, const double *cn,
+                           const double *un, const double *vn, void *hip_stream, double norms[5]);
+const char *qnsch_residual_noalloc_error(void);
+
 /* Copy-kernel probe on the current device: copies n doubles reps times
  * between two buffers it allocates and frees; out = {GB/s counting read and
  * write, milliseconds per copy}. */

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -871,7 +872,9 @@ void qnsch_destroy(qnsch_ctx *x)
     delete x;
 }
 
-static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o)
+// the finest grid alone (even dimensions of at least 4, square cells,
+// boundary kinds) and the physical parameters
+static int validate_grid_params(const qnsch_grid *g, const qnsch_params *p)
 {
     if (!g || !p) return QNSCH_EINVAL;
     if (g->m1 < 4 || g->m2 < 4 || (g->m1 & 1) || (g->m2 & 1)) return QNSCH_EINVAL;
@@ -882,6 +885,12 @@ static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts
     if (!(p->rho1 > 0) || !(p->rho2 > 0) || !(p->visc1 > 0) || !(p->visc2 > 0) || !(p->Re > 0) || !(p->We > 0)
         || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
         return QNSCH_EINVAL;
+    return QNSCH_OK;
+}
+
+static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o)
+{
+    if (validate_grid_params(g, p)) return QNSCH_EINVAL;
     if (o && (o->nu1 < 0 || o->nu2 < 0 || o->nu1 >= PROLONG_FIRST || o->nu2 >= PROLONG_FIRST || o->nu_coarse < 1
               || o->max_vcycles < 0
               || (o->precision != QNSCH_FP64 && o->precision != QNSCH_MIXED)
@@ -1505,6 +1514,115 @@ int qnsch_copy_probe(size_t n, int reps, double out[2])
     (void)hipFree(a);
     (void)hipFree(b);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// residual norms without allocation.  The level descriptor, the reduction's
+// partial sums and the reduced values live in `scratch`, a static device
+// array of every device the library runs on (held until the process ends);
+// host code reaches it only through the device address hipGetSymbolAddress
+// gives for the current device.
+
+} // extern "C"
+
+#define NOALLOC_MAX_CELLS (1 << 22)
+#define NOALLOC_DESC_BYTES ((sizeof(Desc) + 255) & ~(size_t)255)
+#define NOALLOC_TILES 20480
+#define NOALLOC_BYTES (NOALLOC_DESC_BYTES + (size_t)(NOALLOC_TILES + 2) * NRED * sizeof(double))
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+// device address of `scratch` on the current device (nullptr on error)
+static char *noalloc_scratch(std::string &err)
+{
+    static std::mutex mu;
+    static char *ptr[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        err = "no current HIP device";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptr[dev] = (char *)p;
+    }
+    return ptr[dev];
+}
+
+static std::string noalloc_err;
+
+extern "C" {
+
+const char *qnsch_residual_noalloc_error(void) { return noalloc_err.c_str(); }
+
+int qnsch_residual_noalloc(const qnsch_grid *g, const qnsch_params *prm, double dt, const double *c,
+                           const double *mu, const double *p, const double *u, const double *v, const double *cn,
+                           const double *un, const double *vn, void *stream, double norms[5])
+{
+    if (!g || !prm || !c || !mu || !p || !u || !v || !cn || !un || !vn || !norms || !(dt > 0)) {
+        noalloc_err = "residual_noalloc: NULL argument or dt <= 0";
+        return QNSCH_EINVAL;
+    }
+    if (validate_grid_params(g, prm)) {
+        noalloc_err = "residual_noalloc: invalid grid or parameters";
+        return QNSCH_EINVAL;
+    }
+    if ((size_t)g->m1 * g->m2 > NOALLOC_MAX_CELLS || (size_t)tiles_x(g->m1) * tiles_y(g->m2) > NOALLOC_TILES) {
+        noalloc_err = "residual_noalloc: more than 4194304 cells or 20480 tiles of 16 x 16";
+        return QNSCH_EINVAL;
+    }
+    char *base = noalloc_scratch(noalloc_err);
+    if (!base) return QNSCH_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    const int tx = tiles_x(g->m1), ty = tiles_y(g->m2);
+    Desc d;
+    memset((void *)&d, 0, sizeof(d));
+    Phys P;
+    phys_of(prm, P);
+    P.inv_dt = 1.0 / dt;
+    P.dt = dt;
+    d.P = P;
+    d.Pf = physf_of(P);
+    d.c = (double *)c; d.mu = (double *)mu; d.p = (double *)p;
+    d.ub[0] = d.ub[1] = (double *)u;
+    d.vb[0] = d.vb[1] = (double *)v;
+    d.cn = (double *)cn; d.un = (double *)un; d.vn = (double *)vn;
+    d.m1 = g->m1; d.m2 = g->m2; d.pitch = g->m1; d.bcx = g->bc_x; d.bcy = g->bc_y;
+    d.h = g->Lx / g->m1;
+    d.inv_h = 1.0 / d.h;
+    d.finv_h = (float)d.inv_h;
+    d.partials = (double *)(base + NOALLOC_DESC_BYTES);
+    d.red = d.partials + (size_t)NOALLOC_TILES * NRED;
+    d.red_host = d.red + NRED;  // the reduced values stay on the device
+    hipError_t e = hipMemcpyAsync(base, &d, sizeof(d), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        Item1 it;
+        memset(&it, 0, sizeof(it));
+        it.n = 1;
+        it.start[0] = 0;
+        it.start[1] = tx * ty;
+        it.d[0] = (const Desc *)base;
+        it.tx[0] = tx;
+        it.acc[0] = -1;
+        hipLaunchKernelGGL(k_resid_norm<Item1>, dim3(tx * ty), dim3(TBLK), 0, s, it);
+        Item1 f = it;
+        f.start[1] = 1;
+        f.tx[0] = tx * ty;
+        hipLaunchKernelGGL(k_finalize<Item1>, dim3(1), dim3(BLK), 0, s, f, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(norms, d.red, 5 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        noalloc_err = std::string("residual_noalloc: ") + hipGetErrorString(e);
+        return QNSCH_EDEVICE;
+    }
+    return QNSCH_OK;
 }
 
 } // extern "C"

@@ -27,7 +27,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
            "qnsch_server_latency",
-           "qnsch_default_eta")
+           "qnsch_default_eta", "qnsch_residual_noalloc", "qnsch_residual_noalloc_error")
 
 
 # operation classes of qnsch_profile_breakdown, in the library's numbering
@@ -112,6 +112,9 @@ def lib():
         L.qnsch_profile_read.argtypes = [vp, P]
         L.qnsch_profile_breakdown.argtypes = [vp, C.POINTER(C.c_int32), P, C.c_int32]
         L.qnsch_copy_probe.argtypes = [C.c_size_t, C.c_int, P]
+        L.qnsch_residual_noalloc.argtypes = [C.POINTER(Grid), C.POINTER(Params), C.c_double] + [vp] * 8 + [vp, P]
+        L.qnsch_residual_noalloc_error.argtypes = []
+        L.qnsch_residual_noalloc_error.restype = C.c_char_p
         L.qnsch_footprint.argtypes = [C.POINTER(Grid), C.POINTER(Opts)]
         L.qnsch_footprint.restype = C.c_size_t
         L.qnsch_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
@@ -141,6 +144,21 @@ def copy_probe(n_doubles, reps=20):
     if rc != OK:
         raise QnschError(rc, "copy probe failed")
     return float(out[0]), float(out[1])
+
+
+def residual_noalloc(grid, params, dt, w, wn, stream=None):
+    """qnsch_residual_noalloc: the residual norms of the iterate w (device
+    pointers to c, mu, p, u, v) with the time-n data wn (device pointers to
+    c, u, v), without allocating; returns the five norms"""
+    g, p, _ = _structs(grid, params, None)
+    out = np.zeros(5)
+    ptrs = [C.c_void_p(int(w[k])) for k in ("c", "mu", "p", "u", "v")] + \
+           [C.c_void_p(int(wn[k])) for k in ("c", "u", "v")]
+    rc = lib().qnsch_residual_noalloc(C.byref(g), C.byref(p), float(dt), *ptrs,
+                                      C.c_void_p(stream) if stream else None, _ptr(out))
+    if rc != OK:
+        raise QnschError(rc, lib().qnsch_residual_noalloc_error().decode())
+    return out
 
 
 def default_eta(rho1, rho2):
