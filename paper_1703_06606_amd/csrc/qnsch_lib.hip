@@ -1665,7 +1665,8 @@ struct Req {
     int step = 0, vcycles = 0;
     std::vector<Op> prog; // operations still to issue, from pc on
     size_t pc = 0;
-    int wait = W_NONE;    // what the request's event stands for
+    int wait = W_NONE;    // what the request waits for
+    hipEvent_t gate = nullptr; // W_NORM / W_STEPEND: the event of its group's reduction
     std::chrono::steady_clock::time_point t_submit, t_admit, t_step0, t_done;
     std::vector<double> step_ms, mass, energy;
     std::vector<int> vc;
@@ -1701,7 +1702,33 @@ struct qnsch_server {
     long launches = 0, ticks = 0, created = 0;
     double host_admit_ms = 0, host_finish_ms = 0, host_wait_ms = 0;
     std::string err;
+    // one event per launched reduction, shared by the requests of its group
+    std::vector<hipEvent_t> gate_pool;
+    std::map<hipEvent_t, int> gate_users;
 };
+
+// an event for the reduction of a group of requests (from the pool)
+static hipEvent_t gate_take(qnsch_server *S)
+{
+    if (!S->gate_pool.empty()) {
+        hipEvent_t e = S->gate_pool.back();
+        S->gate_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+static void gate_release(qnsch_server *S, Req *r)
+{
+    if (!r->gate) return;
+    auto it = S->gate_users.find(r->gate);
+    if (it != S->gate_users.end() && --it->second == 0) {
+        S->gate_pool.push_back(r->gate);
+        S->gate_users.erase(it);
+    }
+    r->gate = nullptr;
+}
 
 static double ms_between(Clock::time_point a, Clock::time_point b)
 {
@@ -1823,6 +1850,7 @@ static void complete_finish(qnsch_server *S, Req *r)
 static void after_reduction(qnsch_server *S, Req *r)
 {
     qnsch_ctx *x = r->x;
+    gate_release(S, r);
     if (r->wait == W_STEPEND) { // step-end sums: record mass and energy, next step
         double m[2], e[5];
         me_from_sums(x, x->red_host, m, e);
@@ -1899,6 +1927,8 @@ void qnsch_server_destroy(qnsch_server *S)
         delete kv.second;
     }
     for (auto &kv : S->pool) qnsch_destroy(kv.second);
+    for (hipEvent_t e : S->gate_pool) (void)hipEventDestroy(e);
+    for (auto &kv : S->gate_users) (void)hipEventDestroy(kv.first);
     for (size_t l = 0; l < S->lanes.size(); l++)
         if (S->own[l]) (void)hipStreamDestroy(S->lanes[l]);
     delete S;
@@ -1966,47 +1996,69 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
             start_step(r);
             S->active.push_back(r);
         }
-        // completed events: reductions and downloads
+        // completed events: reductions (one event per group, queried once
+        // per tick) and downloads
+        std::map<hipEvent_t, bool> ready;
         for (Req *r : S->active) {
-            if (r->wait == W_NONE || hipEventQuery(r->x->ev) != hipSuccess) continue;
+            if (r->wait == W_NONE) continue;
+            hipEvent_t e = r->wait == W_DOWNLOAD ? r->x->ev : r->gate;
+            auto q = ready.find(e);
+            const bool ok = q != ready.end() ? q->second : (ready[e] = hipEventQuery(e) == hipSuccess);
+            if (!ok) continue;
             if (r->wait == W_DOWNLOAD) complete_finish(S, r);
             else after_reduction(S, r);
         }
         S->active.erase(std::remove_if(S->active.begin(), S->active.end(), done), S->active.end());
         // per lane, the largest set of ready requests with the same next
-        // operation (kind, colour, coarse sweeps, relaxation factor)
+        // operation (kind, colour, coarse sweeps, relaxation factors); the
+        // requests left out catch up while the others wait for a reduction,
+        // which keeps a lane's requests in step and its launches full
+        // (launching the largest set again and again within a tick lets it
+        // run ahead: 0.84 instead of 0.78 of the launches the requests need
+        // alone in the serving test, with the same throughput)
         typedef std::tuple<int, int, int, double, double> Key;
         bool launched = false;
         for (size_t lane = 0; lane < S->lanes.size(); lane++) {
-            std::map<Key, std::vector<Req *>> groups;
-            for (Req *r : S->active) {
-                if (r->lane != (int)lane || r->wait != W_NONE || r->pc >= r->prog.size()) continue;
-                const Op &o = r->prog[r->pc];
-                groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega, r->x->opt.coarse_omega)]
-                    .push_back(r);
-            }
-            if (groups.empty()) continue;
-            auto best = groups.begin();
-            for (auto g = groups.begin(); g != groups.end(); ++g)
-                if (g->second.size() > best->second.size()) best = g;
-            std::vector<std::pair<qnsch_ctx *, int>> items;
-            for (Req *r : best->second) items.push_back({ r->x, r->prog[r->pc].level });
-            const int kind = std::get<0>(best->first);
-            hipStream_t st = S->lanes[lane];
-            int rc = launch_op(kind, std::get<1>(best->first), items, st);
-            if (rc) {
-                S->err = items[0].first->err;
-                return rc;
-            }
-            launched = true;
-            S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
-            for (Req *r : best->second) {
-                r->pc++;
+            for (int burst = 0; burst < 1; burst++) {
+                std::map<Key, std::vector<Req *>> groups;
+                for (Req *r : S->active) {
+                    if (r->lane != (int)lane || r->wait != W_NONE || r->pc >= r->prog.size()) continue;
+                    const Op &o = r->prog[r->pc];
+                    groups[Key(o.kind, o.colour, r->x->opt.nu_coarse, r->x->opt.vanka_omega, r->x->opt.coarse_omega)]
+                        .push_back(r);
+                }
+                if (groups.empty()) break;
+                auto best = groups.begin();
+                for (auto g = groups.begin(); g != groups.end(); ++g)
+                    if (g->second.size() > best->second.size()) best = g;
+                std::vector<std::pair<qnsch_ctx *, int>> items;
+                for (Req *r : best->second) items.push_back({ r->x, r->prog[r->pc].level });
+                const int kind = std::get<0>(best->first);
+                hipStream_t st = S->lanes[lane];
+                int rc = launch_op(kind, std::get<1>(best->first), items, st);
+                if (rc) {
+                    S->err = items[0].first->err;
+                    return rc;
+                }
+                launched = true;
+                S->launches += (long)((items.size() + MAXITEMS - 1) / MAXITEMS);
+                hipEvent_t gate = nullptr;
                 if (kind == OP_NORM0 || kind == OP_NORM || kind == OP_NORMACC || kind == OP_STEPEND) {
-                    r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
-                    (void)hipEventRecord(r->x->ev, st);
-                } else if (kind == OP_RESTORE) {
-                    begin_finish(S, r, r->status);
+                    gate = gate_take(S);
+                    if (!gate || hipEventRecord(gate, st) != hipSuccess) {
+                        S->err = "event for a reduction";
+                        return QNSCH_EDEVICE;
+                    }
+                    S->gate_users[gate] = (int)best->second.size();
+                }
+                for (Req *r : best->second) {
+                    r->pc++;
+                    if (gate) {
+                        r->wait = kind == OP_STEPEND ? W_STEPEND : W_NORM;
+                        r->gate = gate;
+                    } else if (kind == OP_RESTORE) {
+                        begin_finish(S, r, r->status);
+                    }
                 }
             }
         }
@@ -2017,7 +2069,7 @@ int qnsch_server_progress(qnsch_server *S, int32_t max_ticks)
             const auto t0 = Clock::now();
             for (Req *r : S->active)
                 if (r->wait != W_NONE) {
-                    (void)hipEventSynchronize(r->x->ev);
+                    (void)hipEventSynchronize(r->wait == W_DOWNLOAD ? r->x->ev : r->gate);
                     break;
                 }
             S->host_wait_ms += ms_between(t0, Clock::now());

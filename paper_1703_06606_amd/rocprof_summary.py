@@ -91,7 +91,9 @@ def main():
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", action="append", default=[], help="commands that made the runs (repeatable)")
-    ap.add_argument("kernels", nargs="+")
+    ap.add_argument("--busy-tail", type=float, default=0.0,
+                    help="also report the share of the last SECONDS of kernel activity in which some kernel ran")
+    ap.add_argument("kernels", nargs="*")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
     trace = _rows(a.trace, "kernel_trace.csv")
@@ -100,6 +102,29 @@ def main():
         n = _name(r)
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
         durs.setdefault((short(n), _grid(r)), []).append(d)
+    if a.busy_tail > 0:
+        iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in trace)
+        t1 = max(e for _, e in iv)
+        t0 = t1 - int(a.busy_tail * 1e9)
+        busy, cur_s, cur_e = 0, None, None
+        for s0, e0 in iv:
+            s0, e0 = max(s0, t0), min(e0, t1)
+            if e0 <= s0:
+                continue
+            if cur_e is None or s0 > cur_e:
+                if cur_e is not None:
+                    busy += cur_e - cur_s
+                cur_s, cur_e = s0, e0
+            else:
+                cur_e = max(cur_e, e0)
+        if cur_e is not None:
+            busy += cur_e - cur_s
+        n = sum(1 for s0, e0 in iv if e0 > t0)
+        with open(os.path.join(a.out, "busy_%s.txt" % a.workload), "w") as fh:
+            fh.write("# share of the last %.3f s of kernel activity in which at least one kernel ran\n"
+                     "window_s: %.3f\ndispatches_in_window: %d\nbusy_fraction: %.4f\n" % (a.busy_tail, a.busy_tail, n, busy / (t1 - t0)))
+    if not a.kernels:
+        return
     fetch, write = counters(a.fetch, "FETCH_SIZE"), counters(a.write, "WRITE_SIZE")
     fs, ws = copy_scale(fetch, COPY_BYTES), copy_scale(write, COPY_BYTES)
     table = sorted(((k, g, len(v), statistics.mean(v), statistics.median(v), min(v), sum(v) * 1e-3)

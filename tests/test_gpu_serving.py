@@ -44,23 +44,24 @@ def alone(cfg, nsteps, opts, count=None):
     return g.get_state(), np.array(ms), np.array(en)
 
 
-@pytest.mark.parametrize("lanes", [1, 4])
-def test_served_results_equal_alone(lanes):
+@pytest.mark.parametrize("lanes,slots", [(1, 3), (4, 8)])
+def test_served_results_equal_alone(lanes, slots):
     """FP64 and mixed-precision requests of several shapes in one server, the
-    list submitted twice through three slots (so that contexts are recycled),
-    on one stream and spread over four: every result bit-identical to the
-    same request run alone"""
-    say("serving: alone vs mix, lanes", lanes)
+    list submitted twice (so that contexts are recycled), through three slots
+    on one stream and through eight spread over four streams: every result
+    bit-identical to the same request run alone"""
+    say("serving: alone vs mix, lanes", lanes, "slots", slots)
     # a server runs its requests without temporal blocking; the requests
-    # alone take the same options so that launches compare like with like
-    fp64 = dict(W.default_opts(1e-10), blocking=0)
+    # alone take the same options so that launches compare like with like.
+    # Plain cycles, as the served benchmark submits them.
+    fp64 = dict(W.default_opts(1e-10), blocking=0, accel=0)
     mixed = dict(fp64, precision=Q.MIXED)
     cases = mix() * 2
     opts = [mixed if k % 2 else fp64 for k in range(len(mix()))] * 2
     nsteps = 3
     count = []
     ref = [alone(c, nsteps, o, count) for c, o in zip(cases, opts)]
-    srv = Q.Server(hbm_budget=8 << 30, max_slots=3, lanes=lanes)
+    srv = Q.Server(hbm_budget=8 << 30, max_slots=slots, lanes=lanes)
     ids = [srv.submit(c["grid"], c["params"], o, c["state"]["c"], nsteps, c["dt"]) for c, o in zip(cases, opts)]
     left = len(ids)
     for _ in range(100000):
@@ -83,16 +84,10 @@ def test_served_results_equal_alone(lanes):
     # needed alone (an alone step had two step-end reductions, mass() and
     # energy(); a served step has one).  FP64 and mixed requests alternate
     # and never share a launch, and requests of one kind are at different
-    # points of their steps, so the saving is well short of the 3x of three
-    # slots: at least 5 % on one lane (7 % measured with the default
-    # acceleration, whose combination adds an operation to each cycle; 20 %
-    # with plain cycles)
+    # points of their steps, so the saving is well short of the slot count
     alone_launches = sum(count) - nsteps * len(cases)
     say("launches served", s["launches"], "alone", alone_launches)
-    if lanes == 1:
-        assert s["launches"] < 0.95 * alone_launches
-    else:
-        assert s["launches"] <= alone_launches
+    assert s["launches"] <= (0.8 if lanes == 1 else 0.9) * alone_launches
     assert s["contexts_created"] < len(cases)  # the second round reuses contexts
 
 
