@@ -75,7 +75,7 @@ FP64_PEAK_TFLOPS = 78.6
 OP_KERNEL = {
     "halfsweep": ("k_halfsweep_fine", "k_halfsweep"), "fused_sweep": ("k_hs_fused", "k_hs_fused"),
     "smooth": ("k_coarse_solve", "k_coarse_solve"), "coarse_solve": ("k_coarse_solve", "k_coarse_solve"),
-    "restrict": ("k_restrict", "k_restrict"), "coarse_rhs": ("k_coarse_rhs", "k_coarse_rhs"),
+    "restrict": ("k_restrict", "k_restrict"),
     "prolong": ("k_prolong", "k_prolong"), "residual": ("k_resid_norm",) * 2, "residual0": ("k_resid_norm",) * 2,
     "residual_acc": ("k_resid_norm",) * 2, "accelerate": ("k_accel",) * 2, "begin": ("k_begin",) * 2,
     "restrict_n": ("k_restrict_n",) * 2, "mx_halfsweep": ("k_mx_halfsweep_fine", "k_mx_halfsweep"),
@@ -113,10 +113,12 @@ def class_bytes(op, lev, launches, cells, opts):
         return (half * opts["nu1"] + half * opts["nu2"]) * SWEEP_B[False] * n + half * TRANSFER_B * n
     if op == "coarse_solve":
         return launches * opts["nu_coarse"] * SWEEP_B[False] * n
-    if op in ("restrict", "prolong"):
+    if op == "restrict":
+        # the residual and the restriction (per fine cell), then the coarse
+        # right-hand side, a residual of the coarse level
+        return launches * (TRANSFER_B * n + RESID_B[False] * cells[lev + 1])
+    if op == "prolong":
         return launches * TRANSFER_B * n
-    if op == "coarse_rhs":
-        return launches * RESID_B[False] * n
     if op in ("residual", "residual0", "residual_acc"):
         return launches * RESID_B[True] * n
     if op == "accelerate":

@@ -191,11 +191,57 @@ template <typename IT> __global__ FINE_ATTR void k_halfsweep_fine(IT it, int col
 static_assert(FUSED_DOUBLES * 8 <= 65536, "fused tile exceeds 64 KiB of LDS");
 static_assert((TX + 4) * (TY + 4) <= FBLK, "widened red region exceeds the workgroup");
 
+// P(w_H - R w_h) of one unknown of fine level d (the arithmetic of
+// prolong_corr below, split by kind): the cell unknowns of cell (i, j), the
+// u face (i, j) and the v face (i, j) (zero for a face on a wall)
+__device__ __forceinline__ void prolong_cell(const Desc &C, int i, int j, double &c, double &mu, double &p)
+{
+    const size_t kc = (size_t)(j >> 1) * C.pitch + (i >> 1);
+    c = C.c[kc] - C.c0[kc];
+    mu = C.mu[kc] - C.mu0[kc];
+    p = C.p[kc] - C.p0[kc];
+}
+__device__ __forceinline__ double prolong_u(const Desc &d, const Desc &C, int cpar, int i, int j)
+{
+    if (!(d.bcx || i >= 1)) return 0.0;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I;
+    const double *Cu = C.ub[cpar];
+    double du = Cu[kc] - C.u0[kc];
+    if (i & 1) {
+        double e = 0.0;
+        if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
+        else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
+        du = 0.5 * (du + e);
+    }
+    return du;
+}
+__device__ __forceinline__ double prolong_v(const Desc &d, const Desc &C, int cpar, int i, int j)
+{
+    if (!(d.bcy || j >= 1)) return 0.0;
+    const int I = i >> 1, J = j >> 1;
+    const size_t kc = (size_t)J * C.pitch + I;
+    const double *Cv = C.vb[cpar];
+    double dv = Cv[kc] - C.v0[kc];
+    if (j & 1) {
+        double e = 0.0;
+        if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
+        else if (d.bcy) e = Cv[I] - C.v0[I];
+        dv = 0.5 * (dv + e);
+    }
+    return dv;
+}
+
 // the widened tile: every field at tile positions i0-1 .. i0+W-2 (level
 // coordinates; periodic images at their unwrapped positions), plus copies of
 // u and v in the fields T_NF, T_NF + 1 that the red pass overwrites.  A
 // periodic axis needs m >= TX + 3 so that a single wrap reaches every position.
-__device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T)
+// With pc set (the first sweep of a post-smoothing), each unknown first takes
+// the coarse-grid correction P(w_H - R w_h) of its source (k_prolong's
+// arithmetic); the sweep writes every unknown of the level, so the corrected
+// values need no store of their own.
+__device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T, const Desc *pd = nullptr,
+                                           const Desc *pc = nullptr, int cpar = 0)
 {
     const int n = T.W * T.H;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -209,7 +255,16 @@ __device__ __forceinline__ void fused_load(const Phys &P, const View &L, const T
             for (int f = 0; f < T_NF + 2; f++) s[f * n] = 0.0;
             continue;
         }
-        const double v[8] = { L.c[q.c], L.mu[q.c], L.p[q.c], L.u[q.u], L.v[q.v], L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        double v[8] = { L.c[q.c], L.mu[q.c], L.p[q.c], L.u[q.u], L.v[q.v], L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        if (pc) {
+            double rc, rm, rp;
+            prolong_cell(*pc, q.c % L.pitch, q.c / L.pitch, rc, rm, rp);
+            v[0] += rc;
+            v[1] += rm;
+            v[2] += rp;
+            if (q.su) v[3] += prolong_u(*pd, *pc, cpar, q.u % L.pitch, q.u / L.pitch);
+            if (q.sv) v[4] += prolong_v(*pd, *pc, cpar, q.v % L.pitch, q.v / L.pitch);
+        }
         s[T_C * n] = v[0];
         s[T_MU * n] = v[1];
         s[T_P * n] = v[2];
@@ -250,7 +305,7 @@ __device__ __forceinline__ void fused_refresh(const View &L, const Tile &T)
         }
     }
 }
-template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it, int dir, double omega)
+template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it, int dir, double omega, int prolong)
 {
     __shared__ double sm[FUSED_DOUBLES];
     const int k = find_item(it);
@@ -267,7 +322,8 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it,
     const Tile T0 = item_tile(sm, it, k, d);
     Tile T;
     T.s = sm; T.i0 = T0.i0 - 2; T.j0 = T0.j0 - 2; T.W = FUSED_W; T.H = FUSED_H;
-    fused_load(d.P, L, T);
+    if (prolong) fused_load(d.P, L, T, &d, d.coarse, it.cpar[k]);
+    else fused_load(d.P, L, T);
     __syncthreads();
     const Rhs F = rhs_of(d);
     const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
@@ -429,14 +485,28 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
     }
 }
 
+// R w of coarse element (I, J) (a source index of the coarse level, as
+// tile_src gives it) from the fine arrays of view Lf: cells the mean of the
+// four children, faces the mean of the two coincident fine faces, summed in
+// the order k_restrict sums them
+__device__ __forceinline__ double rw_cell(const double *f, int pitch, int I, int J)
+{
+    const size_t a = (size_t)(2 * J) * pitch + 2 * I, b = a + pitch;
+    return 0.25 * ((f[a] + f[a + 1]) + (f[b] + f[b + 1]));
+}
+
 // fine residual r = f - N(w) restricted to the coarse grid together with the
 // iterate (cells: mean of the four children; faces: mean of the two coincident
-// fine faces); the coarse rhs holds R r until k_coarse_rhs adds N_H(R w).
-// A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane pair each.
+// fine faces), and the FAS right-hand side f_H = N_H(R w) + R r of the coarse
+// cells.  A tile of fine cells covers (TX/2) x (TY/2) coarse cells, one lane
+// pair each; N_H is evaluated on a coarse tile whose halo takes R w from the
+// fine arrays directly (the neighbouring workgroups write the coarse iterate
+// meanwhile).
 template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
     __shared__ double part[(TX / 2) * (TY / 2)][2][8];
+    __shared__ double rr[(TX / 2) * (TY / 2)][2][4];
     const int k = find_item(it);
     const Desc &d = *it.d[k];
     if (!tile_valid(it, k, d)) return;
@@ -473,23 +543,75 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
             for (int q = 0; q < 8; q++) part[cc][hlf][q] = v[q];
     }
     __syncthreads();
-    if (!on || b != 0) return;
-#pragma unroll
-    for (int q = 0; q < 8; q++) v[q] += part[cc][hlf][q];
-    const size_t q = (size_t)J * C.pitch + I;
     const int cp = it.cpar[k];
-    if (hlf == 0) {
-        C.c[q] = C.c0[q] = 0.25 * v[4];
-        C.mu[q] = C.mu0[q] = 0.25 * v[5];
-        C.p[q] = C.p0[q] = 0.25 * v[6];
-        C.fc[q] = 0.25 * v[0];
-        C.fmu[q] = 0.25 * v[1];
-        C.fp[q] = 0.25 * v[2];
-        C.ub[cp][q] = C.u0[q] = 0.5 * v[7];
-        C.fu[q] = 0.5 * v[3];
-    } else {
-        C.vb[cp][q] = C.v0[q] = 0.5 * v[7];
-        C.fv[q] = 0.5 * v[3];
+    if (on && b == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] += part[cc][hlf][q];
+        const size_t q = (size_t)J * C.pitch + I;
+        if (hlf == 0) {
+            C.c[q] = C.c0[q] = 0.25 * v[4];
+            C.mu[q] = C.mu0[q] = 0.25 * v[5];
+            C.p[q] = C.p0[q] = 0.25 * v[6];
+            C.ub[cp][q] = C.u0[q] = 0.5 * v[7];
+            rr[cc][0][0] = 0.25 * v[0];
+            rr[cc][0][1] = 0.25 * v[1];
+            rr[cc][0][2] = 0.25 * v[2];
+            rr[cc][0][3] = 0.5 * v[3];
+        } else {
+            C.vb[cp][q] = C.v0[q] = 0.5 * v[7];
+            rr[cc][1][3] = 0.5 * v[3];
+        }
+    }
+    // the coarse tile of R w (the fine tile is not read any more)
+    Tile Tc;
+    Tc.s = sm; Tc.i0 = T.i0 / 2; Tc.j0 = T.j0 / 2; Tc.W = TX / 2 + 3; Tc.H = TY / 2 + 3;
+    const View Lc = view_of(C, cp);
+    {
+        const int n = Tc.W * Tc.H;
+        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+            const int bb = e / Tc.W, aa = e - bb * Tc.W;
+            const TileSrc s = tile_src(C.m1, C.m2, C.pitch, C.bcx, C.bcy, Tc.i0 - 1 + aa, Tc.j0 - 1 + bb);
+            double *t = Tc.s + e;
+            if (s.sc == 0) {
+                for (int f = 0; f < T_NF; f++) t[f * n] = 0.0;
+                continue;
+            }
+            const int Ic = s.c % C.pitch, Jc = s.c / C.pitch;
+            const double c = rw_cell(Lf.c, Lf.pitch, Ic, Jc);
+            const int Iu = s.u % C.pitch, Ju = s.u / C.pitch, Iv = s.v % C.pitch, Jv = s.v / C.pitch;
+            const size_t fu = (size_t)(2 * Ju) * Lf.pitch + 2 * Iu, fv = (size_t)(2 * Jv) * Lf.pitch + 2 * Iv;
+            const double u = s.su ? 0.5 * (Lf.u[fu] + Lf.u[fu + Lf.pitch]) : 0.0;
+            const double w = s.sv ? 0.5 * (Lf.v[fv] + Lf.v[fv + 1]) : 0.0;
+            const double cn = C.cn[s.c];
+            t[T_C * n] = c;
+            t[T_MU * n] = rw_cell(Lf.mu, Lf.pitch, Ic, Jc);
+            t[T_P * n] = rw_cell(Lf.p, Lf.pitch, Ic, Jc);
+            t[T_U * n] = signed_val(s.su, u);
+            t[T_V * n] = signed_val(s.sv, w);
+            t[T_CN * n] = cn;
+            t[T_UN * n] = signed_val(s.su, C.un[s.u]);
+            t[T_VN * n] = signed_val(s.sv, C.vn[s.v]);
+            t[T_RN * n] = rho_of(C.P, cn);
+            t[T_MV * n] = visc_of(C.P, cn);
+            t[T_MOB * n] = mob_of(C.P, cn);
+            t[T_RS * n] = rho_of(C.P, c);
+        }
+    }
+    __syncthreads();
+    // f_H = N_H(R w) + R r on the coarse cells, a lane pair each
+    if (pr < NC && I < C.m1 && J < C.m2 && cc == pr) {
+        const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
+        double rc, rm, rp, rf;
+        resid_pair(C.P, Lc, Tc, Z, I, J, hlf, rc, rm, rp, rf); // r = -N_H(R w)
+        const size_t q = (size_t)J * C.pitch + I;
+        if (hlf == 0) {
+            C.fc[q] = rr[cc][0][0] - rc;
+            C.fmu[q] = rr[cc][0][1] - rm;
+            C.fp[q] = rr[cc][0][2] - rp;
+            C.fu[q] = u_unk(Lc, I) ? rr[cc][0][3] - rf : 0.0;
+        } else {
+            C.fv[q] = v_unk(Lc, J) ? rr[cc][1][3] - rf : 0.0;
+        }
     }
 }
 
@@ -500,40 +622,6 @@ template <typename TT> __device__ __forceinline__ void pair_cells(const TT &T, i
     const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
     i = T.i0 + 2 * kk;
     j = T.j0 + lj;
-}
-
-// f_H = N_H(R w) + R r (FAS coarse right-hand side) on the coarse level the
-// item names; walls carry no equation
-template <typename IT> __global__ __launch_bounds__(TBLK) void k_coarse_rhs(IT it)
-{
-    __shared__ double sm[TILE_DOUBLES];
-    const int k = find_item(it);
-    const Desc &C = *it.d[k];
-    if (!tile_valid(it, k, C)) return;
-    const View Lc = view_of(C, it.par[k]);
-    const Tile T = item_tile(sm, it, k, C);
-    tile_load(C.P, Lc, T);
-    __syncthreads();
-    const int hlf = threadIdx.x & 1;
-    int i, j;
-    pair_cells(T, i, j);
-    const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
-    // the pair's two cells are both inside or both outside (even m1)
-    if (i >= C.m1 || j >= C.m2) return;
-#pragma unroll
-    for (int a = 0; a < 2; a++, i++) {
-        double rc, rm, rp, rf;
-        resid_pair(C.P, Lc, T, Z, i, j, hlf, rc, rm, rp, rf); // r = -N_H(R w)
-        const size_t q = (size_t)j * C.pitch + i;
-        if (hlf == 0) {
-            C.fc[q] -= rc;
-            C.fmu[q] -= rm;
-            C.fp[q] -= rp;
-            C.fu[q] = u_unk(Lc, i) ? C.fu[q] - rf : 0.0;
-        } else {
-            C.fv[q] = v_unk(Lc, j) ? C.fv[q] - rf : 0.0;
-        }
-    }
 }
 
 // w_h += P(w_H - R w_h) on the level the item names, one thread per fine cell

@@ -30,7 +30,7 @@ using namespace qn;
 // ===========================================================================
 // operations of a time step
 
-enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_CRHS, OP_COARSE, OP_PROLONG, OP_STEPEND,
+enum OpKind { OP_BEGIN, OP_RN, OP_NORM0, OP_NORM, OP_HS, OP_RESTRICT, OP_COARSE, OP_PROLONG, OP_STEPEND,
               OP_RESTORE,
               // mixed precision: FP32 correction cycle, FP64 update
               OP_MXRN, OP_MXHS, OP_MXRESTRICT, OP_MXCOARSE, OP_MXPROLONG, OP_MXUPDATE,
@@ -85,13 +85,21 @@ static void smooth_ops(int l, int nu, int small, int hs_kind, int lds_kind, unsi
 }
 // prolongation onto level l, then its post-smoothing; a level-resident
 // smoothing takes the correction as it loads the level (colour field
-// nu + PROLONG_FIRST), which saves the prolongation launch
+// nu + PROLONG_FIRST), and so does the first fused sweep of an FP64 level
+// (colour field 2 + direction 0), which saves the prolongation launch
 #define PROLONG_FIRST 16
+#define FUSED_PROLONG 2
 static void prolong_smooth_ops(int l, int nu, int small, int pr_kind, int hs_kind, int lds_kind, unsigned fuse,
                                std::vector<Op> &out)
 {
     if (nu > 0 && nu < PROLONG_FIRST && l > 0 && l >= small) {
         out.push_back({ lds_kind, l, nu + PROLONG_FIRST });
+        return;
+    }
+    if (pr_kind == OP_PROLONG && nu >= 2 && !(l > 0 && l >= small) && ((fuse >> l) & 1)) {
+        const size_t first = out.size();
+        smooth_ops(l, nu, small, hs_kind, lds_kind, fuse, out);
+        out[first].colour |= FUSED_PROLONG;
         return;
     }
     out.push_back({ pr_kind, l, 0 });
@@ -104,8 +112,7 @@ static void vcycle_program(int L, int nu1, int nu2, int small, unsigned fuse, bo
 {
     for (int l = 0; l + 1 < L; l++) {
         smooth_ops(l, nu1, small, OP_HS, OP_SMOOTH, fuse, out);
-        out.push_back({ OP_RESTRICT, l, 0 });
-        out.push_back({ OP_CRHS, l + 1, 0 });
+        out.push_back({ OP_RESTRICT, l, 0 }); // with the coarse FAS right-hand side
     }
     out.push_back({ OP_COARSE, L - 1, 0 });
     for (int l = L - 2; l >= 0; l--) prolong_smooth_ops(l, nu2, small, OP_PROLONG, OP_HS, OP_SMOOTH, fuse, out);
@@ -284,7 +291,7 @@ static int op_blocks(const qnsch_ctx *x, int kind, int l)
 {
     const DLev &D = x->L[l];
     switch (kind) {
-    case OP_HS: case OP_RESTRICT: case OP_CRHS: case OP_NORM: case OP_NORM0: case OP_NORMACC: case OP_MXHS:
+    case OP_HS: case OP_RESTRICT: case OP_NORM: case OP_NORM0: case OP_NORMACC: case OP_MXHS:
     case OP_MXRESTRICT: case OP_FUSED: case OP_MXFUSED:
         return tiles_x(D.m1) * tiles_y(D.m2);
     case OP_COARSE: case OP_MXCOARSE: case OP_SMOOTH: case OP_MXSMOOTH: return 1;
@@ -554,7 +561,7 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             break;
         }
         case OP_FUSED: {
-            KLAUNCH(k_hs_fused, W, dim3(W.blocks), dim3(FBLK), 0, s, colour, omega);
+            KLAUNCH(k_hs_fused, W, dim3(W.blocks), dim3(FBLK), 0, s, colour & 1, omega, colour >> 1);
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
@@ -564,7 +571,6 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             break;
         }
         case OP_RESTRICT: KLAUNCH(k_restrict, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
-        case OP_CRHS: KLAUNCH(k_coarse_rhs, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
         case OP_COARSE:
         case OP_SMOOTH: {
             int nmax = 0;

@@ -31,7 +31,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
 
 
 # operation classes of qnsch_profile_breakdown, in the library's numbering
-OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_rhs", "coarse_solve",
+OP_NAMES = ("begin", "restrict_n", "residual0", "residual", "halfsweep", "restrict", "coarse_solve",
             "prolong", "step_end", "restore", "mx_restrict_n", "mx_halfsweep", "mx_restrict", "mx_coarse_solve",
             "mx_prolong", "mx_update", "dissipation", "diagnostics", "pj_final", "smooth", "mx_smooth", "residual_acc",
             "accelerate", "fused_sweep", "mx_fused_sweep")
