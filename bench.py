@@ -112,7 +112,10 @@ def class_bytes(op, lev, launches, cells, opts):
         half = launches / 2.0
         return (half * opts["nu1"] + half * opts["nu2"]) * SWEEP_B[False] * n + half * TRANSFER_B * n
     if op == "coarse_solve":
-        return launches * opts["nu_coarse"] * SWEEP_B[False] * n
+        # the coarsest solve's sweeps (0 in the options: the library's
+        # automatic 4 for the primitive scheme on 6 levels or more, else 6)
+        nu_c = opts["nu_coarse"] or (4 if opts.get("scheme", 0) != Q.PROJECTION and len(cells) >= 6 else 6)
+        return launches * nu_c * SWEEP_B[False] * n
     if op == "restrict":
         # the residual and the restriction (per fine cell), then the coarse
         # right-hand side, a residual of the coarse level

@@ -124,13 +124,16 @@ typedef struct {
     double tol;          /* stop when every per-equation norm sqrt(h^2 sum r^2) <= tol */
     int32_t max_vcycles; /* error QNSCH_ENOCONV beyond this */
     int32_t nu1, nu2;    /* pre/post smoothing sweeps (one sweep = red + black), 0..15 */
-    int32_t nu_coarse;   /* sweeps on the coarsest level */
+    int32_t nu_coarse;   /* sweeps on the coarsest level; 0 = automatic (4 for the
+                            primitive scheme on 6 levels or more, else 6) */
     double vanka_omega;  /* relaxation factor of the box update (1 = exact box solve) */
     int32_t smoother;    /* QNSCH_SMOOTH_COUPLED or QNSCH_SMOOTH_SEGREGATED */
     int32_t scheme;      /* QNSCH_PRIMITIVE or QNSCH_PROJECTION */
     double coarse_omega; /* relaxation factor of the velocity and pressure updates on the
                             coarsest level (the primitive box's faces and pbar; the
-                            projection scheme's pressure step); in (0, 2) */
+                            projection scheme's pressure step); in (0, 2), or 0 =
+                            automatic (1.75 where nu_coarse's automatic value is 4,
+                            else 1.6) */
     int32_t accel;       /* depth m (0..3) of the acceleration of the cycle iteration
                             below; 0 = plain cycles */
     int32_t blocking;    /* temporal blocking of the smoothing (below): 0 = off,
@@ -188,10 +191,12 @@ typedef struct {
 
 typedef struct qnsch_ctx qnsch_ctx;
 
-/* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), 6 coarsest sweeps
- * over-relaxed by coarse_omega = 1.6 (as accurate as 30 plain sweeps on the
- * workloads of sec. 8), omega 1, coupled smoother, primitive scheme,
- * acceleration depth 2, temporal blocking of the coarse levels (1). */
+/* Defaults: FP64, tol 1e-10, 50 V-cycles, V(2,2), the coarsest solve's
+ * automatic settings (nu_coarse = coarse_omega = 0: 4 sweeps over-relaxed by
+ * 1.75 in the primitive scheme on hierarchies of 6 levels or more, else 6 by
+ * 1.6; as many or fewer V-cycles than 30 plain sweeps on the workloads of
+ * sec. 8), omega 1, coupled smoother, primitive scheme, acceleration depth
+ * 2, temporal blocking of the coarse levels (1). */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to

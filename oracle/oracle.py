@@ -105,7 +105,7 @@ class Oracle:
         g = _Grid(grid["m1"], grid["m2"], grid["Lx"], grid["Ly"], grid["bcx"], grid["bcy"], grid.get("levels", 0))
         p = _Params(*[float(params[n]) for n, _ in _Params._fields_])
         o = _Opts(opts["tol"], opts["max_vcycles"], opts["nu1"], opts["nu2"], opts["nu_coarse"], opts["vanka_omega"],
-                  opts.get("smoother", 1), opts.get("scheme", 0), opts.get("coarse_omega", 1.6), opts.get("accel", 2))
+                  opts.get("smoother", 1), opts.get("scheme", 0), opts.get("coarse_omega", 0.0), opts.get("accel", 2))
         self.h = lib().orc_create(C.byref(g), C.byref(p), C.byref(o))
         if not self.h:
             raise ValueError("oracle rejected the grid")

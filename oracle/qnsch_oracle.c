@@ -1000,6 +1000,15 @@ orc_ctx *orc_create(const orc_grid *g, const orc_params *p, const orc_opts *opt)
     }
     if (nl > ORC_MAXLEV || g->m1 % (1 << nl) != 0 || g->m2 % (1 << nl) != 0) { free(o); return NULL; }
     o->nlev = nl;
+    /* the coarsest solve's automatic settings (a reading of the multigrid
+     * that sec. 7 defers to its references): 4 sweeps over-relaxed by 1.75
+     * in the primitive scheme on hierarchies of 6 levels or more, else 6
+     * sweeps by 1.6 */
+    {
+        const int deep = opt->scheme != ORC_PROJECTION && nl >= 6;
+        if (o->o.nu_coarse <= 0) o->o.nu_coarse = deep ? 4 : 6;
+        if (o->o.coarse_omega <= 0.0) o->o.coarse_omega = deep ? 1.75 : 1.6;
+    }
     for (int l = 0; l < nl; l++) {
         Level *L = &o->lev[l];
         L->m1 = g->m1 >> l;

@@ -33,11 +33,12 @@ enum { ORC_PRIMITIVE = 0, ORC_PROJECTION = 1 };
 
 typedef struct {
     double tol;
-    int max_vcycles, nu1, nu2, nu_coarse;
+    int max_vcycles, nu1, nu2, nu_coarse; /* nu_coarse 0: automatic (4 primitive with 6 levels or more, else 6) */
     double vanka_omega;
     int smoother; /* ORC_SMOOTH_COUPLED (default) or ORC_SMOOTH_SEGREGATED; projection scheme: step 1 with or without pbar */
     int scheme;   /* ORC_PRIMITIVE (sec. 6.1) or ORC_PROJECTION (sec. 6.2) */
-    double coarse_omega; /* relaxation of the velocity/pressure updates on the coarsest level */
+    double coarse_omega; /* relaxation of the velocity/pressure updates on the coarsest level;
+                            0: automatic (1.75 with 4 automatic sweeps, else 1.6) */
     int accel;           /* depth (0..ORC_MAXACC) of the acceleration of the cycle iteration; 0 = off */
 } orc_opts;
 

@@ -56,8 +56,8 @@ PRIMITIVE, PROJECTION = 0, 1
 
 
 def default_opts(tol=1e-10):
-    return dict(tol=tol, max_vcycles=50, nu1=2, nu2=2, nu_coarse=6, vanka_omega=1.0, smoother=SMOOTH_COUPLED,
-                coarse_omega=1.6, accel=2, blocking=1)
+    return dict(tol=tol, max_vcycles=50, nu1=2, nu2=2, nu_coarse=0, vanka_omega=1.0, smoother=SMOOTH_COUPLED,
+                coarse_omega=0.0, accel=2, blocking=1)
 
 
 def params(rho1, rho2, visc1, visc2, Re, We, inv_Fr, eps, M=None, Pe=None, eta=None, mob_reg=None, rho_ref=0.0):
