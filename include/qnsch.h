@@ -283,6 +283,21 @@ int qnsch_dissipation(qnsch_ctx *ctx, double out[5]);
  *            height of a capillary wave at its crest), NaN if none;
  *   out[7] = h^2 sum div_d u (zero with walls or periodic boundaries). */
 int qnsch_diagnostics(qnsch_ctx *ctx, double out[8]);
+/* Launches of a cycle (qnsch_step, qnsch_vcycle): with enable != 0 the
+ * operations of a cycle before its residual reduction are captured once into
+ * an executable HIP graph (per pattern of the levels' double-buffered faces,
+ * on a stream of the context's own) and replayed on the context's stream, one
+ * host call per cycle instead of one per kernel; the acceleration's
+ * combination and the residual reduction, whose arguments change from cycle
+ * to cycle, are launched directly.  The kernels, their arguments and their
+ * order are those of the direct launches, so results are bitwise the same.
+ * Cycles run with launches timed by qnsch_profile or qnsch_profile_ops are
+ * launched directly.  Off (enable = 0) by default: the kernels of a cycle run
+ * long enough that the device takes the next directly launched kernel
+ * without a longer gap than from a graph (the step times of the benchmark
+ * workloads agree within 1 %).  QNSCH_EINVAL on a NULL context; a failed
+ * capture is reported by the step that needed it. */
+int qnsch_graphs(qnsch_ctx *ctx, int enable);
 /* Statistics of the last step (above); launches nothing. */
 int qnsch_stats(qnsch_ctx *ctx, qnsch_step_stats *out);
 /* Block until all work of the context's stream has finished. */

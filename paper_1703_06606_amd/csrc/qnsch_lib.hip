@@ -204,6 +204,16 @@ struct qnsch_ctx {
     bool acc_first = true;  // the next cycle is the first of its step (not recorded)
     double acc_g[3] = { 0.0, 0.0, 0.0 };
     double acc_last = 0.0;  // largest residual norm of the latest result
+    // replay of a cycle's operations before its residual reduction as one
+    // executable graph (qnsch_graphs; off by default).  One graph per pattern
+    // of the levels' current face buffers (bit l = L[l].cur) the cycle
+    // starts from; every cycle toggles each level's buffer an even number of
+    // times, so the pattern after the cycle is the one it started from.
+    // Captured on a stream of the context's own (the caller's stream may be
+    // the null stream, which cannot capture) and launched on the caller's.
+    bool graphs = false;
+    hipStream_t cap = nullptr;
+    std::vector<std::pair<unsigned, hipGraphExec_t>> cyc_graphs;
 };
 
 static bool is_mixed(const qnsch_ctx *x) { return x->opt.precision == QNSCH_MIXED; }
@@ -690,7 +700,60 @@ static int run_ops(qnsch_ctx *x, const std::vector<Op> &prog)
     return QNSCH_OK;
 }
 
-// wait for the context's stream (the reduced values are then in red_host)
+// pattern of the levels' current face buffers
+static unsigned cur_key(const qnsch_ctx *x)
+{
+    unsigned k = 0;
+    for (int l = 0; l < x->nlev; l++) k |= (unsigned)(x->L[l].cur & 1) << l;
+    return k;
+}
+
+// the operations of a cycle before its residual reduction: launched one by
+// one while launches are timed or graphs are off, else as the replay of the
+// graph captured for the current buffer pattern (captured on first use)
+static int run_body(qnsch_ctx *x, const std::vector<Op> &body)
+{
+    if (!x->graphs || x->prof) return run_ops(x, body);
+    const unsigned key = cur_key(x);
+    hipGraphExec_t ge = nullptr;
+    for (auto &c : x->cyc_graphs)
+        if (c.first == key) ge = c.second;
+    if (!ge) {
+        if (!x->cap) HIPCHK(x, hipStreamCreateWithFlags(&x->cap, hipStreamNonBlocking));
+        HIPCHK(x, hipStreamBeginCapture(x->cap, hipStreamCaptureModeThreadLocal));
+        const hipStream_t s = x->s;
+        x->s = x->cap;
+        const int rc = run_ops(x, body);
+        x->s = s;
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(x->cap, &g);
+        if (rc || e != hipSuccess || !g || cur_key(x) != key) {
+            if (g) (void)hipGraphDestroy(g);
+            for (int l = 0; l < x->nlev; l++) x->L[l].cur = (int)((key >> l) & 1);
+            if (rc) return rc;
+            x->err = e != hipSuccess ? std::string("hipStreamEndCapture: ") + hipGetErrorString(e)
+                                     : std::string("cycle capture: the levels' buffer pattern changed");
+            return QNSCH_EDEVICE;
+        }
+        const hipError_t ei = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(x, ei);
+        x->cyc_graphs.push_back({ key, ge });
+    }
+    HIPCHK(x, hipGraphLaunch(ge, x->s));
+    return QNSCH_OK;
+}
+
+// one cycle: the pending combination of the acceleration, the operations of
+// the cycle programme cyc before its residual reduction, the reduction
+static int run_cycle(qnsch_ctx *x, const std::vector<Op> &cyc, const std::vector<Op> &body)
+{
+    int rc;
+    if (x->acc_use > 0 && (rc = run_ops(x, { { OP_ACCEL, 0, 0 } }))) return rc;
+    if ((rc = run_body(x, body))) return rc;
+    return run_ops(x, { cyc.back() });
+}
+
 // wait for the context's stream (the reduced values are then in red_host).
 // The host polls the completion of an event for a while before blocking: a
 // step waits here once per V-cycle, and a blocking wait wakes up tens of
@@ -872,6 +935,8 @@ void qnsch_destroy(qnsch_ctx *x)
     for (void *p : x->allocs) (void)hipFree(p);
     for (hipEvent_t e : x->pev) (void)hipEventDestroy(e);
     if (x->ev) (void)hipEventDestroy(x->ev);
+    for (auto &c : x->cyc_graphs) (void)hipGraphExecDestroy(c.second);
+    if (x->cap) (void)hipStreamDestroy(x->cap);
     if (x->red_host) (void)hipHostFree(x->red_host);
     if (x->stage) (void)hipHostFree(x->stage);
     if (x->hd) (void)hipHostFree(x->hd);
@@ -1147,8 +1212,9 @@ int qnsch_vcycle(qnsch_ctx *x)
     std::vector<Op> prog;
     x->acc_use = 0; // a combination not applied by qnsch_accelerate is dropped
     cycle_program(x, prog);
+    const std::vector<Op> body(prog.begin(), prog.end() - 1);
     int rc;
-    if ((rc = run_ops(x, prog))) return rc;
+    if ((rc = run_cycle(x, prog, body))) return rc;
     if ((rc = read_red(x))) return rc;
     if (x->acc_wait) acc_after(x);
     x->st.vcycles++;
@@ -1295,10 +1361,10 @@ int qnsch_step(qnsch_ctx *x, double dt)
     int rc;
     x->diss_state = 0;
     if ((rc = set_dt(x, dt))) return rc;
-    std::vector<Op> begin, cyc, cyc_acc = { { OP_ACCEL, 0, 0 } };
+    std::vector<Op> begin, cyc;
     step_begin_program(x, begin);
     cycle_program(x, cyc);
-    cyc_acc.insert(cyc_acc.end(), cyc.begin(), cyc.end());
+    const std::vector<Op> body(cyc.begin(), cyc.end() - 1);
     acc_reset(x);
     // the begin programme only copies the state into the time-n data
     if ((rc = run_ops(x, begin))) { x->in_step = 0; return rc; }
@@ -1313,7 +1379,7 @@ int qnsch_step(qnsch_ctx *x, double dt)
         const int j = stop_test(x, it);
         if (j < 0) return fail_step(x, j);
         if (j == 1) break;
-        if ((rc = run_ops(x, x->acc_use > 0 ? cyc_acc : cyc))) return fail_step(x, rc);
+        if ((rc = run_cycle(x, cyc, body))) return fail_step(x, rc);
         if ((rc = read_red(x))) return fail_step(x, rc);
         if (x->acc_wait) acc_after(x);
         it++;
@@ -1460,6 +1526,13 @@ int qnsch_profile_ops(qnsch_ctx *x, uint64_t op_mask)
 {
     if (!x) return QNSCH_EINVAL;
     return profile_reset(x, op_mask ? 1 : 0, op_mask, false);
+}
+
+int qnsch_graphs(qnsch_ctx *x, int enable)
+{
+    if (!x) return QNSCH_EINVAL;
+    x->graphs = enable != 0;
+    return QNSCH_OK;
 }
 
 int qnsch_profile_read(qnsch_ctx *x, double out[2])

@@ -23,7 +23,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_accelerate",
            "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy",
            "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
-           "qnsch_synchronize", "qnsch_profile", "qnsch_profile_ops", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
+           "qnsch_synchronize", "qnsch_graphs", "qnsch_profile", "qnsch_profile_ops", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
            "qnsch_server_latency",
@@ -107,6 +107,7 @@ def lib():
         L.qnsch_diagnostics.argtypes = [vp, P]
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.qnsch_synchronize.argtypes = [vp]
+        L.qnsch_graphs.argtypes = [vp, C.c_int]
         L.qnsch_profile.argtypes = [vp, C.c_int]
         L.qnsch_profile_ops.argtypes = [vp, C.c_uint64]
         L.qnsch_profile_read.argtypes = [vp, P]
@@ -287,6 +288,11 @@ class Solver:
 
     def synchronize(self):
         self._chk(lib().qnsch_synchronize(self.h))
+
+    def graphs(self, enable):
+        """replay each cycle's fixed launches as a captured HIP graph, or
+        launch them one by one (the default)"""
+        self._chk(lib().qnsch_graphs(self.h, int(bool(enable))))
 
     def profile(self, mode):
         """0 off, 1 (or True) finest half-sweeps, 2 every launch"""
