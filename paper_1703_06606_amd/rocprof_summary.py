@@ -12,10 +12,16 @@ Reads the CSV output of three rocprofv3 runs of the same bench command
   the kernel's dispatches of FETCH_SIZE and WRITE_SIZE, KiB, each scaled by
   what the counter reads for the copy-probe kernel that bench.py runs first:
   it reads and writes 512 MiB), and the hash of the device code the counters
-  were taken on (bench.py ignores a summary of other device code).
+  were taken on (bench.py ignores a summary of other device code);
+* with ``--valu DIR`` (a ``--pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_ADD_F64
+  SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64`` run),
+  ``<kernel>_<workload>_valu.txt``: waves, vector-ALU wave instructions and
+  FP64 wave instructions per dispatch (means over the kernel's dispatches)
+  and the FP64 flops they execute with every lane counted.
 
-Usage: python -m paper_1703_06606_amd.rocprof_summary --trace DIR --fetch DIR
---write DIR --workload NAME --out DIR --command "..." KERNEL [KERNEL ...]
+Usage: python -m paper_1703_06606_amd.rocprof_summary [--trace DIR --fetch DIR
+--write DIR] [--valu DIR] --workload NAME --out DIR --command "..." KERNEL
+[KERNEL ...]
 """
 import argparse
 import csv
@@ -83,11 +89,44 @@ def copy_scale(c, factor_bytes):
     return factor_bytes / (statistics.median(vals) * 1024.0)
 
 
+VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64",
+                 "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64")
+
+
+def valu_summaries(a):
+    c = {n: counters(a.valu, n) for n in VALU_COUNTERS}
+    h = device_source_hash()
+    for kern in a.kernels:
+        rx = _match(kern)
+        m = {n: [v for (name, g, v) in c[n].values() if rx.search(name)] for n in VALU_COUNTERS}
+        if not all(m.values()):
+            continue
+        mean = {n: statistics.mean(v) for n, v in m.items()}
+        f64 = mean["SQ_INSTS_VALU_ADD_F64"] + mean["SQ_INSTS_VALU_MUL_F64"] + mean["SQ_INSTS_VALU_FMA_F64"] \
+            + mean["SQ_INSTS_VALU_TRANS_F64"]
+        flops = 64.0 * (mean["SQ_INSTS_VALU_ADD_F64"] + mean["SQ_INSTS_VALU_MUL_F64"]
+                        + 2.0 * mean["SQ_INSTS_VALU_FMA_F64"] + mean["SQ_INSTS_VALU_TRANS_F64"])
+        with open(os.path.join(a.out, "%s_%s_valu.txt" % (kern, a.workload)), "w") as fh:
+            fh.write("# SQ counters of %s on %s, mean per dispatch over %d dispatches (every level);\n"
+                     % (kern, a.workload, len(m["SQ_WAVES"])))
+            for cmd in a.command:
+                fh.write("# command: %s\n" % cmd)
+            fh.write("# summarised by: python -m paper_1703_06606_amd.rocprof_summary --valu;\n"
+                     "# FP64 flops = 64 lanes x (ADD + MUL + 2 FMA + TRANS wave instructions), every lane counted;\n"
+                     "# valid for the device code with this hash\n")
+            fh.write("source_hash: %s\nwaves_per_launch: %.0f\nvalu_wave_insts_per_launch: %.0f\n"
+                     "valu_wave_insts_per_wave: %.1f\nfp64_wave_insts_per_launch: %.0f\nfp64_flops_per_launch: %.0f\n"
+                     "dispatches: %d\n" % (h, mean["SQ_WAVES"], mean["SQ_INSTS_VALU"],
+                                          mean["SQ_INSTS_VALU"] / max(mean["SQ_WAVES"], 1.0), f64, flops,
+                                          len(m["SQ_WAVES"])))
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--trace")
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--valu", help="directory of the SQ counter run (see above)")
     ap.add_argument("--workload", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", action="append", default=[], help="commands that made the runs (repeatable)")
@@ -96,6 +135,10 @@ def main():
     ap.add_argument("kernels", nargs="*")
     a = ap.parse_args()
     os.makedirs(a.out, exist_ok=True)
+    if a.valu:
+        valu_summaries(a)
+    if not (a.trace and a.fetch and a.write):
+        return
     trace = _rows(a.trace, "kernel_trace.csv")
     durs = {}
     for r in trace:
