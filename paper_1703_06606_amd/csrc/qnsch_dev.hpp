@@ -653,24 +653,27 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
         xlo = -0.5 * ih * w_o - v_o;
         xhi = 0.5 * ih * w_o - v_o;
     }
-    const double o_xlo = other(xlo), o_xhi = other(xhi);
-    // exchange: the pair now holds the x rows (lane 0) and the y rows (lane 1)
+    // exchange: each lane of the pair now holds the rows of both axes.  A
+    // lane orders the box's unknowns with its own axis first: lane 0 as uW,
+    // uE, vS, vN, p, lane 1 as vS, vN, uW, uE, p; the rows of the two axes
+    // have the same form, so the matrix is assembled without selecting by
+    // lane, and each lane eliminates its own faces first (lane 0 in the
+    // order of the oracle, lane 1 with the axes swapped, a symmetric
+    // permutation that keeps the pivots positive)
     const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const double o_xlo = other(xlo), o_xhi = other(xhi);
     const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
-    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
-    const double wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
     double A[5][5], b[5];
-    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi; b[4] = bp;
-    const double d0 = hlf ? o_dlo : dlo, d1 = hlf ? o_dhi : dhi, d2 = hlf ? dlo : o_dlo, d3 = hlf ? dhi : o_dhi;
-    // rows: momentum at uW, uE, vS, vN, then mass; columns in the same order;
-    // a face on a wall is not an unknown (identity row, no coupling)
-    const double mW = xl ? 1.0 : 0.0, mE = xh ? 1.0 : 0.0, mS = yl ? 1.0 : 0.0, mN = yh ? 1.0 : 0.0;
-    A[0][0] = d0; A[0][1] = mW * (0.5 * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd; A[0][4] = mW * gp;
-    A[1][1] = d1; A[1][0] = mE * (-0.5 * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd; A[1][4] = -mE * gp;
-    A[2][2] = d2; A[2][3] = mS * (0.5 * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
-    A[3][3] = d3; A[3][2] = mN * (-0.5 * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
-    A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
-    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    b[0] = blo; b[1] = bhi; b[2] = o_blo; b[3] = o_bhi; b[4] = bp;
+    // rows: momentum at the own axis' low and high faces, the other axis' low
+    // and high faces, then mass; columns in the same order; a face on a wall
+    // is not an unknown (identity row, no coupling)
+    const double m0l = hlo ? 1.0 : 0.0, m0h = hhi ? 1.0 : 0.0, m1l = o_hlo ? 1.0 : 0.0, m1h = o_hhi ? 1.0 : 0.0;
+    A[0][0] = dlo; A[0][1] = m0l * (0.5 * ih * w_ax - vis) + xlo; A[0][2] = m0l * gd; A[0][3] = -m0l * gd; A[0][4] = m0l * gp;
+    A[1][1] = dhi; A[1][0] = m0h * (-0.5 * ih * w_ax - vis) + xhi; A[1][2] = -m0h * gd; A[1][3] = m0h * gd; A[1][4] = -m0h * gp;
+    A[2][2] = o_dlo; A[2][3] = m1l * (0.5 * ih * o_w - vis) + o_xlo; A[2][0] = m1l * gd; A[2][1] = -m1l * gd; A[2][4] = m1l * gp;
+    A[3][3] = o_dhi; A[3][2] = m1h * (-0.5 * ih * o_w - vis) + o_xhi; A[3][0] = -m1h * gd; A[3][1] = m1h * gd; A[3][4] = -m1h * gp;
+    A[4][0] = -m0l * ih; A[4][1] = m0h * ih; A[4][2] = -m1l * ih; A[4][3] = m1h * ih; A[4][4] = q.Jpp;
     // coupled box: border of the c and mubar rows and columns, eliminated
     // into the 5x5 system (see above)
     double ac[5] = { 0.0, 0.0, 0.0, 0.0, 0.0 };
@@ -679,9 +682,8 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
         const double alo = hlo ? 0.5 * ih * tq(T, T_RN, e - a.dn) * (tq(T, T_CN, e) - tq(T, T_CN, e - a.dn)) : 0.0;
         const double ahi = hhi ? 0.5 * ih * tq(T, T_RN, e1) * (tq(T, T_CN, e1) - tq(T, T_CN, e)) : 0.0;
         const double ulo = hlo ? tq(T, a.FN, e) : 0.0, uhi = hhi ? tq(T, a.FN, e1) : 0.0;
-        const double o_alo = other(alo), o_ahi = other(ahi), o_ulo = other(ulo), o_uhi = other(uhi);
-        ac[0] = hlf ? o_alo : alo; ac[1] = hlf ? o_ahi : ahi; ac[2] = hlf ? alo : o_alo; ac[3] = hlf ? ahi : o_ahi;
-        const double uf[4] = { hlf ? o_ulo : ulo, hlf ? o_uhi : uhi, hlf ? ulo : o_ulo, hlf ? uhi : o_uhi };
+        ac[0] = alo; ac[1] = ahi; ac[2] = other(alo); ac[3] = other(ahi);
+        const double uf[4] = { ulo, uhi, other(ulo), other(uhi) };
         ac[4] = Jcp;
         double gam[5];
 #pragma unroll
@@ -700,9 +702,10 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
             b[r] -= t * bc;
         }
     }
-    // Gaussian elimination in the order u, u, v, v, p: the velocity block has a
-    // positive definite symmetric part (mass + viscous; advection is skew) and
-    // the last pivot is the positive pressure Schur complement
+    // Gaussian elimination in the lane's order (own faces, other faces, p):
+    // the velocity block has a positive definite symmetric part (mass +
+    // viscous; advection is skew) and the last pivot is the positive pressure
+    // Schur complement
     double inv[5];
 #pragma unroll
     for (int c = 0; c < 4; c++) {
@@ -738,8 +741,7 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
             L.mu[k] = m0 + kbm - kmc * dc;
         }
     }
-    const double dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
-    const double nlo = tq(T, a.FN, e) + omega * dl, nhi = tq(T, a.FN, e + a.dn) + omega * dh;
+    const double nlo = tq(T, a.FN, e) + omega * b[0], nhi = tq(T, a.FN, e + a.dn) + omega * b[1];
     if (TO) {
         const int n = T.W * T.H;
         double *fo = T.s + (T_NF + hlf) * n;
@@ -918,19 +920,18 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         xlo = -0.5 * ih * w_o - v_o;
         xhi = 0.5 * ih * w_o - v_o;
     }
-    const double o_xlo = other(xlo), o_xhi = other(xhi);
+    // the four faces in the lane's order, its own axis first (as in the box
+    // of the primitive scheme)
     const double o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const double o_xlo = other(xlo), o_xhi = other(xhi);
     const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
-    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
-    const double wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
     double A[4][4], b[4];
-    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi;
-    const double mW = xl ? 1.0 : 0.0, mE = xh ? 1.0 : 0.0, mS = yl ? 1.0 : 0.0, mN = yh ? 1.0 : 0.0;
-    A[0][0] = hlf ? o_dlo : dlo; A[0][1] = mW * (0.5 * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd;
-    A[1][1] = hlf ? o_dhi : dhi; A[1][0] = mE * (-0.5 * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd;
-    A[2][2] = hlf ? dlo : o_dlo; A[2][3] = mS * (0.5 * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd;
-    A[3][3] = hlf ? dhi : o_dhi; A[3][2] = mN * (-0.5 * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd;
-    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    b[0] = blo; b[1] = bhi; b[2] = o_blo; b[3] = o_bhi;
+    const double m0l = hlo ? 1.0 : 0.0, m0h = hhi ? 1.0 : 0.0, m1l = o_hlo ? 1.0 : 0.0, m1h = o_hhi ? 1.0 : 0.0;
+    A[0][0] = dlo; A[0][1] = m0l * (0.5 * ih * w_ax - vis) + xlo; A[0][2] = m0l * gd; A[0][3] = -m0l * gd;
+    A[1][1] = dhi; A[1][0] = m0h * (-0.5 * ih * w_ax - vis) + xhi; A[1][2] = -m0h * gd; A[1][3] = m0h * gd;
+    A[2][2] = o_dlo; A[2][3] = m1l * (0.5 * ih * o_w - vis) + o_xlo; A[2][0] = m1l * gd; A[2][1] = -m1l * gd;
+    A[3][3] = o_dhi; A[3][2] = m1h * (-0.5 * ih * o_w - vis) + o_xhi; A[3][0] = -m1h * gd; A[3][1] = m1h * gd;
     double inv[4];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -951,8 +952,8 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         for (int t = c + 1; t < 4; t++) acc -= A[c][t] * b[t];
         b[c] = acc * inv[c];
     }
-    const double ulo = tq(T, a.FN, e) + omega * (hlf ? b[2] : b[0]);
-    const double uhi = tq(T, a.FN, e + a.dn) + omega * (hlf ? b[3] : b[1]);
+    const double ulo = tq(T, a.FN, e) + omega * b[0];
+    const double uhi = tq(T, a.FN, e + a.dn) + omega * b[1];
     if (TO) {
         double *fo = T.s + (T_NF + hlf) * st;
         if (hlo) fo[e] = ulo;

@@ -411,30 +411,27 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
         xlo = -0.5f * ih * w_o - v_o;
         xhi = 0.5f * ih * w_o - v_o;
     }
-    const float o_xlo = other(xlo), o_xhi = other(xhi);
+    // the box's unknowns in the lane's order, its own axis first (as in the
+    // FP64 box)
     const float o_blo = other(blo), o_dlo = other(dlo), o_bhi = other(bhi), o_dhi = other(dhi), o_w = other(w_ax);
+    const float o_xlo = other(xlo), o_xhi = other(xhi);
     const int o_hlo = other((int)hlo), o_hhi = other((int)hhi);
-    const bool xl = hlf ? o_hlo : hlo, xh = hlf ? o_hhi : hhi, yl = hlf ? hlo : o_hlo, yh = hlf ? hhi : o_hhi;
-    const float wx = hlf ? o_w : w_ax, wy = hlf ? w_ax : o_w;
     float A[5][5], b[5];
-    b[0] = hlf ? o_blo : blo; b[1] = hlf ? o_bhi : bhi; b[2] = hlf ? blo : o_blo; b[3] = hlf ? bhi : o_bhi; b[4] = bp;
-    const float d0 = hlf ? o_dlo : dlo, d1 = hlf ? o_dhi : dhi, d2 = hlf ? dlo : o_dlo, d3 = hlf ? dhi : o_dhi;
-    const float mW = xl ? 1.0f : 0.0f, mE = xh ? 1.0f : 0.0f, mS = yl ? 1.0f : 0.0f, mN = yh ? 1.0f : 0.0f;
-    A[0][0] = d0; A[0][1] = mW * (0.5f * ih * wx - vis); A[0][2] = mW * gd; A[0][3] = -mW * gd; A[0][4] = mW * gp;
-    A[1][1] = d1; A[1][0] = mE * (-0.5f * ih * wx - vis); A[1][2] = -mE * gd; A[1][3] = mE * gd; A[1][4] = -mE * gp;
-    A[2][2] = d2; A[2][3] = mS * (0.5f * ih * wy - vis); A[2][0] = mS * gd; A[2][1] = -mS * gd; A[2][4] = mS * gp;
-    A[3][3] = d3; A[3][2] = mN * (-0.5f * ih * wy - vis); A[3][0] = -mN * gd; A[3][1] = mN * gd; A[3][4] = -mN * gp;
-    A[4][0] = -mW * ih; A[4][1] = mE * ih; A[4][2] = -mS * ih; A[4][3] = mN * ih; A[4][4] = q.Jpp;
-    A[0][1] += hlf ? o_xlo : xlo; A[1][0] += hlf ? o_xhi : xhi; A[2][3] += hlf ? xlo : o_xlo; A[3][2] += hlf ? xhi : o_xhi;
+    b[0] = blo; b[1] = bhi; b[2] = o_blo; b[3] = o_bhi; b[4] = bp;
+    const float m0l = hlo ? 1.0f : 0.0f, m0h = hhi ? 1.0f : 0.0f, m1l = o_hlo ? 1.0f : 0.0f, m1h = o_hhi ? 1.0f : 0.0f;
+    A[0][0] = dlo; A[0][1] = m0l * (0.5f * ih * w_ax - vis) + xlo; A[0][2] = m0l * gd; A[0][3] = -m0l * gd; A[0][4] = m0l * gp;
+    A[1][1] = dhi; A[1][0] = m0h * (-0.5f * ih * w_ax - vis) + xhi; A[1][2] = -m0h * gd; A[1][3] = m0h * gd; A[1][4] = -m0h * gp;
+    A[2][2] = o_dlo; A[2][3] = m1l * (0.5f * ih * o_w - vis) + o_xlo; A[2][0] = m1l * gd; A[2][1] = -m1l * gd; A[2][4] = m1l * gp;
+    A[3][3] = o_dhi; A[3][2] = m1h * (-0.5f * ih * o_w - vis) + o_xhi; A[3][0] = -m1h * gd; A[3][1] = m1h * gd; A[3][4] = -m1h * gp;
+    A[4][0] = -m0l * ih; A[4][1] = m0h * ih; A[4][2] = -m1l * ih; A[4][3] = m1h * ih; A[4][4] = q.Jpp;
     float ac[5] = { 0.0f, 0.0f, 0.0f, 0.0f, 0.0f }, icc = 0.0f, bc = 0.0f, imm = 0.0f;
     if (cpl) {
         const int e1 = e + a.dn;
         const float alo = hlo ? 0.5f * ih * tq(T, L_RN, e - a.dn) * (tq(T, L_CN, e) - tq(T, L_CN, e - a.dn)) : 0.0f;
         const float ahi = hhi ? 0.5f * ih * tq(T, L_RN, e1) * (tq(T, L_CN, e1) - tq(T, L_CN, e)) : 0.0f;
         const float ulo = hlo ? uhlo : 0.0f, uhi = hhi ? uhhi : 0.0f;
-        const float o_alo = other(alo), o_ahi = other(ahi), o_ulo = other(ulo), o_uhi = other(uhi);
-        ac[0] = hlf ? o_alo : alo; ac[1] = hlf ? o_ahi : ahi; ac[2] = hlf ? alo : o_alo; ac[3] = hlf ? ahi : o_ahi;
-        const float uf[4] = { hlf ? o_ulo : ulo, hlf ? o_uhi : uhi, hlf ? ulo : o_ulo, hlf ? uhi : o_uhi };
+        ac[0] = alo; ac[1] = ahi; ac[2] = other(alo); ac[3] = other(ahi);
+        const float uf[4] = { ulo, uhi, other(ulo), other(uhi) };
         const float gc = 0.25f * (-P.alpha * rs * rs) * P.inv_dt;
         const float Jcp = P.alpha * P.inv_Pe * s.Sm;
         ac[4] = Jcp;
@@ -493,7 +490,7 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
             L.dmu[k] = m0 + (r2 - q.Jmc * dc) * imm;
         }
     }
-    const float dl = hlf ? b[2] : b[0], dh = hlf ? b[3] : b[1];
+    const float dl = b[0], dh = b[1];
     if (TO) {
         float *fo = T.s + (L_NF + hlf) * st;
         if (hlo) fo[e] = tq(T, a.FN, e) + omega * dl;
