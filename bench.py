@@ -594,6 +594,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-capillary", action="store_true")
     ap.add_argument("--no-paper-smoother", action="store_true")
+    ap.add_argument("--event-pass-only", action="store_true",
+                    help="skip the plain timed pass (for a profiler's trace of the event-timed pass alone, "
+                         "whose kernel averages the roofline uses); value is then the event pass's rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the time step of one simulation is a single-GPU "
@@ -636,17 +639,20 @@ def main():
     g.set_state(cfg["state"]["c"])
     for _ in range(args.warmup):
         g.step(cfg["dt"])
-    elapsed, lat, nv = timed_steps(g, cfg, args.steps)
-    value = cells * args.steps / elapsed
+    if not args.event_pass_only:
+        elapsed, lat, nv = timed_steps(g, cfg, args.steps)
     # the kernels' durations: the same steps again, the launches of the
     # dominant and the finest smoothing kernels carrying HIP events (the
     # kernel's own start and end; such launches take longer to issue, which
     # the timed region above does not pay)
     note("main: the same", args.steps, "steps; launches of", dominant, "and", finest, "carry HIP events")
     g.profile_ops(timed_ops)
-    elapsed_direct, _, nv_direct = timed_steps(g, cfg, args.steps)
+    elapsed_direct, lat_direct, nv_direct = timed_steps(g, cfg, args.steps)
     tbd = g.profile_breakdown(by_level=True)
     g.profile(0)
+    if args.event_pass_only:
+        elapsed, lat, nv = elapsed_direct, lat_direct, nv_direct
+    value = cells * args.steps / elapsed
     ttab = kernel_table(tbd, lc, opts)
 
     def roof(k):
@@ -691,6 +697,7 @@ def main():
                    "parallelism": "none"},
         "p50_ms": 1e3 * float(np.percentile(lat, 50)), "p99_ms": 1e3 * float(np.percentile(lat, 99)),
         "vcycles_per_step": float(np.mean(nv)),
+        "timed_region": "event pass (profiling run)" if args.event_pass_only else "plain steps",
         "event_timed_pass": {"ms_per_step": 1e3 * elapsed_direct / args.steps,
                              "vcycles_per_step": float(np.mean(nv_direct))},
         "roofline": rf,

@@ -13,6 +13,9 @@ Reads the CSV output of three rocprofv3 runs of the same bench command
   what the counter reads for the copy-probe kernel that bench.py runs first:
   it reads and writes 512 MiB), and the hash of the device code the counters
   were taken on (bench.py ignores a summary of other device code);
+* with ``--busy-tail SECONDS``, ``busy_<workload>.md``: the share of the
+  last SECONDS of kernel activity in which some kernel ran, and the kernels
+  of that window;
 * with ``--valu DIR`` (a ``--pmc SQ_WAVES SQ_INSTS_VALU SQ_INSTS_VALU_ADD_F64
   SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_TRANS_F64`` run),
   ``<kernel>_<workload>_valu.txt``: waves, vector-ALU wave instructions and
@@ -121,6 +124,45 @@ def valu_summaries(a):
                                           len(m["SQ_WAVES"])))
 
 
+def busy_summary(a, trace):
+    """busy_<workload>.md: the share of the last busy_tail seconds of kernel
+    activity in which at least one kernel ran (the union of the kernels'
+    intervals), and the kernels of that window"""
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short(_name(r))) for r in trace)
+    t1 = max(e for _, e, _ in iv)
+    t0 = t1 - int(a.busy_tail * 1e9)
+    busy, cur_s, cur_e = 0, None, None
+    per = {}
+    for s0, e0, k in iv:
+        if e0 <= t0:
+            continue
+        per.setdefault(k, []).append((e0 - s0) * 1e-3)
+        s0, e0 = max(s0, t0), min(e0, t1)
+        if e0 <= s0:
+            continue
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    n = sum(len(v) for v in per.values())
+    lines = ["# kernel activity of %s" % a.workload, ""]
+    lines += ["command: `%s`" % c for c in a.command]
+    lines += ["summarised by: `python -m paper_1703_06606_amd.rocprof_summary --busy-tail %.3f` (device code %s)"
+              % (a.busy_tail, device_source_hash()), "",
+              "window: the last %.3f s of kernel activity in the trace" % a.busy_tail,
+              "dispatches_in_window: %d" % n,
+              "busy_fraction: %.4f (share of the window in which at least one kernel ran)" % (busy / (t1 - t0)), "",
+              "| kernel | dispatches | avg us | total ms |", "|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        lines.append("| %s | %d | %.2f | %.3f |" % (k, len(v), statistics.mean(v), sum(v) * 1e-3))
+    with open(os.path.join(a.out, "busy_%s.md" % a.workload), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace")
@@ -137,7 +179,7 @@ def main():
     os.makedirs(a.out, exist_ok=True)
     if a.valu:
         valu_summaries(a)
-    if not (a.trace and a.fetch and a.write):
+    if not a.trace:
         return
     trace = _rows(a.trace, "kernel_trace.csv")
     durs = {}
@@ -146,27 +188,8 @@ def main():
         d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
         durs.setdefault((short(n), _grid(r)), []).append(d)
     if a.busy_tail > 0:
-        iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in trace)
-        t1 = max(e for _, e in iv)
-        t0 = t1 - int(a.busy_tail * 1e9)
-        busy, cur_s, cur_e = 0, None, None
-        for s0, e0 in iv:
-            s0, e0 = max(s0, t0), min(e0, t1)
-            if e0 <= s0:
-                continue
-            if cur_e is None or s0 > cur_e:
-                if cur_e is not None:
-                    busy += cur_e - cur_s
-                cur_s, cur_e = s0, e0
-            else:
-                cur_e = max(cur_e, e0)
-        if cur_e is not None:
-            busy += cur_e - cur_s
-        n = sum(1 for s0, e0 in iv if e0 > t0)
-        with open(os.path.join(a.out, "busy_%s.txt" % a.workload), "w") as fh:
-            fh.write("# share of the last %.3f s of kernel activity in which at least one kernel ran\n"
-                     "window_s: %.3f\ndispatches_in_window: %d\nbusy_fraction: %.4f\n" % (a.busy_tail, a.busy_tail, n, busy / (t1 - t0)))
-    if not a.kernels:
+        busy_summary(a, trace)
+    if not (a.fetch and a.write and a.kernels):
         return
     fetch, write = counters(a.fetch, "FETCH_SIZE"), counters(a.write, "WRITE_SIZE")
     fs, ws = copy_scale(fetch, COPY_BYTES), copy_scale(write, COPY_BYTES)
