@@ -36,7 +36,8 @@
  *              with the same convention in y.
  *
  * Ownership: the caller owns every host buffer; calls copy synchronously on the
- * context's stream.  The library owns all device memory of a context.  A
+ * context's stream.  The library owns all device memory of a context (taken
+ * from hipMalloc, or from the caller's allocator: qnsch_set_allocator).  A
  * context must be used from one host thread at a time.
  *
  * Errors: functions return QNSCH_OK (0) or a negative code; qnsch_last_error()
@@ -114,8 +115,9 @@ typedef struct {
     double inv_Fr;       /* 1/Fr, gravity along -y; 0 = no gravity */
     double Pe, M;        /* Peclet number and the Mach-like number M, > 0 */
     double eps;          /* interface thickness parameter, > 0 */
-    double eta;          /* interface ratio parameter, > 0 */
-    double mob_reg;      /* constant under the square root of the mobility (sec. 6.1); >= 0 */
+    double eta;          /* interface ratio parameter; <= 0 takes qnsch_default_eta(rho1, rho2) */
+    double mob_reg;      /* constant under the square root of the mobility (sec. 6.1), >= 0;
+                            < 0 takes eps, the paper's choice */
     double rho_ref;      /* density the gravity force is measured against (0 with walls in y) */
 } qnsch_params;
 
@@ -200,8 +202,9 @@ typedef struct qnsch_ctx qnsch_ctx;
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to
- * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates all
- * device memory in one allocation (qnsch_footprint: roughly 150 bytes per
+ * run on, or NULL for the default stream.  opts NULL = defaults.  Allocates its
+ * device memory in two blocks, the level descriptors and the fields of every
+ * level, from hipMalloc or the allocator of qnsch_set_allocator (qnsch_footprint: roughly 150 bytes per
  * finest cell in FP64, 182 in mixed precision, plus 80 (accel + 1) for the
  * acceleration's history and 32 (16 in mixed precision) for the second cell
  * set of temporal blocking).  Returns
@@ -283,6 +286,24 @@ int qnsch_dissipation(qnsch_ctx *ctx, double out[5]);
  *            height of a capillary wave at its crest), NaN if none;
  *   out[7] = h^2 sum div_d u (zero with walls or periodic boundaries). */
 int qnsch_diagnostics(qnsch_ctx *ctx, double out[8]);
+/* Device memory of contexts.  By default a context takes its device arrays
+ * (one block for the level descriptors, one for every level's fields, and
+ * the residual fields qnsch_residual returns, at its first call) from
+ * hipMalloc and returns them with hipFree at qnsch_destroy.  For callers
+ * whose framework owns device memory: after qnsch_set_allocator(alloc,
+ * free_fn, user), contexts created from then on (server contexts included)
+ * take every such block from alloc(bytes, user) and return it with
+ * free_fn(ptr, bytes, user) when destroyed; a context keeps the functions it
+ * was created with.  alloc must return memory of the current device that this
+ * library's HIP runtime can address, aligned to 256 bytes, or NULL (the call
+ * that needed it then fails with QNSCH_ENOMEM and frees what it took).
+ * qnsch_set_allocator(NULL, NULL, NULL) restores hipMalloc / hipFree.  Pinned
+ * host staging buffers always come from hipHostMalloc.  Process-wide and
+ * thread-safe; QNSCH_EINVAL if exactly one of the functions is NULL. */
+typedef void *(*qnsch_alloc_fn)(size_t bytes, void *user);
+typedef void (*qnsch_free_fn)(void *ptr, size_t bytes, void *user);
+int qnsch_set_allocator(qnsch_alloc_fn alloc, qnsch_free_fn free_fn, void *user);
+
 /* Launches of a cycle (qnsch_step, qnsch_vcycle): with enable != 0 the
  * operations of a cycle before its residual reduction are captured once into
  * an executable HIP graph (per pattern of the levels' double-buffered faces,

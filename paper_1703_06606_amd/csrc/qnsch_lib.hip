@@ -145,6 +145,17 @@ static void begin_program(int L, bool mixed, std::vector<Op> &out)
 // contexts
 
 namespace {
+// device memory of contexts: hipMalloc / hipFree, or the functions set by
+// qnsch_set_allocator (taken by a context when it is created; it frees with
+// the functions it allocated with)
+struct Allocator {
+    qnsch_alloc_fn alloc = nullptr;
+    qnsch_free_fn free = nullptr;
+    void *user = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
 struct DLev {
     int m1 = 0, m2 = 0, pitch = 0;
     double h = 0;
@@ -162,7 +173,8 @@ struct qnsch_ctx {
     Desc *hd = nullptr;   // pinned host copy of the level descriptors
     Desc *dd = nullptr;   // device descriptors
     hipStream_t s = nullptr;
-    std::vector<void *> allocs;
+    Allocator al;                                    // device memory functions of this context
+    std::vector<std::pair<void *, size_t>> allocs;   // device blocks and their sizes
     double *red_host = nullptr; // pinned
     double *stage = nullptr;    // pinned staging for state transfers (server contexts)
     void *arena = nullptr;      // the device arrays (one allocation)
@@ -774,14 +786,35 @@ static int read_red(qnsch_ctx *x)
     return QNSCH_OK;
 }
 
-static double *dalloc(qnsch_ctx *x, size_t n, int *rc)
+// a device block of the context (256-byte aligned), or nullptr with the
+// message in x->err
+static void *dev_alloc(qnsch_ctx *x, size_t bytes)
 {
     void *p = nullptr;
-    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) {
+    if (x->al.alloc) {
+        p = x->al.alloc(bytes, x->al.user);
+        if (p && ((uintptr_t)p & 255)) {
+            x->al.free(p, bytes, x->al.user);
+            x->err = "allocator returned memory not aligned to 256 bytes";
+            return nullptr;
+        }
+        if (!p) x->err = "allocator returned NULL";
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        x->err = "hipMalloc failed";
+        p = nullptr;
+    }
+    if (p) x->allocs.push_back({ p, bytes });
+    return p;
+}
+
+static double *dalloc(qnsch_ctx *x, size_t n, int *rc)
+{
+    void *p = dev_alloc(x, n * sizeof(double));
+    if (!p) {
         *rc = QNSCH_ENOMEM;
         return nullptr;
     }
-    x->allocs.push_back(p);
     x->footprint += n * sizeof(double);
     if (hipMemsetAsync(p, 0, n * sizeof(double), x->s) != hipSuccess) *rc = QNSCH_EDEVICE;
     return (double *)p;
@@ -932,7 +965,10 @@ void qnsch_destroy(qnsch_ctx *x)
 {
     if (!x) return;
     (void)hipStreamSynchronize(x->s);
-    for (void *p : x->allocs) (void)hipFree(p);
+    for (auto &a : x->allocs) {
+        if (x->al.free) x->al.free(a.first, a.second, x->al.user);
+        else (void)hipFree(a.first);
+    }
     for (hipEvent_t e : x->pev) (void)hipEventDestroy(e);
     if (x->ev) (void)hipEventDestroy(x->ev);
     for (auto &c : x->cyc_graphs) (void)hipGraphExecDestroy(c.second);
@@ -954,9 +990,20 @@ static int validate_grid_params(const qnsch_grid *g, const qnsch_params *p)
     if (fabs(hx - hy) > 1e-12 * hx) return QNSCH_EINVAL;
     if ((g->bc_x != 0 && g->bc_x != 1) || (g->bc_y != 0 && g->bc_y != 1)) return QNSCH_EINVAL;
     if (!(p->rho1 > 0) || !(p->rho2 > 0) || !(p->visc1 > 0) || !(p->visc2 > 0) || !(p->Re > 0) || !(p->We > 0)
-        || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || !(p->eta > 0) || !(p->mob_reg >= 0))
+        || !(p->Pe > 0) || !(p->M > 0) || !(p->eps > 0) || std::isnan(p->eta) || std::isnan(p->mob_reg))
         return QNSCH_EINVAL;
     return QNSCH_OK;
+}
+
+// the parameters with their defaults filled in: eta <= 0 takes the interface
+// ratio of sec. 8.1 for the density pair, mob_reg < 0 takes eps (the constant
+// under the square root of the mobility in sec. 6.1)
+static qnsch_params resolve_params(const qnsch_params &p)
+{
+    qnsch_params q = p;
+    if (!(q.eta > 0)) q.eta = qnsch_default_eta(q.rho1, q.rho2);
+    if (q.mob_reg < 0) q.mob_reg = q.eps;
+    return q;
 }
 
 static int validate(const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o)
@@ -994,9 +1041,9 @@ static void resolve_opts(qnsch_opts &o, int nlev)
 // physical parameters of every level descriptor (host copy)
 static void set_params(qnsch_ctx *x, const qnsch_params *p)
 {
-    x->prm = *p;
+    x->prm = resolve_params(*p);
     Phys P;
-    phys_of(p, P);
+    phys_of(&x->prm, P);
     P.coupled = x->opt.smoother == QNSCH_SMOOTH_COUPLED;
     P.scheme = x->opt.scheme == QNSCH_PROJECTION;
     const PhysF Pf = physf_of(P);
@@ -1035,10 +1082,14 @@ static size_t device_lds_max()
 static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream)
 {
     int rc = QNSCH_OK;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        x->al = g_alloc;
+    }
     x->g = *g;
     x->nlev = level_count(g);
     x->g.levels = x->nlev;
-    x->prm = *p;
+    x->prm = resolve_params(*p);
     qnsch_default_opts(&x->opt);
     if (o) x->opt = *o;
     resolve_opts(x->opt, x->nlev);
@@ -1057,15 +1108,13 @@ static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, co
         return QNSCH_ENOMEM;
     memset((void *)x->hd, 0, x->nlev * sizeof(Desc));
     memset(x->red_host, 0, 16 * sizeof(double));
-    void *ddp = nullptr;
-    if (hipMalloc(&ddp, x->nlev * sizeof(Desc)) != hipSuccess) return QNSCH_ENOMEM;
-    x->allocs.push_back(ddp);
+    void *ddp = dev_alloc(x, x->nlev * sizeof(Desc));
+    if (!ddp) return QNSCH_ENOMEM;
     x->dd = (Desc *)ddp;
     const bool mixed = is_mixed(x);
     const size_t bytes = carve(g, x->nlev, mixed, x->opt.accel, two_sets(x->opt), nullptr, nullptr);
-    void *arena = nullptr;
-    if (hipMalloc(&arena, bytes) != hipSuccess) return QNSCH_ENOMEM;
-    x->allocs.push_back(arena);
+    void *arena = dev_alloc(x, bytes);
+    if (!arena) return QNSCH_ENOMEM;
     x->arena = arena;
     x->arena_bytes = bytes;
     x->footprint = bytes + (size_t)x->nlev * sizeof(Desc);
@@ -1528,6 +1577,16 @@ int qnsch_profile_ops(qnsch_ctx *x, uint64_t op_mask)
     return profile_reset(x, op_mask ? 1 : 0, op_mask, false);
 }
 
+int qnsch_set_allocator(qnsch_alloc_fn alloc, qnsch_free_fn free_fn, void *user)
+{
+    if ((alloc == nullptr) != (free_fn == nullptr)) return QNSCH_EINVAL;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free = free_fn;
+    g_alloc.user = alloc ? user : nullptr;
+    return QNSCH_OK;
+}
+
 int qnsch_graphs(qnsch_ctx *x, int enable)
 {
     if (!x) return QNSCH_EINVAL;
@@ -1679,7 +1738,8 @@ int qnsch_residual_noalloc(const qnsch_grid *g, const qnsch_params *prm, double 
     Desc d;
     memset((void *)&d, 0, sizeof(d));
     Phys P;
-    phys_of(prm, P);
+    const qnsch_params pr = resolve_params(*prm);
+    phys_of(&pr, P);
     P.inv_dt = 1.0 / dt;
     P.dt = dt;
     d.P = P;
@@ -2043,7 +2103,7 @@ int qnsch_server_submit(qnsch_server *S, const qnsch_grid *g, const qnsch_params
     Req *r = new Req();
     r->id = S->next_id++;
     r->g = *g;
-    r->p = *p;
+    r->p = resolve_params(*p);
     qnsch_default_opts(&r->o);
     if (o) r->o = *o;
     resolve_opts(r->o, level_count(g));

@@ -23,7 +23,7 @@ SYMBOLS = ("qnsch_default_opts", "qnsch_create", "qnsch_destroy", "qnsch_last_er
            "qnsch_accelerate",
            "qnsch_residual", "qnsch_halfsweep", "qnsch_end_step", "qnsch_lin_apply", "qnsch_mass", "qnsch_energy",
            "qnsch_dissipation", "qnsch_diagnostics", "qnsch_stats",
-           "qnsch_synchronize", "qnsch_graphs", "qnsch_profile", "qnsch_profile_ops", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
+           "qnsch_synchronize", "qnsch_set_allocator", "qnsch_graphs", "qnsch_profile", "qnsch_profile_ops", "qnsch_profile_read", "qnsch_profile_breakdown", "qnsch_copy_probe",
            "qnsch_footprint", "qnsch_server_create", "qnsch_server_destroy", "qnsch_server_last_error", "qnsch_server_submit",
            "qnsch_server_progress", "qnsch_server_poll", "qnsch_server_result", "qnsch_server_stats",
            "qnsch_server_latency",
@@ -69,6 +69,13 @@ class StepStats(C.Structure):
 
 
 _lib = None
+# qnsch_alloc_fn / qnsch_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p)
+# every pair of callbacks ever given to the library, kept alive for the
+# process: a context calls the functions it was created with until it is
+# destroyed, also after the allocator was changed
+_allocators = []
 
 
 def lib():
@@ -108,6 +115,7 @@ def lib():
         L.qnsch_stats.argtypes = [vp, C.POINTER(StepStats)]
         L.qnsch_synchronize.argtypes = [vp]
         L.qnsch_graphs.argtypes = [vp, C.c_int]
+        L.qnsch_set_allocator.argtypes = [ALLOC_FN, FREE_FN, vp]
         L.qnsch_profile.argtypes = [vp, C.c_int]
         L.qnsch_profile_ops.argtypes = [vp, C.c_uint64]
         L.qnsch_profile_read.argtypes = [vp, P]
@@ -136,6 +144,22 @@ def lib():
 
 def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def set_allocator(alloc=None, free=None):
+    """device memory of contexts created from now on: alloc(bytes) -> int
+    device address (256-byte aligned, 0 on failure) and free(address, bytes),
+    or both None for hipMalloc / hipFree (qnsch_set_allocator)"""
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        rc = lib().qnsch_set_allocator(ALLOC_FN(), FREE_FN(), None)
+    else:
+        cbs = (ALLOC_FN(lambda n, user: alloc(n) or None), FREE_FN(lambda ptr, n, user: free(ptr, n)))
+        _allocators.append(cbs)
+        rc = lib().qnsch_set_allocator(cbs[0], cbs[1], None)
+    if rc != OK:
+        raise QnschError(rc, "qnsch_set_allocator failed")
 
 
 def copy_probe(n_doubles, reps=20):
