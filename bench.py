@@ -258,6 +258,14 @@ def cpu_baseline(c1_repeats=3, c2_steps=2):
         assert o.step(c1["dt"]) == OR.OK
         lat1.append(time.perf_counter() - t0)
         nv1.append(o.stats()[0])
+    # the same step on one thread (the oracle's arithmetic does not depend on
+    # the thread count)
+    OR.threads(1)
+    o.set_state(c1["state"]["c"])
+    t0 = time.perf_counter()
+    assert o.step(c1["dt"]) == OR.OK
+    t1s = time.perf_counter() - t0
+    OR.threads(threads)
     c2 = W.rising_drop()
     o = OR.Oracle(c2["grid"], c2["params"], dict(W.default_opts(1e-8), accel=ACCEL))
     o.set_state(c2["state"]["c"])
@@ -276,7 +284,8 @@ def cpu_baseline(c1_repeats=3, c2_steps=2):
                       % (threads, model, ncpu, c2_steps, c2["grid"]["m1"], c2["grid"]["m2"], t2, nv2, c1_repeats,
                          nv1),
             "capillary_32x64": {"p50_ms": 1e3 * float(np.percentile(lat1, 50)),
-                                "cell_steps_per_s": 2048 / float(np.mean(lat1))},
+                                "cell_steps_per_s": 2048 / float(np.mean(lat1)),
+                                "single_thread_ms": 1e3 * t1s},
             "rising_drop_256x512": {"s_per_step": t2 / c2_steps, "vcycles": nv2}}
 
 
