@@ -502,70 +502,30 @@ __device__ __forceinline__ double rw_cell(const double *f, int pitch, int I, int
 // pair each; N_H is evaluated on a coarse tile whose halo takes R w from the
 // fine arrays directly (the neighbouring workgroups write the coarse iterate
 // meanwhile).
-template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
+#define RBLK (2 * TBLK)
+template <typename IT> __global__ __launch_bounds__(RBLK) void k_restrict(IT it)
 {
     __shared__ double sm[TILE_DOUBLES];
-    __shared__ double part[(TX / 2) * (TY / 2)][2][8];
-    __shared__ double rr[(TX / 2) * (TY / 2)][2][4];
+    __shared__ double smc[T_NF * (TX / 2 + 3) * (TY / 2 + 3)];
+    // sums of the three fine cells of a coarse cell other than its (0, 0)
+    // child: the x lane's residuals and iterate (rc, rm, rp, rf, c, mu, p,
+    // u face), the y lane's face residual and v face
+    __shared__ double part[3][(TX / 2) * (TY / 2)][10];
     const int k = find_item(it);
     const Desc &d = *it.d[k];
     if (!tile_valid(it, k, d)) return;
     const Desc &C = *d.coarse;
+    const int cp = it.cpar[k];
     const View Lf = view_of(d, it.par[k]);
+    const View Lc = view_of(C, cp);
     const Tile T = item_tile(sm, it, k, d);
     tile_load(d.P, Lf, T);
-    __syncthreads();
-    // lane pair pr: coarse cell cc of the tile, fine row b of it (both
-    // halves of the workgroup busy); the b = 1 pairs hand their sums to the
-    // b = 0 pairs through LDS
-    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
-    const int NC = (TX / 2) * (TY / 2);
-    const int cc = pr % NC, b = pr / NC;
-    const int I = T.i0 / 2 + cc % (TX / 2), J = T.j0 / 2 + cc / (TX / 2);
-    const bool on = b < 2 && I < C.m1 && J < C.m2;
-    double v[8] = { 0, 0, 0, 0, 0, 0, 0, 0 }; // rc, rm, rp, rf, sc, smu, sp, sf
-    if (on) {
-        const int fN = hlf ? T_V : T_U;
-        const Rhs F = rhs_of(d);
-#pragma unroll
-        for (int a = 0; a < 2; a++) {
-            const int i = 2 * I + a, j = 2 * J + b;
-            double xc, xm, xp, xf;
-            resid_pair(d.P, Lf, T, F, i, j, hlf, xc, xm, xp, xf);
-            v[0] += xc; v[1] += xm; v[2] += xp;
-            // the lane's faces of the coarse cell: west faces (a = 0) on the
-            // x lane, south faces (b = 0) on the y lane
-            if ((hlf ? b : a) == 0) { v[3] += xf; v[7] += T.q(fN, i, j); }
-            v[4] += T.q(T_C, i, j); v[5] += T.q(T_MU, i, j); v[6] += T.q(T_P, i, j);
-        }
-        if (b == 1)
-#pragma unroll
-            for (int q = 0; q < 8; q++) part[cc][hlf][q] = v[q];
-    }
-    __syncthreads();
-    const int cp = it.cpar[k];
-    if (on && b == 0) {
-#pragma unroll
-        for (int q = 0; q < 8; q++) v[q] += part[cc][hlf][q];
-        const size_t q = (size_t)J * C.pitch + I;
-        if (hlf == 0) {
-            C.c[q] = C.c0[q] = 0.25 * v[4];
-            C.mu[q] = C.mu0[q] = 0.25 * v[5];
-            C.p[q] = C.p0[q] = 0.25 * v[6];
-            C.ub[cp][q] = C.u0[q] = 0.5 * v[7];
-            rr[cc][0][0] = 0.25 * v[0];
-            rr[cc][0][1] = 0.25 * v[1];
-            rr[cc][0][2] = 0.25 * v[2];
-            rr[cc][0][3] = 0.5 * v[3];
-        } else {
-            C.vb[cp][q] = C.v0[q] = 0.5 * v[7];
-            rr[cc][1][3] = 0.5 * v[3];
-        }
-    }
-    // the coarse tile of R w (the fine tile is not read any more)
+    // the coarse tile of R w, from the fine arrays directly (its halo lies
+    // in the neighbouring workgroups' tiles), loaded together with the fine
+    // tile: cells the mean of the four children, faces the mean of the two
+    // coincident fine faces
     Tile Tc;
-    Tc.s = sm; Tc.i0 = T.i0 / 2; Tc.j0 = T.j0 / 2; Tc.W = TX / 2 + 3; Tc.H = TY / 2 + 3;
-    const View Lc = view_of(C, cp);
+    Tc.s = smc; Tc.i0 = T.i0 / 2; Tc.j0 = T.j0 / 2; Tc.W = TX / 2 + 3; Tc.H = TY / 2 + 3;
     {
         const int n = Tc.W * Tc.H;
         for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -598,20 +558,69 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_restrict(IT it)
         }
     }
     __syncthreads();
-    // f_H = N_H(R w) + R r on the coarse cells, a lane pair each
-    if (pr < NC && I < C.m1 && J < C.m2 && cc == pr) {
-        const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
-        double rc, rm, rp, rf;
-        resid_pair(C.P, Lc, Tc, Z, I, J, hlf, rc, rm, rp, rf); // r = -N_H(R w)
-        const size_t q = (size_t)J * C.pitch + I;
-        if (hlf == 0) {
-            C.fc[q] = rr[cc][0][0] - rc;
-            C.fmu[q] = rr[cc][0][1] - rm;
-            C.fp[q] = rr[cc][0][2] - rp;
-            C.fu[q] = u_unk(Lc, I) ? rr[cc][0][3] - rf : 0.0;
-        } else {
-            C.fv[q] = v_unk(Lc, J) ? rr[cc][1][3] - rf : 0.0;
+    // lane pair pr: coarse cell cc of the tile, fine child (a, b) = (ch & 1,
+    // ch >> 1) of it; children other than (0, 0) hand their values to the
+    // (0, 0) pair through LDS
+    const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
+    const int NC = (TX / 2) * (TY / 2);
+    const int cc = pr % NC, ch = pr / NC, a = ch & 1, b = ch >> 1;
+    const int I = T.i0 / 2 + cc % (TX / 2), J = T.j0 / 2 + cc / (TX / 2);
+    const bool on = I < C.m1 && J < C.m2;
+    double v[8] = { 0, 0, 0, 0, 0, 0, 0, 0 }; // rc, rm, rp, rf, c, mu, p, face
+    if (on) {
+        const int i = 2 * I + a, j = 2 * J + b;
+        double xc, xm, xp, xf;
+        resid_pair(d.P, Lf, T, rhs_of(d), i, j, hlf, xc, xm, xp, xf);
+        v[0] = xc; v[1] = xm; v[2] = xp;
+        // the lane's faces of the coarse cell: west faces (a = 0) on the x
+        // lane, south faces (b = 0) on the y lane
+        if ((hlf ? b : a) == 0) { v[3] = xf; v[7] = T.q(hlf ? T_V : T_U, i, j); }
+        v[4] = T.q(T_C, i, j); v[5] = T.q(T_MU, i, j); v[6] = T.q(T_P, i, j);
+        if (ch > 0) {
+            double *o = part[ch - 1][cc];
+            if (hlf == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; q++) o[q] = v[q];
+            } else {
+                o[8] = v[3];
+                o[9] = v[7];
+            }
         }
+    }
+    __syncthreads();
+    if (!on || ch != 0) return;
+    // sums over the four children as (0,0) + (1,0) plus (0,1) + (1,1), the
+    // order in which the coarse tile's R w was summed (rw_cell)
+    if (hlf == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; q++) v[q] = (v[q] + part[0][cc][q]) + (part[1][cc][q] + part[2][cc][q]);
+    } else {
+#pragma unroll
+        for (int g = 0; g < 3; g++) {
+            v[3] += part[g][cc][8];
+            v[7] += part[g][cc][9];
+        }
+    }
+    const size_t q = (size_t)J * C.pitch + I;
+    if (hlf == 0) {
+        C.c[q] = C.c0[q] = 0.25 * v[4];
+        C.mu[q] = C.mu0[q] = 0.25 * v[5];
+        C.p[q] = C.p0[q] = 0.25 * v[6];
+        C.ub[cp][q] = C.u0[q] = 0.5 * v[7];
+    } else {
+        C.vb[cp][q] = C.v0[q] = 0.5 * v[7];
+    }
+    // f_H = N_H(R w) + R r on the coarse cell
+    const Rhs Z = { nullptr, nullptr, nullptr, nullptr, nullptr };
+    double rc, rm, rp, rf;
+    resid_pair(C.P, Lc, Tc, Z, I, J, hlf, rc, rm, rp, rf); // r = -N_H(R w)
+    if (hlf == 0) {
+        C.fc[q] = 0.25 * v[0] - rc;
+        C.fmu[q] = 0.25 * v[1] - rm;
+        C.fp[q] = 0.25 * v[2] - rp;
+        C.fu[q] = u_unk(Lc, I) ? 0.5 * v[3] - rf : 0.0;
+    } else {
+        C.fv[q] = v_unk(Lc, J) ? 0.5 * v[3] - rf : 0.0;
     }
 }
 

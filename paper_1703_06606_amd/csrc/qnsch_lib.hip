@@ -592,7 +592,7 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             for (auto &pe : part) pe.first->L[pe.second].cur ^= 1;
             break;
         }
-        case OP_RESTRICT: KLAUNCH(k_restrict, W, dim3(W.blocks), dim3(TBLK), 0, s); break;
+        case OP_RESTRICT: KLAUNCH(k_restrict, W, dim3(W.blocks), dim3(RBLK), 0, s); break;
         case OP_COARSE:
         case OP_SMOOTH: {
             int nmax = 0;
