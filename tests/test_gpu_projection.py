@@ -191,6 +191,25 @@ def test_projection_full_size_rising_drop():
     say("projection full size V-cycles", g.stats()["vcycles"])
 
 
+def test_projection_rayleigh_taylor_full_size_vcycle():
+    """512 x 2048 Rayleigh-Taylor grid in the projection scheme (4096 finest
+    tiles, 9 levels down to a 2 x 8 level periodic in x): one V-cycle field by
+    field against the oracle (1e-10)"""
+    cfg = W.rayleigh_taylor()
+    say("projection full size", cfg["name"])
+    g, o = pair(cfg, pj())
+    for s in (g, o):
+        s.set_state(cfg["state"]["c"])
+        s.begin_step(cfg["dt"])
+    g.vcycle()
+    say("oracle V-cycle at 512 x 2048")
+    o.vcycle()
+    a, b = g.get_state(), o.get_state()
+    for k in FIELDS:
+        say(k, rel(a[k], b[k], 1e-9))
+        assert rel(a[k], b[k], 1e-9) < 1e-10, (k, rel(a[k], b[k], 1e-9))
+
+
 def test_projection_rejections():
     cfg = W.rising_drop(16, 32, eps=0.08)
     with pytest.raises(Q.QnschError):
