@@ -193,13 +193,21 @@ def test_projection_full_size_rising_drop():
 
 def test_projection_rayleigh_taylor_full_size_vcycle():
     """512 x 2048 Rayleigh-Taylor grid in the projection scheme (4096 finest
-    tiles, 9 levels down to a 2 x 8 level periodic in x): one V-cycle field by
+    tiles, 9 levels down to a 2 x 8 level periodic in x), moving with a
+    discretely divergence-free velocity (u = D_y psi, v = -D_x psi from a
+    stream function at the vertices, zero on the walls): one V-cycle field by
     field against the oracle (1e-10)"""
     cfg = W.rayleigh_taylor()
+    m2, m1 = cfg["state"]["c"].shape
+    h = 1.0 / m1
+    xv, yv = np.arange(m1 + 1) * h, np.arange(m2 + 1) * h
+    psi = 0.05 * np.sin(np.pi * yv / (m2 * h))[:, None] ** 2 * np.cos(2 * np.pi * xv)[None, :]
+    u0 = (psi[1:, :m1] - psi[:-1, :m1]) / h
+    v0 = -(psi[:m2, 1:] - psi[:m2, :-1]) / h
     say("projection full size", cfg["name"])
     g, o = pair(cfg, pj())
     for s in (g, o):
-        s.set_state(cfg["state"]["c"])
+        s.set_state(cfg["state"]["c"], None, None, u0, v0)
         s.begin_step(cfg["dt"])
     g.vcycle()
     say("oracle V-cycle at 512 x 2048")
