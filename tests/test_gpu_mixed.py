@@ -200,7 +200,8 @@ def test_mixed_full_size_rayleigh_taylor():
     """512 x 2048 Rayleigh-Taylor (the mixed-precision comparison workload) at
     full size: two mixed steps against two FP64 GPU steps (1e-6 relative),
     the oracle's own residual at the first mixed solution (<= 2e-8 at tol
-    1e-8), total mass to 1e-8"""
+    1e-8) and the oracle's own converged step (1e-6 relative), total mass to
+    1e-8"""
     cfg = W.rayleigh_taylor()
     say("mixed full size", cfg["name"])
     opts = W.default_opts(1e-8)
@@ -217,6 +218,13 @@ def test_mixed_full_size_rayleigh_taylor():
             o.set_time_n_and_iterate(dict(c=cfg["state"]["c"]), gm.get_state(), cfg["dt"])
             _, no = o.residual()
             assert no.max() <= 2e-8, no
+            # the oracle's own converged FP64 step from the same state
+            o.set_state(cfg["state"]["c"])
+            assert o.step(cfg["dt"]) == OR.OK
+            a, b = gm.get_state(), o.get_state()
+            for k in FIELDS:
+                say("mixed vs oracle step", k, rel(a[k], b[k], 1e-9))
+                assert rel(a[k], b[k], 1e-9) < MIXED_TOL, (k, rel(a[k], b[k], 1e-9))
             del o
         say("step", step, "mixed outer", gm.stats()["vcycles"], "fp64 V-cycles", gd.stats()["vcycles"])
     a, b = gm.get_state(), gd.get_state()
