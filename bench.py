@@ -590,7 +590,7 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=200)
     ap.add_argument("--serve-requests", type=int, default=64)
     ap.add_argument("--serve-steps", type=int, default=50)
-    ap.add_argument("--serve-lanes", type=int, default=2)
+    ap.add_argument("--serve-lanes", type=int, default=3)
     ap.add_argument("--no-seq", action="store_true", help="skip the sequential baselines of the served run")
     ap.add_argument("--no-serve-scale", action="store_true", help="skip the serving-at-scale workload")
     ap.add_argument("--scale-boxes", type=int, default=16)

@@ -385,7 +385,7 @@ def footprint(grid, opts=None):
 class Server:
     """Continuous-batching server of many simulations (qnsch_server_*)."""
 
-    def __init__(self, hbm_budget, max_slots, lanes=2, stream=None):
+    def __init__(self, hbm_budget, max_slots, lanes=3, stream=None):
         h = C.c_void_p()
         rc = lib().qnsch_server_create(int(hbm_budget), int(max_slots), int(lanes),
                                        C.c_void_p(stream) if stream else None, C.byref(h))
