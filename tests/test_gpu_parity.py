@@ -312,6 +312,34 @@ def test_dissipation_and_energy_law(name):
         assert abs(e1[0] - e0[0] + dg.sum()) < 1e-12, (e1[0] - e0[0], dg)
 
 
+@pytest.mark.parametrize("prec", [Q.FP64, Q.MIXED], ids=["fp64", "mixed"])
+def test_long_run_mass_and_energy(prec):
+    """400 steps of a 64 x 128 rising droplet (walls, density ratio 10, tol
+    1e-10): the total mass of each component stays at its initial value
+    (1e-12 relative in FP64, 1e-8 in mixed precision, the paper's bound),
+    the discrete energy never increases, and in FP64 every step satisfies
+    E^{n+1} - E^n + D = 0 (Theorem of sec. 6.1) to 1e-12"""
+    cfg = W.rising_drop(64, 128, eps=0.02)
+    say("long run", prec)
+    g = Q.Solver(cfg["grid"], cfg["params"], dict(W.default_opts(1e-10), precision=prec))
+    g.set_state(cfg["state"]["c"])
+    m0 = g.mass()
+    e_prev = g.energy()[0]
+    mtol = 1e-12 if prec == Q.FP64 else 1e-8
+    for step in range(400):
+        assert g.step(cfg["dt"]) == Q.OK, step
+        e = g.energy()[0]
+        assert e <= e_prev + 1e-13 * abs(e_prev), (step, e, e_prev)
+        if prec == Q.FP64 and step % 20 == 0:
+            d = g.dissipation()
+            assert (d >= 0).all() and abs(e - e_prev + d.sum()) < 1e-12, (step, e - e_prev, d)
+        e_prev = e
+        if step % 50 == 49:
+            m = g.mass()
+            assert np.abs(m - m0).max() <= mtol * np.abs(m0).max(), (step, m - m0)
+    say("long run", prec, "energy", e_prev, "mass drift", np.abs(g.mass() - m0).max() / np.abs(m0).max())
+
+
 def _to_fine(c):
     """bilinear interpolation of a cell-centred field to the grid of half the
     spacing, with mirror images at the walls (second order)"""
