@@ -34,6 +34,9 @@ Beside it, on the same JSON line:
              one step, p50/p99 latency;
   paper_smoother -- the droplet with the printed smoother of sec. 7.1 and
              plain cycles;
+  paper_table2 -- the GPU's seconds per step on the grids of the paper's
+             Table 2 (the convergence-study workload) beside the paper's own
+             CPU seconds per step, quoted with its hardware as context;
   cpu_baseline -- the FP64 CPU oracle on the host's cores: the capillary
              step in full and full droplet steps.
 """
@@ -357,6 +360,46 @@ def run_mixed(steps, tol):
     return out
 
 
+# the paper's own timings of the primitive method (Table 2: average CPU time
+# per time step on the convergence test of sec. 9, one desktop with a 4.0 GHz
+# AMD FX-8350; thread count, physical parameters and multigrid tolerance not
+# stated): context for the GPU's time per step on the same grids, not a target
+PAPER_TABLE2_S_PER_STEP = {16: 2.913e-2, 32: 1.659e-1, 64: 2.659e-1, 128: 1.027, 256: 2.622}
+
+
+def run_paper_table2(steps=20):
+    """the convergence-study workload of sec. 9 (walls, the bounded initial
+    condition, density ratio 3, dt = (1/16)(16/m)^2) on the grids of the
+    paper's Table 2, FP64 to 1e-8: GPU seconds per step beside the paper's CPU
+    seconds per step"""
+    out = {"source": "Table 2 of the paper: primitive method, average CPU time per step on the convergence "
+                     "test of sec. 9, one 4.0 GHz AMD FX-8350 desktop (threads, parameters and tolerance not "
+                     "stated); the GPU runs this repository's reading of that workload (its printed initial "
+                     "condition crosses the density pole), FP64, tol 1e-8, %d steps from the initial state" % steps,
+           "grids": {}}
+    for m in sorted(PAPER_TABLE2_S_PER_STEP):
+        cfg = W.convergence_case(m)
+        note("paper Table 2 grid:", cfg["name"], steps, "steps")
+        g = Q.Solver(cfg["grid"], cfg["params"], base_opts(1e-8))
+        g.set_state(cfg["state"]["c"])
+        g.step(cfg["dt"])
+        g.set_state(cfg["state"]["c"])
+        g.synchronize()
+        nv = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.step(cfg["dt"])
+            nv.append(g.stats()["vcycles"])
+        g.synchronize()
+        s_gpu = (time.perf_counter() - t0) / steps
+        s_cpu = PAPER_TABLE2_S_PER_STEP[m]
+        out["grids"]["%dx%d" % (m, m)] = {"gpu_s_per_step": s_gpu, "gpu_vcycles_per_step": float(np.mean(nv)),
+                                          "paper_cpu_s_per_step": s_cpu, "paper_cpu_cell_steps_per_s": m * m / s_cpu,
+                                          "gpu_cell_steps_per_s": m * m / s_gpu, "ratio": s_cpu / s_gpu}
+        del g
+    return out
+
+
 def run_capillary(repeats=100, warmup=3):
     """capillary 32 x 64 (periodic in x, walls in y, 4 levels), FP64 to a
     residual of 1e-10: the same step from the same state `repeats` times after
@@ -603,6 +646,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-capillary", action="store_true")
     ap.add_argument("--no-paper-smoother", action="store_true")
+    ap.add_argument("--no-paper-table2", action="store_true")
     ap.add_argument("--event-pass-only", action="store_true",
                     help="skip the plain timed pass (for a profiler's trace of the event-timed pass alone, "
                          "whose kernel averages the roofline uses); value is then the event pass's rate")
@@ -720,6 +764,8 @@ def main():
         out["capillary"] = run_capillary()
     if not args.no_paper_smoother:
         out["paper_smoother"] = run_paper_smoother(min(args.steps, 30), args.warmup, args.tol, value)
+    if not args.no_paper_table2:
+        out["paper_table2"] = run_paper_table2()
     if not args.no_projection:
         out["projection"] = run_projection(args.steps, args.warmup, args.tol, value)
     if not args.no_mixed:
