@@ -683,8 +683,9 @@ def main():
     ktab = kernel_table(bd, lc, opts)
     smoothers = [k for k in ktab if ktab[k]["alg_bytes"] is not None]
     dominant = max(smoothers, key=lambda k: ktab[k]["ms"])
-    fine_fused = BLOCKING is not None and BLOCKING >= 2
-    finest = "k_hs_fused" if fine_fused else "k_halfsweep_fine"
+    # the finest level's smoothing kernel: fused sweeps where blocking covers
+    # the finest level, else the half-sweeps
+    finest = "k_halfsweep_fine" if ("halfsweep", 0) in bd else "k_hs_fused"
     timed_ops = sorted(ktab[dominant]["ops"] | (ktab[finest]["ops"] if finest in ktab else set()))
 
     # the timed region: the steps as they run for any caller

@@ -139,15 +139,18 @@ typedef struct {
     int32_t accel;       /* depth m (0..3) of the acceleration of the cycle iteration
                             below; 0 = plain cycles */
     int32_t blocking;    /* temporal blocking of the smoothing (below): 0 = off,
-                            1 = coarse levels, 2 = the finest level too */
+                            1 = coarse levels, and the finest level where it has at
+                            most one 16 x 16 tile per compute unit, 2 = the finest
+                            level also with two */
 } qnsch_opts;
 
 /* Temporal blocking (a performance variant of the smoother of sec. 7.1; the
  * iterates are those of the plain half-sweeps up to rounding).  On the levels
  * that are smoothed by launches over many workgroups (not those resident in
  * one workgroup's LDS) and have at most two 16 x 16 tiles per compute unit
- * (where launch latency, not throughput, sets the time), a red and the
- * following black half-sweep run in one launch: each tile relaxes the red
+ * (one on the finest level unless blocking is 2), where a launch's fixed
+ * cost is as large as its relaxation, a red and the following black
+ * half-sweep run in one launch: each tile relaxes the red
  * cells of its tile widened by two cells on every side in LDS, then its own
  * black cells.  Sweeps go in pairs (an odd last sweep takes two half-sweep
  * launches).  Needs a second set of
@@ -198,7 +201,8 @@ typedef struct qnsch_ctx qnsch_ctx;
  * 1.75 in the primitive scheme on hierarchies of 6 levels or more, else 6 by
  * 1.6; as many or fewer V-cycles than 30 plain sweeps on the workloads of
  * sec. 8), omega 1, coupled smoother, primitive scheme, acceleration depth
- * 2, temporal blocking of the coarse levels (1). */
+ * 2, temporal blocking (1: the coarse levels, and the finest level where it
+ * has at most one 16 x 16 tile per compute unit). */
 void qnsch_default_opts(qnsch_opts *opts);
 
 /* Create a context on the current HIP device.  hip_stream: a hipStream_t to

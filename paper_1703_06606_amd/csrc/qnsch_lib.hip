@@ -248,25 +248,29 @@ static int small_level(const qnsch_ctx *x)
 // cell corrections (mixed precision)
 static bool two_sets(const qnsch_opts &o) { return o.blocking > 0; }
 // levels whose sweeps run fused (bit l): those smoothed by half-sweep
-// launches (below small), the finest one only with blocking 2, with at most
-// two tiles per compute unit, and a periodic axis at least TX + 3 (TY + 3)
-// cells long (the widened tile wraps once).  The tile limit: a fused sweep
-// pays for its redundant red work (200 red cells per tile instead of 128, at
-// one workgroup per CU) with a dependent launch less, which is worth it only
-// where launch latency rules; measured on one MI355X, 256 x 512 droplet: the
-// finest level (512 tiles) 23.5 us fused against 2 x 9.6 us plus a launch
-// gap, the step 4.5 % faster; 512 x 2048 (4096 tiles): 159 us against
-// 2 x 50 us, the step 17 % slower.
+// launches (below small) with a periodic axis at least TX + 3 (TY + 3) cells
+// long (the widened tile wraps once) and few enough tiles: coarse levels with
+// at most two tiles per compute unit; the finest level with at most one
+// (blocking 1), or two (blocking 2).  A fused sweep pays for its redundant red
+// work (200 red cells per tile instead of 128, with the workgroup's LDS tile
+// widened) with a launch less, which is worth it only where a launch's fixed
+// cost is as large as its relaxation.  Measured on one MI355X (alternating
+// settings on one box): fusing the finest level too, 32 x 64 capillary (8
+// tiles) 0.326-0.329 against 0.340-0.341 ms per step, 64 x 128 droplet (32
+// tiles) 1.354-1.357 against 1.389-1.392, 128 x 256 (128 tiles) 1.901
+// against 1.965-1.966, but 256 x 512 (512 tiles, two per CU) 2.716-2.722
+// against 2.652-2.656 ms and 512 x 2048 (4096 tiles) 17 % slower.
 static unsigned fused_levels(const qnsch_ctx *x)
 {
     if (!two_sets(x->opt)) return 0u;
     unsigned m = 0;
     const int small = small_level(x);
-    for (int l = (x->opt.blocking >= 2 ? 0 : 1); l < small && l < x->nlev; l++) {
+    for (int l = 0; l < small && l < x->nlev; l++) {
         const DLev &D = x->L[l];
         if ((x->g.bc_x == QNSCH_BC_PERIODIC && D.m1 < TX + 3) || (x->g.bc_y == QNSCH_BC_PERIODIC && D.m2 < TY + 3))
             continue;
-        if (((D.m1 + TX - 1) / TX) * ((D.m2 + TY - 1) / TY) > 2 * x->ncu) continue;
+        const int tiles = ((D.m1 + TX - 1) / TX) * ((D.m2 + TY - 1) / TY);
+        if (tiles > (l > 0 || x->opt.blocking >= 2 ? 2 : 1) * x->ncu) continue;
         m |= 1u << l;
     }
     return m;
