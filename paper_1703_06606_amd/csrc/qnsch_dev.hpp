@@ -531,9 +531,33 @@ __device__ __forceinline__ FaceEq face_eq(const Phys &P, const Tile &T, const Ax
     return q;
 }
 
-__device__ __forceinline__ double ldf(const double *f, const View &L, int i, int j)
+// loads and stores through a pointer of address space AS (1: global memory,
+// 3: LDS, 0: either).  A level's arrays reach the kernels inside structures,
+// so without it the compiler issues generic accesses, which count as LDS
+// accesses too: every wait for an LDS read would then also wait for the
+// outstanding global loads.
+template <int AS, typename R> __device__ __forceinline__ R lda(const R *p, size_t k)
 {
-    return f ? f[(size_t)j * L.pitch + i] : 0.0;
+    if constexpr (AS == 1)
+        return ((const __attribute__((address_space(1))) R *)p)[k];
+    else if constexpr (AS == 3)
+        return ((const __attribute__((address_space(3))) R *)p)[k];
+    else
+        return p[k];
+}
+template <int AS, typename R> __device__ __forceinline__ void sta(R *p, size_t k, R v)
+{
+    if constexpr (AS == 1)
+        ((__attribute__((address_space(1))) R *)p)[k] = v;
+    else if constexpr (AS == 3)
+        ((__attribute__((address_space(3))) R *)p)[k] = v;
+    else
+        p[k] = v;
+}
+
+template <int AS = 0> __device__ __forceinline__ double ldf(const double *f, const View &L, int i, int j)
+{
+    return f ? lda<AS>(f, (size_t)j * L.pitch + i) : 0.0;
 }
 
 // face right-hand side of the lane's axis: the select is taken on the pointer
@@ -567,7 +591,7 @@ __device__ __forceinline__ const double *face_rhs(const Rhs &F, int hlf)
 // form c, mubar and rho(c) of the cell are also written to the tile between
 // the steps (identical values from both lanes), which no other pair of this
 // colour reads.
-template <bool TO>
+template <bool TO, int AS>
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
                               int i, int j, int ti, int tj, int hlf, double omega, double pomega);
 __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j, int hlf,
@@ -579,14 +603,16 @@ __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, cons
 // tj), which differs from its level position (i, j) at a periodic image, and
 // the results stay in the tile: c, mubar, pbar and rho(c) in place (no other
 // cell of the colour reads them), the box faces in the fields T_NF (u) and
-// T_NF + 1 (v), whose elements only this cell's box writes.
-template <bool TO>
+// T_NF + 1 (v), whose elements only this cell's box writes.  AS is the
+// address space of the level arrays and right-hand sides (1: global memory,
+// 3: LDS, where the level resides in the workgroup's LDS).
+template <bool TO, int AS>
 __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
                                            double *vnew, int i, int j, int ti, int tj, int hlf, double omega,
                                            double pomega)
 {
     if (P.scheme) {
-        relax_pair_pj<TO>(P, L, T, F, unew, vnew, i, j, ti, tj, hlf, omega, pomega);
+        relax_pair_pj<TO, AS>(P, L, T, F, unew, vnew, i, j, ti, tj, hlf, omega, pomega);
         return;
     }
     const size_t k = (size_t)j * L.pitch + i;
@@ -594,10 +620,18 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
     const int e = T.idx(ti, tj);
     const Ax a = make_ax(L, T, i, j, hlf);
     const bool cpl = P.coupled;
+    // the right-hand sides first: their loads are then in flight during the
+    // cell equations
+    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
+    const double *fN = face_rhs(F, hlf);
+    const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
+    const size_t khi = (size_t)jhi * L.pitch + ihi;
+    const double f_c = ldf<AS>(F.fc, L, i, j), f_mu = ldf<AS>(F.fmu, L, i, j), f_p = ldf<AS>(F.fp, L, i, j);
+    const double f_lo = hlo ? ldf<AS>(fN, L, i, j) : 0.0, f_hi = hhi ? ldf<AS>(fN, L, ihi, jhi) : 0.0;
     CellAx x = cell_axis(T, a, e, ih);
     CellAx s = cell_sum(x);
     CellEq q = cell_eq(P, T, e, s);
-    const double r1 = ldf(F.fc, L, i, j) - q.Nc, r2 = ldf(F.fmu, L, i, j) - q.Nmu;
+    const double r1 = f_c - q.Nc, r2 = f_mu - q.Nmu;
     const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e);
     double cnew = c0, mnew = m0;
     // coupled box: mubar eliminated by N_mu (pivot Jmm), then c by N_c (pivot
@@ -619,25 +653,21 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
         cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
         mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
         if (!TO && hlf == 0) {
-            L.c[k] = cnew;
-            L.mu[k] = mnew;
+            sta<AS>(L.c, k, cnew);
+            sta<AS>(L.mu, k, mnew);
         }
         T.s[T_C * T.W * T.H + e] = cnew;
         T.s[T_MU * T.W * T.H + e] = mnew;
         T.s[T_RS * T.W * T.H + e] = rho_of(P, cnew);
     }
     // ---- the box: this lane's two faces along its axis
-    const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const FaceEq flo = face_eq(P, T, a, e, a.it, ih);
     const FaceEq fhi = face_eq(P, T, a, e + a.dn, a.it, ih);
-    const double *fN = face_rhs(F, hlf);
-    const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
-    const size_t khi = (size_t)jhi * L.pitch + ihi;
-    const double blo = hlo ? ldf(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
-    const double bhi = hhi ? ldf(fN, L, ihi, jhi) - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
+    const double blo = hlo ? f_lo - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
+    const double bhi = hhi ? f_hi - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
     // mass equation with the new mubar of the cell (linear in it: -Sm per axis)
     const double Lmu_new = s.Lmu - s.Sm * (mnew - m0);
-    const double bp = ldf(F.fp, L, i, j) - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
+    const double bp = f_p - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
     // box-cell coefficients of the off-diagonal couplings
     const double w_ax = tq(T, T_RN, e) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn)); // rho^n a u^n
     const double mv0 = tq(T, T_MV, e);
@@ -737,8 +767,8 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
             T.s[T_MU * n + e] = m0 + kbm - kmc * dc;
             T.s[T_RS * n + e] = rho_of(P, c0 + dc);
         } else {
-            L.c[k] = c0 + dc;
-            L.mu[k] = m0 + kbm - kmc * dc;
+            sta<AS>(L.c, k, c0 + dc);
+            sta<AS>(L.mu, k, m0 + kbm - kmc * dc);
         }
     }
     const double nlo = tq(T, a.FN, e) + omega * b[0], nhi = tq(T, a.FN, e + a.dn) + omega * b[1];
@@ -751,24 +781,26 @@ __device__ __forceinline__ void relax_cell(const Phys &P, const View &L, const T
         return;
     }
     if (hlf) {
-        if (hlo) vnew[k] = nlo;
-        if (hhi) vnew[khi] = nhi;
+        if (hlo) sta<AS>(vnew, k, nlo);
+        if (hhi) sta<AS>(vnew, khi, nhi);
     } else {
-        if (hlo) unew[k] = nlo;
-        if (hhi) unew[khi] = nhi;
+        if (hlo) sta<AS>(unew, k, nlo);
+        if (hhi) sta<AS>(unew, khi, nhi);
     }
-    if (hlf == 0) L.p[k] = tq(T, T_P, e) + omega * b[4];
+    if (hlf == 0) sta<AS>(L.p, k, tq(T, T_P, e) + omega * b[4]);
 }
+template <int AS>
 __device__ __forceinline__ void relax_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew,
                                            double *vnew, int i, int j, int hlf, double omega, double pomega)
 {
-    relax_cell<false>(P, L, T, F, unew, vnew, i, j, i, j, hlf, omega, pomega);
+    relax_cell<false, AS>(P, L, T, F, unew, vnew, i, j, i, j, hlf, omega, pomega);
 }
 
 // residuals r = f - N(w) of the five equations attached to cell (i,j): the
 // cell equations and the momentum equation of its west face (lane 0) or south
 // face (lane 1); zero for a face on a wall.  Both lanes return rc, rm, rp;
-// rf is this lane's face residual.
+// rf is this lane's face residual.  The level and its right-hand sides are
+// in global memory.
 __device__ __forceinline__ void resid_pair(const Phys &P, const View &L, const Tile &T, const Rhs &F, int i, int j,
                                            int hlf, double &rc, double &rm, double &rp, double &rf)
 {
@@ -780,12 +812,12 @@ __device__ __forceinline__ void resid_pair(const Phys &P, const View &L, const T
     const Ax a = make_ax(L, T, i, j, hlf);
     const CellAx s = cell_sum(cell_axis(T, a, e, L.inv_h));
     const CellEq q = cell_eq(P, T, e, s);
-    rc = ldf(F.fc, L, i, j) - q.Nc;
-    rm = ldf(F.fmu, L, i, j) - q.Nmu;
-    rp = ldf(F.fp, L, i, j) - q.Np;
+    rc = ldf<1>(F.fc, L, i, j) - q.Nc;
+    rm = ldf<1>(F.fmu, L, i, j) - q.Nmu;
+    rp = ldf<1>(F.fp, L, i, j) - q.Np;
     const bool hlo = a.per || a.ia >= 1;
     const FaceEq f = face_eq(P, T, a, e, a.it, L.inv_h);
-    rf = hlo ? ldf(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
+    rf = hlo ? ldf<1>(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
 }
 
 // --------------------------------------------------------------------------
@@ -840,7 +872,7 @@ __device__ __forceinline__ PjAx pj_axis(const Tile &T, const Ax &a, int e, doubl
 // rho^n (c - c^n)/dt, the advection at time n+1 and rho^n mubar.  The tile
 // entries of the cell (c, mubar, rho(c)) are updated after step 1; no other
 // pair of this colour reads them.
-template <bool TO>
+template <bool TO, int AS>
 __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, const Tile &T, const Rhs &F, double *unew, double *vnew,
                               int i, int j, int ti, int tj, int hlf, double omega, double pomega)
 {
@@ -862,7 +894,7 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double Nc = rn * (c0 - n0) * P.inv_dt + adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp;
     const double Nmu = q.Nmu - (rs - rn) * m0;
     const double Jcc = rn * P.inv_dt + dadv, Jcm = q.Jcm, Jmm = rn, Jmc = q.Jmc - drs * m0;
-    const double r1 = ldf(F.fc, L, i, j) - Nc, r2 = ldf(F.fmu, L, i, j) - Nmu;
+    const double r1 = ldf<AS>(F.fc, L, i, j) - Nc, r2 = ldf<AS>(F.fmu, L, i, j) - Nmu;
     const double p0 = tq(T, T_P, e);
     double cnew, mnew, pnew = p0;
     if (P.coupled) {
@@ -878,7 +910,7 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         const double Jcp = cl + other(cl) + P.alpha * P.inv_Pe * s.Sm, Jpm = P.alpha * P.inv_Pe * s.Sm;
         const double Jpp = jx + other(jx) + q.Jpp;
         const double Np = dv + other(dv) - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp;
-        const double r3 = ldf(F.fp, L, i, j) - Np;
+        const double r3 = ldf<AS>(F.fp, L, i, j) - Np;
         // eliminate pbar by the mass row (pivot Jpp), then mubar by the
         // chemical row (pivot Jmm): a 2x2 system in c and mubar remains
         const double ipp = frcp(Jpp);
@@ -896,8 +928,8 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         mnew = m0 + (Jcc * r2 - Jmc * r1) * idet;
     }
     if (!TO && hlf == 0) {
-        L.c[k] = cnew;
-        L.mu[k] = mnew;
+        sta<AS>(L.c, k, cnew);
+        sta<AS>(L.mu, k, mnew);
     }
     T.s[T_C * st + e] = cnew;
     T.s[T_MU * st + e] = mnew;
@@ -908,8 +940,8 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double *fN = face_rhs(F, hlf);
     const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
     const size_t khi = (size_t)jhi * L.pitch + ihi;
-    const double blo = hlo ? ldf(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
-    const double bhi = hhi ? ldf(fN, L, ihi, jhi) - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
+    const double blo = hlo ? ldf<AS>(fN, L, i, j) - flo.N : 0.0, dlo = hlo ? flo.diag : 1.0;
+    const double bhi = hhi ? ldf<AS>(fN, L, ihi, jhi) - fhi.N : 0.0, dhi = hhi ? fhi.diag : 1.0;
     const double w_ax = tq(T, T_RN, e) * 0.5 * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
     const double mv0 = tq(T, T_MV, e);
     const double vis = (4.0 / 3.0) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0;
@@ -959,11 +991,11 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
         if (hlo) fo[e] = ulo;
         if (hhi) fo[e + a.dn] = uhi;
     } else if (hlf) {
-        if (hlo) vnew[k] = ulo;
-        if (hhi) vnew[khi] = uhi;
+        if (hlo) sta<AS>(vnew, k, ulo);
+        if (hhi) sta<AS>(vnew, khi, uhi);
     } else {
-        if (hlo) unew[k] = ulo;
-        if (hhi) unew[khi] = uhi;
+        if (hlo) sta<AS>(unew, k, ulo);
+        if (hhi) sta<AS>(unew, khi, uhi);
     }
     // ---- step 3: pbar from the mass equation with the new u~ (passed by
     // value: the tile keeps the snapshot that other boxes of this colour read)
@@ -976,9 +1008,9 @@ __device__ __forceinline__ void relax_pair_pj(const Phys &P, const View &L, cons
     const double Np = div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * Lp_new;
     const double Jp = jp + q.Jpp;
     if (hlf == 0) {
-        const double pf = pnew + pomega * (ldf(F.fp, L, i, j) - Np) * frcp(Jp);
+        const double pf = pnew + pomega * (ldf<AS>(F.fp, L, i, j) - Np) * frcp(Jp);
         if (TO) T.s[T_P * st + e] = pf;
-        else L.p[k] = pf;
+        else sta<AS>(L.p, k, pf);
     }
 }
 
@@ -1000,11 +1032,11 @@ __device__ __forceinline__ void resid_pair_pj(const Phys &P, const View &L, cons
     const double adv = x.adv + other(x.adv), div = x.div + other(x.div);
     const double c0 = tq(T, T_C, e), m0 = tq(T, T_MU, e), n0 = tq(T, T_CN, e);
     const double rs = tq(T, T_RS, e), rn = tq(T, T_RN, e);
-    rc = ldf(F.fc, L, i, j) - (rn * (c0 - n0) * P.inv_dt + adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp);
-    rm = ldf(F.fmu, L, i, j) - (q.Nmu - (rs - rn) * m0);
-    rp = ldf(F.fp, L, i, j) - (div - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp);
+    rc = ldf<1>(F.fc, L, i, j) - (rn * (c0 - n0) * P.inv_dt + adv - P.inv_Pe * s.Lmu - P.alpha * P.inv_Pe * s.Lp);
+    rm = ldf<1>(F.fmu, L, i, j) - (q.Nmu - (rs - rn) * m0);
+    rp = ldf<1>(F.fp, L, i, j) - (div - P.alpha * P.inv_Pe * s.Lmu - P.alpha * P.alpha * P.inv_Pe * s.Lp);
     const FaceEq f = face_eq(P, T, a, e, a.it, ih, true);
-    rf = hlo ? ldf(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
+    rf = hlo ? ldf<1>(face_rhs(F, hlf), L, i, j) - f.N : 0.0;
 }
 
 } // namespace qn
