@@ -705,23 +705,36 @@ __device__ __forceinline__ void acc_put(const Desc &d, int s, size_t w, int hlf,
 // ... and the lane's share of the normal equations of
 // min || r + sum_a g_a (r - r_a) ||, r_a the residual a + 1 slots back
 // (a < np): v[7 + b(b+1)/2 + a] += e_a e_b (a <= b), v[13 + a] += e_a r,
-// e_a = r - r_a.  Reads back what acc_put of the same lane wrote.
+// e_a = r - r_a.  Reads back what acc_put of the same lane wrote (the
+// residuals' registers are free by then), all slots of all the lane's fields
+// (lane 0: four, lane 1: one) before the first product.
 __device__ __forceinline__ void acc_dots(const Desc &d, int ac, size_t w, int hlf, double (&v)[NRED])
 {
     const int s = ac & 15, np = ac >> 4, R = d.am;
     const size_t st = (size_t)d.pitch * d.m2;
-    for (int f = hlf ? 4 : 0; f < (hlf ? 5 : 4); f++) {
-        const double x = d.ar[(size_t)(s * 5 + f) * st + w];
+    const int nf = hlf ? 1 : 4;
+    double x[4], old[4][3];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int f = hlf ? 4 : q;
+        x[q] = q < nf ? d.ar[(size_t)(s * 5 + f) * st + w] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+            old[q][a] = (q < nf && a < np) ? d.ar[(size_t)(((s - 1 - a + R) % R) * 5 + f) * st + w] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        if (q >= nf) continue;
         double e[3] = { 0.0, 0.0, 0.0 };
 #pragma unroll
         for (int a = 0; a < 3; a++)
-            if (a < np) e[a] = x - d.ar[(size_t)(((s - 1 - a + R) % R) * 5 + f) * st + w];
+            if (a < np) e[a] = x[q] - old[q][a];
 #pragma unroll
         for (int b = 0; b < 3; b++)
 #pragma unroll
             for (int a = 0; a <= b; a++) v[7 + b * (b + 1) / 2 + a] += e[a] * e[b];
 #pragma unroll
-        for (int a = 0; a < 3; a++) v[13 + a] += e[a] * x;
+        for (int a = 0; a < 3; a++) v[13 + a] += e[a] * x[q];
     }
 }
 
