@@ -125,6 +125,46 @@ __device__ __forceinline__ TileSrc tile_src(int m1, int m2, int pitch, int bcx, 
     s.v = jv * pitch + iv;
     return s;
 }
+// the sources of tile_src as level coordinates: cell (ic, jc), u face
+// (iu, ju), v face (iv, jv), resolved by the same rules (tile_src keeps its own
+// copy: composing it from this one measured slower in the tile loads)
+struct TileSrcIJ {
+    int ic, jc, iu, ju, iv, jv;
+    int sc, su, sv;
+};
+__device__ __forceinline__ TileSrcIJ tile_src_ij(int m1, int m2, int bcx, int bcy, int i, int j)
+{
+    TileSrcIJ s;
+    if (i > m1 + 1 || j > m2 + 1) {
+        s.ic = s.jc = s.iu = s.ju = s.iv = s.jv = 0;
+        s.sc = s.su = s.sv = 0;
+        return s;
+    }
+    int ic = i, jc = j;
+    if (ic < 0 || ic >= m1) ic = bcx ? wrapi(ic, m1) : (ic < 0 ? 0 : m1 - 1);
+    if (jc < 0 || jc >= m2) jc = bcy ? wrapi(jc, m2) : (jc < 0 ? 0 : m2 - 1);
+    s.ic = ic; s.jc = jc;
+    s.sc = 1;
+    int iu = i, ju = j;
+    s.su = 1;
+    if (bcx) iu = wrapi(iu, m1);
+    else if (iu <= 0 || iu >= m1) { s.su = 0; iu = 0; }
+    if (ju < 0 || ju >= m2) {
+        if (bcy) ju = wrapi(ju, m2);
+        else { s.su = -s.su; ju = ju < 0 ? 0 : m2 - 1; }
+    }
+    s.iu = iu; s.ju = ju;
+    int iv = i, jv = j;
+    s.sv = 1;
+    if (bcy) jv = wrapi(jv, m2);
+    else if (jv <= 0 || jv >= m2) { s.sv = 0; jv = 0; }
+    if (iv < 0 || iv >= m1) {
+        if (bcx) iv = wrapi(iv, m1);
+        else { s.sv = -s.sv; iv = iv < 0 ? 0 : m1 - 1; }
+    }
+    s.iv = iv; s.jv = jv;
+    return s;
+}
 template <typename R> __device__ __forceinline__ R signed_val(int sg, R x) { return sg > 0 ? x : (sg < 0 ? -x : R(0)); }
 
 __device__ __forceinline__ bool u_unk(const View &L, int i) { return L.bcx || (i >= 1 && i <= L.m1 - 1); }

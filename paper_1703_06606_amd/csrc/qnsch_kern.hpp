@@ -417,8 +417,9 @@ __device__ __forceinline__ PCorr prolong_corr(const Desc &d, const Desc &C, int 
     return r;
 }
 
-// LDS doubles of the coarsest-level solve: 15 level arrays + one tile + the
-// tile's source map (4 ints per element)
+// LDS doubles of the level-resident solve: 15 per cell (the level arrays and
+// right-hand sides take 12) + one tile + the tile's source map (4 ints per
+// element)
 __host__ __device__ inline size_t coarse_lds_doubles(int m1, int m2)
 {
     return (size_t)15 * m1 * m2 + (size_t)(T_NF + 2) * (m1 + 3) * (m2 + 3);
@@ -445,41 +446,82 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
     double *ua = d.ub[par], *va = d.vb[par];
     const int m1 = L.m1, m2 = L.m2, n = m1 * m2;
     double *hc = sm, *hmu = sm + n, *hp = sm + 2 * n, *uA = sm + 3 * n, *vA = sm + 4 * n, *uB = sm + 5 * n,
-           *vB = sm + 6 * n, *hcn = sm + 7 * n, *hun = sm + 8 * n, *hvn = sm + 9 * n, *hf = sm + 10 * n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        const int j = e / m1, i = e - j * m1;
-        const size_t q = (size_t)j * L.pitch + i;
-        hc[e] = L.c[q]; hmu[e] = L.mu[q]; hp[e] = L.p[q]; uA[e] = ua[q]; vA[e] = va[q];
+           *vB = sm + 6 * n, *hf = sm + 7 * n;
+    Tile T;
+    T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
+    const int nt = T.W * T.H;
+    int *map = (int *)(T.s + (size_t)T_NF * nt);
+    // one pass over the tile's elements: each loads its sources from the level
+    // arrays (the boundary images of tile_load), adds the coarse-grid
+    // correction of each source, and fills the tile (with the cell functions),
+    // the refresh map (level indices in LDS, as tile_map_build) and, for an
+    // element that is a cell of the level, the level arrays in LDS and the
+    // right-hand sides
+    for (int e = threadIdx.x; e < nt; e += blockDim.x) {
+        const int b = e / T.W, a = e - b * T.W;
+        const int i = a - 1, j = b - 1;
+        const TileSrcIJ q = tile_src_ij(m1, m2, L.bcx, L.bcy, i, j);
+        const size_t kc = (size_t)q.jc * L.pitch + q.ic, ku = (size_t)q.ju * L.pitch + q.iu,
+                     kv = (size_t)q.jv * L.pitch + q.iv;
+        double c = L.c[kc], mu = L.mu[kc], p = L.p[kc], u = ua[ku], v = va[kv];
+        const double cn = L.cn[kc], un = L.un[ku], vn = L.vn[kv];
         if (prolong) {
-            const PCorr r = prolong_corr(d, *d.coarse, it.cpar[k], i, j);
-            hc[e] += r.c; hmu[e] += r.mu; hp[e] += r.p;
-            if (r.hu) uA[e] += r.u;
-            if (r.hv) vA[e] += r.v;
+            const Desc &C = *d.coarse;
+            const PCorr rc = prolong_corr(d, C, it.cpar[k], q.ic, q.jc);
+            const PCorr ru = prolong_corr(d, C, it.cpar[k], q.iu, q.ju);
+            const PCorr rv = prolong_corr(d, C, it.cpar[k], q.iv, q.jv);
+            c += rc.c; mu += rc.mu; p += rc.p;
+            if (ru.hu) u += ru.u;
+            if (rv.hv) v += rv.v;
         }
-        hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
-        hf[e] = d.fc ? d.fc[q] : 0.0;
-        hf[n + e] = d.fmu ? d.fmu[q] : 0.0;
-        hf[2 * n + e] = d.fp ? d.fp[q] : 0.0;
-        hf[3 * n + e] = d.fu ? d.fu[q] : 0.0;
-        hf[4 * n + e] = d.fv ? d.fv[q] : 0.0;
+        const bool out = i > m1 + 1 || j > m2 + 1;
+        map[4 * e] = q.jc * m1 + q.ic;
+        map[4 * e + 1] = q.ju * m1 + q.iu;
+        map[4 * e + 2] = q.jv * m1 + q.iv;
+        map[4 * e + 3] = (q.su + 1) | ((q.sv + 1) << 2) | (((q.ic + q.jc) & 1) << 5) | (out ? 16 : 0);
+        double *t = T.s + e;
+        if (q.sc == 0) {
+            for (int f = 0; f < T_NF; f++) t[f * nt] = 0.0;
+        } else {
+            t[T_C * nt] = c;
+            t[T_MU * nt] = mu;
+            t[T_P * nt] = p;
+            t[T_U * nt] = signed_val(q.su, u);
+            t[T_V * nt] = signed_val(q.sv, v);
+            t[T_CN * nt] = cn;
+            t[T_UN * nt] = signed_val(q.su, un);
+            t[T_VN * nt] = signed_val(q.sv, vn);
+            t[T_RN * nt] = rho_of(P, cn);
+            t[T_MV * nt] = visc_of(P, cn);
+            t[T_MOB * nt] = mob_of(P, cn);
+            t[T_RS * nt] = rho_of(P, c);
+        }
+        if (i >= 0 && i < m1 && j >= 0 && j < m2) {
+            // a cell of the level: its own source for every field
+            const int el = j * m1 + i;
+            const size_t ql = (size_t)j * L.pitch + i;
+            hc[el] = c; hmu[el] = mu; hp[el] = p; uA[el] = u; vA[el] = v;
+            hf[el] = d.fc ? d.fc[ql] : 0.0;
+            hf[n + el] = d.fmu ? d.fmu[ql] : 0.0;
+            hf[2 * n + el] = d.fp ? d.fp[ql] : 0.0;
+            hf[3 * n + el] = d.fu ? d.fu[ql] : 0.0;
+            hf[4 * n + el] = d.fv ? d.fv[ql] : 0.0;
+        }
     }
     __syncthreads();
     View H = L;
-    H.c = hc; H.mu = hmu; H.p = hp; H.cn = hcn; H.un = hun; H.vn = hvn; H.pitch = m1;
+    H.c = hc; H.mu = hmu; H.p = hp; H.pitch = m1;
     const Rhs FH = { hf, hf + n, hf + 2 * n, hf + 3 * n, hf + 4 * n };
-    Tile T;
-    T.s = sm + 15 * n; T.i0 = 0; T.j0 = 0; T.W = m1 + 3; T.H = m2 + 3;
-    int *map = (int *)(T.s + (size_t)T_NF * T.W * T.H);
-    tile_map_build(H, T, map);
     const int half = m1 >> 1;
     for (int s = 0; s < 2 * sweeps; s++) {
         const int colour = s & 1;
         double *uw, *vw;
         if (s & 1) { H.u = uB; H.v = vB; uw = uA; vw = vA; }
         else { H.u = uA; H.v = vA; uw = uB; vw = vB; }
-        if (s == 0) tile_load(P, H, T);
-        else tile_refresh_map(P, H, T, map, colour ^ 1);
-        __syncthreads();
+        if (s > 0) {
+            tile_refresh_map(P, H, T, map, colour ^ 1);
+            __syncthreads();
+        }
         for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
             const int pr = t >> 1;
             const int j = pr / half;
