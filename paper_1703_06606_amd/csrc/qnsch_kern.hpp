@@ -195,45 +195,63 @@ template <typename IT> __global__ FINE_ATTR void k_halfsweep_fine(IT it, int col
 static_assert(FUSED_DOUBLES * 8 <= 65536, "fused tile exceeds 64 KiB of LDS");
 static_assert((TX + 4) * (TY + 4) <= FBLK, "widened red region exceeds the workgroup");
 
-// P(w_H - R w_h) of one unknown of fine level d (the arithmetic of
+// the coarse level's arrays that the coarse-grid correction reads, and the
+// fine level's boundary kinds, taken from the level descriptors once per
+// workgroup (read inside the tile loader, the descriptors would be reloaded
+// per element behind the tile stores)
+struct PSrc {
+    const double *c, *c0, *mu, *mu0, *p, *p0, *u, *u0, *v, *v0;
+    int pitch, m1, m2, bcx, bcy;
+};
+__device__ __forceinline__ PSrc psrc_of(const Desc &d, const Desc &C, int cpar)
+{
+    PSrc s;
+    s.c = C.c; s.c0 = C.c0; s.mu = C.mu; s.mu0 = C.mu0; s.p = C.p; s.p0 = C.p0;
+    s.u = C.ub[cpar]; s.u0 = C.u0; s.v = C.vb[cpar]; s.v0 = C.v0;
+    s.pitch = C.pitch; s.m1 = C.m1; s.m2 = C.m2; s.bcx = d.bcx; s.bcy = d.bcy;
+    return s;
+}
+// P(w_H - R w_h) of one unknown of the fine level (the arithmetic of
 // prolong_corr below, split by kind): the cell unknowns of cell (i, j), the
-// u face (i, j) and the v face (i, j) (zero for a face on a wall)
-__device__ __forceinline__ void prolong_cell(const Desc &C, int i, int j, double &c, double &mu, double &p)
+// u face (i, j) and the v face (i, j) (zero for a face on a wall).  Every
+// value a face may need is loaded before the selects, so that the loads are
+// in flight together.
+__device__ __forceinline__ void prolong_cell(const PSrc &C, int i, int j, double &c, double &mu, double &p)
 {
     const size_t kc = (size_t)(j >> 1) * C.pitch + (i >> 1);
     c = C.c[kc] - C.c0[kc];
     mu = C.mu[kc] - C.mu0[kc];
     p = C.p[kc] - C.p0[kc];
 }
-__device__ __forceinline__ double prolong_u(const Desc &d, const Desc &C, int cpar, int i, int j)
+__device__ __forceinline__ double prolong_u(const PSrc &C, int i, int j)
 {
-    if (!(d.bcx || i >= 1)) return 0.0;
     const int I = i >> 1, J = j >> 1;
     const size_t kc = (size_t)J * C.pitch + I;
-    const double *Cu = C.ub[cpar];
-    double du = Cu[kc] - C.u0[kc];
+    // the coarse face east of the coarse cell: the next one, its periodic
+    // image, or (none: loaded, not used) the cell's own
+    const bool east = I + 1 < C.m1;
+    const size_t ke = east ? kc + 1 : (C.bcx ? (size_t)J * C.pitch : kc);
+    const double a0 = C.u[kc], b0 = C.u0[kc], a1 = C.u[ke], b1 = C.u0[ke];
+    double du = a0 - b0;
     if (i & 1) {
-        double e = 0.0;
-        if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
-        else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
+        const double e = (east || C.bcx) ? a1 - b1 : 0.0;
         du = 0.5 * (du + e);
     }
-    return du;
+    return (C.bcx || i >= 1) ? du : 0.0;
 }
-__device__ __forceinline__ double prolong_v(const Desc &d, const Desc &C, int cpar, int i, int j)
+__device__ __forceinline__ double prolong_v(const PSrc &C, int i, int j)
 {
-    if (!(d.bcy || j >= 1)) return 0.0;
     const int I = i >> 1, J = j >> 1;
     const size_t kc = (size_t)J * C.pitch + I;
-    const double *Cv = C.vb[cpar];
-    double dv = Cv[kc] - C.v0[kc];
+    const bool north = J + 1 < C.m2;
+    const size_t kn = north ? kc + C.pitch : (C.bcy ? (size_t)I : kc);
+    const double a0 = C.v[kc], b0 = C.v0[kc], a1 = C.v[kn], b1 = C.v0[kn];
+    double dv = a0 - b0;
     if (j & 1) {
-        double e = 0.0;
-        if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
-        else if (d.bcy) e = Cv[I] - C.v0[I];
+        const double e = (north || C.bcy) ? a1 - b1 : 0.0;
         dv = 0.5 * (dv + e);
     }
-    return dv;
+    return (C.bcy || j >= 1) ? dv : 0.0;
 }
 
 // the widened tile: every field at tile positions i0-1 .. i0+W-2 (level
@@ -244,8 +262,7 @@ __device__ __forceinline__ double prolong_v(const Desc &d, const Desc &C, int cp
 // the coarse-grid correction P(w_H - R w_h) of its source (k_prolong's
 // arithmetic); the sweep writes every unknown of the level, so the corrected
 // values need no store of their own.
-__device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T, const Desc *pd = nullptr,
-                                           const Desc *pc = nullptr, int cpar = 0)
+__device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T, const PSrc *pc = nullptr)
 {
     const int n = T.W * T.H;
     for (int e = threadIdx.x; e < n; e += blockDim.x) {
@@ -263,12 +280,18 @@ __device__ __forceinline__ void fused_load(const Phys &P, const View &L, const T
         if (pc) {
             double rc, rm, rp;
             prolong_cell(*pc, q.c % L.pitch, q.c / L.pitch, rc, rm, rp);
+            const double du = prolong_u(*pc, q.u % L.pitch, q.u / L.pitch);
+            const double dv = prolong_v(*pc, q.v % L.pitch, q.v / L.pitch);
             v[0] += rc;
             v[1] += rm;
             v[2] += rp;
-            if (q.su) v[3] += prolong_u(*pd, *pc, cpar, q.u % L.pitch, q.u / L.pitch);
-            if (q.sv) v[4] += prolong_v(*pd, *pc, cpar, q.v % L.pitch, q.v / L.pitch);
+            if (q.su) v[3] += du;
+            if (q.sv) v[4] += dv;
         }
+        // every load above is issued before anything uses a loaded value (the
+        // scheduler otherwise interleaves uses with the loads, one memory
+        // latency each)
+        __builtin_amdgcn_sched_barrier(0);
         s[T_C * n] = v[0];
         s[T_MU * n] = v[1];
         s[T_P * n] = v[2];
@@ -329,8 +352,12 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it,
     const Tile T0 = item_tile(sm, it, k, d);
     Tile T;
     T.s = sm; T.i0 = T0.i0 - 2; T.j0 = T0.j0 - 2; T.W = FUSED_W; T.H = FUSED_H;
-    if (prolong) fused_load(P, L, T, &d, d.coarse, it.cpar[k]);
-    else fused_load(P, L, T);
+    if (prolong) {
+        const PSrc ps = psrc_of(d, *d.coarse, it.cpar[k]);
+        fused_load(P, L, T, &ps);
+    } else {
+        fused_load(P, L, T);
+    }
     __syncthreads();
     const Rhs F = rhs_of(d);
     const int pr = threadIdx.x >> 1, hlf = threadIdx.x & 1;
