@@ -203,55 +203,67 @@ struct PSrc {
     const double *c, *c0, *mu, *mu0, *p, *p0, *u, *u0, *v, *v0;
     int pitch, m1, m2, bcx, bcy;
 };
-__device__ __forceinline__ PSrc psrc_of(const Desc &d, const Desc &C, int cpar)
+__device__ __forceinline__ PSrc psrc_of(const Desc &d, const Desc *cp, int cpar)
 {
+    // the descriptor is in global memory: read through a global pointer, its
+    // fields are scalar loads issued at once (a generic pointer would make
+    // them vector loads)
+    const __attribute__((address_space(1))) Desc &C = *(const __attribute__((address_space(1))) Desc *)cp;
     PSrc s;
     s.c = C.c; s.c0 = C.c0; s.mu = C.mu; s.mu0 = C.mu0; s.p = C.p; s.p0 = C.p0;
     s.u = C.ub[cpar]; s.u0 = C.u0; s.v = C.vb[cpar]; s.v0 = C.v0;
     s.pitch = C.pitch; s.m1 = C.m1; s.m2 = C.m2; s.bcx = d.bcx; s.bcy = d.bcy;
     return s;
 }
-// P(w_H - R w_h) of one unknown of the fine level (the arithmetic of
-// prolong_corr below, split by kind): the cell unknowns of cell (i, j), the
-// u face (i, j) and the v face (i, j) (zero for a face on a wall).  Every
-// value a face may need is loaded before the selects, so that the loads are
-// in flight together.
-__device__ __forceinline__ void prolong_cell(const PSrc &C, int i, int j, double &c, double &mu, double &p)
+// P(w_H - R w_h) of one tile element (the arithmetic of prolong_corr below,
+// split by kind), in two parts so that every load is in flight before any
+// value is used.  prolong_load reads the coarse cell of the cell source
+// (ic, jc) with its restricted iterate, and for each face source the coarse
+// face it lies on and the next one along its axis (the periodic image, or,
+// where there is none, the same face again: loaded, not used).
+struct PRaw {
+    double c, c0, mu, mu0, p, p0, u[4], v[4];
+};
+__device__ __forceinline__ PRaw prolong_load(const PSrc &C, int ic, int jc, int iu, int ju, int iv, int jv)
 {
-    const size_t kc = (size_t)(j >> 1) * C.pitch + (i >> 1);
-    c = C.c[kc] - C.c0[kc];
-    mu = C.mu[kc] - C.mu0[kc];
-    p = C.p[kc] - C.p0[kc];
+    PRaw r;
+    const size_t kc = (size_t)(jc >> 1) * C.pitch + (ic >> 1);
+    r.c = lda<1>(C.c, kc); r.c0 = lda<1>(C.c0, kc); r.mu = lda<1>(C.mu, kc); r.mu0 = lda<1>(C.mu0, kc);
+    r.p = lda<1>(C.p, kc); r.p0 = lda<1>(C.p0, kc);
+    {
+        const int I = iu >> 1, J = ju >> 1;
+        const size_t k0 = (size_t)J * C.pitch + I;
+        const size_t k1 = I + 1 < C.m1 ? k0 + 1 : (C.bcx ? (size_t)J * C.pitch : k0);
+        r.u[0] = lda<1>(C.u, k0); r.u[1] = lda<1>(C.u0, k0); r.u[2] = lda<1>(C.u, k1); r.u[3] = lda<1>(C.u0, k1);
+    }
+    {
+        const int I = iv >> 1, J = jv >> 1;
+        const size_t k0 = (size_t)J * C.pitch + I;
+        const size_t k1 = J + 1 < C.m2 ? k0 + C.pitch : (C.bcy ? (size_t)I : k0);
+        r.v[0] = lda<1>(C.v, k0); r.v[1] = lda<1>(C.v0, k0); r.v[2] = lda<1>(C.v, k1); r.v[3] = lda<1>(C.v0, k1);
+    }
+    return r;
 }
-__device__ __forceinline__ double prolong_u(const PSrc &C, int i, int j)
+// ... and the corrections: the cell unknowns, the u face (iu, ju) and the v
+// face (iv, jv) (zero for a face on a wall)
+__device__ __forceinline__ void prolong_apply(const PSrc &C, const PRaw &r, int iu, int iv, int jv, double &c,
+                                              double &mu, double &p, double &du, double &dv)
 {
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I;
-    // the coarse face east of the coarse cell: the next one, its periodic
-    // image, or (none: loaded, not used) the cell's own
-    const bool east = I + 1 < C.m1;
-    const size_t ke = east ? kc + 1 : (C.bcx ? (size_t)J * C.pitch : kc);
-    const double a0 = C.u[kc], b0 = C.u0[kc], a1 = C.u[ke], b1 = C.u0[ke];
-    double du = a0 - b0;
-    if (i & 1) {
-        const double e = (east || C.bcx) ? a1 - b1 : 0.0;
+    c = r.c - r.c0;
+    mu = r.mu - r.mu0;
+    p = r.p - r.p0;
+    du = r.u[0] - r.u[1];
+    if (iu & 1) {
+        const double e = ((iu >> 1) + 1 < C.m1 || C.bcx) ? r.u[2] - r.u[3] : 0.0;
         du = 0.5 * (du + e);
     }
-    return (C.bcx || i >= 1) ? du : 0.0;
-}
-__device__ __forceinline__ double prolong_v(const PSrc &C, int i, int j)
-{
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I;
-    const bool north = J + 1 < C.m2;
-    const size_t kn = north ? kc + C.pitch : (C.bcy ? (size_t)I : kc);
-    const double a0 = C.v[kc], b0 = C.v0[kc], a1 = C.v[kn], b1 = C.v0[kn];
-    double dv = a0 - b0;
-    if (j & 1) {
-        const double e = (north || C.bcy) ? a1 - b1 : 0.0;
+    if (!(C.bcx || iu >= 1)) du = 0.0;
+    dv = r.v[0] - r.v[1];
+    if (jv & 1) {
+        const double e = ((jv >> 1) + 1 < C.m2 || C.bcy) ? r.v[2] - r.v[3] : 0.0;
         dv = 0.5 * (dv + e);
     }
-    return (C.bcy || j >= 1) ? dv : 0.0;
+    if (!(C.bcy || jv >= 1)) dv = 0.0;
 }
 
 // the widened tile: every field at tile positions i0-1 .. i0+W-2 (level
@@ -276,22 +288,29 @@ __device__ __forceinline__ void fused_load(const Phys &P, const View &L, const T
             for (int f = 0; f < T_NF + 2; f++) s[f * n] = 0.0;
             continue;
         }
-        double v[8] = { L.c[q.c], L.mu[q.c], L.p[q.c], L.u[q.u], L.v[q.v], L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        double v[8] = { lda<1>(L.c, q.c), lda<1>(L.mu, q.c), lda<1>(L.p, q.c), lda<1>(L.u, q.u),
+                        lda<1>(L.v, q.v), lda<1>(L.cn, q.c), lda<1>(L.un, q.u), lda<1>(L.vn, q.v) };
+        PRaw raw = {};
+        int iu = 0, iv = 0, jv = 0;
         if (pc) {
-            double rc, rm, rp;
-            prolong_cell(*pc, q.c % L.pitch, q.c / L.pitch, rc, rm, rp);
-            const double du = prolong_u(*pc, q.u % L.pitch, q.u / L.pitch);
-            const double dv = prolong_v(*pc, q.v % L.pitch, q.v / L.pitch);
+            iu = q.u % L.pitch;
+            iv = q.v % L.pitch;
+            jv = q.v / L.pitch;
+            raw = prolong_load(*pc, q.c % L.pitch, q.c / L.pitch, iu, q.u / L.pitch, iv, jv);
+        }
+        // every load above is issued before anything uses a loaded value (the
+        // scheduler otherwise interleaves uses with the loads, one memory
+        // latency each)
+        __builtin_amdgcn_sched_barrier(0);
+        if (pc) {
+            double rc, rm, rp, du, dv;
+            prolong_apply(*pc, raw, iu, iv, jv, rc, rm, rp, du, dv);
             v[0] += rc;
             v[1] += rm;
             v[2] += rp;
             if (q.su) v[3] += du;
             if (q.sv) v[4] += dv;
         }
-        // every load above is issued before anything uses a loaded value (the
-        // scheduler otherwise interleaves uses with the loads, one memory
-        // latency each)
-        __builtin_amdgcn_sched_barrier(0);
         s[T_C * n] = v[0];
         s[T_MU * n] = v[1];
         s[T_P * n] = v[2];
@@ -352,11 +371,15 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_hs_fused(IT it,
     const Tile T0 = item_tile(sm, it, k, d);
     Tile T;
     T.s = sm; T.i0 = T0.i0 - 2; T.j0 = T0.j0 - 2; T.W = FUSED_W; T.H = FUSED_H;
-    if (prolong) {
-        const PSrc ps = psrc_of(d, *d.coarse, it.cpar[k]);
-        fused_load(P, L, T, &ps);
-    } else {
-        fused_load(P, L, T);
+    {
+        // the loader's constants by value (no tile store can change them)
+        const Phys Pv = d.P;
+        if (prolong) {
+            const PSrc ps = psrc_of(d, d.coarse, it.cpar[k]);
+            fused_load(Pv, L, T, &ps);
+        } else {
+            fused_load(Pv, L, T);
+        }
     }
     __syncthreads();
     const Rhs F = rhs_of(d);
