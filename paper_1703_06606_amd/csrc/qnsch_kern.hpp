@@ -74,26 +74,30 @@ struct Desc {
     float finv_h;
 };
 
+// (The small entries are 32-bit: a kernel reads them with scalar loads,
+// which have no 16-bit form; a 16-bit entry cost a vector load and its
+// memory latency at the start of every kernel.)
 struct Items {
     int n;
     int start[MAXITEMS + 1];  // first workgroup of each item; start[n] = total
     const Desc *d[MAXITEMS];  // the level worked on
-    short par[MAXITEMS];      // current u/v buffer of that level
-    short cpar[MAXITEMS];     // current u/v buffer of the next coarser level
+    int par[MAXITEMS];        // current u/v buffer of that level
+    int cpar[MAXITEMS];       // current u/v buffer of the next coarser level
     int tx[MAXITEMS];         // tiles per row (tile kernels); partial count (k_finalize)
-    short acc[MAXITEMS];      // acceleration ring slot s | (earlier results used) << 4; -1 none
+    int acc[MAXITEMS];        // acceleration ring slot s | (earlier results used) << 4; -1 none
 };
-// The same for a list of one item (a simulation run on its own): 32 bytes
-// of kernel arguments instead of 1.4 KB, which a dependent launch pays for
-// (about 1.5 us measured per launch).  Kernels are instantiated for both.
+// The same for a list of one item (a simulation run on its own): 40 bytes
+// of kernel arguments instead of 1.8 KB, which a dependent launch pays for
+// (about 1.5 us measured per launch with 1.4 KB).  Kernels are instantiated
+// for both.
 struct Item1 {
     int n;
     int start[2];
     const Desc *d[1];
-    short par[1];
-    short cpar[1];
+    int par[1];
+    int cpar[1];
     int tx[1];
-    short acc[1];
+    int acc[1];
 };
 
 template <typename IT> __device__ __forceinline__ int find_item(const IT &it)
@@ -215,12 +219,15 @@ __device__ __forceinline__ PSrc psrc_of(const Desc &d, const Desc *cp, int cpar)
     s.pitch = C.pitch; s.m1 = C.m1; s.m2 = C.m2; s.bcx = d.bcx; s.bcy = d.bcy;
     return s;
 }
-// P(w_H - R w_h) of one tile element (the arithmetic of prolong_corr below,
-// split by kind), in two parts so that every load is in flight before any
-// value is used.  prolong_load reads the coarse cell of the cell source
-// (ic, jc) with its restricted iterate, and for each face source the coarse
-// face it lies on and the next one along its axis (the periodic image, or,
-// where there is none, the same face again: loaded, not used).
+// The coarse-grid correction P(w_H - R w_h) of the fine unknowns: a cell takes
+// its coarse cell's value (piecewise constant); a face copies the coincident
+// coarse face, or, between two coarse faces, averages them; a face on a wall
+// is no unknown.  For one tile element it comes in two parts so that every
+// load is in flight before any value is used.  prolong_load reads the coarse
+// cell of the cell source (ic, jc) with its restricted iterate, and for each
+// face source the coarse face it lies on and the next one along its axis (the
+// periodic image, or, where there is none, the same face again: loaded, not
+// used).
 struct PRaw {
     double c, c0, mu, mu0, p, p0, u[4], v[4];
 };
@@ -425,48 +432,6 @@ __global__ __launch_bounds__(BLK) void k_copy_probe(const double *__restrict__ a
     for (size_t q = (size_t)blockIdx.x * BLK + threadIdx.x; q < n; q += (size_t)gridDim.x * BLK) b[q] = a[q];
 }
 
-// P(w_H - R w_h) at fine cell (i, j) of level d: cells piecewise constant;
-// faces copy the coincident coarse face and average the two coarse faces
-// across the coarse cell; hu/hv false for a face on a wall (no unknown)
-struct PCorr {
-    double c, mu, p, u, v;
-    bool hu, hv;
-};
-__device__ __forceinline__ PCorr prolong_corr(const Desc &d, const Desc &C, int cpar, int i, int j)
-{
-    PCorr r;
-    const int I = i >> 1, J = j >> 1;
-    const size_t kc = (size_t)J * C.pitch + I;
-    const double *Cu = C.ub[cpar], *Cv = C.vb[cpar];
-    r.c = C.c[kc] - C.c0[kc];
-    r.mu = C.mu[kc] - C.mu0[kc];
-    r.p = C.p[kc] - C.p0[kc];
-    r.hu = d.bcx || i >= 1;
-    r.hv = d.bcy || j >= 1;
-    r.u = r.v = 0.0;
-    if (r.hu) {
-        double du = Cu[kc] - C.u0[kc];
-        if (i & 1) {
-            double e = 0.0;
-            if (I + 1 < C.m1) e = Cu[kc + 1] - C.u0[kc + 1];
-            else if (d.bcx) e = Cu[(size_t)J * C.pitch] - C.u0[(size_t)J * C.pitch];
-            du = 0.5 * (du + e);
-        }
-        r.u = du;
-    }
-    if (r.hv) {
-        double dv = Cv[kc] - C.v0[kc];
-        if (j & 1) {
-            double e = 0.0;
-            if (J + 1 < C.m2) e = Cv[kc + C.pitch] - C.v0[kc + C.pitch];
-            else if (d.bcy) e = Cv[I] - C.v0[I];
-            dv = 0.5 * (dv + e);
-        }
-        r.v = dv;
-    }
-    return r;
-}
-
 // LDS doubles of the level-resident solve: 15 per cell (the level arrays and
 // right-hand sides take 12) + one tile + the tile's source map (4 ints per
 // element)
@@ -507,22 +472,37 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
     // the refresh map (level indices in LDS, as tile_map_build) and, for an
     // element that is a cell of the level, the level arrays in LDS and the
     // right-hand sides
+    PSrc ps = {};
+    if (prolong) ps = psrc_of(d, d.coarse, it.cpar[k]);
+    // the right-hand sides' arrays read before the first store (read after
+    // one, every element would reload them from the descriptor)
+    const double *const rfc = d.fc, *const rfmu = d.fmu, *const rfp = d.fp, *const rfu = d.fu, *const rfv = d.fv;
     for (int e = threadIdx.x; e < nt; e += blockDim.x) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = a - 1, j = b - 1;
         const TileSrcIJ q = tile_src_ij(m1, m2, L.bcx, L.bcy, i, j);
         const size_t kc = (size_t)q.jc * L.pitch + q.ic, ku = (size_t)q.ju * L.pitch + q.iu,
                      kv = (size_t)q.jv * L.pitch + q.iv;
-        double c = L.c[kc], mu = L.mu[kc], p = L.p[kc], u = ua[ku], v = va[kv];
-        const double cn = L.cn[kc], un = L.un[ku], vn = L.vn[kv];
+        const bool cell = i >= 0 && i < m1 && j >= 0 && j < m2;
+        const size_t ql = cell ? (size_t)j * L.pitch + i : 0;
+        // every load of the element before any use: its sources, the
+        // right-hand sides (a cell of the level; index 0 otherwise, not used)
+        // and the coarse values of the correction at each source
+        double c = lda<1>(L.c, kc), mu = lda<1>(L.mu, kc), p = lda<1>(L.p, kc), u = lda<1>(ua, ku),
+               v = lda<1>(va, kv);
+        const double cn = lda<1>(L.cn, kc), un = lda<1>(L.un, ku), vn = lda<1>(L.vn, kv);
+        const double f0 = rfc ? lda<1>(rfc, ql) : 0.0, f1 = rfmu ? lda<1>(rfmu, ql) : 0.0,
+                     f2 = rfp ? lda<1>(rfp, ql) : 0.0, f3 = rfu ? lda<1>(rfu, ql) : 0.0,
+                     f4 = rfv ? lda<1>(rfv, ql) : 0.0;
+        PRaw raw = {};
+        if (prolong) raw = prolong_load(ps, q.ic, q.jc, q.iu, q.ju, q.iv, q.jv);
+        __builtin_amdgcn_sched_barrier(0);
         if (prolong) {
-            const Desc &C = *d.coarse;
-            const PCorr rc = prolong_corr(d, C, it.cpar[k], q.ic, q.jc);
-            const PCorr ru = prolong_corr(d, C, it.cpar[k], q.iu, q.ju);
-            const PCorr rv = prolong_corr(d, C, it.cpar[k], q.iv, q.jv);
-            c += rc.c; mu += rc.mu; p += rc.p;
-            if (ru.hu) u += ru.u;
-            if (rv.hv) v += rv.v;
+            double rc, rm, rp, du, dv;
+            prolong_apply(ps, raw, q.iu, q.iv, q.jv, rc, rm, rp, du, dv);
+            c += rc; mu += rm; p += rp;
+            if (ps.bcx || q.iu >= 1) u += du;
+            if (ps.bcy || q.jv >= 1) v += dv;
         }
         const bool out = i > m1 + 1 || j > m2 + 1;
         map[4 * e] = q.jc * m1 + q.ic;
@@ -546,16 +526,15 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
             t[T_MOB * nt] = mob_of(P, cn);
             t[T_RS * nt] = rho_of(P, c);
         }
-        if (i >= 0 && i < m1 && j >= 0 && j < m2) {
+        if (cell) {
             // a cell of the level: its own source for every field
             const int el = j * m1 + i;
-            const size_t ql = (size_t)j * L.pitch + i;
             hc[el] = c; hmu[el] = mu; hp[el] = p; uA[el] = u; vA[el] = v;
-            hf[el] = d.fc ? d.fc[ql] : 0.0;
-            hf[n + el] = d.fmu ? d.fmu[ql] : 0.0;
-            hf[2 * n + el] = d.fp ? d.fp[ql] : 0.0;
-            hf[3 * n + el] = d.fu ? d.fu[ql] : 0.0;
-            hf[4 * n + el] = d.fv ? d.fv[ql] : 0.0;
+            hf[el] = f0;
+            hf[n + el] = f1;
+            hf[2 * n + el] = f2;
+            hf[3 * n + el] = f3;
+            hf[4 * n + el] = f4;
         }
     }
     __syncthreads();
@@ -587,14 +566,12 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
     }
 }
 
-// R w of coarse element (I, J) (a source index of the coarse level, as
-// tile_src gives it) from the fine arrays of view Lf: cells the mean of the
-// four children, faces the mean of the two coincident fine faces, summed in
-// the order k_restrict sums them
-__device__ __forceinline__ double rw_cell(const double *f, int pitch, int I, int J)
+// R w of a coarse cell from the values of its four children (a, b: the
+// children (0, 0), (1, 0); c, d: (0, 1), (1, 1)): the mean, summed in the order
+// k_restrict sums the children's residuals
+__device__ __forceinline__ double rw_mean(double a, double b, double c, double d)
 {
-    const size_t a = (size_t)(2 * J) * pitch + 2 * I, b = a + pitch;
-    return 0.25 * ((f[a] + f[a + 1]) + (f[b] + f[b + 1]));
+    return 0.25 * ((a + b) + (c + d));
 }
 
 // fine residual r = f - N(w) restricted to the coarse grid together with the
@@ -643,20 +620,29 @@ template <typename IT> __global__ __launch_bounds__(RBLK) void k_restrict(IT it)
                 continue;
             }
             const int Ic = s.c % C.pitch, Jc = s.c / C.pitch;
-            const double c = rw_cell(Lf.c, Lf.pitch, Ic, Jc);
             const int Iu = s.u % C.pitch, Ju = s.u / C.pitch, Iv = s.v % C.pitch, Jv = s.v / C.pitch;
             const size_t fu = (size_t)(2 * Ju) * Lf.pitch + 2 * Iu, fv = (size_t)(2 * Jv) * Lf.pitch + 2 * Iv;
-            const double u = s.su ? 0.5 * (Lf.u[fu] + Lf.u[fu + Lf.pitch]) : 0.0;
-            const double w = s.sv ? 0.5 * (Lf.v[fv] + Lf.v[fv + 1]) : 0.0;
-            const double cn = C.cn[s.c];
+            // every load before any use (the faces of a wall: loaded in any
+            // case, the indices are valid)
+            const size_t fa = (size_t)(2 * Jc) * Lf.pitch + 2 * Ic, fb = fa + Lf.pitch;
+            const double c4[4] = { lda<1>(Lf.c, fa), lda<1>(Lf.c, fa + 1), lda<1>(Lf.c, fb), lda<1>(Lf.c, fb + 1) };
+            const double m4[4] = { lda<1>(Lf.mu, fa), lda<1>(Lf.mu, fa + 1), lda<1>(Lf.mu, fb), lda<1>(Lf.mu, fb + 1) };
+            const double p4[4] = { lda<1>(Lf.p, fa), lda<1>(Lf.p, fa + 1), lda<1>(Lf.p, fb), lda<1>(Lf.p, fb + 1) };
+            const double u0 = lda<1>(Lf.u, fu), u1 = lda<1>(Lf.u, fu + Lf.pitch);
+            const double w0 = lda<1>(Lf.v, fv), w1 = lda<1>(Lf.v, fv + 1);
+            const double cn = lda<1>(C.cn, s.c), un = lda<1>(C.un, s.u), vn = lda<1>(C.vn, s.v);
+            __builtin_amdgcn_sched_barrier(0);
+            const double c = rw_mean(c4[0], c4[1], c4[2], c4[3]);
+            const double u = s.su ? 0.5 * (u0 + u1) : 0.0;
+            const double w = s.sv ? 0.5 * (w0 + w1) : 0.0;
             t[T_C * n] = c;
-            t[T_MU * n] = rw_cell(Lf.mu, Lf.pitch, Ic, Jc);
-            t[T_P * n] = rw_cell(Lf.p, Lf.pitch, Ic, Jc);
+            t[T_MU * n] = rw_mean(m4[0], m4[1], m4[2], m4[3]);
+            t[T_P * n] = rw_mean(p4[0], p4[1], p4[2], p4[3]);
             t[T_U * n] = signed_val(s.su, u);
             t[T_V * n] = signed_val(s.sv, w);
             t[T_CN * n] = cn;
-            t[T_UN * n] = signed_val(s.su, C.un[s.u]);
-            t[T_VN * n] = signed_val(s.sv, C.vn[s.v]);
+            t[T_UN * n] = signed_val(s.su, un);
+            t[T_VN * n] = signed_val(s.sv, vn);
             t[T_RN * n] = rho_of(PC, cn);
             t[T_MV * n] = visc_of(PC, cn);
             t[T_MOB * n] = mob_of(PC, cn);
@@ -696,7 +682,7 @@ template <typename IT> __global__ __launch_bounds__(RBLK) void k_restrict(IT it)
     __syncthreads();
     if (!on || ch != 0) return;
     // sums over the four children as (0,0) + (1,0) plus (0,1) + (1,1), the
-    // order in which the coarse tile's R w was summed (rw_cell)
+    // order in which the coarse tile's R w was summed (rw_mean)
     if (hlf == 0) {
 #pragma unroll
         for (int q = 0; q < 8; q++) v[q] = (v[q] + part[0][cc][q]) + (part[1][cc][q] + part[2][cc][q]);
@@ -749,12 +735,21 @@ template <typename IT> __global__ __launch_bounds__(BLK) void k_prolong(IT it)
     if (t >= d.m1 * d.m2) return;
     const int j = t / d.m1, i = t - j * d.m1;
     const size_t kf = (size_t)j * d.pitch + i;
-    const PCorr r = prolong_corr(d, C, it.cpar[k], i, j);
-    d.c[kf] += r.c;
-    d.mu[kf] += r.mu;
-    d.p[kf] += r.p;
-    if (r.hu) d.ub[it.par[k]][kf] += r.u;
-    if (r.hv) d.vb[it.par[k]][kf] += r.v;
+    // the correction of the cell and its west and south faces, every load
+    // issued before any use
+    const PSrc ps = psrc_of(d, &C, it.cpar[k]);
+    double *ub = d.ub[it.par[k]], *vb = d.vb[it.par[k]];
+    const PRaw raw = prolong_load(ps, i, j, i, j, i, j);
+    const double c = lda<1>(d.c, kf), mu = lda<1>(d.mu, kf), p = lda<1>(d.p, kf), u = lda<1>(ub, kf),
+                 v = lda<1>(vb, kf);
+    __builtin_amdgcn_sched_barrier(0);
+    double rc, rm, rp, du, dv;
+    prolong_apply(ps, raw, i, i, j, rc, rm, rp, du, dv);
+    sta<1>(d.c, kf, c + rc);
+    sta<1>(d.mu, kf, mu + rm);
+    sta<1>(d.p, kf, p + rp);
+    if (ps.bcx || i >= 1) sta<1>(ub, kf, u + du);
+    if (ps.bcy || j >= 1) sta<1>(vb, kf, v + dv);
 }
 
 // wave64 + LDS block sum of NRED values (blocks of up to 16 waves)

@@ -333,8 +333,8 @@ static void add_item(ItemList &W, const qnsch_ctx *x, int kind, int l)
     const int k = it.n;
     it.start[k] = start;
     it.d[k] = x->dd + l;
-    it.par[k] = (short)x->L[l].cur;
-    it.cpar[k] = (short)(l + 1 < x->nlev ? x->L[l + 1].cur : 0);
+    it.par[k] = x->L[l].cur;
+    it.cpar[k] = l + 1 < x->nlev ? x->L[l + 1].cur : 0;
     it.tx[k] = tiles_x(x->L[l].m1);
     it.acc[k] = -1;
     W.blocks = start + op_blocks(x, kind, l);
@@ -355,7 +355,7 @@ static ItemList finalize_list(const std::vector<std::pair<qnsch_ctx *, int>> &v,
         qnsch_ctx *x = e.first;
         const int k = F.it.n;
         F.it.d[k] = x->dd;
-        F.it.par[k] = (short)x->L[0].cur;
+        F.it.par[k] = x->L[0].cur;
         F.it.tx[k] = op_blocks(x, partial_kind, 0);
         F.it.acc[k] = -1;
         F.it.start[k] = k;
@@ -436,7 +436,7 @@ static int prof_mark(qnsch_ctx *x, hipStream_t s, int tag, bool end, bool stampe
 
 // a recording residual reduction is being launched: the result goes to the
 // next ring slot, paired with up to m earlier results of the history
-static void acc_record_launch(qnsch_ctx *x, short &acc)
+static void acc_record_launch(qnsch_ctx *x, int &acc)
 {
     if (x->acc_first) {
         x->acc_first = false;
@@ -447,7 +447,7 @@ static void acc_record_launch(qnsch_ctx *x, short &acc)
     const int m = x->opt.accel, R = m + 1;
     x->acc_pos = (x->acc_pos + 1) % R;
     x->acc_dots = std::min(x->acc_cnt, m);
-    acc = (short)(x->acc_pos | (x->acc_dots << 4));
+    acc = x->acc_pos | (x->acc_dots << 4);
     x->acc_wait = true;
     x->acc_use = 0;
 }
@@ -665,7 +665,7 @@ static int launch_op(int kind, int colour, const std::vector<std::pair<qnsch_ctx
             memset(&G, 0, sizeof(G));
             for (size_t q = 0; q < part.size(); q++) {
                 qnsch_ctx *x = part[q].first;
-                W.it.acc[q] = (short)(x->acc_pos | (x->acc_use << 4));
+                W.it.acc[q] = x->acc_pos | (x->acc_use << 4);
                 for (int b = 0; b < 3; b++) G.g[q][b] = x->acc_g[b];
                 x->acc_use = 0;
             }

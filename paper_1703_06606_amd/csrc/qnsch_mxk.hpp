@@ -227,7 +227,8 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_restrict(IT 
 }
 
 // P delta_H at fine cell (i, j) of level d (the FP32 correction; cells
-// piecewise constant, faces as in prolong_corr); hu/hv false on walls
+// piecewise constant, faces as in prolong_load / prolong_apply); hu/hv false
+// on walls
 struct PCorrF {
     float c, mu, p, u, v;
     bool hu, hv;
