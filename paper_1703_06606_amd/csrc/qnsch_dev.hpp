@@ -23,6 +23,19 @@
 
 namespace qn {
 
+// threads of the workgroup.  Every launch of this library has whole
+// workgroups, so this is the dispatch's group size: the 16-bit field at byte
+// 12 of the implicit kernel arguments (code object v5), read with a scalar
+// load of its 32-bit word.  blockDim.x also allows for a partial last
+// workgroup and reads the field with a vector load, one memory latency at the
+// start of every kernel that uses it.
+__device__ __forceinline__ int block_threads()
+{
+    const __attribute__((address_space(4))) unsigned int *p =
+        (const __attribute__((address_space(4))) unsigned int *)__builtin_amdgcn_implicitarg_ptr();
+    return (int)(p[3] & 0xffffu);
+}
+
 struct Phys {
     double rho1, rho2, rho12, drho;  // rho(c) = rho12 / (drho c + rho1)
     double visc1, visc2, visc12, dvisc;
@@ -225,11 +238,11 @@ __device__ __forceinline__ bool tile_inner(int m1, int m2, int i0, int j0, int W
 __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Tile &T)
 {
     const int n = T.W * T.H;
-    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)blockDim.x) {
+    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)block_threads()) {
         // no boundary images: plain strided loads, the two elements of a
         // thread loaded together (the second one clamped to a valid element
         // and stored only if it exists) so that all loads are in flight at once
-        const int e0 = threadIdx.x, e1r = threadIdx.x + blockDim.x, e1 = e1r < n ? e1r : n - 1;
+        const int e0 = threadIdx.x, e1r = threadIdx.x + block_threads(), e1 = e1r < n ? e1r : n - 1;
         auto at = [&](int e) {
             const int b = e / T.W, a = e - b * T.W;
             return (size_t)(T.j0 - 1 + b) * L.pitch + (T.i0 - 1 + a);
@@ -261,10 +274,10 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
         if (e1r < n) put(e1r, v1);
         return;
     }
-    if (n <= 2 * (int)blockDim.x) {
+    if (n <= 2 * (int)block_threads()) {
         // boundary images: the sources of both elements of the thread first,
         // then all sixteen loads together, then the signs and cell functions
-        const int e0 = threadIdx.x, e1 = threadIdx.x + blockDim.x;
+        const int e0 = threadIdx.x, e1 = threadIdx.x + block_threads();
         auto src = [&](int e) {
             const int b = e / T.W, a = e - b * T.W;
             TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, T.i0 - 1 + a, T.j0 - 1 + b);
@@ -297,7 +310,7 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
         if (e1 < n) put(e1, s1, v1);
         return;
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         double *s = T.s + e;
@@ -332,7 +345,7 @@ __device__ __forceinline__ void tile_load(const Phys &P, const View &L, const Ti
 template <typename V, typename TT> __device__ __forceinline__ void tile_map_build(const V &L, const TT &T, int *map)
 {
     const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         const TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, i, j);
@@ -353,7 +366,7 @@ __device__ __forceinline__ void tile_refresh_map(const Phys &P, const View &L, c
                                                  int colour)
 {
     const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int fl = map[4 * e + 3];
         if (fl & 16) continue;
         double *s = T.s + e;

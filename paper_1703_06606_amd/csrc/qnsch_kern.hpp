@@ -284,7 +284,7 @@ __device__ __forceinline__ void prolong_apply(const PSrc &C, const PRaw &r, int 
 __device__ __forceinline__ void fused_load(const Phys &P, const View &L, const Tile &T, const PSrc *pc = nullptr)
 {
     const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         if (L.bcx) i = wrapi(i, L.m1);
@@ -340,7 +340,7 @@ __device__ __forceinline__ void fused_refresh(const View &L, const Tile &T)
 {
     const int n = T.W * T.H;
     const double *un = T.s + T_NF * n, *vn = T.s + (T_NF + 1) * n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         const bool gx = !L.bcx && (i < 0 || i >= L.m1), gy = !L.bcy && (j < 0 || j >= L.m2);
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
     // the right-hand sides' arrays read before the first store (read after
     // one, every element would reload them from the descriptor)
     const double *const rfc = d.fc, *const rfmu = d.fmu, *const rfp = d.fp, *const rfu = d.fu, *const rfv = d.fv;
-    for (int e = threadIdx.x; e < nt; e += blockDim.x) {
+    for (int e = threadIdx.x; e < nt; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = a - 1, j = b - 1;
         const TileSrcIJ q = tile_src_ij(m1, m2, L.bcx, L.bcy, i, j);
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
             tile_refresh_map(P, H, T, map, colour ^ 1);
             __syncthreads();
         }
-        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
+        for (int t = threadIdx.x; t < 2 * half * m2; t += block_threads()) {
             const int pr = t >> 1;
             const int j = pr / half;
             const int i = 2 * (pr - j * half) + ((j + colour) & 1);
@@ -559,7 +559,7 @@ __global__ __launch_bounds__(512) void k_coarse_solve(IT it, int sweeps, double 
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int j = e / m1, i = e - j * m1;
         const size_t q = (size_t)j * L.pitch + i;
         L.c[q] = hc[e]; L.mu[q] = hmu[e]; L.p[q] = hp[e]; ua[q] = uA[e]; va[q] = vA[e];
@@ -611,7 +611,7 @@ template <typename IT> __global__ __launch_bounds__(RBLK) void k_restrict(IT it)
     Tc.s = smc; Tc.i0 = T.i0 / 2; Tc.j0 = T.j0 / 2; Tc.W = TX / 2 + 3; Tc.H = TY / 2 + 3;
     {
         const int n = Tc.W * Tc.H;
-        for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        for (int e = threadIdx.x; e < n; e += block_threads()) {
             const int bb = e / Tc.W, aa = e - bb * Tc.W;
             const TileSrc s = tile_src(C.m1, C.m2, C.pitch, C.bcx, C.bcy, Tc.i0 - 1 + aa, Tc.j0 - 1 + bb);
             double *t = Tc.s + e;
@@ -767,7 +767,7 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NRED], double *out)
     __syncthreads();
     if (threadIdx.x < NRED) {
         double s = 0.0;
-        for (int ww = 0; ww < (int)(blockDim.x >> 6); ww++) s += sh[ww][threadIdx.x];
+        for (int ww = 0; ww < (int)(block_threads() >> 6); ww++) s += sh[ww][threadIdx.x];
         out[threadIdx.x] = s;
     }
 }

@@ -65,10 +65,10 @@ __device__ __forceinline__ float mobf(const PhysF &P, float c)
 __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const TileF &T)
 {
     const int n = T.W * T.H;
-    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)blockDim.x) {
+    if (tile_inner(L.m1, L.m2, T.i0, T.j0, T.W, T.H) && n <= 2 * (int)block_threads()) {
         // no boundary images: plain strided loads, a thread's two elements
         // loaded together (see tile_load)
-        const int e0 = threadIdx.x, e1r = threadIdx.x + blockDim.x, e1 = e1r < n ? e1r : n - 1;
+        const int e0 = threadIdx.x, e1r = threadIdx.x + block_threads(), e1 = e1r < n ? e1r : n - 1;
         auto at = [&](int e) {
             const int b = e / T.W, a = e - b * T.W;
             return (size_t)(T.j0 - 1 + b) * L.pitch + (T.i0 - 1 + a);
@@ -103,9 +103,9 @@ __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const
         if (e1r < n) put(e1r, v1);
         return;
     }
-    if (n <= 2 * (int)blockDim.x) {
+    if (n <= 2 * (int)block_threads()) {
         // boundary images: sources first, then all loads together (see tile_load)
-        const int e0 = threadIdx.x, e1 = threadIdx.x + blockDim.x;
+        const int e0 = threadIdx.x, e1 = threadIdx.x + block_threads();
         auto src = [&](int e) {
             const int b = e / T.W, a = e - b * T.W;
             TileSrc q = tile_src(L.m1, L.m2, L.pitch, L.bcx, L.bcy, T.i0 - 1 + a, T.j0 - 1 + b);
@@ -143,7 +143,7 @@ __device__ __forceinline__ void ltile_load(const PhysF &P, const LView &L, const
         if (e1 < n) put(e1, s1, v1);
         return;
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         float *s = T.s + e;
@@ -181,7 +181,7 @@ __device__ __forceinline__ void ltile_refresh_map(const PhysF &P, const LView &L
                                                   int colour)
 {
     const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int fl = map[4 * e + 3];
         if (fl & 16) continue;
         float *s = T.s + e;

@@ -70,7 +70,7 @@ static_assert(MX_FUSED_FLOATS * 4 <= 65536, "fused FP32 tile exceeds 64 KiB of L
 __device__ __forceinline__ void mx_fused_load(const PhysF &P, const LView &L, const TileF &T)
 {
     const int n = T.W * T.H;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         if (L.bcx) i = wrapi(i, L.m1);
@@ -106,7 +106,7 @@ __device__ __forceinline__ void mx_fused_refresh(const LView &L, const TileF &T)
 {
     const int n = T.W * T.H;
     const float *un = T.s + L_NF * n, *vn = T.s + (L_NF + 1) * n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int b = e / T.W, a = e - b * T.W;
         const int i = T.i0 - 1 + a, j = T.j0 - 1 + b;
         const bool gx = !L.bcx && (i < 0 || i >= L.m1), gy = !L.bcy && (j < 0 || j >= L.m2);
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, floa
     float *hxc = smf, *hxmu = smf + n, *hxu = smf + 2 * n, *hxv = smf + 3 * n, *hdc = smf + 4 * n,
           *hdmu = smf + 5 * n, *hdp = smf + 6 * n, *uA = smf + 7 * n, *vA = smf + 8 * n, *uB = smf + 9 * n,
           *vB = smf + 10 * n, *hcn = smf + 11 * n, *hun = smf + 12 * n, *hvn = smf + 13 * n, *hr = smf + 14 * n;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int j = e / m1, i = e - j * m1;
         const size_t q = (size_t)j * L.pitch + i;
         hxc[e] = L.c[q]; hxmu[e] = L.mu[q]; hxu[e] = L.u[q]; hxv[e] = L.v[q];
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, floa
         if (s == 0) ltile_load(d.Pf, H, T);
         else ltile_refresh_map(d.Pf, H, T, map, colour ^ 1);
         __syncthreads();
-        for (int t = threadIdx.x; t < 2 * half * m2; t += blockDim.x) {
+        for (int t = threadIdx.x; t < 2 * half * m2; t += block_threads()) {
             const int pr = t >> 1;
             const int j = pr / half;
             const int i = 2 * (pr - j * half) + ((j + colour) & 1);
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, floa
         }
         __syncthreads();
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int j = e / m1, i = e - j * m1;
         const size_t q = (size_t)j * L.pitch + i;
         L.dc[q] = hdc[e]; L.dmu[q] = hdmu[e]; L.dp[q] = hdp[e]; ua[q] = uA[e]; va[q] = vA[e];
