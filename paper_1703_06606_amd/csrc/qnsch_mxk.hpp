@@ -81,8 +81,11 @@ __device__ __forceinline__ void mx_fused_load(const PhysF &P, const LView &L, co
             for (int f = 0; f < L_NF + 2; f++) s[f * n] = 0.0f;
             continue;
         }
-        const float v[9] = { L.c[q.c], L.dc[q.c], L.dmu[q.c], L.dp[q.c], L.du[q.u], L.dv[q.v],
-                             L.cn[q.c], L.un[q.u], L.vn[q.v] };
+        // the level is in global memory; every load before any use
+        const float v[9] = { lda<1>(L.c, q.c), lda<1>(L.dc, q.c), lda<1>(L.dmu, q.c), lda<1>(L.dp, q.c),
+                             lda<1>(L.du, q.u), lda<1>(L.dv, q.v), lda<1>(L.cn, q.c), lda<1>(L.un, q.u),
+                             lda<1>(L.vn, q.v) };
+        __builtin_amdgcn_sched_barrier(0);
         s[L_C * n] = v[0];
         s[L_DC * n] = v[1];
         s[L_MU * n] = v[2];
@@ -226,46 +229,58 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_restrict(IT 
     }
 }
 
-// P delta_H at fine cell (i, j) of level d (the FP32 correction; cells
-// piecewise constant, faces as in prolong_load / prolong_apply); hu/hv false
-// on walls
-struct PCorrF {
-    float c, mu, p, u, v;
-    bool hu, hv;
+// P delta_H of the FP32 correction at fine cell (i, j): cells piecewise
+// constant, faces as in prolong_load / prolong_apply (a face on a wall is no
+// unknown), in two parts so that every load is in flight before any value is
+// used.  The coarse arrays are read from the descriptor once per workgroup,
+// through a global pointer (scalar loads).
+struct PSrcF {
+    const float *dc, *dmu, *dp, *du, *dv;
+    int pitch, m1, m2, bcx, bcy;
 };
-__device__ __forceinline__ PCorrF mx_prolong_corr(const Desc &d, const Desc &C, int cpar, int i, int j)
+__device__ __forceinline__ PSrcF psrcf_of(const Desc &d, const Desc *cp, int cpar)
 {
-    PCorrF r;
+    const __attribute__((address_space(1))) Desc &C = *(const __attribute__((address_space(1))) Desc *)cp;
+    PSrcF s;
+    s.dc = C.dc; s.dmu = C.dmu; s.dp = C.dp; s.du = C.dub[cpar]; s.dv = C.dvb[cpar];
+    s.pitch = C.pitch; s.m1 = C.m1; s.m2 = C.m2; s.bcx = d.bcx; s.bcy = d.bcy;
+    return s;
+}
+// the coarse cell of fine cell (i, j), and for its west (south) face the
+// coarse face it lies on and the next one east (north): the periodic image,
+// or, where there is none, the same face again (loaded, not used)
+struct PRawF {
+    float c, mu, p, u[2], v[2];
+};
+__device__ __forceinline__ PRawF mx_prolong_load(const PSrcF &C, int i, int j)
+{
+    PRawF r;
     const int I = i >> 1, J = j >> 1;
     const size_t kc = (size_t)J * C.pitch + I;
-    const float *Cu = C.dub[cpar], *Cv = C.dvb[cpar];
-    r.c = C.dc[kc];
-    r.mu = C.dmu[kc];
-    r.p = C.dp[kc];
-    r.hu = d.bcx || i >= 1;
-    r.hv = d.bcy || j >= 1;
-    r.u = r.v = 0.0f;
-    if (r.hu) {
-        float du = Cu[kc];
-        if (i & 1) {
-            float e = 0.0f;
-            if (I + 1 < C.m1) e = Cu[kc + 1];
-            else if (d.bcx) e = Cu[(size_t)J * C.pitch];
-            du = 0.5f * (du + e);
-        }
-        r.u = du;
-    }
-    if (r.hv) {
-        float dv = Cv[kc];
-        if (j & 1) {
-            float e = 0.0f;
-            if (J + 1 < C.m2) e = Cv[kc + C.pitch];
-            else if (d.bcy) e = Cv[I];
-            dv = 0.5f * (dv + e);
-        }
-        r.v = dv;
-    }
+    r.c = lda<1>(C.dc, kc); r.mu = lda<1>(C.dmu, kc); r.p = lda<1>(C.dp, kc);
+    const size_t ke = I + 1 < C.m1 ? kc + 1 : (C.bcx ? (size_t)J * C.pitch : kc);
+    const size_t kn = J + 1 < C.m2 ? kc + C.pitch : (C.bcy ? (size_t)I : kc);
+    r.u[0] = lda<1>(C.du, kc); r.u[1] = lda<1>(C.du, ke);
+    r.v[0] = lda<1>(C.dv, kc); r.v[1] = lda<1>(C.dv, kn);
     return r;
+}
+// ... the corrections; hu / hv: the face is an unknown
+__device__ __forceinline__ void mx_prolong_apply(const PSrcF &C, const PRawF &r, int i, int j, float &c, float &mu,
+                                                 float &p, float &du, float &dv, bool &hu, bool &hv)
+{
+    c = r.c; mu = r.mu; p = r.p;
+    hu = C.bcx || i >= 1;
+    hv = C.bcy || j >= 1;
+    du = r.u[0];
+    if (i & 1) {
+        const float e = ((i >> 1) + 1 < C.m1 || C.bcx) ? r.u[1] : 0.0f;
+        du = 0.5f * (du + e);
+    }
+    dv = r.v[0];
+    if (j & 1) {
+        const float e = ((j >> 1) + 1 < C.m2 || C.bcy) ? r.v[1] : 0.0f;
+        dv = 0.5f * (dv + e);
+    }
 }
 
 // delta_h += P delta_H, one thread per fine cell
@@ -273,17 +288,24 @@ template <typename IT> __global__ __launch_bounds__(BLK) void k_mx_prolong(IT it
 {
     const int k = find_item(it);
     const Desc &d = *it.d[k];
-    const Desc &C = *d.coarse;
     const int t = ((int)blockIdx.x - it.start[k]) * BLK + threadIdx.x;
     if (t >= d.m1 * d.m2) return;
     const int j = t / d.m1, i = t - j * d.m1;
     const size_t kf = (size_t)j * d.pitch + i;
-    const PCorrF r = mx_prolong_corr(d, C, it.cpar[k], i, j);
-    d.dc[kf] += r.c;
-    d.dmu[kf] += r.mu;
-    d.dp[kf] += r.p;
-    if (r.hu) d.dub[it.par[k]][kf] += r.u;
-    if (r.hv) d.dvb[it.par[k]][kf] += r.v;
+    const PSrcF ps = psrcf_of(d, d.coarse, it.cpar[k]);
+    float *ub = d.dub[it.par[k]], *vb = d.dvb[it.par[k]];
+    const PRawF raw = mx_prolong_load(ps, i, j);
+    const float c0 = lda<1>(d.dc, kf), m0 = lda<1>(d.dmu, kf), p0 = lda<1>(d.dp, kf), u0 = lda<1>(ub, kf),
+                v0 = lda<1>(vb, kf);
+    __builtin_amdgcn_sched_barrier(0);
+    float c, mu, p, du, dv;
+    bool hu, hv;
+    mx_prolong_apply(ps, raw, i, j, c, mu, p, du, dv, hu, hv);
+    sta<1>(d.dc, kf, c0 + c);
+    sta<1>(d.dmu, kf, m0 + mu);
+    sta<1>(d.dp, kf, p0 + p);
+    if (hu) sta<1>(ub, kf, u0 + du);
+    if (hv) sta<1>(vb, kf, v0 + dv);
 }
 
 // LDS floats of the coarsest-level correction solve: 19 level arrays + a tile
@@ -309,20 +331,34 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, floa
     float *hxc = smf, *hxmu = smf + n, *hxu = smf + 2 * n, *hxv = smf + 3 * n, *hdc = smf + 4 * n,
           *hdmu = smf + 5 * n, *hdp = smf + 6 * n, *uA = smf + 7 * n, *vA = smf + 8 * n, *uB = smf + 9 * n,
           *vB = smf + 10 * n, *hcn = smf + 11 * n, *hun = smf + 12 * n, *hvn = smf + 13 * n, *hr = smf + 14 * n;
+    PSrcF ps = {};
+    if (prolong) ps = psrcf_of(d, d.coarse, it.cpar[k]);
     for (int e = threadIdx.x; e < n; e += block_threads()) {
         const int j = e / m1, i = e - j * m1;
         const size_t q = (size_t)j * L.pitch + i;
-        hxc[e] = L.c[q]; hxmu[e] = L.mu[q]; hxu[e] = L.u[q]; hxv[e] = L.v[q];
-        hdc[e] = L.dc[q]; hdmu[e] = L.dmu[q]; hdp[e] = L.dp[q]; uA[e] = ua[q]; vA[e] = va[q];
+        // every load of the element before any use
+        const float xc = lda<1>(L.c, q), xmu = lda<1>(L.mu, q), xu = lda<1>(L.u, q), xv = lda<1>(L.v, q);
+        float dc = lda<1>(L.dc, q), dmu = lda<1>(L.dmu, q), dp = lda<1>(L.dp, q), du = lda<1>(ua, q),
+              dv = lda<1>(va, q);
+        const float cn = lda<1>(L.cn, q), un = lda<1>(L.un, q), vn = lda<1>(L.vn, q);
+        const float r0 = lda<1>(L.rc, q), r1 = lda<1>(L.rmu, q), r2 = lda<1>(L.rp, q), r3 = lda<1>(L.ru, q),
+                    r4 = lda<1>(L.rv, q);
+        PRawF raw = {};
+        if (prolong) raw = mx_prolong_load(ps, i, j);
+        __builtin_amdgcn_sched_barrier(0);
         if (prolong) {
-            const PCorrF r = mx_prolong_corr(d, *d.coarse, it.cpar[k], i, j);
-            hdc[e] += r.c; hdmu[e] += r.mu; hdp[e] += r.p;
-            if (r.hu) uA[e] += r.u;
-            if (r.hv) vA[e] += r.v;
+            float c, mu, p, pu, pv;
+            bool hu, hv;
+            mx_prolong_apply(ps, raw, i, j, c, mu, p, pu, pv, hu, hv);
+            dc += c; dmu += mu; dp += p;
+            if (hu) du += pu;
+            if (hv) dv += pv;
         }
-        hcn[e] = L.cn[q]; hun[e] = L.un[q]; hvn[e] = L.vn[q];
-        hr[e] = L.rc[q]; hr[n + e] = L.rmu[q]; hr[2 * n + e] = L.rp[q]; hr[3 * n + e] = L.ru[q];
-        hr[4 * n + e] = L.rv[q];
+        hxc[e] = xc; hxmu[e] = xmu; hxu[e] = xu; hxv[e] = xv;
+        hdc[e] = dc; hdmu[e] = dmu; hdp[e] = dp; uA[e] = du; vA[e] = dv;
+        hcn[e] = cn; hun[e] = un; hvn[e] = vn;
+        hr[e] = r0; hr[n + e] = r1; hr[2 * n + e] = r2; hr[3 * n + e] = r3;
+        hr[4 * n + e] = r4;
     }
     __syncthreads();
     LView H = L;
