@@ -367,17 +367,20 @@ __device__ __forceinline__ void tile_refresh_map(const Phys &P, const View &L, c
 {
     const int n = T.W * T.H;
     for (int e = threadIdx.x; e < n; e += block_threads()) {
-        const int fl = map[4 * e + 3];
+        // the map entry, then every value the element may take (the indices
+        // are valid in any case), before any use: two round trips to LDS
+        // instead of one per dependent step
+        const int q = map[4 * e], qu = map[4 * e + 1], qv = map[4 * e + 2], fl = map[4 * e + 3];
+        const double u = L.u[qu], v = L.v[qv], c = L.c[q], mu = L.mu[q], p = L.p[q];
+        __builtin_amdgcn_sched_barrier(0);
         if (fl & 16) continue;
         double *s = T.s + e;
-        s[T_U * n] = signed_val((fl & 3) - 1, L.u[map[4 * e + 1]]);
-        s[T_V * n] = signed_val(((fl >> 2) & 3) - 1, L.v[map[4 * e + 2]]);
+        s[T_U * n] = signed_val((fl & 3) - 1, u);
+        s[T_V * n] = signed_val(((fl >> 2) & 3) - 1, v);
         if (((fl >> 5) & 1) != colour) continue;
-        const int q = map[4 * e];
-        const double c = L.c[q];
         s[T_C * n] = c;
-        s[T_MU * n] = L.mu[q];
-        s[T_P * n] = L.p[q];
+        s[T_MU * n] = mu;
+        s[T_P * n] = p;
         s[T_RS * n] = rho_of(P, c);
     }
 }

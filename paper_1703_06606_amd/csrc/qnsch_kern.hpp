@@ -347,14 +347,19 @@ __device__ __forceinline__ void fused_refresh(const View &L, const Tile &T)
         const int si = gx ? (i < 0 ? 0 : L.m1 - 1) : i, sj = gy ? (j < 0 ? 0 : L.m2 - 1) : j;
         const int su = (!L.bcx && (i <= 0 || i >= L.m1)) ? 0 : (gy ? -1 : 1);
         const int sv = (!L.bcy && (j <= 0 || j >= L.m2)) ? 0 : (gx ? -1 : 1);
-        T.s[T_U * n + e] = signed_val(su, un[T.idx(i, sj)]);
-        T.s[T_V * n + e] = signed_val(sv, vn[T.idx(si, j)]);
+        // every value the element may take, before any store (an image's
+        // source q is never an image, so no element read here is written)
+        const int q = T.idx(si, sj);
+        const double u = un[T.idx(i, sj)], v = vn[T.idx(si, j)], c = T.s[T_C * n + q], mu = T.s[T_MU * n + q],
+                     p = T.s[T_P * n + q], rs = T.s[T_RS * n + q];
+        __builtin_amdgcn_sched_barrier(0);
+        T.s[T_U * n + e] = signed_val(su, u);
+        T.s[T_V * n + e] = signed_val(sv, v);
         if (gx || gy) {
-            const int q = T.idx(si, sj);
-            T.s[T_C * n + e] = T.s[T_C * n + q];
-            T.s[T_MU * n + e] = T.s[T_MU * n + q];
-            T.s[T_P * n + e] = T.s[T_P * n + q];
-            T.s[T_RS * n + e] = T.s[T_RS * n + q];
+            T.s[T_C * n + e] = c;
+            T.s[T_MU * n + e] = mu;
+            T.s[T_P * n + e] = p;
+            T.s[T_RS * n + e] = rs;
         }
     }
 }

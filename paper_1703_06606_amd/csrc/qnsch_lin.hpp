@@ -182,18 +182,19 @@ __device__ __forceinline__ void ltile_refresh_map(const PhysF &P, const LView &L
 {
     const int n = T.W * T.H;
     for (int e = threadIdx.x; e < n; e += block_threads()) {
-        const int fl = map[4 * e + 3];
-        if (fl & 16) continue;
+        // the map entry, then every value the element may take, before any
+        // use (as tile_refresh_map)
+        const int q = map[4 * e], qu = map[4 * e + 1], qv = map[4 * e + 2], fl = map[4 * e + 3];
         float *s = T.s + e;
-        s[L_U * n] = signed_val((fl & 3) - 1, L.du[map[4 * e + 1]]);
-        s[L_V * n] = signed_val(((fl >> 2) & 3) - 1, L.dv[map[4 * e + 2]]);
+        const float du = L.du[qu], dv = L.dv[qv], dc = L.dc[q], dmu = L.dmu[q], dp = L.dp[q], rs = s[L_RS * n];
+        __builtin_amdgcn_sched_barrier(0);
+        if (fl & 16) continue;
+        s[L_U * n] = signed_val((fl & 3) - 1, du);
+        s[L_V * n] = signed_val(((fl >> 2) & 3) - 1, dv);
         if (((fl >> 5) & 1) != colour) continue;
-        const int q = map[4 * e];
-        const float dc = L.dc[q];
-        const float rs = s[L_RS * n];
         s[L_DC * n] = dc;
-        s[L_MU * n] = L.dmu[q];
-        s[L_P * n] = L.dp[q];
+        s[L_MU * n] = dmu;
+        s[L_P * n] = dp;
         s[L_DRS * n] = -P.alpha * rs * rs * dc;
     }
 }

@@ -116,14 +116,19 @@ __device__ __forceinline__ void mx_fused_refresh(const LView &L, const TileF &T)
         const int si = gx ? (i < 0 ? 0 : L.m1 - 1) : i, sj = gy ? (j < 0 ? 0 : L.m2 - 1) : j;
         const int su = (!L.bcx && (i <= 0 || i >= L.m1)) ? 0 : (gy ? -1 : 1);
         const int sv = (!L.bcy && (j <= 0 || j >= L.m2)) ? 0 : (gx ? -1 : 1);
-        T.s[L_U * n + e] = signed_val(su, un[T.idx(i, sj)]);
-        T.s[L_V * n + e] = signed_val(sv, vn[T.idx(si, j)]);
+        // every value the element may take, before any store (as
+        // fused_refresh)
+        const int q = T.idx(si, sj);
+        const float u = un[T.idx(i, sj)], v = vn[T.idx(si, j)], dc = T.s[L_DC * n + q], mu = T.s[L_MU * n + q],
+                    p = T.s[L_P * n + q], drs = T.s[L_DRS * n + q];
+        __builtin_amdgcn_sched_barrier(0);
+        T.s[L_U * n + e] = signed_val(su, u);
+        T.s[L_V * n + e] = signed_val(sv, v);
         if (gx || gy) {
-            const int q = T.idx(si, sj);
-            T.s[L_DC * n + e] = T.s[L_DC * n + q];
-            T.s[L_MU * n + e] = T.s[L_MU * n + q];
-            T.s[L_P * n + e] = T.s[L_P * n + q];
-            T.s[L_DRS * n + e] = T.s[L_DRS * n + q];
+            T.s[L_DC * n + e] = dc;
+            T.s[L_MU * n + e] = mu;
+            T.s[L_P * n + e] = p;
+            T.s[L_DRS * n + e] = drs;
         }
     }
 }
