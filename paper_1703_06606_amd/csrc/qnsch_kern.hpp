@@ -1177,29 +1177,48 @@ template <typename IT, int N> __global__ __launch_bounds__(BLK) void k_accel(IT 
 #pragma unroll
     for (int b = 0; b < 3; b++) sl[b] = (s - 1 - b + R) % R;
     double *const live[5] = { d.c, d.mu, d.p, d.ub[par], d.vb[par] };
+    const bool mixed = d.rc != nullptr;
+    // every value the cell's combination needs, loaded before any use or
+    // store (the stores into the live arrays would otherwise hold back the
+    // next field's loads)
+    // (global-typed, so that a wait for a scalar load does not also wait for
+    // them)
+    const double *const aw = d.aw, *const ar = d.ar, *const amean = d.amean;
+    double x[5], w[5][3], am[3], xr[5], wr[5][3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) am[b] = b < np ? lda<1>(amean, sl[b]) : 0.0;
+#pragma unroll
+    for (int f = 0; f < 5; f++) {
+        x[f] = lda<1>(live[f], q);
+        xr[f] = mixed ? lda<1>(ar, (size_t)(s * 5 + f) * st + q) : 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; b++) {
+            w[f][b] = b < np ? lda<1>(aw, (size_t)(sl[b] * 5 + f) * st + q) : 0.0;
+            wr[f][b] = (mixed && b < np) ? lda<1>(ar, (size_t)(sl[b] * 5 + f) * st + q) : 0.0;
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
     double y[5];
 #pragma unroll
     for (int f = 0; f < 5; f++) {
-        const double x = live[f][q];
-        double a = x;
+        double a = x[f];
 #pragma unroll
         for (int b = 0; b < 3; b++)
             if (b < np) {
-                const double wb = d.aw[(size_t)(sl[b] * 5 + f) * st + q] - (f == 2 ? d.amean[sl[b]] : 0.0);
-                a += G.g[k][b] * (x - wb);
+                const double wb = w[f][b] - (f == 2 ? am[b] : 0.0);
+                a += G.g[k][b] * (x[f] - wb);
             }
         y[f] = a;
         live[f][q] = a;
     }
-    if (d.rc) {
+    if (mixed) {
         float r[5];
 #pragma unroll
         for (int f = 0; f < 5; f++) {
-            const double x = d.ar[(size_t)(s * 5 + f) * st + q];
-            double a = x;
+            double a = xr[f];
 #pragma unroll
             for (int b = 0; b < 3; b++)
-                if (b < np) a += G.g[k][b] * (x - d.ar[(size_t)(sl[b] * 5 + f) * st + q]);
+                if (b < np) a += G.g[k][b] * (xr[f] - wr[f][b]);
             r[f] = (float)a;
         }
         d.rc[q] = r[0]; d.rmu[q] = r[1]; d.rp[q] = r[2]; d.ru[q] = r[3]; d.rv[q] = r[4];
