@@ -212,7 +212,11 @@ void qnsch_default_opts(qnsch_opts *opts);
  * finest cell in FP64, 182 in mixed precision, plus 80 (accel + 1) for the
  * acceleration's history and 32 (16 in mixed precision) for the second cell
  * set of temporal blocking).  Returns
- * QNSCH_EINVAL for grids or parameters outside the ranges stated above. */
+ * QNSCH_EINVAL for grids or parameters outside the ranges stated above, and
+ * QNSCH_EDEVICE if the device check that the first creation on a device runs
+ * fails (the kernels read their workgroup size from the dispatch's implicit
+ * kernel arguments; a library built for another layout of them refuses to
+ * run; the check's reason goes to stderr). */
 int qnsch_create(const qnsch_grid *grid, const qnsch_params *params, const qnsch_opts *opts,
                  void *hip_stream, qnsch_ctx **out);
 void qnsch_destroy(qnsch_ctx *ctx);

@@ -1083,6 +1083,44 @@ static size_t device_lds_max()
     return r;
 }
 
+// the workgroup size as block_threads() reads it, written by the first thread
+// of a one-workgroup launch of BLK threads, for group_size_check below
+static __device__ int g_group_size;
+__global__ __launch_bounds__(BLK) void k_group_size_check()
+{
+    if (threadIdx.x == 0) g_group_size = block_threads();
+}
+
+// The kernels read their workgroup size from a fixed place of the dispatch's
+// implicit kernel arguments (block_threads: code object versions 5 and 6); a
+// build for another layout must not run.  One check per device, before the
+// first kernel there: QNSCH_OK, or QNSCH_EDEVICE with the reason in err.
+static int group_size_check(std::string &err)
+{
+    static std::mutex mu;
+    static int state[64] = {}; // 0 unchecked, 1 passed, -1 failed
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        err = "no current HIP device";
+        return QNSCH_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (state[dev] == 0) {
+        hipLaunchKernelGGL(k_group_size_check, dim3(1), dim3(BLK), 0, nullptr);
+        int h = 0;
+        const hipError_t e = hipMemcpyFromSymbol(&h, HIP_SYMBOL(g_group_size), sizeof(h));
+        state[dev] = (e == hipSuccess && h == BLK) ? 1 : -1;
+        if (state[dev] < 0) {
+            char b[160];
+            snprintf(b, sizeof(b), "workgroup size check: %d read from the dispatch for %d threads (%s)", h, BLK,
+                     hipGetErrorString(e));
+            err = b;
+        }
+    }
+    if (state[dev] < 0 && err.empty()) err = "workgroup size check failed on this device";
+    return state[dev] > 0 ? QNSCH_OK : QNSCH_EDEVICE;
+}
+
 static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, const qnsch_opts *o, void *stream)
 {
     int rc = QNSCH_OK;
@@ -1098,6 +1136,10 @@ static int ctx_init(qnsch_ctx *x, const qnsch_grid *g, const qnsch_params *p, co
     if (o) x->opt = *o;
     resolve_opts(x->opt, x->nlev);
     x->lds_max = device_lds_max();
+    if ((rc = group_size_check(x->err))) {
+        fprintf(stderr, "qnsch: %s\n", x->err.c_str());
+        return rc;
+    }
     {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess
@@ -1737,6 +1779,15 @@ int qnsch_residual_noalloc(const qnsch_grid *g, const qnsch_params *prm, double 
     }
     char *base = noalloc_scratch(noalloc_err);
     if (!base) return QNSCH_EDEVICE;
+    {
+        // the workgroup-size check (a launch and a synchronous copy), unless
+        // the stream is being captured: then it waits for a call outside a
+        // capture or a context creation on this device
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing((hipStream_t)stream, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone
+            && group_size_check(noalloc_err))
+            return QNSCH_EDEVICE;
+    }
     hipStream_t s = (hipStream_t)stream;
     const int tx = tiles_x(g->m1), ty = tiles_y(g->m2);
     Desc d;
