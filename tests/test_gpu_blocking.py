@@ -5,8 +5,9 @@ unfused path, through the C ABI.
 
 Cases span walls, periodic axes, ragged tiles, an odd number of sweeps (the
 last sweep unfused) and the benchmark's 256 x 512 droplet, whose three
-coarse multi-workgroup levels are the ones fused by default (blocking 1;
-blocking 2 also fuses the finest level, as it does on the small cases).  Tolerances:
+coarse multi-workgroup levels are the ones fused by default (blocking 1,
+which also fuses a finest level of at most one tile per compute unit, as on
+the small cases; blocking 2 fuses the finest level in any case).  Tolerances:
 1e-10 relative against the oracle (FP64 parity), 1e-12 against the unfused
 GPU path (same arithmetic; only the compiler's contraction of the two
 instances may differ).
