@@ -359,7 +359,7 @@ __device__ __forceinline__ float face_point(const LView &L, int hlf, size_t k) {
 // With TO set, as relax_cell: the cell at tile position (ti, tj), results
 // kept in the tile (dc, dmu, dp and the density change in place, the face
 // corrections in the fields L_NF (u) and L_NF + 1 (v)).
-template <bool TO>
+template <bool TO, int AS = 0>
 __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, const TileF &T, float *dunew,
                                             float *dvnew, int i, int j, int ti, int tj, int hlf, float omega)
 {
@@ -369,8 +369,8 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
     const Ax a = make_ax(L, T, i, j, hlf);
     const bool cpl = P.coupled;
     const LCellAx s = lcell_sum(lcell_axis(T, a, e, ih));
-    const LCellEq q = lcell_eq(P, T, e, s, L.mu[k]);
-    const float r1 = L.rc[k] - q.Nc, r2 = L.rmu[k] - q.Nmu;
+    const LCellEq q = lcell_eq(P, T, e, s, lda<AS>(L.mu, k));
+    const float r1 = lda<AS>(L.rc, k) - q.Nc, r2 = lda<AS>(L.rmu, k) - q.Nmu;
     const float c0 = tq(T, L_DC, e), m0 = tq(T, L_MU, e);
     const int st = T.W * T.H;
     const float rs = tq(T, L_RS, e);
@@ -381,8 +381,8 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
         const float cnew = c0 + (q.Jmm * r1 - q.Jcm * r2) * idet;
         mnew = m0 + (q.Jcc * r2 - q.Jmc * r1) * idet;
         if (!TO && hlf == 0) {
-            L.dc[k] = cnew;
-            L.dmu[k] = mnew;
+            sta<AS>(L.dc, k, cnew);
+            sta<AS>(L.dmu, k, mnew);
         }
         T.s[L_DC * st + e] = cnew;
         T.s[L_MU * st + e] = mnew;
@@ -392,14 +392,14 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
     const size_t khi = (size_t)jhi * L.pitch + ihi;
-    const float uhlo = face_point(L, hlf, k), uhhi = face_point(L, hlf, khi);
+    const float uhlo = lda<AS>(hlf ? L.v : L.u, k), uhhi = lda<AS>(hlf ? L.v : L.u, khi);
     const FaceEqF flo = lface_eq(P, T, a, e, a.it, ih, uhlo);
     const FaceEqF fhi = lface_eq(P, T, a, e + a.dn, a.it, ih, uhhi);
     const float *rN = hlf ? L.rv : L.ru;
-    const float blo = hlo ? rN[k] - flo.N : 0.0f, dlo = hlo ? flo.diag : 1.0f;
-    const float bhi = hhi ? rN[khi] - fhi.N : 0.0f, dhi = hhi ? fhi.diag : 1.0f;
+    const float blo = hlo ? lda<AS>(rN, k) - flo.N : 0.0f, dlo = hlo ? flo.diag : 1.0f;
+    const float bhi = hhi ? lda<AS>(rN, khi) - fhi.N : 0.0f, dhi = hhi ? fhi.diag : 1.0f;
     const float Lmu_new = s.Lmu - s.Sm * (mnew - m0);
-    const float bp = L.rp[k] - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
+    const float bp = lda<AS>(L.rp, k) - (s.div - P.alpha * P.inv_Pe * Lmu_new - P.alpha * P.alpha * P.inv_Pe * s.Lp);
     const float w_ax = tq(T, L_RN, e) * 0.5f * (tq(T, a.FNN, e) + tq(T, a.FNN, e + a.dn));
     const float mv0 = tq(T, L_MV, e);
     const float vis = (4.0f / 3.0f) * P.inv_Re * ih2 * mv0, gd = P.inv_Re * ih2 * mv0 / 3.0f;
@@ -487,8 +487,8 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
             T.s[L_MU * st + e] = m0 + (r2 - q.Jmc * dc) * imm;
             T.s[L_DRS * st + e] = -P.alpha * rs * rs * (c0 + dc);
         } else {
-            L.dc[k] = c0 + dc;
-            L.dmu[k] = m0 + (r2 - q.Jmc * dc) * imm;
+            sta<AS>(L.dc, k, c0 + dc);
+            sta<AS>(L.dmu, k, m0 + (r2 - q.Jmc * dc) * imm);
         }
     }
     const float dl = b[0], dh = b[1];
@@ -500,14 +500,15 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
         return;
     }
     float *dst = hlf ? dvnew : dunew;
-    if (hlo) dst[k] = tq(T, a.FN, e) + omega * dl;
-    if (hhi) dst[khi] = tq(T, a.FN, e + a.dn) + omega * dh;
-    if (hlf == 0) L.dp[k] = tq(T, L_P, e) + omega * b[4];
+    if (hlo) sta<AS>(dst, k, tq(T, a.FN, e) + omega * dl);
+    if (hhi) sta<AS>(dst, khi, tq(T, a.FN, e + a.dn) + omega * dh);
+    if (hlf == 0) sta<AS>(L.dp, k, tq(T, L_P, e) + omega * b[4]);
 }
+template <int AS = 0>
 __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, const TileF &T, float *dunew,
                                             float *dvnew, int i, int j, int hlf, float omega)
 {
-    lrelax_cell<false>(P, L, T, dunew, dvnew, i, j, i, j, hlf, omega);
+    lrelax_cell<false, AS>(P, L, T, dunew, dvnew, i, j, i, j, hlf, omega);
 }
 
 // residual of the correction equation r - J(w^) delta for the five equations

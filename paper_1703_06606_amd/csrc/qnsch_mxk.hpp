@@ -49,7 +49,7 @@ template <typename IT> __device__ __forceinline__ void mx_halfsweep_body(const I
     const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
     const int j = T.j0 + lj;
     const int i = T.i0 + 2 * kk + ((j + colour) & 1);
-    if (i < L.m1 && j < L.m2) lrelax_pair(d.Pf, L, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, hlf, omega);
+    if (i < L.m1 && j < L.m2) lrelax_pair<1>(d.Pf, L, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, hlf, omega);
 }
 template <typename IT> __global__ HS_ATTR void k_mx_halfsweep(IT it, int colour, float omega)
 {
@@ -159,7 +159,7 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_mx_fused(IT it,
         const bool in = lj < TY + 4 && (L.bcx || (ti >= 0 && ti < L.m1)) && (L.bcy || (tj >= 0 && tj < L.m2));
         if (in) {
             const int i = L.bcx ? wrapi(ti, L.m1) : ti, j = L.bcy ? wrapi(tj, L.m2) : tj;
-            lrelax_cell<true>(d.Pf, L, T, nullptr, nullptr, i, j, ti, tj, hlf, omega);
+            lrelax_cell<true, 1>(d.Pf, L, T, nullptr, nullptr, i, j, ti, tj, hlf, omega);
         }
     }
     __syncthreads();
@@ -169,7 +169,7 @@ template <typename IT> __global__ __launch_bounds__(FBLK) void k_mx_fused(IT it,
         const int lj = pr / (TX / 2), kk = pr - lj * (TX / 2);
         const int j = T0.j0 + lj;
         const int i = T0.i0 + 2 * kk + ((j + 1) & 1);
-        if (i < L.m1 && j < L.m2) lrelax_cell<false>(d.Pf, O, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, i, j, hlf, omega);
+        if (i < L.m1 && j < L.m2) lrelax_cell<false, 1>(d.Pf, O, T, d.dub[par ^ 1], d.dvb[par ^ 1], i, j, i, j, hlf, omega);
     } else {
         const int q = pr - TBLK / 2;
         const int lj = q / (TX / 2), kk = q - lj * (TX / 2);
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(512) void k_mx_coarse_solve(IT it, int sweeps, floa
             const int pr = t >> 1;
             const int j = pr / half;
             const int i = 2 * (pr - j * half) + ((j + colour) & 1);
-            lrelax_pair(d.Pf, H, T, uw, vw, i, j, t & 1, omega);
+            lrelax_pair<3>(d.Pf, H, T, uw, vw, i, j, t & 1, omega);
         }
         __syncthreads();
     }
