@@ -346,9 +346,6 @@ __device__ __forceinline__ FaceEqF lface_eq(const PhysF &P, const TileF &T, cons
     return q;
 }
 
-// the velocity at w^ on the face of element ef's row: the west face of cell
-// (i, j) (x lane) or its south face (y lane), or the next one along the axis
-__device__ __forceinline__ float face_point(const LView &L, int hlf, size_t k) { return (hlf ? L.v : L.u)[k]; }
 
 // one cell of the current colour: the FP64 smoother applied to the
 // correction equation J(w^) delta = r.  Segregated: step 1 is a 2x2 solve for
@@ -392,6 +389,8 @@ __device__ __forceinline__ void lrelax_cell(const PhysF &P, const LView &L, cons
     const bool hlo = a.per || a.ia >= 1, hhi = a.per || a.ia + 1 < a.ma;
     const int ihi = hlf ? i : (i + 1 < L.m1 ? i + 1 : 0), jhi = hlf ? (j + 1 < L.m2 ? j + 1 : 0) : j;
     const size_t khi = (size_t)jhi * L.pitch + ihi;
+    // the velocity at w^ on the lane's two faces (west and east, or south and
+    // north, of the cell)
     const float uhlo = lda<AS>(hlf ? L.v : L.u, k), uhhi = lda<AS>(hlf ? L.v : L.u, khi);
     const FaceEqF flo = lface_eq(P, T, a, e, a.it, ih, uhlo);
     const FaceEqF fhi = lface_eq(P, T, a, e + a.dn, a.it, ih, uhhi);
@@ -513,7 +512,7 @@ __device__ __forceinline__ void lrelax_pair(const PhysF &P, const LView &L, cons
 
 // residual of the correction equation r - J(w^) delta for the five equations
 // attached to cell (i, j) (cell equations; west face on lane 0, south face on
-// lane 1, zero for a face on a wall)
+// lane 1, zero for a face on a wall); the level is in global memory
 __device__ __forceinline__ void lresid_pair(const PhysF &P, const LView &L, const TileF &T, int i, int j, int hlf,
                                             float &rc, float &rm, float &rp, float &rf)
 {
@@ -521,13 +520,14 @@ __device__ __forceinline__ void lresid_pair(const PhysF &P, const LView &L, cons
     const int e = T.idx(i, j);
     const Ax a = make_ax(L, T, i, j, hlf);
     const LCellAx s = lcell_sum(lcell_axis(T, a, e, L.inv_h));
-    const LCellEq q = lcell_eq(P, T, e, s, L.mu[k]);
-    rc = L.rc[k] - q.Nc;
-    rm = L.rmu[k] - q.Nmu;
-    rp = L.rp[k] - q.Np;
+    const LCellEq q = lcell_eq(P, T, e, s, lda<1>(L.mu, k));
+    rc = lda<1>(L.rc, k) - q.Nc;
+    rm = lda<1>(L.rmu, k) - q.Nmu;
+    rp = lda<1>(L.rp, k) - q.Np;
     const bool hlo = a.per || a.ia >= 1;
-    const FaceEqF f = lface_eq(P, T, a, e, a.it, L.inv_h, face_point(L, hlf, k));
-    rf = hlo ? (hlf ? L.rv : L.ru)[k] - f.N : 0.0f;
+    // (the velocity at w^ on the lane's face)
+    const FaceEqF f = lface_eq(P, T, a, e, a.it, L.inv_h, lda<1>(hlf ? L.v : L.u, k));
+    rf = hlo ? lda<1>(hlf ? L.rv : L.ru, k) - f.N : 0.0f;
 }
 
 } // namespace qn

@@ -212,8 +212,8 @@ template <typename IT> __global__ __launch_bounds__(TBLK) void k_mx_restrict(IT 
             float xc, xm, xp, xf;
             lresid_pair(d.Pf, Lf, T, i, j, hlf, xc, xm, xp, xf);
             rc += xc; rm += xm; rp += xp;
-            if ((hlf ? b : a) == 0) { rf += xf; sf += (hlf ? Lf.v : Lf.u)[q]; }
-            sc += T.q(L_C, i, j); smu += Lf.mu[q];
+            if ((hlf ? b : a) == 0) { rf += xf; sf += lda<1>(hlf ? Lf.v : Lf.u, q); }
+            sc += T.q(L_C, i, j); smu += lda<1>(Lf.mu, q);
         }
     const size_t q = (size_t)J * C.pitch + I;
     const int cp = it.cpar[k];
